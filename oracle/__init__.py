@@ -1,0 +1,233 @@
+"""DiffPower FP64 CPU oracle -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liborc.so`` (built from
+``diffpower_oracle.c`` with gcc by ``oracle/build.py``) with ctypes and
+numpy; it never loads or calls the HIP library, and the HIP library never
+loads it.
+
+Every function follows the paper (arXiv 2608.03778) passage named in the C
+source.  The wrappers only marshal arrays and loop over query columns.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = ctypes.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_d = ctypes.c_double
+_int = ctypes.c_int
+
+
+def _declare(lib):
+    lib.orc_op_arity.argtypes = [_int]
+    lib.orc_op_arity.restype = _int
+    lib.orc_topo_order.argtypes = [_i32, _i32, _p, _p, _p, _p]
+    lib.orc_topo_order.restype = _int
+    lib.orc_levels.argtypes = [_i32, _i32, _p, _p, _p, _p]
+    lib.orc_levels.restype = None
+    lib.orc_gate_sp.argtypes = [_int, _p]
+    lib.orc_gate_sp.restype = _d
+    lib.orc_gate_partials.argtypes = [_int, _p, _p]
+    lib.orc_gate_partials.restype = None
+    lib.orc_gate_bits.argtypes = [_int, _p]
+    lib.orc_gate_bits.restype = _u64
+    lib.orc_sp.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p]
+    lib.orc_sp.restype = None
+    lib.orc_power_complex_step.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _p, _d, _i32, _d]
+    lib.orc_power_complex_step.restype = _d
+    lib.orc_philox4x32_10.argtypes = [_p, _p, _p]
+    lib.orc_philox4x32_10.restype = None
+    lib.orc_threshold.argtypes = [ctypes.c_float]
+    lib.orc_threshold.restype = _u64
+    lib.orc_stimulus_word.argtypes = [_i32, _i64, ctypes.c_float, _u64]
+    lib.orc_stimulus_word.restype = _u64
+    lib.orc_stimulus.argtypes = [_i32, _p, _u64, _i64, _i64, _p]
+    lib.orc_stimulus.restype = None
+    lib.orc_sim.argtypes = [_i32, _i32, _p, _p, _p, _p, _i64, _p, _p, _u64, _p, _p]
+    lib.orc_sim.restype = None
+    lib.orc_power.argtypes = [_i32, _i32, _p, _p, _p, _i64, _p, _p, _d, _int, _d, _d, _p,
+                              _p, _p, _p, _p, _p, _p]
+    lib.orc_power.restype = _d
+    lib.orc_adjoint.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _p, _p, _d, _int, _p, _p, _p]
+    lib.orc_adjoint.restype = None
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+class Netlist:
+    """The oracle's own copy of a netlist (caller numbering) plus its
+    topological order."""
+
+    def __init__(self, n_pi, op, fanin_ptr, fanin):
+        lib = _load()
+        self.n_pi = int(n_pi)
+        self.op = _c(op, np.uint8)
+        self.fanin_ptr = _c(fanin_ptr, np.int32)
+        self.fanin = _c(fanin, np.int32)
+        self.n_gates = int(self.op.shape[0])
+        self.n_nets = self.n_pi + self.n_gates
+        self.order = np.zeros(max(self.n_gates, 1), dtype=np.int32)
+        rc = lib.orc_topo_order(self.n_pi, self.n_gates, _ptr(self.op), _ptr(self.fanin_ptr),
+                                _ptr(self.fanin), _ptr(self.order))
+        if rc == -1:
+            raise ValueError("malformed netlist")
+        if rc == -2:
+            raise ValueError("combinational cycle")
+
+    @classmethod
+    def of(cls, nl):
+        return cls(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin)
+
+    def _args(self):
+        return (self.n_pi, self.n_gates, _ptr(self.op), _ptr(self.fanin_ptr), _ptr(self.fanin),
+                _ptr(self.order))
+
+    def levels(self) -> np.ndarray:
+        lv = np.zeros(self.n_nets, dtype=np.int32)
+        _load().orc_levels(self.n_pi, self.n_gates, _ptr(self.fanin_ptr), _ptr(self.fanin),
+                           _ptr(self.order), _ptr(lv))
+        return lv
+
+    def sp(self, p_pi) -> np.ndarray:
+        """Modeled static probability of every net (float64 [n_nets])."""
+        p = _c(p_pi, np.float64)
+        P = np.zeros(self.n_nets, dtype=np.float64)
+        _load().orc_sp(*self._args(), _ptr(p), _ptr(P))
+        return P
+
+    def sim(self, n_words, pi_words=None, p_pi=None, seed=0):
+        """(ones, toggles) uint64 [n_nets] over n_words simulated words."""
+        w = _c(pi_words, np.uint64)
+        p = _c(p_pi, np.float32)
+        ones = np.zeros(self.n_nets, dtype=np.uint64)
+        tog = np.zeros(self.n_nets, dtype=np.uint64)
+        _load().orc_sim(*self._args(), int(n_words), _ptr(w), _ptr(p), int(seed), _ptr(ones),
+                        _ptr(tog))
+        return ones, tog
+
+    def power(self, P, cap, size=None, *, kappa=0.5, hybrid=False, ones=None, toggles=None,
+              n_words=0, beta_min=0.1, beta_max=10.0, beta=None):
+        """Finalize: dict of tr_model, sp_acc, tr_acc, beta, tr_hyb, ceff and
+        the total power."""
+        n = self.n_nets
+        out = {k: np.zeros(n, dtype=np.float64)
+               for k in ("tr_model", "sp_acc", "tr_acc", "beta", "tr_hyb", "ceff")}
+        P = _c(P, np.float64)
+        cap = _c(cap, np.float32)
+        size = _c(size, np.float32)
+        ones = _c(ones, np.uint64)
+        toggles = _c(toggles, np.uint64)
+        beta = _c(beta, np.float64)
+        out["power"] = _load().orc_power(
+            self.n_pi, self.n_gates, _ptr(P), _ptr(ones), _ptr(toggles), int(n_words), _ptr(cap),
+            _ptr(size), float(kappa), int(bool(hybrid)), float(beta_min), float(beta_max),
+            _ptr(beta), _ptr(out["tr_model"]), _ptr(out["sp_acc"]), _ptr(out["tr_acc"]),
+            _ptr(out["beta"]), _ptr(out["tr_hyb"]), _ptr(out["ceff"]))
+        return out
+
+    def adjoint(self, P, beta, cap, size=None, *, kappa=0.5, beta_ste=False):
+        """dict of lambda [n_nets], dpi [n_pi], dcap [n_nets], dsize [n_gates]."""
+        n = self.n_nets
+        lam = np.zeros(n, dtype=np.float64)
+        dcap = np.zeros(n, dtype=np.float64)
+        dsize = np.zeros(max(self.n_gates, 1), dtype=np.float64)
+        _load().orc_adjoint(*self._args(), _ptr(_c(P, np.float64)), _ptr(_c(beta, np.float64)),
+                            _ptr(_c(cap, np.float32)), _ptr(_c(size, np.float32)), float(kappa),
+                            int(bool(beta_ste)), _ptr(lam), _ptr(dcap), _ptr(dsize))
+        return dict(lam=lam, dpi=lam[: self.n_pi].copy(), dcap=dcap, dsize=dsize[: self.n_gates])
+
+    def power_complex_step(self, p_pi, beta, ceff, pi, *, kappa=0.5, h=1e-30):
+        return _load().orc_power_complex_step(
+            *self._args(), _ptr(_c(p_pi, np.float64)), _ptr(_c(beta, np.float64)),
+            _ptr(_c(ceff, np.float64)), float(kappa), int(pi), float(h))
+
+    # -- whole-query compositions -----------------------------------------
+    def forward(self, p_pi, cap, size=None, *, hybrid=False, n_words=0, seed=0, pi_words=None,
+                kappa=0.5, beta_min=0.1, beta_max=10.0):
+        """One query column: SP, optional simulation, finalize."""
+        P = self.sp(np.asarray(p_pi, dtype=np.float32).astype(np.float64))
+        ones = tog = None
+        if hybrid:
+            ones, tog = self.sim(n_words, pi_words=pi_words, p_pi=p_pi, seed=seed)
+        out = self.power(P, cap, size, kappa=kappa, hybrid=hybrid, ones=ones, toggles=tog,
+                         n_words=n_words, beta_min=beta_min, beta_max=beta_max)
+        out["sp"] = P
+        if hybrid:
+            out["ones"], out["toggles"] = ones, tog
+        return out
+
+    def frozen_power(self, p_pi64, beta, cap, size=None, *, kappa=0.5):
+        """Power with beta held fixed, for finite differences."""
+        P = self.sp(p_pi64)
+        return self.power(P, cap, size, kappa=kappa, beta=beta)["power"]
+
+
+def op_arity(op: int) -> int:
+    return int(_load().orc_op_arity(int(op)))
+
+
+def gate_sp(op: int, x) -> float:
+    x = np.ascontiguousarray(np.resize(np.asarray(x, dtype=np.float64), 3))
+    return float(_load().orc_gate_sp(int(op), _ptr(x)))
+
+
+def gate_partials(op: int, x) -> np.ndarray:
+    x = np.ascontiguousarray(np.resize(np.asarray(x, dtype=np.float64), 3))
+    d = np.zeros(3, dtype=np.float64)
+    _load().orc_gate_partials(int(op), _ptr(x), _ptr(d))
+    return d[: op_arity(op)]
+
+
+def gate_bits(op: int, w) -> int:
+    w = np.ascontiguousarray(np.resize(np.asarray(w, dtype=np.uint64), 3))
+    return int(_load().orc_gate_bits(int(op), _ptr(w)))
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def threshold(p: float) -> int:
+    return int(_load().orc_threshold(float(np.float32(p))))
+
+
+def stimulus(p_pi, seed: int, t0: int, n_words: int) -> np.ndarray:
+    """uint64 [n_pi][n_words] stimulus words t0 .. t0+n_words-1."""
+    p = _c(p_pi, np.float32)
+    w = np.zeros((p.shape[0], n_words), dtype=np.uint64)
+    _load().orc_stimulus(int(p.shape[0]), _ptr(p), int(seed), int(t0), int(n_words), _ptr(w))
+    return w
