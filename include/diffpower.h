@@ -1,0 +1,304 @@
+/*
+ * diffpower.h -- C ABI of the MI355X (gfx950) DiffPower hot path.
+ *
+ * DiffPower (arXiv 2608.03778) estimates switching power of a gate netlist by
+ * propagating static probabilities (SP) level by level (Sec. III-A/B,
+ * Alg. 2), turns them into toggle rates under temporal independence (Eq. 2),
+ * calibrates them with a bit-packed logic simulation (Sec. III-C, Eq. 4) via
+ * a clipped per-net ratio beta (Sec. III-D, Eq. 5), sums C-weighted activity
+ * into power (Eq. 1) and differentiates that power in one reverse sweep
+ * (Sec. III-E, Eq. 6-7).  This library runs all of it on one AMD GPU.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a dp_status; nothing throws or aborts across the
+ *    ABI.  dp_last_error() returns a thread-local message for the last
+ *    failing call of the calling thread.
+ *  - The caller owns every buffer it passes.  dp_compile and dp_set_* copy
+ *    what they need before returning (host inputs) or before the stream
+ *    work they enqueue runs (device inputs).  The library owns designs,
+ *    evals and servers and their device memory until *_destroy.
+ *  - `on_device` = 1 means a pointer is GPU memory on the context's device
+ *    (e.g. a torch tensor's data_ptr()); 0 means host memory.  Host outputs
+ *    are complete when the call returns; device outputs are complete when
+ *    the context's stream reaches the point where the call enqueued them.
+ *  - Per-net arrays use the caller's net numbering: nets [0, n_pi) are the
+ *    primary inputs (PIs), net n_pi + g is the output of gate g.  The
+ *    library's internal renumbering never shows.
+ *  - Floating point on the GPU is float32; counts are uint32.
+ *  - Designs are immutable after dp_compile and may be shared by many evals.
+ *    An eval, a server and a context are used by one host thread at a time.
+ */
+#ifndef DIFFPOWER_H
+#define DIFFPOWER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DP_OK = 0,
+  DP_E_INVALID = -1,     /* malformed argument or netlist, value out of range */
+  DP_E_CYCLE = -2,       /* the netlist has a combinational cycle */
+  DP_E_OOM = -3,         /* device or host allocation failed */
+  DP_E_HIP = -4,         /* a HIP runtime call failed */
+  DP_E_UNSUPPORTED = -5, /* valid request this build does not implement */
+  DP_E_STATE = -6,       /* call out of order (e.g. backward before forward) */
+  DP_E_BUDGET = -7,      /* request can never fit the server's memory budget */
+  DP_E_NOTFOUND = -8     /* unknown ticket or design id */
+} dp_status;
+
+/* The nine fixed cells (Sec. III-A routes common gates to hand-written
+ * rules; AOI21 and MUX2 get their exact single-cell rules as well).
+ * Pin order in brackets; the SP rule assumes independent inputs (Sec. II-B). */
+enum {
+  DP_INV = 0,   /* [A]        !A               SP 1-a               */
+  DP_BUF = 1,   /* [A]        A                SP a                 */
+  DP_AND2 = 2,  /* [A,B]      A&B              SP ab                */
+  DP_OR2 = 3,   /* [A,B]      A|B              SP a+b-ab            */
+  DP_NAND2 = 4, /* [A,B]      !(A&B)           SP 1-ab              */
+  DP_NOR2 = 5,  /* [A,B]      !(A|B)           SP (1-a)(1-b)        */
+  DP_XOR2 = 6,  /* [A,B]      A^B              SP a+b-2ab           */
+  DP_AOI21 = 7, /* [A1,A2,B]  !((A1&A2)|B)     SP (1-a1 a2)(1-b)    */
+  DP_MUX2 = 8,  /* [I0,I1,S]  S?I1:I0          SP (1-s)i0 + s i1    */
+  DP_N_OPS = 9
+};
+
+/* Propagation modes (Sec. V-B names all three). */
+enum {
+  DP_MODELED = 0,     /* algebraic SP only, beta = 1 */
+  DP_HYBRID = 1,      /* SP + bit-packed simulation + beta calibration */
+  DP_FROZEN_BETA = 2  /* algebraic SP scaled by a beta set with dp_set_beta */
+};
+
+/* How beta enters the gradient (Eq. 6). */
+enum {
+  DP_BETA_LOCAL = 0, /* beta scales each net's local power term: the exact
+                        gradient of sum beta*C*TR_model with beta frozen */
+  DP_BETA_STE = 1    /* Eq. 6 literally: a net's accumulated gradient is
+                        multiplied by its beta before it flows upstream */
+};
+
+/* Sweep schedules (see dp_eval_set_schedule). */
+enum {
+  DP_SCHED_AUTO = 0,  /* the autotuned choice (default) */
+  DP_SCHED_LEVEL = 1, /* one launch per level */
+  DP_SCHED_GRAPH = 2  /* the same launches captured once into a HIP graph */
+};
+
+typedef struct dp_ctx dp_ctx;
+typedef struct dp_design dp_design;
+typedef struct dp_eval dp_eval;
+typedef struct dp_server dp_server;
+
+/* A combinational gate netlist (Sec. III-A: sequential outputs become PIs
+ * with fixed probability).  fanin[fanin_ptr[g] .. fanin_ptr[g+1]) are the
+ * input nets of gate g in pin order; their count must equal the cell's
+ * arity.  Gates may be given in any order. */
+typedef struct {
+  int32_t n_pi;
+  int32_t n_gates;
+  const uint8_t *op;        /* [n_gates] DP_INV .. DP_MUX2 */
+  const int32_t *fanin_ptr; /* [n_gates + 1], fanin_ptr[0] = 0 */
+  const int32_t *fanin;     /* [fanin_ptr[n_gates]] net ids */
+} dp_netlist;
+
+/* Electrical and calibration parameters.
+ * Power = energy_factor * vdd^2 * fclk * sum_n beta_n C_eff,n TR_model,n
+ * (Eq. 1 with energy_factor = 1/2).  With vdd in V, fclk in GHz and C in fF
+ * the unit is uW.  beta is clipped to [beta_min, beta_max] (Eq. 5; the paper
+ * uses 0.1 and 10).  n_sim is the number of simulated vectors (a multiple of
+ * 64, at least 128 in DP_HYBRID); seed keys the stimulus generator. */
+typedef struct {
+  double vdd;
+  double fclk;
+  double energy_factor;
+  double beta_min;
+  double beta_max;
+  int32_t mode;      /* DP_MODELED | DP_HYBRID | DP_FROZEN_BETA */
+  int32_t beta_grad; /* DP_BETA_LOCAL | DP_BETA_STE */
+  int64_t n_sim;
+  uint64_t seed;
+} dp_params;
+
+/* Sizes of a compiled design. */
+typedef struct {
+  int32_t n_pi, n_gates, n_nets;
+  int32_t depth;           /* number of gate levels */
+  int64_t n_edges;         /* total fan-in pins */
+  int32_t max_level_width; /* gates in the widest level */
+  int32_t reserved;
+  int64_t device_bytes;    /* device memory held by the design */
+} dp_design_info_t;
+
+/* Forward outputs.  Any pointer may be NULL to skip that output.  Per-net
+ * arrays are [B][n_nets] (caller numbering, column-major over queries);
+ * power is [B][S'] with S' = max(S, 1).  In DP_MODELED mode sp_acc, tr_acc,
+ * ones and toggles are not produced (must be NULL) and beta is 1. */
+typedef struct {
+  float *sp;         /* static probability (Alg. 2) */
+  float *tr;         /* TR_model = 2 SP (1 - SP) (Eq. 2) */
+  float *sp_acc;     /* simulated SP = ones / (64 T) */
+  float *tr_acc;     /* simulated TR = toggles / (64 (T - 1)) (Eq. 4) */
+  float *beta;       /* clip(TR_acc / TR_model, beta_min, beta_max) (Eq. 5) */
+  float *tr_hyb;     /* beta * TR_model */
+  uint32_t *ones;    /* lanes at 1 over all simulated words */
+  uint32_t *toggles; /* lane transitions between consecutive words */
+  float *power;      /* [B][S'] switching power (Eq. 1) */
+  int32_t on_device; /* all pointers above are device (1) or host (0) */
+} dp_fwd_out;
+
+/* Defaults: vdd 1, fclk 1, energy_factor 0.5, beta in [0.1, 10],
+ * DP_MODELED, DP_BETA_LOCAL, n_sim 4096, seed 1. */
+void dp_params_default(dp_params *p);
+
+/* Thread-local message of the calling thread's last failure ("" if none). */
+const char *dp_last_error(void);
+
+/* Library version string. */
+const char *dp_version(void);
+
+/* --- context ----------------------------------------------------------- */
+/* Bind to GPU `device`; work is enqueued on `hip_stream` (a hipStream_t,
+ * NULL = the library creates and owns a stream).  Errors: DP_E_INVALID (no
+ * such device), DP_E_HIP. */
+dp_status dp_ctx_create(int32_t device, void *hip_stream, dp_ctx **out);
+/* Switch the stream later calls enqueue on (NULL = the owned stream). */
+dp_status dp_ctx_set_stream(dp_ctx *ctx, void *hip_stream);
+/* Block until the context's stream is idle. */
+dp_status dp_ctx_synchronize(dp_ctx *ctx);
+void dp_ctx_destroy(dp_ctx *ctx);
+
+/* --- design (Sec. III-A, Alg. 1's role: build the levelized graph) ------- */
+/* Validate the netlist (arity, net ids, no cycles), levelize it as soon as
+ * possible (PIs at level 0, a gate one above its deepest input), sort gates
+ * by (level, cell), renumber nets so a level's outputs are contiguous, build
+ * the per-pin fan-in arrays and the fan-out lists, and upload everything.
+ * Host inputs only; they are copied.  Errors: DP_E_INVALID, DP_E_CYCLE,
+ * DP_E_OOM, DP_E_HIP. */
+dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out);
+dp_status dp_design_info(const dp_design *design, dp_design_info_t *out);
+/* Level of every net in caller numbering ([n_nets], host). */
+dp_status dp_design_levels(const dp_design *design, int32_t *level);
+void dp_design_destroy(dp_design *design);
+
+/* --- evaluation state -------------------------------------------------- */
+/* Workspaces for B query columns (independent PI-probability vectors) and S
+ * cell-size vectors (S = 0: no sizes, every s = 1).  Every (b, s) pair is
+ * one power value.  Errors: DP_E_INVALID (B < 1, S < 0, bad params),
+ * DP_E_OOM. */
+dp_status dp_eval_create(dp_design *design, int32_t n_cols, int32_t n_size,
+                         const dp_params *params, dp_eval **out);
+dp_status dp_eval_set_params(dp_eval *ev, const dp_params *params);
+void dp_eval_destroy(dp_eval *ev);
+
+/* PI probabilities p[b][i], [B][n_pi], each in [0, 1] (Alg. 2 inputs,
+ * "startpoint SPs").  DP_E_INVALID on NaN or out of range. */
+dp_status dp_set_pi_prob(dp_eval *ev, const float *p, int32_t on_device);
+/* Net load capacitances C[n], [n_nets] (Eq. 1), finite and >= 0. */
+dp_status dp_set_caps(dp_eval *ev, const float *cap, int32_t on_device);
+/* Cell size factors s[s][g], [S][n_gates], finite and >= 0.  A gate's size
+ * scales the load of the net it drives: C_eff = C * s_driver. */
+dp_status dp_set_cell_sizes(dp_eval *ev, const float *size, int32_t on_device);
+/* Frozen calibration beta[b][n], [B][n_nets], used by DP_FROZEN_BETA. */
+dp_status dp_set_beta(dp_eval *ev, const float *beta, int32_t on_device);
+/* Replace the generated stimulus with explicit PI words w[b][i][t],
+ * [B][n_pi][n_sim/64] (bit j of word t = lane j at cycle t); NULL restores
+ * the generator.  A test and replay hook. */
+dp_status dp_set_stimulus(dp_eval *ev, const uint64_t *words, int32_t on_device);
+
+/* Forward pass over all B columns (and S size vectors): SP sweep; in
+ * DP_HYBRID also stimulus, bit-packed simulation and beta; finalize; power
+ * reduction.  Errors: DP_E_STATE (PI probabilities or caps never set),
+ * DP_E_INVALID (output not available in this mode), DP_E_HIP. */
+dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out);
+
+/* Reverse sweep (Eq. 7) of the last forward, weighted by the upstream
+ * gradient w[b][s] ([B][S'], NULL = all ones; the adjoint is linear in it):
+ *  dpower_dpi  [B][n_pi]     sum_s w[b][s] dP[b][s]/dp[b][i]
+ *  dpower_dcap [n_nets]      sum_{b,s} w[b][s] dP[b][s]/dC[n]
+ *  dpower_dsize[S][n_gates]  sum_b w[b][s] dP[b][s]/ds[s][g]   (S > 0 only)
+ * Any output may be NULL.  beta, C, s and the stimulus are held fixed.
+ * Errors: DP_E_STATE (no completed forward since the inputs changed). */
+dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi,
+                      float *dpower_dcap, float *dpower_dsize,
+                      int32_t on_device);
+
+/* Per-(b, s) gradients with respect to the PI probabilities, [B][S'][n_pi]:
+ * one multi-right-hand-side reverse sweep that applies each column b's
+ * partial derivatives to its S' seeds.  Errors as dp_backward. */
+dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device);
+
+/* Schedule of the level sweeps (DP_SCHED_*), the number of simulated words
+ * held on the device at once (0 = automatic; otherwise a multiple of 2 that
+ * splits the n_sim/64 words into chunks carrying a two-word halo), and the
+ * word pairs each simulation lane handles per wave (1, 2, 4 or 8; 0 =
+ * automatic).  Results are bitwise independent of all three. */
+dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule,
+                               int64_t words_per_chunk,
+                               int32_t sim_pairs_per_lane);
+
+/* Kernel timing of the last forward/backward, accumulated with HIP events
+ * on the context's stream while profiling is enabled. */
+typedef struct {
+  double sim_ms;          /* simulation level kernels, summed per launch */
+  int64_t sim_launches;
+  double sim_bytes;       /* algorithmic bytes moved by those launches */
+  double sp_ms;           /* SP level kernels (modeled sweeps) */
+  int64_t sp_launches;
+  double sp_bytes;
+  double bwd_ms;          /* reverse level kernels */
+  int64_t bwd_launches;
+  double bwd_bytes;
+  double stim_ms;         /* stimulus generation */
+  int64_t stim_launches;
+} dp_profile;
+dp_status dp_eval_profile(dp_eval *ev, int32_t enable);
+dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
+
+/* --- serving: continuous batching of queries (see dp_server_*) ---------- */
+enum { DP_Q_FWD = 0, DP_Q_FWD_BWD = 1 };
+
+/* One query against a device-resident design.  Host buffers; they must stay
+ * valid until dp_wait/dp_poll reports the ticket done. */
+typedef struct {
+  int32_t design_id;
+  int32_t kind;             /* DP_Q_FWD | DP_Q_FWD_BWD */
+  const float *pi_prob;     /* [n_pi] */
+  const float *cap_scale;   /* [n_gates] per-gate size factor, NULL = 1 */
+  float *power;             /* [1] out */
+  float *dpower_dpi;        /* [n_pi] out (DP_Q_FWD_BWD), may be NULL */
+} dp_query;
+
+/* A server owns a scheduler thread and the device memory of its query
+ * slots; `hbm_budget_bytes` bounds the slot memory it may hold at once. */
+dp_status dp_server_create(dp_ctx *ctx, size_t hbm_budget_bytes,
+                           dp_server **out);
+/* Register a compiled design.  Queries use params->mode (DP_MODELED, or
+ * DP_FROZEN_BETA with beta calibrated once here at p = 0.5 from
+ * params->n_sim vectors). */
+dp_status dp_server_add_design(dp_server *srv, dp_design *design,
+                               const float *cap, const dp_params *params,
+                               int32_t *design_id);
+/* Enqueue a query; returns at once.  DP_E_BUDGET if the query alone can
+ * never fit the budget. */
+dp_status dp_submit(dp_server *srv, const dp_query *q, uint64_t *ticket);
+dp_status dp_poll(dp_server *srv, uint64_t ticket, int32_t *done);
+/* Block until the ticket is done; latency_s = completion - submission. */
+dp_status dp_wait(dp_server *srv, uint64_t ticket, double *latency_s);
+typedef struct {
+  int64_t submitted, completed, device_steps;
+  double busy_s;            /* time with device work in flight */
+  int64_t peak_slot_bytes;  /* slot memory high-water mark */
+  int32_t max_inflight;     /* most queries on the device at once */
+  int32_t reserved;
+} dp_server_stats;
+dp_status dp_server_get_stats(dp_server *srv, dp_server_stats *out);
+void dp_server_destroy(dp_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFPOWER_H */

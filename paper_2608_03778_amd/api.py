@@ -1,0 +1,250 @@
+"""Thin Python binding over the C ABI (argument marshalling only).
+
+Arrays may be numpy arrays (host memory, ``on_device = 0``) or torch CUDA
+tensors (device memory, ``on_device = 1``; the context should then run on
+torch's current stream).  Every computation happens in libdiffpower.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import check
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _in_ptr(x, dtype):
+    """(pointer, on_device, keepalive) for an input array."""
+    if x is None:
+        return None, 0, None
+    if _is_torch(x):
+        import torch
+        tdt = {np.float32: torch.float32, np.uint64: torch.int64, np.int32: torch.int32}[dtype]
+        if x.dtype != tdt and not (dtype == np.uint64 and x.dtype == torch.uint64):
+            x = x.to(tdt)
+        x = x.contiguous()
+        return ctypes.c_void_p(x.data_ptr()), int(x.is_cuda), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(ctypes.c_void_p), 0, a
+
+
+class Context:
+    """A GPU and the stream library calls enqueue on."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.lib = L.load()
+        h = ctypes.c_void_p()
+        check(self.lib.dp_ctx_create(int(device), ctypes.c_void_p(stream) if stream else None,
+                                     ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    @classmethod
+    def for_torch(cls, device: int = 0):
+        import torch
+        torch.cuda.set_device(device)
+        return cls(device, torch.cuda.current_stream(device).cuda_stream)
+
+    def set_stream(self, stream: Optional[int]):
+        check(self.lib.dp_ctx_set_stream(self.handle, ctypes.c_void_p(stream) if stream else None))
+
+    def synchronize(self):
+        check(self.lib.dp_ctx_synchronize(self.handle))
+
+    def close(self):
+        if self.handle:
+            self.lib.dp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Design:
+    """A compiled, device-resident netlist (immutable)."""
+
+    def __init__(self, ctx: Context, netlist):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        op = np.ascontiguousarray(netlist.op, dtype=np.uint8)
+        ptr = np.ascontiguousarray(netlist.fanin_ptr, dtype=np.int32)
+        fan = np.ascontiguousarray(netlist.fanin, dtype=np.int32)
+        nl = L.Netlist(int(netlist.n_pi), int(op.shape[0]), op.ctypes.data, ptr.ctypes.data,
+                       fan.ctypes.data)
+        h = ctypes.c_void_p()
+        check(self.lib.dp_compile(ctx.handle, ctypes.byref(nl), ctypes.byref(h)))
+        self.handle = h
+        info = L.DesignInfo()
+        check(self.lib.dp_design_info(h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in L.DesignInfo._fields_ if k != "reserved"}
+        self.n_pi, self.n_gates, self.n_nets = info.n_pi, info.n_gates, info.n_nets
+        self.depth = info.depth
+
+    def levels(self) -> np.ndarray:
+        lv = np.zeros(self.n_nets, dtype=np.int32)
+        check(self.lib.dp_design_levels(self.handle, lv.ctypes.data_as(ctypes.c_void_p)))
+        return lv
+
+    def close(self):
+        if self.handle:
+            self.lib.dp_design_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params(mode=L.DP_MODELED, *, n_sim=4096, seed=1, vdd=1.0, fclk=1.0, energy_factor=0.5,
+           beta_min=0.1, beta_max=10.0, beta_grad=L.DP_BETA_LOCAL) -> L.Params:
+    p = L.Params()
+    L.load().dp_params_default(ctypes.byref(p))
+    p.mode, p.n_sim, p.seed = int(mode), int(n_sim), int(seed)
+    p.vdd, p.fclk, p.energy_factor = float(vdd), float(fclk), float(energy_factor)
+    p.beta_min, p.beta_max, p.beta_grad = float(beta_min), float(beta_max), int(beta_grad)
+    return p
+
+
+_FWD_FIELDS = ("sp", "tr", "sp_acc", "tr_acc", "beta", "tr_hyb", "ones", "toggles", "power")
+
+
+class Eval:
+    """Workspaces for B query columns and S size vectors of one design."""
+
+    def __init__(self, design: Design, n_cols: int = 1, n_size: int = 0, **kw):
+        self.design = design
+        self.lib = design.lib
+        self.B, self.S = int(n_cols), int(n_size)
+        self.prm = params(**kw)
+        h = ctypes.c_void_p()
+        check(self.lib.dp_eval_create(design.handle, self.B, self.S, ctypes.byref(self.prm),
+                                      ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    @property
+    def n_words(self) -> int:
+        return int(self.prm.n_sim) // 64
+
+    def set_params(self, **kw):
+        self.prm = params(**kw)
+        check(self.lib.dp_eval_set_params(self.handle, ctypes.byref(self.prm)))
+
+    def _set(self, fn, x, dtype, key):
+        ptr, dev, keep = _in_ptr(x, dtype)
+        self._keep[key] = keep  # device copies are enqueued, keep the source alive
+        check(fn(self.handle, ptr, dev))
+
+    def set_pi_prob(self, p):
+        self._set(self.lib.dp_set_pi_prob, p, np.float32, "p")
+
+    def set_caps(self, cap):
+        self._set(self.lib.dp_set_caps, cap, np.float32, "cap")
+
+    def set_cell_sizes(self, size):
+        self._set(self.lib.dp_set_cell_sizes, size, np.float32, "size")
+
+    def set_beta(self, beta):
+        self._set(self.lib.dp_set_beta, beta, np.float32, "beta")
+
+    def set_stimulus(self, words):
+        if words is None:
+            check(self.lib.dp_set_stimulus(self.handle, None, 0))
+            return
+        self._set(self.lib.dp_set_stimulus, words, np.uint64, "stim")
+
+    def set_schedule(self, schedule=L.DP_SCHED_AUTO, words_per_chunk=0, pairs_per_lane=0):
+        check(self.lib.dp_eval_set_schedule(self.handle, int(schedule), int(words_per_chunk),
+                                            int(pairs_per_lane)))
+
+    def _out(self, name, device):
+        nn = self.design.n_nets
+        shape = {"power": (self.B, max(self.S, 1))}.get(name, (self.B, nn))
+        dt = np.uint32 if name in ("ones", "toggles") else np.float32
+        if device:
+            import torch
+            tdt = torch.int32 if dt == np.uint32 else torch.float32
+            return torch.empty(shape, dtype=tdt, device=f"cuda:{self.design.ctx.device}")
+        return np.empty(shape, dtype=dt)
+
+    def forward(self, outputs: Iterable[str] = ("power",), device: bool = False) -> dict:
+        """Run the forward sweep; returns the requested outputs (numpy on the
+        host, or torch CUDA tensors with device=True; counts come back as
+        int32 tensors holding uint32 bit patterns)."""
+        res = {}
+        out = L.FwdOut()
+        out.on_device = int(bool(device))
+        for name in outputs:
+            if name not in _FWD_FIELDS:
+                raise ValueError(f"unknown forward output {name!r}")
+            arr = self._out(name, device)
+            res[name] = arr
+            setattr(out, name, arr.data_ptr() if device else arr.ctypes.data)
+        check(self.lib.dp_forward(self.handle, ctypes.byref(out)))
+        return res
+
+    def backward(self, grad_power=None, want=("dpi",), device: bool = False) -> dict:
+        """Reverse sweep weighted by grad_power [B][S'] (None = ones)."""
+        d = self.design
+        shapes = {"dpi": (self.B, d.n_pi), "dcap": (d.n_nets,), "dsize": (self.S, d.n_gates)}
+        res = {}
+        ptrs = {}
+        for name in want:
+            if device:
+                import torch
+                arr = torch.empty(shapes[name], dtype=torch.float32, device=f"cuda:{d.ctx.device}")
+                ptrs[name] = ctypes.c_void_p(arr.data_ptr())
+            else:
+                arr = np.empty(shapes[name], dtype=np.float32)
+                ptrs[name] = arr.ctypes.data_as(ctypes.c_void_p)
+            res[name] = arr
+        gptr, gdev, keep = _in_ptr(grad_power, np.float32)
+        if grad_power is not None and gdev != int(bool(device)):
+            raise ValueError("grad_power must live where the outputs do")
+        self._keep["grad"] = keep
+        check(self.lib.dp_backward(self.handle, gptr, ptrs.get("dpi"), ptrs.get("dcap"),
+                                   ptrs.get("dsize"), int(bool(device))))
+        return res
+
+    def backward_columns(self, device: bool = False):
+        d = self.design
+        shape = (self.B, max(self.S, 1), d.n_pi)
+        if device:
+            import torch
+            arr = torch.empty(shape, dtype=torch.float32, device=f"cuda:{d.ctx.device}")
+            ptr = ctypes.c_void_p(arr.data_ptr())
+        else:
+            arr = np.empty(shape, dtype=np.float32)
+            ptr = arr.ctypes.data_as(ctypes.c_void_p)
+        check(self.lib.dp_backward_columns(self.handle, ptr, int(bool(device))))
+        return arr
+
+    def profile(self, enable: bool = True):
+        check(self.lib.dp_eval_profile(self.handle, int(bool(enable))))
+
+    def get_profile(self) -> dict:
+        p = L.Profile()
+        check(self.lib.dp_eval_get_profile(self.handle, ctypes.byref(p)))
+        return {k: getattr(p, k) for k, _ in L.Profile._fields_}
+
+    def close(self):
+        if self.handle:
+            self.lib.dp_eval_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,813 @@
+// C-ABI entry points of libdiffpower: contexts, designs, evals, forward and
+// reverse sweeps.  The serving layer lives in dp_server.cpp.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "dp_eval.h"
+
+namespace dp {
+
+static thread_local std::string g_err;
+
+dp_status fail(dp_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+void clear_error() { g_err.clear(); }
+
+}  // namespace dp
+
+using dp::DevBuf;
+using dp::fail;
+
+namespace {
+
+constexpr int64_t kAutoWordBudget = 24ll << 30;  // bytes of simulation words per chunk
+const char *kVersion = "diffpower-mi355x 0.1 (gfx950)";
+enum { SPAN_SIM = 0, SPAN_SP = 1, SPAN_BWD = 2, SPAN_STIM = 3 };
+
+dp::GraphView view(const dp_design *d) {
+  dp::GraphView g;
+  g.op = d->op.as<uint8_t>();
+  g.in = d->in.as<int32_t>();
+  g.rev_ptr = d->rev_ptr.as<int32_t>();
+  g.rev_edge = d->rev_edge.as<int32_t>();
+  g.n_pi = d->n_pi;
+  g.G = d->n_gates;
+  g.n_nets = d->n_nets;
+  return g;
+}
+
+int32_t s_prime(const dp_eval *ev) { return ev->S > 0 ? ev->S : 1; }
+double kappa_of(const dp_params &p) { return p.energy_factor * p.vdd * p.vdd * p.fclk; }
+int64_t n_words(const dp_params &p) { return p.n_sim / 64; }
+
+dp_status check_params(const dp_params *p) {
+  if (!p) return fail(DP_E_INVALID, "NULL params");
+  if (p->mode < DP_MODELED || p->mode > DP_FROZEN_BETA)
+    return fail(DP_E_INVALID, "params.mode must be DP_MODELED, DP_HYBRID or DP_FROZEN_BETA");
+  if (p->beta_grad != DP_BETA_LOCAL && p->beta_grad != DP_BETA_STE)
+    return fail(DP_E_INVALID, "params.beta_grad must be DP_BETA_LOCAL or DP_BETA_STE");
+  if (!(p->beta_min > 0.0) || !(p->beta_max >= p->beta_min) || !std::isfinite(p->beta_max))
+    return fail(DP_E_INVALID, "params: need 0 < beta_min <= beta_max < inf");
+  const double k = kappa_of(*p);
+  if (!std::isfinite(k) || k < 0.0) return fail(DP_E_INVALID, "params: bad vdd/fclk/energy_factor");
+  if (p->mode == DP_HYBRID) {
+    if (p->n_sim < 128 || p->n_sim % 64 != 0)
+      return fail(DP_E_INVALID, "params.n_sim must be a multiple of 64 and >= 128 in DP_HYBRID");
+    if (p->n_sim / 64 > (int64_t)INT32_MAX)
+      return fail(DP_E_INVALID, "params.n_sim too large");
+  }
+  return DP_OK;
+}
+
+// Validate a float array (host or device) against [lo, hi] (NaN rejected).
+dp_status check_values(dp_eval *ev, const float *v, int64_t n, float lo, float hi, int on_device,
+                       const char *what) {
+  if (!v) return fail(DP_E_INVALID, std::string(what) + ": NULL pointer");
+  if (!on_device) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!(v[i] >= lo && v[i] <= hi))
+        return fail(DP_E_INVALID, std::string(what) + ": value " + std::to_string(v[i]) +
+                                      " at index " + std::to_string(i) + " out of range");
+    return DP_OK;
+  }
+  hipStream_t s = ev->d->ctx->stream;
+  DP_TRY(ev->flag.alloc(sizeof(int32_t)));
+  DP_HIP_TRY(dp::launch_fill_u32(ev->flag.as<uint32_t>(), 1, 0u, s));
+  DP_HIP_TRY(dp::launch_check_range(v, n, lo, hi, ev->flag.as<int32_t>(), s));
+  int32_t bad = 0;
+  DP_HIP_TRY(hipMemcpyAsync(&bad, ev->flag.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  DP_HIP_TRY(hipStreamSynchronize(s));
+  if (bad) return fail(DP_E_INVALID, std::string(what) + ": a value is NaN or out of range");
+  return DP_OK;
+}
+
+// Copy a caller array into a device staging buffer (device-to-device when on_device).
+dp_status stage_in(DevBuf &buf, const void *src, size_t bytes, int on_device, hipStream_t s) {
+  DP_TRY(buf.alloc(std::max<size_t>(bytes, 16)));
+  if (bytes)
+    DP_HIP_TRY(hipMemcpyAsync(buf.ptr, src, bytes,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  return DP_OK;
+}
+
+// --- profiling: events around launches, resolved after the stream drains
+hipEvent_t take_event(dp_eval *ev) {
+  if (ev->ev_used == ev->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev->ev_pool.push_back(e);
+  }
+  return ev->ev_pool[ev->ev_used++];
+}
+
+struct SpanGuard {
+  dp_eval *ev;
+  size_t a = 0;
+  int kind;
+  double bytes;
+  bool on;
+  SpanGuard(dp_eval *e, int k, double b, bool enabled) : ev(e), kind(k), bytes(b), on(enabled) {
+    if (on) {
+      a = ev->ev_used;
+      hipEvent_t x = take_event(ev);
+      if (!x) { on = false; return; }
+      (void)hipEventRecord(x, ev->d->ctx->stream);
+    }
+  }
+  ~SpanGuard() {
+    if (!on) return;
+    size_t b = ev->ev_used;
+    hipEvent_t x = take_event(ev);
+    if (!x) return;
+    (void)hipEventRecord(x, ev->d->ctx->stream);
+    ev->spans.push_back({a, b, kind, bytes});
+  }
+};
+
+dp_status resolve_profile(dp_eval *ev) {
+  if (ev->spans.empty()) {
+    ev->ev_used = 0;
+    return DP_OK;
+  }
+  DP_HIP_TRY(hipStreamSynchronize(ev->d->ctx->stream));
+  for (const auto &sp : ev->spans) {
+    float ms = 0.0f;
+    DP_HIP_TRY(hipEventElapsedTime(&ms, ev->ev_pool[sp.a], ev->ev_pool[sp.b]));
+    switch (sp.kind) {
+      case SPAN_SIM: ev->prof.sim_ms += ms; ev->prof.sim_launches++; ev->prof.sim_bytes += sp.bytes; break;
+      case SPAN_SP: ev->prof.sp_ms += ms; ev->prof.sp_launches++; ev->prof.sp_bytes += sp.bytes; break;
+      case SPAN_BWD: ev->prof.bwd_ms += ms; ev->prof.bwd_launches++; ev->prof.bwd_bytes += sp.bytes; break;
+      default: ev->prof.stim_ms += ms; ev->prof.stim_launches++; break;
+    }
+  }
+  ev->spans.clear();
+  ev->ev_used = 0;
+  return DP_OK;
+}
+
+// --- chunking of the simulated words
+struct ChunkPlan {
+  int64_t T = 0, Tc = 0, pitch = 0;
+  int32_t halo = 0, n_chunks = 0;
+};
+
+ChunkPlan plan_chunks(const dp_eval *ev) {
+  ChunkPlan c;
+  c.T = n_words(ev->prm);
+  int64_t want = ev->words_per_chunk;
+  const int64_t row_budget = std::max<int64_t>(kAutoWordBudget / (8 * (int64_t)ev->d->n_nets), 4);
+  if (want <= 0) want = c.T <= row_budget ? c.T : row_budget - 2;
+  want = std::max<int64_t>(2, want + (want & 1));
+  if (want >= c.T) {
+    c.Tc = c.T + (c.T & 1);
+    c.halo = 0;
+    c.n_chunks = 1;
+  } else {
+    c.Tc = want;
+    c.halo = 2;
+    c.n_chunks = (int32_t)((c.T + c.Tc - 1) / c.Tc);
+  }
+  c.pitch = c.halo + c.Tc;
+  return c;
+}
+
+dp::ChunkView chunk_view(const dp_eval *ev, const ChunkPlan &pl, int32_t k) {
+  dp::ChunkView v;
+  v.W = ev->words.as<uint64_t>();
+  v.pitch = pl.pitch;
+  const int64_t t0 = (int64_t)k * pl.Tc;
+  const int64_t nw = std::min<int64_t>(pl.Tc, pl.T - t0);
+  v.t_first = t0 - pl.halo;
+  v.u_lo = pl.halo;
+  v.u_hi = (int32_t)(pl.halo + nw);
+  v.u_tog_lo = t0 == 0 ? pl.halo + 1 : pl.halo;
+  v.pairs = (v.u_hi + 1) / 2;
+  return v;
+}
+
+int32_t pick_iters(const dp_eval *ev, const ChunkPlan &pl) {
+  if (ev->sim_iters > 0) return ev->sim_iters;
+  // about two waves per row: enough waves per level, few carry recomputes
+  const int64_t pairs = pl.pitch / 2;
+  if (pairs >= 1024) return 8;
+  if (pairs >= 512) return 4;
+  if (pairs >= 256) return 2;
+  return 1;
+}
+
+bool hybrid(const dp_eval *ev) { return ev->prm.mode == DP_HYBRID; }
+
+// Allocate everything the forward sweep touches (before any capture).
+dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
+  const dp_design *d = ev->d;
+  const size_t nb = (size_t)d->n_nets * ev->B;
+  DP_TRY(ev->beta.alloc(nb * sizeof(float)));
+  DP_TRY(ev->xterm.alloc(nb * sizeof(float)));
+  DP_TRY(ev->seed_base.alloc(nb * sizeof(float)));
+  const int32_t cols = ev->B * s_prime(ev);
+  DP_TRY(ev->power_partial.alloc((size_t)dp::power_chunks(d->n_nets) * cols * sizeof(double)));
+  DP_TRY(ev->power.alloc((size_t)cols * sizeof(float)));
+  if (pl) {
+    DP_TRY(ev->ones.alloc(nb * sizeof(uint32_t)));
+    DP_TRY(ev->tog.alloc(nb * sizeof(uint32_t)));
+    DP_TRY(ev->words.alloc((size_t)d->n_nets * pl->pitch * sizeof(uint64_t)));
+  }
+  return DP_OK;
+}
+
+double sim_level_bytes(const dp_design *d, int32_t l, int64_t words, int32_t B, bool fused) {
+  const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
+  const int64_t pins = d->lvl_pins[l];
+  double b = (double)(8 * pins + 8 * n) * (double)words  // fan-in words + output word
+             + (double)(4 * pins + n) + 8.0 * n;         // indices, cell, counters
+  if (fused) b += (double)B * (4 * pins + 4 * n);         // SP gathers and writes
+  return b;
+}
+
+double sp_level_bytes(const dp_design *d, int32_t l, int32_t B) {
+  const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
+  const int64_t pins = d->lvl_pins[l];
+  return (double)B * (4 * pins + 4 * n) + (double)(4 * pins + n);
+}
+
+double bwd_level_bytes(const dp_design *d, int32_t l, int32_t C) {
+  const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
+  const int64_t pins = d->lvl_pins[l], fo = d->lvl_fanout[l];
+  // per column: seed, pulled contributions, fan-in SP gathers, contribution writes
+  const double per_col = 4.0 * n + 4.0 * fo + 4.0 * pins + 4.0 * pins;
+  // structure: fan-out offsets and edge ids, fan-in indices, cell
+  const double structure = 8.0 * n + 4.0 * fo + 4.0 * pins + n;
+  return (double)C * per_col + structure;
+}
+
+// Enqueue the whole forward sweep (no host sync, no allocation).
+dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
+  const dp_design *d = ev->d;
+  hipStream_t s = d->ctx->stream;
+  const dp::GraphView g = view(d);
+  const bool prof = ev->profiling;
+  float *sp = ev->sp.as<float>();
+  if (!pl) {  // modeled (or frozen-beta) sweep
+    for (int32_t l = 1; l <= d->depth; ++l) {
+      dp::SpLevel lv{sp, ev->B, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l]};
+      SpanGuard sg(ev, SPAN_SP, sp_level_bytes(d, l, ev->B), prof);
+      DP_HIP_TRY(dp::launch_sp_level(g, lv, s));
+    }
+  } else {
+    const size_t nb = (size_t)d->n_nets * ev->B;
+    DP_HIP_TRY(dp::launch_fill_u32(ev->ones.as<uint32_t>(), (int64_t)nb, 0u, s));
+    DP_HIP_TRY(dp::launch_fill_u32(ev->tog.as<uint32_t>(), (int64_t)nb, 0u, s));
+    dp::SimTune tune{pick_iters(ev, *pl)};
+    for (int32_t b = 0; b < ev->B; ++b) {
+      dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), ev->B, b};
+      const uint64_t *stim =
+          ev->have_stim ? ev->stim.as<uint64_t>() + (size_t)b * d->n_pi * pl->T : nullptr;
+      for (int32_t k = 0; k < pl->n_chunks; ++k) {
+        const dp::ChunkView cv = chunk_view(ev, *pl, k);
+        {
+          SpanGuard sg(ev, SPAN_STIM, 0.0, prof);
+          DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, ev->prm.seed, tune, s));
+        }
+        const bool fuse = (b == 0 && k == 0);
+        const int64_t nw = cv.u_hi - cv.u_lo;
+        for (int32_t l = 1; l <= d->depth; ++l) {
+          const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+          dp::SpLevel lv{sp, ev->B, g0, n};
+          SpanGuard sg(ev, SPAN_SIM, sim_level_bytes(d, l, nw, ev->B, fuse), prof);
+          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, tune, s));
+        }
+      }
+    }
+  }
+  dp::FinalizeArgs fa{};
+  fa.sp = sp;
+  fa.ones = pl ? ev->ones.as<uint32_t>() : nullptr;
+  fa.tog = pl ? ev->tog.as<uint32_t>() : nullptr;
+  fa.beta_frozen = ev->prm.mode == DP_FROZEN_BETA ? ev->beta_frozen.as<float>() : nullptr;
+  fa.cap = ev->cap.as<float>();
+  fa.T = pl ? pl->T : 0;
+  fa.kappa = (float)kappa_of(ev->prm);
+  fa.beta_min = (float)ev->prm.beta_min;
+  fa.beta_max = (float)ev->prm.beta_max;
+  fa.mode = ev->prm.mode;
+  fa.ste = ev->prm.beta_grad == DP_BETA_STE;
+  fa.beta = ev->beta.as<float>();
+  fa.xterm = ev->xterm.as<float>();
+  fa.seed_base = ev->seed_base.as<float>();
+  fa.n_nets = d->n_nets;
+  fa.B = ev->B;
+  DP_HIP_TRY(dp::launch_finalize(fa, s));
+  dp::PowerArgs pa{};
+  pa.xterm = ev->xterm.as<float>();
+  pa.cap = ev->cap.as<float>();
+  pa.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
+  pa.n_pi = d->n_pi;
+  pa.n_nets = d->n_nets;
+  pa.G = d->n_gates;
+  pa.B = ev->B;
+  pa.S = ev->S;
+  pa.partial = ev->power_partial.as<double>();
+  pa.n_chunks = dp::power_chunks(d->n_nets);
+  pa.power = ev->power.as<float>();
+  DP_HIP_TRY(dp::launch_power(pa, s));
+  return DP_OK;
+}
+
+// Output helper: a caller pointer, or a staging buffer copied out later.
+struct OutMap {
+  dp_eval *ev;
+  int on_device;
+  int slot = 0;
+  struct Copy { void *dst; const void *src; size_t bytes; };
+  std::vector<Copy> copies;
+  template <class T>
+  dp_status map(T *user, size_t count, T **dev) {
+    *dev = nullptr;
+    if (!user) return DP_OK;
+    if (on_device) {
+      *dev = user;
+      return DP_OK;
+    }
+    DevBuf &b = ev->stage[slot++ % 8];
+    DP_TRY(b.alloc(std::max<size_t>(count * sizeof(T), 16)));
+    *dev = b.as<T>();
+    copies.push_back({user, b.ptr, count * sizeof(T)});
+    return DP_OK;
+  }
+  dp_status flush(hipStream_t s) {
+    for (auto &c : copies)
+      DP_HIP_TRY(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost, s));
+    if (!on_device && !copies.empty()) DP_HIP_TRY(hipStreamSynchronize(s));
+    return DP_OK;
+  }
+};
+
+dp_status capture_forward(dp_eval *ev, const ChunkPlan *pl, uint64_t key) {
+  hipStream_t s = ev->d->ctx->stream;
+  if (ev->graph_fwd) {
+    (void)hipGraphExecDestroy(ev->graph_fwd);
+    ev->graph_fwd = nullptr;
+  }
+  DP_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const bool prof = ev->profiling;
+  ev->profiling = false;
+  dp_status st = enqueue_forward(ev, pl);
+  ev->profiling = prof;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != DP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(DP_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&ev->graph_fwd, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    ev->graph_fwd = nullptr;
+    return fail(DP_E_HIP, std::string("graph instantiate failed: ") + hipGetErrorString(e));
+  }
+  ev->graph_key = key;
+  return DP_OK;
+}
+
+uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
+  uint64_t k = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
+  mix((uint64_t)ev->prm.mode);
+  mix((uint64_t)ev->prm.beta_grad);
+  mix((uint64_t)ev->prm.n_sim);
+  mix(ev->prm.seed);
+  uint64_t bits;
+  double kap = kappa_of(ev->prm);
+  std::memcpy(&bits, &kap, 8); mix(bits);
+  std::memcpy(&bits, &ev->prm.beta_min, 8); mix(bits);
+  std::memcpy(&bits, &ev->prm.beta_max, 8); mix(bits);
+  mix((uint64_t)ev->have_stim);
+  mix((uint64_t)(uintptr_t)ev->stim.ptr);
+  mix((uint64_t)(uintptr_t)ev->words.ptr);
+  mix((uint64_t)(uintptr_t)ev->beta_frozen.ptr);
+  mix((uint64_t)(uintptr_t)ev->size.ptr);
+  mix((uint64_t)(uintptr_t)ev->d->ctx->stream);
+  if (pl) {
+    mix((uint64_t)pl->Tc);
+    mix((uint64_t)pick_iters(ev, *pl));
+  }
+  return k;
+}
+
+}  // namespace
+
+dp_eval::~dp_eval() {
+  if (graph_fwd) (void)hipGraphExecDestroy(graph_fwd);
+  for (auto e : ev_pool) (void)hipEventDestroy(e);
+}
+
+// =========================================================================
+extern "C" {
+
+void dp_params_default(dp_params *p) {
+  if (!p) return;
+  p->vdd = 1.0;
+  p->fclk = 1.0;
+  p->energy_factor = 0.5;
+  p->beta_min = 0.1;
+  p->beta_max = 10.0;
+  p->mode = DP_MODELED;
+  p->beta_grad = DP_BETA_LOCAL;
+  p->n_sim = 4096;
+  p->seed = 1;
+}
+
+const char *dp_last_error(void) { return dp::g_err.c_str(); }
+const char *dp_version(void) { return kVersion; }
+
+dp_status dp_ctx_create(int32_t device, void *hip_stream, dp_ctx **out) {
+  if (!out) return fail(DP_E_INVALID, "dp_ctx_create: NULL out");
+  int n = 0;
+  DP_HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n)
+    return fail(DP_E_INVALID, "dp_ctx_create: no device " + std::to_string(device));
+  DP_HIP_TRY(hipSetDevice(device));
+  auto *c = new dp_ctx();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->owned, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(DP_E_HIP, std::string("hipStreamCreate failed: ") + hipGetErrorString(e));
+    }
+    c->stream = c->owned;
+  }
+  *out = c;
+  return DP_OK;
+}
+
+dp_status dp_ctx_set_stream(dp_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(DP_E_INVALID, "dp_ctx_set_stream: NULL ctx");
+  if (!hip_stream && !ctx->owned) {
+    DP_HIP_TRY(hipSetDevice(ctx->device));
+    DP_HIP_TRY(hipStreamCreateWithFlags(&ctx->owned, hipStreamNonBlocking));
+  }
+  ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->owned;
+  return DP_OK;
+}
+
+dp_status dp_ctx_synchronize(dp_ctx *ctx) {
+  if (!ctx) return fail(DP_E_INVALID, "dp_ctx_synchronize: NULL ctx");
+  DP_HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return DP_OK;
+}
+
+void dp_ctx_destroy(dp_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->owned) {
+    (void)hipStreamSynchronize(ctx->owned);
+    (void)hipStreamDestroy(ctx->owned);
+  }
+  delete ctx;
+}
+
+dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out) {
+  if (ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(DP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  return dp::compile_design(ctx, netlist, out);
+}
+
+dp_status dp_design_info(const dp_design *d, dp_design_info_t *out) {
+  if (!d || !out) return fail(DP_E_INVALID, "dp_design_info: NULL argument");
+  out->n_pi = d->n_pi;
+  out->n_gates = d->n_gates;
+  out->n_nets = d->n_nets;
+  out->depth = d->depth;
+  out->n_edges = d->n_edges;
+  out->max_level_width = d->max_level_width;
+  out->reserved = 0;
+  out->device_bytes = d->device_bytes;
+  return DP_OK;
+}
+
+dp_status dp_design_levels(const dp_design *d, int32_t *level) {
+  if (!d || !level) return fail(DP_E_INVALID, "dp_design_levels: NULL argument");
+  std::memcpy(level, d->h_level.data(), sizeof(int32_t) * d->n_nets);
+  return DP_OK;
+}
+
+void dp_design_destroy(dp_design *d) {
+  if (!d) return;
+  (void)hipStreamSynchronize(d->ctx->stream);
+  delete d;
+}
+
+dp_status dp_eval_create(dp_design *d, int32_t n_cols, int32_t n_size, const dp_params *params,
+                         dp_eval **out) {
+  if (!d || !out) return fail(DP_E_INVALID, "dp_eval_create: NULL argument");
+  if (n_cols < 1 || n_size < 0) return fail(DP_E_INVALID, "dp_eval_create: need B >= 1, S >= 0");
+  DP_TRY(check_params(params));
+  DP_HIP_TRY(hipSetDevice(d->ctx->device));
+  auto *ev = new dp_eval();
+  ev->d = d;
+  ev->B = n_cols;
+  ev->S = n_size;
+  ev->prm = *params;
+  dp_status st = ev->sp.alloc((size_t)d->n_nets * n_cols * sizeof(float));
+  if (st == DP_OK) st = ev->cap.alloc((size_t)d->n_nets * sizeof(float));
+  if (st == DP_OK && n_size > 0) st = ev->size.alloc((size_t)n_size * d->n_gates * sizeof(float));
+  if (st != DP_OK) {
+    delete ev;
+    return st;
+  }
+  *out = ev;
+  return DP_OK;
+}
+
+dp_status dp_eval_set_params(dp_eval *ev, const dp_params *params) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_set_params: NULL eval");
+  DP_TRY(check_params(params));
+  ev->prm = *params;
+  ev->inputs_version++;
+  return DP_OK;
+}
+
+void dp_eval_destroy(dp_eval *ev) {
+  if (!ev) return;
+  (void)hipStreamSynchronize(ev->d->ctx->stream);
+  delete ev;
+}
+
+dp_status dp_set_pi_prob(dp_eval *ev, const float *p, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_pi_prob: NULL eval");
+  const dp_design *d = ev->d;
+  const int64_t n = (int64_t)ev->B * d->n_pi;
+  if (n == 0) {
+    ev->have_pi = true;
+    ev->inputs_version++;
+    return DP_OK;
+  }
+  DP_TRY(check_values(ev, p, n, 0.0f, 1.0f, on_device, "dp_set_pi_prob"));
+  hipStream_t s = d->ctx->stream;
+  DP_TRY(stage_in(ev->p_stage, p, n * sizeof(float), on_device, s));
+  DP_HIP_TRY(dp::launch_load_pi(ev->p_stage.as<float>(), ev->sp.as<float>(), d->n_pi, ev->B, s));
+  if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  ev->have_pi = true;
+  ev->inputs_version++;
+  return DP_OK;
+}
+
+dp_status dp_set_caps(dp_eval *ev, const float *cap, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_caps: NULL eval");
+  const dp_design *d = ev->d;
+  DP_TRY(check_values(ev, cap, d->n_nets, 0.0f, 3.0e38f, on_device, "dp_set_caps"));
+  hipStream_t s = d->ctx->stream;
+  DP_TRY(stage_in(ev->cap_stage, cap, (size_t)d->n_nets * sizeof(float), on_device, s));
+  DP_HIP_TRY(dp::launch_gather_nets_f32(ev->cap_stage.as<float>(), d->int2ext.as<int32_t>(),
+                                        ev->cap.as<float>(), d->n_nets, s));
+  if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  ev->have_cap = true;
+  ev->inputs_version++;
+  return DP_OK;
+}
+
+dp_status dp_set_cell_sizes(dp_eval *ev, const float *size, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_cell_sizes: NULL eval");
+  if (ev->S == 0) return fail(DP_E_INVALID, "dp_set_cell_sizes: eval was created with S = 0");
+  const dp_design *d = ev->d;
+  const int64_t n = (int64_t)ev->S * d->n_gates;
+  DP_TRY(check_values(ev, size, n, 0.0f, 3.0e38f, on_device, "dp_set_cell_sizes"));
+  hipStream_t s = d->ctx->stream;
+  DP_TRY(stage_in(ev->size_stage, size, n * sizeof(float), on_device, s));
+  DP_HIP_TRY(dp::launch_import_sizes(ev->size_stage.as<float>(), d->int2ext.as<int32_t>(),
+                                     ev->size.as<float>(), d->n_pi, d->n_gates, ev->S, s));
+  if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  ev->have_size = true;
+  ev->inputs_version++;
+  return DP_OK;
+}
+
+dp_status dp_set_beta(dp_eval *ev, const float *beta, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_beta: NULL eval");
+  const dp_design *d = ev->d;
+  const int64_t n = (int64_t)ev->B * d->n_nets;
+  DP_TRY(check_values(ev, beta, n, 0.0f, 3.0e38f, on_device, "dp_set_beta"));
+  hipStream_t s = d->ctx->stream;
+  DP_TRY(ev->beta_frozen.alloc(n * sizeof(float)));
+  DP_TRY(stage_in(ev->beta_stage, beta, n * sizeof(float), on_device, s));
+  DP_HIP_TRY(dp::launch_import_cols_f32(ev->beta_stage.as<float>(), d->int2ext.as<int32_t>(),
+                                        ev->beta_frozen.as<float>(), d->n_nets, ev->B, s));
+  if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  ev->have_beta = true;
+  ev->inputs_version++;
+  return DP_OK;
+}
+
+dp_status dp_set_stimulus(dp_eval *ev, const uint64_t *words, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_stimulus: NULL eval");
+  ev->inputs_version++;
+  if (!words) {
+    ev->have_stim = false;
+    return DP_OK;
+  }
+  const dp_design *d = ev->d;
+  const int64_t T = n_words(ev->prm);
+  if (T <= 0) return fail(DP_E_INVALID, "dp_set_stimulus: params.n_sim is 0");
+  const size_t bytes = (size_t)ev->B * d->n_pi * T * sizeof(uint64_t);
+  hipStream_t s = d->ctx->stream;
+  DP_TRY(stage_in(ev->stim, words, bytes, on_device, s));
+  if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  ev->have_stim = true;
+  return DP_OK;
+}
+
+dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_chunk,
+                               int32_t sim_pairs_per_lane) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_set_schedule: NULL eval");
+  if (schedule < DP_SCHED_AUTO || schedule > DP_SCHED_GRAPH)
+    return fail(DP_E_INVALID, "dp_eval_set_schedule: unknown schedule");
+  if (words_per_chunk < 0 || (words_per_chunk > 0 && words_per_chunk < 2))
+    return fail(DP_E_INVALID, "dp_eval_set_schedule: words_per_chunk must be 0 or >= 2");
+  if (!(sim_pairs_per_lane == 0 || sim_pairs_per_lane == 1 || sim_pairs_per_lane == 2 ||
+        sim_pairs_per_lane == 4 || sim_pairs_per_lane == 8))
+    return fail(DP_E_INVALID, "dp_eval_set_schedule: sim_pairs_per_lane must be 0, 1, 2, 4 or 8");
+  ev->schedule = schedule;
+  ev->words_per_chunk = words_per_chunk;
+  ev->sim_iters = sim_pairs_per_lane;
+  return DP_OK;
+}
+
+dp_status dp_eval_profile(dp_eval *ev, int32_t enable) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_profile: NULL eval");
+  ev->profiling = enable != 0;
+  ev->prof = dp_profile{};
+  return DP_OK;
+}
+
+dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out) {
+  if (!ev || !out) return fail(DP_E_INVALID, "dp_eval_get_profile: NULL argument");
+  DP_TRY(resolve_profile(ev));
+  *out = ev->prof;
+  return DP_OK;
+}
+
+dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out) {
+  if (!ev) return fail(DP_E_INVALID, "dp_forward: NULL eval");
+  const dp_design *d = ev->d;
+  if (!ev->have_pi) return fail(DP_E_STATE, "dp_forward: PI probabilities not set");
+  if (!ev->have_cap) return fail(DP_E_STATE, "dp_forward: capacitances not set");
+  if (ev->S > 0 && !ev->have_size) return fail(DP_E_STATE, "dp_forward: cell sizes not set");
+  if (ev->prm.mode == DP_FROZEN_BETA && !ev->have_beta)
+    return fail(DP_E_STATE, "dp_forward: DP_FROZEN_BETA needs dp_set_beta");
+  const bool hyb = hybrid(ev);
+  if (out && !hyb && (out->sp_acc || out->tr_acc || out->ones || out->toggles))
+    return fail(DP_E_INVALID, "dp_forward: simulation outputs need DP_HYBRID");
+  if (hyb && ev->have_stim &&
+      ev->stim.bytes < (size_t)ev->B * d->n_pi * n_words(ev->prm) * sizeof(uint64_t))
+    return fail(DP_E_STATE, "dp_forward: the explicit stimulus is shorter than n_sim/64 words");
+  DP_HIP_TRY(hipSetDevice(d->ctx->device));
+  hipStream_t s = d->ctx->stream;
+  ChunkPlan plan;
+  if (hyb) plan = plan_chunks(ev);
+  const ChunkPlan *pl = hyb ? &plan : nullptr;
+  DP_TRY(ensure_forward_buffers(ev, pl));
+  const bool use_graph = ev->schedule == DP_SCHED_GRAPH && !ev->profiling;
+  if (use_graph) {
+    const uint64_t key = graph_key(ev, pl);
+    if (!ev->graph_fwd || ev->graph_key != key) DP_TRY(capture_forward(ev, pl, key));
+    DP_HIP_TRY(hipGraphLaunch(ev->graph_fwd, s));
+  } else {
+    DP_TRY(enqueue_forward(ev, pl));
+  }
+  ev->fwd_version = ev->inputs_version;
+  if (out) {
+    OutMap om{ev, out->on_device};
+    const int64_t nb = (int64_t)d->n_nets * ev->B;
+    dp::ExportArgs ea{};
+    ea.sp = ev->sp.as<float>();
+    ea.beta = ev->beta.as<float>();
+    ea.ones = hyb ? ev->ones.as<uint32_t>() : nullptr;
+    ea.tog = hyb ? ev->tog.as<uint32_t>() : nullptr;
+    ea.int2ext = d->int2ext.as<int32_t>();
+    ea.T = hyb ? plan.T : 0;
+    ea.n_nets = d->n_nets;
+    ea.B = ev->B;
+    DP_TRY(om.map(out->sp, nb, &ea.o_sp));
+    DP_TRY(om.map(out->tr, nb, &ea.o_tr));
+    DP_TRY(om.map(out->sp_acc, nb, &ea.o_sp_acc));
+    DP_TRY(om.map(out->tr_acc, nb, &ea.o_tr_acc));
+    DP_TRY(om.map(out->beta, nb, &ea.o_beta));
+    DP_TRY(om.map(out->tr_hyb, nb, &ea.o_tr_hyb));
+    DP_TRY(om.map(out->ones, nb, &ea.o_ones));
+    DP_TRY(om.map(out->toggles, nb, &ea.o_tog));
+    if (ea.o_sp || ea.o_tr || ea.o_sp_acc || ea.o_tr_acc || ea.o_beta || ea.o_tr_hyb || ea.o_ones ||
+        ea.o_tog)
+      DP_HIP_TRY(dp::launch_export(ea, s));
+    if (out->power) {
+      const size_t bytes = (size_t)ev->B * s_prime(ev) * sizeof(float);
+      DP_HIP_TRY(hipMemcpyAsync(out->power, ev->power.ptr, bytes,
+                                out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    }
+    DP_TRY(om.flush(s));
+    if (!out->on_device && out->power) DP_HIP_TRY(hipStreamSynchronize(s));
+  }
+  return DP_OK;
+}
+
+static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_column,
+                              float *dpi, float *dcap, float *dsize, int32_t on_device) {
+  const dp_design *d = ev->d;
+  if (ev->fwd_version != ev->inputs_version || ev->fwd_version == 0)
+    return fail(DP_E_STATE, "dp_backward: no completed forward for the current inputs");
+  DP_HIP_TRY(hipSetDevice(d->ctx->device));
+  hipStream_t s = d->ctx->stream;
+  const int32_t Sp = s_prime(ev);
+  const int32_t cols = ev->B * Sp;
+  const int32_t C = per_column ? cols : ev->B;
+  const float *w = nullptr;
+  if (grad_power) {
+    DP_TRY(check_values(ev, grad_power, cols, -3.0e38f, 3.0e38f, on_device, "dp_backward grad"));
+    DP_TRY(stage_in(ev->w, grad_power, (size_t)cols * sizeof(float), on_device, s));
+    w = ev->w.as<float>();
+  }
+  const dp::GraphView g = view(d);
+  if (dpi) {
+    DP_TRY(ev->seed.alloc((size_t)d->n_nets * C * sizeof(float)));
+    DP_TRY(ev->contrib.alloc((size_t)3 * d->n_gates * C * sizeof(float)));
+    dp::SeedArgs sa{};
+    sa.seed_base = ev->seed_base.as<float>();
+    sa.w = w;
+    sa.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
+    sa.seed = ev->seed.as<float>();
+    sa.n_pi = d->n_pi;
+    sa.n_nets = d->n_nets;
+    sa.G = d->n_gates;
+    sa.B = ev->B;
+    sa.S = ev->S;
+    sa.per_column = per_column;
+    DP_HIP_TRY(dp::launch_seed(sa, s));
+    dp::BwdArgs ba{};
+    ba.sp = ev->sp.as<float>();
+    ba.beta = ev->beta.as<float>();
+    ba.seed = ev->seed.as<float>();
+    ba.contrib = ev->contrib.as<float>();
+    ba.B = ev->B;
+    ba.C = C;
+    ba.cdiv = per_column ? Sp : 1;
+    ba.ste = ev->prm.beta_grad == DP_BETA_STE;
+    for (int32_t l = d->depth; l >= 1; --l) {
+      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+      SpanGuard sg(ev, SPAN_BWD, bwd_level_bytes(d, l, C), ev->profiling);
+      DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
+    }
+    float *dst = dpi;
+    const size_t bytes = (size_t)C * d->n_pi * sizeof(float);
+    if (!on_device) {
+      DP_TRY(ev->pi_out.alloc(std::max<size_t>(bytes, 16)));
+      dst = ev->pi_out.as<float>();
+    }
+    DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
+    if (!on_device && bytes)
+      DP_HIP_TRY(hipMemcpyAsync(dpi, dst, bytes, hipMemcpyDeviceToHost, s));
+  }
+  if (dcap || (dsize && ev->S > 0)) {
+    OutMap om{ev, on_device};
+    dp::GradExportArgs ga{};
+    ga.xterm = ev->xterm.as<float>();
+    ga.cap = ev->cap.as<float>();
+    ga.w = w;
+    ga.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
+    ga.int2ext = d->int2ext.as<int32_t>();
+    ga.n_pi = d->n_pi;
+    ga.n_nets = d->n_nets;
+    ga.G = d->n_gates;
+    ga.B = ev->B;
+    ga.S = ev->S;
+    DP_TRY(om.map(dcap, (size_t)d->n_nets, &ga.dcap));
+    if (ev->S > 0) DP_TRY(om.map(dsize, (size_t)ev->S * d->n_gates, &ga.dsize));
+    DP_HIP_TRY(dp::launch_grad_export(ga, s));
+    DP_TRY(om.flush(s));
+  }
+  if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  return DP_OK;
+}
+
+dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi, float *dpower_dcap,
+                      float *dpower_dsize, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_backward: NULL eval");
+  if (dpower_dsize && ev->S == 0)
+    return fail(DP_E_INVALID, "dp_backward: dpower_dsize needs cell sizes (S > 0)");
+  return run_backward(ev, grad_power, 0, dpower_dpi, dpower_dcap, dpower_dsize, on_device);
+}
+
+dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_backward_columns: NULL eval");
+  if (!dpower_dpi) return fail(DP_E_INVALID, "dp_backward_columns: NULL output");
+  return run_backward(ev, nullptr, 1, dpower_dpi, nullptr, nullptr, on_device);
+}
+
+}  // extern "C"

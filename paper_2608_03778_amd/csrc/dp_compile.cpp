@@ -1,0 +1,198 @@
+// Design compilation (host): the levelized graph of Sec. III-A.
+//
+// The paper levelizes a pin-level DAG so that every node of level L depends
+// only on levels < L and all nodes of a level run in one launch.  Here the
+// graph is net-level: a sink pin always carries its driver's value, so the
+// per-level wire copy of Alg. 2 folds into the gate's gather, and power,
+// which sums over nets (Eq. 1), is unchanged.
+//
+// Steps: validate -> ASAP levels with Kahn's algorithm (cycle detection) ->
+// counting sort of gates by (level, cell, caller id) -> renumber nets so
+// level l's outputs are one contiguous range and a gate's output id is
+// implicit -> per-pin fan-in arrays (structure of arrays) -> fan-out lists
+// (reverse CSR, edges in ascending order, which fixes the summation order
+// of the reverse sweep) -> upload.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "dp_internal.h"
+
+namespace dp {
+
+static const int kArity[DP_N_OPS] = {1, 1, 2, 2, 2, 2, 2, 3, 3};
+
+dp_status DevBuf::alloc(size_t n) {
+  if (n <= bytes && ptr) return DP_OK;
+  release();
+  if (n == 0) n = 16;
+  hipError_t e = hipMalloc(&ptr, n);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(DP_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed: " +
+                              hipGetErrorString(e));
+  }
+  bytes = n;
+  return DP_OK;
+}
+
+template <class T>
+static dp_status upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
+  DP_TRY(buf.alloc(std::max<size_t>(v.size() * sizeof(T), 16)));
+  if (!v.empty())
+    DP_HIP_TRY(hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T),
+                              hipMemcpyHostToDevice, s));
+  return DP_OK;
+}
+
+dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
+  if (!ctx || !nl || !out) return fail(DP_E_INVALID, "dp_compile: NULL argument");
+  const int32_t n_pi = nl->n_pi, G = nl->n_gates;
+  if (n_pi < 0 || G < 0) return fail(DP_E_INVALID, "dp_compile: negative size");
+  if ((int64_t)n_pi + G > INT32_MAX / 2)
+    return fail(DP_E_INVALID, "dp_compile: too many nets");
+  if (G > 0 && (!nl->op || !nl->fanin_ptr || !nl->fanin))
+    return fail(DP_E_INVALID, "dp_compile: NULL netlist array");
+  const int32_t n_nets = n_pi + G;
+  if (G > 0 && nl->fanin_ptr[0] != 0)
+    return fail(DP_E_INVALID, "dp_compile: fanin_ptr[0] must be 0");
+  for (int32_t g = 0; g < G; ++g) {
+    if (nl->op[g] >= DP_N_OPS)
+      return fail(DP_E_INVALID, "dp_compile: gate " + std::to_string(g) + " has unknown cell " +
+                                    std::to_string(nl->op[g]));
+    if (nl->fanin_ptr[g + 1] - nl->fanin_ptr[g] != kArity[nl->op[g]])
+      return fail(DP_E_INVALID, "dp_compile: gate " + std::to_string(g) +
+                                    " has the wrong number of inputs");
+    for (int32_t e = nl->fanin_ptr[g]; e < nl->fanin_ptr[g + 1]; ++e)
+      if (nl->fanin[e] < 0 || nl->fanin[e] >= n_nets)
+        return fail(DP_E_INVALID, "dp_compile: gate " + std::to_string(g) +
+                                      " reads net id out of range");
+  }
+  const int64_t n_edges = G > 0 ? nl->fanin_ptr[G] : 0;
+
+  // --- ASAP levels by Kahn's algorithm over gate->gate edges
+  std::vector<int32_t> indeg(G, 0), cons_ptr(G + 1, 0), cons;
+  for (int32_t g = 0; g < G; ++g)
+    for (int32_t e = nl->fanin_ptr[g]; e < nl->fanin_ptr[g + 1]; ++e)
+      if (nl->fanin[e] >= n_pi) {
+        ++indeg[g];
+        ++cons_ptr[nl->fanin[e] - n_pi + 1];
+      }
+  for (int32_t d = 0; d < G; ++d) cons_ptr[d + 1] += cons_ptr[d];
+  cons.resize(cons_ptr[G]);
+  {
+    std::vector<int32_t> fill(cons_ptr.begin(), cons_ptr.end() - 1);
+    for (int32_t g = 0; g < G; ++g)
+      for (int32_t e = nl->fanin_ptr[g]; e < nl->fanin_ptr[g + 1]; ++e)
+        if (nl->fanin[e] >= n_pi) cons[fill[nl->fanin[e] - n_pi]++] = g;
+  }
+  std::vector<int32_t> level(n_nets, 0), queue;
+  queue.reserve(G);
+  for (int32_t g = 0; g < G; ++g)
+    if (indeg[g] == 0) queue.push_back(g);
+  for (size_t h = 0; h < queue.size(); ++h) {
+    int32_t g = queue[h];
+    int32_t l = 0;
+    for (int32_t e = nl->fanin_ptr[g]; e < nl->fanin_ptr[g + 1]; ++e)
+      l = std::max(l, level[nl->fanin[e]]);
+    level[n_pi + g] = l + 1;
+    for (int32_t c = cons_ptr[g]; c < cons_ptr[g + 1]; ++c)
+      if (--indeg[cons[c]] == 0) queue.push_back(cons[c]);
+  }
+  if ((int32_t)queue.size() != G)
+    return fail(DP_E_CYCLE, "dp_compile: the netlist has a combinational cycle (" +
+                                std::to_string(G - (int32_t)queue.size()) +
+                                " gates on or behind it)");
+  int32_t depth = 0;
+  for (int32_t g = 0; g < G; ++g) depth = std::max(depth, level[n_pi + g]);
+
+  // --- counting sort by (level, cell); stable, so caller id breaks ties
+  const int32_t n_keys = (depth + 1) * DP_N_OPS;
+  std::vector<int32_t> key_ptr(n_keys + 1, 0);
+  for (int32_t g = 0; g < G; ++g) ++key_ptr[level[n_pi + g] * DP_N_OPS + nl->op[g] + 1];
+  for (int32_t k = 0; k < n_keys; ++k) key_ptr[k + 1] += key_ptr[k];
+  std::vector<int32_t> gate_of(G);  // internal -> caller gate
+  {
+    std::vector<int32_t> fill(key_ptr.begin(), key_ptr.end() - 1);
+    for (int32_t g = 0; g < G; ++g) gate_of[fill[level[n_pi + g] * DP_N_OPS + nl->op[g]]++] = g;
+  }
+  auto *d = new dp_design();
+  d->ctx = ctx;
+  d->n_pi = n_pi;
+  d->n_gates = G;
+  d->n_nets = n_nets;
+  d->depth = depth;
+  d->n_edges = n_edges;
+  d->level_ptr.assign(depth + 2, 0);
+  for (int32_t l = 1; l <= depth + 1; ++l)
+    d->level_ptr[l] = (l <= depth) ? key_ptr[l * DP_N_OPS] : G;
+  d->level_ptr[0] = 0;
+  for (int32_t l = 1; l <= depth; ++l)
+    d->max_level_width = std::max(d->max_level_width, d->level_ptr[l + 1] - d->level_ptr[l]);
+  d->h_level = level;
+  d->h_int2ext.resize(n_nets);
+  d->h_ext2int.resize(n_nets);
+  for (int32_t i = 0; i < n_pi; ++i) d->h_int2ext[i] = d->h_ext2int[i] = i;
+  for (int32_t gi = 0; gi < G; ++gi) {
+    d->h_int2ext[n_pi + gi] = n_pi + gate_of[gi];
+    d->h_ext2int[n_pi + gate_of[gi]] = n_pi + gi;
+  }
+  d->h_op.resize(G);
+  d->h_arity_prefix.assign(G + 1, 0);
+  std::vector<int32_t> in(3 * (size_t)G, 0);
+  std::vector<int32_t> rev_ptr(n_nets + 1, 0), rev_edge(n_edges);
+  for (int32_t gi = 0; gi < G; ++gi) {
+    int32_t g = gate_of[gi];
+    d->h_op[gi] = nl->op[g];
+    int32_t k = nl->fanin_ptr[g + 1] - nl->fanin_ptr[g];
+    d->h_arity_prefix[gi + 1] = d->h_arity_prefix[gi] + k;
+    for (int32_t j = 0; j < 3; ++j) {
+      // unused pins alias pin 0 so that no index is ever out of range
+      int32_t e = nl->fanin_ptr[g] + (j < k ? j : 0);
+      in[(size_t)j * G + gi] = d->h_ext2int[nl->fanin[e]];
+    }
+    for (int32_t j = 0; j < k; ++j) ++rev_ptr[in[(size_t)j * G + gi] + 1];
+  }
+  for (int32_t n = 0; n < n_nets; ++n) rev_ptr[n + 1] += rev_ptr[n];
+  {
+    // ascending internal gate, then pin: a fixed order for the reverse sums
+    std::vector<int32_t> fill(rev_ptr.begin(), rev_ptr.end() - 1);
+    for (int32_t gi = 0; gi < G; ++gi) {
+      int32_t k = d->h_arity_prefix[gi + 1] - d->h_arity_prefix[gi];
+      for (int32_t j = 0; j < k; ++j) {
+        int32_t src = in[(size_t)j * G + gi];
+        rev_edge[fill[src]++] = j * G + gi;
+      }
+    }
+  }
+  d->lvl_pins.assign(depth + 1, 0);
+  d->lvl_fanout.assign(depth + 1, 0);
+  for (int32_t l = 1; l <= depth; ++l)
+    for (int32_t gi = d->level_ptr[l]; gi < d->level_ptr[l + 1]; ++gi) {
+      d->lvl_pins[l] += d->h_arity_prefix[gi + 1] - d->h_arity_prefix[gi];
+      d->lvl_fanout[l] += rev_ptr[n_pi + gi + 1] - rev_ptr[n_pi + gi];
+    }
+  d->lvl_fanout[0] = rev_ptr[n_pi] - rev_ptr[0];
+  hipStream_t s = ctx->stream;
+  dp_status st = DP_OK;
+  if ((st = upload(d->op, d->h_op, s)) != DP_OK || (st = upload(d->in, in, s)) != DP_OK ||
+      (st = upload(d->rev_ptr, rev_ptr, s)) != DP_OK ||
+      (st = upload(d->rev_edge, rev_edge, s)) != DP_OK ||
+      (st = upload(d->int2ext, d->h_int2ext, s)) != DP_OK ||
+      (st = upload(d->ext2int, d->h_ext2int, s)) != DP_OK) {
+    delete d;
+    return st;
+  }
+  hipError_t e = hipStreamSynchronize(s);  // host vectors above go out of scope
+  if (e != hipSuccess) {
+    delete d;
+    return fail(DP_E_HIP, std::string("dp_compile: upload failed: ") + hipGetErrorString(e));
+  }
+  d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
+                              d->int2ext.bytes + d->ext2int.bytes);
+  *out = d;
+  return DP_OK;
+}
+
+}  // namespace dp

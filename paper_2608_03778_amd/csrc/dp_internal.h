@@ -1,0 +1,89 @@
+// Internal structures of libdiffpower (host side).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/diffpower.h"
+
+namespace dp {
+
+// Thread-local error message plus status helper.
+dp_status fail(dp_status st, const std::string &msg);
+void clear_error();
+
+#define DP_HIP_TRY(expr)                                                     \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess)                                                    \
+      return ::dp::fail(DP_E_HIP, std::string(#expr " failed: ") +           \
+                                      hipGetErrorString(_e));                \
+  } while (0)
+
+#define DP_TRY(expr)                 \
+  do {                               \
+    dp_status _s = (expr);           \
+    if (_s != DP_OK) return _s;      \
+  } while (0)
+
+// A device allocation that frees itself.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  dp_status alloc(size_t n);  // keeps the buffer if already large enough
+  template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+}  // namespace dp
+
+struct dp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // stream calls enqueue on
+  hipStream_t owned = nullptr;    // stream created by the library, if any
+};
+
+// Immutable compiled design.  Internal numbering: PIs keep ids [0, n_pi);
+// gates are sorted by (level, cell, caller id) and gate g' drives internal
+// net n_pi + g'.  Level l (1..depth) holds gates [level_ptr[l], level_ptr[l+1]).
+struct dp_design {
+  dp_ctx *ctx = nullptr;
+  int32_t n_pi = 0, n_gates = 0, n_nets = 0, depth = 0;
+  int64_t n_edges = 0;
+  std::vector<int32_t> level_ptr;     // [depth + 2], level_ptr[1] = 0
+  std::vector<int32_t> h_level;       // caller numbering, [n_nets]
+  std::vector<uint8_t> h_op;          // internal order
+  std::vector<int32_t> h_arity_prefix;  // [n_gates+1] internal order (for byte counts)
+  std::vector<int32_t> h_int2ext;     // [n_nets]
+  std::vector<int32_t> h_ext2int;     // [n_nets]
+  int32_t max_level_width = 0;
+  std::vector<int64_t> lvl_pins;      // [depth + 1] fan-in pins of the level's gates
+  std::vector<int64_t> lvl_fanout;    // [depth + 1] fan-out edges of the level's nets (0 = PIs)
+  // device arrays
+  dp::DevBuf op;        // uint8 [n_gates]
+  dp::DevBuf in;        // int32 [3][n_gates] input net of pin j (SoA)
+  dp::DevBuf rev_ptr;   // int32 [n_nets + 1] fan-out list offsets
+  dp::DevBuf rev_edge;  // int32 [n_edges] fan-out edges, id = j * n_gates + g'
+  dp::DevBuf int2ext;   // int32 [n_nets]
+  dp::DevBuf ext2int;   // int32 [n_nets]
+  int64_t device_bytes = 0;
+};
+
+namespace dp {
+
+// Host-side compile: validation, levelization, sort, renumbering and the
+// device upload.  Implemented in dp_compile.cpp.
+dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out);
+
+}  // namespace dp

@@ -1,0 +1,158 @@
+// Launch interface of the gfx950 kernels (dp_kernels.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dp {
+
+// Net-level graph arrays in internal numbering (see dp_design).
+struct GraphView {
+  const uint8_t *op;        // [G]
+  const int32_t *in;        // [3][G]
+  const int32_t *rev_ptr;   // [n_nets + 1]
+  const int32_t *rev_edge;  // [n_edges]
+  int32_t n_pi, G, n_nets;
+};
+
+// Simulation word buffer: row r (an internal net) holds words
+// [t0 - halo, t0 - halo + pitch) of the current chunk at W + r * pitch.
+// Local word u counts ones when u in [u_lo, u_hi) and toggles (against
+// word u - 1) when u in [u_tog_lo, u_hi).
+struct ChunkView {
+  uint64_t *W;
+  int64_t pitch;       // words per row (even)
+  int64_t t_first;     // global cycle of local word 0 (t0 - halo)
+  int32_t pairs;       // word pairs per row to compute, ceil(u_hi / 2)
+  int32_t u_lo, u_hi, u_tog_lo;
+};
+
+// Counter arrays [n_nets][B]; this launch adds into column `col`.
+struct CountView {
+  uint32_t *ones, *tog;
+  int32_t B, col;
+};
+
+// SP of one level of B columns, optionally fused into a simulation launch.
+struct SpLevel {
+  float *sp;          // [n_nets][B]
+  int32_t B;
+  int32_t g0, n;      // level gate range (internal ids)
+};
+
+// Tunables of the simulation launch.
+struct SimTune {
+  int32_t iters;      // word pairs per lane per wave: 1, 2, 4 or 8
+};
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+
+// PI probabilities [B][n_pi] (caller layout) -> SP rows [n_pi][B].
+hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t s);
+// Check values are finite and inside [lo, hi]; sets *bad = 1 otherwise.
+hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
+                              hipStream_t s);
+// Caller-numbered per-net array [n_nets] -> internal numbering.
+hipError_t launch_gather_nets_f32(const float *src_ext, const int32_t *int2ext, float *dst_int,
+                                  int32_t n_nets, hipStream_t s);
+// [B][n_nets] caller numbering -> [n_nets][B] internal.
+hipError_t launch_import_cols_f32(const float *src, const int32_t *int2ext, float *dst,
+                                  int32_t n_nets, int32_t B, hipStream_t s);
+// Sizes [S][G] caller gate numbering -> [S][G] internal gate order.
+hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *dst, int32_t n_pi,
+                               int32_t G, int32_t S, hipStream_t s);
+
+// One SP level (modeled sweep).
+hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s);
+
+// PI rows of one chunk: Philox stimulus (stim == nullptr) or explicit words
+// stim[i][T]; counts ones/toggles of the PI nets.
+hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
+                           const float *p_col /* [n_pi][B] SP rows, column cnt.col */,
+                           const uint64_t *stim, int64_t T, uint64_t seed, const SimTune &tune,
+                           hipStream_t s);
+
+// One simulation level of one chunk, with the level's SP fused in when
+// sp != nullptr.
+hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
+                            int32_t g0, int32_t n, const SpLevel *sp, const SimTune &tune,
+                            hipStream_t s);
+
+// Finalize per internal net and column: beta, X = kappa*beta*TR_model, the
+// local adjoint seed base, optional caller-numbered exports.
+struct FinalizeArgs {
+  const float *sp;          // [n_nets][B]
+  const uint32_t *ones, *tog;  // [n_nets][B] or null (modeled)
+  const float *beta_frozen; // [n_nets][B] or null
+  const float *cap;         // [n_nets] internal
+  int64_t T;                // simulated words
+  float kappa, beta_min, beta_max;
+  int32_t mode, ste;
+  float *beta;              // out [n_nets][B]
+  float *xterm;             // out [n_nets][B] kappa * beta * TR_model
+  float *seed_base;         // out [n_nets][B] local adjoint term without s
+  int32_t n_nets, B;
+};
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+
+// Caller-numbered exports of forward quantities, [B][n_nets].
+struct ExportArgs {
+  const float *sp, *beta;
+  const uint32_t *ones, *tog;
+  const int32_t *int2ext;
+  int64_t T;
+  float *o_sp, *o_tr, *o_sp_acc, *o_tr_acc, *o_beta, *o_tr_hyb;
+  uint32_t *o_ones, *o_tog;
+  int32_t n_nets, B;
+};
+hipError_t launch_export(const ExportArgs &a, hipStream_t s);
+
+// Power P[b][s] = sum_n xterm[n][b] * cap[n] * size_s(n), double accumulation
+// in a fixed order.  partial: [n_chunks][B*S'] doubles.
+struct PowerArgs {
+  const float *xterm, *cap, *size;  // size: [S][G] internal or null
+  int32_t n_pi, n_nets, G, B, S;    // S = 0: no sizes
+  double *partial;                  // scratch
+  int32_t n_chunks;
+  float *power;                     // [B][S'] (device)
+};
+int32_t power_chunks(int32_t n_nets);
+hipError_t launch_power(const PowerArgs &a, hipStream_t s);
+
+// Reverse sweep.  Columns c in [0, C); the SP column of c is c / cdiv.
+struct BwdArgs {
+  const float *sp;            // [n_nets][B]
+  const float *beta;          // [n_nets][B]  (STE only)
+  float *seed;                // [n_nets][C]
+  float *contrib;             // [3][G][C]
+  int32_t B, C, cdiv, ste;
+};
+// seed[n][c] from seed_base, upstream weights w[b][s] and sizes.
+struct SeedArgs {
+  const float *seed_base;     // [n_nets][B]
+  const float *w;             // [B][S'] device (null = 1)
+  const float *size;          // [S][G] internal or null
+  float *seed;                // [n_nets][C]
+  int32_t n_pi, n_nets, G, B, S, per_column;
+};
+hipError_t launch_seed(const SeedArgs &a, hipStream_t s);
+hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
+                            hipStream_t s);
+// PI adjoints -> out[c][n_pi].
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s);
+// dcap[ext n] = sum_b xterm[n][b]/cap... computed as kappa*beta*TR * wsum.
+struct GradExportArgs {
+  const float *xterm;         // [n_nets][B]
+  const float *cap;           // [n_nets]
+  const float *w;             // [B][S'] or null
+  const float *size;          // [S][G] internal or null
+  const int32_t *int2ext;
+  int32_t n_pi, n_nets, G, B, S;
+  float *dcap;                // [n_nets] caller numbering (sum over b, s) or null
+  float *dsize;               // [S][G] caller gate numbering (sum over b) or null
+};
+hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t s);
+
+}  // namespace dp

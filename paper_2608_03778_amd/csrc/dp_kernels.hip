@@ -1,0 +1,747 @@
+// gfx950 kernels of the DiffPower hot path.
+//
+// Layouts (internal net numbering, see dp_design):
+//   SP, beta, xterm, seed_base     float  [n_nets][B]      (query column innermost)
+//   seed                           float  [n_nets][C]      (C reverse-sweep columns)
+//   contrib                        float  [3][G][C]        (one slot per fan-in pin)
+//   simulation words W             uint64 [n_nets][pitch]  (one chunk of cycles)
+//   ones, toggles                  uint32 [n_nets][B]
+//
+// Work mapping: the SP, finalize and reverse kernels give one lane to each
+// (gate or net, column).  The simulation kernel gives one 64-lane wave to a
+// (gate, run of word pairs): the wave's cell is uniform, so the cell switch
+// is a scalar branch outside the word loop; each lane moves 16-byte word
+// pairs, so every fan-in row is read as contiguous 1 KiB wave-wide accesses.
+#include "dp_kernels.h"
+
+namespace dp {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// Two consecutive simulation words as one 16-byte vector (a single
+// dwordx4 access per lane).
+typedef uint64_t w2 __attribute__((ext_vector_type(2)));
+
+enum : int { INV = 0, BUF, AND2, OR2, NAND2, NOR2, XOR2, AOI21, MUX2 };
+
+__device__ __forceinline__ int arity_of(int op) { return op < AND2 ? 1 : (op < AOI21 ? 2 : 3); }
+
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+
+// Probability that the cell output is 1 for independent inputs (Sec. II-B;
+// Alg. 2 gives AND = a0 a1 and NAND = 1 - a0 a1).  Forms are chosen so that
+// no term cancels: OR = a + b(1 - a), XOR = a(1 - b) + b(1 - a),
+// MUX = i0 + s (i1 - i0).
+__device__ __forceinline__ float sp_rule(int op, float a, float b, float c) {
+  switch (op) {
+    case INV: return 1.0f - a;
+    case BUF: return a;
+    case AND2: return a * b;
+    case OR2: return fmaf(b, 1.0f - a, a);
+    case NAND2: return fmaf(-a, b, 1.0f);
+    case NOR2: return (1.0f - a) * (1.0f - b);
+    case XOR2: return fmaf(a, 1.0f - b, b * (1.0f - a));
+    case AOI21: return fmaf(-a, b, 1.0f) * (1.0f - c);
+    default: return fmaf(c, b - a, a);  // MUX2
+  }
+}
+
+// Partial derivatives of sp_rule (Sec. III-E).
+__device__ __forceinline__ void sp_partials(int op, float a, float b, float c, float &d0, float &d1,
+                                            float &d2) {
+  d1 = 0.0f;
+  d2 = 0.0f;
+  switch (op) {
+    case INV: d0 = -1.0f; break;
+    case BUF: d0 = 1.0f; break;
+    case AND2: d0 = b; d1 = a; break;
+    case OR2: d0 = 1.0f - b; d1 = 1.0f - a; break;
+    case NAND2: d0 = -b; d1 = -a; break;
+    case NOR2: d0 = b - 1.0f; d1 = a - 1.0f; break;
+    case XOR2: d0 = fmaf(-2.0f, b, 1.0f); d1 = fmaf(-2.0f, a, 1.0f); break;
+    case AOI21: d0 = -b * (1.0f - c); d1 = -a * (1.0f - c); d2 = fmaf(a, b, -1.0f); break;
+    default: d0 = 1.0f - c; d1 = c; d2 = b - a; break;  // MUX2
+  }
+}
+
+// Boolean function of a cell on 64 lanes (Sec. III-C).
+template <int OP>
+__device__ __forceinline__ uint64_t cell_bits(uint64_t a, uint64_t b, uint64_t c) {
+  if constexpr (OP == INV) return ~a;
+  else if constexpr (OP == BUF) return a;
+  else if constexpr (OP == AND2) return a & b;
+  else if constexpr (OP == OR2) return a | b;
+  else if constexpr (OP == NAND2) return ~(a & b);
+  else if constexpr (OP == NOR2) return ~(a | b);
+  else if constexpr (OP == XOR2) return a ^ b;
+  else if constexpr (OP == AOI21) return ~((a & b) | c);
+  else return (a & ~c) | (b & c);  // MUX2
+}
+
+template <int OP>
+constexpr int kArity = OP < AND2 ? 1 : (OP < AOI21 ? 2 : 3);
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ int64_t gidx() {
+  return (int64_t)blockIdx.x * kBlock + threadIdx.x;
+}
+
+// Launches stay below 2^32 threads in total.
+constexpr int64_t kMaxBlocks = (1ll << 32) / kBlock - 1;
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline bool too_big(int64_t items) { return (items + kBlock - 1) / kBlock > kMaxBlocks; }
+
+// ---------------------------------------------------------------- plumbing
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  int64_t i = gidx();
+  if (i < n) p[i] = v;
+}
+__global__ __launch_bounds__(kBlock) void k_fill_f32(float *p, int64_t n, float v) {
+  int64_t i = gidx();
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_load_pi(const float *__restrict__ p,
+                                                     float *__restrict__ sp, int32_t n_pi,
+                                                     int32_t B) {
+  int64_t idx = gidx();
+  if (idx >= (int64_t)n_pi * B) return;
+  int32_t i = (int32_t)(idx / B), b = (int32_t)(idx - (int64_t)i * B);
+  sp[idx] = p[(int64_t)b * n_pi + i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_range(const float *__restrict__ v, int64_t n,
+                                                         float lo, float hi, int32_t *bad) {
+  int64_t i = gidx();
+  if (i >= n) return;
+  float x = v[i];
+  if (!(x >= lo && x <= hi)) *bad = 1;  // NaN fails both comparisons
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_nets(const float *__restrict__ src,
+                                                         const int32_t *__restrict__ int2ext,
+                                                         float *__restrict__ dst, int32_t n) {
+  int64_t i = gidx();
+  if (i < n) dst[i] = src[int2ext[i]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_import_cols(const float *__restrict__ src,
+                                                         const int32_t *__restrict__ int2ext,
+                                                         float *__restrict__ dst, int32_t n_nets,
+                                                         int32_t B) {
+  int64_t idx = gidx();
+  if (idx >= (int64_t)n_nets * B) return;
+  int32_t n = (int32_t)(idx / B), b = (int32_t)(idx - (int64_t)n * B);
+  dst[idx] = src[(int64_t)b * n_nets + int2ext[n]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_import_sizes(const float *__restrict__ src,
+                                                          const int32_t *__restrict__ int2ext,
+                                                          float *__restrict__ dst, int32_t n_pi,
+                                                          int32_t G, int32_t S) {
+  int64_t idx = gidx();
+  if (idx >= (int64_t)G * S) return;
+  int32_t s = (int32_t)(idx / G), g = (int32_t)(idx - (int64_t)s * G);
+  dst[idx] = src[(int64_t)s * G + (int2ext[n_pi + g] - n_pi)];
+}
+
+// ---------------------------------------------------------------- SP level
+// One lane per (gate, column) of level [g0, g0 + n): gather the fan-in
+// probabilities, apply the cell rule, clip to [0, 1] (Alg. 2).
+__device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, int64_t idx) {
+  const int32_t B = lv.B;
+  const int32_t gl = (int32_t)(idx / B);
+  const int32_t b = (int32_t)(idx - (int64_t)gl * B);
+  const int32_t gi = lv.g0 + gl;
+  const int op = g.op[gi];
+  const int k = arity_of(op);
+  const float a = lv.sp[(int64_t)g.in[gi] * B + b];
+  const float bb = k > 1 ? lv.sp[(int64_t)g.in[g.G + gi] * B + b] : 0.0f;
+  const float cc = k > 2 ? lv.sp[(int64_t)g.in[2 * g.G + gi] * B + b] : 0.0f;
+  lv.sp[(int64_t)(g.n_pi + gi) * B + b] = clamp01(sp_rule(op, a, bb, cc));
+}
+
+__global__ __launch_bounds__(kBlock) void k_sp_level(GraphView g, SpLevel lv) {
+  int64_t idx = gidx();
+  if (idx < (int64_t)lv.n * lv.B) sp_item(g, lv, idx);
+}
+
+// ---------------------------------------------------------------- simulation
+// Count ones / toggles of one word pair computed by this lane.  `prev` is the
+// word before the pair's first word.
+__device__ __forceinline__ void count_pair(const ChunkView &c, int32_t p, w2 y, uint64_t prev,
+                                           uint32_t &ones, uint32_t &togs) {
+  const int32_t u0 = 2 * p, u1 = u0 + 1;
+  if (u0 >= c.u_lo && u0 < c.u_hi) ones += __popcll(y.x);
+  if (u1 >= c.u_lo && u1 < c.u_hi) ones += __popcll(y.y);
+  if (u0 >= c.u_tog_lo && u0 < c.u_hi) togs += __popcll(y.x ^ prev);
+  if (u1 >= c.u_tog_lo && u1 < c.u_hi) togs += __popcll(y.y ^ y.x);
+}
+
+// One gate's row over pairs [p_begin, p_begin + 64*ITERS): loads of all
+// iterations are issued before any store so they overlap in flight.  Rows
+// are addressed as 16-byte word pairs so each lane moves one pair per access.
+template <int OP, int ITERS>
+__device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
+                                             const w2 *__restrict__ r1,
+                                             const w2 *__restrict__ r2,
+                                             w2 *__restrict__ out, int32_t p_begin,
+                                             const ChunkView &c, int lane, uint32_t &ones,
+                                             uint32_t &togs) {
+  constexpr int K = kArity<OP>;
+  uint64_t carry = 0;
+  if (p_begin > 0) {  // word just before this run, recomputed from its inputs
+    const int32_t q = p_begin - 1;
+    carry = cell_bits<OP>(r0[q].y, K > 1 ? r1[q].y : 0, K > 2 ? r2[q].y : 0);
+  }
+  w2 x0[ITERS], x1[ITERS], x2[ITERS];
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int32_t p = p_begin + it * 64 + lane;
+    const bool ok = p < c.pairs;
+    const w2 z = w2{0, 0};
+    x0[it] = ok ? r0[p] : z;
+    x1[it] = (ok && K > 1) ? r1[p] : z;
+    x2[it] = (ok && K > 2) ? r2[p] : z;
+  }
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int32_t p = p_begin + it * 64 + lane;
+    w2 y;
+    y.x = cell_bits<OP>(x0[it].x, x1[it].x, x2[it].x);
+    y.y = cell_bits<OP>(x0[it].y, x1[it].y, x2[it].y);
+    uint64_t prev = __shfl_up(y.y, 1u);
+    if (lane == 0) prev = carry;
+    carry = __shfl(y.y, 63);
+    if (p < c.pairs) {
+      out[p] = y;
+      count_pair(c, p, y, prev, ones, togs);
+    }
+  }
+}
+
+template <int ITERS>
+__global__ __launch_bounds__(kBlock) void k_sim_level(GraphView g, ChunkView c, CountView cnt,
+                                                      int32_t g0, int32_t n, int32_t waves_per_row,
+                                                      int32_t sim_blocks, SpLevel sp) {
+  if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level
+    const int64_t idx = (int64_t)(blockIdx.x - sim_blocks) * kBlock + threadIdx.x;
+    if (idx < (int64_t)sp.n * sp.B) sp_item(g, sp, idx);
+    return;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  if (task >= (int64_t)n * waves_per_row) return;
+  const int32_t gl = (int32_t)(task / waves_per_row);
+  const int32_t seg = (int32_t)(task - (int64_t)gl * waves_per_row);
+  const int32_t gi = g0 + gl;
+  const int op = __builtin_amdgcn_readfirstlane((int)g.op[gi]);
+  const int64_t pp = c.pitch / 2;  // pairs per row
+  const w2 *W = reinterpret_cast<const w2 *>(c.W);
+  const w2 *r0 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[gi]) * pp;
+  const w2 *r1 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[g.G + gi]) * pp;
+  const w2 *r2 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[2 * g.G + gi]) * pp;
+  w2 *out = reinterpret_cast<w2 *>(c.W) + (int64_t)(g.n_pi + gi) * pp;
+  const int32_t p_begin = seg * 64 * ITERS;
+  uint32_t ones = 0, togs = 0;
+  switch (op) {
+    case INV: sim_gate_row<INV, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case BUF: sim_gate_row<BUF, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case AND2: sim_gate_row<AND2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case OR2: sim_gate_row<OR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case NAND2: sim_gate_row<NAND2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case NOR2: sim_gate_row<NOR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case XOR2: sim_gate_row<XOR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case AOI21: sim_gate_row<AOI21, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    default: sim_gate_row<MUX2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+  }
+  ones = wave_sum(ones);
+  togs = wave_sum(togs);
+  if (lane == 0) {
+    const int64_t o = (int64_t)(g.n_pi + gi) * cnt.B + cnt.col;
+    if (ones) atomicAdd(cnt.ones + o, ones);
+    if (togs) atomicAdd(cnt.tog + o, togs);
+  }
+}
+
+// ---------------------------------------------------------------- stimulus
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of
+// (c0,c1,c2,c3) -> (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)),
+// key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// floor(p * 2^32) of a float32 probability, exact in double.
+__device__ __forceinline__ uint64_t prob_threshold(float p) {
+  const double v = (double)p * 4294967296.0;
+  if (!(v > 0.0)) return 0;
+  if (v >= 4294967296.0) return 1ull << 32;
+  return (uint64_t)v;
+}
+
+// Word t of PI i: i.i.d. Bernoulli(p) lanes, the temporal-independence case
+// of the Markov stimulus of Sec. III-C; lane j = 4q + l is 1 iff lane l of
+// Philox(t, i, q, 0; seed) is below the threshold.
+__device__ __forceinline__ uint64_t stim_word(uint32_t pi, int64_t t, uint64_t thr, uint32_t k0,
+                                              uint32_t k1) {
+  uint64_t w = 0;
+#pragma unroll 4
+  for (uint32_t q = 0; q < 16; ++q) {
+    const uint4 u = philox4x32_10(make_uint4((uint32_t)t, pi, q, 0u), k0, k1);
+    const uint64_t bits = (uint64_t)((uint64_t)u.x < thr) | ((uint64_t)((uint64_t)u.y < thr) << 1) |
+                          ((uint64_t)((uint64_t)u.z < thr) << 2) |
+                          ((uint64_t)((uint64_t)u.w < thr) << 3);
+    w |= bits << (4 * q);
+  }
+  return w;
+}
+
+template <int ITERS>
+__global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, CountView cnt,
+                                                     const float *__restrict__ p_rows,
+                                                     const uint64_t *__restrict__ stim, int64_t T,
+                                                     uint32_t k0, uint32_t k1,
+                                                     int32_t waves_per_row) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  if (task >= (int64_t)n_pi * waves_per_row) return;
+  const int32_t i = (int32_t)(task / waves_per_row);
+  const int32_t seg = (int32_t)(task - (int64_t)i * waves_per_row);
+  const uint64_t thr = prob_threshold(p_rows[(int64_t)i * cnt.B + cnt.col]);
+  const uint64_t *srow = stim ? stim + (int64_t)i * T : nullptr;
+  auto word = [&](int64_t u) -> uint64_t {
+    const int64_t t = c.t_first + u;
+    if (t < 0 || t >= T) return 0;
+    return srow ? srow[t] : stim_word((uint32_t)i, t, thr, k0, k1);
+  };
+  uint64_t *out = c.W + (int64_t)i * c.pitch;
+  const int32_t p_begin = seg * 64 * ITERS;
+  uint64_t carry = p_begin > 0 ? word(2 * (int64_t)p_begin - 1) : 0;
+  uint32_t ones = 0, togs = 0;
+  for (int it = 0; it < ITERS; ++it) {
+    const int32_t p = p_begin + it * 64 + lane;
+    w2 y = w2{0, 0};
+    if (p < c.pairs) {
+      y.x = word(2 * (int64_t)p);
+      y.y = word(2 * (int64_t)p + 1);
+    }
+    uint64_t prev = __shfl_up(y.y, 1u);
+    if (lane == 0) prev = carry;
+    carry = __shfl(y.y, 63);
+    if (p < c.pairs) {
+      reinterpret_cast<w2 *>(out)[p] = y;
+      count_pair(c, p, y, prev, ones, togs);
+    }
+  }
+  ones = wave_sum(ones);
+  togs = wave_sum(togs);
+  if (lane == 0) {
+    const int64_t o = (int64_t)i * cnt.B + cnt.col;
+    if (ones) atomicAdd(cnt.ones + o, ones);
+    if (togs) atomicAdd(cnt.tog + o, togs);
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+// Per (net, column): TR_model = 2P(1-P) (Eq. 2); in hybrid mode
+// TR_acc = toggles / (64 (T-1)) (Eq. 4) and beta = clip(TR_acc / TR_model)
+// (Eq. 5, 0/0 -> 1, x/0 -> beta_max); xterm = kappa beta TR_model is the
+// per-unit-capacitance power of the net (Eq. 1); seed_base is the local
+// adjoint term kappa beta C 2(1 - 2P) (without the driver's size factor).
+__global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)a.n_nets * a.B) return;
+  const int32_t n = (int32_t)(idx / a.B);
+  const float P = a.sp[idx];
+  const float tm = 2.0f * P * (1.0f - P);
+  float beta = 1.0f;
+  if (a.mode == 1) {
+    const float ta = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
+    if (tm == 0.0f)
+      beta = (ta == 0.0f) ? 1.0f : a.beta_max;
+    else
+      beta = ta / tm;
+    beta = fminf(fmaxf(beta, a.beta_min), a.beta_max);
+  } else if (a.mode == 2) {
+    beta = a.beta_frozen[idx];
+  }
+  const float C = a.cap[n];
+  a.beta[idx] = beta;
+  a.xterm[idx] = a.kappa * beta * tm;
+  const float local = a.kappa * C * 2.0f * fmaf(-2.0f, P, 1.0f);
+  a.seed_base[idx] = a.ste ? local : beta * local;
+}
+
+__global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)a.n_nets * a.B) return;
+  const int32_t n = (int32_t)(idx / a.B), b = (int32_t)(idx - (int64_t)n * a.B);
+  const int64_t o = (int64_t)b * a.n_nets + a.int2ext[n];
+  const float P = a.sp[idx];
+  const float tm = 2.0f * P * (1.0f - P);
+  if (a.o_sp) a.o_sp[o] = P;
+  if (a.o_tr) a.o_tr[o] = tm;
+  if (a.o_beta) a.o_beta[o] = a.beta[idx];
+  if (a.o_tr_hyb) a.o_tr_hyb[o] = a.beta[idx] * tm;
+  if (a.o_sp_acc) a.o_sp_acc[o] = (float)((double)a.ones[idx] / (64.0 * (double)a.T));
+  if (a.o_tr_acc) a.o_tr_acc[o] = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
+  if (a.o_ones) a.o_ones[o] = a.ones[idx];
+  if (a.o_tog) a.o_tog[o] = a.tog[idx];
+}
+
+// ---------------------------------------------------------------- power
+// P[b][s] = sum_n xterm[n][b] C_n s_s(drv n), accumulated in double: one
+// block per (chunk of nets, column), fixed thread -> net map, LDS tree, then
+// a fixed-order sum over chunks.  The result is independent of the launch.
+constexpr int32_t kPowerChunk = 8192;
+
+__device__ __forceinline__ double block_sum_d(double v, double *lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kWavesPerBlock; ++i) r += lds[i];
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_power_partial(PowerArgs a) {
+  __shared__ double lds[kWavesPerBlock];
+  const int32_t n_cols = a.B * (a.S > 0 ? a.S : 1);
+  const int32_t col = (int32_t)(blockIdx.x / a.n_chunks);  // b * S' + s
+  const int32_t chunk = (int32_t)(blockIdx.x - (uint32_t)col * a.n_chunks);
+  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t b = col / Sp, s = col - b * Sp;
+  const int32_t n_lo = chunk * kPowerChunk;
+  const int32_t n_hi = min(n_lo + kPowerChunk, a.n_nets);
+  double acc = 0.0;
+  for (int32_t n = n_lo + threadIdx.x; n < n_hi; n += kBlock) {
+    float sz = 1.0f;
+    if (a.size && n >= a.n_pi) sz = a.size[(int64_t)s * a.G + (n - a.n_pi)];
+    acc += (double)a.xterm[(int64_t)n * a.B + b] * (double)(a.cap[n] * sz);
+  }
+  const double r = block_sum_d(acc, lds);
+  if (threadIdx.x == 0) a.partial[(int64_t)chunk * n_cols + col] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_cols) {
+  const int64_t col = gidx();
+  if (col >= n_cols) return;
+  double acc = 0.0;
+  for (int32_t k = 0; k < a.n_chunks; ++k) acc += a.partial[(int64_t)k * n_cols + col];
+  a.power[col] = (float)acc;
+}
+
+// ---------------------------------------------------------------- reverse sweep
+// seed[n][c]: the local adjoint term of net n for reverse column c, scaled by
+// the upstream weight and the driver's size factor.
+__global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
+  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t C = a.per_column ? a.B * Sp : a.B;
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)a.n_nets * C) return;
+  const int32_t n = (int32_t)(idx / C), c = (int32_t)(idx - (int64_t)n * C);
+  const bool gate = n >= a.n_pi && a.size;
+  float v;
+  if (a.per_column) {
+    const int32_t b = c / Sp, s = c - b * Sp;
+    const float w = a.w ? a.w[c] : 1.0f;
+    const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
+    v = a.seed_base[(int64_t)n * a.B + b] * w * sz;
+  } else {
+    const int32_t b = c;
+    float ws = 0.0f;
+    for (int32_t s = 0; s < Sp; ++s) {
+      const float w = a.w ? a.w[(int64_t)b * Sp + s] : 1.0f;
+      const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
+      ws = fmaf(w, sz, ws);
+    }
+    v = a.seed_base[(int64_t)n * a.B + b] * ws;
+  }
+  a.seed[idx] = v;
+}
+
+// Eq. 7 for one level: a gate's output adjoint is its seed plus the
+// contributions its readers left on their fan-in slots (pulled in the fixed
+// fan-out order, so the sum is deterministic); it then leaves
+// lambda * dR/dx_j on each of its own fan-in slots.
+__global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
+                                                      int32_t n) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)n * a.C) return;
+  const int32_t gl = (int32_t)(idx / a.C);
+  const int32_t c = (int32_t)(idx - (int64_t)gl * a.C);
+  const int32_t b = c / a.cdiv;
+  const int32_t gi = g0 + gl;
+  const int32_t out = g.n_pi + gi;
+  float lam = a.seed[(int64_t)out * a.C + c];
+  const int32_t e1 = g.rev_ptr[out + 1];
+  for (int32_t e = g.rev_ptr[out]; e < e1; ++e) lam += a.contrib[(int64_t)g.rev_edge[e] * a.C + c];
+  if (a.ste) lam *= a.beta[(int64_t)out * a.B + b];
+  const int op = g.op[gi];
+  const int k = arity_of(op);
+  const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
+  const float x0 = a.sp[(int64_t)i0 * a.B + b];
+  const float x1 = k > 1 ? a.sp[(int64_t)i1 * a.B + b] : 0.0f;
+  const float x2 = k > 2 ? a.sp[(int64_t)i2 * a.B + b] : 0.0f;
+  float d0, d1, d2;
+  sp_partials(op, x0, x1, x2, d0, d1, d2);
+  a.contrib[(int64_t)gi * a.C + c] = lam * d0;
+  if (k > 1) a.contrib[((int64_t)g.G + gi) * a.C + c] = lam * d1;
+  if (k > 2) a.contrib[(2 * (int64_t)g.G + gi) * a.C + c] = lam * d2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)g.n_pi * a.C) return;
+  const int32_t i = (int32_t)(idx / a.C);
+  const int32_t c = (int32_t)(idx - (int64_t)i * a.C);
+  float lam = a.seed[idx];
+  const int32_t e1 = g.rev_ptr[i + 1];
+  for (int32_t e = g.rev_ptr[i]; e < e1; ++e) lam += a.contrib[(int64_t)g.rev_edge[e] * a.C + c];
+  if (a.ste) lam *= a.beta[(int64_t)i * a.B + c / a.cdiv];
+  out[(int64_t)c * g.n_pi + i] = lam;
+}
+
+// dP/dC_n = sum_{b,s} w[b][s] kappa beta TR_model s_s(drv n);
+// dP/ds[s][g] = sum_b w[b][s] kappa beta TR_model C of g's output net.
+__global__ __launch_bounds__(kBlock) void k_grad_cap(GradExportArgs a) {
+  const int64_t n = gidx();
+  if (n >= a.n_nets) return;
+  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const bool gate = n >= a.n_pi && a.size;
+  double acc = 0.0;
+  for (int32_t b = 0; b < a.B; ++b) {
+    float ws = 0.0f;
+    for (int32_t s = 0; s < Sp; ++s) {
+      const float w = a.w ? a.w[(int64_t)b * Sp + s] : 1.0f;
+      const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
+      ws = fmaf(w, sz, ws);
+    }
+    acc += (double)a.xterm[n * a.B + b] * (double)ws;
+  }
+  a.dcap[a.int2ext[n]] = (float)acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_size(GradExportArgs a) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)a.G * a.S) return;
+  const int32_t s = (int32_t)(idx / a.G), g = (int32_t)(idx - (int64_t)s * a.G);
+  const int32_t n = a.n_pi + g;
+  double acc = 0.0;
+  for (int32_t b = 0; b < a.B; ++b) {
+    const float w = a.w ? a.w[(int64_t)b * a.S + s] : 1.0f;
+    acc += (double)a.xterm[(int64_t)n * a.B + b] * (double)w;
+  }
+  a.dsize[(int64_t)s * a.G + (a.int2ext[n] - a.n_pi)] = (float)(acc * (double)a.cap[n]);
+}
+
+}  // namespace
+
+// ==================================================================== launchers
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_fill_u32<<<blocks_for(n), kBlock, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_fill_f32<<<blocks_for(n), kBlock, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t s) {
+  const int64_t n = (int64_t)n_pi * B;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_load_pi<<<blocks_for(n), kBlock, 0, s>>>(p, sp, n_pi, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_check_range<<<blocks_for(n), kBlock, 0, s>>>(v, n, lo, hi, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_nets_f32(const float *src_ext, const int32_t *int2ext, float *dst_int,
+                                  int32_t n_nets, hipStream_t s) {
+  if (n_nets <= 0) return hipSuccess;
+  k_gather_nets<<<blocks_for(n_nets), kBlock, 0, s>>>(src_ext, int2ext, dst_int, n_nets);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_cols_f32(const float *src, const int32_t *int2ext, float *dst,
+                                  int32_t n_nets, int32_t B, hipStream_t s) {
+  const int64_t n = (int64_t)n_nets * B;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_import_cols<<<blocks_for(n), kBlock, 0, s>>>(src, int2ext, dst, n_nets, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *dst, int32_t n_pi,
+                               int32_t G, int32_t S, hipStream_t s) {
+  const int64_t n = (int64_t)G * S;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_import_sizes<<<blocks_for(n), kBlock, 0, s>>>(src, int2ext, dst, n_pi, G, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s) {
+  const int64_t n = (int64_t)lv.n * lv.B;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_sp_level<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
+  return hipGetLastError();
+}
+
+static int32_t waves_per_row(const ChunkView &c, int iters) {
+  return (c.pairs + 64 * iters - 1) / (64 * iters);
+}
+
+hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
+                           const float *p_col, const uint64_t *stim, int64_t T, uint64_t seed,
+                           const SimTune &tune, hipStream_t s) {
+  if (g.n_pi <= 0 || c.pairs <= 0) return hipSuccess;
+  const int iters = tune.iters;
+  const int32_t wpr = waves_per_row(c, iters);
+  const int64_t tasks = (int64_t)g.n_pi * wpr;
+  if ((tasks + kWavesPerBlock - 1) / kWavesPerBlock > kMaxBlocks) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)((tasks + kWavesPerBlock - 1) / kWavesPerBlock);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  switch (iters) {
+    case 1: k_stimulus<1><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
+    case 2: k_stimulus<2><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
+    case 4: k_stimulus<4><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
+    default: k_stimulus<8><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
+                            int32_t g0, int32_t n, const SpLevel *sp, const SimTune &tune,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int iters = tune.iters;
+  const int32_t wpr = waves_per_row(c, iters);
+  const int64_t tasks = (int64_t)n * wpr;
+  const int64_t sim_blocks64 = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+  SpLevel spl{};
+  int64_t sp_blocks = 0;
+  if (sp) {
+    spl = *sp;
+    sp_blocks = blocks_for((int64_t)spl.n * spl.B);
+  }
+  if (sim_blocks64 + sp_blocks > kMaxBlocks || sim_blocks64 > INT32_MAX) return hipErrorInvalidValue;
+  const int32_t sim_blocks = (int32_t)sim_blocks64;
+  const unsigned grid = (unsigned)(sim_blocks + sp_blocks);
+  switch (iters) {
+    case 1: k_sim_level<1><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 2: k_sim_level<2><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 4: k_sim_level<4><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    default: k_sim_level<8><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
+  const int64_t n = (int64_t)a.n_nets * a.B;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_finalize<<<blocks_for(n), kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const ExportArgs &a, hipStream_t s) {
+  const int64_t n = (int64_t)a.n_nets * a.B;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_export<<<blocks_for(n), kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+int32_t power_chunks(int32_t n_nets) {
+  return n_nets <= 0 ? 1 : (n_nets + kPowerChunk - 1) / kPowerChunk;
+}
+
+hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
+  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t n_cols = a.B * Sp;
+  const int64_t blocks = (int64_t)a.n_chunks * n_cols;
+  if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+  k_power_partial<<<(unsigned)blocks, kBlock, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_power_final<<<blocks_for(n_cols), kBlock, 0, s>>>(a, n_cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(const SeedArgs &a, hipStream_t s) {
+  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int64_t C = a.per_column ? (int64_t)a.B * Sp : a.B;
+  const int64_t n = (int64_t)a.n_nets * C;
+  if (n <= 0) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_seed<<<blocks_for(n), kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
+                            hipStream_t s) {
+  const int64_t items = (int64_t)n * a.C;
+  if (items <= 0) return hipSuccess;
+  if (too_big(items)) return hipErrorInvalidValue;
+  k_bwd_level<<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s) {
+  const int64_t items = (int64_t)g.n_pi * a.C;
+  if (items <= 0) return hipSuccess;
+  if (too_big(items)) return hipErrorInvalidValue;
+  k_bwd_pi<<<blocks_for(items), kBlock, 0, s>>>(g, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t s) {
+  if (a.dcap && a.n_nets > 0) {
+    k_grad_cap<<<blocks_for(a.n_nets), kBlock, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.dsize && a.S > 0 && a.G > 0) {
+    k_grad_size<<<blocks_for((int64_t)a.G * a.S), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+}  // namespace dp

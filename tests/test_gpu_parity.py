@@ -1,0 +1,295 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Sizes span several tiles and ragged tails; the full-size workloads are in
+test_gpu_workloads.py."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_03778_amd import _lib as L
+from paper_2608_03778_amd import api, synth
+from tests import brute
+from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, oracle_column, say)
+
+pytestmark = pytest.mark.gpu
+
+FWD_ALL = ("sp", "tr", "sp_acc", "tr_acc", "beta", "tr_hyb", "ones", "toggles", "power")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return api.Context(0)
+
+
+def _inputs(nl, seed, B=1, S=0):
+    p = synth.pi_probs(nl.n_pi, seed, batch=B)
+    cap = synth.net_caps(nl.n_nets, seed + 1)
+    size = synth.cell_sizes(nl.n_gates, seed + 2, n_size=S) if S else None
+    return p, cap, size
+
+
+def _check_forward(res, f, col, hybrid):
+    np.testing.assert_allclose(res["sp"][col], f["sp"], atol=SP_ABS, rtol=0)
+    np.testing.assert_allclose(res["tr"][col], f["tr_model"], atol=SP_ABS, rtol=0)
+    if hybrid:
+        np.testing.assert_array_equal(res["ones"][col].astype(np.uint64), f["ones"])
+        np.testing.assert_array_equal(res["toggles"][col].astype(np.uint64), f["toggles"])
+        np.testing.assert_allclose(res["sp_acc"][col], f["sp_acc"], atol=SP_ABS, rtol=0)
+        np.testing.assert_allclose(res["tr_acc"][col], f["tr_acc"], atol=SP_ABS, rtol=0)
+        np.testing.assert_allclose(res["tr_hyb"][col], f["tr_hyb"], atol=SP_ABS, rtol=0)
+        # beta = TR_acc / TR_model: its float32 error is relative to TR_model's
+        ok = f["tr_model"] > 1e-3
+        np.testing.assert_allclose(res["beta"][col][ok], f["beta"][ok], rtol=2e-4, atol=0)
+
+
+@pytest.mark.parametrize("op", range(9))
+def test_single_cell_level(ctx, op):
+    """Every cell alone on one level, many instances with random inputs."""
+    say(f"single cell {synth.OP_NAMES[op]}")
+    rng = np.random.default_rng(op)
+    n_pi, G = 40, 700
+    k = int(synth.ARITY[op])
+    gates = [(op, list(rng.choice(n_pi, size=k, replace=False))) for _ in range(G)]
+    nl = synth.from_gates(n_pi, gates)
+    p, cap, _ = _inputs(nl, 10 + op)
+    d = api.Design(ctx, nl)
+    assert d.depth == 1
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 9, seed=5)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(FWD_ALL)
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid", n_words=9, seed=5)
+    _check_forward(res, f, 0, True)
+    assert_power_close(res["power"], f["power"])
+    g = ev.backward(want=("dpi", "dcap"))
+    assert_grad_close(g["dpi"][0], adj["dpi"], "dP/dp")
+    assert_grad_close(g["dcap"], adj["dcap"], "dP/dC")
+
+
+@pytest.mark.parametrize("mode", ["modeled", "hybrid"])
+def test_dag2k_all_outputs(ctx, mode):
+    """2,000-gate DAG, 64 PIs, depth 20, 4,096 vectors: every output."""
+    say(f"dag2k {mode}")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 1)
+    p, cap, _ = _inputs(nl, 1)
+    d = api.Design(ctx, nl)
+    hyb = mode == "hybrid"
+    ev = api.Eval(d, mode=L.DP_HYBRID if hyb else L.DP_MODELED, n_sim=4096, seed=7)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    outs = FWD_ALL if hyb else ("sp", "tr", "beta", "tr_hyb", "power")
+    res = ev.forward(outs)
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode=mode, n_words=64, seed=7)
+    _check_forward(res, f, 0, hyb)
+    assert_power_close(res["power"], f["power"])
+    g = ev.backward(want=("dpi", "dcap"))
+    assert_grad_close(g["dpi"][0], adj["dpi"], "dP/dp")
+    assert_grad_close(g["dcap"], adj["dcap"], "dP/dC")
+    np.testing.assert_array_equal(d.levels(), o.levels())
+
+
+@pytest.mark.parametrize("chunk,ppl", [(0, 1), (0, 2), (0, 8), (2, 0), (6, 4), (64, 0), (30, 1)])
+def test_chunking_and_lane_tiling_are_bit_exact(ctx, chunk, ppl):
+    """Word chunks (with their halo) and pairs per lane change no count."""
+    say(f"chunk={chunk} pairs/lane={ppl}")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 2)
+    p, cap, _ = _inputs(nl, 2)
+    d = api.Design(ctx, nl)
+    T = 131  # ragged: odd word count, several waves per row at small tilings
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * T, seed=3)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    ev.set_schedule(L.DP_SCHED_LEVEL, chunk, ppl)
+    res = ev.forward(("ones", "toggles", "power"))
+    o = oracle.Netlist.of(nl)
+    ones, tog = o.sim(T, p_pi=p[0], seed=3)
+    np.testing.assert_array_equal(res["ones"][0].astype(np.uint64), ones)
+    np.testing.assert_array_equal(res["toggles"][0].astype(np.uint64), tog)
+
+
+def test_explicit_stimulus_matches_generator(ctx):
+    """dp_set_stimulus with the oracle's Philox words gives the generator's
+    counts; exhaustive words give the exact minterm counts."""
+    say("explicit stimulus")
+    nl = synth.random_dag(synth.DagSpec(n_gates=300, n_pi=6, depth=12, reconv=0.5), 4)
+    p = np.full((1, nl.n_pi), 0.5, np.float32)
+    cap = synth.net_caps(nl.n_nets, 4)
+    d = api.Design(ctx, nl)
+    T = 10
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * T, seed=99)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    gen = ev.forward(("ones", "toggles"))
+    ev.set_stimulus(oracle.stimulus(p[0], 99, 0, T)[None])
+    exp = ev.forward(("ones", "toggles"))
+    np.testing.assert_array_equal(gen["ones"], exp["ones"])
+    np.testing.assert_array_equal(gen["toggles"], exp["toggles"])
+    w = np.repeat(brute.pack_minterm_words(nl.n_pi)[:, None], T, axis=1)
+    ev.set_stimulus(w[None])
+    ex = ev.forward(("ones", "toggles", "sp_acc"))
+    vals = brute.eval_all_minterms(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin)
+    np.testing.assert_array_equal(ex["ones"][0], T * vals.sum(axis=1))
+    assert (ex["toggles"] == 0).all()
+
+
+def test_batched_columns_and_sizes(ctx):
+    """B = 3 query columns x S = 2 size vectors: every column equals the
+    oracle's independent run; power[b][s] and the contracted gradients."""
+    say("batched B=3 S=2")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 3)
+    B, S = 3, 2
+    p, cap, size = _inputs(nl, 3, B=B, S=S)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, B, S, mode=L.DP_HYBRID, n_sim=64 * 20, seed=11)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    ev.set_cell_sizes(size)
+    res = ev.forward(FWD_ALL)
+    w = np.random.default_rng(0).uniform(-1, 2, (B, S)).astype(np.float32)
+    g = ev.backward(w, want=("dpi", "dcap", "dsize"))
+    cols = ev.backward_columns()
+    o = oracle.Netlist.of(nl)
+    dpi_ref = np.zeros((B, nl.n_pi))
+    dcap_ref = np.zeros(nl.n_nets)
+    dsize_ref = np.zeros((S, nl.n_gates))
+    for b in range(B):
+        for s in range(S):
+            f, adj = oracle_column(o, p[b], cap, size[s], mode="hybrid", n_words=20, seed=11)
+            if s == 0:
+                _check_forward(res, f, b, True)
+            assert_power_close(res["power"][b, s], f["power"], f"power[{b},{s}]")
+            assert_grad_close(cols[b, s], adj["dpi"], f"columns[{b},{s}]")
+            dpi_ref[b] += w[b, s] * adj["dpi"]
+            dcap_ref += w[b, s] * adj["dcap"]
+            dsize_ref[s] += w[b, s] * adj["dsize"]
+    assert_grad_close(g["dpi"].ravel(), dpi_ref.ravel(), "dP/dp contracted")
+    assert_grad_close(g["dcap"], dcap_ref, "dP/dC contracted")
+    assert_grad_close(g["dsize"].ravel(), dsize_ref.ravel(), "dP/ds contracted")
+
+
+def test_beta_ste_and_frozen(ctx):
+    """Eq. 6 taken literally (DP_BETA_STE) and a frozen beta."""
+    say("beta modes")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 6)
+    p, cap, _ = _inputs(nl, 6)
+    d = api.Design(ctx, nl)
+    o = oracle.Netlist.of(nl)
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 16, seed=2, beta_grad=L.DP_BETA_STE)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(("beta", "power"))
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid", n_words=16, seed=2, ste=True)
+    assert_power_close(res["power"], f["power"])
+    assert_grad_close(ev.backward()["dpi"][0], adj["dpi"], "STE dP/dp")
+    beta = np.random.default_rng(1).uniform(0.1, 10, (1, nl.n_nets)).astype(np.float32)
+    ev2 = api.Eval(d, mode=L.DP_FROZEN_BETA)
+    ev2.set_pi_prob(p)
+    ev2.set_caps(cap)
+    ev2.set_beta(beta)
+    r2 = ev2.forward(("beta", "power"))
+    np.testing.assert_array_equal(r2["beta"], beta)
+    f2, adj2 = oracle_column(o, p[0], cap, mode="frozen", beta=beta[0].astype(np.float64))
+    assert_power_close(r2["power"], f2["power"])
+    assert_grad_close(ev2.backward()["dpi"][0], adj2["dpi"], "frozen dP/dp")
+
+
+def test_graph_schedule_matches_level_schedule(ctx):
+    """The HIP-graph-captured sweep gives the per-level launches' results
+    bit for bit, across replays with changed inputs."""
+    say("graph schedule")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 8)
+    p, cap, _ = _inputs(nl, 8, B=2)
+    d = api.Design(ctx, nl)
+    runs = {}
+    for sched in (L.DP_SCHED_LEVEL, L.DP_SCHED_GRAPH):
+        ev = api.Eval(d, 2, mode=L.DP_HYBRID, n_sim=64 * 33, seed=4)
+        ev.set_caps(cap)
+        ev.set_schedule(sched)
+        out = []
+        for rep in range(3):
+            ev.set_pi_prob(np.clip(p + 0.01 * rep, 0, 1))
+            out.append(ev.forward(("sp", "ones", "toggles", "power")))
+        runs[sched] = out
+    for a, b in zip(runs[L.DP_SCHED_LEVEL], runs[L.DP_SCHED_GRAPH]):
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_repeat_runs_are_bitwise_deterministic(ctx):
+    say("determinism")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 9)
+    p, cap, _ = _inputs(nl, 9, B=4)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, 4, mode=L.DP_HYBRID, n_sim=64 * 8)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    a = ev.forward(("sp", "power", "ones"))
+    ga = ev.backward(want=("dpi", "dcap"))
+    b = ev.forward(("sp", "power", "ones"))
+    gb = ev.backward(want=("dpi", "dcap"))
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+    for k in ga:
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_edge_cases(ctx):
+    """No gates; a single PI; self-XOR reconvergence; constant probabilities
+    (TR_model = 0 -> the beta zero-denominator rule)."""
+    say("edge cases")
+    nl = synth.from_gates(3, [])
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=128)
+    p = np.array([[0.0, 1.0, 0.5]], np.float32)
+    cap = np.array([1.0, 2.0, 3.0], np.float32)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    r = ev.forward(("power", "beta", "ones", "toggles"))
+    o = oracle.Netlist.of(nl)
+    f, _ = oracle_column(o, p[0], cap, mode="hybrid", n_words=2, seed=1)
+    assert_power_close(r["power"], f["power"])
+    np.testing.assert_allclose(r["beta"][0], f["beta"], rtol=1e-6)
+    nl = synth.from_gates(2, [(synth.XOR2, [0, 0]), (synth.AND2, [0, 1]), (synth.INV, [3])])
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 3)
+    p = np.array([[0.3, 1.0]], np.float32)
+    cap = np.ones(nl.n_nets, np.float32)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    r = ev.forward(FWD_ALL)
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid", n_words=3, seed=1)
+    _check_forward(r, f, 0, True)
+    np.testing.assert_allclose(r["beta"][0], f["beta"], rtol=1e-5)
+    assert_grad_close(ev.backward()["dpi"][0], adj["dpi"])
+
+
+def test_errors_and_state(ctx):
+    say("errors")
+    with pytest.raises(L.DiffPowerError, match="CYCLE"):
+        api.Design(ctx, synth.from_gates(1, [(synth.AND2, [0, 2]), (synth.BUF, [1])]))
+    with pytest.raises(L.DiffPowerError, match="INVALID"):
+        api.Design(ctx, synth.from_gates(1, [(synth.AND2, [0])]))
+    nl = synth.random_dag(synth.SPECS["dag2k"], 1)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d)
+    with pytest.raises(L.DiffPowerError, match="STATE"):
+        ev.forward()
+    with pytest.raises(L.DiffPowerError, match="INVALID"):
+        ev.set_pi_prob(np.full((1, nl.n_pi), 1.5, np.float32))
+    with pytest.raises(L.DiffPowerError, match="INVALID"):
+        ev.set_pi_prob(np.full((1, nl.n_pi), np.nan, np.float32))
+    ev.set_pi_prob(synth.pi_probs(nl.n_pi, 1))
+    ev.set_caps(synth.net_caps(nl.n_nets, 1))
+    with pytest.raises(L.DiffPowerError, match="STATE"):
+        ev.backward()
+    ev.forward()
+    ev.set_caps(synth.net_caps(nl.n_nets, 2))
+    with pytest.raises(L.DiffPowerError, match="STATE"):
+        ev.backward()
+    with pytest.raises(L.DiffPowerError, match="INVALID"):
+        api.Eval(d, mode=L.DP_HYBRID, n_sim=100)
