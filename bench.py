@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--pairs-per-lane", type=int, default=0)
     ap.add_argument("--words-per-chunk", type=int, default=0)
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="short run for hardware counters: a 1 GiB device copy (known bytes, "
+                         "for scaling FETCH_SIZE/WRITE_SIZE) then the timed steps only")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -110,6 +113,15 @@ def main():
     log(f"[bench] compiled {G} gates depth {d.depth} in {compile_s:.2f}s")
     p_dev = torch.from_numpy(p).cuda()
     cap_dev = torch.from_numpy(cap).cuda()
+
+    if args.pmc_pass:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)  # 1 GiB read + 1 GiB written per dispatch
+        _sync()
+        log("[bench] calibration copies done (1 GiB each)")
+        args.no_cpu = args.no_forms = True
 
     # --- headline: hybrid fwd+bwd, one query column
     ev = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=args.n_sim, seed=1)

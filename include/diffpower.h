@@ -276,6 +276,11 @@ typedef struct {
  * slots; `hbm_budget_bytes` bounds the slot memory it may hold at once. */
 dp_status dp_server_create(dp_ctx *ctx, size_t hbm_budget_bytes,
                            dp_server **out);
+/* Batching limits: at most max_batch queries per launched sweep and
+ * max_inflight sweeps on the device at once (defaults 64 and 8; 1 and 1
+ * serve one query at a time, first come first served). */
+dp_status dp_server_configure(dp_server *srv, int32_t max_batch,
+                              int32_t max_inflight);
 /* Register a compiled design.  Queries use params->mode (DP_MODELED, or
  * DP_FROZEN_BETA with beta calibrated once here at p = 0.5 from
  * params->n_sim vectors). */

@@ -98,6 +98,7 @@ SIGNATURES = {
     "dp_eval_profile": (_st, [_p, _i32]),
     "dp_eval_get_profile": (_st, [_p, _p]),
     "dp_server_create": (_st, [_p, ctypes.c_size_t, _p]),
+    "dp_server_configure": (_st, [_p, _i32, _i32]),
     "dp_server_add_design": (_st, [_p, _p, _p, _p, _p]),
     "dp_submit": (_st, [_p, _p, _p]),
     "dp_poll": (_st, [_p, _u64, _p]),

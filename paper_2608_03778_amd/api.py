@@ -248,3 +248,75 @@ class Eval:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Continuous-batching query server over device-resident designs."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_batch: int = 64,
+                 max_inflight: int = 8):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = ctypes.c_void_p()
+        check(self.lib.dp_server_create(ctx.handle, int(hbm_budget_bytes), ctypes.byref(h)))
+        self.handle = h
+        check(self.lib.dp_server_configure(h, int(max_batch), int(max_inflight)))
+        self._live = {}
+        self._designs = {}
+
+    def configure(self, max_batch: int, max_inflight: int):
+        check(self.lib.dp_server_configure(self.handle, int(max_batch), int(max_inflight)))
+
+    def add_design(self, design: Design, cap, **kw) -> int:
+        prm = params(**kw)
+        c = np.ascontiguousarray(cap, dtype=np.float32)
+        i = ctypes.c_int32()
+        check(self.lib.dp_server_add_design(self.handle, design.handle,
+                                            c.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm),
+                                            ctypes.byref(i)))
+        self._designs[i.value] = design
+        return i.value
+
+    def submit(self, design_id: int, p, cap_scale=None, backward: bool = False) -> int:
+        """Enqueue one query; returns its ticket.  The result arrays are kept
+        here until wait() hands them back."""
+        d = self._designs[design_id]
+        pa = np.ascontiguousarray(p, dtype=np.float32)
+        sa = None if cap_scale is None else np.ascontiguousarray(cap_scale, dtype=np.float32)
+        power = np.zeros(1, dtype=np.float32)
+        dpi = np.zeros(d.n_pi, dtype=np.float32) if backward else None
+        q = L.Query(design_id, L.DP_Q_FWD_BWD if backward else L.DP_Q_FWD, pa.ctypes.data,
+                    sa.ctypes.data if sa is not None else None, power.ctypes.data,
+                    dpi.ctypes.data if dpi is not None else None)
+        t = ctypes.c_uint64()
+        check(self.lib.dp_submit(self.handle, ctypes.byref(q), ctypes.byref(t)))
+        self._live[t.value] = (pa, sa, power, dpi)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int32()
+        check(self.lib.dp_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket: int):
+        """Block until done; returns (power, dP/dp or None, latency seconds)."""
+        lat = ctypes.c_double()
+        check(self.lib.dp_wait(self.handle, ctypes.c_uint64(ticket), ctypes.byref(lat)))
+        _, _, power, dpi = self._live.pop(ticket)
+        return float(power[0]), dpi, lat.value
+
+    def stats(self) -> dict:
+        s = L.ServerStats()
+        check(self.lib.dp_server_get_stats(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in L.ServerStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if self.handle:
+            self.lib.dp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -40,7 +40,7 @@ dp::GraphView view(const dp_design *d) {
   return g;
 }
 
-int32_t s_prime(const dp_eval *ev) { return ev->S > 0 ? ev->S : 1; }
+int32_t s_prime(const dp_eval *ev) { return (ev->S > 0 && !ev->paired_sizes) ? ev->S : 1; }
 double kappa_of(const dp_params &p) { return p.energy_factor * p.vdd * p.vdd * p.fclk; }
 int64_t n_words(const dp_params &p) { return p.n_sim / 64; }
 
@@ -74,7 +74,7 @@ dp_status check_values(dp_eval *ev, const float *v, int64_t n, float lo, float h
                                       " at index " + std::to_string(i) + " out of range");
     return DP_OK;
   }
-  hipStream_t s = ev->d->ctx->stream;
+  hipStream_t s = ev->stream();
   DP_TRY(ev->flag.alloc(sizeof(int32_t)));
   DP_HIP_TRY(dp::launch_fill_u32(ev->flag.as<uint32_t>(), 1, 0u, s));
   DP_HIP_TRY(dp::launch_check_range(v, n, lo, hi, ev->flag.as<int32_t>(), s));
@@ -115,7 +115,7 @@ struct SpanGuard {
       a = ev->ev_used;
       hipEvent_t x = take_event(ev);
       if (!x) { on = false; return; }
-      (void)hipEventRecord(x, ev->d->ctx->stream);
+      (void)hipEventRecord(x, ev->stream());
     }
   }
   ~SpanGuard() {
@@ -123,7 +123,7 @@ struct SpanGuard {
     size_t b = ev->ev_used;
     hipEvent_t x = take_event(ev);
     if (!x) return;
-    (void)hipEventRecord(x, ev->d->ctx->stream);
+    (void)hipEventRecord(x, ev->stream());
     ev->spans.push_back({a, b, kind, bytes});
   }
 };
@@ -133,7 +133,7 @@ dp_status resolve_profile(dp_eval *ev) {
     ev->ev_used = 0;
     return DP_OK;
   }
-  DP_HIP_TRY(hipStreamSynchronize(ev->d->ctx->stream));
+  DP_HIP_TRY(hipStreamSynchronize(ev->stream()));
   for (const auto &sp : ev->spans) {
     float ms = 0.0f;
     DP_HIP_TRY(hipEventElapsedTime(&ms, ev->ev_pool[sp.a], ev->ev_pool[sp.b]));
@@ -247,7 +247,7 @@ double bwd_level_bytes(const dp_design *d, int32_t l, int32_t C) {
 // Enqueue the whole forward sweep (no host sync, no allocation).
 dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   const dp_design *d = ev->d;
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   const dp::GraphView g = view(d);
   const bool prof = ev->profiling;
   float *sp = ev->sp.as<float>();
@@ -288,6 +288,7 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   fa.ones = pl ? ev->ones.as<uint32_t>() : nullptr;
   fa.tog = pl ? ev->tog.as<uint32_t>() : nullptr;
   fa.beta_frozen = ev->prm.mode == DP_FROZEN_BETA ? ev->beta_frozen.as<float>() : nullptr;
+  fa.beta_shared = ev->beta_shared;
   fa.cap = ev->cap.as<float>();
   fa.T = pl ? pl->T : 0;
   fa.kappa = (float)kappa_of(ev->prm);
@@ -310,6 +311,7 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   pa.G = d->n_gates;
   pa.B = ev->B;
   pa.S = ev->S;
+  pa.paired = ev->paired_sizes;
   pa.partial = ev->power_partial.as<double>();
   pa.n_chunks = dp::power_chunks(d->n_nets);
   pa.power = ev->power.as<float>();
@@ -347,7 +349,7 @@ struct OutMap {
 };
 
 dp_status capture_forward(dp_eval *ev, const ChunkPlan *pl, uint64_t key) {
-  hipStream_t s = ev->d->ctx->stream;
+  hipStream_t s = ev->stream();
   if (ev->graph_fwd) {
     (void)hipGraphExecDestroy(ev->graph_fwd);
     ev->graph_fwd = nullptr;
@@ -391,7 +393,7 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
   mix((uint64_t)(uintptr_t)ev->words.ptr);
   mix((uint64_t)(uintptr_t)ev->beta_frozen.ptr);
   mix((uint64_t)(uintptr_t)ev->size.ptr);
-  mix((uint64_t)(uintptr_t)ev->d->ctx->stream);
+  mix((uint64_t)(uintptr_t)ev->stream());
   if (pl) {
     mix((uint64_t)pl->Tc);
     mix((uint64_t)pick_iters(ev, *pl));
@@ -538,7 +540,7 @@ dp_status dp_eval_set_params(dp_eval *ev, const dp_params *params) {
 
 void dp_eval_destroy(dp_eval *ev) {
   if (!ev) return;
-  (void)hipStreamSynchronize(ev->d->ctx->stream);
+  (void)hipStreamSynchronize(ev->stream());
   delete ev;
 }
 
@@ -552,7 +554,7 @@ dp_status dp_set_pi_prob(dp_eval *ev, const float *p, int32_t on_device) {
     return DP_OK;
   }
   DP_TRY(check_values(ev, p, n, 0.0f, 1.0f, on_device, "dp_set_pi_prob"));
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   DP_TRY(stage_in(ev->p_stage, p, n * sizeof(float), on_device, s));
   DP_HIP_TRY(dp::launch_load_pi(ev->p_stage.as<float>(), ev->sp.as<float>(), d->n_pi, ev->B, s));
   if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
@@ -565,7 +567,7 @@ dp_status dp_set_caps(dp_eval *ev, const float *cap, int32_t on_device) {
   if (!ev) return fail(DP_E_INVALID, "dp_set_caps: NULL eval");
   const dp_design *d = ev->d;
   DP_TRY(check_values(ev, cap, d->n_nets, 0.0f, 3.0e38f, on_device, "dp_set_caps"));
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   DP_TRY(stage_in(ev->cap_stage, cap, (size_t)d->n_nets * sizeof(float), on_device, s));
   DP_HIP_TRY(dp::launch_gather_nets_f32(ev->cap_stage.as<float>(), d->int2ext.as<int32_t>(),
                                         ev->cap.as<float>(), d->n_nets, s));
@@ -581,7 +583,7 @@ dp_status dp_set_cell_sizes(dp_eval *ev, const float *size, int32_t on_device) {
   const dp_design *d = ev->d;
   const int64_t n = (int64_t)ev->S * d->n_gates;
   DP_TRY(check_values(ev, size, n, 0.0f, 3.0e38f, on_device, "dp_set_cell_sizes"));
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   DP_TRY(stage_in(ev->size_stage, size, n * sizeof(float), on_device, s));
   DP_HIP_TRY(dp::launch_import_sizes(ev->size_stage.as<float>(), d->int2ext.as<int32_t>(),
                                      ev->size.as<float>(), d->n_pi, d->n_gates, ev->S, s));
@@ -596,7 +598,7 @@ dp_status dp_set_beta(dp_eval *ev, const float *beta, int32_t on_device) {
   const dp_design *d = ev->d;
   const int64_t n = (int64_t)ev->B * d->n_nets;
   DP_TRY(check_values(ev, beta, n, 0.0f, 3.0e38f, on_device, "dp_set_beta"));
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   DP_TRY(ev->beta_frozen.alloc(n * sizeof(float)));
   DP_TRY(stage_in(ev->beta_stage, beta, n * sizeof(float), on_device, s));
   DP_HIP_TRY(dp::launch_import_cols_f32(ev->beta_stage.as<float>(), d->int2ext.as<int32_t>(),
@@ -618,7 +620,7 @@ dp_status dp_set_stimulus(dp_eval *ev, const uint64_t *words, int32_t on_device)
   const int64_t T = n_words(ev->prm);
   if (T <= 0) return fail(DP_E_INVALID, "dp_set_stimulus: params.n_sim is 0");
   const size_t bytes = (size_t)ev->B * d->n_pi * T * sizeof(uint64_t);
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   DP_TRY(stage_in(ev->stim, words, bytes, on_device, s));
   if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
   ev->have_stim = true;
@@ -670,7 +672,7 @@ dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out) {
       ev->stim.bytes < (size_t)ev->B * d->n_pi * n_words(ev->prm) * sizeof(uint64_t))
     return fail(DP_E_STATE, "dp_forward: the explicit stimulus is shorter than n_sim/64 words");
   DP_HIP_TRY(hipSetDevice(d->ctx->device));
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   ChunkPlan plan;
   if (hyb) plan = plan_chunks(ev);
   const ChunkPlan *pl = hyb ? &plan : nullptr;
@@ -724,7 +726,7 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
   if (ev->fwd_version != ev->inputs_version || ev->fwd_version == 0)
     return fail(DP_E_STATE, "dp_backward: no completed forward for the current inputs");
   DP_HIP_TRY(hipSetDevice(d->ctx->device));
-  hipStream_t s = d->ctx->stream;
+  hipStream_t s = ev->stream();
   const int32_t Sp = s_prime(ev);
   const int32_t cols = ev->B * Sp;
   const int32_t C = per_column ? cols : ev->B;
@@ -749,6 +751,7 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     sa.B = ev->B;
     sa.S = ev->S;
     sa.per_column = per_column;
+    sa.paired = ev->paired_sizes;
     DP_HIP_TRY(dp::launch_seed(sa, s));
     dp::BwdArgs ba{};
     ba.sp = ev->sp.as<float>();
@@ -787,6 +790,7 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     ga.G = d->n_gates;
     ga.B = ev->B;
     ga.S = ev->S;
+    ga.paired = ev->paired_sizes;
     DP_TRY(om.map(dcap, (size_t)d->n_nets, &ga.dcap));
     if (ev->S > 0) DP_TRY(om.map(dsize, (size_t)ev->S * d->n_gates, &ga.dsize));
     DP_HIP_TRY(dp::launch_grad_export(ga, s));
@@ -811,3 +815,137 @@ dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device)
 }
 
 }  // extern "C"
+
+// =========================================================================
+// Serving lanes (internal).
+namespace dp {
+
+size_t lane_bytes(const dp_design *d, int32_t capacity) {
+  const size_t nn = d->n_nets, G = d->n_gates, np = d->n_pi;
+  const size_t per_col = 4 * (6 * nn + 3 * G + 2 * G + 2 * np) +
+                         8 * (size_t)power_chunks(d->n_nets) + 16;
+  return (size_t)capacity * per_col + 8 * nn;
+}
+
+dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipStream_t stream,
+                      const float *cap_int, const float *beta_int, dp_eval **out) {
+  DP_TRY(check_params(prm));
+  if (prm->mode == DP_HYBRID) return fail(DP_E_UNSUPPORTED, "serving lanes run DP_MODELED or DP_FROZEN_BETA");
+  auto *ev = new dp_eval();
+  ev->d = d;
+  ev->B = capacity;
+  ev->S = capacity;
+  ev->paired_sizes = true;
+  ev->prm = *prm;
+  ev->own_stream = stream;
+  ev->schedule = DP_SCHED_LEVEL;
+  const size_t nn = d->n_nets;
+  dp_status st = DP_OK;
+  auto A = [&](DevBuf &b, size_t bytes) {
+    if (st == DP_OK) st = b.alloc(std::max<size_t>(bytes, 16));
+  };
+  A(ev->sp, nn * capacity * 4);
+  A(ev->cap, nn * 4);
+  A(ev->size, (size_t)capacity * d->n_gates * 4);
+  A(ev->size_stage, (size_t)capacity * d->n_gates * 4);
+  A(ev->p_stage, (size_t)capacity * d->n_pi * 4);
+  A(ev->beta, nn * capacity * 4);
+  A(ev->xterm, nn * capacity * 4);
+  A(ev->seed_base, nn * capacity * 4);
+  A(ev->power_partial, (size_t)power_chunks(d->n_nets) * capacity * 8);
+  A(ev->power, (size_t)capacity * 4);
+  A(ev->seed, nn * capacity * 4);
+  A(ev->contrib, (size_t)3 * d->n_gates * capacity * 4);
+  A(ev->pi_out, (size_t)capacity * d->n_pi * 4);
+  if (beta_int) A(ev->beta_frozen, nn * 4);
+  if (st != DP_OK) {
+    delete ev;
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(ev->cap.ptr, cap_int, nn * 4, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && beta_int)
+    e = hipMemcpyAsync(ev->beta_frozen.ptr, beta_int, nn * 4, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) {
+    delete ev;
+    return fail(DP_E_HIP, std::string("lane_create: ") + hipGetErrorString(e));
+  }
+  ev->beta_shared = beta_int != nullptr;
+  ev->have_cap = ev->have_pi = true;
+  ev->have_beta = beta_int != nullptr;
+  *out = ev;
+  return DP_OK;
+}
+
+dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bool backward,
+                   float *power, float *dpi) {
+  const dp_design *d = ev->d;
+  hipStream_t s = ev->stream();
+  ev->B = n;
+  ev->S = size ? n : 0;
+  ev->paired_sizes = size != nullptr;
+  if (d->n_pi > 0) {
+    DP_HIP_TRY(hipMemcpyAsync(ev->p_stage.ptr, p, (size_t)n * d->n_pi * 4, hipMemcpyHostToDevice, s));
+    DP_HIP_TRY(launch_load_pi(ev->p_stage.as<float>(), ev->sp.as<float>(), d->n_pi, n, s));
+  }
+  if (size && d->n_gates > 0) {
+    DP_HIP_TRY(hipMemcpyAsync(ev->size_stage.ptr, size, (size_t)n * d->n_gates * 4,
+                              hipMemcpyHostToDevice, s));
+    DP_HIP_TRY(launch_import_sizes(ev->size_stage.as<float>(), d->int2ext.as<int32_t>(),
+                                   ev->size.as<float>(), d->n_pi, d->n_gates, n, s));
+  }
+  DP_TRY(enqueue_forward(ev, nullptr));
+  DP_HIP_TRY(hipMemcpyAsync(power, ev->power.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  if (backward) {
+    const GraphView g = view(d);
+    SeedArgs sa{};
+    sa.seed_base = ev->seed_base.as<float>();
+    sa.size = size ? ev->size.as<float>() : nullptr;
+    sa.seed = ev->seed.as<float>();
+    sa.n_pi = d->n_pi;
+    sa.n_nets = d->n_nets;
+    sa.G = d->n_gates;
+    sa.B = n;
+    sa.S = ev->S;
+    sa.paired = ev->paired_sizes;
+    DP_HIP_TRY(launch_seed(sa, s));
+    BwdArgs ba{};
+    ba.sp = ev->sp.as<float>();
+    ba.beta = ev->beta.as<float>();
+    ba.seed = ev->seed.as<float>();
+    ba.contrib = ev->contrib.as<float>();
+    ba.B = n;
+    ba.C = n;
+    ba.cdiv = 1;
+    ba.ste = ev->prm.beta_grad == DP_BETA_STE;
+    for (int32_t l = d->depth; l >= 1; --l)
+      DP_HIP_TRY(launch_bwd_level(g, ba, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l], s));
+    DP_HIP_TRY(launch_bwd_pi(g, ba, ev->pi_out.as<float>(), s));
+    if (dpi && d->n_pi > 0)
+      DP_HIP_TRY(hipMemcpyAsync(dpi, ev->pi_out.ptr, (size_t)n * d->n_pi * 4,
+                                hipMemcpyDeviceToHost, s));
+  }
+  return DP_OK;
+}
+
+dp_status calibrate_beta(dp_design *d, const float *cap_ext, const dp_params *prm, float p_all,
+                         float *beta_int) {
+  dp_params hp = *prm;
+  hp.mode = DP_HYBRID;
+  dp_eval *ev = nullptr;
+  DP_TRY(dp_eval_create(d, 1, 0, &hp, &ev));
+  std::vector<float> p(d->n_pi, p_all);
+  dp_status st = dp_set_pi_prob(ev, p.data(), 0);
+  if (st == DP_OK) st = dp_set_caps(ev, cap_ext, 0);
+  if (st == DP_OK) st = dp_forward(ev, nullptr);
+  if (st == DP_OK) {
+    hipError_t e = hipMemcpyAsync(beta_int, ev->beta.ptr, (size_t)d->n_nets * 4,
+                                  hipMemcpyDeviceToDevice, ev->stream());
+    if (e == hipSuccess) e = hipStreamSynchronize(ev->stream());
+    if (e != hipSuccess) st = fail(DP_E_HIP, std::string("calibrate_beta: ") + hipGetErrorString(e));
+  }
+  dp_eval_destroy(ev);
+  return st;
+}
+
+}  // namespace dp
+

@@ -40,6 +40,13 @@ struct dp_eval {
   dp::DevBuf contrib;        // [3][G][C]
   dp::DevBuf pi_out;         // [C][n_pi] staging for host outputs
   dp::DevBuf stage[8];       // host-output staging
+  // A stream of its own (serving lanes); null = the context's stream.
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream() const { return own_stream ? own_stream : d->ctx->stream; }
+  // Column b uses size vector b (S == B) and power is [B] (serving).
+  bool paired_sizes = false;
+  // DP_FROZEN_BETA with one beta [n_nets] shared by every column (serving).
+  bool beta_shared = false;
   // profiling
   bool profiling = false;
   dp_profile prof{};
@@ -52,3 +59,26 @@ struct dp_eval {
   uint64_t graph_key = 0;
   ~dp_eval();
 };
+
+namespace dp {
+
+// Serving lanes: an eval with its own stream that runs whole batches without
+// validation or host synchronisation.  Implemented in dp_api.cpp.
+//   cap_int:   [n_nets] internal-order capacitances (device)
+//   beta_int:  [n_nets] internal-order frozen beta (device) or null
+dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipStream_t stream,
+                      const float *cap_int, const float *beta_int, dp_eval **out);
+// Enqueue one batch of n columns: p [n][n_pi] and sizes [n][n_gates] (caller
+// gate order, or null) in pinned host memory; outputs power [n] and, when
+// backward, dP/dp [n][n_pi] into pinned host memory.
+dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bool backward,
+                   float *power, float *dpi);
+// Device bytes a lane of `capacity` columns holds.
+size_t lane_bytes(const dp_design *d, int32_t capacity);
+// Hybrid calibration at probability p_all for every PI: beta [n_nets] in
+// internal order into beta_int (device), on the context's stream.
+dp_status calibrate_beta(dp_design *d, const float *cap_ext, const dp_params *prm, float p_all,
+                         float *beta_int);
+
+}  // namespace dp
+

@@ -85,7 +85,8 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
 struct FinalizeArgs {
   const float *sp;          // [n_nets][B]
   const uint32_t *ones, *tog;  // [n_nets][B] or null (modeled)
-  const float *beta_frozen; // [n_nets][B] or null
+  const float *beta_frozen; // [n_nets][B], or [n_nets] when beta_shared, or null
+  int32_t beta_shared;      // one frozen beta for every column
   const float *cap;         // [n_nets] internal
   int64_t T;                // simulated words
   float kappa, beta_min, beta_max;
@@ -114,6 +115,7 @@ hipError_t launch_export(const ExportArgs &a, hipStream_t s);
 struct PowerArgs {
   const float *xterm, *cap, *size;  // size: [S][G] internal or null
   int32_t n_pi, n_nets, G, B, S;    // S = 0: no sizes
+  int32_t paired;                   // column b uses size row b; power is [B]
   double *partial;                  // scratch
   int32_t n_chunks;
   float *power;                     // [B][S'] (device)
@@ -136,6 +138,7 @@ struct SeedArgs {
   const float *size;          // [S][G] internal or null
   float *seed;                // [n_nets][C]
   int32_t n_pi, n_nets, G, B, S, per_column;
+  int32_t paired;             // column b uses size row b
 };
 hipError_t launch_seed(const SeedArgs &a, hipStream_t s);
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
@@ -150,6 +153,7 @@ struct GradExportArgs {
   const float *size;          // [S][G] internal or null
   const int32_t *int2ext;
   int32_t n_pi, n_nets, G, B, S;
+  int32_t paired;             // column b uses size row b
   float *dcap;                // [n_nets] caller numbering (sum over b, s) or null
   float *dsize;               // [S][G] caller gate numbering (sum over b) or null
 };

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a) {
       beta = ta / tm;
     beta = fminf(fmaxf(beta, a.beta_min), a.beta_max);
   } else if (a.mode == 2) {
-    beta = a.beta_frozen[idx];
+    beta = a.beta_shared ? a.beta_frozen[n] : a.beta_frozen[idx];
   }
   const float C = a.cap[n];
   a.beta[idx] = beta;
@@ -428,11 +428,12 @@ __device__ __forceinline__ double block_sum_d(double v, double *lds) {
 
 __global__ __launch_bounds__(kBlock) void k_power_partial(PowerArgs a) {
   __shared__ double lds[kWavesPerBlock];
-  const int32_t n_cols = a.B * (a.S > 0 ? a.S : 1);
+  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
+  const int32_t n_cols = a.B * Sp;
   const int32_t col = (int32_t)(blockIdx.x / a.n_chunks);  // b * S' + s
   const int32_t chunk = (int32_t)(blockIdx.x - (uint32_t)col * a.n_chunks);
-  const int32_t Sp = a.S > 0 ? a.S : 1;
-  const int32_t b = col / Sp, s = col - b * Sp;
+  const int32_t b = col / Sp;
+  const int32_t s = a.paired ? b : col - b * Sp;
   const int32_t n_lo = chunk * kPowerChunk;
   const int32_t n_hi = min(n_lo + kPowerChunk, a.n_nets);
   double acc = 0.0;
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_c
 // seed[n][c]: the local adjoint term of net n for reverse column c, scaled by
 // the upstream weight and the driver's size factor.
 __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
-  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const int32_t C = a.per_column ? a.B * Sp : a.B;
   const int64_t idx = gidx();
   if (idx >= (int64_t)a.n_nets * C) return;
@@ -469,6 +470,11 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
     const float w = a.w ? a.w[c] : 1.0f;
     const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
     v = a.seed_base[(int64_t)n * a.B + b] * w * sz;
+  } else if (a.paired) {
+    const int32_t b = c;
+    const float w = a.w ? a.w[b] : 1.0f;
+    const float sz = gate ? a.size[(int64_t)b * a.G + (n - a.n_pi)] : 1.0f;
+    v = a.seed_base[(int64_t)n * a.B + b] * (w * sz);
   } else {
     const int32_t b = c;
     float ws = 0.0f;
@@ -529,14 +535,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float
 __global__ __launch_bounds__(kBlock) void k_grad_cap(GradExportArgs a) {
   const int64_t n = gidx();
   if (n >= a.n_nets) return;
-  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const bool gate = n >= a.n_pi && a.size;
   double acc = 0.0;
   for (int32_t b = 0; b < a.B; ++b) {
     float ws = 0.0f;
     for (int32_t s = 0; s < Sp; ++s) {
+      const int32_t row = a.paired ? b : s;
       const float w = a.w ? a.w[(int64_t)b * Sp + s] : 1.0f;
-      const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
+      const float sz = gate ? a.size[(int64_t)row * a.G + (n - a.n_pi)] : 1.0f;
       ws = fmaf(w, sz, ws);
     }
     acc += (double)a.xterm[n * a.B + b] * (double)ws;
@@ -550,9 +557,13 @@ __global__ __launch_bounds__(kBlock) void k_grad_size(GradExportArgs a) {
   const int32_t s = (int32_t)(idx / a.G), g = (int32_t)(idx - (int64_t)s * a.G);
   const int32_t n = a.n_pi + g;
   double acc = 0.0;
-  for (int32_t b = 0; b < a.B; ++b) {
-    const float w = a.w ? a.w[(int64_t)b * a.S + s] : 1.0f;
-    acc += (double)a.xterm[(int64_t)n * a.B + b] * (double)w;
+  if (a.paired) {  // size row s belongs to column s only
+    acc = (double)a.xterm[(int64_t)n * a.B + s] * (double)(a.w ? a.w[s] : 1.0f);
+  } else {
+    for (int32_t b = 0; b < a.B; ++b) {
+      const float w = a.w ? a.w[(int64_t)b * a.S + s] : 1.0f;
+      acc += (double)a.xterm[(int64_t)n * a.B + b] * (double)w;
+    }
   }
   a.dsize[(int64_t)s * a.G + (a.int2ext[n] - a.n_pi)] = (float)(acc * (double)a.cap[n]);
 }
@@ -693,7 +704,7 @@ int32_t power_chunks(int32_t n_nets) {
 }
 
 hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
-  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const int32_t n_cols = a.B * Sp;
   const int64_t blocks = (int64_t)a.n_chunks * n_cols;
   if (blocks > kMaxBlocks) return hipErrorInvalidValue;
@@ -705,7 +716,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_seed(const SeedArgs &a, hipStream_t s) {
-  const int32_t Sp = a.S > 0 ? a.S : 1;
+  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const int64_t C = a.per_column ? (int64_t)a.B * Sp : a.B;
   const int64_t n = (int64_t)a.n_nets * C;
   if (n <= 0) return hipSuccess;

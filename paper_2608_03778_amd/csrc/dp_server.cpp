@@ -1,34 +1,399 @@
 // Serving layer: continuous batching of forward / gradient queries against
-// device-resident designs.
-#include "dp_internal.h"
+// device-resident compiled designs.
+//
+// Optimizer clients submit queries (a design id, their own PI probabilities
+// and per-gate size factors) and return at once.  A scheduler thread:
+//   * admits pending queries into idle lanes of their design, oldest first,
+//     as long as the lanes' device memory stays inside the HBM budget
+//     (a lane is an eval of `capacity` columns with its own stream);
+//   * launches each filled lane as one batched sweep (column b = query b),
+//     so lanes of different designs, and several lanes of one design, run
+//     concurrently on the device while new queries keep arriving;
+//   * polls lane completion events, copies results to the queries' buffers
+//     and timestamps them.
+// A query's result does not depend on the batch it rides in: every column
+// of a sweep is computed independently and reduced in a fixed order.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "dp_eval.h"
 
 using dp::fail;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t design = 0, kind = 0;
+  const float *p = nullptr, *size = nullptr;
+  float *out_power = nullptr, *out_dpi = nullptr;
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+};
+
+struct DesignEntry {
+  dp_design *d = nullptr;
+  dp_params prm{};
+  dp::DevBuf cap_int, beta_int;
+  bool frozen = false;
+};
+
+struct Lane {
+  dp_eval *ev = nullptr;
+  int32_t design = 0, capacity = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<Request *> batch;
+  float *pin_p = nullptr, *pin_size = nullptr, *pin_power = nullptr, *pin_dpi = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
 
 struct dp_server {
   dp_ctx *ctx = nullptr;
+  size_t budget = 0;
+  int32_t max_batch = 64, max_inflight = 8;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> pending;
+  std::unordered_map<uint64_t, Request *> reqs;
+  std::vector<DesignEntry *> designs;
+  std::vector<Lane *> lanes;
+  size_t used = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread th;
+  dp_server_stats st{};
+  Clock::time_point busy_since;
+  int32_t inflight = 0;
+  std::string thread_error;
 };
+
+namespace {
+
+void destroy_lane(Lane *l) {
+  if (l->stream) (void)hipStreamSynchronize(l->stream);
+  dp_eval_destroy(l->ev);
+  if (l->done) (void)hipEventDestroy(l->done);
+  if (l->stream) (void)hipStreamDestroy(l->stream);
+  (void)hipHostFree(l->pin_p);
+  (void)hipHostFree(l->pin_size);
+  (void)hipHostFree(l->pin_power);
+  (void)hipHostFree(l->pin_dpi);
+  delete l;
+}
+
+// Create a lane for `design` holding up to `cap` columns (caller holds mu).
+Lane *make_lane(dp_server *s, int32_t design, int32_t cap) {
+  DesignEntry *de = s->designs[design];
+  auto *l = new Lane();
+  l->design = design;
+  l->capacity = cap;
+  const dp_design *d = de->d;
+  bool ok = hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&l->done, hipEventDisableTiming) == hipSuccess &&
+            hipHostMalloc((void **)&l->pin_p, std::max<size_t>((size_t)cap * d->n_pi * 4, 16)) == hipSuccess &&
+            hipHostMalloc((void **)&l->pin_size, std::max<size_t>((size_t)cap * d->n_gates * 4, 16)) == hipSuccess &&
+            hipHostMalloc((void **)&l->pin_power, (size_t)cap * 4) == hipSuccess &&
+            hipHostMalloc((void **)&l->pin_dpi, std::max<size_t>((size_t)cap * d->n_pi * 4, 16)) == hipSuccess;
+  if (ok)
+    ok = dp::lane_create(de->d, cap, &de->prm, l->stream, de->cap_int.as<float>(),
+                         de->frozen ? de->beta_int.as<float>() : nullptr, &l->ev) == DP_OK;
+  if (!ok) {
+    (void)hipGetLastError();
+    destroy_lane(l);
+    return nullptr;
+  }
+  l->bytes = dp::lane_bytes(d, cap);
+  s->lanes.push_back(l);
+  s->used += l->bytes;
+  s->st.peak_slot_bytes = std::max<int64_t>(s->st.peak_slot_bytes, (int64_t)s->used);
+  return l;
+}
+
+// Free idle lanes of other designs until `need` bytes fit (caller holds mu).
+bool make_room(dp_server *s, size_t need, int32_t keep_design) {
+  for (size_t i = 0; i < s->lanes.size() && s->used + need > s->budget;) {
+    Lane *l = s->lanes[i];
+    if (!l->busy && l->design != keep_design) {
+      s->used -= l->bytes;
+      destroy_lane(l);
+      s->lanes.erase(s->lanes.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  return s->used + need <= s->budget;
+}
+
+void launch_lane(dp_server *s, Lane *l) {
+  const dp_design *d = s->designs[l->design]->d;
+  const int32_t n = (int32_t)l->batch.size();
+  bool any_size = false;
+  for (int32_t b = 0; b < n; ++b) {
+    Request *r = l->batch[b];
+    std::memcpy(l->pin_p + (size_t)b * d->n_pi, r->p, (size_t)d->n_pi * 4);
+    any_size |= r->size != nullptr;
+  }
+  if (any_size)
+    for (int32_t b = 0; b < n; ++b) {
+      float *dst = l->pin_size + (size_t)b * d->n_gates;
+      if (l->batch[b]->size)
+        std::memcpy(dst, l->batch[b]->size, (size_t)d->n_gates * 4);
+      else
+        std::fill(dst, dst + d->n_gates, 1.0f);
+    }
+  const bool bwd = l->batch[0]->kind == DP_Q_FWD_BWD;
+  dp_status rc = dp::lane_run(l->ev, n, l->pin_p, any_size ? l->pin_size : nullptr, bwd,
+                              l->pin_power, l->pin_dpi);
+  if (rc == DP_OK && hipEventRecord(l->done, l->stream) != hipSuccess) rc = DP_E_HIP;
+  if (rc != DP_OK) s->thread_error = dp_last_error();
+  l->busy = true;
+  if (s->inflight++ == 0) s->busy_since = Clock::now();
+  s->st.max_inflight = std::max(s->st.max_inflight, s->inflight);
+  s->st.device_steps++;
+}
+
+void finish_lane(dp_server *s, Lane *l) {
+  const dp_design *d = s->designs[l->design]->d;
+  const auto now = Clock::now();
+  for (size_t b = 0; b < l->batch.size(); ++b) {
+    Request *r = l->batch[b];
+    if (r->out_power) *r->out_power = l->pin_power[b];
+    if (r->out_dpi && r->kind == DP_Q_FWD_BWD)
+      std::memcpy(r->out_dpi, l->pin_dpi + b * (size_t)d->n_pi, (size_t)d->n_pi * 4);
+    r->t_done = now;
+    r->done = true;
+    s->st.completed++;
+  }
+  l->batch.clear();
+  l->busy = false;
+  if (--s->inflight == 0)
+    s->st.busy_s += std::chrono::duration<double>(now - s->busy_since).count();
+}
+
+// Admit pending queries into idle lanes, oldest first (caller holds mu).
+void admit(dp_server *s) {
+  for (size_t i = 0; i < s->pending.size() && s->inflight < s->max_inflight;) {
+    Request *r = s->pending[i];
+    Lane *lane = nullptr;
+    for (Lane *l : s->lanes)
+      if (!l->busy && l->design == r->design) {
+        lane = l;
+        break;
+      }
+    if (!lane) {
+      const dp_design *d = s->designs[r->design]->d;
+      int32_t want = 0;  // queries of this design waiting
+      for (Request *q : s->pending) want += q->design == r->design;
+      int32_t cap = std::min(s->max_batch, std::max(want, 1));
+      // round the capacity up to a power of two so lanes are reused
+      int32_t c2 = 1;
+      while (c2 < cap) c2 <<= 1;
+      cap = std::min(c2, s->max_batch);
+      while (cap > 1 && dp::lane_bytes(d, cap) > s->budget) cap >>= 1;
+      const size_t need = dp::lane_bytes(d, cap);
+      if (s->used + need > s->budget && !make_room(s, need, r->design)) {
+        ++i;  // no memory now; a running lane will free some
+        continue;
+      }
+      lane = make_lane(s, r->design, cap);
+      if (!lane) {
+        ++i;
+        continue;
+      }
+    }
+    // fill the lane with same-design, same-kind queries in arrival order
+    for (size_t j = i; j < s->pending.size() && (int32_t)lane->batch.size() < lane->capacity;) {
+      Request *q = s->pending[j];
+      if (q->design == r->design && q->kind == r->kind) {
+        lane->batch.push_back(q);
+        s->pending.erase(s->pending.begin() + j);
+      } else {
+        ++j;
+      }
+    }
+    launch_lane(s, lane);
+  }
+}
+
+void scheduler(dp_server *s) {
+  (void)hipSetDevice(s->ctx->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    bool completed = false;
+    for (Lane *l : s->lanes)
+      if (l->busy && hipEventQuery(l->done) == hipSuccess) {
+        finish_lane(s, l);
+        completed = true;
+      }
+    if (completed) s->cv_done.notify_all();
+    admit(s);
+    if (s->inflight == 0 && s->pending.empty()) {
+      s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+    } else if (s->inflight == 0) {  // nothing could be admitted (allocation failed)
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+    } else {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    }
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
-dp_status dp_server_create(dp_ctx *ctx, size_t, dp_server **out) {
+dp_status dp_server_create(dp_ctx *ctx, size_t hbm_budget_bytes, dp_server **out) {
   if (!ctx || !out) return fail(DP_E_INVALID, "dp_server_create: NULL argument");
-  return fail(DP_E_UNSUPPORTED, "dp_server_create: serving is not built yet");
+  if (hbm_budget_bytes == 0) return fail(DP_E_INVALID, "dp_server_create: zero budget");
+  auto *s = new dp_server();
+  s->ctx = ctx;
+  s->budget = hbm_budget_bytes;
+  s->th = std::thread(scheduler, s);
+  *out = s;
+  return DP_OK;
 }
-dp_status dp_server_add_design(dp_server *, dp_design *, const float *, const dp_params *, int32_t *) {
-  return fail(DP_E_UNSUPPORTED, "serving is not built yet");
+
+dp_status dp_server_configure(dp_server *s, int32_t max_batch, int32_t max_inflight) {
+  if (!s || max_batch < 1 || max_inflight < 1)
+    return fail(DP_E_INVALID, "dp_server_configure: need max_batch >= 1, max_inflight >= 1");
+  std::lock_guard<std::mutex> g(s->mu);
+  s->max_batch = max_batch;
+  s->max_inflight = max_inflight;
+  return DP_OK;
 }
-dp_status dp_submit(dp_server *, const dp_query *, uint64_t *) {
-  return fail(DP_E_UNSUPPORTED, "serving is not built yet");
+
+dp_status dp_server_add_design(dp_server *s, dp_design *d, const float *cap,
+                               const dp_params *params, int32_t *design_id) {
+  if (!s || !d || !cap || !params || !design_id)
+    return fail(DP_E_INVALID, "dp_server_add_design: NULL argument");
+  if (params->mode == DP_HYBRID)
+    return fail(DP_E_UNSUPPORTED,
+                "dp_server_add_design: queries run DP_MODELED or DP_FROZEN_BETA (beta is "
+                "calibrated once here)");
+  for (int32_t n = 0; n < d->n_nets; ++n)
+    if (!(cap[n] >= 0.0f && cap[n] <= 3.0e38f))
+      return fail(DP_E_INVALID, "dp_server_add_design: bad capacitance");
+  auto *de = new DesignEntry();
+  de->d = d;
+  de->prm = *params;
+  de->frozen = params->mode == DP_FROZEN_BETA;
+  dp_status st = de->cap_int.alloc((size_t)d->n_nets * 4 + 16);
+  if (st == DP_OK) {
+    std::vector<float> ci(d->n_nets);
+    for (int32_t n = 0; n < d->n_nets; ++n) ci[n] = cap[d->h_int2ext[n]];
+    hipError_t e = hipMemcpy(de->cap_int.ptr, ci.data(), ci.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = fail(DP_E_HIP, std::string("dp_server_add_design: ") + hipGetErrorString(e));
+  }
+  if (st == DP_OK && de->frozen) {
+    st = de->beta_int.alloc((size_t)d->n_nets * 4 + 16);
+    if (st == DP_OK) st = dp::calibrate_beta(d, cap, params, 0.5f, de->beta_int.as<float>());
+  }
+  if (st != DP_OK) {
+    delete de;
+    return st;
+  }
+  std::lock_guard<std::mutex> g(s->mu);
+  *design_id = (int32_t)s->designs.size();
+  s->designs.push_back(de);
+  return DP_OK;
 }
-dp_status dp_poll(dp_server *, uint64_t, int32_t *) {
-  return fail(DP_E_UNSUPPORTED, "serving is not built yet");
+
+dp_status dp_submit(dp_server *s, const dp_query *q, uint64_t *ticket) {
+  if (!s || !q || !ticket) return fail(DP_E_INVALID, "dp_submit: NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (q->design_id < 0 || q->design_id >= (int32_t)s->designs.size())
+    return fail(DP_E_NOTFOUND, "dp_submit: unknown design id");
+  if (q->kind != DP_Q_FWD && q->kind != DP_Q_FWD_BWD)
+    return fail(DP_E_INVALID, "dp_submit: unknown query kind");
+  const dp_design *d = s->designs[q->design_id]->d;
+  if (dp::lane_bytes(d, 1) > s->budget)
+    return fail(DP_E_BUDGET, "dp_submit: one query of this design exceeds the HBM budget");
+  if (!s->thread_error.empty()) return fail(DP_E_HIP, "server: " + s->thread_error);
+  lk.unlock();
+  if (!q->pi_prob) return fail(DP_E_INVALID, "dp_submit: NULL pi_prob");
+  for (int32_t i = 0; i < d->n_pi; ++i)
+    if (!(q->pi_prob[i] >= 0.0f && q->pi_prob[i] <= 1.0f))
+      return fail(DP_E_INVALID, "dp_submit: PI probability NaN or outside [0, 1]");
+  if (q->cap_scale)
+    for (int32_t g = 0; g < d->n_gates; ++g)
+      if (!(q->cap_scale[g] >= 0.0f && q->cap_scale[g] <= 3.0e38f))
+        return fail(DP_E_INVALID, "dp_submit: bad cap_scale");
+  auto *r = new Request();
+  r->design = q->design_id;
+  r->kind = q->kind;
+  r->p = q->pi_prob;
+  r->size = q->cap_scale;
+  r->out_power = q->power;
+  r->out_dpi = q->dpower_dpi;
+  r->t_submit = Clock::now();
+  lk.lock();
+  r->ticket = s->next_ticket++;
+  s->reqs[r->ticket] = r;
+  s->pending.push_back(r);
+  s->st.submitted++;
+  *ticket = r->ticket;
+  lk.unlock();
+  s->cv_work.notify_one();
+  return DP_OK;
 }
-dp_status dp_wait(dp_server *, uint64_t, double *) {
-  return fail(DP_E_UNSUPPORTED, "serving is not built yet");
+
+dp_status dp_poll(dp_server *s, uint64_t ticket, int32_t *done) {
+  if (!s || !done) return fail(DP_E_INVALID, "dp_poll: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(DP_E_NOTFOUND, "dp_poll: unknown ticket");
+  *done = it->second->done ? 1 : 0;
+  return DP_OK;
 }
-dp_status dp_server_get_stats(dp_server *, dp_server_stats *) {
-  return fail(DP_E_UNSUPPORTED, "serving is not built yet");
+
+dp_status dp_wait(dp_server *s, uint64_t ticket, double *latency_s) {
+  if (!s) return fail(DP_E_INVALID, "dp_wait: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(DP_E_NOTFOUND, "dp_wait: unknown ticket");
+  Request *r = it->second;
+  s->cv_done.wait(lk, [&] { return r->done || !s->thread_error.empty(); });
+  if (!r->done) return fail(DP_E_HIP, "server: " + s->thread_error);
+  if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  s->reqs.erase(it);
+  delete r;
+  return DP_OK;
 }
-void dp_server_destroy(dp_server *srv) { delete srv; }
+
+dp_status dp_server_get_stats(dp_server *s, dp_server_stats *out) {
+  if (!s || !out) return fail(DP_E_INVALID, "dp_server_get_stats: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  *out = s->st;
+  if (s->inflight > 0)
+    out->busy_s += std::chrono::duration<double>(Clock::now() - s->busy_since).count();
+  return DP_OK;
+}
+
+void dp_server_destroy(dp_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (Lane *l : s->lanes) destroy_lane(l);
+  for (DesignEntry *de : s->designs) delete de;
+  for (auto &kv : s->reqs) delete kv.second;
+  delete s;
+}
 
 }  // extern "C"
