@@ -69,6 +69,8 @@ def _declare(lib):
     lib.orc_stimulus.restype = None
     lib.orc_sim.argtypes = [_i32, _i32, _p, _p, _p, _p, _i64, _p, _p, _u64, _p, _p]
     lib.orc_sim.restype = None
+    lib.orc_sim_range.argtypes = [_i32, _i32, _p, _p, _p, _p, _i64, _i64, _p, _u64, _p, _p]
+    lib.orc_sim_range.restype = None
     lib.orc_power.argtypes = [_i32, _i32, _p, _p, _p, _i64, _p, _p, _d, _int, _d, _d, _p,
                               _p, _p, _p, _p, _p, _p]
     lib.orc_power.restype = _d
@@ -133,6 +135,16 @@ class Netlist:
         tog = np.zeros(self.n_nets, dtype=np.uint64)
         _load().orc_sim(*self._args(), int(n_words), _ptr(w), _ptr(p), int(seed), _ptr(ones),
                         _ptr(tog))
+        return ones, tog
+
+    def sim_range(self, t_begin, t_end, p_pi, seed=0):
+        """(ones, toggles) over the cycles [t_begin, t_end) with generated
+        stimulus; disjoint ranges add up."""
+        p = _c(p_pi, np.float32)
+        ones = np.zeros(self.n_nets, dtype=np.uint64)
+        tog = np.zeros(self.n_nets, dtype=np.uint64)
+        _load().orc_sim_range(*self._args(), int(t_begin), int(t_end), _ptr(p), int(seed),
+                              _ptr(ones), _ptr(tog))
         return ones, tog
 
     def power(self, P, cap, size=None, *, kappa=0.5, hybrid=False, ones=None, toggles=None,

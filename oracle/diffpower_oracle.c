@@ -313,19 +313,32 @@ static int popcount64(uint64_t x) {
  * ones[n] adds popcount(w_n(t)) and, for t >= 1, toggles[n] adds
  * popcount(w_n(t) ^ w_n(t-1)).  The stimulus is read from `pi_words`
  * ([n_pi][T]) when given, otherwise generated from (p_pi, seed). */
+/* Counts restricted to the cycles [t_begin, t_end): ones over those cycles,
+ * toggles for the transitions into them (cycle t_begin - 1 is simulated
+ * too when t_begin > 0).  Counts of disjoint ranges add up to the counts of
+ * their union.  Generated stimulus only. */
+void orc_sim_range(int32_t n_pi, int32_t n_gates, const uint8_t *op,
+                   const int32_t *fanin_ptr, const int32_t *fanin,
+                   const int32_t *order, int64_t t_begin, int64_t t_end,
+                   const float *p_pi, uint64_t seed, uint64_t *ones,
+                   uint64_t *toggles);
+
 void orc_sim(int32_t n_pi, int32_t n_gates, const uint8_t *op,
              const int32_t *fanin_ptr, const int32_t *fanin,
              const int32_t *order, int64_t T, const uint64_t *pi_words,
              const float *p_pi, uint64_t seed, uint64_t *ones,
              uint64_t *toggles) {
+  if (!pi_words) {
+    orc_sim_range(n_pi, n_gates, op, fanin_ptr, fanin, order, 0, T, p_pi, seed,
+                  ones, toggles);
+    return;
+  }
   int64_t n_nets = (int64_t)n_pi + n_gates;
   uint64_t *cur = calloc((size_t)n_nets, sizeof(uint64_t));
   uint64_t *prev = calloc((size_t)n_nets, sizeof(uint64_t));
   for (int64_t n = 0; n < n_nets; ++n) ones[n] = toggles[n] = 0;
   for (int64_t t = 0; t < T; ++t) {
-    for (int32_t i = 0; i < n_pi; ++i)
-      cur[i] = pi_words ? pi_words[(int64_t)i * T + t]
-                        : orc_stimulus_word(i, t, p_pi[i], seed);
+    for (int32_t i = 0; i < n_pi; ++i) cur[i] = pi_words[(int64_t)i * T + t];
     for (int32_t k = 0; k < n_gates; ++k) {
       int32_t g = order[k];
       uint64_t w[3] = {0, 0, 0};
@@ -336,6 +349,37 @@ void orc_sim(int32_t n_pi, int32_t n_gates, const uint8_t *op,
     for (int64_t n = 0; n < n_nets; ++n) {
       ones[n] += (uint64_t)popcount64(cur[n]);
       if (t > 0) toggles[n] += (uint64_t)popcount64(cur[n] ^ prev[n]);
+    }
+    uint64_t *tmp = prev;
+    prev = cur;
+    cur = tmp;
+  }
+  free(cur);
+  free(prev);
+}
+
+void orc_sim_range(int32_t n_pi, int32_t n_gates, const uint8_t *op,
+                   const int32_t *fanin_ptr, const int32_t *fanin,
+                   const int32_t *order, int64_t t_begin, int64_t t_end,
+                   const float *p_pi, uint64_t seed, uint64_t *ones,
+                   uint64_t *toggles) {
+  int64_t n_nets = (int64_t)n_pi + n_gates;
+  uint64_t *cur = calloc((size_t)n_nets, sizeof(uint64_t));
+  uint64_t *prev = calloc((size_t)n_nets, sizeof(uint64_t));
+  for (int64_t n = 0; n < n_nets; ++n) ones[n] = toggles[n] = 0;
+  int64_t t_first = t_begin > 0 ? t_begin - 1 : 0;
+  for (int64_t t = t_first; t < t_end; ++t) {
+    for (int32_t i = 0; i < n_pi; ++i) cur[i] = orc_stimulus_word(i, t, p_pi[i], seed);
+    for (int32_t k = 0; k < n_gates; ++k) {
+      int32_t g = order[k];
+      uint64_t w[3] = {0, 0, 0};
+      for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
+        w[e - fanin_ptr[g]] = cur[fanin[e]];
+      cur[n_pi + g] = bit_rule(op[g], w);
+    }
+    for (int64_t n = 0; n < n_nets; ++n) {
+      if (t >= t_begin) ones[n] += (uint64_t)popcount64(cur[n]);
+      if (t > t_first) toggles[n] += (uint64_t)popcount64(cur[n] ^ prev[n]);
     }
     uint64_t *tmp = prev;
     prev = cur;

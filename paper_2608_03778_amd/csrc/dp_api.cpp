@@ -17,6 +17,24 @@ dp_status fail(dp_status st, const std::string &msg) {
 }
 void clear_error() { g_err.clear(); }
 
+void ctx_retain(dp_ctx *c) { c->refs.fetch_add(1); }
+void ctx_release(dp_ctx *c) {
+  if (c->refs.fetch_sub(1) != 1) return;
+  if (c->owned) {
+    (void)hipStreamSynchronize(c->owned);
+    (void)hipStreamDestroy(c->owned);
+  }
+  delete c;
+}
+void design_retain(dp_design *d) { d->refs.fetch_add(1); }
+void design_release(dp_design *d) {
+  if (d->refs.fetch_sub(1) != 1) return;
+  dp_ctx *c = d->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  delete d;
+  ctx_release(c);
+}
+
 }  // namespace dp
 
 using dp::DevBuf;
@@ -110,7 +128,9 @@ struct SpanGuard {
   int kind;
   double bytes;
   bool on;
-  SpanGuard(dp_eval *e, int k, double b, bool enabled) : ev(e), kind(k), bytes(b), on(enabled) {
+  int64_t launches;
+  SpanGuard(dp_eval *e, int k, double b, bool enabled, int64_t n_launch)
+      : ev(e), kind(k), bytes(b), on(enabled), launches(n_launch) {
     if (on) {
       a = ev->ev_used;
       hipEvent_t x = take_event(ev);
@@ -124,7 +144,7 @@ struct SpanGuard {
     hipEvent_t x = take_event(ev);
     if (!x) return;
     (void)hipEventRecord(x, ev->stream());
-    ev->spans.push_back({a, b, kind, bytes});
+    ev->spans.push_back({a, b, kind, bytes, launches});
   }
 };
 
@@ -138,10 +158,10 @@ dp_status resolve_profile(dp_eval *ev) {
     float ms = 0.0f;
     DP_HIP_TRY(hipEventElapsedTime(&ms, ev->ev_pool[sp.a], ev->ev_pool[sp.b]));
     switch (sp.kind) {
-      case SPAN_SIM: ev->prof.sim_ms += ms; ev->prof.sim_launches++; ev->prof.sim_bytes += sp.bytes; break;
-      case SPAN_SP: ev->prof.sp_ms += ms; ev->prof.sp_launches++; ev->prof.sp_bytes += sp.bytes; break;
-      case SPAN_BWD: ev->prof.bwd_ms += ms; ev->prof.bwd_launches++; ev->prof.bwd_bytes += sp.bytes; break;
-      default: ev->prof.stim_ms += ms; ev->prof.stim_launches++; break;
+      case SPAN_SIM: ev->prof.sim_ms += ms; ev->prof.sim_launches += sp.launches; ev->prof.sim_bytes += sp.bytes; break;
+      case SPAN_SP: ev->prof.sp_ms += ms; ev->prof.sp_launches += sp.launches; ev->prof.sp_bytes += sp.bytes; break;
+      case SPAN_BWD: ev->prof.bwd_ms += ms; ev->prof.bwd_launches += sp.launches; ev->prof.bwd_bytes += sp.bytes; break;
+      default: ev->prof.stim_ms += ms; ev->prof.stim_launches += sp.launches; break;
     }
   }
   ev->spans.clear();
@@ -251,10 +271,12 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   const dp::GraphView g = view(d);
   const bool prof = ev->profiling;
   float *sp = ev->sp.as<float>();
-  if (!pl) {  // modeled (or frozen-beta) sweep
+  if (!pl) {  // modeled (or frozen-beta) sweep: one span over all level launches
+    double bytes = 0.0;
+    for (int32_t l = 1; l <= d->depth; ++l) bytes += sp_level_bytes(d, l, ev->B);
+    SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth);
     for (int32_t l = 1; l <= d->depth; ++l) {
       dp::SpLevel lv{sp, ev->B, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l]};
-      SpanGuard sg(ev, SPAN_SP, sp_level_bytes(d, l, ev->B), prof);
       DP_HIP_TRY(dp::launch_sp_level(g, lv, s));
     }
   } else {
@@ -269,15 +291,18 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       for (int32_t k = 0; k < pl->n_chunks; ++k) {
         const dp::ChunkView cv = chunk_view(ev, *pl, k);
         {
-          SpanGuard sg(ev, SPAN_STIM, 0.0, prof);
+          SpanGuard sg(ev, SPAN_STIM, 0.0, prof, 1);
           DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, ev->prm.seed, tune, s));
         }
         const bool fuse = (b == 0 && k == 0);
         const int64_t nw = cv.u_hi - cv.u_lo;
+        double bytes = 0.0;
+        for (int32_t l = 1; l <= d->depth; ++l) bytes += sim_level_bytes(d, l, nw, ev->B, fuse);
+        // one span over the chunk's level launches (their back-to-back time)
+        SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth);
         for (int32_t l = 1; l <= d->depth; ++l) {
           const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
           dp::SpLevel lv{sp, ev->B, g0, n};
-          SpanGuard sg(ev, SPAN_SIM, sim_level_bytes(d, l, nw, ev->B, fuse), prof);
           DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, tune, s));
         }
       }
@@ -467,12 +492,7 @@ dp_status dp_ctx_synchronize(dp_ctx *ctx) {
 }
 
 void dp_ctx_destroy(dp_ctx *ctx) {
-  if (!ctx) return;
-  if (ctx->owned) {
-    (void)hipStreamSynchronize(ctx->owned);
-    (void)hipStreamDestroy(ctx->owned);
-  }
-  delete ctx;
+  if (ctx) dp::ctx_release(ctx);
 }
 
 dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out) {
@@ -503,9 +523,7 @@ dp_status dp_design_levels(const dp_design *d, int32_t *level) {
 }
 
 void dp_design_destroy(dp_design *d) {
-  if (!d) return;
-  (void)hipStreamSynchronize(d->ctx->stream);
-  delete d;
+  if (d) dp::design_release(d);
 }
 
 dp_status dp_eval_create(dp_design *d, int32_t n_cols, int32_t n_size, const dp_params *params,
@@ -526,6 +544,7 @@ dp_status dp_eval_create(dp_design *d, int32_t n_cols, int32_t n_size, const dp_
     delete ev;
     return st;
   }
+  dp::design_retain(d);
   *out = ev;
   return DP_OK;
 }
@@ -541,7 +560,9 @@ dp_status dp_eval_set_params(dp_eval *ev, const dp_params *params) {
 void dp_eval_destroy(dp_eval *ev) {
   if (!ev) return;
   (void)hipStreamSynchronize(ev->stream());
+  dp_design *d = ev->d;
   delete ev;
+  dp::design_release(d);
 }
 
 dp_status dp_set_pi_prob(dp_eval *ev, const float *p, int32_t on_device) {
@@ -762,10 +783,14 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     ba.C = C;
     ba.cdiv = per_column ? Sp : 1;
     ba.ste = ev->prm.beta_grad == DP_BETA_STE;
-    for (int32_t l = d->depth; l >= 1; --l) {
-      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-      SpanGuard sg(ev, SPAN_BWD, bwd_level_bytes(d, l, C), ev->profiling);
-      DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
+    double bwd_bytes = 0.0;
+    for (int32_t l = d->depth; l >= 1; --l) bwd_bytes += bwd_level_bytes(d, l, C);
+    {
+      SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
+      for (int32_t l = d->depth; l >= 1; --l) {
+        const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+        DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
+      }
     }
     float *dst = dpi;
     const size_t bytes = (size_t)C * d->n_pi * sizeof(float);
@@ -872,6 +897,7 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   ev->beta_shared = beta_int != nullptr;
   ev->have_cap = ev->have_pi = true;
   ev->have_beta = beta_int != nullptr;
+  design_retain(d);
   *out = ev;
   return DP_OK;
 }

@@ -191,6 +191,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
   }
   d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
                               d->int2ext.bytes + d->ext2int.bytes);
+  ctx_retain(ctx);
   *out = d;
   return DP_OK;
 }

@@ -52,7 +52,7 @@ struct dp_eval {
   dp_profile prof{};
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Span { size_t a, b; int kind; double bytes; };
+  struct Span { size_t a, b; int kind; double bytes; int64_t launches; };
   std::vector<Span> spans;
   // captured sweeps
   hipGraphExec_t graph_fwd = nullptr;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -48,10 +49,15 @@ struct DevBuf {
 
 }  // namespace dp
 
+// Contexts and designs are reference counted: a design holds its context,
+// an eval (and a server lane) holds its design, a server holds its context
+// and its designs.  *_destroy drops the caller's reference, so handles may be
+// destroyed in any order.
 struct dp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;   // stream calls enqueue on
   hipStream_t owned = nullptr;    // stream created by the library, if any
+  std::atomic<int> refs{1};
 };
 
 // Immutable compiled design.  Internal numbering: PIs keep ids [0, n_pi);
@@ -59,6 +65,7 @@ struct dp_ctx {
 // net n_pi + g'.  Level l (1..depth) holds gates [level_ptr[l], level_ptr[l+1]).
 struct dp_design {
   dp_ctx *ctx = nullptr;
+  std::atomic<int> refs{1};
   int32_t n_pi = 0, n_gates = 0, n_nets = 0, depth = 0;
   int64_t n_edges = 0;
   std::vector<int32_t> level_ptr;     // [depth + 2], level_ptr[1] = 0
@@ -85,5 +92,10 @@ namespace dp {
 // Host-side compile: validation, levelization, sort, renumbering and the
 // device upload.  Implemented in dp_compile.cpp.
 dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out);
+
+void ctx_retain(dp_ctx *c);
+void ctx_release(dp_ctx *c);
+void design_retain(dp_design *d);
+void design_release(dp_design *d);
 
 }  // namespace dp

@@ -155,10 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_import_sizes(const float *__restrict
 // ---------------------------------------------------------------- SP level
 // One lane per (gate, column) of level [g0, g0 + n): gather the fan-in
 // probabilities, apply the cell rule, clip to [0, 1] (Alg. 2).
-__device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, int64_t idx) {
+__device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, uint32_t idx) {
   const int32_t B = lv.B;
-  const int32_t gl = (int32_t)(idx / B);
-  const int32_t b = (int32_t)(idx - (int64_t)gl * B);
+  const uint32_t gl32 = idx / (uint32_t)B;
+  const int32_t gl = (int32_t)gl32;
+  const int32_t b = (int32_t)(idx - gl32 * (uint32_t)B);
   const int32_t gi = lv.g0 + gl;
   const int op = g.op[gi];
   const int k = arity_of(op);
@@ -169,8 +170,8 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, i
 }
 
 __global__ __launch_bounds__(kBlock) void k_sp_level(GraphView g, SpLevel lv) {
-  int64_t idx = gidx();
-  if (idx < (int64_t)lv.n * lv.B) sp_item(g, lv, idx);
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item(g, lv, idx);
 }
 
 // ---------------------------------------------------------------- simulation
@@ -232,8 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_sim_level(GraphView g, ChunkView c, 
                                                       int32_t g0, int32_t n, int32_t waves_per_row,
                                                       int32_t sim_blocks, SpLevel sp) {
   if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level
-    const int64_t idx = (int64_t)(blockIdx.x - sim_blocks) * kBlock + threadIdx.x;
-    if (idx < (int64_t)sp.n * sp.B) sp_item(g, sp, idx);
+    const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kBlock + threadIdx.x;
+    if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item(g, sp, idx);
     return;
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -368,9 +369,9 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
 // per-unit-capacitance power of the net (Eq. 1); seed_base is the local
 // adjoint term kappa beta C 2(1 - 2P) (without the driver's size factor).
 __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a) {
-  const int64_t idx = gidx();
-  if (idx >= (int64_t)a.n_nets * a.B) return;
-  const int32_t n = (int32_t)(idx / a.B);
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (uint32_t)a.n_nets * (uint32_t)a.B) return;
+  const int32_t n = (int32_t)(idx / (uint32_t)a.B);
   const float P = a.sp[idx];
   const float tm = 2.0f * P * (1.0f - P);
   float beta = 1.0f;
@@ -460,9 +461,9 @@ __global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_c
 __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const int32_t C = a.per_column ? a.B * Sp : a.B;
-  const int64_t idx = gidx();
-  if (idx >= (int64_t)a.n_nets * C) return;
-  const int32_t n = (int32_t)(idx / C), c = (int32_t)(idx - (int64_t)n * C);
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (uint32_t)a.n_nets * (uint32_t)C) return;
+  const int32_t n = (int32_t)(idx / (uint32_t)C), c = (int32_t)(idx - (uint32_t)n * (uint32_t)C);
   const bool gate = n >= a.n_pi && a.size;
   float v;
   if (a.per_column) {
@@ -488,22 +489,69 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   a.seed[idx] = v;
 }
 
+// Sum of the contributions the readers of a net left on their fan-in slots,
+// in an order fixed by the graph alone (not by the column, its lane or the
+// batch): nets with at most kLightFanout readers are summed serially in
+// fan-out order by their own lane, with the loads of four edges in flight
+// at once; heavier nets are summed by the whole wave, lane l taking edges
+// l, l + 64, ..., then a butterfly reduction.  Every lane of the wave must
+// call this (inactive lanes pass e0 == e1 and active == false).
+constexpr int32_t kLightFanout = 8;
+
+__device__ __forceinline__ float pull_sum(const float *__restrict__ contrib,
+                                          const int32_t *__restrict__ rev_edge, int32_t e0,
+                                          int32_t e1, int32_t C, int32_t c, bool active,
+                                          int lane) {
+  float acc = 0.0f;
+  const bool light = active && (e1 - e0) <= kLightFanout;
+  if (light) {
+    int32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      const int32_t r0 = rev_edge[e], r1 = rev_edge[e + 1], r2 = rev_edge[e + 2],
+                    r3 = rev_edge[e + 3];
+      const float v0 = contrib[(int64_t)r0 * C + c], v1 = contrib[(int64_t)r1 * C + c];
+      const float v2 = contrib[(int64_t)r2 * C + c], v3 = contrib[(int64_t)r3 * C + c];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; e < e1; ++e) acc += contrib[(int64_t)rev_edge[e] * C + c];
+  }
+  uint64_t heavy = __ballot(active && !light);
+  while (heavy) {
+    const int src = __builtin_ctzll(heavy);
+    heavy &= heavy - 1;
+    const int32_t h0 = __shfl(e0, src), h1 = __shfl(e1, src), hc = __shfl(c, src);
+    float part = 0.0f;
+    for (int32_t e = h0 + lane; e < h1; e += 64) part += contrib[(int64_t)rev_edge[e] * C + hc];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane == src) acc = part;
+  }
+  return acc;
+}
+
 // Eq. 7 for one level: a gate's output adjoint is its seed plus the
-// contributions its readers left on their fan-in slots (pulled in the fixed
-// fan-out order, so the sum is deterministic); it then leaves
-// lambda * dR/dx_j on each of its own fan-in slots.
+// contributions its readers left on their fan-in slots (pulled in a fixed
+// order, so the sum is deterministic); it then leaves lambda * dR/dx_j on
+// each of its own fan-in slots.  Items are (gate, column) pairs, column
+// innermost; item counts stay below 2^31.
 __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
                                                       int32_t n) {
-  const int64_t idx = gidx();
-  if (idx >= (int64_t)n * a.C) return;
-  const int32_t gl = (int32_t)(idx / a.C);
-  const int32_t c = (int32_t)(idx - (int64_t)gl * a.C);
-  const int32_t b = c / a.cdiv;
-  const int32_t gi = g0 + gl;
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool active = idx < (uint32_t)n * (uint32_t)a.C;
+  const uint32_t gl = active ? idx / (uint32_t)a.C : 0;
+  const int32_t c = active ? (int32_t)(idx - gl * (uint32_t)a.C) : 0;
+  const int32_t gi = g0 + (int32_t)gl;
   const int32_t out = g.n_pi + gi;
-  float lam = a.seed[(int64_t)out * a.C + c];
-  const int32_t e1 = g.rev_ptr[out + 1];
-  for (int32_t e = g.rev_ptr[out]; e < e1; ++e) lam += a.contrib[(int64_t)g.rev_edge[e] * a.C + c];
+  const int32_t e0 = active ? g.rev_ptr[out] : 0;
+  const int32_t e1 = active ? g.rev_ptr[out + 1] : 0;
+  const float pulled = pull_sum(a.contrib, g.rev_edge, e0, e1, a.C, c, active, lane);
+  if (!active) return;
+  const int32_t b = c / a.cdiv;
+  float lam = a.seed[(int64_t)out * a.C + c] + pulled;
   if (a.ste) lam *= a.beta[(int64_t)out * a.B + b];
   const int op = g.op[gi];
   const int k = arity_of(op);
@@ -519,13 +567,16 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, in
 }
 
 __global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
-  const int64_t idx = gidx();
-  if (idx >= (int64_t)g.n_pi * a.C) return;
-  const int32_t i = (int32_t)(idx / a.C);
-  const int32_t c = (int32_t)(idx - (int64_t)i * a.C);
-  float lam = a.seed[idx];
-  const int32_t e1 = g.rev_ptr[i + 1];
-  for (int32_t e = g.rev_ptr[i]; e < e1; ++e) lam += a.contrib[(int64_t)g.rev_edge[e] * a.C + c];
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool active = idx < (uint32_t)g.n_pi * (uint32_t)a.C;
+  const uint32_t i = active ? idx / (uint32_t)a.C : 0;
+  const int32_t c = active ? (int32_t)(idx - i * (uint32_t)a.C) : 0;
+  const int32_t e0 = active ? g.rev_ptr[i] : 0;
+  const int32_t e1 = active ? g.rev_ptr[i + 1] : 0;
+  const float pulled = pull_sum(a.contrib, g.rev_edge, e0, e1, a.C, c, active, lane);
+  if (!active) return;
+  float lam = a.seed[idx] + pulled;
   if (a.ste) lam *= a.beta[(int64_t)i * a.B + c / a.cdiv];
   out[(int64_t)c * g.n_pi + i] = lam;
 }
@@ -629,7 +680,7 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
 hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s) {
   const int64_t n = (int64_t)lv.n * lv.B;
   if (n <= 0) return hipSuccess;
-  if (too_big(n)) return hipErrorInvalidValue;
+  if (n >= (1ll << 31)) return hipErrorInvalidValue;
   k_sp_level<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
   return hipGetLastError();
 }
@@ -669,6 +720,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   int64_t sp_blocks = 0;
   if (sp) {
     spl = *sp;
+    if ((int64_t)spl.n * spl.B >= (1ll << 31)) return hipErrorInvalidValue;
     sp_blocks = blocks_for((int64_t)spl.n * spl.B);
   }
   if (sim_blocks64 + sp_blocks > kMaxBlocks || sim_blocks64 > INT32_MAX) return hipErrorInvalidValue;
@@ -686,7 +738,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
   const int64_t n = (int64_t)a.n_nets * a.B;
   if (n <= 0) return hipSuccess;
-  if (too_big(n)) return hipErrorInvalidValue;
+  if (n >= (1ll << 31)) return hipErrorInvalidValue;
   k_finalize<<<blocks_for(n), kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
@@ -720,7 +772,7 @@ hipError_t launch_seed(const SeedArgs &a, hipStream_t s) {
   const int64_t C = a.per_column ? (int64_t)a.B * Sp : a.B;
   const int64_t n = (int64_t)a.n_nets * C;
   if (n <= 0) return hipSuccess;
-  if (too_big(n)) return hipErrorInvalidValue;
+  if (n >= (1ll << 31)) return hipErrorInvalidValue;
   k_seed<<<blocks_for(n), kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
@@ -729,7 +781,7 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
                             hipStream_t s) {
   const int64_t items = (int64_t)n * a.C;
   if (items <= 0) return hipSuccess;
-  if (too_big(items)) return hipErrorInvalidValue;
+  if (items >= (1ll << 31)) return hipErrorInvalidValue;
   k_bwd_level<<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
   return hipGetLastError();
 }
@@ -737,7 +789,7 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
 hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s) {
   const int64_t items = (int64_t)g.n_pi * a.C;
   if (items <= 0) return hipSuccess;
-  if (too_big(items)) return hipErrorInvalidValue;
+  if (items >= (1ll << 31)) return hipErrorInvalidValue;
   k_bwd_pi<<<blocks_for(items), kBlock, 0, s>>>(g, a, out);
   return hipGetLastError();
 }

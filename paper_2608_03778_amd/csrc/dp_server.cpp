@@ -15,6 +15,7 @@
 // of a sweep is computed independently and reduced in a fixed order.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <condition_variable>
 #include <deque>
@@ -251,6 +252,26 @@ void scheduler(dp_server *s) {
   }
 }
 
+// Scheduler threads still running when the process exits are stopped
+// before the HIP runtime tears down (handlers registered later run first).
+std::mutex g_live_mu;
+std::vector<dp_server *> g_live;
+std::once_flag g_atexit_once;
+
+void stop_thread(dp_server *s) {
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->th.joinable()) s->th.join();
+}
+
+void stop_all_at_exit() {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  for (dp_server *s : g_live) stop_thread(s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -258,10 +279,16 @@ extern "C" {
 dp_status dp_server_create(dp_ctx *ctx, size_t hbm_budget_bytes, dp_server **out) {
   if (!ctx || !out) return fail(DP_E_INVALID, "dp_server_create: NULL argument");
   if (hbm_budget_bytes == 0) return fail(DP_E_INVALID, "dp_server_create: zero budget");
+  std::call_once(g_atexit_once, [] { std::atexit(stop_all_at_exit); });
   auto *s = new dp_server();
   s->ctx = ctx;
+  dp::ctx_retain(ctx);
   s->budget = hbm_budget_bytes;
   s->th = std::thread(scheduler, s);
+  {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    g_live.push_back(s);
+  }
   *out = s;
   return DP_OK;
 }
@@ -288,6 +315,7 @@ dp_status dp_server_add_design(dp_server *s, dp_design *d, const float *cap,
       return fail(DP_E_INVALID, "dp_server_add_design: bad capacitance");
   auto *de = new DesignEntry();
   de->d = d;
+  dp::design_retain(d);
   de->prm = *params;
   de->frozen = params->mode == DP_FROZEN_BETA;
   dp_status st = de->cap_int.alloc((size_t)d->n_nets * 4 + 16);
@@ -303,6 +331,7 @@ dp_status dp_server_add_design(dp_server *s, dp_design *d, const float *cap,
   }
   if (st != DP_OK) {
     delete de;
+    dp::design_release(d);
     return st;
   }
   std::lock_guard<std::mutex> g(s->mu);
@@ -385,14 +414,18 @@ dp_status dp_server_get_stats(dp_server *s, dp_server_stats *out) {
 void dp_server_destroy(dp_server *s) {
   if (!s) return;
   {
-    std::lock_guard<std::mutex> g(s->mu);
-    s->stop = true;
+    std::lock_guard<std::mutex> g(g_live_mu);
+    g_live.erase(std::remove(g_live.begin(), g_live.end(), s), g_live.end());
   }
-  s->cv_work.notify_all();
-  if (s->th.joinable()) s->th.join();
+  stop_thread(s);
   for (Lane *l : s->lanes) destroy_lane(l);
-  for (DesignEntry *de : s->designs) delete de;
+  for (DesignEntry *de : s->designs) {
+    dp_design *d = de->d;
+    delete de;
+    dp::design_release(d);
+  }
   for (auto &kv : s->reqs) delete kv.second;
+  dp::ctx_release(s->ctx);
   delete s;
 }
 

@@ -3,7 +3,6 @@ Each result must equal the oracle and be identical alone and in the mix."""
 from __future__ import annotations
 
 import threading
-import time
 
 import numpy as np
 import pytest
@@ -51,14 +50,14 @@ def test_served_results_match_oracle_and_alone(setup, mode):
     alone = []
     for (i, p, s, bwd) in qs[:12]:
         alone.append(srv.wait(srv.submit(ids[i], p, s, bwd)))
-    # mixed: everything submitted at once from two client threads
+    # mixed: a burst from two client threads, so queries queue behind the
+    # sweeps already on the device and get batched
     tickets = [None] * len(qs)
 
     def client(lo, hi):
         for k in range(lo, hi):
             i, p, s, bwd = qs[k]
             tickets[k] = srv.submit(ids[i], p, s, bwd)
-            time.sleep(0.0002)
     th = [threading.Thread(target=client, args=(0, 30)), threading.Thread(target=client, args=(30, 60))]
     for t in th:
         t.start()

@@ -1,0 +1,77 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: the 117K-gate design with 65,536 vectors and finite differences, the
+1M-gate bench design with 65,536 vectors (every net, counts bit-exact)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_03778_amd import _lib as L
+from paper_2608_03778_amd import api, synth
+from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, say)
+from tests.oracle_parallel import sim_counts
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return api.Context(0)
+
+
+def _full_check(ctx, name, n_sim, seed, fd_samples=0):
+    spec = synth.SPECS[name]
+    nl = synth.random_dag(spec, seed=1)
+    p = synth.pi_probs(nl.n_pi, seed=2)
+    cap = synth.net_caps(nl.n_nets, seed=3)
+    T = n_sim // 64
+    say(f"{name}: GPU hybrid fwd+bwd, {T} words")
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=n_sim, seed=seed)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(("sp", "tr", "tr_acc", "tr_hyb", "ones", "toggles", "power"))
+    g = ev.backward(want=("dpi", "dcap"))
+    say(f"{name}: oracle")
+    o = oracle.Netlist.of(nl)
+    ones, tog = sim_counts(nl, p[0], T, seed)
+    P = o.sp(p[0].astype(np.float64))
+    f = o.power(P, cap, hybrid=True, ones=ones, toggles=tog, n_words=T)
+    adj = o.adjoint(P, f["beta"], cap)
+    np.testing.assert_array_equal(res["ones"][0].astype(np.uint64), ones)
+    np.testing.assert_array_equal(res["toggles"][0].astype(np.uint64), tog)
+    np.testing.assert_allclose(res["sp"][0], P, atol=SP_ABS, rtol=0)
+    np.testing.assert_allclose(res["tr"][0], f["tr_model"], atol=SP_ABS, rtol=0)
+    np.testing.assert_allclose(res["tr_acc"][0], f["tr_acc"], atol=SP_ABS, rtol=0)
+    np.testing.assert_allclose(res["tr_hyb"][0], f["tr_hyb"], atol=SP_ABS, rtol=0)
+    assert_power_close(res["power"], f["power"], f"{name} power")
+    assert_grad_close(g["dpi"][0], adj["dpi"], f"{name} dP/dp")
+    assert_grad_close(g["dcap"], adj["dcap"], f"{name} dP/dC")
+    if fd_samples:
+        # FP64 central differences of the oracle's frozen-beta power, h = 1e-6
+        rng = np.random.default_rng(7)
+        idx = rng.choice(nl.n_pi, fd_samples, replace=False)
+        h = 1e-6
+        p64 = p[0].astype(np.float64)
+        fd = np.zeros(fd_samples)
+        for k, i in enumerate(idx):
+            e = np.zeros_like(p64)
+            e[i] = h
+            fd[k] = (o.frozen_power(p64 + e, f["beta"], cap)
+                     - o.frozen_power(p64 - e, f["beta"], cap)) / (2 * h)
+        rounding = 4 * np.finfo(np.float64).eps * abs(f["power"]) / h
+        err = np.abs(g["dpi"][0][idx] - fd)
+        tol = 1e-4 * np.abs(fd) + 1e-6 * np.abs(adj["dpi"]).max() + rounding
+        assert (err <= tol).all(), f"FD mismatch at {idx[err > tol][:5]}"
+
+
+def test_dag117k_hybrid_fwd_bwd_with_fd():
+    """117,000 gates, 2,048 PIs, depth 60, 65,536 vectors; FD on 200 PIs."""
+    _full_check(api.Context(0), "dag117k", 65536, seed=11, fd_samples=200)
+
+
+def test_dag1m_bench_configuration():
+    """The bench workload: 1M gates, 8,192 PIs, depth 100, 65,536 vectors,
+    default schedule; every net's counts bit-exact."""
+    _full_check(api.Context(0), "dag1m", 65536, seed=1)

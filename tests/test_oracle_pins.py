@@ -417,3 +417,26 @@ def test_stimulus_threshold_boundary():
     assert (int(w[0, 0]) >> lane) & 1 == 0
     w2 = oracle.stimulus(np.array([np.nextafter(p, np.float32(1))]), seed, t0=t, n_words=1)
     assert (int(w2[0, 0]) >> lane) & 1 == 1
+
+
+def test_sim_ranges_add_up():
+    """Counts over disjoint cycle ranges sum to the counts of their union, and
+    the range form agrees with explicit stimulus words."""
+    nl = synth.random_dag(synth.SPECS["dag2k"], 8)
+    o = oracle.Netlist.of(nl)
+    p = synth.pi_probs(nl.n_pi, 8)[0]
+    T = 37
+    ones, tog = o.sim(T, p_pi=p, seed=21)
+    parts = [(0, 1), (1, 10), (10, 11), (11, 37)]
+    so = np.zeros_like(ones)
+    st = np.zeros_like(tog)
+    for a, b in parts:
+        x, y = o.sim_range(a, b, p, seed=21)
+        so += x
+        st += y
+    np.testing.assert_array_equal(so, ones)
+    np.testing.assert_array_equal(st, tog)
+    w = oracle.stimulus(p, 21, 0, T)
+    ones2, tog2 = o.sim(T, pi_words=w)
+    np.testing.assert_array_equal(ones2, ones)
+    np.testing.assert_array_equal(tog2, tog)
