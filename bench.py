@@ -69,6 +69,172 @@ def cpu_baseline(nl, p, cap, n_words_full, sample_words, seed):
                 sim_s_per_word=t_sim / sample_words, grad_norm=float(np.abs(adj["dpi"]).max()))
 
 
+SERVING_DESIGNS = ("dag10k", "dag50k", "dag117k", "dag300k", "dag500k", "dag1m", "dag1500k",
+                   "dag2m")
+
+
+def serving_bench(ctx, rate, warm_s, meas_s, budget, max_batch, max_inflight):
+    """Poisson query stream against 8 device-resident designs (10K..2M
+    gates), half forward and half forward+backward, each query with its own
+    PI probabilities and per-gate size factors; continuous batching against
+    one query at a time on the same arrival trace."""
+    import threading
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    designs, pools = [], []
+    for i, name in enumerate(SERVING_DESIGNS):
+        nl = synth.random_dag(synth.SPECS[name], seed=100 + i)
+        d = api.Design(ctx, nl)
+        cap = synth.net_caps(nl.n_nets, seed=200 + i)
+        # a pool of per-query vectors; every query still carries its own copy
+        ps = synth.pi_probs(nl.n_pi, seed=300 + i, batch=4)
+        ss = synth.cell_sizes(nl.n_gates, seed=400 + i, n_size=4)
+        designs.append((nl, d, cap))
+        pools.append((ps, ss))
+        log(f"[serve] design {name}: {nl.n_gates} gates, depth {d.depth}")
+    rng = np.random.default_rng(7)
+    n = int(rate * (warm_s + meas_s))
+    t_arr = np.cumsum(rng.exponential(1.0 / rate, n))
+    which = rng.integers(0, len(designs), n)
+    bwd = rng.random(n) < 0.5
+    pick = rng.integers(0, 4, n)
+
+    def run(batch, inflight):
+        srv = api.Server(ctx, budget, max_batch=batch, max_inflight=inflight)
+        ids = [srv.add_design(d, cap, mode=L.DP_FROZEN_BETA, n_sim=65536, seed=1)
+               for (_, d, cap) in designs]
+        tickets = [None] * n
+        lat = np.zeros(n)
+        submit_lag = np.zeros(n)
+        done = threading.Event()
+
+        def waiter():
+            for k in range(n):
+                while tickets[k] is None:
+                    time.sleep(0.0001)
+                _, _, l = srv.wait(tickets[k])
+                lat[k] = l + submit_lag[k]
+            done.set()
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for k in range(n):
+            while time.perf_counter() - t0 < t_arr[k]:
+                pass
+            i = int(which[k])
+            ps, ss = pools[i]
+            submit_lag[k] = time.perf_counter() - t0 - t_arr[k]
+            tickets[k] = srv.submit(ids[i], ps[pick[k]], ss[pick[k]], bool(bwd[k]))
+        done.wait()
+        t_end = time.perf_counter() - t0
+        th.join()
+        st = srv.stats()
+        srv.close()
+        m = t_arr >= warm_s
+        return dict(p50_ms=float(np.percentile(lat[m], 50) * 1e3),
+                    p99_ms=float(np.percentile(lat[m], 99) * 1e3),
+                    mean_ms=float(lat[m].mean() * 1e3),
+                    throughput_qps=float(n / t_end), device_steps=int(st["device_steps"]),
+                    queries=n, busy_fraction=float(st["busy_s"] / t_end),
+                    max_inflight=int(st["max_inflight"]),
+                    peak_slot_bytes=int(st["peak_slot_bytes"]),
+                    max_submit_lag_ms=float(submit_lag.max() * 1e3))
+
+    log("[serve] continuous batching")
+    cb = run(max_batch, max_inflight)
+    log(f"[serve] {json.dumps(cb)}")
+    log("[serve] one query at a time")
+    fifo = run(1, 1)
+    log(f"[serve] {json.dumps(fifo)}")
+    return dict(rate_qps=rate, warmup_s=warm_s, measured_s=meas_s, hbm_budget_bytes=budget,
+                designs=[f"{nm}:{nl.n_gates}" for nm, (nl, _, _) in zip(SERVING_DESIGNS, designs)],
+                mode="frozen beta (65,536-vector calibration at p = 0.5 when a design is added)",
+                continuous=cb, one_at_a_time=fifo)
+
+
+def sizing_bench(ctx, reps=3):
+    """Batched sizing sweep on the 117K-gate design: 32 PI-probability vectors
+    U(0.05, 0.95) x 256 cell-size vectors, hybrid with 65,536 vectors; the
+    forward gives power[32][256] and the multi-right-hand-side reverse sweep
+    the 8,192 per-(b, s) gradients dP/dp.  Compared with one query at a time
+    (B = 1, S = 1), whose per-query time is measured and multiplied by 8,192."""
+    import torch
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    nl = synth.random_dag(synth.SPECS["dag117k"], seed=1)
+    d = api.Design(ctx, nl)
+    B, S = 32, 256
+    p = torch.from_numpy(synth.pi_probs(nl.n_pi, seed=5, batch=B, lo=0.05, hi=0.95)).cuda()
+    cap = torch.from_numpy(synth.net_caps(nl.n_nets, seed=6)).cuda()
+    size = torch.from_numpy(synth.cell_sizes(nl.n_gates, seed=7, n_size=S)).cuda()
+    ev = api.Eval(d, B, S, mode=L.DP_HYBRID, n_sim=65536, seed=1)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    ev.set_cell_sizes(size)
+    ev.autotune(2)
+
+    def batched():
+        ev.forward(("power",), device=True)
+        ev.backward_columns(device=True)
+    t_b = time_steps(batched, reps, 1)
+    t_f = time_steps(lambda: ev.forward(("power",), device=True), reps, 1)
+    one = api.Eval(d, 1, 1, mode=L.DP_HYBRID, n_sim=65536, seed=1)
+    one.set_pi_prob(p[:1])
+    one.set_caps(cap)
+    one.set_cell_sizes(size[:1])
+    one.autotune(2)
+
+    def single():
+        one.forward(("power",), device=True)
+        one.backward_columns(device=True)
+    t_1 = time_steps(single, reps, 1)
+    return dict(design="dag117k", columns=B, size_vectors=S, results=B * S, n_sim=65536,
+                batched_fwd_ms=t_f * 1e3, batched_fwdbwd_ms=t_b * 1e3,
+                single_query_fwdbwd_ms=t_1 * 1e3,
+                one_at_a_time_fwdbwd_ms=t_1 * 1e3 * B * S,
+                speedup_vs_one_at_a_time=t_1 * B * S / t_b,
+                schedule=ev.get_schedule())
+
+
+def scale_bench(ctx, reps=3):
+    """Scale test: 2M gates, 16,384 PIs, depth 120, 262,144 vectors (4,096
+    words, chunked); hybrid forward and forward+backward, per-level launches
+    against the captured HIP graph, with the simulation kernel's algorithmic
+    bandwidth."""
+    import torch
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    nl = synth.random_dag(synth.SPECS["dag2m"], seed=1)
+    d = api.Design(ctx, nl)
+    p = torch.from_numpy(synth.pi_probs(nl.n_pi, seed=2)).cuda()
+    cap = torch.from_numpy(synth.net_caps(nl.n_nets, seed=3)).cuda()
+    ev = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=262144, seed=1)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    out = dict(design="dag2m", gates=nl.n_gates, pins=int(nl.stats["pins"]), depth=d.depth,
+               n_sim=262144)
+    for sched, name in ((L.DP_SCHED_LEVEL, "level"), (L.DP_SCHED_GRAPH, "graph")):
+        ev.set_schedule(sched)
+        ev.profile(True)
+        tf = time_steps(lambda: ev.forward(("power",), device=True), reps, 1)
+        prof = ev.get_profile()
+        ev.profile(False)
+        tfb = time_steps(lambda: (ev.forward(("power",), device=True),
+                                  ev.backward(want=("dpi", "dcap"), device=True)), reps, 1)
+        gbs = prof["sim_bytes"] / (prof["sim_ms"] / 1e3) / 1e9 if prof["sim_ms"] else None
+        out[name] = dict(fwd_ms=tf * 1e3, fwdbwd_ms=tfb * 1e3, fwd_gate_evals_s=nl.n_gates / tf,
+                         fwdbwd_gate_evals_s=nl.n_gates / tfb, sim_level_gbs=gbs,
+                         sim_level_hbm_frac=(gbs / HBM_PEAK_GBS) if gbs else None)
+    out["schedule"] = ev.get_schedule()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +249,11 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--pairs-per-lane", type=int, default=0)
     ap.add_argument("--words-per-chunk", type=int, default=0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a 1 GiB device copy (known bytes, "
                          "for scaling FETCH_SIZE/WRITE_SIZE) then the timed steps only")
@@ -121,13 +292,19 @@ def main():
             dst.copy_(src)  # 1 GiB read + 1 GiB written per dispatch
         _sync()
         log("[bench] calibration copies done (1 GiB each)")
-        args.no_cpu = args.no_forms = True
+        args.no_cpu = args.no_forms = args.no_serving = True
 
     # --- headline: hybrid fwd+bwd, one query column
     ev = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=args.n_sim, seed=1)
-    ev.set_schedule(args.schedule, args.words_per_chunk, args.pairs_per_lane)
     ev.set_pi_prob(p_dev)
     ev.set_caps(cap_dev)
+    tuned_ms = None
+    if args.schedule or args.words_per_chunk or args.pairs_per_lane:
+        ev.set_schedule(args.schedule, args.words_per_chunk, args.pairs_per_lane)
+    else:
+        tuned_ms = ev.autotune(3)
+    schedule = ev.get_schedule()
+    log(f"[bench] schedule {schedule} (autotuned forward {tuned_ms} ms)")
 
     def step():
         ev.forward(("power",), device=True)
@@ -185,8 +362,15 @@ def main():
         forms["hybrid_b1"] = dict(fwd_ms=fwd_only * 1e3, fwdbwd_ms=dt * 1e3,
                                   fwd_gate_evals_s=G / fwd_only, fwdbwd_gate_evals_s=G / dt,
                                   sim_gate_word_evals_s=G * T / fwd_only)
+        forms["sizing_sweep"] = sizing_bench(ctx)
+        forms["scale_2m"] = scale_bench(ctx)
         for k, v in forms.items():
             log(f"[bench] {k}: {json.dumps(v)}")
+
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(ctx, args.serve_rate, args.serve_warmup, args.serve_seconds,
+                                int(args.serve_budget_gb * (1 << 30)), 64, 8)
 
     cpu = None
     if not args.no_cpu:
@@ -218,7 +402,7 @@ def main():
                          f"{d.depth}; hybrid fwd+bwd of one query with {args.n_sim} simulated "
                          f"vectors ({T} words)"),
             "gates": G, "pis": nl.n_pi, "depth": d.depth, "n_sim": args.n_sim,
-            "query_columns": 1, "parallelism": "single GPU",
+            "query_columns": 1, "parallelism": "single GPU", "schedule": schedule,
         },
         "roofline": {
             "kernel": "k_sim_level (bit-packed simulation level, fused SP)",
@@ -234,6 +418,9 @@ def main():
         },
         "cpu_baseline": cpu,
         "forms": forms,
+        "serving": serving,
+        "p50_ms": serving["continuous"]["p50_ms"] if serving else None,
+        "p99_ms": serving["continuous"]["p99_ms"] if serving else None,
         "compile_s": compile_s,
     }
     print(json.dumps(res), flush=True)

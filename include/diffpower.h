@@ -240,6 +240,18 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule,
                                int64_t words_per_chunk,
                                int32_t sim_pairs_per_lane);
 
+/* Autotuner: time the forward sweep (one warm-up and `reps` timed runs
+ * with HIP events on the context's stream) for every schedule candidate --
+ * per-level launches or a captured HIP graph, 1/2/4/8 word pairs per lane,
+ * the whole run or 2 or 4 word chunks -- and keep the fastest.  Needs the
+ * inputs set; overwrites the eval's forward results.  best_ms (may be NULL)
+ * receives the winner's time per forward. */
+dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms);
+/* The schedule in force (as set or as chosen by the autotuner). */
+dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule,
+                               int64_t *words_per_chunk,
+                               int32_t *sim_pairs_per_lane);
+
 /* Kernel timing of the last forward/backward, accumulated with HIP events
  * on the context's stream while profiling is enabled. */
 typedef struct {
@@ -288,7 +300,9 @@ dp_status dp_server_add_design(dp_server *srv, dp_design *design,
                                const float *cap, const dp_params *params,
                                int32_t *design_id);
 /* Enqueue a query; returns at once.  DP_E_BUDGET if the query alone can
- * never fit the budget. */
+ * never fit the budget, DP_E_INVALID for a probability outside [0, 1].
+ * cap_scale is checked when the query is staged for the device; a bad entry
+ * makes dp_wait return DP_E_INVALID for that query. */
 dp_status dp_submit(dp_server *srv, const dp_query *q, uint64_t *ticket);
 dp_status dp_poll(dp_server *srv, uint64_t ticket, int32_t *done);
 /* Block until the ticket is done; latency_s = completion - submission. */

@@ -230,6 +230,18 @@ class Eval:
         check(self.lib.dp_backward_columns(self.handle, ptr, int(bool(device))))
         return arr
 
+    def autotune(self, reps: int = 3) -> float:
+        """Pick the fastest forward schedule; returns its ms per forward."""
+        ms = ctypes.c_double()
+        check(self.lib.dp_eval_autotune(self.handle, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def get_schedule(self) -> dict:
+        sc, ch, pp = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        check(self.lib.dp_eval_get_schedule(self.handle, ctypes.byref(sc), ctypes.byref(ch),
+                                            ctypes.byref(pp)))
+        return dict(schedule=sc.value, words_per_chunk=ch.value, pairs_per_lane=pp.value)
+
     def profile(self, enable: bool = True):
         check(self.lib.dp_eval_profile(self.handle, int(bool(enable))))
 
@@ -301,8 +313,11 @@ class Server:
     def wait(self, ticket: int):
         """Block until done; returns (power, dP/dp or None, latency seconds)."""
         lat = ctypes.c_double()
-        check(self.lib.dp_wait(self.handle, ctypes.c_uint64(ticket), ctypes.byref(lat)))
-        _, _, power, dpi = self._live.pop(ticket)
+        try:
+            check(self.lib.dp_wait(self.handle, ctypes.c_uint64(ticket), ctypes.byref(lat)))
+        finally:
+            live = self._live.pop(ticket, None)
+        _, _, power, dpi = live
         return float(power[0]), dpi, lat.value
 
     def stats(self) -> dict:

@@ -229,7 +229,9 @@ dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
   DP_TRY(ev->xterm.alloc(nb * sizeof(float)));
   DP_TRY(ev->seed_base.alloc(nb * sizeof(float)));
   const int32_t cols = ev->B * s_prime(ev);
-  DP_TRY(ev->power_partial.alloc((size_t)dp::power_chunks(d->n_nets) * cols * sizeof(double)));
+  DP_TRY(ev->power_partial.alloc(
+      (size_t)dp::power_partial_doubles(d->n_nets, ev->B, ev->S, ev->paired_sizes) *
+      sizeof(double)));
   DP_TRY(ev->power.alloc((size_t)cols * sizeof(float)));
   if (pl) {
     DP_TRY(ev->ones.alloc(nb * sizeof(uint32_t)));
@@ -661,6 +663,72 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_
   ev->schedule = schedule;
   ev->words_per_chunk = words_per_chunk;
   ev->sim_iters = sim_pairs_per_lane;
+  return DP_OK;
+}
+
+dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_autotune: NULL eval");
+  if (reps < 1) reps = 1;
+  const int32_t s0 = ev->schedule, i0 = ev->sim_iters;
+  const int64_t c0 = ev->words_per_chunk;
+  const bool prof = ev->profiling;
+  ev->profiling = false;
+  struct Cand { int32_t sched; int32_t iters; int64_t chunk; };
+  std::vector<Cand> cands;
+  const int64_t T = n_words(ev->prm);
+  if (hybrid(ev)) {
+    const int64_t chunks[3] = {0, (T / 2 + 1) & ~1ll, (T / 4 + 1) & ~1ll};
+    for (int k = 0; k < 3; ++k) {
+      if (k > 0 && chunks[k] < 128) continue;
+      for (int32_t it : {1, 2, 4, 8})
+        for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, it, chunks[k]});
+    }
+  } else {
+    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, 0, 0});
+  }
+  hipStream_t s = ev->stream();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DP_HIP_TRY(hipEventCreate(&e0));
+  DP_HIP_TRY(hipEventCreate(&e1));
+  double best = 1e300;
+  Cand win{s0, i0, c0};
+  dp_status st = DP_OK;
+  for (const Cand &c : cands) {
+    ev->schedule = c.sched;
+    ev->sim_iters = c.iters;
+    ev->words_per_chunk = c.chunk;
+    if ((st = dp_forward(ev, nullptr)) != DP_OK) break;  // warm-up, graph capture
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(DP_E_HIP, "autotune: event"); break; }
+    for (int32_t r = 0; r < reps && st == DP_OK; ++r) st = dp_forward(ev, nullptr);
+    if (st != DP_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(DP_E_HIP, "autotune: event timing failed");
+      break;
+    }
+    if (ms / reps < best) {
+      best = ms / reps;
+      win = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ev->profiling = prof;
+  ev->schedule = win.sched;
+  ev->sim_iters = win.iters;
+  ev->words_per_chunk = win.chunk;
+  if (st != DP_OK) return st;
+  if (best_ms) *best_ms = best;
+  return DP_OK;
+}
+
+dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule, int64_t *words_per_chunk,
+                               int32_t *sim_pairs_per_lane) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_get_schedule: NULL eval");
+  if (schedule) *schedule = ev->schedule;
+  if (words_per_chunk) *words_per_chunk = ev->words_per_chunk;
+  if (sim_pairs_per_lane) *sim_pairs_per_lane = ev->sim_iters;
   return DP_OK;
 }
 

@@ -121,6 +121,8 @@ struct PowerArgs {
   float *power;                     // [B][S'] (device)
 };
 int32_t power_chunks(int32_t n_nets);
+// Doubles of partial-sum scratch launch_power needs.
+int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t paired);
 hipError_t launch_power(const PowerArgs &a, hipStream_t s);
 
 // Reverse sweep.  Columns c in [0, C); the SP column of c is c / cdiv.

@@ -12,6 +12,8 @@
 // (gate, run of word pairs): the wave's cell is uniform, so the cell switch
 // is a scalar branch outside the word loop; each lane moves 16-byte word
 // pairs, so every fan-in row is read as contiguous 1 KiB wave-wide accesses.
+#include <algorithm>
+
 #include "dp_kernels.h"
 
 namespace dp {
@@ -447,6 +449,65 @@ __global__ __launch_bounds__(kBlock) void k_power_partial(PowerArgs a) {
   if (threadIdx.x == 0) a.partial[(int64_t)chunk * n_cols + col] = r;
 }
 
+// Many size vectors (S > 0, not paired): P[b][s] = sum_n X[n][b] Y[n][s]
+// with X = xterm and Y[n][s] = C_n s_s(drv n) is a small dense product
+// (B x N) (N x S).  A block owns a 32 x 64 (b, s) tile and one slab of nets;
+// X and Y slabs are staged through LDS and each thread accumulates 8 outputs
+// in double.  Partials [slab][b][s] are summed over slabs in a fixed order.
+constexpr int32_t kTileB = 32, kTileS = 64, kSlabNets = 2048, kStage = 64;
+
+__global__ __launch_bounds__(kBlock) void k_power_tiled(PowerArgs a, int32_t n_slabs) {
+  __shared__ float xs[kStage][kTileB];
+  __shared__ float ys[kStage][kTileS + 1];
+  const int32_t tiles_s = (a.S + kTileS - 1) / kTileS;
+  const int32_t tile = blockIdx.x % tiles_s;
+  const int32_t rest = blockIdx.x / tiles_s;
+  const int32_t tiles_b = (a.B + kTileB - 1) / kTileB;
+  const int32_t tb = rest % tiles_b;
+  const int32_t slab = rest / tiles_b;
+  const int32_t b0 = tb * kTileB, s0 = tile * kTileS;
+  const int32_t n_lo = slab * kSlabNets, n_hi = min(n_lo + kSlabNets, a.n_nets);
+  const int tid = threadIdx.x;
+  const int bl = tid % kTileB;          // this thread's b
+  const int sg = tid / kTileB;          // 8 groups of 8 s values
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  for (int32_t base = n_lo; base < n_hi; base += kStage) {
+    // stage X[n][b0..b0+31] and Y[n][s0..s0+63] for kStage nets
+    for (int e = tid; e < kStage * kTileB; e += kBlock) {
+      const int r = e / kTileB, cb = e % kTileB;
+      const int32_t n = base + r, b = b0 + cb;
+      xs[r][cb] = (n < n_hi && b < a.B) ? a.xterm[(int64_t)n * a.B + b] : 0.0f;
+    }
+    for (int e = tid; e < kStage * kTileS; e += kBlock) {
+      const int cs = e / kStage, r = e % kStage;  // consecutive lanes walk nets
+      const int32_t n = base + r, s = s0 + cs;
+      float y = 0.0f;
+      if (n < n_hi && s < a.S) {
+        const float sz = n >= a.n_pi ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
+        y = a.cap[n] * sz;
+      }
+      ys[r][cs] = y;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = 0; r < kStage; ++r) {
+      const double x = (double)xs[r][bl];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = fma(x, (double)ys[r][sg * 8 + j], acc[j]);
+    }
+    __syncthreads();
+  }
+  const int32_t b = b0 + bl;
+  if (b < a.B)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int32_t s = s0 + sg * 8 + j;
+      if (s < a.S) a.partial[((int64_t)slab * a.B + b) * a.S + s] = acc[j];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_cols) {
   const int64_t col = gidx();
   if (col >= n_cols) return;
@@ -755,9 +816,29 @@ int32_t power_chunks(int32_t n_nets) {
   return n_nets <= 0 ? 1 : (n_nets + kPowerChunk - 1) / kPowerChunk;
 }
 
+int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t paired) {
+  const int64_t cols = (int64_t)B * ((S > 0 && !paired) ? S : 1);
+  int64_t slabs = power_chunks(n_nets);
+  if (S > 0 && !paired) slabs = std::max<int64_t>(slabs, (n_nets + kSlabNets - 1) / kSlabNets);
+  return (int32_t)(slabs * cols);
+}
+
 hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
   const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const int32_t n_cols = a.B * Sp;
+  if (a.S > 0 && !a.paired && a.size) {
+    const int32_t n_slabs = (a.n_nets + kSlabNets - 1) / kSlabNets;
+    const int64_t blocks = (int64_t)n_slabs * ((a.B + kTileB - 1) / kTileB) *
+                           ((a.S + kTileS - 1) / kTileS);
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    k_power_tiled<<<(unsigned)blocks, kBlock, 0, s>>>(a, n_slabs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PowerArgs f = a;
+    f.n_chunks = n_slabs;
+    k_power_final<<<blocks_for(n_cols), kBlock, 0, s>>>(f, n_cols);
+    return hipGetLastError();
+  }
   const int64_t blocks = (int64_t)a.n_chunks * n_cols;
   if (blocks > kMaxBlocks) return hipErrorInvalidValue;
   k_power_partial<<<(unsigned)blocks, kBlock, 0, s>>>(a);

@@ -38,6 +38,7 @@ struct Request {
   float *out_power = nullptr, *out_dpi = nullptr;
   Clock::time_point t_submit, t_done;
   bool done = false;
+  dp_status status = DP_OK;
 };
 
 struct DesignEntry {
@@ -149,10 +150,22 @@ void launch_lane(dp_server *s, Lane *l) {
   if (any_size)
     for (int32_t b = 0; b < n; ++b) {
       float *dst = l->pin_size + (size_t)b * d->n_gates;
-      if (l->batch[b]->size)
-        std::memcpy(dst, l->batch[b]->size, (size_t)d->n_gates * 4);
-      else
+      const float *src = l->batch[b]->size;
+      if (!src) {
         std::fill(dst, dst + d->n_gates, 1.0f);
+        continue;
+      }
+      // copy and validate in one pass (kept off the submitting thread)
+      bool ok = true;
+      for (int32_t g = 0; g < d->n_gates; ++g) {
+        const float v = src[g];
+        ok &= (v >= 0.0f) & (v <= 3.0e38f);
+        dst[g] = v;
+      }
+      if (!ok) {
+        l->batch[b]->status = DP_E_INVALID;
+        std::fill(dst, dst + d->n_gates, 1.0f);
+      }
     }
   const bool bwd = l->batch[0]->kind == DP_Q_FWD_BWD;
   dp_status rc = dp::lane_run(l->ev, n, l->pin_p, any_size ? l->pin_size : nullptr, bwd,
@@ -356,10 +369,6 @@ dp_status dp_submit(dp_server *s, const dp_query *q, uint64_t *ticket) {
   for (int32_t i = 0; i < d->n_pi; ++i)
     if (!(q->pi_prob[i] >= 0.0f && q->pi_prob[i] <= 1.0f))
       return fail(DP_E_INVALID, "dp_submit: PI probability NaN or outside [0, 1]");
-  if (q->cap_scale)
-    for (int32_t g = 0; g < d->n_gates; ++g)
-      if (!(q->cap_scale[g] >= 0.0f && q->cap_scale[g] <= 3.0e38f))
-        return fail(DP_E_INVALID, "dp_submit: bad cap_scale");
   auto *r = new Request();
   r->design = q->design_id;
   r->kind = q->kind;
@@ -397,8 +406,10 @@ dp_status dp_wait(dp_server *s, uint64_t ticket, double *latency_s) {
   s->cv_done.wait(lk, [&] { return r->done || !s->thread_error.empty(); });
   if (!r->done) return fail(DP_E_HIP, "server: " + s->thread_error);
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  const dp_status st = r->status;
   s->reqs.erase(it);
   delete r;
+  if (st != DP_OK) return fail(st, "dp_wait: the query's cap_scale had a NaN or negative entry");
   return DP_OK;
 }
 

@@ -330,3 +330,22 @@ def test_heavy_fanout_reverse_sweep(ctx, B):
         ev1.set_pi_prob(p[b:b + 1])
         ev1.forward()
         np.testing.assert_array_equal(ev1.backward()["dpi"][0], g[b])
+
+
+def test_autotune_keeps_results(ctx):
+    """The autotuner picks among schedules that give identical results."""
+    say("autotune")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 13)
+    p, cap, _ = _inputs(nl, 13)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 512, seed=8)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    a = ev.forward(("sp", "ones", "toggles", "power"))
+    ms = ev.autotune(2)
+    sch = ev.get_schedule()
+    assert ms > 0 and sch["schedule"] in (L.DP_SCHED_LEVEL, L.DP_SCHED_GRAPH)
+    assert sch["pairs_per_lane"] in (1, 2, 4, 8)
+    b = ev.forward(("sp", "ones", "toggles", "power"))
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])

@@ -107,4 +107,11 @@ def test_budget_rejection_and_errors(setup):
     did = srv.add_design(designs[0], caps[0])
     with pytest.raises(L.DiffPowerError, match="INVALID"):
         srv.submit(did, np.full(nls[0].n_pi, 2.0, np.float32))
+    bad = np.ones(nls[0].n_gates, np.float32)
+    bad[7] = np.nan
+    t_bad = srv.submit(did, np.full(nls[0].n_pi, 0.5, np.float32), bad)
+    t_ok = srv.submit(did, np.full(nls[0].n_pi, 0.5, np.float32))
+    with pytest.raises(L.DiffPowerError, match="INVALID"):
+        srv.wait(t_bad)
+    assert srv.wait(t_ok)[0] > 0
     srv.close()

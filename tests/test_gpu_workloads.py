@@ -75,3 +75,40 @@ def test_dag1m_bench_configuration():
     """The bench workload: 1M gates, 8,192 PIs, depth 100, 65,536 vectors,
     default schedule; every net's counts bit-exact."""
     _full_check(api.Context(0), "dag1m", 65536, seed=1)
+
+
+def test_dag117k_sizing_sweep_spot_parity():
+    """32 PI vectors x 256 size vectors on the 117K-gate design, hybrid with
+    65,536 vectors: power[b][s] and the per-(b, s) gradients of 64 random
+    (b, s) pairs against the oracle."""
+    ctx = api.Context(0)
+    nl = synth.random_dag(synth.SPECS["dag117k"], seed=1)
+    B, S, T = 32, 256, 1024
+    p = synth.pi_probs(nl.n_pi, seed=5, batch=B, lo=0.05, hi=0.95)
+    cap = synth.net_caps(nl.n_nets, seed=6)
+    size = synth.cell_sizes(nl.n_gates, seed=7, n_size=S)
+    say("sizing sweep: GPU")
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, B, S, mode=L.DP_HYBRID, n_sim=64 * T, seed=1)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    ev.set_cell_sizes(size)
+    power = ev.forward(("power",))["power"]
+    cols = ev.backward_columns()
+    o = oracle.Netlist.of(nl)
+    rng = np.random.default_rng(3)
+    for b in rng.choice(B, 4, replace=False):
+        say(f"sizing sweep: oracle column {b}")
+        ones, tog = sim_counts(nl, p[b], T, 1)
+        P = o.sp(p[b].astype(np.float64))
+        for s_ in rng.choice(S, 16, replace=False):
+            f = o.power(P, cap, size[s_], hybrid=True, ones=ones, toggles=tog, n_words=T)
+            adj = o.adjoint(P, f["beta"], cap, size[s_])
+            assert_power_close(power[b, s_], f["power"], f"power[{b},{s_}]")
+            assert_grad_close(cols[b, s_], adj["dpi"], f"dP/dp[{b},{s_}]")
+
+
+def test_dag2m_scale_chunked():
+    """2M gates, 16,384 PIs, depth 120, 262,144 vectors in word chunks: every
+    net's counts bit-exact, SP/TR, power and gradients."""
+    _full_check(api.Context(0), "dag2m", 262144, seed=1)
