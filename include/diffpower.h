@@ -243,14 +243,20 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule,
 /* Autotuner: time the forward sweep (one warm-up and `reps` timed runs
  * with HIP events on the context's stream) for every schedule candidate --
  * per-level launches or a captured HIP graph, 1/2/4/8 word pairs per lane,
- * the whole run or 2 or 4 word chunks -- and keep the fastest.  Needs the
+ * the whole run or 2 or 4 word chunks, 1/2/4 simulation streams -- and keep
+ * the fastest.  Needs the
  * inputs set; overwrites the eval's forward results.  best_ms (may be NULL)
  * receives the winner's time per forward. */
 dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms);
+/* Number of streams that simulate independent (query column, word chunk)
+ * pieces concurrently, each with its own word buffer (0 = automatic = 1).
+ * Counts are integer sums, so results do not depend on it. */
+dp_status dp_eval_set_sim_streams(dp_eval *ev, int32_t sim_streams);
 /* The schedule in force (as set or as chosen by the autotuner). */
 dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule,
                                int64_t *words_per_chunk,
-                               int32_t *sim_pairs_per_lane);
+                               int32_t *sim_pairs_per_lane,
+                               int32_t *sim_streams);
 
 /* Kernel timing of the last forward/backward, accumulated with HIP events
  * on the context's stream while profiling is enabled. */

@@ -236,11 +236,15 @@ class Eval:
         check(self.lib.dp_eval_autotune(self.handle, int(reps), ctypes.byref(ms)))
         return ms.value
 
+    def set_sim_streams(self, n: int):
+        check(self.lib.dp_eval_set_sim_streams(self.handle, int(n)))
+
     def get_schedule(self) -> dict:
-        sc, ch, pp = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        sc, ch, pp, ns = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         check(self.lib.dp_eval_get_schedule(self.handle, ctypes.byref(sc), ctypes.byref(ch),
-                                            ctypes.byref(pp)))
-        return dict(schedule=sc.value, words_per_chunk=ch.value, pairs_per_lane=pp.value)
+                                            ctypes.byref(pp), ctypes.byref(ns)))
+        return dict(schedule=sc.value, words_per_chunk=ch.value, pairs_per_lane=pp.value,
+                    sim_streams=ns.value)
 
     def profile(self, enable: bool = True):
         check(self.lib.dp_eval_profile(self.handle, int(bool(enable))))

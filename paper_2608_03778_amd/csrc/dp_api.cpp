@@ -42,7 +42,7 @@ using dp::fail;
 
 namespace {
 
-constexpr int64_t kAutoWordBudget = 24ll << 30;  // bytes of simulation words per chunk
+constexpr int64_t kAutoWordBudget = 32ll << 30;  // bytes of simulation words in flight
 const char *kVersion = "diffpower-mi355x 0.1 (gfx950)";
 enum { SPAN_SIM = 0, SPAN_SP = 1, SPAN_BWD = 2, SPAN_STIM = 3 };
 
@@ -129,13 +129,16 @@ struct SpanGuard {
   double bytes;
   bool on;
   int64_t launches;
-  SpanGuard(dp_eval *e, int k, double b, bool enabled, int64_t n_launch)
-      : ev(e), kind(k), bytes(b), on(enabled), launches(n_launch) {
+  hipStream_t st;
+  SpanGuard(dp_eval *e, int k, double b, bool enabled, int64_t n_launch,
+            hipStream_t stream = nullptr)
+      : ev(e), kind(k), bytes(b), on(enabled), launches(n_launch),
+        st(stream ? stream : e->stream()) {
     if (on) {
       a = ev->ev_used;
       hipEvent_t x = take_event(ev);
       if (!x) { on = false; return; }
-      (void)hipEventRecord(x, ev->stream());
+      (void)hipEventRecord(x, st);
     }
   }
   ~SpanGuard() {
@@ -143,7 +146,7 @@ struct SpanGuard {
     size_t b = ev->ev_used;
     hipEvent_t x = take_event(ev);
     if (!x) return;
-    (void)hipEventRecord(x, ev->stream());
+    (void)hipEventRecord(x, st);
     ev->spans.push_back({a, b, kind, bytes, launches});
   }
 };
@@ -175,11 +178,14 @@ struct ChunkPlan {
   int32_t halo = 0, n_chunks = 0;
 };
 
+int32_t n_sim_streams(const dp_eval *ev) { return ev->sim_streams > 0 ? ev->sim_streams : 1; }
+
 ChunkPlan plan_chunks(const dp_eval *ev) {
   ChunkPlan c;
   c.T = n_words(ev->prm);
   int64_t want = ev->words_per_chunk;
-  const int64_t row_budget = std::max<int64_t>(kAutoWordBudget / (8 * (int64_t)ev->d->n_nets), 4);
+  const int64_t row_budget = std::max<int64_t>(
+      kAutoWordBudget / (8 * (int64_t)ev->d->n_nets * n_sim_streams(ev)), 4);
   if (want <= 0) want = c.T <= row_budget ? c.T : row_budget - 2;
   want = std::max<int64_t>(2, want + (want & 1));
   if (want >= c.T) {
@@ -195,9 +201,9 @@ ChunkPlan plan_chunks(const dp_eval *ev) {
   return c;
 }
 
-dp::ChunkView chunk_view(const dp_eval *ev, const ChunkPlan &pl, int32_t k) {
+dp::ChunkView chunk_view(const dp_eval *ev, const ChunkPlan &pl, int32_t k, int32_t lane) {
   dp::ChunkView v;
-  v.W = ev->words.as<uint64_t>();
+  v.W = ev->words.as<uint64_t>() + (size_t)lane * ev->d->n_nets * pl.pitch;
   v.pitch = pl.pitch;
   const int64_t t0 = (int64_t)k * pl.Tc;
   const int64_t nw = std::min<int64_t>(pl.Tc, pl.T - t0);
@@ -236,7 +242,18 @@ dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
   if (pl) {
     DP_TRY(ev->ones.alloc(nb * sizeof(uint32_t)));
     DP_TRY(ev->tog.alloc(nb * sizeof(uint32_t)));
-    DP_TRY(ev->words.alloc((size_t)d->n_nets * pl->pitch * sizeof(uint64_t)));
+    const int32_t L = n_sim_streams(ev);
+    DP_TRY(ev->words.alloc((size_t)L * d->n_nets * pl->pitch * sizeof(uint64_t)));
+    while ((int32_t)ev->lane_streams.size() < L - 1) {
+      hipStream_t st = nullptr;
+      DP_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      ev->lane_streams.push_back(st);
+    }
+    while ((int32_t)ev->lane_events.size() < L) {
+      hipEvent_t e = nullptr;
+      DP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ev->lane_events.push_back(e);
+    }
   }
   return DP_OK;
 }
@@ -286,29 +303,43 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
     DP_HIP_TRY(dp::launch_fill_u32(ev->ones.as<uint32_t>(), (int64_t)nb, 0u, s));
     DP_HIP_TRY(dp::launch_fill_u32(ev->tog.as<uint32_t>(), (int64_t)nb, 0u, s));
     dp::SimTune tune{pick_iters(ev, *pl)};
-    for (int32_t b = 0; b < ev->B; ++b) {
+    // (column, chunk) pieces are independent: piece j runs on stream j % L
+    // with its own word buffer; the SP of each level is fused into piece 0.
+    const int32_t n_pieces = ev->B * pl->n_chunks;
+    const int32_t L = std::min<int32_t>(n_sim_streams(ev), n_pieces);
+    if (L > 1) {
+      DP_HIP_TRY(hipEventRecord(ev->lane_events[0], s));
+      for (int32_t i = 1; i < L; ++i)
+        DP_HIP_TRY(hipStreamWaitEvent(ev->lane_streams[i - 1], ev->lane_events[0], 0));
+    }
+    for (int32_t j = 0; j < n_pieces; ++j) {
+      const int32_t b = j / pl->n_chunks, k = j % pl->n_chunks, lane = j % L;
+      hipStream_t ls = lane == 0 ? s : ev->lane_streams[lane - 1];
       dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), ev->B, b};
       const uint64_t *stim =
           ev->have_stim ? ev->stim.as<uint64_t>() + (size_t)b * d->n_pi * pl->T : nullptr;
-      for (int32_t k = 0; k < pl->n_chunks; ++k) {
-        const dp::ChunkView cv = chunk_view(ev, *pl, k);
-        {
-          SpanGuard sg(ev, SPAN_STIM, 0.0, prof, 1);
-          DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, ev->prm.seed, tune, s));
-        }
-        const bool fuse = (b == 0 && k == 0);
-        const int64_t nw = cv.u_hi - cv.u_lo;
-        double bytes = 0.0;
-        for (int32_t l = 1; l <= d->depth; ++l) bytes += sim_level_bytes(d, l, nw, ev->B, fuse);
-        // one span over the chunk's level launches (their back-to-back time)
-        SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth);
-        for (int32_t l = 1; l <= d->depth; ++l) {
-          const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-          dp::SpLevel lv{sp, ev->B, g0, n};
-          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, tune, s));
-        }
+      const dp::ChunkView cv = chunk_view(ev, *pl, k, lane);
+      {
+        SpanGuard sg(ev, SPAN_STIM, 0.0, prof, 1, ls);
+        DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, ev->prm.seed, tune, ls));
+      }
+      const bool fuse = (j == 0);
+      const int64_t nw = cv.u_hi - cv.u_lo;
+      double bytes = 0.0;
+      for (int32_t l = 1; l <= d->depth; ++l) bytes += sim_level_bytes(d, l, nw, ev->B, fuse);
+      // one span over the piece's level launches (their back-to-back time)
+      SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth, ls);
+      for (int32_t l = 1; l <= d->depth; ++l) {
+        const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+        dp::SpLevel lv{sp, ev->B, g0, n};
+        DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, tune, ls));
       }
     }
+    if (L > 1)
+      for (int32_t i = 1; i < L; ++i) {
+        DP_HIP_TRY(hipEventRecord(ev->lane_events[i], ev->lane_streams[i - 1]));
+        DP_HIP_TRY(hipStreamWaitEvent(s, ev->lane_events[i], 0));
+      }
   }
   dp::FinalizeArgs fa{};
   fa.sp = sp;
@@ -424,6 +455,7 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
   if (pl) {
     mix((uint64_t)pl->Tc);
     mix((uint64_t)pick_iters(ev, *pl));
+    mix((uint64_t)n_sim_streams(ev));
   }
   return k;
 }
@@ -433,6 +465,11 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
 dp_eval::~dp_eval() {
   if (graph_fwd) (void)hipGraphExecDestroy(graph_fwd);
   for (auto e : ev_pool) (void)hipEventDestroy(e);
+  for (auto st : lane_streams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (auto e : lane_events) (void)hipEventDestroy(e);
 }
 
 // =========================================================================
@@ -669,34 +706,42 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_
 dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms) {
   if (!ev) return fail(DP_E_INVALID, "dp_eval_autotune: NULL eval");
   if (reps < 1) reps = 1;
-  const int32_t s0 = ev->schedule, i0 = ev->sim_iters;
+  const int32_t s0 = ev->schedule, i0 = ev->sim_iters, l0 = ev->sim_streams;
   const int64_t c0 = ev->words_per_chunk;
   const bool prof = ev->profiling;
   ev->profiling = false;
-  struct Cand { int32_t sched; int32_t iters; int64_t chunk; };
+  struct Cand { int32_t sched; int32_t iters; int64_t chunk; int32_t lanes; };
   std::vector<Cand> cands;
   const int64_t T = n_words(ev->prm);
   if (hybrid(ev)) {
     const int64_t chunks[3] = {0, (T / 2 + 1) & ~1ll, (T / 4 + 1) & ~1ll};
     for (int k = 0; k < 3; ++k) {
       if (k > 0 && chunks[k] < 128) continue;
-      for (int32_t it : {1, 2, 4, 8})
-        for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, it, chunks[k]});
+      const int64_t pieces = (int64_t)ev->B * (k == 0 ? 1 : (T + chunks[k] - 1) / chunks[k]);
+      for (int32_t lanes : {1, 2, 4}) {
+        if (lanes > 1 && lanes > pieces) continue;
+        if ((int64_t)lanes * ev->d->n_nets * 8 * (k == 0 ? T : chunks[k] + 2) > kAutoWordBudget)
+          continue;
+        for (int32_t it : {1, 2, 4, 8})
+          for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH})
+            cands.push_back({sc, it, chunks[k], lanes});
+      }
     }
   } else {
-    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, 0, 0});
+    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, 0, 0, 1});
   }
   hipStream_t s = ev->stream();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   DP_HIP_TRY(hipEventCreate(&e0));
   DP_HIP_TRY(hipEventCreate(&e1));
   double best = 1e300;
-  Cand win{s0, i0, c0};
+  Cand win{s0, i0, c0, l0};
   dp_status st = DP_OK;
   for (const Cand &c : cands) {
     ev->schedule = c.sched;
     ev->sim_iters = c.iters;
     ev->words_per_chunk = c.chunk;
+    ev->sim_streams = c.lanes;
     if ((st = dp_forward(ev, nullptr)) != DP_OK) break;  // warm-up, graph capture
     if (hipEventRecord(e0, s) != hipSuccess) { st = fail(DP_E_HIP, "autotune: event"); break; }
     for (int32_t r = 0; r < reps && st == DP_OK; ++r) st = dp_forward(ev, nullptr);
@@ -718,17 +763,27 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms) {
   ev->schedule = win.sched;
   ev->sim_iters = win.iters;
   ev->words_per_chunk = win.chunk;
+  ev->sim_streams = win.lanes;
   if (st != DP_OK) return st;
   if (best_ms) *best_ms = best;
   return DP_OK;
 }
 
+dp_status dp_eval_set_sim_streams(dp_eval *ev, int32_t sim_streams) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_set_sim_streams: NULL eval");
+  if (sim_streams < 0 || sim_streams > 16)
+    return fail(DP_E_INVALID, "dp_eval_set_sim_streams: need 0 <= sim_streams <= 16");
+  ev->sim_streams = sim_streams;
+  return DP_OK;
+}
+
 dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule, int64_t *words_per_chunk,
-                               int32_t *sim_pairs_per_lane) {
+                               int32_t *sim_pairs_per_lane, int32_t *sim_streams) {
   if (!ev) return fail(DP_E_INVALID, "dp_eval_get_schedule: NULL eval");
   if (schedule) *schedule = ev->schedule;
   if (words_per_chunk) *words_per_chunk = ev->words_per_chunk;
   if (sim_pairs_per_lane) *sim_pairs_per_lane = ev->sim_iters;
+  if (sim_streams) *sim_streams = n_sim_streams(ev);
   return DP_OK;
 }
 

@@ -14,6 +14,9 @@ struct dp_eval {
   int32_t schedule = DP_SCHED_AUTO;
   int64_t words_per_chunk = 0;
   int32_t sim_iters = 0;
+  int32_t sim_streams = 0;                 // 0 = automatic (1)
+  std::vector<hipStream_t> lane_streams;   // extra simulation streams (owned)
+  std::vector<hipEvent_t> lane_events;     // fork + one join per extra stream
   // inputs
   dp::DevBuf p_stage;        // [B][n_pi] caller layout
   dp::DevBuf sp;             // [n_nets][B]

@@ -508,12 +508,16 @@ __global__ __launch_bounds__(kBlock) void k_power_tiled(PowerArgs a, int32_t n_s
     }
 }
 
+// One block per column: thread t sums chunks t, t + 256, ... in order, then
+// a fixed tree over the block.
 __global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_cols) {
-  const int64_t col = gidx();
-  if (col >= n_cols) return;
+  __shared__ double lds[kWavesPerBlock];
+  const int32_t col = blockIdx.x;
   double acc = 0.0;
-  for (int32_t k = 0; k < a.n_chunks; ++k) acc += a.partial[(int64_t)k * n_cols + col];
-  a.power[col] = (float)acc;
+  for (int32_t k = threadIdx.x; k < a.n_chunks; k += kBlock)
+    acc += a.partial[(int64_t)k * n_cols + col];
+  const double r = block_sum_d(acc, lds);
+  if (threadIdx.x == 0) a.power[col] = (float)r;
 }
 
 // ---------------------------------------------------------------- reverse sweep
@@ -836,7 +840,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     PowerArgs f = a;
     f.n_chunks = n_slabs;
-    k_power_final<<<blocks_for(n_cols), kBlock, 0, s>>>(f, n_cols);
+    k_power_final<<<(unsigned)n_cols, kBlock, 0, s>>>(f, n_cols);
     return hipGetLastError();
   }
   const int64_t blocks = (int64_t)a.n_chunks * n_cols;
@@ -844,7 +848,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
   k_power_partial<<<(unsigned)blocks, kBlock, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_power_final<<<blocks_for(n_cols), kBlock, 0, s>>>(a, n_cols);
+  k_power_final<<<(unsigned)n_cols, kBlock, 0, s>>>(a, n_cols);
   return hipGetLastError();
 }
 

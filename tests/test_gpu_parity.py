@@ -92,10 +92,13 @@ def test_dag2k_all_outputs(ctx, mode):
     np.testing.assert_array_equal(d.levels(), o.levels())
 
 
-@pytest.mark.parametrize("chunk,ppl", [(0, 1), (0, 2), (0, 8), (2, 0), (6, 4), (64, 0), (30, 1)])
-def test_chunking_and_lane_tiling_are_bit_exact(ctx, chunk, ppl):
-    """Word chunks (with their halo) and pairs per lane change no count."""
-    say(f"chunk={chunk} pairs/lane={ppl}")
+@pytest.mark.parametrize("chunk,ppl,streams", [(0, 1, 1), (0, 2, 1), (0, 8, 1), (2, 0, 1),
+                                               (6, 4, 1), (64, 0, 1), (30, 1, 1), (30, 1, 3),
+                                               (64, 0, 2), (6, 2, 4)])
+def test_chunking_and_lane_tiling_are_bit_exact(ctx, chunk, ppl, streams):
+    """Word chunks (with their halo), pairs per lane and concurrent
+    simulation streams change no count."""
+    say(f"chunk={chunk} pairs/lane={ppl} streams={streams}")
     nl = synth.random_dag(synth.SPECS["dag2k"], 2)
     p, cap, _ = _inputs(nl, 2)
     d = api.Design(ctx, nl)
@@ -104,6 +107,7 @@ def test_chunking_and_lane_tiling_are_bit_exact(ctx, chunk, ppl):
     ev.set_pi_prob(p)
     ev.set_caps(cap)
     ev.set_schedule(L.DP_SCHED_LEVEL, chunk, ppl)
+    ev.set_sim_streams(streams)
     res = ev.forward(("ones", "toggles", "power"))
     o = oracle.Netlist.of(nl)
     ones, tog = o.sim(T, p_pi=p[0], seed=3)
@@ -208,7 +212,8 @@ def test_graph_schedule_matches_level_schedule(ctx):
     for sched in (L.DP_SCHED_LEVEL, L.DP_SCHED_GRAPH):
         ev = api.Eval(d, 2, mode=L.DP_HYBRID, n_sim=64 * 33, seed=4)
         ev.set_caps(cap)
-        ev.set_schedule(sched)
+        ev.set_schedule(sched, 12)
+        ev.set_sim_streams(3 if sched == L.DP_SCHED_GRAPH else 1)
         out = []
         for rep in range(3):
             ev.set_pi_prob(np.clip(p + 0.01 * rep, 0, 1))
