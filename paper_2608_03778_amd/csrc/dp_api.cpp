@@ -263,21 +263,21 @@ double sim_level_bytes(const dp_design *d, int32_t l, int64_t words, int32_t B, 
   const int64_t pins = d->lvl_pins[l];
   double b = (double)(8 * pins + 8 * n) * (double)words  // fan-in words + output word
              + (double)(4 * pins + n) + 8.0 * n;         // indices, cell, counters
-  if (fused) b += (double)B * (4 * pins + 4 * n);         // SP gathers and writes
+  if (fused) b += (double)B * (8 * pins + 8 * n);         // SP pair gathers and writes
   return b;
 }
 
 double sp_level_bytes(const dp_design *d, int32_t l, int32_t B) {
   const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
   const int64_t pins = d->lvl_pins[l];
-  return (double)B * (4 * pins + 4 * n) + (double)(4 * pins + n);
+  return (double)B * (8 * pins + 8 * n) + (double)(4 * pins + n);  // (p, q) pairs
 }
 
 double bwd_level_bytes(const dp_design *d, int32_t l, int32_t C) {
   const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
   const int64_t pins = d->lvl_pins[l], fo = d->lvl_fanout[l];
-  // per column: seed, pulled contributions, fan-in SP gathers, contribution writes
-  const double per_col = 4.0 * n + 4.0 * fo + 4.0 * pins + 4.0 * pins;
+  // per column: seed, pulled contributions, fan-in SP pair gathers, contribution writes
+  const double per_col = 4.0 * n + 4.0 * fo + 8.0 * pins + 4.0 * pins;
   // structure: fan-out offsets and edge ids, fan-in indices, cell
   const double structure = 8.0 * n + 4.0 * fo + 4.0 * pins + n;
   return (double)C * per_col + structure;
@@ -576,7 +576,7 @@ dp_status dp_eval_create(dp_design *d, int32_t n_cols, int32_t n_size, const dp_
   ev->B = n_cols;
   ev->S = n_size;
   ev->prm = *params;
-  dp_status st = ev->sp.alloc((size_t)d->n_nets * n_cols * sizeof(float));
+  dp_status st = ev->sp.alloc((size_t)d->n_nets * n_cols * 2 * sizeof(float));  // (p, 1-p)
   if (st == DP_OK) st = ev->cap.alloc((size_t)d->n_nets * sizeof(float));
   if (st == DP_OK && n_size > 0) st = ev->size.alloc((size_t)n_size * d->n_gates * sizeof(float));
   if (st != DP_OK) {
@@ -992,7 +992,7 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   auto A = [&](DevBuf &b, size_t bytes) {
     if (st == DP_OK) st = b.alloc(std::max<size_t>(bytes, 16));
   };
-  A(ev->sp, nn * capacity * 4);
+  A(ev->sp, nn * capacity * 8);  // (p, 1-p) pairs
   A(ev->cap, nn * 4);
   A(ev->size, (size_t)capacity * d->n_gates * 4);
   A(ev->size_stage, (size_t)capacity * d->n_gates * 4);

@@ -34,9 +34,13 @@ struct CountView {
   int32_t B, col;
 };
 
+// Signal probabilities are stored as pairs (p, q = 1 - p) per net and
+// column, [n_nets][B][2]: every cell rule has a form without cancellation
+// for both, so TR = 2 p q keeps its relative accuracy when p is near 0 or 1.
+
 // SP of one level of B columns, optionally fused into a simulation launch.
 struct SpLevel {
-  float *sp;          // [n_nets][B]
+  float *sp;          // [n_nets][B][2]
   int32_t B;
   int32_t g0, n;      // level gate range (internal ids)
 };
@@ -49,7 +53,7 @@ struct SimTune {
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 
-// PI probabilities [B][n_pi] (caller layout) -> SP rows [n_pi][B].
+// PI probabilities [B][n_pi] (caller layout) -> SP pairs [n_pi][B][2].
 hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t s);
 // Check values are finite and inside [lo, hi]; sets *bad = 1 otherwise.
 hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
@@ -70,7 +74,7 @@ hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s)
 // PI rows of one chunk: Philox stimulus (stim == nullptr) or explicit words
 // stim[i][T]; counts ones/toggles of the PI nets.
 hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
-                           const float *p_col /* [n_pi][B] SP rows, column cnt.col */,
+                           const float *p_col /* SP pairs [n_pi][B][2], column cnt.col */,
                            const uint64_t *stim, int64_t T, uint64_t seed, const SimTune &tune,
                            hipStream_t s);
 
@@ -83,7 +87,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
 // Finalize per internal net and column: beta, X = kappa*beta*TR_model, the
 // local adjoint seed base, optional caller-numbered exports.
 struct FinalizeArgs {
-  const float *sp;          // [n_nets][B]
+  const float *sp;          // [n_nets][B][2]
   const uint32_t *ones, *tog;  // [n_nets][B] or null (modeled)
   const float *beta_frozen; // [n_nets][B], or [n_nets] when beta_shared, or null
   int32_t beta_shared;      // one frozen beta for every column
@@ -100,7 +104,8 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
 // Caller-numbered exports of forward quantities, [B][n_nets].
 struct ExportArgs {
-  const float *sp, *beta;
+  const float *sp;            // [n_nets][B][2]
+  const float *beta;
   const uint32_t *ones, *tog;
   const int32_t *int2ext;
   int64_t T;
@@ -127,7 +132,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s);
 
 // Reverse sweep.  Columns c in [0, C); the SP column of c is c / cdiv.
 struct BwdArgs {
-  const float *sp;            // [n_nets][B]
+  const float *sp;            // [n_nets][B][2]
   const float *beta;          // [n_nets][B]  (STE only)
   float *seed;                // [n_nets][C]
   float *contrib;             // [3][G][C]

@@ -25,6 +25,8 @@ constexpr int kWavesPerBlock = kBlock / 64;
 // Two consecutive simulation words as one 16-byte vector (a single
 // dwordx4 access per lane).
 typedef uint64_t w2 __attribute__((ext_vector_type(2)));
+// A signal probability and its complement (p, q = 1 - p), one 8-byte access.
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 enum : int { INV = 0, BUF, AND2, OR2, NAND2, NOR2, XOR2, AOI21, MUX2 };
 
@@ -32,39 +34,55 @@ __device__ __forceinline__ int arity_of(int op) { return op < AND2 ? 1 : (op < A
 
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
 
-// Probability that the cell output is 1 for independent inputs (Sec. II-B;
-// Alg. 2 gives AND = a0 a1 and NAND = 1 - a0 a1).  Forms are chosen so that
-// no term cancels: OR = a + b(1 - a), XOR = a(1 - b) + b(1 - a),
-// MUX = i0 + s (i1 - i0).
-__device__ __forceinline__ float sp_rule(int op, float a, float b, float c) {
-  switch (op) {
-    case INV: return 1.0f - a;
-    case BUF: return a;
-    case AND2: return a * b;
-    case OR2: return fmaf(b, 1.0f - a, a);
-    case NAND2: return fmaf(-a, b, 1.0f);
-    case NOR2: return (1.0f - a) * (1.0f - b);
-    case XOR2: return fmaf(a, 1.0f - b, b * (1.0f - a));
-    case AOI21: return fmaf(-a, b, 1.0f) * (1.0f - c);
-    default: return fmaf(c, b - a, a);  // MUX2
-  }
+// Clip to [0, 1] (Alg. 2) and re-tie the pair: the smaller of p and q comes
+// from its own formula (full relative accuracy), the larger is 1 minus it.
+// Without this, rounding drift of p + q - 1 adds up along reconvergent
+// paths and grows with the number of paths.
+__device__ __forceinline__ f2 settle(f2 v) {
+  const float p = clamp01(v.x), q = clamp01(v.y);
+  return p <= q ? f2{p, 1.0f - p} : f2{1.0f - q, q};
 }
 
-// Partial derivatives of sp_rule (Sec. III-E).
-__device__ __forceinline__ void sp_partials(int op, float a, float b, float c, float &d0, float &d1,
+// Probability that the cell output is 1, and its complement, for
+// independent inputs (Sec. II-B; Alg. 2 gives AND = a0 a1 and NAND =
+// 1 - a0 a1).  Inputs and outputs are (p, q = 1 - p) pairs and every
+// formula is a sum of products of p's and q's, so neither output loses
+// relative accuracy when the probability is close to 0 or 1.
+__device__ __forceinline__ f2 sp_rule(int op, f2 a, f2 b, f2 c) {
+  const float pa = a.x, qa = a.y, pb = b.x, qb = b.y, pc = c.x, qc = c.y;
+  f2 r;
+  switch (op) {
+    case INV: r = f2{qa, pa}; break;
+    case BUF: r = a; break;
+    case AND2: r = f2{pa * pb, fmaf(pa, qb, qa)}; break;
+    case OR2: r = f2{fmaf(qa, pb, pa), qa * qb}; break;
+    case NAND2: r = f2{fmaf(pa, qb, qa), pa * pb}; break;
+    case NOR2: r = f2{qa * qb, fmaf(qa, pb, pa)}; break;
+    case XOR2: r = f2{fmaf(pa, qb, qa * pb), fmaf(pa, pb, qa * qb)}; break;
+    case AOI21: r = f2{fmaf(pa, qb, qa) * qc, fmaf(pa * pb, qc, pc)}; break;  // !((A1&A2)|B)
+    default: r = f2{fmaf(qc, pa, pc * pb), fmaf(qc, qa, pc * qb)}; break;     // MUX2 S?I1:I0
+  }
+  return r;
+}
+
+// Partial derivatives of the output probability with respect to each input
+// probability (Sec. III-E: dAND/da = b, dOR/da = 1 - b, dXOR/da = 1 - 2b,
+// dNOT = -1; the compound cells by the product rule).
+__device__ __forceinline__ void sp_partials(int op, f2 a, f2 b, f2 c, float &d0, float &d1,
                                             float &d2) {
+  const float pa = a.x, qa = a.y, pb = b.x, qb = b.y, pc = c.x, qc = c.y;
   d1 = 0.0f;
   d2 = 0.0f;
   switch (op) {
     case INV: d0 = -1.0f; break;
     case BUF: d0 = 1.0f; break;
-    case AND2: d0 = b; d1 = a; break;
-    case OR2: d0 = 1.0f - b; d1 = 1.0f - a; break;
-    case NAND2: d0 = -b; d1 = -a; break;
-    case NOR2: d0 = b - 1.0f; d1 = a - 1.0f; break;
-    case XOR2: d0 = fmaf(-2.0f, b, 1.0f); d1 = fmaf(-2.0f, a, 1.0f); break;
-    case AOI21: d0 = -b * (1.0f - c); d1 = -a * (1.0f - c); d2 = fmaf(a, b, -1.0f); break;
-    default: d0 = 1.0f - c; d1 = c; d2 = b - a; break;  // MUX2
+    case AND2: d0 = pb; d1 = pa; break;
+    case OR2: d0 = qb; d1 = qa; break;
+    case NAND2: d0 = -pb; d1 = -pa; break;
+    case NOR2: d0 = -qb; d1 = -qa; break;
+    case XOR2: d0 = qb - pb; d1 = qa - pa; break;
+    case AOI21: d0 = -pb * qc; d1 = -pa * qc; d2 = -fmaf(pa, qb, qa); break;
+    default: d0 = qc; d1 = pc; d2 = pb - pa; break;  // MUX2
   }
 }
 
@@ -116,7 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_load_pi(const float *__restrict__ p,
   int64_t idx = gidx();
   if (idx >= (int64_t)n_pi * B) return;
   int32_t i = (int32_t)(idx / B), b = (int32_t)(idx - (int64_t)i * B);
-  sp[idx] = p[(int64_t)b * n_pi + i];
+  const float v = p[(int64_t)b * n_pi + i];
+  reinterpret_cast<f2 *>(sp)[idx] = f2{v, 1.0f - v};  // exact for v >= 1/2
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_range(const float *__restrict__ v, int64_t n,
@@ -165,10 +184,12 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int32_t gi = lv.g0 + gl;
   const int op = g.op[gi];
   const int k = arity_of(op);
-  const float a = lv.sp[(int64_t)g.in[gi] * B + b];
-  const float bb = k > 1 ? lv.sp[(int64_t)g.in[g.G + gi] * B + b] : 0.0f;
-  const float cc = k > 2 ? lv.sp[(int64_t)g.in[2 * g.G + gi] * B + b] : 0.0f;
-  lv.sp[(int64_t)(g.n_pi + gi) * B + b] = clamp01(sp_rule(op, a, bb, cc));
+  f2 *sp = reinterpret_cast<f2 *>(lv.sp);
+  const f2 z = f2{0.0f, 1.0f};
+  const f2 a = sp[(int64_t)g.in[gi] * B + b];
+  const f2 bb = k > 1 ? sp[(int64_t)g.in[g.G + gi] * B + b] : z;
+  const f2 cc = k > 2 ? sp[(int64_t)g.in[2 * g.G + gi] * B + b] : z;
+  sp[(int64_t)(g.n_pi + gi) * B + b] = settle(sp_rule(op, a, bb, cc));
 }
 
 __global__ __launch_bounds__(kBlock) void k_sp_level(GraphView g, SpLevel lv) {
@@ -329,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
   if (task >= (int64_t)n_pi * waves_per_row) return;
   const int32_t i = (int32_t)(task / waves_per_row);
   const int32_t seg = (int32_t)(task - (int64_t)i * waves_per_row);
-  const uint64_t thr = prob_threshold(p_rows[(int64_t)i * cnt.B + cnt.col]);
+  const uint64_t thr = prob_threshold(p_rows[((int64_t)i * cnt.B + cnt.col) * 2]);
   const uint64_t *srow = stim ? stim + (int64_t)i * T : nullptr;
   auto word = [&](int64_t u) -> uint64_t {
     const int64_t t = c.t_first + u;
@@ -374,8 +395,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a) {
   const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
   if (idx >= (uint32_t)a.n_nets * (uint32_t)a.B) return;
   const int32_t n = (int32_t)(idx / (uint32_t)a.B);
-  const float P = a.sp[idx];
-  const float tm = 2.0f * P * (1.0f - P);
+  const f2 pq = reinterpret_cast<const f2 *>(a.sp)[idx];
+  const float tm = 2.0f * pq.x * pq.y;
   float beta = 1.0f;
   if (a.mode == 1) {
     const float ta = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
@@ -390,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a) {
   const float C = a.cap[n];
   a.beta[idx] = beta;
   a.xterm[idx] = a.kappa * beta * tm;
-  const float local = a.kappa * C * 2.0f * fmaf(-2.0f, P, 1.0f);
+  const float local = a.kappa * C * 2.0f * (pq.y - pq.x);  // d TR_model / dP = 2 (1 - 2P)
   a.seed_base[idx] = a.ste ? local : beta * local;
 }
 
@@ -399,9 +420,9 @@ __global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
   if (idx >= (int64_t)a.n_nets * a.B) return;
   const int32_t n = (int32_t)(idx / a.B), b = (int32_t)(idx - (int64_t)n * a.B);
   const int64_t o = (int64_t)b * a.n_nets + a.int2ext[n];
-  const float P = a.sp[idx];
-  const float tm = 2.0f * P * (1.0f - P);
-  if (a.o_sp) a.o_sp[o] = P;
+  const f2 pq = reinterpret_cast<const f2 *>(a.sp)[idx];
+  const float tm = 2.0f * pq.x * pq.y;
+  if (a.o_sp) a.o_sp[o] = pq.x;
   if (a.o_tr) a.o_tr[o] = tm;
   if (a.o_beta) a.o_beta[o] = a.beta[idx];
   if (a.o_tr_hyb) a.o_tr_hyb[o] = a.beta[idx] * tm;
@@ -621,9 +642,11 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, in
   const int op = g.op[gi];
   const int k = arity_of(op);
   const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
-  const float x0 = a.sp[(int64_t)i0 * a.B + b];
-  const float x1 = k > 1 ? a.sp[(int64_t)i1 * a.B + b] : 0.0f;
-  const float x2 = k > 2 ? a.sp[(int64_t)i2 * a.B + b] : 0.0f;
+  const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
+  const f2 z = f2{0.0f, 1.0f};
+  const f2 x0 = sp[(int64_t)i0 * a.B + b];
+  const f2 x1 = k > 1 ? sp[(int64_t)i1 * a.B + b] : z;
+  const f2 x2 = k > 2 ? sp[(int64_t)i2 * a.B + b] : z;
   float d0, d1, d2;
   sp_partials(op, x0, x1, x2, d0, d1, d2);
   a.contrib[(int64_t)gi * a.C + c] = lam * d0;
