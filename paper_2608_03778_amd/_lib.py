@@ -119,6 +119,21 @@ class DiffPowerError(RuntimeError):
         self.status = status
 
 
+def _settle_hip_runtime():
+    """Make sure a process holds one HIP runtime.
+
+    The torch wheel ships its own libamdhip64 (soname libamdhip64.so.7) and
+    loads it as "libamdhip64.so".  If libdiffpower.so (which needs
+    libamdhip64.so.7) loaded the system runtime first, torch would not
+    recognise it by that name and would load a second runtime, which then
+    finds no GPU.  Importing torch first, when it is installed, lets
+    libdiffpower.so bind to the runtime torch already loaded.
+    """
+    import importlib.util
+    if importlib.util.find_spec("torch") is not None:
+        import torch  # noqa: F401
+
+
 def load(path: str = LIB_PATH):
     """Load and declare the library (cached).  Raises if it is not built."""
     global _lib
@@ -127,6 +142,7 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -c 'import __graft_entry__ as g; "
                           "g.build()'` (hipcc, gfx950) first")
+    _settle_hip_runtime()
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

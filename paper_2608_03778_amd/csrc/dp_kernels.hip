@@ -634,19 +634,28 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, in
   const int32_t out = g.n_pi + gi;
   const int32_t e0 = active ? g.rev_ptr[out] : 0;
   const int32_t e1 = active ? g.rev_ptr[out + 1] : 0;
+  // loads that do not depend on the pull are issued first, so their latency
+  // overlaps the fan-out gather
+  const int32_t b = c / a.cdiv;
+  int op = 0, k = 1;
+  float seed = 0.0f, beta = 1.0f;
+  const f2 z = f2{0.0f, 1.0f};
+  f2 x0 = z, x1 = z, x2 = z;
+  if (active) {
+    op = g.op[gi];
+    k = arity_of(op);
+    const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
+    const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
+    x0 = sp[(int64_t)i0 * a.B + b];
+    if (k > 1) x1 = sp[(int64_t)i1 * a.B + b];
+    if (k > 2) x2 = sp[(int64_t)i2 * a.B + b];
+    seed = a.seed[(int64_t)out * a.C + c];
+    if (a.ste) beta = a.beta[(int64_t)out * a.B + b];
+  }
   const float pulled = pull_sum(a.contrib, g.rev_edge, e0, e1, a.C, c, active, lane);
   if (!active) return;
-  const int32_t b = c / a.cdiv;
-  float lam = a.seed[(int64_t)out * a.C + c] + pulled;
-  if (a.ste) lam *= a.beta[(int64_t)out * a.B + b];
-  const int op = g.op[gi];
-  const int k = arity_of(op);
-  const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
-  const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
-  const f2 z = f2{0.0f, 1.0f};
-  const f2 x0 = sp[(int64_t)i0 * a.B + b];
-  const f2 x1 = k > 1 ? sp[(int64_t)i1 * a.B + b] : z;
-  const f2 x2 = k > 2 ? sp[(int64_t)i2 * a.B + b] : z;
+  float lam = seed + pulled;
+  if (a.ste) lam *= beta;
   float d0, d1, d2;
   sp_partials(op, x0, x1, x2, d0, d1, d2);
   a.contrib[(int64_t)gi * a.C + c] = lam * d0;

@@ -71,3 +71,19 @@ def test_null_arguments_are_rejected_without_a_gpu(lib):
     assert lib.dp_forward(None, None) == L.DP_E_INVALID
     assert lib.dp_backward(None, None, None, None, None, 0) == L.DP_E_INVALID
     assert lib.dp_eval_set_schedule(None, 0, 0, 0) == L.DP_E_INVALID
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library after torch binds it to torch's HIP runtime: a
+    fresh process that loads the binding holds a single libamdhip64."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2608_03778_amd import _lib\n"
+            "_lib.load()\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "paths = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(paths))\n") % (os.path.dirname(HEADER).rsplit("/include", 1)[0],)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
