@@ -48,6 +48,30 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def measured_traffic(workload, n_sim, schedule):
+    """HBM bytes per simulation launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
+    the kernel source changed since the counters were taken or the launch
+    configuration differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sim_level_dag1m_traffic.txt")
+    src = os.path.join(ROOT, "paper_2608_03778_amd", "csrc", "dp_kernels.hip")
+    if workload != "dag1m" or n_sim != 65536 or schedule.get("pairs_per_lane") != 4 \
+            or schedule.get("words_per_chunk", 0) != 0 or schedule.get("sim_streams", 1) != 1:
+        return None
+    try:
+        kv = dict(ln.strip().split("=", 1) for ln in open(path)
+                  if "=" in ln and not ln.startswith("#"))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256_16") != sha:
+        return None
+    kib = (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"])
+           + float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+    return kib * 1024.0
+
+
 def cpu_baseline(nl, p, cap, n_words_full, sample_words, seed):
     """The FP64 oracle on the same design: SP, finalize and adjoint in full,
     the simulation on `sample_words` of the words, scaled linearly in words."""
@@ -415,7 +439,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": sim_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, args.n_sim, schedule),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                            "scaled by a 1 GiB copy; null if the kernel changed)",
             "launches": prof["sim_launches"] // args.steps,
             "avg_launch_us": prof["sim_ms"] * 1e3 / max(prof["sim_launches"], 1),
             "algorithmic_bytes_per_launch": prof["sim_bytes"] / max(prof["sim_launches"], 1),
