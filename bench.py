@@ -330,7 +330,7 @@ def main():
     if args.schedule or args.words_per_chunk or args.pairs_per_lane:
         ev.set_schedule(args.schedule, args.words_per_chunk, args.pairs_per_lane)
     else:
-        tuned_ms = ev.autotune(3)
+        tuned_ms = ev.autotune(3, with_backward=True)
     schedule = ev.get_schedule()
     log(f"[bench] schedule {schedule} (autotuned forward {tuned_ms} ms)")
 
@@ -362,7 +362,8 @@ def main():
         evm = api.Eval(d, 1, mode=L.DP_MODELED)
         evm.set_pi_prob(p_dev)
         evm.set_caps(cap_dev)
-        for sched, name in ((L.DP_SCHED_LEVEL, "level"), (L.DP_SCHED_GRAPH, "graph")):
+        for sched, name in ((L.DP_SCHED_LEVEL, "level"), (L.DP_SCHED_GRAPH, "graph"),
+                            (L.DP_SCHED_PERSISTENT, "persistent")):
             evm.set_schedule(sched)
             tf = time_steps(lambda: evm.forward(("power",), device=True), 20, 3)
             tfb = time_steps(lambda: (evm.forward(("power",), device=True),

@@ -83,9 +83,12 @@ enum {
 
 /* Sweep schedules (see dp_eval_set_schedule). */
 enum {
-  DP_SCHED_AUTO = 0,  /* the autotuned choice (default) */
-  DP_SCHED_LEVEL = 1, /* one launch per level */
-  DP_SCHED_GRAPH = 2  /* the same launches captured once into a HIP graph */
+  DP_SCHED_AUTO = 0,      /* the autotuned choice (default) */
+  DP_SCHED_LEVEL = 1,     /* one launch per level */
+  DP_SCHED_GRAPH = 2,     /* the same launches captured once into a HIP graph */
+  DP_SCHED_PERSISTENT = 3 /* SP-only sweeps (modeled forward, reverse sweep) as
+                             one cooperative launch with a grid barrier per
+                             level; the simulation keeps one launch per level */
 };
 
 typedef struct dp_ctx dp_ctx;
@@ -240,14 +243,16 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule,
                                int64_t words_per_chunk,
                                int32_t sim_pairs_per_lane);
 
-/* Autotuner: time the forward sweep (one warm-up and `reps` timed runs
- * with HIP events on the context's stream) for every schedule candidate --
- * per-level launches or a captured HIP graph, 1/2/4/8 word pairs per lane,
- * the whole run or 2 or 4 word chunks, 1/2/4 simulation streams -- and keep
- * the fastest.  Needs the
- * inputs set; overwrites the eval's forward results.  best_ms (may be NULL)
- * receives the winner's time per forward. */
-dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms);
+/* Autotuner: time the forward sweep, followed by the reverse sweep when
+ * with_backward is nonzero (one warm-up and `reps` timed runs with HIP
+ * events on the context's stream), for every schedule candidate --
+ * per-level launches, a captured HIP graph or persistent SP-only sweeps;
+ * 1/2/4/8 word pairs per lane; the whole run or 2 or 4 word chunks; 1/2/4
+ * simulation streams -- and keep the fastest.  Needs the inputs set;
+ * overwrites the eval's results.  best_ms (may be NULL) receives the
+ * winner's time. */
+dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward,
+                           double *best_ms);
 /* Number of streams that simulate independent (query column, word chunk)
  * pieces concurrently, each with its own word buffer (0 = automatic = 1).
  * Counts are integer sums, so results do not depend on it. */

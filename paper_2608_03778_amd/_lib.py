@@ -21,7 +21,7 @@ DP_OK, DP_E_INVALID, DP_E_CYCLE, DP_E_OOM, DP_E_HIP, DP_E_UNSUPPORTED, DP_E_STAT
     DP_E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8
 DP_MODELED, DP_HYBRID, DP_FROZEN_BETA = 0, 1, 2
 DP_BETA_LOCAL, DP_BETA_STE = 0, 1
-DP_SCHED_AUTO, DP_SCHED_LEVEL, DP_SCHED_GRAPH = 0, 1, 2
+DP_SCHED_AUTO, DP_SCHED_LEVEL, DP_SCHED_GRAPH, DP_SCHED_PERSISTENT = 0, 1, 2, 3
 DP_Q_FWD, DP_Q_FWD_BWD = 0, 1
 
 STATUS_NAMES = {0: "DP_OK", -1: "DP_E_INVALID", -2: "DP_E_CYCLE", -3: "DP_E_OOM",
@@ -95,7 +95,7 @@ SIGNATURES = {
     "dp_backward": (_st, [_p, _p, _p, _p, _p, _i32]),
     "dp_backward_columns": (_st, [_p, _p, _i32]),
     "dp_eval_set_schedule": (_st, [_p, _i32, _i64, _i32]),
-    "dp_eval_autotune": (_st, [_p, _i32, _p]),
+    "dp_eval_autotune": (_st, [_p, _i32, _i32, _p]),
     "dp_eval_set_sim_streams": (_st, [_p, _i32]),
     "dp_eval_get_schedule": (_st, [_p, _p, _p, _p, _p]),
     "dp_eval_profile": (_st, [_p, _i32]),

@@ -230,10 +230,12 @@ class Eval:
         check(self.lib.dp_backward_columns(self.handle, ptr, int(bool(device))))
         return arr
 
-    def autotune(self, reps: int = 3) -> float:
-        """Pick the fastest forward schedule; returns its ms per forward."""
+    def autotune(self, reps: int = 3, with_backward: bool = False) -> float:
+        """Pick the fastest schedule for the forward (and, with_backward,
+        the reverse) sweep; returns its ms."""
         ms = ctypes.c_double()
-        check(self.lib.dp_eval_autotune(self.handle, int(reps), ctypes.byref(ms)))
+        check(self.lib.dp_eval_autotune(self.handle, int(reps), int(bool(with_backward)),
+                                        ctypes.byref(ms)))
         return ms.value
 
     def set_sim_streams(self, n: int):

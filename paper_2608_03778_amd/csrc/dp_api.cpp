@@ -52,6 +52,7 @@ dp::GraphView view(const dp_design *d) {
   g.in = d->in.as<int32_t>();
   g.rev_ptr = d->rev_ptr.as<int32_t>();
   g.rev_edge = d->rev_edge.as<int32_t>();
+  g.slot = d->slot.as<int32_t>();
   g.n_pi = d->n_pi;
   g.G = d->n_gates;
   g.n_nets = d->n_nets;
@@ -294,9 +295,15 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
     double bytes = 0.0;
     for (int32_t l = 1; l <= d->depth; ++l) bytes += sp_level_bytes(d, l, ev->B);
     SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth);
-    for (int32_t l = 1; l <= d->depth; ++l) {
-      dp::SpLevel lv{sp, ev->B, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l]};
-      DP_HIP_TRY(dp::launch_sp_level(g, lv, s));
+    if (ev->schedule == DP_SCHED_PERSISTENT) {
+      dp::SpLevel lv{sp, ev->B, 0, 0};
+      DP_HIP_TRY(dp::launch_sp_persistent(g, lv, d->level_dev.as<int32_t>(), d->depth,
+                                          (int64_t)d->max_level_width * ev->B, s));
+    } else {
+      for (int32_t l = 1; l <= d->depth; ++l) {
+        dp::SpLevel lv{sp, ev->B, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l]};
+        DP_HIP_TRY(dp::launch_sp_level(g, lv, s));
+      }
     }
   } else {
     const size_t nb = (size_t)d->n_nets * ev->B;
@@ -690,7 +697,7 @@ dp_status dp_set_stimulus(dp_eval *ev, const uint64_t *words, int32_t on_device)
 dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_chunk,
                                int32_t sim_pairs_per_lane) {
   if (!ev) return fail(DP_E_INVALID, "dp_eval_set_schedule: NULL eval");
-  if (schedule < DP_SCHED_AUTO || schedule > DP_SCHED_GRAPH)
+  if (schedule < DP_SCHED_AUTO || schedule > DP_SCHED_PERSISTENT)
     return fail(DP_E_INVALID, "dp_eval_set_schedule: unknown schedule");
   if (words_per_chunk < 0 || (words_per_chunk > 0 && words_per_chunk < 2))
     return fail(DP_E_INVALID, "dp_eval_set_schedule: words_per_chunk must be 0 or >= 2");
@@ -703,7 +710,10 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_
   return DP_OK;
 }
 
-dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms) {
+static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_column,
+                              float *dpi, float *dcap, float *dsize, int32_t on_device);
+
+dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward, double *best_ms) {
   if (!ev) return fail(DP_E_INVALID, "dp_eval_autotune: NULL eval");
   if (reps < 1) reps = 1;
   const int32_t s0 = ev->schedule, i0 = ev->sim_iters, l0 = ev->sim_streams;
@@ -723,13 +733,18 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms) {
         if ((int64_t)lanes * ev->d->n_nets * 8 * (k == 0 ? T : chunks[k] + 2) > kAutoWordBudget)
           continue;
         for (int32_t it : {1, 2, 4, 8})
-          for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH})
+          for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH, DP_SCHED_PERSISTENT}) {
+            if (sc == DP_SCHED_PERSISTENT && !with_backward) continue;  // same forward as LEVEL
             cands.push_back({sc, it, chunks[k], lanes});
+          }
       }
     }
   } else {
-    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, 0, 0, 1});
+    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH, DP_SCHED_PERSISTENT})
+      cands.push_back({sc, 0, 0, 1});
   }
+  DevBuf bwd_out;  // scratch for the timed reverse sweeps
+  if (with_backward) DP_TRY(bwd_out.alloc((size_t)ev->B * std::max(ev->d->n_pi, 1) * 4));
   hipStream_t s = ev->stream();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   DP_HIP_TRY(hipEventCreate(&e0));
@@ -742,9 +757,15 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, double *best_ms) {
     ev->sim_iters = c.iters;
     ev->words_per_chunk = c.chunk;
     ev->sim_streams = c.lanes;
-    if ((st = dp_forward(ev, nullptr)) != DP_OK) break;  // warm-up, graph capture
+    auto once = [&]() -> dp_status {
+      dp_status r = dp_forward(ev, nullptr);
+      if (r == DP_OK && with_backward)
+        r = run_backward(ev, nullptr, 0, bwd_out.as<float>(), nullptr, nullptr, 1);
+      return r;
+    };
+    if ((st = once()) != DP_OK) break;  // warm-up, graph capture
     if (hipEventRecord(e0, s) != hipSuccess) { st = fail(DP_E_HIP, "autotune: event"); break; }
-    for (int32_t r = 0; r < reps && st == DP_OK; ++r) st = dp_forward(ev, nullptr);
+    for (int32_t r = 0; r < reps && st == DP_OK; ++r) st = once();
     if (st != DP_OK) break;
     float ms = 0.0f;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -883,7 +904,7 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
   const dp::GraphView g = view(d);
   if (dpi) {
     DP_TRY(ev->seed.alloc((size_t)d->n_nets * C * sizeof(float)));
-    DP_TRY(ev->contrib.alloc((size_t)3 * d->n_gates * C * sizeof(float)));
+    DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * C * sizeof(float), 16)));
     dp::SeedArgs sa{};
     sa.seed_base = ev->seed_base.as<float>();
     sa.w = w;
@@ -908,20 +929,26 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     ba.ste = ev->prm.beta_grad == DP_BETA_STE;
     double bwd_bytes = 0.0;
     for (int32_t l = d->depth; l >= 1; --l) bwd_bytes += bwd_level_bytes(d, l, C);
-    {
-      SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
-      for (int32_t l = d->depth; l >= 1; --l) {
-        const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-        DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
-      }
-    }
     float *dst = dpi;
     const size_t bytes = (size_t)C * d->n_pi * sizeof(float);
     if (!on_device) {
       DP_TRY(ev->pi_out.alloc(std::max<size_t>(bytes, 16)));
       dst = ev->pi_out.as<float>();
     }
-    DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
+    if (ev->schedule == DP_SCHED_PERSISTENT) {
+      SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
+      DP_HIP_TRY(dp::launch_bwd_persistent(g, ba, d->level_dev.as<int32_t>(), d->depth,
+                                           (int64_t)d->max_level_width * C, dst, s));
+    } else {
+      {
+        SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
+        for (int32_t l = d->depth; l >= 1; --l) {
+          const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+          DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
+        }
+      }
+      DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
+    }
     if (!on_device && bytes)
       DP_HIP_TRY(hipMemcpyAsync(dpi, dst, bytes, hipMemcpyDeviceToHost, s));
   }
@@ -970,7 +997,7 @@ namespace dp {
 
 size_t lane_bytes(const dp_design *d, int32_t capacity) {
   const size_t nn = d->n_nets, G = d->n_gates, np = d->n_pi;
-  const size_t per_col = 4 * (6 * nn + 3 * G + 2 * G + 2 * np) +
+  const size_t per_col = 4 * (6 * nn + (size_t)d->n_edges + 2 * G + 2 * np) +
                          8 * (size_t)power_chunks(d->n_nets) + 16;
   return (size_t)capacity * per_col + 8 * nn;
 }
@@ -1003,7 +1030,7 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   A(ev->power_partial, (size_t)power_chunks(d->n_nets) * capacity * 8);
   A(ev->power, (size_t)capacity * 4);
   A(ev->seed, nn * capacity * 4);
-  A(ev->contrib, (size_t)3 * d->n_gates * capacity * 4);
+  A(ev->contrib, (size_t)d->n_edges * capacity * 4);
   A(ev->pi_out, (size_t)capacity * d->n_pi * 4);
   if (beta_int) A(ev->beta_frozen, nn * 4);
   if (st != DP_OK) {

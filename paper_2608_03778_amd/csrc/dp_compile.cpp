@@ -166,6 +166,11 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
       }
     }
   }
+  // slot[j][g'] = where pin j of gate g' sits in its source net's fan-out
+  // list: the reverse sweep writes a pin's contribution there, so a net sums
+  // one contiguous range
+  std::vector<int32_t> slot(3 * (size_t)G, 0);
+  for (int64_t e = 0; e < n_edges; ++e) slot[rev_edge[e]] = (int32_t)e;
   d->lvl_pins.assign(depth + 1, 0);
   d->lvl_fanout.assign(depth + 1, 0);
   for (int32_t l = 1; l <= depth; ++l)
@@ -179,6 +184,8 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
   if ((st = upload(d->op, d->h_op, s)) != DP_OK || (st = upload(d->in, in, s)) != DP_OK ||
       (st = upload(d->rev_ptr, rev_ptr, s)) != DP_OK ||
       (st = upload(d->rev_edge, rev_edge, s)) != DP_OK ||
+      (st = upload(d->slot, slot, s)) != DP_OK ||
+      (st = upload(d->level_dev, d->level_ptr, s)) != DP_OK ||
       (st = upload(d->int2ext, d->h_int2ext, s)) != DP_OK ||
       (st = upload(d->ext2int, d->h_ext2int, s)) != DP_OK) {
     delete d;
@@ -190,7 +197,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
     return fail(DP_E_HIP, std::string("dp_compile: upload failed: ") + hipGetErrorString(e));
   }
   d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
-                              d->int2ext.bytes + d->ext2int.bytes);
+                              d->slot.bytes + d->int2ext.bytes + d->ext2int.bytes);
   ctx_retain(ctx);
   *out = d;
   return DP_OK;

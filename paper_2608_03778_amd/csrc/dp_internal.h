@@ -82,6 +82,8 @@ struct dp_design {
   dp::DevBuf in;        // int32 [3][n_gates] input net of pin j (SoA)
   dp::DevBuf rev_ptr;   // int32 [n_nets + 1] fan-out list offsets
   dp::DevBuf rev_edge;  // int32 [n_edges] fan-out edges, id = j * n_gates + g'
+  dp::DevBuf slot;      // int32 [3][n_gates] position of pin (g', j) in its source's fan-out list
+  dp::DevBuf level_dev; // int32 [depth + 2] device copy of level_ptr
   dp::DevBuf int2ext;   // int32 [n_nets]
   dp::DevBuf ext2int;   // int32 [n_nets]
   int64_t device_bytes = 0;

@@ -13,6 +13,7 @@ struct GraphView {
   const int32_t *in;        // [3][G]
   const int32_t *rev_ptr;   // [n_nets + 1]
   const int32_t *rev_edge;  // [n_edges]
+  const int32_t *slot;      // [3][G] fan-out position of each pin
   int32_t n_pi, G, n_nets;
 };
 
@@ -135,7 +136,7 @@ struct BwdArgs {
   const float *sp;            // [n_nets][B][2]
   const float *beta;          // [n_nets][B]  (STE only)
   float *seed;                // [n_nets][C]
-  float *contrib;             // [3][G][C]
+  float *contrib;             // [n_edges][C], in fan-out (reader) order
   int32_t B, C, cdiv, ste;
 };
 // seed[n][c] from seed_base, upstream weights w[b][s] and sizes.
@@ -152,6 +153,15 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
                             hipStream_t s);
 // PI adjoints -> out[c][n_pi].
 hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s);
+
+// Persistent (cooperative) sweeps: all levels in one launch with a grid
+// barrier between levels.  level_ptr is the device copy of the design's
+// level table; max_items the largest level's item count.
+hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
+                                int32_t depth, int64_t max_items, hipStream_t s);
+// Reverse levels depth..1 and then the PI adjoints into pi_out[c][n_pi].
+hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
+                                 int32_t depth, int64_t max_items, float *pi_out, hipStream_t s);
 // dcap[ext n] = sum_b xterm[n][b]/cap... computed as kappa*beta*TR * wsum.
 struct GradExportArgs {
   const float *xterm;         // [n_nets][B]

@@ -12,6 +12,8 @@
 // (gate, run of word pairs): the wave's cell is uniform, so the cell switch
 // is a scalar branch outside the word loop; each lane moves 16-byte word
 // pairs, so every fan-in row is read as contiguous 1 KiB wave-wide accesses.
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 
 #include "dp_kernels.h"
@@ -575,17 +577,17 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
   a.seed[idx] = v;
 }
 
-// Sum of the contributions the readers of a net left on their fan-in slots,
-// in an order fixed by the graph alone (not by the column, its lane or the
-// batch): nets with at most kLightFanout readers are summed serially in
-// fan-out order by their own lane, with the loads of four edges in flight
-// at once; heavier nets are summed by the whole wave, lane l taking edges
-// l, l + 64, ..., then a butterfly reduction.  Every lane of the wave must
-// call this (inactive lanes pass e0 == e1 and active == false).
+// Sum of the contributions the readers of a net left for it.  Readers write
+// into the net's own contiguous range [e0, e1) of the contribution buffer
+// (fan-out order), so the sum needs no index indirection; its order is
+// fixed by the graph alone (not by the column, its lane or the batch): nets
+// with at most kLightFanout readers are summed serially by their own lane,
+// four loads in flight; heavier nets by the whole wave, lane l taking
+// entries l, l + 64, ..., then a butterfly reduction.  Every lane of the
+// wave must call this (inactive lanes pass e0 == e1 and active == false).
 constexpr int32_t kLightFanout = 8;
 
-__device__ __forceinline__ float pull_sum(const float *__restrict__ contrib,
-                                          const int32_t *__restrict__ rev_edge, int32_t e0,
+__device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int32_t e0,
                                           int32_t e1, int32_t C, int32_t c, bool active,
                                           int lane) {
   float acc = 0.0f;
@@ -593,16 +595,14 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib,
   if (light) {
     int32_t e = e0;
     for (; e + 4 <= e1; e += 4) {
-      const int32_t r0 = rev_edge[e], r1 = rev_edge[e + 1], r2 = rev_edge[e + 2],
-                    r3 = rev_edge[e + 3];
-      const float v0 = contrib[(int64_t)r0 * C + c], v1 = contrib[(int64_t)r1 * C + c];
-      const float v2 = contrib[(int64_t)r2 * C + c], v3 = contrib[(int64_t)r3 * C + c];
+      const float v0 = contrib[(int64_t)e * C + c], v1 = contrib[(int64_t)(e + 1) * C + c];
+      const float v2 = contrib[(int64_t)(e + 2) * C + c], v3 = contrib[(int64_t)(e + 3) * C + c];
       acc += v0;
       acc += v1;
       acc += v2;
       acc += v3;
     }
-    for (; e < e1; ++e) acc += contrib[(int64_t)rev_edge[e] * C + c];
+    for (; e < e1; ++e) acc += contrib[(int64_t)e * C + c];
   }
   uint64_t heavy = __ballot(active && !light);
   while (heavy) {
@@ -610,7 +610,7 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib,
     heavy &= heavy - 1;
     const int32_t h0 = __shfl(e0, src), h1 = __shfl(e1, src), hc = __shfl(c, src);
     float part = 0.0f;
-    for (int32_t e = h0 + lane; e < h1; e += 64) part += contrib[(int64_t)rev_edge[e] * C + hc];
+    for (int32_t e = h0 + lane; e < h1; e += 64) part += contrib[(int64_t)e * C + hc];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if (lane == src) acc = part;
@@ -623,10 +623,10 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib,
 // order, so the sum is deterministic); it then leaves lambda * dR/dx_j on
 // each of its own fan-in slots.  Items are (gate, column) pairs, column
 // innermost; item counts stay below 2^31.
-__global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
-                                                      int32_t n) {
-  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+// One (gate, column) item of a reverse level; every lane of the wave calls
+// it (pull_sum needs the whole wave), lanes past the end pass active = false.
+__device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, int32_t g0,
+                                         int32_t n, uint32_t idx, int lane) {
   const bool active = idx < (uint32_t)n * (uint32_t)a.C;
   const uint32_t gl = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - gl * (uint32_t)a.C) : 0;
@@ -652,30 +652,79 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, in
     seed = a.seed[(int64_t)out * a.C + c];
     if (a.ste) beta = a.beta[(int64_t)out * a.B + b];
   }
-  const float pulled = pull_sum(a.contrib, g.rev_edge, e0, e1, a.C, c, active, lane);
+  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane);
   if (!active) return;
   float lam = seed + pulled;
   if (a.ste) lam *= beta;
   float d0, d1, d2;
   sp_partials(op, x0, x1, x2, d0, d1, d2);
-  a.contrib[(int64_t)gi * a.C + c] = lam * d0;
-  if (k > 1) a.contrib[((int64_t)g.G + gi) * a.C + c] = lam * d1;
-  if (k > 2) a.contrib[(2 * (int64_t)g.G + gi) * a.C + c] = lam * d2;
+  a.contrib[(int64_t)g.slot[gi] * a.C + c] = lam * d0;
+  if (k > 1) a.contrib[(int64_t)g.slot[g.G + gi] * a.C + c] = lam * d1;
+  if (k > 2) a.contrib[(int64_t)g.slot[2 * g.G + gi] * a.C + c] = lam * d2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
-  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
+                                                      int32_t n) {
+  bwd_item(g, a, g0, n, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+}
+
+__device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a, float *out,
+                                            uint32_t idx, int lane) {
   const bool active = idx < (uint32_t)g.n_pi * (uint32_t)a.C;
   const uint32_t i = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - i * (uint32_t)a.C) : 0;
   const int32_t e0 = active ? g.rev_ptr[i] : 0;
   const int32_t e1 = active ? g.rev_ptr[i + 1] : 0;
-  const float pulled = pull_sum(a.contrib, g.rev_edge, e0, e1, a.C, c, active, lane);
+  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane);
   if (!active) return;
   float lam = a.seed[idx] + pulled;
   if (a.ste) lam *= a.beta[(int64_t)i * a.B + c / a.cdiv];
   out[(int64_t)c * g.n_pi + i] = lam;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
+  bwd_pi_item(g, a, out, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------- persistent sweeps
+// One cooperative launch runs every level: a grid-stride loop over the
+// level's items, then a grid barrier (cooperative launch guarantees all
+// blocks are resident, so the barrier cannot deadlock).  Whole waves step
+// together so the wave-wide pull of the reverse sweep sees all its lanes.
+__global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel lv,
+                                                          const int32_t *__restrict__ level_ptr,
+                                                          int32_t depth) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const uint32_t stride = gridDim.x * kBlock;
+  for (int32_t l = 1; l <= depth; ++l) {
+    SpLevel cur = lv;
+    cur.g0 = level_ptr[l];
+    cur.n = level_ptr[l + 1] - cur.g0;
+    const uint32_t items = (uint32_t)cur.n * (uint32_t)cur.B;
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < items; idx += stride)
+      sp_item(g, cur, idx);
+    grid.sync();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs a,
+                                                           const int32_t *__restrict__ level_ptr,
+                                                           int32_t depth, float *pi_out) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const uint32_t stride = gridDim.x * kBlock;
+  const int lane = threadIdx.x & 63;
+  const uint32_t first = blockIdx.x * kBlock + threadIdx.x;
+  for (int32_t l = depth; l >= 1; --l) {
+    const int32_t g0 = level_ptr[l], n = level_ptr[l + 1] - g0;
+    const uint32_t items = (uint32_t)n * (uint32_t)a.C;
+    // round the trip count up to whole waves
+    for (uint32_t base = first - lane; base < items; base += stride)
+      bwd_item(g, a, g0, n, base + lane, lane);
+    grid.sync();
+  }
+  const uint32_t items = (uint32_t)g.n_pi * (uint32_t)a.C;
+  for (uint32_t base = first - lane; base < items; base += stride)
+    bwd_pi_item(g, a, pi_out, base + lane, lane);
 }
 
 // dP/dC_n = sum_{b,s} w[b][s] kappa beta TR_model s_s(drv n);
@@ -909,6 +958,54 @@ hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipSt
   if (items >= (1ll << 31)) return hipErrorInvalidValue;
   k_bwd_pi<<<blocks_for(items), kBlock, 0, s>>>(g, a, out);
   return hipGetLastError();
+}
+
+// Blocks of a cooperative launch: enough for the widest level, at most what
+// stays resident on the device.
+static hipError_t persistent_grid(const void *kernel, int64_t max_items, unsigned *grid) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
+  if (e != hipSuccess) return e;
+  const int64_t resident = (int64_t)per_cu * ncu;
+  if (resident < 1) return hipErrorInvalidValue;
+  const int64_t want = std::max<int64_t>(1, (max_items + kBlock - 1) / kBlock);
+  *grid = (unsigned)std::min(resident, want);
+  return hipSuccess;
+}
+
+hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
+                                int32_t depth, int64_t max_items, hipStream_t s) {
+  if (depth <= 0) return hipSuccess;
+  if (max_items >= (1ll << 31)) return hipErrorInvalidValue;
+  unsigned grid = 0;
+  hipError_t e = persistent_grid(reinterpret_cast<const void *>(&k_sp_persistent), max_items, &grid);
+  if (e != hipSuccess) return e;
+  GraphView gv = g;
+  SpLevel l = lv;
+  const int32_t *lp = level_ptr;
+  int32_t d = depth;
+  void *args[] = {&gv, &l, &lp, &d};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_sp_persistent), dim3(grid),
+                                    dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
+                                 int32_t depth, int64_t max_items, float *pi_out, hipStream_t s) {
+  max_items = std::max<int64_t>(max_items, (int64_t)g.n_pi * a.C);
+  if (max_items >= (1ll << 31)) return hipErrorInvalidValue;
+  unsigned grid = 0;
+  hipError_t e = persistent_grid(reinterpret_cast<const void *>(&k_bwd_persistent), max_items, &grid);
+  if (e != hipSuccess) return e;
+  GraphView gv = g;
+  BwdArgs ba = a;
+  const int32_t *lp = level_ptr;
+  int32_t d = depth;
+  float *po = pi_out;
+  void *args[] = {&gv, &ba, &lp, &d, &po};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_bwd_persistent), dim3(grid),
+                                    dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t s) {

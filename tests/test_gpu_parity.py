@@ -354,3 +354,30 @@ def test_autotune_keeps_results(ctx):
     b = ev.forward(("sp", "ones", "toggles", "power"))
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("mode,B,ste", [(L.DP_MODELED, 1, False), (L.DP_MODELED, 3, True),
+                                        (L.DP_HYBRID, 2, False)])
+def test_persistent_schedule_is_bitwise_equal(ctx, mode, B, ste):
+    """One cooperative launch per sweep (grid barrier between levels) gives
+    the per-level launches' SP, power and gradients bit for bit."""
+    say(f"persistent mode={mode} B={B} ste={ste}")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 14)
+    p, cap, _ = _inputs(nl, 14, B=B)
+    d = api.Design(ctx, nl)
+    grad = L.DP_BETA_STE if ste else L.DP_BETA_LOCAL
+    res = {}
+    for sched in (L.DP_SCHED_LEVEL, L.DP_SCHED_PERSISTENT):
+        ev = api.Eval(d, B, mode=mode, n_sim=64 * 40, seed=6, beta_grad=grad)
+        ev.set_pi_prob(p)
+        ev.set_caps(cap)
+        ev.set_schedule(sched)
+        out = ev.forward(("sp", "power"))
+        out.update(ev.backward(want=("dpi", "dcap")))
+        res[sched] = out
+    for k in res[L.DP_SCHED_LEVEL]:
+        np.testing.assert_array_equal(res[L.DP_SCHED_LEVEL][k], res[L.DP_SCHED_PERSISTENT][k])
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid" if mode == L.DP_HYBRID else "modeled",
+                           n_words=40, seed=6, ste=ste)
+    assert_grad_close(res[L.DP_SCHED_PERSISTENT]["dpi"][0], adj["dpi"], "persistent dP/dp")
