@@ -259,6 +259,103 @@ def scale_bench(ctx, reps=3):
     return out
 
 
+FORMS_DEFAULT = ("modeled_b1_level", "modeled_b1_graph", "modeled_b1_persistent", "modeled_b64")
+FORMS_EXTRA = ("sizing_sweep", "scale_2m")
+
+
+def modeled_form(args, schedule_name, B):
+    """MODELED forward and forward+backward on the bench design, B query
+    columns, one schedule; % of HBM peak = the level sweeps' algorithmic
+    bytes over the wall time of the pass."""
+    import torch
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    sched = {"level": L.DP_SCHED_LEVEL, "graph": L.DP_SCHED_GRAPH,
+             "persistent": L.DP_SCHED_PERSISTENT, "auto": None}[schedule_name]
+    nl = synth.random_dag(synth.SPECS[args.workload], seed=1)
+    G = nl.n_gates
+    ctx = api.Context.for_torch(0)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, B, mode=L.DP_MODELED)
+    ev.set_pi_prob(torch.from_numpy(synth.pi_probs(nl.n_pi, seed=2 if B == 1 else 4,
+                                                   batch=B)).cuda())
+    ev.set_caps(torch.from_numpy(synth.net_caps(nl.n_nets, seed=3)).cuda())
+    _sync()
+    log(f"[form] modeled B={B} {schedule_name}: design ready")
+    if sched is None:
+        ev.autotune(3, with_backward=True)
+        log(f"[form] autotuned: {ev.get_schedule()}")
+    else:
+        ev.set_schedule(sched)
+    reps = 20 if B == 1 else 10
+
+    def fwd():
+        ev.forward(("power",), device=True)
+
+    def fwdbwd():
+        ev.forward(("power",), device=True)
+        ev.backward(want=("dpi", "dcap"), device=True)
+    tf = time_steps(fwd, reps, 3)
+    log(f"[form] forward {tf * 1e6:.1f} us")
+    tfb = time_steps(fwdbwd, reps, 3)
+    log(f"[form] forward+backward {tfb * 1e6:.1f} us")
+    # one profiled pass of each for the algorithmic bytes (graphs replay the
+    # same launches, so the bytes are the per-level sweep's)
+    ev.profile(True)
+    fwdbwd()
+    pr = ev.get_profile()
+    ev.profile(False)
+    fwd_bytes, bwd_bytes = pr["sp_bytes"], pr["bwd_bytes"]
+    return dict(columns=B, schedule=ev.get_schedule(), fwd_us=tf * 1e6, fwdbwd_us=tfb * 1e6,
+                fwd_gate_evals_s=G * B / tf, fwdbwd_gate_evals_s=G * B / tfb,
+                fwd_bytes=fwd_bytes, bwd_bytes=bwd_bytes,
+                fwd_hbm_frac=fwd_bytes / tf / 1e9 / HBM_PEAK_GBS,
+                fwdbwd_hbm_frac=(fwd_bytes + bwd_bytes) / tfb / 1e9 / HBM_PEAK_GBS)
+
+
+def run_form(name, args):
+    import torch
+    torch.cuda.set_device(0)
+    if name.startswith("modeled_b1_"):
+        return modeled_form(args, name[len("modeled_b1_"):], 1)
+    if name == "modeled_b64":
+        return modeled_form(args, "auto", args.batch)
+    from paper_2608_03778_amd import api
+    ctx = api.Context.for_torch(0)
+    if name == "sizing_sweep":
+        return sizing_bench(ctx)
+    if name == "scale_2m":
+        return scale_bench(ctx)
+    raise SystemExit(f"unknown form {name}")
+
+
+def forms_in_children(names, args):
+    """Each form in a child process of its own (fresh HIP context; a failure
+    in one form is reported and does not end the benchmark)."""
+    import subprocess
+    out = {}
+    for name in names:
+        log(f"[bench] form {name}")
+        cmd = [sys.executable, "-u", os.path.abspath(__file__), "--form", name,
+               "--workload", args.workload, "--batch", str(args.batch)]
+        try:
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
+        except subprocess.TimeoutExpired:
+            out[name] = {"error": "timed out after 600 s"}
+            log(f"[bench] form {name}: timed out")
+            continue
+        lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+        if r.returncode != 0 or not lines:
+            out[name] = {"error": f"child exited with status {r.returncode}"}
+            log(f"[bench] form {name}: child exited with status {r.returncode}")
+            continue
+        out[name] = json.loads(lines[-1])
+        log(f"[bench] {name}: {lines[-1]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,11 +366,12 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="columns of the batched modeled form")
     ap.add_argument("--cpu-sample-words", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--forms", action="store_true",
-                    help="also time the extra forms (modeled single query and batched, sizing "
-                         "sweep, 2M scale); off by default while a host-side crash in that "
-                         "section is unexplained")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the modeled single-query and batched forms")
+    ap.add_argument("--extra-forms", action="store_true",
+                    help="also time the sizing sweep (117K gates, 32 x 256 columns) and the 2M "
+                         "scale design")
+    ap.add_argument("--form", default=None, help=argparse.SUPPRESS)  # child mode
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--pairs-per-lane", type=int, default=0)
     ap.add_argument("--words-per-chunk", type=int, default=0)
@@ -291,6 +389,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding "
                           "of the sweep is a design note, not a measured path"}), flush=True)
         sys.exit(2)
+
+    if args.form:
+        print(json.dumps(run_form(args.form, args)), flush=True)
+        return
 
     import torch
 
@@ -357,44 +459,18 @@ def main():
     log(f"[bench] hybrid fwd+bwd {dt*1e3:.3f} ms/step; fwd {fwd_only*1e3:.3f} ms; "
         f"sim level kernel {sim_gbs:.0f} GB/s over {prof['sim_launches']} launches")
 
-    forms = {}
-    if args.forms and not args.no_forms:
-        evm = api.Eval(d, 1, mode=L.DP_MODELED)
-        evm.set_pi_prob(p_dev)
-        evm.set_caps(cap_dev)
-        for sched, name in ((L.DP_SCHED_LEVEL, "level"), (L.DP_SCHED_GRAPH, "graph"),
-                            (L.DP_SCHED_PERSISTENT, "persistent")):
-            evm.set_schedule(sched)
-            tf = time_steps(lambda: evm.forward(("power",), device=True), 20, 3)
-            tfb = time_steps(lambda: (evm.forward(("power",), device=True),
-                                      evm.backward(want=("dpi", "dcap"), device=True)), 20, 3)
-            forms[f"modeled_b1_{name}"] = dict(fwd_us=tf * 1e6, fwdbwd_us=tfb * 1e6,
-                                               fwd_gate_evals_s=G / tf, fwdbwd_gate_evals_s=G / tfb)
-        B = args.batch
-        evb = api.Eval(d, B, mode=L.DP_MODELED)
-        pb = torch.from_numpy(synth.pi_probs(nl.n_pi, seed=4, batch=B)).cuda()
-        evb.set_pi_prob(pb)
-        evb.set_caps(cap_dev)
-        evb.profile(True)
-        tf = time_steps(lambda: evb.forward(("power",), device=True), 10, 2)
-        pf = evb.get_profile()
-        tfb = time_steps(lambda: (evb.forward(("power",), device=True),
-                                  evb.backward(want=("dpi", "dcap"), device=True)), 10, 2)
-        pb_ = evb.get_profile()
-        evb.profile(False)
-        fwd_frac = pf["sp_bytes"] / (pf["sp_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS if pf["sp_ms"] else None
-        forms[f"modeled_b{B}"] = dict(
-            fwd_ms=tf * 1e3, fwdbwd_ms=tfb * 1e3, fwd_gate_evals_s=G * B / tf,
-            fwdbwd_gate_evals_s=G * B / tfb, sp_level_hbm_frac=fwd_frac,
-            bwd_level_hbm_frac=(pb_["bwd_bytes"] / (pb_["bwd_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
-                                if pb_["bwd_ms"] else None))
-        forms["hybrid_b1"] = dict(fwd_ms=fwd_only * 1e3, fwdbwd_ms=dt * 1e3,
-                                  fwd_gate_evals_s=G / fwd_only, fwdbwd_gate_evals_s=G / dt,
-                                  sim_gate_word_evals_s=G * T / fwd_only)
-        forms["sizing_sweep"] = sizing_bench(ctx)
-        forms["scale_2m"] = scale_bench(ctx)
-        for k, v in forms.items():
-            log(f"[bench] {k}: {json.dumps(v)}")
+    forms = {"hybrid_b1": dict(fwd_ms=fwd_only * 1e3, fwdbwd_ms=dt * 1e3,
+                               fwd_gate_evals_s=G / fwd_only, fwdbwd_gate_evals_s=G / dt,
+                               sim_gate_word_evals_s=G * T / fwd_only,
+                               fwd_hbm_frac=prof["sim_bytes"] / args.steps / fwd_only / 1e9
+                               / HBM_PEAK_GBS,
+                               fwdbwd_hbm_frac=(prof["sim_bytes"] + prof["bwd_bytes"]) / args.steps
+                               / dt / 1e9 / HBM_PEAK_GBS)}
+    names = () if args.no_forms else FORMS_DEFAULT
+    if args.extra_forms:
+        names = names + FORMS_EXTRA
+    if names:
+        forms.update(forms_in_children(names, args))
 
     serving = None
     if not args.no_serving:

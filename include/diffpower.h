@@ -85,10 +85,13 @@ enum {
 enum {
   DP_SCHED_AUTO = 0,      /* the autotuned choice (default) */
   DP_SCHED_LEVEL = 1,     /* one launch per level */
-  DP_SCHED_GRAPH = 2,     /* the same launches captured once into a HIP graph */
+  DP_SCHED_GRAPH = 2,     /* the same launches captured once into a HIP graph
+                             (forward sweeps of at most 1024 launches; a
+                             larger one returns DP_E_UNSUPPORTED) */
   DP_SCHED_PERSISTENT = 3 /* SP-only sweeps (modeled forward, reverse sweep) as
                              one cooperative launch with a grid barrier per
-                             level; the simulation keeps one launch per level */
+                             level; the simulation keeps one launch per level.
+                             Opt-in: the autotuner does not pick it */
 };
 
 typedef struct dp_ctx dp_ctx;
@@ -164,11 +167,14 @@ const char *dp_last_error(void);
 const char *dp_version(void);
 
 /* --- context ----------------------------------------------------------- */
-/* Bind to GPU `device`; work is enqueued on `hip_stream` (a hipStream_t,
- * NULL = the library creates and owns a stream).  Errors: DP_E_INVALID (no
- * such device), DP_E_HIP. */
+/* Bind to GPU `device`; work is enqueued on `hip_stream` (a hipStream_t;
+ * NULL = the library creates and owns a non-blocking stream;
+ * hipStreamLegacy = the device's null stream, e.g. the one torch uses by
+ * default).  Graphs are captured on a private stream and launched on this
+ * one, so any of these may be used with DP_SCHED_GRAPH.  Errors:
+ * DP_E_INVALID (no such device), DP_E_HIP. */
 dp_status dp_ctx_create(int32_t device, void *hip_stream, dp_ctx **out);
-/* Switch the stream later calls enqueue on (NULL = the owned stream). */
+/* Switch the stream later calls enqueue on (same meanings as above). */
 dp_status dp_ctx_set_stream(dp_ctx *ctx, void *hip_stream);
 /* Block until the context's stream is idle. */
 dp_status dp_ctx_synchronize(dp_ctx *ctx);
@@ -246,8 +252,9 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule,
 /* Autotuner: time the forward sweep, followed by the reverse sweep when
  * with_backward is nonzero (one warm-up and `reps` timed runs with HIP
  * events on the context's stream), for every schedule candidate --
- * per-level launches, a captured HIP graph or persistent SP-only sweeps;
- * 1/2/4/8 word pairs per lane; the whole run or 2 or 4 word chunks; 1/2/4
+ * per-level launches or a captured HIP graph (the persistent schedule is
+ * opt-in only, through dp_eval_set_schedule); 1/2/4/8 word pairs per lane;
+ * the whole run or 2 or 4 word chunks; 1/2/4
  * simulation streams -- and keep the fastest.  Needs the inputs set;
  * overwrites the eval's results.  best_ms (may be NULL) receives the
  * winner's time. */

@@ -34,6 +34,9 @@ def _in_ptr(x, dtype):
     return a.ctypes.data_as(ctypes.c_void_p), 0, a
 
 
+HIP_STREAM_LEGACY = 1  # hipStreamLegacy: the device's null stream
+
+
 class Context:
     """A GPU and the stream library calls enqueue on."""
 
@@ -47,9 +50,12 @@ class Context:
 
     @classmethod
     def for_torch(cls, device: int = 0):
+        """Enqueue on torch's current stream, so library calls are ordered
+        with torch's work on the tensors they read and write."""
         import torch
         torch.cuda.set_device(device)
-        return cls(device, torch.cuda.current_stream(device).cuda_stream)
+        h = torch.cuda.current_stream(device).cuda_stream
+        return cls(device, h if h else HIP_STREAM_LEGACY)
 
     def set_stream(self, stream: Optional[int]):
         check(self.lib.dp_ctx_set_stream(self.handle, ctypes.c_void_p(stream) if stream else None))

@@ -43,6 +43,9 @@ using dp::fail;
 namespace {
 
 constexpr int64_t kAutoWordBudget = 32ll << 30;  // bytes of simulation words in flight
+// Largest forward sweep (kernel launches) captured into one HIP graph.  A graph
+// pays off where a sweep is launch-bound; bigger sweeps run per level.
+constexpr int64_t kMaxGraphLaunches = 1024;
 const char *kVersion = "diffpower-mi355x 0.1 (gfx950)";
 enum { SPAN_SIM = 0, SPAN_SP = 1, SPAN_BWD = 2, SPAN_STIM = 3 };
 
@@ -228,13 +231,45 @@ int32_t pick_iters(const dp_eval *ev, const ChunkPlan &pl) {
 
 bool hybrid(const dp_eval *ev) { return ev->prm.mode == DP_HYBRID; }
 
+// A cooperative launch cannot be enqueued on the null stream; there it runs
+// on a private stream that waits for the caller's stream and that the caller's
+// stream then waits for.  Elsewhere it goes to `s` itself.
+template <class F>
+dp_status on_coop_stream(dp_eval *ev, hipStream_t s, F launch) {
+  if (s) {
+    DP_HIP_TRY(launch(s));
+    return DP_OK;
+  }
+  if (!ev->coop_stream) {
+    DP_HIP_TRY(hipStreamCreateWithFlags(&ev->coop_stream, hipStreamNonBlocking));
+    for (hipEvent_t &e : ev->coop_events) DP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  DP_HIP_TRY(hipEventRecord(ev->coop_events[0], s));
+  DP_HIP_TRY(hipStreamWaitEvent(ev->coop_stream, ev->coop_events[0], 0));
+  DP_HIP_TRY(launch(ev->coop_stream));
+  DP_HIP_TRY(hipEventRecord(ev->coop_events[1], ev->coop_stream));
+  DP_HIP_TRY(hipStreamWaitEvent(s, ev->coop_events[1], 0));
+  return DP_OK;
+}
+
+// Per-net beta of the last forward, or null in modeled mode (beta = 1).
+float *beta_or_null(dp_eval *ev) {
+  return ev->prm.mode == DP_MODELED ? nullptr : ev->beta.as<float>();
+}
+
+// Kernel launches of one forward sweep (what a captured graph would hold).
+int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
+  const int64_t depth = ev->d->depth;
+  if (!pl) return depth + 2;
+  return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4;
+}
+
 // Allocate everything the forward sweep touches (before any capture).
 dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
   const dp_design *d = ev->d;
   const size_t nb = (size_t)d->n_nets * ev->B;
-  DP_TRY(ev->beta.alloc(nb * sizeof(float)));
+  if (ev->prm.mode != DP_MODELED) DP_TRY(ev->beta.alloc(nb * sizeof(float)));
   DP_TRY(ev->xterm.alloc(nb * sizeof(float)));
-  DP_TRY(ev->seed_base.alloc(nb * sizeof(float)));
   const int32_t cols = ev->B * s_prime(ev);
   DP_TRY(ev->power_partial.alloc(
       (size_t)dp::power_partial_doubles(d->n_nets, ev->B, ev->S, ev->paired_sizes) *
@@ -297,8 +332,10 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
     SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth);
     if (ev->schedule == DP_SCHED_PERSISTENT) {
       dp::SpLevel lv{sp, ev->B, 0, 0};
-      DP_HIP_TRY(dp::launch_sp_persistent(g, lv, d->level_dev.as<int32_t>(), d->depth,
-                                          (int64_t)d->max_level_width * ev->B, s));
+      DP_TRY(on_coop_stream(ev, s, [&](hipStream_t cs) {
+        return dp::launch_sp_persistent(g, lv, d->level_dev.as<int32_t>(), d->depth,
+                                        (int64_t)d->max_level_width * ev->B, cs);
+      }));
     } else {
       for (int32_t l = 1; l <= d->depth; ++l) {
         dp::SpLevel lv{sp, ev->B, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l]};
@@ -361,9 +398,8 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   fa.beta_max = (float)ev->prm.beta_max;
   fa.mode = ev->prm.mode;
   fa.ste = ev->prm.beta_grad == DP_BETA_STE;
-  fa.beta = ev->beta.as<float>();
+  fa.beta = beta_or_null(ev);
   fa.xterm = ev->xterm.as<float>();
-  fa.seed_base = ev->seed_base.as<float>();
   fa.n_nets = d->n_nets;
   fa.B = ev->B;
   DP_HIP_TRY(dp::launch_finalize(fa, s));
@@ -413,16 +449,24 @@ struct OutMap {
   }
 };
 
+// Capture the forward sweep into ev->graph_fwd.  The capture runs on a
+// private stream (the caller's stream may be the null stream, which cannot be
+// captured); the graph is then launched on the caller's stream.
 dp_status capture_forward(dp_eval *ev, const ChunkPlan *pl, uint64_t key) {
-  hipStream_t s = ev->stream();
+  if (!ev->capture_stream_owned)
+    DP_HIP_TRY(hipStreamCreateWithFlags(&ev->capture_stream_owned, hipStreamNonBlocking));
   if (ev->graph_fwd) {
+    DP_HIP_TRY(hipStreamSynchronize(ev->stream()));  // no launch of the old graph in flight
     (void)hipGraphExecDestroy(ev->graph_fwd);
     ev->graph_fwd = nullptr;
   }
+  hipStream_t s = ev->capture_stream_owned;
   DP_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   const bool prof = ev->profiling;
   ev->profiling = false;
+  ev->capturing = true;  // stream() is the capture stream meanwhile
   dp_status st = enqueue_forward(ev, pl);
+  ev->capturing = false;
   ev->profiling = prof;
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);
@@ -471,6 +515,13 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
 
 dp_eval::~dp_eval() {
   if (graph_fwd) (void)hipGraphExecDestroy(graph_fwd);
+  if (capture_stream_owned) (void)hipStreamDestroy(capture_stream_owned);
+  if (coop_stream) {
+    (void)hipStreamSynchronize(coop_stream);
+    (void)hipStreamDestroy(coop_stream);
+  }
+  for (auto e : coop_events)
+    if (e) (void)hipEventDestroy(e);
   for (auto e : ev_pool) (void)hipEventDestroy(e);
   for (auto st : lane_streams) {
     (void)hipStreamSynchronize(st);
@@ -507,7 +558,9 @@ dp_status dp_ctx_create(int32_t device, void *hip_stream, dp_ctx **out) {
   DP_HIP_TRY(hipSetDevice(device));
   auto *c = new dp_ctx();
   c->device = device;
-  if (hip_stream) {
+  if (hip_stream == (void *)hipStreamLegacy) {
+    c->stream = nullptr;  // the null stream
+  } else if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
     hipError_t e = hipStreamCreateWithFlags(&c->owned, hipStreamNonBlocking);
@@ -523,6 +576,10 @@ dp_status dp_ctx_create(int32_t device, void *hip_stream, dp_ctx **out) {
 
 dp_status dp_ctx_set_stream(dp_ctx *ctx, void *hip_stream) {
   if (!ctx) return fail(DP_E_INVALID, "dp_ctx_set_stream: NULL ctx");
+  if (hip_stream == (void *)hipStreamLegacy) {
+    ctx->stream = nullptr;  // the null stream
+    return DP_OK;
+  }
   if (!hip_stream && !ctx->owned) {
     DP_HIP_TRY(hipSetDevice(ctx->device));
     DP_HIP_TRY(hipStreamCreateWithFlags(&ctx->owned, hipStreamNonBlocking));
@@ -733,15 +790,11 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward, dou
         if ((int64_t)lanes * ev->d->n_nets * 8 * (k == 0 ? T : chunks[k] + 2) > kAutoWordBudget)
           continue;
         for (int32_t it : {1, 2, 4, 8})
-          for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH, DP_SCHED_PERSISTENT}) {
-            if (sc == DP_SCHED_PERSISTENT && !with_backward) continue;  // same forward as LEVEL
-            cands.push_back({sc, it, chunks[k], lanes});
-          }
+          for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, it, chunks[k], lanes});
       }
     }
   } else {
-    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH, DP_SCHED_PERSISTENT})
-      cands.push_back({sc, 0, 0, 1});
+    for (int32_t sc : {DP_SCHED_LEVEL, DP_SCHED_GRAPH}) cands.push_back({sc, 0, 0, 1});
   }
   DevBuf bwd_out;  // scratch for the timed reverse sweeps
   if (with_backward) DP_TRY(bwd_out.alloc((size_t)ev->B * std::max(ev->d->n_pi, 1) * 4));
@@ -757,6 +810,11 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward, dou
     ev->sim_iters = c.iters;
     ev->words_per_chunk = c.chunk;
     ev->sim_streams = c.lanes;
+    if (c.sched == DP_SCHED_GRAPH) {
+      ChunkPlan cp;
+      if (hybrid(ev)) cp = plan_chunks(ev);
+      if (forward_launches(ev, hybrid(ev) ? &cp : nullptr) > kMaxGraphLaunches) continue;
+    }
     auto once = [&]() -> dp_status {
       dp_status r = dp_forward(ev, nullptr);
       if (r == DP_OK && with_backward)
@@ -842,6 +900,10 @@ dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out) {
   if (hyb) plan = plan_chunks(ev);
   const ChunkPlan *pl = hyb ? &plan : nullptr;
   DP_TRY(ensure_forward_buffers(ev, pl));
+  if (ev->schedule == DP_SCHED_GRAPH && forward_launches(ev, pl) > kMaxGraphLaunches)
+    return fail(DP_E_UNSUPPORTED, "dp_forward: the sweep has " +
+                std::to_string(forward_launches(ev, pl)) + " launches, more than the " +
+                std::to_string(kMaxGraphLaunches) + " a graph may hold; use DP_SCHED_LEVEL");
   const bool use_graph = ev->schedule == DP_SCHED_GRAPH && !ev->profiling;
   if (use_graph) {
     const uint64_t key = graph_key(ev, pl);
@@ -856,7 +918,7 @@ dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out) {
     const int64_t nb = (int64_t)d->n_nets * ev->B;
     dp::ExportArgs ea{};
     ea.sp = ev->sp.as<float>();
-    ea.beta = ev->beta.as<float>();
+    ea.beta = beta_or_null(ev);
     ea.ones = hyb ? ev->ones.as<uint32_t>() : nullptr;
     ea.tog = hyb ? ev->tog.as<uint32_t>() : nullptr;
     ea.int2ext = d->int2ext.as<int32_t>();
@@ -903,30 +965,24 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
   }
   const dp::GraphView g = view(d);
   if (dpi) {
-    DP_TRY(ev->seed.alloc((size_t)d->n_nets * C * sizeof(float)));
     DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * C * sizeof(float), 16)));
-    dp::SeedArgs sa{};
-    sa.seed_base = ev->seed_base.as<float>();
-    sa.w = w;
-    sa.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
-    sa.seed = ev->seed.as<float>();
-    sa.n_pi = d->n_pi;
-    sa.n_nets = d->n_nets;
-    sa.G = d->n_gates;
-    sa.B = ev->B;
-    sa.S = ev->S;
-    sa.per_column = per_column;
-    sa.paired = ev->paired_sizes;
-    DP_HIP_TRY(dp::launch_seed(sa, s));
     dp::BwdArgs ba{};
     ba.sp = ev->sp.as<float>();
-    ba.beta = ev->beta.as<float>();
-    ba.seed = ev->seed.as<float>();
+    ba.beta = beta_or_null(ev);
+    ba.cap = ev->cap.as<float>();
+    ba.w = w;
+    ba.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
     ba.contrib = ev->contrib.as<float>();
+    ba.kappa = (float)kappa_of(ev->prm);
+    ba.n_pi = d->n_pi;
+    ba.G = d->n_gates;
     ba.B = ev->B;
+    ba.S = ev->S;
     ba.C = C;
     ba.cdiv = per_column ? Sp : 1;
     ba.ste = ev->prm.beta_grad == DP_BETA_STE;
+    ba.per_column = per_column;
+    ba.paired = ev->paired_sizes;
     double bwd_bytes = 0.0;
     for (int32_t l = d->depth; l >= 1; --l) bwd_bytes += bwd_level_bytes(d, l, C);
     float *dst = dpi;
@@ -937,8 +993,10 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     }
     if (ev->schedule == DP_SCHED_PERSISTENT) {
       SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
-      DP_HIP_TRY(dp::launch_bwd_persistent(g, ba, d->level_dev.as<int32_t>(), d->depth,
-                                           (int64_t)d->max_level_width * C, dst, s));
+      DP_TRY(on_coop_stream(ev, s, [&](hipStream_t cs) {
+        return dp::launch_bwd_persistent(g, ba, d->level_dev.as<int32_t>(), d->depth,
+                                         (int64_t)d->max_level_width * C, dst, cs);
+      }));
     } else {
       {
         SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
@@ -997,7 +1055,7 @@ namespace dp {
 
 size_t lane_bytes(const dp_design *d, int32_t capacity) {
   const size_t nn = d->n_nets, G = d->n_gates, np = d->n_pi;
-  const size_t per_col = 4 * (6 * nn + (size_t)d->n_edges + 2 * G + 2 * np) +
+  const size_t per_col = 4 * (4 * nn + (size_t)d->n_edges + 2 * G + 2 * np) +
                          8 * (size_t)power_chunks(d->n_nets) + 16;
   return (size_t)capacity * per_col + 8 * nn;
 }
@@ -1024,12 +1082,10 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   A(ev->size, (size_t)capacity * d->n_gates * 4);
   A(ev->size_stage, (size_t)capacity * d->n_gates * 4);
   A(ev->p_stage, (size_t)capacity * d->n_pi * 4);
-  A(ev->beta, nn * capacity * 4);
+  if (prm->mode != DP_MODELED) A(ev->beta, nn * capacity * 4);
   A(ev->xterm, nn * capacity * 4);
-  A(ev->seed_base, nn * capacity * 4);
   A(ev->power_partial, (size_t)power_chunks(d->n_nets) * capacity * 8);
   A(ev->power, (size_t)capacity * 4);
-  A(ev->seed, nn * capacity * 4);
   A(ev->contrib, (size_t)d->n_edges * capacity * 4);
   A(ev->pi_out, (size_t)capacity * d->n_pi * 4);
   if (beta_int) A(ev->beta_frozen, nn * 4);
@@ -1073,26 +1129,21 @@ dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bo
   DP_HIP_TRY(hipMemcpyAsync(power, ev->power.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, s));
   if (backward) {
     const GraphView g = view(d);
-    SeedArgs sa{};
-    sa.seed_base = ev->seed_base.as<float>();
-    sa.size = size ? ev->size.as<float>() : nullptr;
-    sa.seed = ev->seed.as<float>();
-    sa.n_pi = d->n_pi;
-    sa.n_nets = d->n_nets;
-    sa.G = d->n_gates;
-    sa.B = n;
-    sa.S = ev->S;
-    sa.paired = ev->paired_sizes;
-    DP_HIP_TRY(launch_seed(sa, s));
     BwdArgs ba{};
     ba.sp = ev->sp.as<float>();
-    ba.beta = ev->beta.as<float>();
-    ba.seed = ev->seed.as<float>();
+    ba.beta = beta_or_null(ev);
+    ba.cap = ev->cap.as<float>();
+    ba.size = size ? ev->size.as<float>() : nullptr;
     ba.contrib = ev->contrib.as<float>();
+    ba.kappa = (float)kappa_of(ev->prm);
+    ba.n_pi = d->n_pi;
+    ba.G = d->n_gates;
     ba.B = n;
+    ba.S = ev->S;
     ba.C = n;
     ba.cdiv = 1;
     ba.ste = ev->prm.beta_grad == DP_BETA_STE;
+    ba.paired = ev->paired_sizes;
     for (int32_t l = d->depth; l >= 1; --l)
       DP_HIP_TRY(launch_bwd_level(g, ba, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l], s));
     DP_HIP_TRY(launch_bwd_pi(g, ba, ev->pi_out.as<float>(), s));

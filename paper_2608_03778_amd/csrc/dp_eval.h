@@ -33,19 +33,29 @@ struct dp_eval {
   // forward state
   dp::DevBuf words;          // simulation chunk [n_nets][pitch]
   dp::DevBuf ones, tog;      // [n_nets][B]
-  dp::DevBuf beta, xterm, seed_base;  // [n_nets][B]
+  dp::DevBuf beta;           // [n_nets][B] (not in modeled mode)
+  dp::DevBuf xterm;          // [B][n_nets]
   dp::DevBuf power_partial;  // [chunks][B*S'] double
   dp::DevBuf power;          // [B*S']
   dp::DevBuf flag;           // int32 validation flag
   // reverse state
   dp::DevBuf w;              // [B*S'] upstream weights
-  dp::DevBuf seed;           // [n_nets][C]
   dp::DevBuf contrib;        // [3][G][C]
   dp::DevBuf pi_out;         // [C][n_pi] staging for host outputs
   dp::DevBuf stage[8];       // host-output staging
   // A stream of its own (serving lanes); null = the context's stream.
   hipStream_t own_stream = nullptr;
-  hipStream_t stream() const { return own_stream ? own_stream : d->ctx->stream; }
+  // Private stream graphs are captured on, and whether a capture is running.
+  hipStream_t capture_stream_owned = nullptr;
+  // Private stream and fork/join events for cooperative launches when the
+  // caller's stream is the null stream.
+  hipStream_t coop_stream = nullptr;
+  hipEvent_t coop_events[2] = {nullptr, nullptr};
+  bool capturing = false;
+  hipStream_t stream() const {
+    if (capturing) return capture_stream_owned;
+    return own_stream ? own_stream : d->ctx->stream;
+  }
   // Column b uses size vector b (S == B) and power is [B] (serving).
   bool paired_sizes = false;
   // DP_FROZEN_BETA with one beta [n_nets] shared by every column (serving).

@@ -96,9 +96,8 @@ struct FinalizeArgs {
   int64_t T;                // simulated words
   float kappa, beta_min, beta_max;
   int32_t mode, ste;
-  float *beta;              // out [n_nets][B]
-  float *xterm;             // out [n_nets][B] kappa * beta * TR_model
-  float *seed_base;         // out [n_nets][B] local adjoint term without s
+  float *beta;              // out [n_nets][B], or null (modeled: beta = 1)
+  float *xterm;             // out [B][n_nets] kappa * beta * TR_model
   int32_t n_nets, B;
 };
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
@@ -116,7 +115,7 @@ struct ExportArgs {
 };
 hipError_t launch_export(const ExportArgs &a, hipStream_t s);
 
-// Power P[b][s] = sum_n xterm[n][b] * cap[n] * size_s(n), double accumulation
+// Power P[b][s] = sum_n xterm[b][n] * cap[n] * size_s(n), double accumulation
 // in a fixed order.  partial: [n_chunks][B*S'] doubles.
 struct PowerArgs {
   const float *xterm, *cap, *size;  // size: [S][G] internal or null
@@ -131,24 +130,22 @@ int32_t power_chunks(int32_t n_nets);
 int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t paired);
 hipError_t launch_power(const PowerArgs &a, hipStream_t s);
 
-// Reverse sweep.  Columns c in [0, C); the SP column of c is c / cdiv.
+// Reverse sweep.  Columns c in [0, C); the SP column of c is c / cdiv.  The
+// local seed of net n in column c is computed where it is used:
+//   kappa C_n 2 (q - p) * (beta unless STE) * weight(n, c),
+// with weight the upstream weight times the driver's size factor:
+//   per_column: w[c] s_{c mod S'}(n);  paired: w[b] s_b(n);
+//   otherwise (contracted): sum_s w[b][s] s_s(n).
 struct BwdArgs {
   const float *sp;            // [n_nets][B][2]
-  const float *beta;          // [n_nets][B]  (STE only)
-  float *seed;                // [n_nets][C]
+  const float *beta;          // [n_nets][B], or null (beta = 1)
+  const float *cap;           // [n_nets] internal
+  const float *w;             // [B][S'] (null = 1)
+  const float *size;          // [S][G] internal, or null (all 1)
   float *contrib;             // [n_edges][C], in fan-out (reader) order
-  int32_t B, C, cdiv, ste;
+  float kappa;
+  int32_t n_pi, G, B, S, C, cdiv, ste, per_column, paired;
 };
-// seed[n][c] from seed_base, upstream weights w[b][s] and sizes.
-struct SeedArgs {
-  const float *seed_base;     // [n_nets][B]
-  const float *w;             // [B][S'] device (null = 1)
-  const float *size;          // [S][G] internal or null
-  float *seed;                // [n_nets][C]
-  int32_t n_pi, n_nets, G, B, S, per_column;
-  int32_t paired;             // column b uses size row b
-};
-hipError_t launch_seed(const SeedArgs &a, hipStream_t s);
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
                             hipStream_t s);
 // PI adjoints -> out[c][n_pi].
@@ -162,9 +159,9 @@ hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int
 // Reverse levels depth..1 and then the PI adjoints into pi_out[c][n_pi].
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
                                  int32_t depth, int64_t max_items, float *pi_out, hipStream_t s);
-// dcap[ext n] = sum_b xterm[n][b]/cap... computed as kappa*beta*TR * wsum.
+// dcap[ext n] = sum_{b,s} w[b][s] xterm[b][n] size_s(n); dsize likewise.
 struct GradExportArgs {
-  const float *xterm;         // [n_nets][B]
+  const float *xterm;         // [B][n_nets]
   const float *cap;           // [n_nets]
   const float *w;             // [B][S'] or null
   const float *size;          // [S][G] internal or null

@@ -1,9 +1,12 @@
 // gfx950 kernels of the DiffPower hot path.
 //
 // Layouts (internal net numbering, see dp_design):
-//   SP, beta, xterm, seed_base     float  [n_nets][B]      (query column innermost)
-//   seed                           float  [n_nets][C]      (C reverse-sweep columns)
-//   contrib                        float  [3][G][C]        (one slot per fan-in pin)
+//   SP (p, 1 - p pairs)            float2 [n_nets][B]      (query column innermost)
+//   beta                           float  [n_nets][B]      (absent when modeled)
+//   xterm                          float  [B][n_nets]      (net innermost: the power
+//                                                          and gradient reductions
+//                                                          run along nets)
+//   contrib                        float  [n_edges][C]     (fan-out order of the reader)
 //   simulation words W             uint64 [n_nets][pitch]  (one chunk of cycles)
 //   ones, toggles                  uint32 [n_nets][B]
 //
@@ -391,30 +394,45 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
 // Per (net, column): TR_model = 2P(1-P) (Eq. 2); in hybrid mode
 // TR_acc = toggles / (64 (T-1)) (Eq. 4) and beta = clip(TR_acc / TR_model)
 // (Eq. 5, 0/0 -> 1, x/0 -> beta_max); xterm = kappa beta TR_model is the
-// per-unit-capacitance power of the net (Eq. 1); seed_base is the local
-// adjoint term kappa beta C 2(1 - 2P) (without the driver's size factor).
-__global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a) {
-  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= (uint32_t)a.n_nets * (uint32_t)a.B) return;
-  const int32_t n = (int32_t)(idx / (uint32_t)a.B);
-  const f2 pq = reinterpret_cast<const f2 *>(a.sp)[idx];
-  const float tm = 2.0f * pq.x * pq.y;
-  float beta = 1.0f;
-  if (a.mode == 1) {
-    const float ta = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
-    if (tm == 0.0f)
-      beta = (ta == 0.0f) ? 1.0f : a.beta_max;
-    else
-      beta = ta / tm;
-    beta = fminf(fmaxf(beta, a.beta_min), a.beta_max);
-  } else if (a.mode == 2) {
-    beta = a.beta_shared ? a.beta_frozen[n] : a.beta_frozen[idx];
+// per-unit-capacitance power of the net (Eq. 1).
+// A block owns a tile of tn nets x tb columns (tb = min(B, 64), tn * tb <=
+// kFinTile): beta is written in [n][b] order, xterm is staged
+// in LDS and written transposed, [b][n], so both sides stay coalesced.
+constexpr int32_t kFinTile = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a, int32_t tb, int32_t tn) {
+  __shared__ float xt[kFinTile + 64];
+  const int32_t tiles_b = (a.B + tb - 1) / tb;
+  const int32_t n0 = (int32_t)(blockIdx.x / tiles_b) * tn;
+  const int32_t b0 = (int32_t)(blockIdx.x % tiles_b) * tb;
+  const int32_t items = tn * tb;
+  for (int32_t e = threadIdx.x; e < items; e += kBlock) {
+    const int32_t r = e / tb, c = e - r * tb;
+    const int32_t n = n0 + r, b = b0 + c;
+    if (n >= a.n_nets || b >= a.B) continue;
+    const int64_t idx = (int64_t)n * a.B + b;
+    const f2 pq = reinterpret_cast<const f2 *>(a.sp)[idx];
+    const float tm = 2.0f * pq.x * pq.y;
+    float beta = 1.0f;
+    if (a.mode == 1) {
+      const float ta = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
+      if (tm == 0.0f)
+        beta = (ta == 0.0f) ? 1.0f : a.beta_max;
+      else
+        beta = ta / tm;
+      beta = fminf(fmaxf(beta, a.beta_min), a.beta_max);
+    } else if (a.mode == 2) {
+      beta = a.beta_shared ? a.beta_frozen[n] : a.beta_frozen[idx];
+    }
+    if (a.beta) a.beta[idx] = beta;
+    xt[c * (tn + 1) + r] = a.kappa * beta * tm;
   }
-  const float C = a.cap[n];
-  a.beta[idx] = beta;
-  a.xterm[idx] = a.kappa * beta * tm;
-  const float local = a.kappa * C * 2.0f * (pq.y - pq.x);  // d TR_model / dP = 2 (1 - 2P)
-  a.seed_base[idx] = a.ste ? local : beta * local;
+  __syncthreads();
+  for (int32_t e = threadIdx.x; e < items; e += kBlock) {
+    const int32_t c = e / tn, r = e - c * tn;
+    const int32_t n = n0 + r, b = b0 + c;
+    if (n < a.n_nets && b < a.B) a.xterm[(int64_t)b * a.n_nets + n] = xt[c * (tn + 1) + r];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
@@ -426,8 +444,9 @@ __global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
   const float tm = 2.0f * pq.x * pq.y;
   if (a.o_sp) a.o_sp[o] = pq.x;
   if (a.o_tr) a.o_tr[o] = tm;
-  if (a.o_beta) a.o_beta[o] = a.beta[idx];
-  if (a.o_tr_hyb) a.o_tr_hyb[o] = a.beta[idx] * tm;
+  const float beta = a.beta ? a.beta[idx] : 1.0f;
+  if (a.o_beta) a.o_beta[o] = beta;
+  if (a.o_tr_hyb) a.o_tr_hyb[o] = beta * tm;
   if (a.o_sp_acc) a.o_sp_acc[o] = (float)((double)a.ones[idx] / (64.0 * (double)a.T));
   if (a.o_tr_acc) a.o_tr_acc[o] = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
   if (a.o_ones) a.o_ones[o] = a.ones[idx];
@@ -462,12 +481,23 @@ __global__ __launch_bounds__(kBlock) void k_power_partial(PowerArgs a) {
   const int32_t s = a.paired ? b : col - b * Sp;
   const int32_t n_lo = chunk * kPowerChunk;
   const int32_t n_hi = min(n_lo + kPowerChunk, a.n_nets);
+  const float *__restrict__ x = a.xterm + (int64_t)b * a.n_nets;
+  auto term = [&](int32_t n, float xv) {
+    const float sz = (a.size && n >= a.n_pi) ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
+    return (double)xv * (double)(a.cap[n] * sz);
+  };
+  // each thread adds its nets n_lo + t, n_lo + t + 256, ... in that order;
+  // eight loads are issued before their eight adds
   double acc = 0.0;
-  for (int32_t n = n_lo + threadIdx.x; n < n_hi; n += kBlock) {
-    float sz = 1.0f;
-    if (a.size && n >= a.n_pi) sz = a.size[(int64_t)s * a.G + (n - a.n_pi)];
-    acc += (double)a.xterm[(int64_t)n * a.B + b] * (double)(a.cap[n] * sz);
+  int32_t n = n_lo + threadIdx.x;
+  for (; n + 7 * kBlock < n_hi; n += 8 * kBlock) {
+    float xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[n + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += term(n + u * kBlock, xv[u]);
   }
+  for (; n < n_hi; n += kBlock) acc += term(n, x[n]);
   const double r = block_sum_d(acc, lds);
   if (threadIdx.x == 0) a.partial[(int64_t)chunk * n_cols + col] = r;
 }
@@ -499,9 +529,9 @@ __global__ __launch_bounds__(kBlock) void k_power_tiled(PowerArgs a, int32_t n_s
   for (int32_t base = n_lo; base < n_hi; base += kStage) {
     // stage X[n][b0..b0+31] and Y[n][s0..s0+63] for kStage nets
     for (int e = tid; e < kStage * kTileB; e += kBlock) {
-      const int r = e / kTileB, cb = e % kTileB;
+      const int cb = e / kStage, r = e % kStage;  // consecutive lanes walk nets
       const int32_t n = base + r, b = b0 + cb;
-      xs[r][cb] = (n < n_hi && b < a.B) ? a.xterm[(int64_t)n * a.B + b] : 0.0f;
+      xs[r][cb] = (n < n_hi && b < a.B) ? a.xterm[(int64_t)b * a.n_nets + n] : 0.0f;
     }
     for (int e = tid; e < kStage * kTileS; e += kBlock) {
       const int cs = e / kStage, r = e % kStage;  // consecutive lanes walk nets
@@ -544,76 +574,96 @@ __global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_c
 }
 
 // ---------------------------------------------------------------- reverse sweep
-// seed[n][c]: the local adjoint term of net n for reverse column c, scaled by
-// the upstream weight and the driver's size factor.
-__global__ __launch_bounds__(kBlock) void k_seed(SeedArgs a) {
-  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
-  const int32_t C = a.per_column ? a.B * Sp : a.B;
-  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= (uint32_t)a.n_nets * (uint32_t)C) return;
-  const int32_t n = (int32_t)(idx / (uint32_t)C), c = (int32_t)(idx - (uint32_t)n * (uint32_t)C);
+// Local adjoint seed of net n in reverse column c (SP column b): the
+// derivative of the net's own power term, kappa C 2 (1 - 2P) (Eq. 2 and
+// Eq. 7), times beta (unless STE), the upstream weight and the driver's size
+// factor (per column, paired, or summed over the size vectors).
+__device__ __forceinline__ float seed_of(const BwdArgs &a, int32_t n, int32_t c, int32_t b,
+                                         f2 pq, float beta) {
+  const float local = a.kappa * a.cap[n] * 2.0f * (pq.y - pq.x);
+  const float base = a.ste ? local : beta * local;
   const bool gate = n >= a.n_pi && a.size;
-  float v;
+  const int64_t g = (int64_t)(n - a.n_pi);
   if (a.per_column) {
-    const int32_t b = c / Sp, s = c - b * Sp;
+    const int32_t s = c - b * a.cdiv;
     const float w = a.w ? a.w[c] : 1.0f;
-    const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
-    v = a.seed_base[(int64_t)n * a.B + b] * w * sz;
-  } else if (a.paired) {
-    const int32_t b = c;
-    const float w = a.w ? a.w[b] : 1.0f;
-    const float sz = gate ? a.size[(int64_t)b * a.G + (n - a.n_pi)] : 1.0f;
-    v = a.seed_base[(int64_t)n * a.B + b] * (w * sz);
-  } else {
-    const int32_t b = c;
-    float ws = 0.0f;
-    for (int32_t s = 0; s < Sp; ++s) {
-      const float w = a.w ? a.w[(int64_t)b * Sp + s] : 1.0f;
-      const float sz = gate ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
-      ws = fmaf(w, sz, ws);
-    }
-    v = a.seed_base[(int64_t)n * a.B + b] * ws;
+    const float sz = gate ? a.size[(int64_t)s * a.G + g] : 1.0f;
+    return base * w * sz;
   }
-  a.seed[idx] = v;
+  if (a.paired) {
+    const float w = a.w ? a.w[b] : 1.0f;
+    const float sz = gate ? a.size[(int64_t)b * a.G + g] : 1.0f;
+    return base * (w * sz);
+  }
+  const int32_t Sp = a.S > 0 ? a.S : 1;
+  float ws = 0.0f;
+  for (int32_t s = 0; s < Sp; ++s) {
+    const float w = a.w ? a.w[(int64_t)b * Sp + s] : 1.0f;
+    const float sz = gate ? a.size[(int64_t)s * a.G + g] : 1.0f;
+    ws = fmaf(w, sz, ws);
+  }
+  return base * ws;
 }
 
 // Sum of the contributions the readers of a net left for it.  Readers write
 // into the net's own contiguous range [e0, e1) of the contribution buffer
-// (fan-out order), so the sum needs no index indirection; its order is
-// fixed by the graph alone (not by the column, its lane or the batch): nets
-// with at most kLightFanout readers are summed serially by their own lane,
-// four loads in flight; heavier nets by the whole wave, lane l taking
-// entries l, l + 64, ..., then a butterfly reduction.  Every lane of the
-// wave must call this (inactive lanes pass e0 == e1 and active == false).
-constexpr int32_t kLightFanout = 8;
+// (fan-out order), so the sum needs no index indirection.  Its order is fixed
+// by the graph alone (not by the column, its lane or the batch): the range is
+// cut into strands of kStrand consecutive entries, each strand is summed
+// serially, and the strand sums are added in strand order.  Two ways reach
+// that same sum bit for bit:
+//  * lane-serial: a lane walks its own (net, column) strands.  With many
+//    columns the wave's lanes are the columns of one net, so every load is a
+//    contiguous row;
+//  * wave-cooperative, for nets with more than one strand when columns are
+//    few: lane j sums strand j of one (net, column) and the strand sums are
+//    then added in order through lane shuffles.
+// Every lane of the wave must call this (inactive lanes pass e0 == e1 and
+// active == false); `serial` must be uniform across the wave.
+constexpr int32_t kStrand = 8;
+constexpr int32_t kSerialColumns = 32;  // C at which every pull is lane-serial
+
+__device__ __forceinline__ float strand_sum(const float *__restrict__ contrib, int32_t e,
+                                            int32_t e1, int32_t C, int32_t c) {
+  const int32_t m = min(kStrand, e1 - e);
+  float v[kStrand];
+#pragma unroll
+  for (int i = 0; i < kStrand; ++i) v[i] = i < m ? contrib[(int64_t)(e + i) * C + c] : 0.0f;
+  float acc = v[0];
+#pragma unroll
+  for (int i = 1; i < kStrand; ++i)
+    if (i < m) acc += v[i];
+  return acc;
+}
 
 __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int32_t e0,
                                           int32_t e1, int32_t C, int32_t c, bool active,
-                                          int lane) {
+                                          int lane, bool serial) {
   float acc = 0.0f;
-  const bool light = active && (e1 - e0) <= kLightFanout;
-  if (light) {
-    int32_t e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const float v0 = contrib[(int64_t)e * C + c], v1 = contrib[(int64_t)(e + 1) * C + c];
-      const float v2 = contrib[(int64_t)(e + 2) * C + c], v3 = contrib[(int64_t)(e + 3) * C + c];
-      acc += v0;
-      acc += v1;
-      acc += v2;
-      acc += v3;
+  const bool mine = active && (serial || e1 - e0 <= kStrand);
+  if (mine)
+    for (int32_t e = e0; e < e1; e += kStrand) {
+      const float v = strand_sum(contrib, e, e1, C, c);
+      acc = (e == e0) ? v : acc + v;
     }
-    for (; e < e1; ++e) acc += contrib[(int64_t)e * C + c];
-  }
-  uint64_t heavy = __ballot(active && !light);
+  if (serial) return acc;
+  uint64_t heavy = __ballot(active && !mine);
   while (heavy) {
     const int src = __builtin_ctzll(heavy);
     heavy &= heavy - 1;
     const int32_t h0 = __shfl(e0, src), h1 = __shfl(e1, src), hc = __shfl(c, src);
-    float part = 0.0f;
-    for (int32_t e = h0 + lane; e < h1; e += 64) part += contrib[(int64_t)e * C + hc];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if (lane == src) acc = part;
+    const int32_t strands = (h1 - h0 + kStrand - 1) / kStrand;
+    float total = 0.0f;
+    for (int32_t base = 0; base < strands; base += 64) {
+      const int32_t j = base + lane;
+      const float v = j < strands ? strand_sum(contrib, h0 + j * kStrand, h1, C, hc) : 0.0f;
+      const int32_t m = min(64, strands - base);
+      for (int32_t t = 0; t < m; ++t) {
+        const float u = __shfl(v, t);
+        total = (base == 0 && t == 0) ? u : total + u;
+      }
+    }
+    if (lane == src) acc = total;
   }
   return acc;
 }
@@ -649,10 +699,10 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
     x0 = sp[(int64_t)i0 * a.B + b];
     if (k > 1) x1 = sp[(int64_t)i1 * a.B + b];
     if (k > 2) x2 = sp[(int64_t)i2 * a.B + b];
-    seed = a.seed[(int64_t)out * a.C + c];
-    if (a.ste) beta = a.beta[(int64_t)out * a.B + b];
+    if (a.beta) beta = a.beta[(int64_t)out * a.B + b];
+    seed = seed_of(a, out, c, b, sp[(int64_t)out * a.B + b], beta);
   }
-  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane);
+  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
   if (!active) return;
   float lam = seed + pulled;
   if (a.ste) lam *= beta;
@@ -675,10 +725,17 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   const int32_t c = active ? (int32_t)(idx - i * (uint32_t)a.C) : 0;
   const int32_t e0 = active ? g.rev_ptr[i] : 0;
   const int32_t e1 = active ? g.rev_ptr[i + 1] : 0;
-  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane);
+  const int32_t b = c / a.cdiv;
+  float beta = 1.0f, seed = 0.0f;
+  if (active) {
+    if (a.beta) beta = a.beta[(int64_t)i * a.B + b];
+    seed = seed_of(a, (int32_t)i, c, b, reinterpret_cast<const f2 *>(a.sp)[(int64_t)i * a.B + b],
+                   beta);
+  }
+  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
   if (!active) return;
-  float lam = a.seed[idx] + pulled;
-  if (a.ste) lam *= a.beta[(int64_t)i * a.B + c / a.cdiv];
+  float lam = seed + pulled;
+  if (a.ste) lam *= beta;
   out[(int64_t)c * g.n_pi + i] = lam;
 }
 
@@ -734,8 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_cap(GradExportArgs a) {
   if (n >= a.n_nets) return;
   const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const bool gate = n >= a.n_pi && a.size;
-  double acc = 0.0;
-  for (int32_t b = 0; b < a.B; ++b) {
+  auto weight = [&](int32_t b) {
     float ws = 0.0f;
     for (int32_t s = 0; s < Sp; ++s) {
       const int32_t row = a.paired ? b : s;
@@ -743,8 +799,19 @@ __global__ __launch_bounds__(kBlock) void k_grad_cap(GradExportArgs a) {
       const float sz = gate ? a.size[(int64_t)row * a.G + (n - a.n_pi)] : 1.0f;
       ws = fmaf(w, sz, ws);
     }
-    acc += (double)a.xterm[n * a.B + b] * (double)ws;
+    return ws;
+  };
+  // columns in order; eight xterm loads are issued before their adds
+  double acc = 0.0;
+  int32_t b = 0;
+  for (; b + 8 <= a.B; b += 8) {
+    float xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = a.xterm[(int64_t)(b + u) * a.n_nets + n];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)xv[u] * (double)weight(b + u);
   }
+  for (; b < a.B; ++b) acc += (double)a.xterm[(int64_t)b * a.n_nets + n] * (double)weight(b);
   a.dcap[a.int2ext[n]] = (float)acc;
 }
 
@@ -755,11 +822,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_size(GradExportArgs a) {
   const int32_t n = a.n_pi + g;
   double acc = 0.0;
   if (a.paired) {  // size row s belongs to column s only
-    acc = (double)a.xterm[(int64_t)n * a.B + s] * (double)(a.w ? a.w[s] : 1.0f);
+    acc = (double)a.xterm[(int64_t)s * a.n_nets + n] * (double)(a.w ? a.w[s] : 1.0f);
   } else {
     for (int32_t b = 0; b < a.B; ++b) {
       const float w = a.w ? a.w[(int64_t)b * a.S + s] : 1.0f;
-      acc += (double)a.xterm[(int64_t)n * a.B + b] * (double)w;
+      acc += (double)a.xterm[(int64_t)b * a.n_nets + n] * (double)w;
     }
   }
   a.dsize[(int64_t)s * a.G + (a.int2ext[n] - a.n_pi)] = (float)(acc * (double)a.cap[n]);
@@ -884,8 +951,11 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
   const int64_t n = (int64_t)a.n_nets * a.B;
   if (n <= 0) return hipSuccess;
-  if (n >= (1ll << 31)) return hipErrorInvalidValue;
-  k_finalize<<<blocks_for(n), kBlock, 0, s>>>(a);
+  const int32_t tb = std::min<int32_t>(a.B, 64);
+  const int32_t tn = kFinTile / tb;
+  const int64_t blocks = ((int64_t)a.n_nets + tn - 1) / tn * ((a.B + tb - 1) / tb);
+  if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+  k_finalize<<<(unsigned)blocks, kBlock, 0, s>>>(a, tb, tn);
   return hipGetLastError();
 }
 
@@ -933,15 +1003,6 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_seed(const SeedArgs &a, hipStream_t s) {
-  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
-  const int64_t C = a.per_column ? (int64_t)a.B * Sp : a.B;
-  const int64_t n = (int64_t)a.n_nets * C;
-  if (n <= 0) return hipSuccess;
-  if (n >= (1ll << 31)) return hipErrorInvalidValue;
-  k_seed<<<blocks_for(n), kBlock, 0, s>>>(a);
-  return hipGetLastError();
-}
 
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
                             hipStream_t s) {

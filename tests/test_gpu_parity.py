@@ -298,6 +298,17 @@ def test_errors_and_state(ctx):
         ev.backward()
     with pytest.raises(L.DiffPowerError, match="INVALID"):
         api.Eval(d, mode=L.DP_HYBRID, n_sim=100)
+    # a hybrid sweep of 64 columns x 21 launches is more than a graph holds:
+    # refused before any capture, and the autotuner does not offer it
+    big = api.Eval(d, 64, mode=L.DP_HYBRID, n_sim=128)
+    big.set_pi_prob(synth.pi_probs(nl.n_pi, 1, batch=64))
+    big.set_caps(synth.net_caps(nl.n_nets, 1))
+    big.set_schedule(L.DP_SCHED_GRAPH)
+    with pytest.raises(L.DiffPowerError, match="UNSUPPORTED"):
+        big.forward()
+    big.autotune(1)
+    assert big.get_schedule()["schedule"] != L.DP_SCHED_GRAPH
+    big.forward()
 
 
 @pytest.mark.parametrize("B", [1, 3, 70])
@@ -357,7 +368,7 @@ def test_autotune_keeps_results(ctx):
 
 
 @pytest.mark.parametrize("mode,B,ste", [(L.DP_MODELED, 1, False), (L.DP_MODELED, 3, True),
-                                        (L.DP_HYBRID, 2, False)])
+                                        (L.DP_HYBRID, 2, False), (L.DP_MODELED, 40, False)])
 def test_persistent_schedule_is_bitwise_equal(ctx, mode, B, ste):
     """One cooperative launch per sweep (grid barrier between levels) gives
     the per-level launches' SP, power and gradients bit for bit."""
