@@ -259,7 +259,8 @@ def scale_bench(ctx, reps=3):
     return out
 
 
-FORMS_DEFAULT = ("modeled_b1_level", "modeled_b1_graph", "modeled_b1_persistent", "modeled_b64")
+FORMS_DEFAULT = ("modeled_b1_level", "modeled_b1_graph", "modeled_b1_persistent", "modeled_b64",
+                 "design_group")
 FORMS_EXTRA = ("sizing_sweep", "scale_2m")
 
 
@@ -315,6 +316,66 @@ def modeled_form(args, schedule_name, B):
                 fwdbwd_hbm_frac=(fwd_bytes + bwd_bytes) / tfb / 1e9 / HBM_PEAK_GBS)
 
 
+def group_form(args):
+    """Eight designs of uneven size (10K..2M gates), one modeled query each:
+    forward and forward+backward of all eight as one design group (one
+    branch per design) against the same evals run one after another."""
+    import torch
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    ctx = api.Context(0)
+    evs, gates = [], 0
+    for i, name in enumerate(SERVING_DESIGNS):
+        nl = synth.random_dag(synth.SPECS[name], seed=100 + i)
+        d = api.Design(ctx, nl)
+        ev = api.Eval(d, 1, mode=L.DP_MODELED)
+        ev.set_pi_prob(synth.pi_probs(nl.n_pi, seed=300 + i))
+        ev.set_caps(synth.net_caps(nl.n_nets, seed=200 + i))
+        ev.set_schedule(L.DP_SCHED_LEVEL)
+        evs.append(ev)
+        gates += nl.n_gates
+    log(f"[form] group of {len(evs)} designs, {gates} gates")
+    grp = api.Group(ctx, evs)
+
+    def sync():
+        ctx.synchronize()
+        torch.cuda.synchronize()
+
+    def timed(fn, reps=10, warm=2):
+        for _ in range(warm):
+            fn()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        sync()
+        return (time.perf_counter() - t0) / reps
+
+    def seq(bwd):
+        for ev in evs:
+            ev.forward(("power",), device=True)
+            if bwd:
+                ev.backward(want=("dpi",), device=True)
+    t_seq_f = timed(lambda: seq(False))
+    t_grp_f = timed(lambda: grp.run(("power",), device=True))
+    grp.configure(use_graph=False)
+    t_grp_f_direct = timed(lambda: grp.run(("power",), device=True))
+    grp.configure()
+    log(f"[form] forward: one after another {t_seq_f * 1e3:.3f} ms, group {t_grp_f * 1e3:.3f} ms "
+        f"(graph), {t_grp_f_direct * 1e3:.3f} ms (direct)")
+    t_seq_fb = timed(lambda: seq(True))
+    t_grp_fb = timed(lambda: grp.run(("power",), backward=True, device=True))
+    log(f"[form] fwd+bwd: one after another {t_seq_fb * 1e3:.3f} ms, group {t_grp_fb * 1e3:.3f} ms")
+    return dict(designs=list(SERVING_DESIGNS), gates=gates, mode="modeled, one query per design",
+                sequential_fwd_ms=t_seq_f * 1e3, group_fwd_ms=t_grp_f * 1e3,
+                group_fwd_direct_ms=t_grp_f_direct * 1e3,
+                sequential_fwdbwd_ms=t_seq_fb * 1e3, group_fwdbwd_ms=t_grp_fb * 1e3,
+                group_fwd_gate_evals_s=gates / t_grp_f, group_fwdbwd_gate_evals_s=gates / t_grp_fb,
+                speedup_fwd=t_seq_f / t_grp_f, speedup_fwdbwd=t_seq_fb / t_grp_fb)
+
+
 def run_form(name, args):
     import torch
     torch.cuda.set_device(0)
@@ -322,6 +383,8 @@ def run_form(name, args):
         return modeled_form(args, name[len("modeled_b1_"):], 1)
     if name == "modeled_b64":
         return modeled_form(args, "auto", args.batch)
+    if name == "design_group":
+        return group_form(args)
     from paper_2608_03778_amd import api
     ctx = api.Context.for_torch(0)
     if name == "sizing_sweep":
@@ -474,7 +537,9 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = serving_bench(ctx, args.serve_rate, args.serve_warmup, args.serve_seconds,
+        # the server runs on streams of its own; its context is not torch's
+        serving = serving_bench(api.Context(0), args.serve_rate, args.serve_warmup,
+                                args.serve_seconds,
                                 int(args.serve_budget_gb * (1 << 30)), 64, 8)
 
     cpu = None

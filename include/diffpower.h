@@ -288,6 +288,39 @@ typedef struct {
 dp_status dp_eval_profile(dp_eval *ev, int32_t enable);
 dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
 
+/* --- design groups: several designs in one launch ----------------------- */
+/* A group runs several evals -- of any designs of one context, of uneven
+ * sizes -- as one unit (the batched form over designs): their forward sweeps,
+ * and with `backward` their reverse sweeps, are enqueued on up to four branch
+ * streams (the hardware queues a process gets by default; longest sweeps
+ * first, each to the least loaded branch), forked from and joined back into
+ * the context's stream.  Up to 1024 launches in total the whole unit is
+ * captured once into a HIP graph and each run is one graph launch; larger
+ * units are enqueued directly on the same branches.  Results are bitwise
+ * those of dp_forward and dp_backward on each eval alone (per-level
+ * launches, grad_power = 1).
+ *
+ * The group does not own the evals: they must outlive it, and must not be
+ * used elsewhere while a run is in flight.  Every eval's design must belong
+ * to `ctx`; an eval may appear once; serving lanes cannot join.
+ * Errors: DP_E_INVALID, DP_E_HIP, DP_E_OOM. */
+typedef struct dp_group dp_group;
+dp_status dp_group_create(dp_ctx *ctx, dp_eval *const *evals, int32_t n_evals,
+                          dp_group **out);
+/* One run: the forward of every eval and, if backward != 0, its reverse
+ * sweep.  outs: NULL, or n_evals output descriptors (as dp_forward; each
+ * with its own on_device).  dpower_dpi: NULL, or n_evals pointers (each
+ * NULL or [B_i][n_pi_i], host or device as on_device) for dPower/dp.
+ * Errors: DP_E_STATE (an eval's inputs are missing), DP_E_INVALID, DP_E_HIP,
+ * DP_E_OOM. */
+dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
+                       float *const *dpower_dpi, int32_t on_device);
+/* use_graph = 0 never captures (direct enqueue on the branches);
+ * max_branches = 0 is automatic (4), otherwise at most that many branches
+ * (1 = one after another, in one stream).  Errors: DP_E_INVALID. */
+dp_status dp_group_configure(dp_group *g, int32_t use_graph, int32_t max_branches);
+void dp_group_destroy(dp_group *g);
+
 /* --- serving: continuous batching of queries (see dp_server_*) ---------- */
 enum { DP_Q_FWD = 0, DP_Q_FWD_BWD = 1 };
 

@@ -94,6 +94,10 @@ SIGNATURES = {
     "dp_forward": (_st, [_p, _p]),
     "dp_backward": (_st, [_p, _p, _p, _p, _p, _i32]),
     "dp_backward_columns": (_st, [_p, _p, _i32]),
+    "dp_group_create": (_st, [_p, _p, _i32, _p]),
+    "dp_group_run": (_st, [_p, _i32, _p, _p, _i32]),
+    "dp_group_configure": (_st, [_p, _i32, _i32]),
+    "dp_group_destroy": (None, [_p]),
     "dp_eval_set_schedule": (_st, [_p, _i32, _i64, _i32]),
     "dp_eval_autotune": (_st, [_p, _i32, _i32, _p]),
     "dp_eval_set_sim_streams": (_st, [_p, _i32]),

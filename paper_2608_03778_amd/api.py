@@ -274,6 +274,68 @@ class Eval:
             pass
 
 
+class Group:
+    """Several evals (any designs of one context) run as one unit: one
+    branch stream per eval, captured once into a HIP graph when the unit is
+    small enough, one launch per run."""
+
+    def __init__(self, ctx: Context, evals):
+        self.lib = L.load()
+        self.ctx = ctx
+        self.evals = list(evals)
+        arr = (ctypes.c_void_p * len(self.evals))(*[e.handle.value for e in self.evals])
+        h = ctypes.c_void_p()
+        check(self.lib.dp_group_create(ctx.handle, arr, len(self.evals), ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, outputs: Iterable[str] = ("power",), backward: bool = False,
+            device: bool = False):
+        """Forward (and reverse) sweeps of every eval; returns one dict per
+        eval with the requested outputs (and "dpi" when backward)."""
+        n = len(self.evals)
+        outs = (L.FwdOut * n)()
+        res = [dict() for _ in range(n)]
+        for i, ev in enumerate(self.evals):
+            outs[i].on_device = int(bool(device))
+            for name in outputs:
+                if name not in _FWD_FIELDS:
+                    raise ValueError(f"unknown forward output {name!r}")
+                arr = ev._out(name, device)
+                res[i][name] = arr
+                setattr(outs[i], name, arr.data_ptr() if device else arr.ctypes.data)
+        dpi = None
+        if backward:
+            dpi = (ctypes.c_void_p * n)()
+            for i, ev in enumerate(self.evals):
+                shape = (ev.B, ev.design.n_pi)
+                if device:
+                    import torch
+                    arr = torch.empty(shape, dtype=torch.float32,
+                                      device=f"cuda:{self.ctx.device}")
+                    dpi[i] = arr.data_ptr()
+                else:
+                    arr = np.empty(shape, dtype=np.float32)
+                    dpi[i] = arr.ctypes.data
+                res[i]["dpi"] = arr
+        check(self.lib.dp_group_run(self.handle, int(bool(backward)), outs, dpi,
+                                    int(bool(device))))
+        return res
+
+    def configure(self, use_graph: bool = True, max_branches: int = 0):
+        check(self.lib.dp_group_configure(self.handle, int(bool(use_graph)), int(max_branches)))
+
+    def close(self):
+        if self.handle:
+            self.lib.dp_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Continuous-batching query server over device-resident designs."""
 

@@ -2,8 +2,12 @@
 // reverse sweeps.  The serving layer lives in dp_server.cpp.
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 
 #include "dp_eval.h"
 
@@ -320,6 +324,8 @@ double bwd_level_bytes(const dp_design *d, int32_t l, int32_t C) {
 }
 
 // Enqueue the whole forward sweep (no host sync, no allocation).
+dp_status enqueue_forward_tail(dp_eval *ev, const ChunkPlan *pl);
+
 dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   const dp_design *d = ev->d;
   hipStream_t s = ev->stream();
@@ -385,6 +391,14 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
         DP_HIP_TRY(hipStreamWaitEvent(s, ev->lane_events[i], 0));
       }
   }
+  return enqueue_forward_tail(ev, pl);
+}
+
+// Finalize (TR, beta, xterm) and the power reduction of a swept forward.
+dp_status enqueue_forward_tail(dp_eval *ev, const ChunkPlan *pl) {
+  const dp_design *d = ev->d;
+  hipStream_t s = ev->stream();
+  float *sp = ev->sp.as<float>();
   dp::FinalizeArgs fa{};
   fa.sp = sp;
   fa.ones = pl ? ev->ones.as<uint32_t>() : nullptr;
@@ -509,6 +523,93 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
     mix((uint64_t)n_sim_streams(ev));
   }
   return k;
+}
+
+// Copy the last forward's results out (caller numbering), on the eval's
+// stream; host outputs are complete on return.
+dp_status export_forward(dp_eval *ev, const dp_fwd_out *out, const ChunkPlan *pl) {
+  const dp_design *d = ev->d;
+  hipStream_t s = ev->stream();
+  OutMap om{ev, out->on_device};
+  const int64_t nb = (int64_t)d->n_nets * ev->B;
+  dp::ExportArgs ea{};
+  ea.sp = ev->sp.as<float>();
+  ea.beta = beta_or_null(ev);
+  ea.ones = pl ? ev->ones.as<uint32_t>() : nullptr;
+  ea.tog = pl ? ev->tog.as<uint32_t>() : nullptr;
+  ea.int2ext = d->int2ext.as<int32_t>();
+  ea.T = pl ? pl->T : 0;
+  ea.n_nets = d->n_nets;
+  ea.B = ev->B;
+  DP_TRY(om.map(out->sp, nb, &ea.o_sp));
+  DP_TRY(om.map(out->tr, nb, &ea.o_tr));
+  DP_TRY(om.map(out->sp_acc, nb, &ea.o_sp_acc));
+  DP_TRY(om.map(out->tr_acc, nb, &ea.o_tr_acc));
+  DP_TRY(om.map(out->beta, nb, &ea.o_beta));
+  DP_TRY(om.map(out->tr_hyb, nb, &ea.o_tr_hyb));
+  DP_TRY(om.map(out->ones, nb, &ea.o_ones));
+  DP_TRY(om.map(out->toggles, nb, &ea.o_tog));
+  if (ea.o_sp || ea.o_tr || ea.o_sp_acc || ea.o_tr_acc || ea.o_beta || ea.o_tr_hyb || ea.o_ones ||
+      ea.o_tog)
+    DP_HIP_TRY(dp::launch_export(ea, s));
+  if (out->power) {
+    const size_t bytes = (size_t)ev->B * s_prime(ev) * sizeof(float);
+    DP_HIP_TRY(hipMemcpyAsync(out->power, ev->power.ptr, bytes,
+                              out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  }
+  DP_TRY(om.flush(s));
+  if (!out->on_device && out->power) DP_HIP_TRY(hipStreamSynchronize(s));
+  return DP_OK;
+}
+
+// Arguments of the reverse sweep over C columns with upstream weights w
+// (device, or null = 1).
+dp::BwdArgs backward_args(dp_eval *ev, const float *w, int per_column, int32_t C) {
+  const dp_design *d = ev->d;
+  dp::BwdArgs ba{};
+  ba.sp = ev->sp.as<float>();
+  ba.beta = beta_or_null(ev);
+  ba.cap = ev->cap.as<float>();
+  ba.w = w;
+  ba.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
+  ba.contrib = ev->contrib.as<float>();
+  ba.kappa = (float)kappa_of(ev->prm);
+  ba.n_pi = d->n_pi;
+  ba.G = d->n_gates;
+  ba.B = ev->B;
+  ba.S = ev->S;
+  ba.C = C;
+  ba.cdiv = per_column ? s_prime(ev) : 1;
+  ba.ste = ev->prm.beta_grad == DP_BETA_STE;
+  ba.per_column = per_column;
+  ba.paired = ev->paired_sizes;
+  return ba;
+}
+
+// Enqueue the reverse levels and the PI adjoints into dst [C][n_pi] (device)
+// on the eval's stream; no allocation, no host synchronisation.
+dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
+  const dp_design *d = ev->d;
+  hipStream_t s = ev->stream();
+  const dp::GraphView g = view(d);
+  double bwd_bytes = 0.0;
+  for (int32_t l = d->depth; l >= 1; --l) bwd_bytes += bwd_level_bytes(d, l, ba.C);
+  if (ev->schedule == DP_SCHED_PERSISTENT) {
+    SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
+    return on_coop_stream(ev, s, [&](hipStream_t cs) {
+      return dp::launch_bwd_persistent(g, ba, d->level_dev.as<int32_t>(), d->depth,
+                                       (int64_t)d->max_level_width * ba.C, dst, cs);
+    });
+  }
+  {
+    SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
+    for (int32_t l = d->depth; l >= 1; --l) {
+      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+      DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
+    }
+  }
+  DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
+  return DP_OK;
 }
 
 }  // namespace
@@ -913,37 +1014,7 @@ dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out) {
     DP_TRY(enqueue_forward(ev, pl));
   }
   ev->fwd_version = ev->inputs_version;
-  if (out) {
-    OutMap om{ev, out->on_device};
-    const int64_t nb = (int64_t)d->n_nets * ev->B;
-    dp::ExportArgs ea{};
-    ea.sp = ev->sp.as<float>();
-    ea.beta = beta_or_null(ev);
-    ea.ones = hyb ? ev->ones.as<uint32_t>() : nullptr;
-    ea.tog = hyb ? ev->tog.as<uint32_t>() : nullptr;
-    ea.int2ext = d->int2ext.as<int32_t>();
-    ea.T = hyb ? plan.T : 0;
-    ea.n_nets = d->n_nets;
-    ea.B = ev->B;
-    DP_TRY(om.map(out->sp, nb, &ea.o_sp));
-    DP_TRY(om.map(out->tr, nb, &ea.o_tr));
-    DP_TRY(om.map(out->sp_acc, nb, &ea.o_sp_acc));
-    DP_TRY(om.map(out->tr_acc, nb, &ea.o_tr_acc));
-    DP_TRY(om.map(out->beta, nb, &ea.o_beta));
-    DP_TRY(om.map(out->tr_hyb, nb, &ea.o_tr_hyb));
-    DP_TRY(om.map(out->ones, nb, &ea.o_ones));
-    DP_TRY(om.map(out->toggles, nb, &ea.o_tog));
-    if (ea.o_sp || ea.o_tr || ea.o_sp_acc || ea.o_tr_acc || ea.o_beta || ea.o_tr_hyb || ea.o_ones ||
-        ea.o_tog)
-      DP_HIP_TRY(dp::launch_export(ea, s));
-    if (out->power) {
-      const size_t bytes = (size_t)ev->B * s_prime(ev) * sizeof(float);
-      DP_HIP_TRY(hipMemcpyAsync(out->power, ev->power.ptr, bytes,
-                                out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-    }
-    DP_TRY(om.flush(s));
-    if (!out->on_device && out->power) DP_HIP_TRY(hipStreamSynchronize(s));
-  }
+  if (out) DP_TRY(export_forward(ev, out, pl));
   return DP_OK;
 }
 
@@ -963,50 +1034,16 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     DP_TRY(stage_in(ev->w, grad_power, (size_t)cols * sizeof(float), on_device, s));
     w = ev->w.as<float>();
   }
-  const dp::GraphView g = view(d);
   if (dpi) {
     DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * C * sizeof(float), 16)));
-    dp::BwdArgs ba{};
-    ba.sp = ev->sp.as<float>();
-    ba.beta = beta_or_null(ev);
-    ba.cap = ev->cap.as<float>();
-    ba.w = w;
-    ba.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
-    ba.contrib = ev->contrib.as<float>();
-    ba.kappa = (float)kappa_of(ev->prm);
-    ba.n_pi = d->n_pi;
-    ba.G = d->n_gates;
-    ba.B = ev->B;
-    ba.S = ev->S;
-    ba.C = C;
-    ba.cdiv = per_column ? Sp : 1;
-    ba.ste = ev->prm.beta_grad == DP_BETA_STE;
-    ba.per_column = per_column;
-    ba.paired = ev->paired_sizes;
-    double bwd_bytes = 0.0;
-    for (int32_t l = d->depth; l >= 1; --l) bwd_bytes += bwd_level_bytes(d, l, C);
+    const dp::BwdArgs ba = backward_args(ev, w, per_column, C);
     float *dst = dpi;
     const size_t bytes = (size_t)C * d->n_pi * sizeof(float);
     if (!on_device) {
       DP_TRY(ev->pi_out.alloc(std::max<size_t>(bytes, 16)));
       dst = ev->pi_out.as<float>();
     }
-    if (ev->schedule == DP_SCHED_PERSISTENT) {
-      SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
-      DP_TRY(on_coop_stream(ev, s, [&](hipStream_t cs) {
-        return dp::launch_bwd_persistent(g, ba, d->level_dev.as<int32_t>(), d->depth,
-                                         (int64_t)d->max_level_width * C, dst, cs);
-      }));
-    } else {
-      {
-        SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
-        for (int32_t l = d->depth; l >= 1; --l) {
-          const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-          DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
-        }
-      }
-      DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
-    }
+    DP_TRY(enqueue_backward(ev, ba, dst));
     if (!on_device && bytes)
       DP_HIP_TRY(hipMemcpyAsync(dpi, dst, bytes, hipMemcpyDeviceToHost, s));
   }
@@ -1045,6 +1082,417 @@ dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device)
   if (!ev) return fail(DP_E_INVALID, "dp_backward_columns: NULL eval");
   if (!dpower_dpi) return fail(DP_E_INVALID, "dp_backward_columns: NULL output");
   return run_backward(ev, nullptr, 1, dpower_dpi, nullptr, nullptr, on_device);
+}
+
+}  // extern "C"
+
+// =========================================================================
+// Design groups: the sweeps of several evals as one graph launch.
+constexpr int32_t kGroupBranches = 4;  // streams beyond the hardware queues only queue
+
+// Host threads that enqueue a group's branches side by side: a launch-bound
+// sweep is limited by how fast one thread submits kernels, so each branch
+// gets a thread of its own.  Workers live as long as the group.
+struct GroupPool {
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable cv, done;
+  std::function<void(int)> task;
+  uint64_t gen = 0;
+  int n_tasks = 0, pending = 0;
+  bool stop = false;
+
+  void start(int n, int device) {
+    for (int k = 0; k < n; ++k)
+      workers.emplace_back([this, k, device]() {
+        (void)hipSetDevice(device);
+        uint64_t seen = 0;
+        for (;;) {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return stop || gen != seen; });
+          if (stop) return;
+          seen = gen;
+          const bool mine = k < n_tasks;
+          lk.unlock();
+          if (mine) task(k);
+          lk.lock();
+          if (mine && --pending == 0) done.notify_all();
+        }
+      });
+  }
+  // Run f(0) .. f(n - 1) on the workers and wait for all of them.
+  void run(int n, std::function<void(int)> f) {
+    std::unique_lock<std::mutex> lk(mu);
+    task = std::move(f);
+    n_tasks = n;
+    pending = n;
+    ++gen;
+    cv.notify_all();
+    done.wait(lk, [&] { return pending == 0; });
+  }
+  ~GroupPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto &t : workers) t.join();
+  }
+};
+
+struct dp_group {
+  GroupPool pool;
+  // Merged level launches of the group's modeled evals (one launch per level
+  // index covers that level of every such eval): device segment tables and,
+  // per level l, the offset of its first segment, the count and the blocks.
+  std::vector<int32_t> merged;      // eval indices
+  int32_t max_depth = 0;
+  dp::DevBuf fwd_segs, bwd_segs;
+  std::vector<int32_t> f_off, f_cnt, b_off, b_cnt;
+  std::vector<uint32_t> f_blocks, b_blocks;
+  uint64_t tables_key = 0;
+  dp_ctx *ctx = nullptr;
+  std::vector<dp_eval *> evs;
+  std::vector<hipStream_t> branch;  // up to kGroupBranches
+  std::vector<hipEvent_t> join;     // one per branch
+  std::vector<int32_t> branch_of;   // eval -> branch
+  int32_t max_branches = 0;         // 0 = automatic
+  bool use_graph = true;
+  hipEvent_t fork = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t key = 0;
+  ~dp_group() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (auto st : branch) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    for (auto e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (capture) (void)hipStreamDestroy(capture);
+  }
+};
+
+namespace {
+
+// Assign evals to branches: longest first, each to the least loaded branch
+// (load = kernel launches, the cost of a launch-bound sweep).
+void assign_branches(dp_group *g, const std::vector<int64_t> &cost) {
+  const int32_t nb = (int32_t)g->branch.size();
+  std::vector<int32_t> order(g->evs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  std::vector<int64_t> load(nb, 0);
+  g->branch_of.assign(g->evs.size(), 0);
+  for (int32_t i : order) {
+    const int32_t k = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    g->branch_of[i] = k;
+    load[k] += cost[i];
+  }
+}
+
+// Fork from `origin` into the branches, enqueue each eval's forward (and
+// reverse) sweep on its branch with per-level launches, join back.
+// Segment tables of the merged level launches (host work, one upload).
+// Segments start on block boundaries, so a block (and its waves) belongs to
+// one design.
+dp_status build_merged_tables(dp_group *g) {
+  g->max_depth = 0;
+  for (int32_t i : g->merged) g->max_depth = std::max(g->max_depth, g->evs[i]->d->depth);
+  const int32_t D = g->max_depth;
+  std::vector<dp::SpSeg> fs;
+  std::vector<dp::BwdSeg> bs;
+  g->f_off.assign(D + 2, 0);
+  g->f_cnt.assign(D + 2, 0);
+  g->f_blocks.assign(D + 2, 0);
+  g->b_off = g->f_off;
+  g->b_cnt = g->f_cnt;
+  g->b_blocks = g->f_blocks;
+  for (int32_t l = 1; l <= D; ++l) {
+    g->f_off[l] = (int32_t)fs.size();
+    g->b_off[l] = (int32_t)bs.size();
+    uint32_t fb = 0, bb = 0;
+    for (int32_t i : g->merged) {
+      dp_eval *ev = g->evs[i];
+      const dp_design *d = ev->d;
+      if (l > d->depth) continue;
+      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+      if (n == 0) continue;
+      const uint32_t blocks = (uint32_t)(((int64_t)n * ev->B + 255) / 256);
+      fs.push_back({view(d), dp::SpLevel{ev->sp.as<float>(), ev->B, g0, n}, fb});
+      bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, n, bb});
+      fb += blocks;
+      bb += blocks;
+    }
+    g->f_cnt[l] = (int32_t)fs.size() - g->f_off[l];
+    g->b_cnt[l] = (int32_t)bs.size() - g->b_off[l];
+    g->f_blocks[l] = fb;
+    g->b_blocks[l] = bb;
+  }
+  DP_TRY(g->fwd_segs.alloc(std::max<size_t>(fs.size() * sizeof(dp::SpSeg), 16)));
+  DP_TRY(g->bwd_segs.alloc(std::max<size_t>(bs.size() * sizeof(dp::BwdSeg), 16)));
+  if (!fs.empty())
+    DP_HIP_TRY(hipMemcpy(g->fwd_segs.ptr, fs.data(), fs.size() * sizeof(dp::SpSeg),
+                         hipMemcpyHostToDevice));
+  if (!bs.empty())
+    DP_HIP_TRY(hipMemcpy(g->bwd_segs.ptr, bs.data(), bs.size() * sizeof(dp::BwdSeg),
+                         hipMemcpyHostToDevice));
+  return DP_OK;
+}
+
+// The modeled evals as merged level launches on `origin`: SP levels, each
+// eval's finalize and power, and with backward the reverse levels and each
+// eval's PI adjoints.
+dp_status enqueue_merged(dp_group *g, hipStream_t origin, bool backward) {
+  if (g->merged.empty()) return DP_OK;
+  const dp::SpSeg *fs = g->fwd_segs.as<dp::SpSeg>();
+  const dp::BwdSeg *bs = g->bwd_segs.as<dp::BwdSeg>();
+  for (int32_t l = 1; l <= g->max_depth; ++l)
+    DP_HIP_TRY(dp::launch_sp_multi(fs + g->f_off[l], g->f_cnt[l], g->f_blocks[l], origin));
+  for (int32_t i : g->merged) {
+    dp_eval *ev = g->evs[i];
+    ev->branch = origin;
+    const dp_status st = enqueue_forward_tail(ev, nullptr);
+    ev->branch = nullptr;
+    DP_TRY(st);
+  }
+  if (!backward) return DP_OK;
+  for (int32_t l = g->max_depth; l >= 1; --l)
+    DP_HIP_TRY(dp::launch_bwd_multi(bs + g->b_off[l], g->b_cnt[l], g->b_blocks[l], origin));
+  for (int32_t i : g->merged) {
+    dp_eval *ev = g->evs[i];
+    DP_HIP_TRY(dp::launch_bwd_pi(view(ev->d), backward_args(ev, nullptr, 0, ev->B),
+                                 ev->pi_out.as<float>(), origin));
+  }
+  return DP_OK;
+}
+
+// `threads`: enqueue the branches from the group's worker threads, one
+// each (not while capturing: a capture is recorded by one thread).
+dp_status enqueue_group(dp_group *g, hipStream_t origin, bool backward,
+                        const std::vector<ChunkPlan> &plans, bool threads) {
+  DP_HIP_TRY(hipEventRecord(g->fork, origin));
+  for (hipStream_t b : g->branch) DP_HIP_TRY(hipStreamWaitEvent(b, g->fork, 0));
+  std::vector<bool> is_merged(g->evs.size(), false);
+  for (int32_t i : g->merged) is_merged[i] = true;
+  auto branch_task = [&](int32_t k) -> dp_status {
+    for (size_t i = 0; i < g->evs.size(); ++i) {
+      if (g->branch_of[i] != k || is_merged[i]) continue;
+      dp_eval *ev = g->evs[i];
+      const int32_t sched = ev->schedule;
+      const bool prof = ev->profiling;
+      ev->branch = g->branch[k];
+      ev->schedule = DP_SCHED_LEVEL;
+      ev->profiling = false;
+      dp_status st = enqueue_forward(ev, hybrid(ev) ? &plans[i] : nullptr);
+      if (st == DP_OK && backward)
+        st = enqueue_backward(ev, backward_args(ev, nullptr, 0, ev->B), ev->pi_out.as<float>());
+      ev->branch = nullptr;
+      ev->schedule = sched;
+      ev->profiling = prof;
+      if (st != DP_OK) return st;
+    }
+    return DP_OK;
+  };
+  const int32_t nb = (int32_t)g->branch.size();
+  if (threads && nb > 1) {
+    std::vector<dp_status> st(nb, DP_OK);
+    std::vector<std::string> msg(nb);
+    g->pool.run(nb, [&](int k) {
+      st[k] = branch_task(k);
+      if (st[k] != DP_OK) msg[k] = dp_last_error();
+    });
+    for (int32_t k = 0; k < nb; ++k)
+      if (st[k] != DP_OK) return fail(st[k], msg[k]);
+  } else {
+    for (int32_t k = 0; k < nb; ++k) DP_TRY(branch_task(k));
+  }
+  DP_TRY(enqueue_merged(g, origin, backward));
+  for (size_t k = 0; k < g->branch.size(); ++k) {
+    DP_HIP_TRY(hipEventRecord(g->join[k], g->branch[k]));
+    DP_HIP_TRY(hipStreamWaitEvent(origin, g->join[k], 0));
+  }
+  return DP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dp_status dp_group_create(dp_ctx *ctx, dp_eval *const *evals, int32_t n_evals, dp_group **out) {
+  if (!ctx || !evals || !out) return fail(DP_E_INVALID, "dp_group_create: NULL argument");
+  if (n_evals < 1) return fail(DP_E_INVALID, "dp_group_create: need at least one eval");
+  for (int32_t i = 0; i < n_evals; ++i) {
+    if (!evals[i]) return fail(DP_E_INVALID, "dp_group_create: NULL eval");
+    if (evals[i]->d->ctx != ctx)
+      return fail(DP_E_INVALID, "dp_group_create: every eval's design must belong to this context");
+    if (evals[i]->own_stream) return fail(DP_E_INVALID, "dp_group_create: serving lanes cannot join");
+    for (int32_t j = 0; j < i; ++j)
+      if (evals[j] == evals[i]) return fail(DP_E_INVALID, "dp_group_create: an eval appears twice");
+  }
+  DP_HIP_TRY(hipSetDevice(ctx->device));
+  auto *g = new dp_group();
+  g->ctx = ctx;
+  g->evs.assign(evals, evals + n_evals);
+  hipError_t e = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+  for (int32_t i = 0; i < std::min(n_evals, kGroupBranches) && e == hipSuccess; ++i) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) g->branch.push_back(st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) g->join.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    delete g;
+    return fail(DP_E_HIP, std::string("dp_group_create: ") + hipGetErrorString(e));
+  }
+  if (g->branch.size() > 1) g->pool.start((int)g->branch.size(), ctx->device);
+  dp::ctx_retain(ctx);
+  *out = g;
+  return DP_OK;
+}
+
+dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
+                       float *const *dpower_dpi, int32_t on_device) {
+  if (!g) return fail(DP_E_INVALID, "dp_group_run: NULL group");
+  DP_HIP_TRY(hipSetDevice(g->ctx->device));
+  const size_t n = g->evs.size();
+  std::vector<ChunkPlan> plans(n);
+  std::vector<int64_t> cost(n, 0);
+  int64_t launches = 0;
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+  mix((uint64_t)(backward != 0));
+  for (size_t i = 0; i < n; ++i) {
+    dp_eval *ev = g->evs[i];
+    const dp_design *d = ev->d;
+    if (!ev->have_pi || !ev->have_cap || (ev->S > 0 && !ev->have_size) ||
+        (ev->prm.mode == DP_FROZEN_BETA && !ev->have_beta))
+      return fail(DP_E_STATE, "dp_group_run: eval " + std::to_string(i) + " has inputs missing");
+    if (outs && !hybrid(ev) &&
+        (outs[i].sp_acc || outs[i].tr_acc || outs[i].ones || outs[i].toggles))
+      return fail(DP_E_INVALID, "dp_group_run: simulation outputs need DP_HYBRID");
+    if (hybrid(ev) && ev->have_stim &&
+        ev->stim.bytes < (size_t)ev->B * d->n_pi * n_words(ev->prm) * sizeof(uint64_t))
+      return fail(DP_E_STATE, "dp_group_run: an explicit stimulus is too short");
+    if (hybrid(ev)) plans[i] = plan_chunks(ev);
+    DP_TRY(ensure_forward_buffers(ev, hybrid(ev) ? &plans[i] : nullptr));
+    cost[i] = forward_launches(ev, hybrid(ev) ? &plans[i] : nullptr);
+    if (backward) {
+      DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * ev->B * sizeof(float), 16)));
+      DP_TRY(ev->pi_out.alloc(std::max<size_t>((size_t)ev->B * d->n_pi * sizeof(float), 16)));
+      cost[i] += d->depth + 1;
+    }
+    launches += cost[i];
+    const int32_t sched = ev->schedule;
+    ev->schedule = DP_SCHED_LEVEL;
+    mix(graph_key(ev, hybrid(ev) ? &plans[i] : nullptr));
+    ev->schedule = sched;
+    mix((uint64_t)(uintptr_t)ev->contrib.ptr);
+    mix((uint64_t)(uintptr_t)ev->pi_out.ptr);
+    mix((uint64_t)ev->B);
+    mix((uint64_t)(uintptr_t)ev->sp.ptr);
+    mix((uint64_t)(uintptr_t)ev->beta.ptr);
+    mix((uint64_t)(uintptr_t)ev->cap.ptr);
+    mix((uint64_t)(uintptr_t)ev->xterm.ptr);
+  }
+  // modeled evals go into the merged level launches; the others (hybrid)
+  // run on the branches
+  g->merged.clear();
+  for (size_t i = 0; i < n; ++i)
+    if (!hybrid(g->evs[i])) {
+      g->merged.push_back((int32_t)i);
+      launches -= cost[i];
+      cost[i] = 0;
+    }
+  if (!g->merged.empty()) {
+    int32_t D = 0;
+    for (int32_t i : g->merged) D = std::max(D, g->evs[i]->d->depth);
+    launches += D * (backward ? 2 : 1) + (int64_t)g->merged.size() * (backward ? 4 : 3);
+  }
+  const int32_t want = g->max_branches > 0 ? g->max_branches : kGroupBranches;
+  const int32_t nb = std::max<int32_t>(1, std::min<int32_t>({want, (int32_t)g->branch.size(), (int32_t)n}));
+  std::vector<hipStream_t> all = g->branch;
+  g->branch.resize(nb);
+  assign_branches(g, cost);
+  for (size_t i = 0; i < n; ++i) mix((uint64_t)g->branch_of[i]);
+  hipStream_t s = g->ctx->stream;
+  struct Restore {
+    dp_group *g;
+    std::vector<hipStream_t> all;
+    ~Restore() { g->branch = all; }
+  } restore{g, all};
+  if (g->tables_key != key || g->f_off.empty()) {
+    DP_HIP_TRY(hipStreamSynchronize(s));  // no run reads the old tables
+    DP_TRY(build_merged_tables(g));
+    g->tables_key = key;
+  }
+  if (g->use_graph && launches <= kMaxGraphLaunches) {
+    if (!g->exec || g->key != key) {
+      if (g->exec) {
+        DP_HIP_TRY(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(g->exec);
+        g->exec = nullptr;
+      }
+      DP_HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
+      const dp_status st = enqueue_group(g, g->capture, backward != 0, plans, false);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(g->capture, &graph);
+      if (st != DP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return fail(DP_E_HIP, std::string("group capture failed: ") + hipGetErrorString(e));
+      const hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        g->exec = nullptr;
+        return fail(DP_E_HIP, std::string("group instantiate failed: ") + hipGetErrorString(ei));
+      }
+      g->key = key;
+    }
+    DP_HIP_TRY(hipGraphLaunch(g->exec, s));
+  } else {
+    DP_TRY(enqueue_group(g, s, backward != 0, plans, true));
+  }
+  bool host_out = false;
+  for (size_t i = 0; i < n; ++i) {
+    dp_eval *ev = g->evs[i];
+    ev->fwd_version = ev->inputs_version;
+    if (outs) {
+      DP_TRY(export_forward(ev, &outs[i], hybrid(ev) ? &plans[i] : nullptr));
+      host_out = host_out || !outs[i].on_device;
+    }
+    if (backward && dpower_dpi && dpower_dpi[i] && ev->d->n_pi > 0) {
+      DP_HIP_TRY(hipMemcpyAsync(dpower_dpi[i], ev->pi_out.ptr,
+                                (size_t)ev->B * ev->d->n_pi * sizeof(float),
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                ev->stream()));
+      host_out = host_out || !on_device;
+    }
+  }
+  if (host_out) DP_HIP_TRY(hipStreamSynchronize(s));
+  return DP_OK;
+}
+
+dp_status dp_group_configure(dp_group *g, int32_t use_graph, int32_t max_branches) {
+  if (!g) return fail(DP_E_INVALID, "dp_group_configure: NULL group");
+  if (max_branches < 0) return fail(DP_E_INVALID, "dp_group_configure: max_branches < 0");
+  g->use_graph = use_graph != 0;
+  g->max_branches = max_branches;
+  return DP_OK;
+}
+
+void dp_group_destroy(dp_group *g) {
+  if (!g) return;
+  dp_ctx *c = g->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  delete g;
+  dp::ctx_release(c);
 }
 
 }  // extern "C"

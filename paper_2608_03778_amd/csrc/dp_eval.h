@@ -40,7 +40,7 @@ struct dp_eval {
   dp::DevBuf flag;           // int32 validation flag
   // reverse state
   dp::DevBuf w;              // [B*S'] upstream weights
-  dp::DevBuf contrib;        // [3][G][C]
+  dp::DevBuf contrib;        // [n_edges][C]
   dp::DevBuf pi_out;         // [C][n_pi] staging for host outputs
   dp::DevBuf stage[8];       // host-output staging
   // A stream of its own (serving lanes); null = the context's stream.
@@ -52,8 +52,11 @@ struct dp_eval {
   hipStream_t coop_stream = nullptr;
   hipEvent_t coop_events[2] = {nullptr, nullptr};
   bool capturing = false;
+  // Stream of the eval's branch while a design group enqueues it.
+  hipStream_t branch = nullptr;
   hipStream_t stream() const {
     if (capturing) return capture_stream_owned;
+    if (branch) return branch;
     return own_stream ? own_stream : d->ctx->stream;
   }
   // Column b uses size vector b (S == B) and power is [B] (serving).

@@ -151,6 +151,25 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
 // PI adjoints -> out[c][n_pi].
 hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s);
 
+// Several designs in one launch: one level index of every design of a group.
+// Segment k owns the blocks [block0_k, block0_{k+1}) (block0 ascending, the
+// first 0); its items are the (gate, column) pairs of its level range, column
+// innermost, as in the single-design launches.
+struct SpSeg {
+  GraphView g;
+  SpLevel lv;
+  uint32_t block0;
+};
+struct BwdSeg {
+  GraphView g;
+  BwdArgs a;
+  int32_t g0, n;
+  uint32_t block0;
+};
+// segs: device array of n_segs; blocks: total blocks of the launch.
+hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
+hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
+
 // Persistent (cooperative) sweeps: all levels in one launch with a grid
 // barrier between levels.  level_ptr is the device copy of the design's
 // level table; max_items the largest level's item count.

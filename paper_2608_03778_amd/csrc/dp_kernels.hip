@@ -202,6 +202,30 @@ __global__ __launch_bounds__(kBlock) void k_sp_level(GraphView g, SpLevel lv) {
   if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item(g, lv, idx);
 }
 
+// The same for an even column count, two columns per lane: one 16-byte
+// access moves two (p, q) pairs, and half as many waves cover the level.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_sp_level_x2(GraphView g, SpLevel lv) {
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t half = (uint32_t)lv.B / 2;
+  if (idx >= (uint32_t)lv.n * half) return;
+  const uint32_t gl = idx / half;
+  const int32_t b = 2 * (int32_t)(idx - gl * half);
+  const int32_t gi = lv.g0 + (int32_t)gl;
+  const int op = g.op[gi];
+  const int k = arity_of(op);
+  const f4 *sp4 = reinterpret_cast<const f4 *>(lv.sp);
+  const int64_t B2 = lv.B / 2;
+  const f4 z = f4{0.0f, 1.0f, 0.0f, 1.0f};
+  const f4 a = sp4[(int64_t)g.in[gi] * B2 + b / 2];
+  const f4 bb = k > 1 ? sp4[(int64_t)g.in[g.G + gi] * B2 + b / 2] : z;
+  const f4 cc = k > 2 ? sp4[(int64_t)g.in[2 * g.G + gi] * B2 + b / 2] : z;
+  const f2 r0 = settle(sp_rule(op, f2{a.x, a.y}, f2{bb.x, bb.y}, f2{cc.x, cc.y}));
+  const f2 r1 = settle(sp_rule(op, f2{a.z, a.w}, f2{bb.z, bb.w}, f2{cc.z, cc.w}));
+  reinterpret_cast<f4 *>(lv.sp)[(int64_t)(g.n_pi + gi) * B2 + b / 2] = f4{r0.x, r0.y, r1.x, r1.y};
+}
+
 // ---------------------------------------------------------------- simulation
 // Count ones / toggles of one word pair computed by this lane.  `prev` is the
 // word before the pair's first word.
@@ -636,16 +660,37 @@ __device__ __forceinline__ float strand_sum(const float *__restrict__ contrib, i
   return acc;
 }
 
+// The canonical sum by one lane: a single strand directly; longer ranges four
+// strands (32 loads in flight) at a time, their sums folded in strand order.
+__device__ __forceinline__ float serial_pull(const float *__restrict__ contrib, int32_t e0,
+                                             int32_t e1, int32_t C, int32_t c) {
+  if (e1 - e0 <= kStrand) return e1 > e0 ? strand_sum(contrib, e0, e1, C, c) : 0.0f;
+  float acc = 0.0f;
+  for (int32_t e = e0; e < e1; e += 4 * kStrand) {
+    float v[4 * kStrand];
+#pragma unroll
+    for (int i = 0; i < 4 * kStrand; ++i) v[i] = e + i < e1 ? contrib[(int64_t)(e + i) * C + c] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t es = e + q * kStrand;
+      if (es < e1) {
+        float sum = v[q * kStrand];
+#pragma unroll
+        for (int i = 1; i < kStrand; ++i)
+          if (es + i < e1) sum += v[q * kStrand + i];
+        acc = (es == e0) ? sum : acc + sum;
+      }
+    }
+  }
+  return acc;
+}
+
 __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int32_t e0,
                                           int32_t e1, int32_t C, int32_t c, bool active,
                                           int lane, bool serial) {
   float acc = 0.0f;
   const bool mine = active && (serial || e1 - e0 <= kStrand);
-  if (mine)
-    for (int32_t e = e0; e < e1; e += kStrand) {
-      const float v = strand_sum(contrib, e, e1, C, c);
-      acc = (e == e0) ? v : acc + v;
-    }
+  if (mine) acc = serial_pull(contrib, e0, e1, C, c);
   if (serial) return acc;
   uint64_t heavy = __ballot(active && !mine);
   while (heavy) {
@@ -741,6 +786,29 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
 
 __global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
   bwd_pi_item(g, a, out, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------- several designs
+// The segment of this block (uniform over the block: a short scalar scan).
+template <class Seg>
+__device__ __forceinline__ int32_t seg_of(const Seg *__restrict__ segs, int32_t n_segs) {
+  int32_t k = 0;
+  while (k + 1 < n_segs && segs[k + 1].block0 <= blockIdx.x) ++k;
+  return k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sp_multi(const SpSeg *__restrict__ segs,
+                                                     int32_t n_segs) {
+  const SpSeg sg = segs[seg_of(segs, n_segs)];
+  const uint32_t idx = (blockIdx.x - sg.block0) * kBlock + threadIdx.x;
+  if (idx < (uint32_t)sg.lv.n * (uint32_t)sg.lv.B) sp_item(sg.g, sg.lv, idx);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_multi(const BwdSeg *__restrict__ segs,
+                                                      int32_t n_segs) {
+  const BwdSeg sg = segs[seg_of(segs, n_segs)];
+  bwd_item(sg.g, sg.a, sg.g0, sg.n, (blockIdx.x - sg.block0) * kBlock + threadIdx.x,
+           threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------- persistent sweeps
@@ -890,11 +958,26 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
   return hipGetLastError();
 }
 
+hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s) {
+  if (n_segs <= 0 || blocks == 0) return hipSuccess;
+  k_sp_multi<<<blocks, kBlock, 0, s>>>(segs, n_segs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s) {
+  if (n_segs <= 0 || blocks == 0) return hipSuccess;
+  k_bwd_multi<<<blocks, kBlock, 0, s>>>(segs, n_segs);
+  return hipGetLastError();
+}
+
 hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s) {
   const int64_t n = (int64_t)lv.n * lv.B;
   if (n <= 0) return hipSuccess;
   if (n >= (1ll << 31)) return hipErrorInvalidValue;
-  k_sp_level<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
+  if (lv.B % 2 == 0)
+    k_sp_level_x2<<<blocks_for(n / 2), kBlock, 0, s>>>(g, lv);
+  else
+    k_sp_level<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
   return hipGetLastError();
 }
 
