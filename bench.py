@@ -443,6 +443,8 @@ def main():
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-inflight", type=int, default=3,
+                    help="device steps in flight at once (continuous batching)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a 1 GiB device copy (known bytes, "
                          "for scaling FETCH_SIZE/WRITE_SIZE) then the timed steps only")
@@ -540,7 +542,7 @@ def main():
         # the server runs on streams of its own; its context is not torch's
         serving = serving_bench(api.Context(0), args.serve_rate, args.serve_warmup,
                                 args.serve_seconds,
-                                int(args.serve_budget_gb * (1 << 30)), 64, 8)
+                                int(args.serve_budget_gb * (1 << 30)), 64, args.serve_inflight)
 
     cpu = None
     if not args.no_cpu:

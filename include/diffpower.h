@@ -262,7 +262,8 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward,
                            double *best_ms);
 /* Number of streams that simulate independent (query column, word chunk)
  * pieces concurrently, each with its own word buffer (0 = automatic = 1).
- * Counts are integer sums, so results do not depend on it. */
+ * Counts are integer sums, so results do not depend on it.  A captured
+ * graph (DP_SCHED_GRAPH) records its pieces on one stream. */
 dp_status dp_eval_set_sim_streams(dp_eval *ev, int32_t sim_streams);
 /* The schedule in force (as set or as chosen by the autotuner). */
 dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule,
@@ -295,8 +296,9 @@ dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
  * streams (the hardware queues a process gets by default; longest sweeps
  * first, each to the least loaded branch), forked from and joined back into
  * the context's stream.  Up to 1024 launches in total the whole unit is
- * captured once into a HIP graph and each run is one graph launch; larger
- * units are enqueued directly on the same branches.  Results are bitwise
+ * captured once into a HIP graph, recorded on one stream (no branches), and
+ * each run is one graph launch; larger units, and use_graph = 0, are
+ * enqueued directly on the branches.  Results are bitwise
  * those of dp_forward and dp_backward on each eval alone (per-level
  * launches, grad_power = 1).
  *
@@ -336,12 +338,18 @@ typedef struct {
 } dp_query;
 
 /* A server owns a scheduler thread and the device memory of its query
- * slots; `hbm_budget_bytes` bounds the slot memory it may hold at once. */
+ * slots; `hbm_budget_bytes` bounds the slot memory it may hold at once.
+ * The scheduler admits waiting queries into slots of their design and
+ * launches what it admitted in one pass as one device step: the slots of
+ * all designs in the step share one kernel launch per level index (and per
+ * reverse level), so queries that arrive while the device is busy are
+ * batched across designs.  A query's results do not depend on the step it
+ * rides in. */
 dp_status dp_server_create(dp_ctx *ctx, size_t hbm_budget_bytes,
                            dp_server **out);
-/* Batching limits: at most max_batch queries per launched sweep and
- * max_inflight sweeps on the device at once (defaults 64 and 8; 1 and 1
- * serve one query at a time, first come first served). */
+/* Batching limits: at most max_batch queries per device step (over all
+ * its designs) and max_inflight steps on the device at once (defaults 64
+ * and 8; 1 and 1 serve one query at a time, first come first served). */
 dp_status dp_server_configure(dp_server *srv, int32_t max_batch,
                               int32_t max_inflight);
 /* Register a compiled design.  Queries use params->mode (DP_MODELED, or

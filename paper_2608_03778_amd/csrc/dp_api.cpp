@@ -356,7 +356,8 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
     // (column, chunk) pieces are independent: piece j runs on stream j % L
     // with its own word buffer; the SP of each level is fused into piece 0.
     const int32_t n_pieces = ev->B * pl->n_chunks;
-    const int32_t L = std::min<int32_t>(n_sim_streams(ev), n_pieces);
+    // a capture records one stream only (multi-stream captures are off)
+    const int32_t L = ev->capturing ? 1 : std::min<int32_t>(n_sim_streams(ev), n_pieces);
     if (L > 1) {
       DP_HIP_TRY(hipEventRecord(ev->lane_events[0], s));
       for (int32_t i = 1; i < L; ++i)
@@ -912,6 +913,7 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward, dou
     ev->words_per_chunk = c.chunk;
     ev->sim_streams = c.lanes;
     if (c.sched == DP_SCHED_GRAPH) {
+      if (c.lanes > 1) continue;  // a graph is captured on one stream: same as lanes = 1
       ChunkPlan cp;
       if (hybrid(ev)) cp = plan_chunks(ev);
       if (forward_launches(ev, hybrid(ev) ? &cp : nullptr) > kMaxGraphLaunches) continue;
@@ -1270,9 +1272,29 @@ dp_status enqueue_merged(dp_group *g, hipStream_t origin, bool backward) {
 }
 
 // `threads`: enqueue the branches from the group's worker threads, one
-// each (not while capturing: a capture is recorded by one thread).
+// each.  `single`: everything on `origin` itself, no branches (captures
+// record one stream only).
 dp_status enqueue_group(dp_group *g, hipStream_t origin, bool backward,
-                        const std::vector<ChunkPlan> &plans, bool threads) {
+                        const std::vector<ChunkPlan> &plans, bool threads, bool single) {
+  if (single) {
+    for (size_t i = 0; i < g->evs.size(); ++i) {
+      if (std::find(g->merged.begin(), g->merged.end(), (int32_t)i) != g->merged.end()) continue;
+      dp_eval *ev = g->evs[i];
+      const int32_t sched = ev->schedule;
+      const bool prof = ev->profiling;
+      ev->branch = origin;
+      ev->schedule = DP_SCHED_LEVEL;
+      ev->profiling = false;
+      dp_status st = enqueue_forward(ev, &plans[i]);
+      if (st == DP_OK && backward)
+        st = enqueue_backward(ev, backward_args(ev, nullptr, 0, ev->B), ev->pi_out.as<float>());
+      ev->branch = nullptr;
+      ev->schedule = sched;
+      ev->profiling = prof;
+      DP_TRY(st);
+    }
+    return enqueue_merged(g, origin, backward);
+  }
   DP_HIP_TRY(hipEventRecord(g->fork, origin));
   for (hipStream_t b : g->branch) DP_HIP_TRY(hipStreamWaitEvent(b, g->fork, 0));
   std::vector<bool> is_merged(g->evs.size(), false);
@@ -1439,7 +1461,7 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
         g->exec = nullptr;
       }
       DP_HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
-      const dp_status st = enqueue_group(g, g->capture, backward != 0, plans, false);
+      const dp_status st = enqueue_group(g, g->capture, backward != 0, plans, false, true);
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(g->capture, &graph);
       if (st != DP_OK) {
@@ -1457,7 +1479,7 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
     }
     DP_HIP_TRY(hipGraphLaunch(g->exec, s));
   } else {
-    DP_TRY(enqueue_group(g, s, backward != 0, plans, true));
+    DP_TRY(enqueue_group(g, s, backward != 0, plans, true, false));
   }
   bool host_out = false;
   for (size_t i = 0; i < n; ++i) {
@@ -1597,6 +1619,106 @@ dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bo
     DP_HIP_TRY(launch_bwd_pi(g, ba, ev->pi_out.as<float>(), s));
     if (dpi && d->n_pi > 0)
       DP_HIP_TRY(hipMemcpyAsync(dpi, ev->pi_out.ptr, (size_t)n * d->n_pi * 4,
+                                hipMemcpyDeviceToHost, s));
+  }
+  return DP_OK;
+}
+
+StepScratch::~StepScratch() {
+  if (host) (void)hipHostFree(host);
+}
+
+namespace {
+
+// Stage one lane's inputs on `s` (the first half of lane_run).
+dp_status lane_stage(dp_eval *ev, int32_t n, const float *p, const float *size, hipStream_t s) {
+  const dp_design *d = ev->d;
+  ev->B = n;
+  ev->S = size ? n : 0;
+  ev->paired_sizes = size != nullptr;
+  if (d->n_pi > 0) {
+    DP_HIP_TRY(hipMemcpyAsync(ev->p_stage.ptr, p, (size_t)n * d->n_pi * 4, hipMemcpyHostToDevice, s));
+    DP_HIP_TRY(launch_load_pi(ev->p_stage.as<float>(), ev->sp.as<float>(), d->n_pi, n, s));
+  }
+  if (size && d->n_gates > 0) {
+    DP_HIP_TRY(hipMemcpyAsync(ev->size_stage.ptr, size, (size_t)n * d->n_gates * 4,
+                              hipMemcpyHostToDevice, s));
+    DP_HIP_TRY(launch_import_sizes(ev->size_stage.as<float>(), d->int2ext.as<int32_t>(),
+                                   ev->size.as<float>(), d->n_pi, d->n_gates, n, s));
+  }
+  return DP_OK;
+}
+
+}  // namespace
+
+dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t s,
+                           StepScratch *sc) {
+  int32_t D = 0;
+  for (int32_t j = 0; j < n_jobs; ++j) {
+    DP_TRY(lane_stage(jobs[j].ev, jobs[j].n, jobs[j].p, jobs[j].size, s));
+    D = std::max(D, jobs[j].ev->d->depth);
+  }
+  // segment tables: forward over every lane, reverse over the lanes that
+  // want gradients; level l's segments are contiguous
+  std::vector<SpSeg> fs;
+  std::vector<BwdSeg> bs;
+  std::vector<int32_t> f_off(D + 2, 0), f_cnt(D + 2, 0), b_off(D + 2, 0), b_cnt(D + 2, 0);
+  std::vector<uint32_t> f_blk(D + 2, 0), b_blk(D + 2, 0);
+  for (int32_t l = 1; l <= D; ++l) {
+    f_off[l] = (int32_t)fs.size();
+    b_off[l] = (int32_t)bs.size();
+    for (int32_t j = 0; j < n_jobs; ++j) {
+      dp_eval *ev = jobs[j].ev;
+      const dp_design *d = ev->d;
+      if (l > d->depth) continue;
+      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+      if (n == 0) continue;
+      const uint32_t blocks = (uint32_t)(((int64_t)n * ev->B + 255) / 256);
+      fs.push_back({view(d), SpLevel{ev->sp.as<float>(), ev->B, g0, n}, f_blk[l]});
+      f_blk[l] += blocks;
+      if (jobs[j].backward) {
+        bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, n, b_blk[l]});
+        b_blk[l] += blocks;
+      }
+    }
+    f_cnt[l] = (int32_t)fs.size() - f_off[l];
+    b_cnt[l] = (int32_t)bs.size() - b_off[l];
+  }
+  const size_t f_bytes = fs.size() * sizeof(SpSeg);
+  const size_t b_offset = (f_bytes + 255) & ~(size_t)255;
+  const size_t bytes = std::max<size_t>(b_offset + bs.size() * sizeof(BwdSeg), 256);
+  if (bytes > sc->cap) {
+    if (sc->host) (void)hipHostFree(sc->host);
+    sc->host = nullptr;
+    sc->cap = 0;
+    DP_HIP_TRY(hipHostMalloc(&sc->host, bytes));
+    DP_TRY(sc->dev.alloc(bytes));
+    sc->cap = bytes;
+  }
+  if (!fs.empty()) std::memcpy(sc->host, fs.data(), f_bytes);
+  if (!bs.empty()) std::memcpy((char *)sc->host + b_offset, bs.data(), bs.size() * sizeof(BwdSeg));
+  DP_HIP_TRY(hipMemcpyAsync(sc->dev.ptr, sc->host, bytes, hipMemcpyHostToDevice, s));
+  const SpSeg *fd = sc->dev.as<SpSeg>();
+  const BwdSeg *bd = reinterpret_cast<const BwdSeg *>((char *)sc->dev.ptr + b_offset);
+  for (int32_t l = 1; l <= D; ++l) DP_HIP_TRY(launch_sp_multi(fd + f_off[l], f_cnt[l], f_blk[l], s));
+  for (int32_t j = 0; j < n_jobs; ++j) {
+    dp_eval *ev = jobs[j].ev;
+    ev->branch = s;
+    const dp_status st = enqueue_forward_tail(ev, nullptr);
+    ev->branch = nullptr;
+    DP_TRY(st);
+    DP_HIP_TRY(hipMemcpyAsync(jobs[j].power, ev->power.ptr, (size_t)jobs[j].n * 4,
+                              hipMemcpyDeviceToHost, s));
+  }
+  if (bs.empty()) return DP_OK;
+  for (int32_t l = D; l >= 1; --l) DP_HIP_TRY(launch_bwd_multi(bd + b_off[l], b_cnt[l], b_blk[l], s));
+  for (int32_t j = 0; j < n_jobs; ++j) {
+    if (!jobs[j].backward) continue;
+    dp_eval *ev = jobs[j].ev;
+    const dp_design *d = ev->d;
+    DP_HIP_TRY(launch_bwd_pi(view(d), backward_args(ev, nullptr, 0, ev->B), ev->pi_out.as<float>(), s));
+    if (jobs[j].dpi && d->n_pi > 0)
+      DP_HIP_TRY(hipMemcpyAsync(jobs[j].dpi, ev->pi_out.ptr, (size_t)jobs[j].n * d->n_pi * 4,
                                 hipMemcpyDeviceToHost, s));
   }
   return DP_OK;

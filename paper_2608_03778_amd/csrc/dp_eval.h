@@ -91,6 +91,32 @@ dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bo
                    float *power, float *dpi);
 // Device bytes a lane of `capacity` columns holds.
 size_t lane_bytes(const dp_design *d, int32_t capacity);
+
+// Scratch of one serving step: the merged launches' segment tables, staged
+// in pinned host memory and copied to the device on the step's stream.  Only
+// touched while the step is idle.
+struct StepScratch {
+  void *host = nullptr;
+  dp::DevBuf dev;
+  size_t cap = 0;
+  ~StepScratch();
+};
+// One lane's share of a step: n columns, inputs p [n][n_pi] and sizes
+// [n][n_gates] (or null) in pinned memory, outputs power [n] and, when
+// backward, dP/dp [n][n_pi] in pinned memory.
+struct LaneJob {
+  dp_eval *ev;
+  int32_t n;
+  const float *p, *size;
+  bool backward;
+  float *power, *dpi;
+};
+// Enqueue one step over several lanes (of any designs) on `stream`: their
+// SP levels as merged launches (one per level index), each lane's finalize
+// and power, then the merged reverse levels of the lanes that want
+// gradients.  Each lane's results equal lane_run's bit for bit.
+dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t stream,
+                           StepScratch *scratch);
 // Hybrid calibration at probability p_all for every PI: beta [n_nets] in
 // internal order into beta_int (device), on the context's stream.
 dp_status calibrate_beta(dp_design *d, const float *cap_ext, const dp_params *prm, float p_all,

@@ -6,10 +6,14 @@
 //   * admits pending queries into idle lanes of their design, oldest first,
 //     as long as the lanes' device memory stays inside the HBM budget
 //     (a lane is an eval of `capacity` columns with its own stream);
-//   * launches each filled lane as one batched sweep (column b = query b),
-//     so lanes of different designs, and several lanes of one design, run
-//     concurrently on the device while new queries keep arriving;
-//   * polls lane completion events, copies results to the queries' buffers
+//   * launches the lanes it filled in one pass as one device step: the lanes
+//     of all designs in the step share one launch per level index (merged
+//     level launches), then each lane's finalize and power, then shared
+//     reverse levels for the lanes that want gradients (column b of a lane
+//     = query b).  Steps run concurrently on their own streams while new
+//     queries keep arriving; under load, queries that waited for a free
+//     step are batched across designs into the next one;
+//   * polls step completion events, copies results to the queries' buffers
 //     and timestamps them.
 // A query's result does not depend on the batch it rides in: every column
 // of a sweep is computed independently and reduced in a fixed order.
@@ -52,11 +56,20 @@ struct Lane {
   dp_eval *ev = nullptr;
   int32_t design = 0, capacity = 0;
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
   bool busy = false;
   std::vector<Request *> batch;
   float *pin_p = nullptr, *pin_size = nullptr, *pin_power = nullptr, *pin_dpi = nullptr;
   size_t bytes = 0;
+};
+
+// One device step in flight: its stream, completion event, the merged
+// launches' table scratch and the lanes it carries.
+struct Step {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  dp::StepScratch scratch;
+  std::vector<Lane *> lanes;
+  bool busy = false;
 };
 
 }  // namespace
@@ -71,6 +84,7 @@ struct dp_server {
   std::unordered_map<uint64_t, Request *> reqs;
   std::vector<DesignEntry *> designs;
   std::vector<Lane *> lanes;
+  std::vector<Step *> steps;
   size_t used = 0;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -86,7 +100,6 @@ namespace {
 void destroy_lane(Lane *l) {
   if (l->stream) (void)hipStreamSynchronize(l->stream);
   dp_eval_destroy(l->ev);
-  if (l->done) (void)hipEventDestroy(l->done);
   if (l->stream) (void)hipStreamDestroy(l->stream);
   (void)hipHostFree(l->pin_p);
   (void)hipHostFree(l->pin_size);
@@ -103,7 +116,6 @@ Lane *make_lane(dp_server *s, int32_t design, int32_t cap) {
   l->capacity = cap;
   const dp_design *d = de->d;
   bool ok = hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&l->done, hipEventDisableTiming) == hipSuccess &&
             hipHostMalloc((void **)&l->pin_p, std::max<size_t>((size_t)cap * d->n_pi * 4, 16)) == hipSuccess &&
             hipHostMalloc((void **)&l->pin_size, std::max<size_t>((size_t)cap * d->n_gates * 4, 16)) == hipSuccess &&
             hipHostMalloc((void **)&l->pin_power, (size_t)cap * 4) == hipSuccess &&
@@ -138,7 +150,9 @@ bool make_room(dp_server *s, size_t need, int32_t keep_design) {
   return s->used + need <= s->budget;
 }
 
-void launch_lane(dp_server *s, Lane *l) {
+// Copy a lane's queries into its pinned staging (sizes validated here, off
+// the submitting thread); returns whether any query brought sizes.
+bool stage_lane(dp_server *s, Lane *l) {
   const dp_design *d = s->designs[l->design]->d;
   const int32_t n = (int32_t)l->batch.size();
   bool any_size = false;
@@ -155,7 +169,6 @@ void launch_lane(dp_server *s, Lane *l) {
         std::fill(dst, dst + d->n_gates, 1.0f);
         continue;
       }
-      // copy and validate in one pass (kept off the submitting thread)
       bool ok = true;
       for (int32_t g = 0; g < d->n_gates; ++g) {
         const float v = src[g];
@@ -167,20 +180,47 @@ void launch_lane(dp_server *s, Lane *l) {
         std::fill(dst, dst + d->n_gates, 1.0f);
       }
     }
-  const bool bwd = l->batch[0]->kind == DP_Q_FWD_BWD;
-  dp_status rc = dp::lane_run(l->ev, n, l->pin_p, any_size ? l->pin_size : nullptr, bwd,
-                              l->pin_power, l->pin_dpi);
-  if (rc == DP_OK && hipEventRecord(l->done, l->stream) != hipSuccess) rc = DP_E_HIP;
+  return any_size;
+}
+
+// An idle step, created while fewer than max_inflight exist (caller holds mu).
+Step *idle_step(dp_server *s) {
+  for (Step *st : s->steps)
+    if (!st->busy) return st;
+  if ((int32_t)s->steps.size() >= s->max_inflight) return nullptr;
+  auto *st = new Step();
+  if (hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&st->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (st->stream) (void)hipStreamDestroy(st->stream);
+    delete st;
+    return nullptr;
+  }
+  s->steps.push_back(st);
+  return st;
+}
+
+// Launch the filled lanes as one device step on `st` (caller holds mu).
+void launch_step(dp_server *s, Step *st, const std::vector<Lane *> &ready) {
+  std::vector<dp::LaneJob> jobs;
+  for (Lane *l : ready) {
+    const bool any_size = stage_lane(s, l);
+    jobs.push_back({l->ev, (int32_t)l->batch.size(), l->pin_p, any_size ? l->pin_size : nullptr,
+                    l->batch[0]->kind == DP_Q_FWD_BWD, l->pin_power, l->pin_dpi});
+    l->busy = true;
+  }
+  dp_status rc = dp::lanes_run_merged(jobs.data(), (int32_t)jobs.size(), st->stream, &st->scratch);
+  if (rc == DP_OK && hipEventRecord(st->done, st->stream) != hipSuccess) rc = DP_E_HIP;
   if (rc != DP_OK) s->thread_error = dp_last_error();
-  l->busy = true;
+  st->lanes = ready;
+  st->busy = true;
   if (s->inflight++ == 0) s->busy_since = Clock::now();
   s->st.max_inflight = std::max(s->st.max_inflight, s->inflight);
   s->st.device_steps++;
 }
 
-void finish_lane(dp_server *s, Lane *l) {
+void finish_lane(dp_server *s, Lane *l, Clock::time_point now) {
   const dp_design *d = s->designs[l->design]->d;
-  const auto now = Clock::now();
   for (size_t b = 0; b < l->batch.size(); ++b) {
     Request *r = l->batch[b];
     if (r->out_power) *r->out_power = l->pin_power[b];
@@ -192,13 +232,26 @@ void finish_lane(dp_server *s, Lane *l) {
   }
   l->batch.clear();
   l->busy = false;
+}
+
+void finish_step(dp_server *s, Step *st) {
+  const auto now = Clock::now();
+  for (Lane *l : st->lanes) finish_lane(s, l, now);
+  st->lanes.clear();
+  st->busy = false;
   if (--s->inflight == 0)
     s->st.busy_s += std::chrono::duration<double>(now - s->busy_since).count();
 }
 
-// Admit pending queries into idle lanes, oldest first (caller holds mu).
+// Admit pending queries into idle lanes, oldest first, and launch the lanes
+// filled in this pass as one step (caller holds mu).
 void admit(dp_server *s) {
-  for (size_t i = 0; i < s->pending.size() && s->inflight < s->max_inflight;) {
+  if (s->pending.empty()) return;
+  Step *step = idle_step(s);
+  if (!step) return;  // every step is in flight; queries wait and batch up
+  std::vector<Lane *> ready;
+  int32_t carried = 0;  // queries in this step: at most max_batch
+  for (size_t i = 0; i < s->pending.size() && carried < s->max_batch;) {
     Request *r = s->pending[i];
     Lane *lane = nullptr;
     for (Lane *l : s->lanes)
@@ -228,17 +281,21 @@ void admit(dp_server *s) {
       }
     }
     // fill the lane with same-design, same-kind queries in arrival order
-    for (size_t j = i; j < s->pending.size() && (int32_t)lane->batch.size() < lane->capacity;) {
+    for (size_t j = i; j < s->pending.size() && (int32_t)lane->batch.size() < lane->capacity &&
+                       carried < s->max_batch;) {
       Request *q = s->pending[j];
       if (q->design == r->design && q->kind == r->kind) {
         lane->batch.push_back(q);
         s->pending.erase(s->pending.begin() + j);
+        ++carried;
       } else {
         ++j;
       }
     }
-    launch_lane(s, lane);
+    lane->busy = true;  // taken: not reused or freed while this pass goes on
+    ready.push_back(lane);
   }
+  if (!ready.empty()) launch_step(s, step, ready);
 }
 
 void scheduler(dp_server *s) {
@@ -246,9 +303,9 @@ void scheduler(dp_server *s) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     bool completed = false;
-    for (Lane *l : s->lanes)
-      if (l->busy && hipEventQuery(l->done) == hipSuccess) {
-        finish_lane(s, l);
+    for (Step *st : s->steps)
+      if (st->busy && hipEventQuery(st->done) == hipSuccess) {
+        finish_step(s, st);
         completed = true;
       }
     if (completed) s->cv_done.notify_all();
@@ -429,6 +486,12 @@ void dp_server_destroy(dp_server *s) {
     g_live.erase(std::remove(g_live.begin(), g_live.end(), s), g_live.end());
   }
   stop_thread(s);
+  for (Step *st : s->steps) {
+    (void)hipStreamSynchronize(st->stream);
+    (void)hipEventDestroy(st->done);
+    (void)hipStreamDestroy(st->stream);
+    delete st;
+  }
   for (Lane *l : s->lanes) destroy_lane(l);
   for (DesignEntry *de : s->designs) {
     dp_design *d = de->d;
