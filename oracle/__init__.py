@@ -76,6 +76,10 @@ def _declare(lib):
     lib.orc_power.restype = _d
     lib.orc_adjoint.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _p, _p, _d, _int, _p, _p, _p]
     lib.orc_adjoint.restype = None
+    lib.orc_virus_power.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p]
+    lib.orc_virus_power.restype = _d
+    lib.orc_power_virus.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _i32, _d, _p, _p]
+    lib.orc_power_virus.restype = _d
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -182,6 +186,21 @@ class Netlist:
         return _load().orc_power_complex_step(
             *self._args(), _ptr(_c(p_pi, np.float64)), _ptr(_c(beta, np.float64)),
             _ptr(_c(ceff, np.float64)), float(kappa), int(pi), float(h))
+
+    def virus_power(self, v0, cap) -> float:
+        """P_virus (Eq. 3 at net level) of the vector pair (v0, 1 - v0)."""
+        v = _c(v0, np.uint8)
+        return float(_load().orc_virus_power(*self._args(), _ptr(_c(cap, np.float32)), _ptr(v)))
+
+    def power_virus(self, p0, cap, *, steps=100, eta=0.1, beta=None):
+        """Alg. 4: gradient ascent of the Eq. 9 proxy from p0, then the
+        thresholded pair and its P_virus.  Returns (p_final, v0, p_virus)."""
+        p = np.array(p0, dtype=np.float64, copy=True)
+        v0 = np.zeros(self.n_pi, dtype=np.uint8)
+        pv = _load().orc_power_virus(*self._args(), _ptr(_c(cap, np.float32)),
+                                     _ptr(_c(beta, np.float64)), int(steps), float(eta), _ptr(p),
+                                     _ptr(v0))
+        return p, v0, float(pv)
 
     # -- whole-query compositions -----------------------------------------
     def forward(self, p_pi, cap, size=None, *, hybrid=False, n_words=0, seed=0, pi_words=None,

@@ -19,7 +19,9 @@
  * simulated word t holds cycle t of 64 independent stimulus lanes; the
  * stimulus is i.i.d. Bernoulli(p) per cycle from Philox4x32-10 with an
  * integer threshold; TR_acc is normalised per transition, 64 (T-1); beta's
- * 0/0 is 1 and x/0 is beta_max; the power terms use C_eff = C * s_driver.
+ * 0/0 is 1 and x/0 is beta_max; the power terms use C_eff = C * s_driver;
+ * the power-virus proxy and P_virus sum over nets, since every sink pin
+ * carries its driver's value.
  */
 #include <complex.h>
 #include <math.h>
@@ -481,4 +483,65 @@ void orc_adjoint(int32_t n_pi, int32_t n_gates, const uint8_t *op,
     if (dsize && n >= n_pi) dsize[n - n_pi] = kappa * beta[n] * (double)cap[n] * tm;
   }
   free(acc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Power virus by gradient ascent (Sec. IV-B, Alg. 4).
+ * The startpoint SPs p [n_pi] (in/out) are ascended `steps` times on the
+ * proxy of Eq. 9 at net level (a sink pin carries its driver's value),
+ *   P_proxy = sum_n beta_n * C_n * 2 P_n (1 - P_n),
+ * whose gradient is the adjoint of orc_adjoint with kappa = 1 and the frozen
+ * beta (beta = NULL means 1):  p_i <- clip(p_i + eta * dP_proxy/dp_i, 0, 1).
+ * Then v0_i = [p_i >= 1/2], v1_i = 1 - v0_i, and the transition-weighted
+ * power of Eq. 3 at net level,
+ *   P_virus = sum_n C_n * [value of net n under v0 != value under v1],
+ * is returned (v0 [n_pi] out). */
+double orc_virus_power(int32_t n_pi, int32_t n_gates, const uint8_t *op,
+                       const int32_t *fanin_ptr, const int32_t *fanin,
+                       const int32_t *order, const float *cap, const uint8_t *v0) {
+  int64_t n_nets = (int64_t)n_pi + n_gates;
+  uint64_t *w0 = calloc((size_t)n_nets, sizeof(uint64_t));
+  uint64_t *w1 = calloc((size_t)n_nets, sizeof(uint64_t));
+  for (int32_t i = 0; i < n_pi; ++i) {
+    w0[i] = v0[i] ? ~0ull : 0ull;
+    w1[i] = ~w0[i];
+  }
+  for (int32_t k = 0; k < n_gates; ++k) {
+    int32_t g = order[k];
+    uint64_t a0[3] = {0, 0, 0}, a1[3] = {0, 0, 0};
+    for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e) {
+      a0[e - fanin_ptr[g]] = w0[fanin[e]];
+      a1[e - fanin_ptr[g]] = w1[fanin[e]];
+    }
+    w0[n_pi + g] = bit_rule(op[g], a0);
+    w1[n_pi + g] = bit_rule(op[g], a1);
+  }
+  double total = 0.0;
+  for (int64_t n = 0; n < n_nets; ++n)
+    if ((w0[n] & 1ull) != (w1[n] & 1ull)) total += (double)cap[n];
+  free(w0);
+  free(w1);
+  return total;
+}
+
+double orc_power_virus(int32_t n_pi, int32_t n_gates, const uint8_t *op,
+                       const int32_t *fanin_ptr, const int32_t *fanin,
+                       const int32_t *order, const float *cap, const double *beta,
+                       int32_t steps, double eta, double *p, uint8_t *v0) {
+  int64_t n_nets = (int64_t)n_pi + n_gates;
+  double *P = calloc((size_t)n_nets, sizeof(double));
+  double *b = calloc((size_t)n_nets, sizeof(double));
+  double *lam = calloc((size_t)n_nets, sizeof(double));
+  for (int64_t n = 0; n < n_nets; ++n) b[n] = beta ? beta[n] : 1.0;
+  for (int32_t t = 0; t < steps; ++t) {
+    orc_sp(n_pi, n_gates, op, fanin_ptr, fanin, order, p, P);
+    orc_adjoint(n_pi, n_gates, op, fanin_ptr, fanin, order, P, b, cap, NULL, 1.0, 0, lam,
+                NULL, NULL);
+    for (int32_t i = 0; i < n_pi; ++i) p[i] = clamp01(p[i] + eta * lam[i]);
+  }
+  for (int32_t i = 0; i < n_pi; ++i) v0[i] = p[i] >= 0.5 ? 1 : 0;
+  free(P);
+  free(b);
+  free(lam);
+  return orc_virus_power(n_pi, n_gates, op, fanin_ptr, fanin, order, cap, v0);
 }

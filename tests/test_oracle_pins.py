@@ -440,3 +440,74 @@ def test_sim_ranges_add_up():
     ones2, tog2 = o.sim(T, pi_words=w)
     np.testing.assert_array_equal(ones2, ones)
     np.testing.assert_array_equal(tog2, tog)
+
+
+# ---------------------------------------------------------------- power virus (Alg. 4)
+def _virus_brute(nl, v0, cap):
+    """Eq. 3 at net level by brute force: evaluate every net under v0 and
+    under its complement v1 = 1 - v0 (all assignments enumerated)."""
+    vals = brute.eval_all_minterms(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin)
+    m0 = sum(int(b) << i for i, b in enumerate(v0))
+    m1 = ((1 << nl.n_pi) - 1) ^ m0
+    toggled = vals[:, m0] != vals[:, m1]
+    return float(np.asarray(cap, dtype=np.float64)[toggled].sum())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_virus_power_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    nl = synth.random_dag(synth.DagSpec(n_gates=40, n_pi=8, depth=6), seed)
+    cap = synth.net_caps(nl.n_nets, seed)
+    o = oracle.Netlist.of(nl)
+    for _ in range(5):
+        v0 = rng.integers(0, 2, nl.n_pi).astype(np.uint8)
+        assert o.virus_power(v0, cap) == pytest.approx(_virus_brute(nl, v0, cap), rel=1e-12)
+
+
+def test_virus_power_closed_forms():
+    # a BUF/INV chain toggles everywhere: P_virus = sum of all caps
+    gates = [(synth.INV, [0])] + [(synth.BUF if k % 2 else synth.INV, [k]) for k in range(1, 6)]
+    nl = synth.from_gates(1, gates)
+    cap = synth.net_caps(nl.n_nets, 3)
+    o = oracle.Netlist.of(nl)
+    for v in (0, 1):
+        assert o.virus_power(np.array([v], np.uint8), cap) == pytest.approx(float(cap.sum()))
+    # XOR of two toggling inputs never toggles; AND toggles only from (1, 1)
+    nl = synth.from_gates(2, [(synth.XOR2, [0, 1]), (synth.AND2, [0, 1])])
+    cap = np.array([1.0, 2.0, 4.0, 8.0], np.float32)
+    o = oracle.Netlist.of(nl)
+    assert o.virus_power(np.array([1, 0], np.uint8), cap) == pytest.approx(3.0)
+    assert o.virus_power(np.array([1, 1], np.uint8), cap) == pytest.approx(11.0)
+    assert o.virus_power(np.array([0, 0], np.uint8), cap) == pytest.approx(11.0)
+
+
+def test_virus_ascent_step_is_the_proxy_gradient():
+    """One step moves each unclipped startpoint by eta times the derivative
+    of the Eq. 9 proxy, taken independently by the complex-step method."""
+    nl = synth.random_dag(synth.SPECS["dag2k"], 4)
+    cap = synth.net_caps(nl.n_nets, 4)
+    o = oracle.Netlist.of(nl)
+    rng = np.random.default_rng(4)
+    p0 = rng.uniform(0.2, 0.8, nl.n_pi)
+    beta = rng.uniform(0.5, 2.0, nl.n_nets)
+    eta = 1e-3
+    p1, _, _ = o.power_virus(p0, cap, steps=1, eta=eta, beta=beta)
+    ceff = cap.astype(np.float64)
+    for i in range(0, nl.n_pi, 7):
+        g = o.power_complex_step(p0, beta, ceff, i, kappa=1.0)
+        assert (p1[i] - p0[i]) / eta == pytest.approx(g, rel=1e-9, abs=1e-12)
+
+
+def test_virus_ascent_raises_the_proxy_and_thresholds():
+    nl = synth.random_dag(synth.SPECS["dag2k"], 5)
+    cap = synth.net_caps(nl.n_nets, 5)
+    o = oracle.Netlist.of(nl)
+    proxy = []
+    for steps in range(0, 12, 2):
+        p, v0, pv = o.power_virus(np.full(nl.n_pi, 0.5), cap, steps=steps, eta=1e-3)
+        P = o.sp(p)
+        proxy.append(o.power(P, cap, kappa=1.0)["power"])
+        np.testing.assert_array_equal(v0, (p >= 0.5).astype(np.uint8))
+        assert pv == pytest.approx(o.virus_power(v0, cap))
+        assert ((p >= 0.0) & (p <= 1.0)).all()
+    assert all(b >= a - 1e-9 for a, b in zip(proxy, proxy[1:]))
