@@ -260,7 +260,7 @@ def scale_bench(ctx, reps=3):
 
 
 FORMS_DEFAULT = ("modeled_b1_level", "modeled_b1_graph", "modeled_b1_persistent", "modeled_b64",
-                 "design_group")
+                 "design_group", "power_virus")
 FORMS_EXTRA = ("sizing_sweep", "scale_2m")
 
 
@@ -376,6 +376,49 @@ def group_form(args):
                 speedup_fwd=t_seq_f / t_grp_f, speedup_fwdbwd=t_seq_fb / t_grp_fb)
 
 
+def virus_form(args):
+    """Alg. 4 on the bench design: 100 ascent steps (one modeled forward and
+    reverse sweep each) from p = 1/2, then P_virus of the thresholded pair,
+    against the P_virus of 64 random vector pairs (v1 = 1 - v0)."""
+    import torch
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    nl = synth.random_dag(synth.SPECS[args.workload], seed=1)
+    cap = synth.net_caps(nl.n_nets, seed=3)
+    ctx = api.Context(0)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, 1, mode=L.DP_MODELED)
+    ev.set_caps(cap)
+    # step size: 0.05 over the largest startpoint gradient at p = 1/2
+    ev.set_pi_prob(np.full(nl.n_pi, 0.5, np.float32))
+    ev.forward(("power",))
+    g = ev.backward(want=("dpi",))["dpi"]
+    kappa = 0.5  # energy factor x Vdd^2 x f at the defaults; the proxy is P / kappa
+    eta = 0.05 * kappa / max(float(np.abs(g).max()), 1e-30)
+    log(f"[form] power virus: eta {eta:.3e}")
+    steps = 100
+    ev.set_pi_prob(np.full(nl.n_pi, 0.5, np.float32))
+    ev.power_virus(2, eta)  # warm-up
+    ev.set_pi_prob(np.full(nl.n_pi, 0.5, np.float32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v0, pf, pv = ev.power_virus(steps, eta)
+    dt = time.perf_counter() - t0
+    log(f"[form] power virus: {steps} steps in {dt * 1e3:.1f} ms, P_virus {pv[0]:.1f}")
+    rnd = api.Eval(d, 64, mode=L.DP_MODELED)
+    rnd.set_caps(cap)
+    rnd.set_pi_prob(np.random.default_rng(11).uniform(0, 1, (64, nl.n_pi)).astype(np.float32))
+    _, _, pv_rand = rnd.power_virus(0, 0.0)
+    return dict(design=args.workload, gates=nl.n_gates, steps=steps, eta=eta,
+                ascent_ms=dt * 1e3, ms_per_step=dt * 1e3 / steps,
+                p_virus=float(pv[0]), total_cap=float(cap.astype(np.float64).sum()),
+                random_pairs_mean=float(pv_rand.mean()), random_pairs_max=float(pv_rand.max()),
+                gain_over_random_mean=float(pv[0] / pv_rand.mean()),
+                gain_over_random_max=float(pv[0] / pv_rand.max()))
+
+
 def run_form(name, args):
     import torch
     torch.cuda.set_device(0)
@@ -385,6 +428,8 @@ def run_form(name, args):
         return modeled_form(args, "auto", args.batch)
     if name == "design_group":
         return group_form(args)
+    if name == "power_virus":
+        return virus_form(args)
     from paper_2608_03778_amd import api
     ctx = api.Context.for_torch(0)
     if name == "sizing_sweep":

@@ -240,6 +240,23 @@ dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi,
  * partial derivatives to its S' seeds.  Errors as dp_backward. */
 dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device);
 
+/* Power-virus search by gradient ascent (Sec. IV-B, Alg. 4).  Each of the
+ * eval's B columns is one ascent that starts from its PI probabilities (set
+ * with dp_set_pi_prob; Alg. 4 starts every startpoint at 0.5).  `steps`
+ * times, a forward and a reverse sweep give the gradient of the proxy of
+ * Eq. 9 at net level, P_proxy = sum_n beta_n C_n 2 P_n (1 - P_n) (beta = 1 in
+ * DP_MODELED; the frozen beta in DP_FROZEN_BETA, Alg. 4's optional scaling),
+ * and P <- clip(P + eta * grad, 0, 1).  Then v0 = [P >= 1/2], v1 = 1 - v0,
+ * and P_virus = sum_n C_n [net n differs between v0 and v1] (Eq. 3 at net
+ * level) comes from a two-cycle bit-parallel simulation of the pair.
+ * Outputs (host or device memory as on_device; each may be NULL): v0
+ * [B][n_pi] bytes (0/1), p_final [B][n_pi], p_virus [B] (double).  The
+ * eval's PI probabilities are left at p_final.  Returns after the results
+ * are written.  Needs DP_MODELED or DP_FROZEN_BETA and S = 0.
+ * Errors: DP_E_STATE, DP_E_UNSUPPORTED, DP_E_INVALID, DP_E_HIP, DP_E_OOM. */
+dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0,
+                         float *p_final, double *p_virus, int32_t on_device);
+
 /* Schedule of the level sweeps (DP_SCHED_*), the number of simulated words
  * held on the device at once (0 = automatic; otherwise a multiple of 2 that
  * splits the n_sim/64 words into chunks carrying a two-word halo), and the

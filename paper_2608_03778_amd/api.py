@@ -236,6 +236,17 @@ class Eval:
         check(self.lib.dp_backward_columns(self.handle, ptr, int(bool(device))))
         return arr
 
+    def power_virus(self, steps: int = 100, eta: float = 0.1):
+        """Alg. 4 from the current PI probabilities: returns (v0 [B][n_pi]
+        uint8, p_final [B][n_pi] float32, p_virus [B] float64)."""
+        d = self.design
+        v0 = np.zeros((self.B, d.n_pi), dtype=np.uint8)
+        pf = np.zeros((self.B, d.n_pi), dtype=np.float32)
+        pv = np.zeros(self.B, dtype=np.float64)
+        check(self.lib.dp_power_virus(self.handle, int(steps), float(eta), v0.ctypes.data,
+                                      pf.ctypes.data, pv.ctypes.data, 0))
+        return v0, pf, pv
+
     def autotune(self, reps: int = 3, with_backward: bool = False) -> float:
         """Pick the fastest schedule for the forward (and, with_backward,
         the reverse) sweep; returns its ms."""

@@ -1080,6 +1080,79 @@ dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi, f
   return run_backward(ev, grad_power, 0, dpower_dpi, dpower_dcap, dpower_dsize, on_device);
 }
 
+dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, float *p_final,
+                         double *p_virus, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_power_virus: NULL eval");
+  if (steps < 0 || !std::isfinite(eta))
+    return fail(DP_E_INVALID, "dp_power_virus: need steps >= 0 and a finite eta");
+  if (ev->prm.mode == DP_HYBRID)
+    return fail(DP_E_UNSUPPORTED, "dp_power_virus: the ascent runs DP_MODELED or DP_FROZEN_BETA");
+  if (ev->S > 0) return fail(DP_E_UNSUPPORTED, "dp_power_virus: size vectors are not supported");
+  if (!ev->have_pi) return fail(DP_E_STATE, "dp_power_virus: start probabilities not set");
+  if (!ev->have_cap) return fail(DP_E_STATE, "dp_power_virus: capacitances not set");
+  if (ev->prm.mode == DP_FROZEN_BETA && !ev->have_beta)
+    return fail(DP_E_STATE, "dp_power_virus: DP_FROZEN_BETA needs dp_set_beta");
+  const dp_design *d = ev->d;
+  DP_HIP_TRY(hipSetDevice(d->ctx->device));
+  hipStream_t s = ev->stream();
+  const int32_t B = ev->B;
+  const size_t nb = (size_t)d->n_nets * B, pb = (size_t)d->n_pi * B;
+  DP_TRY(ensure_forward_buffers(ev, nullptr));
+  DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * B * sizeof(float), 16)));
+  DP_TRY(ev->pi_out.alloc(std::max<size_t>(pb * sizeof(float), 16)));
+  // the proxy is the power without kappa: upstream weight 1 / kappa per column
+  DP_TRY(ev->w.alloc(std::max<size_t>((size_t)B * sizeof(float), 16)));
+  DP_HIP_TRY(dp::launch_fill_f32(ev->w.as<float>(), B, (float)(1.0 / kappa_of(ev->prm)), s));
+  const dp::BwdArgs ba = backward_args(ev, ev->w.as<float>(), 0, B);
+  for (int32_t t = 0; t < steps; ++t) {
+    DP_TRY(enqueue_forward(ev, nullptr));
+    DP_TRY(enqueue_backward(ev, ba, ev->pi_out.as<float>()));
+    DP_HIP_TRY(dp::launch_virus_step(ev->sp.as<float>(), ev->pi_out.as<float>(), (float)eta,
+                                     d->n_pi, B, s));
+  }
+  // v0, v1 = 1 - v0 and a two-cycle bit-parallel simulation of the pair
+  DevBuf stim, words, v0_dev, p_dev, pv;
+  DP_TRY(stim.alloc(std::max<size_t>(pb * 2 * sizeof(uint64_t), 16)));
+  DP_TRY(words.alloc((size_t)d->n_nets * 2 * sizeof(uint64_t)));
+  DP_TRY(v0_dev.alloc(std::max<size_t>(pb, 16)));
+  DP_TRY(p_dev.alloc(std::max<size_t>(pb * sizeof(float), 16)));
+  DP_TRY(pv.alloc(std::max<size_t>((size_t)B * sizeof(double), 16)));
+  DP_TRY(ev->ones.alloc(nb * sizeof(uint32_t)));
+  DP_TRY(ev->tog.alloc(nb * sizeof(uint32_t)));
+  DP_HIP_TRY(dp::launch_virus_vectors(ev->sp.as<float>(), stim.as<uint64_t>(), v0_dev.as<uint8_t>(),
+                                      p_dev.as<float>(), d->n_pi, B, s));
+  DP_HIP_TRY(dp::launch_fill_u32(ev->ones.as<uint32_t>(), (int64_t)nb, 0u, s));
+  DP_HIP_TRY(dp::launch_fill_u32(ev->tog.as<uint32_t>(), (int64_t)nb, 0u, s));
+  const dp::GraphView g = view(d);
+  const dp::SimTune tune{1};
+  dp::ChunkView cv{};
+  cv.W = words.as<uint64_t>();
+  cv.pitch = 2;
+  cv.t_first = 0;
+  cv.pairs = 1;
+  cv.u_lo = 0;
+  cv.u_hi = 2;
+  cv.u_tog_lo = 1;
+  for (int32_t b = 0; b < B; ++b) {
+    const dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), B, b};
+    DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, ev->sp.as<float>(),
+                                   stim.as<uint64_t>() + (size_t)b * d->n_pi * 2, 2, 0, tune, s));
+    for (int32_t l = 1; l <= d->depth; ++l) {
+      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
+      DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, nullptr, tune, s));
+    }
+  }
+  DP_HIP_TRY(dp::launch_virus_power(ev->tog.as<uint32_t>(), ev->cap.as<float>(), d->n_nets, B,
+                                    pv.as<double>(), s));
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (v0 && pb) DP_HIP_TRY(hipMemcpyAsync(v0, v0_dev.ptr, pb, k, s));
+  if (p_final && pb) DP_HIP_TRY(hipMemcpyAsync(p_final, p_dev.ptr, pb * sizeof(float), k, s));
+  if (p_virus) DP_HIP_TRY(hipMemcpyAsync(p_virus, pv.ptr, (size_t)B * sizeof(double), k, s));
+  DP_HIP_TRY(hipStreamSynchronize(s));  // the scratch buffers are freed on return
+  ev->inputs_version++;  // the PI probabilities are now the ascended ones
+  return DP_OK;
+}
+
 dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device) {
   if (!ev) return fail(DP_E_INVALID, "dp_backward_columns: NULL eval");
   if (!dpower_dpi) return fail(DP_E_INVALID, "dp_backward_columns: NULL output");

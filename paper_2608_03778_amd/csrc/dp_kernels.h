@@ -170,6 +170,20 @@ struct BwdSeg {
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
 hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
 
+// Power-virus ascent (Alg. 4): P <- clip(P + eta * grad) on the PI rows of
+// the SP pairs [n_pi][B]; grad is [B][n_pi].
+hipError_t launch_virus_step(float *sp, const float *grad, float eta, int32_t n_pi, int32_t B,
+                             hipStream_t s);
+// v0 = [P >= 1/2] ([B][n_pi] bytes), P ([B][n_pi] floats, or null) and the
+// two-cycle stimulus [B][n_pi][2]: word 0 is v0 on every lane, word 1 its
+// complement.
+hipError_t launch_virus_vectors(const float *sp, uint64_t *stim, uint8_t *v0, float *p_out,
+                                int32_t n_pi, int32_t B, hipStream_t s);
+// P_virus[b] = sum_n cap[n] [net n toggled in column b] (toggles [n_nets][B]),
+// accumulated in double in a fixed order.
+hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_nets, int32_t B,
+                              double *out, hipStream_t s);
+
 // Persistent (cooperative) sweeps: all levels in one launch with a grid
 // barrier between levels.  level_ptr is the device copy of the design's
 // level table; max_items the largest level's item count.

@@ -788,6 +788,48 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float
   bwd_pi_item(g, a, out, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
 }
 
+// ---------------------------------------------------------------- power virus
+// One ascent step of Alg. 4 on the startpoints, kept as (p, 1 - p) pairs.
+__global__ __launch_bounds__(kBlock) void k_virus_step(float *sp, const float *__restrict__ grad,
+                                                       float eta, int32_t n_pi, int32_t B) {
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (uint32_t)n_pi * (uint32_t)B) return;
+  const int32_t i = (int32_t)(idx / (uint32_t)B), b = (int32_t)(idx - (uint32_t)i * B);
+  f2 *pq = reinterpret_cast<f2 *>(sp);
+  const float p = clamp01(fmaf(eta, grad[(int64_t)b * n_pi + i], pq[idx].x));
+  pq[idx] = f2{p, 1.0f - p};
+}
+
+// Threshold at 1/2 and spell out the two-cycle stimulus (v0, 1 - v0).
+__global__ __launch_bounds__(kBlock) void k_virus_vectors(const float *__restrict__ sp,
+                                                          uint64_t *stim, uint8_t *v0,
+                                                          float *p_out, int32_t n_pi, int32_t B) {
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (uint32_t)n_pi * (uint32_t)B) return;
+  const int32_t b = (int32_t)(idx / (uint32_t)n_pi), i = (int32_t)(idx - (uint32_t)b * n_pi);
+  const float p = reinterpret_cast<const f2 *>(sp)[(int64_t)i * B + b].x;
+  const bool one = p >= 0.5f;
+  v0[idx] = one ? 1 : 0;
+  if (p_out) p_out[idx] = p;
+  const uint64_t w0 = one ? ~0ull : 0ull;
+  stim[2 * (int64_t)idx] = w0;
+  stim[2 * (int64_t)idx + 1] = ~w0;
+}
+
+// One block per column: thread t adds nets t, t + 256, ... in order, then a
+// fixed tree over the block.
+__global__ __launch_bounds__(kBlock) void k_virus_power(const uint32_t *__restrict__ tog,
+                                                        const float *__restrict__ cap,
+                                                        int32_t n_nets, int32_t B, double *out) {
+  __shared__ double lds[kWavesPerBlock];
+  const int32_t b = blockIdx.x;
+  double acc = 0.0;
+  for (int32_t n = threadIdx.x; n < n_nets; n += kBlock)
+    if (tog[(int64_t)n * B + b] != 0u) acc += (double)cap[n];
+  const double r = block_sum_d(acc, lds);
+  if (threadIdx.x == 0) out[b] = r;
+}
+
 // ---------------------------------------------------------------- several designs
 // The segment of this block (uniform over the block: a short scalar scan).
 template <class Seg>
@@ -955,6 +997,31 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
   if (n <= 0) return hipSuccess;
   if (too_big(n)) return hipErrorInvalidValue;
   k_import_sizes<<<blocks_for(n), kBlock, 0, s>>>(src, int2ext, dst, n_pi, G, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_virus_step(float *sp, const float *grad, float eta, int32_t n_pi, int32_t B,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)n_pi * B;
+  if (n <= 0) return hipSuccess;
+  if (n >= (1ll << 31)) return hipErrorInvalidValue;
+  k_virus_step<<<blocks_for(n), kBlock, 0, s>>>(sp, grad, eta, n_pi, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_virus_vectors(const float *sp, uint64_t *stim, uint8_t *v0, float *p_out,
+                                int32_t n_pi, int32_t B, hipStream_t s) {
+  const int64_t n = (int64_t)n_pi * B;
+  if (n <= 0) return hipSuccess;
+  if (n >= (1ll << 31)) return hipErrorInvalidValue;
+  k_virus_vectors<<<blocks_for(n), kBlock, 0, s>>>(sp, stim, v0, p_out, n_pi, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_nets, int32_t B,
+                              double *out, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  k_virus_power<<<(unsigned)B, kBlock, 0, s>>>(tog, cap, n_nets, B, out);
   return hipGetLastError();
 }
 
