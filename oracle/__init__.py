@@ -76,6 +76,10 @@ def _declare(lib):
     lib.orc_power.restype = _d
     lib.orc_adjoint.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _p, _p, _d, _int, _p, _p, _p]
     lib.orc_adjoint.restype = None
+    lib.orc_sp_override.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _i64, _d, _p]
+    lib.orc_sp_override.restype = None
+    lib.orc_sizing_score.argtypes = [_i32, _i32, _p, _p, _d, _p]
+    lib.orc_sizing_score.restype = None
     lib.orc_virus_power.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p]
     lib.orc_virus_power.restype = _d
     lib.orc_power_virus.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _i32, _d, _p, _p]
@@ -186,6 +190,20 @@ class Netlist:
         return _load().orc_power_complex_step(
             *self._args(), _ptr(_c(p_pi, np.float64)), _ptr(_c(beta, np.float64)),
             _ptr(_c(ceff, np.float64)), float(kappa), int(pi), float(h))
+
+    def sp_override(self, p_pi, net: int, delta: float) -> np.ndarray:
+        """SP with P[net] shifted by delta (propagated downstream)."""
+        P = np.zeros(self.n_nets, dtype=np.float64)
+        _load().orc_sp_override(*self._args(), _ptr(_c(p_pi, np.float64)), int(net),
+                                float(delta), _ptr(P))
+        return P
+
+    def sizing_score(self, P, lam, eps=2.0 ** -20) -> np.ndarray:
+        """Eq. 8 score of every gate (caller gate order)."""
+        S = np.zeros(max(self.n_gates, 1), dtype=np.float64)
+        _load().orc_sizing_score(self.n_pi, self.n_gates, _ptr(_c(P, np.float64)),
+                                 _ptr(_c(lam, np.float64)), float(eps), _ptr(S))
+        return S[: self.n_gates]
 
     def virus_power(self, v0, cap) -> float:
         """P_virus (Eq. 3 at net level) of the vector pair (v0, 1 - v0)."""

@@ -545,3 +545,39 @@ double orc_power_virus(int32_t n_pi, int32_t n_gates, const uint8_t *op,
   free(lam);
   return orc_virus_power(n_pi, n_gates, op, fanin_ptr, fanin, order, cap, v0);
 }
+
+/* ------------------------------------------------------------------------ */
+/* SP with one net overridden: P[net] += delta after its own rule, and the
+ * change propagates to everything downstream (a hook for finite
+ * differences of the adjoint of an internal net). */
+void orc_sp_override(int32_t n_pi, int32_t n_gates, const uint8_t *op,
+                     const int32_t *fanin_ptr, const int32_t *fanin,
+                     const int32_t *order, const double *p_pi, int64_t net,
+                     double delta, double *P) {
+  for (int32_t i = 0; i < n_pi; ++i) P[i] = p_pi[i];
+  if (net >= 0 && net < n_pi) P[net] += delta;
+  for (int32_t k = 0; k < n_gates; ++k) {
+    int32_t g = order[k];
+    double x[3] = {0, 0, 0};
+    for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e) x[e - fanin_ptr[g]] = P[fanin[e]];
+    P[n_pi + g] = clamp01(sp_rule(op[g], x));
+    if ((int64_t)n_pi + g == net) P[net] += delta;
+  }
+}
+
+/* Sizing score (Sec. IV-A, Eq. 8) of every gate, from its output net n:
+ *   alpha_n = TR_model,n = 2 P_n (1 - P_n)              (Eq. 2)
+ *   dP/dalpha_n = lambda_n / (d alpha_n / d P_n) = lambda_n / (2 (1 - 2 P_n))
+ *   P_sw,n = kappa beta_n C_n alpha_n  (its local power), so
+ *   dP/dP_sw,n = dP/dalpha_n / (kappa beta_n C_n) and
+ *   S_g = |dP/dP_sw,n| * P_sw,n = |lambda_n| P_n (1 - P_n) / |1 - 2 P_n|.
+ * Where |1 - 2 P_n| < eps (the activity is flat in P) eps stands in for it. */
+void orc_sizing_score(int32_t n_pi, int32_t n_gates, const double *P, const double *lambda,
+                      double eps, double *score) {
+  for (int32_t g = 0; g < n_gates; ++g) {
+    int64_t n = (int64_t)n_pi + g;
+    double slope = fabs(1.0 - 2.0 * P[n]);
+    if (slope < eps) slope = eps;
+    score[g] = fabs(lambda[n]) * P[n] * (1.0 - P[n]) / slope;
+  }
+}

@@ -511,3 +511,75 @@ def test_virus_ascent_raises_the_proxy_and_thresholds():
         assert pv == pytest.approx(o.virus_power(v0, cap))
         assert ((p >= 0.0) & (p <= 1.0)).all()
     assert all(b >= a - 1e-9 for a, b in zip(proxy, proxy[1:]))
+
+
+# ---------------------------------------------------------------- internal adjoints, Eq. 8 score
+def _fd_internal(o, p, beta, cap, nets, h=1e-6):
+    """Central differences of the frozen-beta power with one net's SP
+    shifted (the SP-override hook), for each net in `nets`."""
+    out = []
+    for n in nets:
+        up = o.power(o.sp_override(p, n, h), cap, beta=beta)["power"]
+        dn = o.power(o.sp_override(p, n, -h), cap, beta=beta)["power"]
+        out.append((up - dn) / (2 * h))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("hybrid_beta", [False, True])
+def test_internal_adjoint_equals_finite_differences(hybrid_beta):
+    nl = synth.random_dag(synth.SPECS["dag2k"], 9)
+    cap = synth.net_caps(nl.n_nets, 9)
+    o = oracle.Netlist.of(nl)
+    p = synth.pi_probs(nl.n_pi, 9)[0].astype(np.float64)
+    rng = np.random.default_rng(9)
+    beta = rng.uniform(0.5, 2.0, nl.n_nets) if hybrid_beta else np.ones(nl.n_nets)
+    P = o.sp(p)
+    lam = o.adjoint(P, beta, cap)["lam"]
+    nets = np.concatenate([rng.choice(nl.n_pi, 10, replace=False),
+                           nl.n_pi + rng.choice(nl.n_gates, 60, replace=False)])
+    nets = [n for n in nets if 1e-3 < P[n] < 1 - 1e-3]
+    fd = _fd_internal(o, p, beta, cap, nets)
+    total = o.power(P, cap, beta=beta)["power"]
+    tol = 1e-4 * np.abs(fd) + 4 * np.finfo(np.float64).eps * abs(total) / 1e-6
+    assert (np.abs(lam[nets] - fd) <= tol).all()
+
+
+def test_sizing_score_equals_chain_rule_by_differences():
+    """Eq. 8 through Eq. 2, checked with a ratio of central differences:
+    dP/dalpha_n = dP_total / dalpha_n as P_n is shifted, times the local
+    power kappa beta C alpha_n."""
+    nl = synth.random_dag(synth.SPECS["dag2k"], 10)
+    cap = synth.net_caps(nl.n_nets, 10)
+    o = oracle.Netlist.of(nl)
+    p = synth.pi_probs(nl.n_pi, 10)[0].astype(np.float64)
+    beta = np.ones(nl.n_nets)
+    P = o.sp(p)
+    S = o.sizing_score(P, o.adjoint(P, beta, cap)["lam"])
+    rng = np.random.default_rng(10)
+    h, kappa = 1e-6, 0.5
+    checked = 0
+    for g in rng.choice(nl.n_gates, 80, replace=False):
+        n = nl.n_pi + g
+        if not (abs(1 - 2 * P[n]) > 0.05 and 1e-3 < P[n] < 1 - 1e-3):
+            continue
+        dP = (o.power(o.sp_override(p, n, h), cap, beta=beta)["power"]
+              - o.power(o.sp_override(p, n, -h), cap, beta=beta)["power"])
+        a_up, a_dn = 2 * (P[n] + h) * (1 - P[n] - h), 2 * (P[n] - h) * (1 - P[n] + h)
+        local = kappa * cap[n] * 2 * P[n] * (1 - P[n])
+        s_fd = abs(dP / (a_up - a_dn)) / (kappa * cap[n]) * local
+        assert S[g] == pytest.approx(s_fd, rel=1e-4)
+        checked += 1
+    assert checked > 40
+    # the flat point: P = 1/2 uses the floor, never divides by zero
+    assert np.isfinite(o.sizing_score(np.full(nl.n_nets, 0.5), np.ones(nl.n_nets))).all()
+
+
+def test_rank_metrics():
+    from paper_2608_03778_amd import rank
+    a = np.array([5.0, -4.0, 3.0, 0.5, 0.1])
+    assert list(rank.top_k(a, 2)) == [0, 1]
+    assert rank.top_k_overlap(a, a * 2, 3) == 1.0
+    assert rank.top_k_overlap(a, [0.1, 0.2, 0.3, 9.0, 8.0], 2) == 0.0
+    assert rank.jaccard_top_k(a, [5.0, 0.0, 3.0, 4.0, 0.0], 2) == pytest.approx(1 / 3)
+    assert rank.pearson(a, 2 * a + 1) == pytest.approx(1.0)
+    assert rank.pearson(a, -a) == pytest.approx(-1.0)
