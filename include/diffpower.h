@@ -240,6 +240,21 @@ dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi,
  * partial derivatives to its S' seeds.  Errors as dp_backward. */
 dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device);
 
+/* Power gradients of every net (Sec. IV): one reverse sweep after a
+ * completed forward (grad_power = 1, per query column) that keeps every
+ * net's adjoint.  dpower_dsp [B][n_nets] (caller numbering) receives
+ * lambda_n = dPower/dP_n, the derivative with respect to the net's static
+ * probability (Eq. 7; the PI entries equal dp_backward's dPower/dp).  score
+ * [B][n_gates] (caller gate order) receives the sizing score of Eq. 8 for the
+ * gate driving each net, through the chain rule of Eq. 2:
+ *   S = |dP/dP_sw| * P_sw = |lambda_n| P_n (1 - P_n) / |1 - 2 P_n|,
+ * with 2^-20 standing in for |1 - 2 P_n| where the activity is flat in P.
+ * Either output may be NULL; host or device memory as on_device.  Returns
+ * after the outputs are written.  Errors: DP_E_STATE (no forward for the
+ * current inputs), DP_E_HIP, DP_E_OOM. */
+dp_status dp_power_gradients(dp_eval *ev, float *dpower_dsp, float *score,
+                             int32_t on_device);
+
 /* Power-virus search by gradient ascent (Sec. IV-B, Alg. 4).  Each of the
  * eval's B columns is one ascent that starts from its PI probabilities (set
  * with dp_set_pi_prob; Alg. 4 starts every startpoint at 0.5).  `steps`

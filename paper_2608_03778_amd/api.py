@@ -236,6 +236,15 @@ class Eval:
         check(self.lib.dp_backward_columns(self.handle, ptr, int(bool(device))))
         return arr
 
+    def power_gradients(self):
+        """Every net's dPower/dP [B][n_nets] and the Eq. 8 sizing score of
+        every gate [B][n_gates] (caller numbering), after a forward."""
+        d = self.design
+        lam = np.zeros((self.B, d.n_nets), dtype=np.float32)
+        score = np.zeros((self.B, d.n_gates), dtype=np.float32)
+        check(self.lib.dp_power_gradients(self.handle, lam.ctypes.data, score.ctypes.data, 0))
+        return lam, score
+
     def power_virus(self, steps: int = 100, eta: float = 0.1):
         """Alg. 4 from the current PI probabilities: returns (v0 [B][n_pi]
         uint8, p_final [B][n_pi] float32, p_virus [B] float64)."""

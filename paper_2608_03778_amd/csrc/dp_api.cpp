@@ -1080,6 +1080,34 @@ dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi, f
   return run_backward(ev, grad_power, 0, dpower_dpi, dpower_dcap, dpower_dsize, on_device);
 }
 
+dp_status dp_power_gradients(dp_eval *ev, float *dpower_dsp, float *score, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_power_gradients: NULL eval");
+  const dp_design *d = ev->d;
+  if (ev->fwd_version != ev->inputs_version || ev->fwd_version == 0)
+    return fail(DP_E_STATE, "dp_power_gradients: no completed forward for the current inputs");
+  if (!dpower_dsp && !score) return DP_OK;
+  DP_HIP_TRY(hipSetDevice(d->ctx->device));
+  hipStream_t s = ev->stream();
+  const int32_t B = ev->B;
+  DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * B * sizeof(float), 16)));
+  DP_TRY(ev->pi_out.alloc(std::max<size_t>((size_t)B * d->n_pi * sizeof(float), 16)));
+  DevBuf lam;
+  DP_TRY(lam.alloc((size_t)B * d->n_nets * sizeof(float)));
+  dp::BwdArgs ba = backward_args(ev, nullptr, 0, B);
+  ba.lam = lam.as<float>();
+  DP_TRY(enqueue_backward(ev, ba, ev->pi_out.as<float>()));
+  OutMap om{ev, on_device};
+  float *o_lam = nullptr, *o_score = nullptr;
+  DP_TRY(om.map(dpower_dsp, (size_t)B * d->n_nets, &o_lam));
+  DP_TRY(om.map(score, (size_t)B * d->n_gates, &o_score));
+  DP_HIP_TRY(dp::launch_grad_lambda_export(lam.as<float>(), ev->sp.as<float>(),
+                                           d->int2ext.as<int32_t>(), d->n_pi, d->n_nets, B, B, 1,
+                                           0x1p-20f, o_lam, o_score, s));
+  DP_TRY(om.flush(s));
+  DP_HIP_TRY(hipStreamSynchronize(s));  // the adjoint buffer is freed on return
+  return DP_OK;
+}
+
 dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, float *p_final,
                          double *p_virus, int32_t on_device) {
   if (!ev) return fail(DP_E_INVALID, "dp_power_virus: NULL eval");

@@ -143,6 +143,7 @@ struct BwdArgs {
   const float *w;             // [B][S'] (null = 1)
   const float *size;          // [S][G] internal, or null (all 1)
   float *contrib;             // [n_edges][C], in fan-out (reader) order
+  float *lam;                 // [C][n_nets] internal: every net's adjoint, or null
   float kappa;
   int32_t n_pi, G, B, S, C, cdiv, ste, per_column, paired;
 };
@@ -169,6 +170,14 @@ struct BwdSeg {
 // segs: device array of n_segs; blocks: total blocks of the launch.
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
 hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
+
+// Every net's adjoint in caller numbering, lam_out [C][n_nets], and the
+// Eq. 8 score of every gate from its output net, score [C][G] caller gate
+// order: |lambda| P (1 - P) / max(|1 - 2P|, eps).  Either may be null.
+hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const int32_t *int2ext,
+                                     int32_t n_pi, int32_t n_nets, int32_t B, int32_t C,
+                                     int32_t cdiv, float eps, float *lam_out, float *score,
+                                     hipStream_t s);
 
 // Power-virus ascent (Alg. 4): P <- clip(P + eta * grad) on the PI rows of
 // the SP pairs [n_pi][B]; grad is [B][n_pi].

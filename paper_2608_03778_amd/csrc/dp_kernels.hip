@@ -751,6 +751,7 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   if (!active) return;
   float lam = seed + pulled;
   if (a.ste) lam *= beta;
+  if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
   float d0, d1, d2;
   sp_partials(op, x0, x1, x2, d0, d1, d2);
   a.contrib[(int64_t)g.slot[gi] * a.C + c] = lam * d0;
@@ -782,10 +783,29 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   float lam = seed + pulled;
   if (a.ste) lam *= beta;
   out[(int64_t)c * g.n_pi + i] = lam;
+  if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + i] = lam;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
   bwd_pi_item(g, a, out, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------- adjoints and scores
+__global__ __launch_bounds__(kBlock) void k_grad_lambda_export(
+    const float *__restrict__ lam, const float *__restrict__ sp, const int32_t *__restrict__ int2ext,
+    int32_t n_pi, int32_t n_nets, int32_t B, int32_t C, int32_t cdiv, float eps, float *lam_out,
+    float *score) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)n_nets * C) return;
+  const int32_t c = (int32_t)(idx / n_nets), n = (int32_t)(idx - (int64_t)c * n_nets);
+  const float l = lam[idx];
+  const int32_t e = int2ext[n];
+  if (lam_out) lam_out[(int64_t)c * n_nets + e] = l;
+  if (score && n >= n_pi) {
+    const f2 pq = reinterpret_cast<const f2 *>(sp)[(int64_t)n * B + c / cdiv];
+    const float slope = fmaxf(fabsf(pq.y - pq.x), eps);  // |1 - 2P| from the pair
+    score[(int64_t)c * (n_nets - n_pi) + (e - n_pi)] = fabsf(l) * (pq.x * pq.y) / slope;
+  }
 }
 
 // ---------------------------------------------------------------- power virus
@@ -997,6 +1017,18 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
   if (n <= 0) return hipSuccess;
   if (too_big(n)) return hipErrorInvalidValue;
   k_import_sizes<<<blocks_for(n), kBlock, 0, s>>>(src, int2ext, dst, n_pi, G, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const int32_t *int2ext,
+                                     int32_t n_pi, int32_t n_nets, int32_t B, int32_t C,
+                                     int32_t cdiv, float eps, float *lam_out, float *score,
+                                     hipStream_t s) {
+  const int64_t n = (int64_t)n_nets * C;
+  if (n <= 0 || (!lam_out && !score)) return hipSuccess;
+  if (too_big(n)) return hipErrorInvalidValue;
+  k_grad_lambda_export<<<blocks_for(n), kBlock, 0, s>>>(lam, sp, int2ext, n_pi, n_nets, B, C,
+                                                        cdiv, eps, lam_out, score);
   return hipGetLastError();
 }
 

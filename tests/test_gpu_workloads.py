@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2608_03778_amd import _lib as L
-from paper_2608_03778_amd import api, synth
+from paper_2608_03778_amd import api, rank, synth
 from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, say)
 from tests.oracle_parallel import sim_counts
 
@@ -64,6 +64,10 @@ def _full_check(ctx, name, n_sim, seed, fd_samples=0):
         err = np.abs(g["dpi"][0][idx] - fd)
         tol = 1e-4 * np.abs(fd) + 1e-6 * np.abs(adj["dpi"]).max() + rounding
         assert (err <= tol).all(), f"FD mismatch at {idx[err > tol][:5]}"
+        # rank agreement of the GPU gradient with the differences (Sec. V-C)
+        m = rank.agreement(g["dpi"][0][idx], fd, 20)
+        say(f"{name}: rank agreement with FD on {fd_samples} PIs: {m}")
+        assert m["pearson"] > 0.9999 and m["top_k_overlap"] >= 0.95
 
 
 def test_dag117k_hybrid_fwd_bwd_with_fd():
