@@ -43,6 +43,10 @@ _int = ctypes.c_int
 
 
 def _declare(lib):
+    lib.orc_cell_compile.argtypes = [ctypes.c_char_p, _p, _p]
+    lib.orc_cell_compile.restype = _int
+    lib.orc_set_cells.argtypes = [_int, _p]
+    lib.orc_set_cells.restype = _int
     lib.orc_op_arity.argtypes = [_int]
     lib.orc_op_arity.restype = _int
     lib.orc_topo_order.argtypes = [_i32, _i32, _p, _p, _p, _p]
@@ -94,12 +98,39 @@ def _c(a, dtype):
     return None if a is None else np.ascontiguousarray(a, dtype=dtype)
 
 
+CELL_BASE = 16  # opcode of library cell c is CELL_BASE + c
+CODE_OPS = ("IN", "NOT", "AND", "OR", "XOR", "CONST0", "CONST1")
+
+
+def cell_code(expr: str):
+    """The oracle's post-order code of one cell expression: ([(op, arg)],
+    n_inputs).  Raises ValueError on a syntax error."""
+    code = np.zeros(64, dtype=np.uint16)
+    n_in = ctypes.c_int(0)
+    n = _load().orc_cell_compile(expr.encode(), _ptr(code), ctypes.byref(n_in))
+    if n < 0:
+        raise ValueError(f"cannot compile cell expression {expr!r}")
+    return [(CODE_OPS[int(c) & 0xFF], int(c) >> 8) for c in code[:n]], n_in.value
+
+
+def set_cells(exprs) -> None:
+    """Register the cell library every later evaluation uses."""
+    exprs = [e.encode() for e in (exprs or [])]
+    arr = (ctypes.c_char_p * max(len(exprs), 1))(*exprs)
+    rc = _load().orc_set_cells(len(exprs), ctypes.cast(arr, ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError(f"cell {-rc - 1} does not compile")
+
+
 class Netlist:
     """The oracle's own copy of a netlist (caller numbering) plus its
-    topological order."""
+    topological order.  Gates with opcode CELL_BASE + c are instances of
+    cells[c], a Boolean expression."""
 
-    def __init__(self, n_pi, op, fanin_ptr, fanin):
+    def __init__(self, n_pi, op, fanin_ptr, fanin, cells=None):
         lib = _load()
+        self.cells = list(cells or [])
+        set_cells(self.cells)
         self.n_pi = int(n_pi)
         self.op = _c(op, np.uint8)
         self.fanin_ptr = _c(fanin_ptr, np.int32)
@@ -116,14 +147,16 @@ class Netlist:
 
     @classmethod
     def of(cls, nl):
-        return cls(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin)
+        return cls(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin, getattr(nl, "cells", None))
 
     def _args(self):
+        set_cells(self.cells)  # the library is process state: bind ours first
         return (self.n_pi, self.n_gates, _ptr(self.op), _ptr(self.fanin_ptr), _ptr(self.fanin),
                 _ptr(self.order))
 
     def levels(self) -> np.ndarray:
         lv = np.zeros(self.n_nets, dtype=np.int32)
+        set_cells(self.cells)
         _load().orc_levels(self.n_pi, self.n_gates, _ptr(self.fanin_ptr), _ptr(self.fanin),
                            _ptr(self.order), _ptr(lv))
         return lv
@@ -168,6 +201,7 @@ class Netlist:
         ones = _c(ones, np.uint64)
         toggles = _c(toggles, np.uint64)
         beta = _c(beta, np.float64)
+        set_cells(self.cells)
         out["power"] = _load().orc_power(
             self.n_pi, self.n_gates, _ptr(P), _ptr(ones), _ptr(toggles), int(n_words), _ptr(cap),
             _ptr(size), float(kappa), int(bool(hybrid)), float(beta_min), float(beta_max),
@@ -201,6 +235,7 @@ class Netlist:
     def sizing_score(self, P, lam, eps=2.0 ** -20) -> np.ndarray:
         """Eq. 8 score of every gate (caller gate order)."""
         S = np.zeros(max(self.n_gates, 1), dtype=np.float64)
+        set_cells(self.cells)
         _load().orc_sizing_score(self.n_pi, self.n_gates, _ptr(_c(P, np.float64)),
                                  _ptr(_c(lam, np.float64)), float(eps), _ptr(S))
         return S[: self.n_gates]
@@ -246,19 +281,19 @@ def op_arity(op: int) -> int:
 
 
 def gate_sp(op: int, x) -> float:
-    x = np.ascontiguousarray(np.resize(np.asarray(x, dtype=np.float64), 3))
+    x = np.ascontiguousarray(np.resize(np.asarray(x, dtype=np.float64), 6))
     return float(_load().orc_gate_sp(int(op), _ptr(x)))
 
 
 def gate_partials(op: int, x) -> np.ndarray:
-    x = np.ascontiguousarray(np.resize(np.asarray(x, dtype=np.float64), 3))
-    d = np.zeros(3, dtype=np.float64)
+    x = np.ascontiguousarray(np.resize(np.asarray(x, dtype=np.float64), 6))
+    d = np.zeros(6, dtype=np.float64)
     _load().orc_gate_partials(int(op), _ptr(x), _ptr(d))
     return d[: op_arity(op)]
 
 
 def gate_bits(op: int, w) -> int:
-    w = np.ascontiguousarray(np.resize(np.asarray(w, dtype=np.uint64), 3))
+    w = np.ascontiguousarray(np.resize(np.asarray(w, dtype=np.uint64), 6))
     return int(_load().orc_gate_bits(int(op), _ptr(w)))
 
 

@@ -42,9 +42,244 @@ enum {
   ORC_MUX2 = 8   /* I0, I1, S : S ? I1 : I0       */
 };
 
+/* ------------------------------------------------------------------------ */
+/* Library cells given as Boolean expressions (Sec. III-A, Alg. 1): each is
+ * parsed (NOT binds tightest, then AND, XOR, OR), compiled in post-order to
+ * a zero-address stack code, and evaluated operation by operation.  A gate
+ * whose opcode is ORC_CELL_BASE + c is an instance of library cell c; its
+ * inputs are the expression's identifiers in order of first appearance. */
+#define ORC_CELL_BASE 16
+#define ORC_MAX_IN 6
+#define ORC_MAX_CODE 64
+#define ORC_MAX_CELLS 240
+enum { OC_IN = 0, OC_NOT = 1, OC_AND = 2, OC_OR = 3, OC_XOR = 4, OC_ZERO = 5, OC_ONE = 6 };
+
+static int g_n_cells = 0;
+static uint16_t g_code[ORC_MAX_CELLS][ORC_MAX_CODE]; /* op | arg << 8 */
+static int g_len[ORC_MAX_CELLS], g_nin[ORC_MAX_CELLS];
+
+/* recursive-descent parser over a NUL-terminated expression */
+typedef struct {
+  const char *s;
+  int pos, n_ids, len, err;
+  char ids[ORC_MAX_IN][32];
+  uint16_t *code;
+} orc_parser;
+
+static void ps_skip(orc_parser *ps) {
+  while (ps->s[ps->pos] == ' ' || ps->s[ps->pos] == '\t') ps->pos++;
+}
+static void ps_emit(orc_parser *ps, int op, int arg) {
+  if (ps->len >= ORC_MAX_CODE) { ps->err = 1; return; }
+  ps->code[ps->len++] = (uint16_t)(op | (arg << 8));
+}
+static int is_id0(char c) { return (c >= 'A' && c <= 'Z') || (c >= 'a' && c <= 'z') || c == '_'; }
+static int is_id(char c) { return is_id0(c) || (c >= '0' && c <= '9'); }
+static void ps_or(orc_parser *ps);
+static void ps_unary(orc_parser *ps) {
+  ps_skip(ps);
+  char c = ps->s[ps->pos];
+  if (c == '!' || c == '~') {
+    ps->pos++;
+    ps_unary(ps);
+    ps_emit(ps, OC_NOT, 0);
+  } else if (c == '(') {
+    ps->pos++;
+    ps_or(ps);
+    ps_skip(ps);
+    if (ps->s[ps->pos] != ')') { ps->err = 1; return; }
+    ps->pos++;
+  } else if (c == '0' || c == '1') {
+    ps->pos++;
+    ps_emit(ps, c == '0' ? OC_ZERO : OC_ONE, 0);
+  } else if (is_id0(c)) {
+    char name[32];
+    int n = 0;
+    while (is_id(ps->s[ps->pos]) && n < 31) name[n++] = ps->s[ps->pos++];
+    name[n] = 0;
+    if (is_id(ps->s[ps->pos])) { ps->err = 1; return; }
+    int k = 0;
+    while (k < ps->n_ids && strcmp(ps->ids[k], name) != 0) ++k;
+    if (k == ps->n_ids) {
+      if (ps->n_ids == ORC_MAX_IN) { ps->err = 1; return; }
+      strcpy(ps->ids[ps->n_ids++], name);
+    }
+    ps_emit(ps, OC_IN, k);
+  } else {
+    ps->err = 1;
+  }
+}
+static void ps_and(orc_parser *ps) {
+  ps_unary(ps);
+  for (;;) {
+    ps_skip(ps);
+    char c = ps->s[ps->pos];
+    if (ps->err || (c != '&' && c != '*')) return;
+    ps->pos++;
+    ps_unary(ps);
+    ps_emit(ps, OC_AND, 0);
+  }
+}
+static void ps_xor(orc_parser *ps) {
+  ps_and(ps);
+  for (;;) {
+    ps_skip(ps);
+    if (ps->err || ps->s[ps->pos] != '^') return;
+    ps->pos++;
+    ps_and(ps);
+    ps_emit(ps, OC_XOR, 0);
+  }
+}
+static void ps_or(orc_parser *ps) {
+  ps_xor(ps);
+  for (;;) {
+    ps_skip(ps);
+    char c = ps->s[ps->pos];
+    if (ps->err || (c != '|' && c != '+')) return;
+    ps->pos++;
+    ps_xor(ps);
+    ps_emit(ps, OC_OR, 0);
+  }
+}
+
+/* Compile one expression; returns the code length, or -1 on a syntax error
+ * (or more than ORC_MAX_IN inputs / ORC_MAX_CODE instructions). */
+int orc_cell_compile(const char *expr, uint16_t *code, int *n_inputs) {
+  orc_parser ps;
+  memset(&ps, 0, sizeof ps);
+  ps.s = expr;
+  ps.code = code;
+  ps_or(&ps);
+  ps_skip(&ps);
+  if (ps.err || ps.s[ps.pos] != 0 || ps.len == 0) return -1;
+  *n_inputs = ps.n_ids;
+  return ps.len;
+}
+
+/* Register the cell library for later calls: 0, or -(1 + c) if cell c does
+ * not compile. */
+int orc_set_cells(int n_cells, const char *const *exprs) {
+  if (n_cells < 0 || n_cells > ORC_MAX_CELLS) return -1;
+  for (int c = 0; c < n_cells; ++c) {
+    int n = orc_cell_compile(exprs[c], g_code[c], &g_nin[c]);
+    if (n < 0) return -(1 + c);
+    g_len[c] = n;
+  }
+  g_n_cells = n_cells;
+  return 0;
+}
+
+/* Op-by-op probability of a cell's code (each operation applies its
+ * independent-input rule to its operands). */
+static double cell_sp(int c, const double *x) {
+  double st[ORC_MAX_CODE];
+  int top = 0;
+  for (int i = 0; i < g_len[c]; ++i) {
+    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
+    double a, b;
+    switch (op) {
+      case OC_IN: st[top++] = x[arg]; break;
+      case OC_ZERO: st[top++] = 0.0; break;
+      case OC_ONE: st[top++] = 1.0; break;
+      case OC_NOT: st[top - 1] = 1.0 - st[top - 1]; break;
+      default:
+        b = st[--top];
+        a = st[--top];
+        st[top++] = op == OC_AND ? a * b : (op == OC_OR ? a + b - a * b : a + b - 2.0 * a * b);
+    }
+  }
+  return st[0];
+}
+
+static double complex cell_sp_c(int c, const double complex *x) {
+  double complex st[ORC_MAX_CODE];
+  int top = 0;
+  for (int i = 0; i < g_len[c]; ++i) {
+    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
+    double complex a, b;
+    switch (op) {
+      case OC_IN: st[top++] = x[arg]; break;
+      case OC_ZERO: st[top++] = 0.0; break;
+      case OC_ONE: st[top++] = 1.0; break;
+      case OC_NOT: st[top - 1] = 1.0 - st[top - 1]; break;
+      default:
+        b = st[--top];
+        a = st[--top];
+        st[top++] = op == OC_AND ? a * b : (op == OC_OR ? a + b - a * b : a + b - 2.0 * a * b);
+    }
+  }
+  return st[0];
+}
+
+/* Reverse-mode derivative of cell_sp (Sec. III-E, Alg. 3): a forward pass
+ * keeps each binary operation's operands; a backward pass over the code in
+ * reverse keeps a stack of output gradients: an input adds its gradient to
+ * its slot, NOT negates, a binary operation replaces the gradient of its
+ * result by those of its two operands (the right operand's on top, as it
+ * was computed last), a constant drops it. */
+static void cell_partials(int c, const double *x, double *d) {
+  double st[ORC_MAX_CODE], ta[ORC_MAX_CODE], tb[ORC_MAX_CODE], gs[ORC_MAX_CODE];
+  int top = 0;
+  for (int k = 0; k < g_nin[c]; ++k) d[k] = 0.0;
+  for (int i = 0; i < g_len[c]; ++i) {
+    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
+    switch (op) {
+      case OC_IN: st[top++] = x[arg]; break;
+      case OC_ZERO: st[top++] = 0.0; break;
+      case OC_ONE: st[top++] = 1.0; break;
+      case OC_NOT: st[top - 1] = 1.0 - st[top - 1]; break;
+      default: {
+        double b = st[--top], a = st[--top];
+        ta[i] = a;
+        tb[i] = b;
+        st[top++] = op == OC_AND ? a * b : (op == OC_OR ? a + b - a * b : a + b - 2.0 * a * b);
+      }
+    }
+  }
+  int gt = 0;
+  gs[gt++] = 1.0;
+  for (int i = g_len[c] - 1; i >= 0; --i) {
+    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
+    double g = gs[--gt];
+    switch (op) {
+      case OC_IN: d[arg] += g; break;
+      case OC_ZERO:
+      case OC_ONE: break;
+      case OC_NOT: gs[gt++] = -g; break;
+      case OC_AND: gs[gt++] = g * tb[i]; gs[gt++] = g * ta[i]; break;
+      case OC_OR: gs[gt++] = g * (1.0 - tb[i]); gs[gt++] = g * (1.0 - ta[i]); break;
+      default: gs[gt++] = g * (1.0 - 2.0 * tb[i]); gs[gt++] = g * (1.0 - 2.0 * ta[i]); break;
+    }
+  }
+}
+
+static uint64_t cell_bits(int c, const uint64_t *w) {
+  uint64_t st[ORC_MAX_CODE];
+  int top = 0;
+  for (int i = 0; i < g_len[c]; ++i) {
+    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
+    uint64_t a, b;
+    switch (op) {
+      case OC_IN: st[top++] = w[arg]; break;
+      case OC_ZERO: st[top++] = 0; break;
+      case OC_ONE: st[top++] = ~0ull; break;
+      case OC_NOT: st[top - 1] = ~st[top - 1]; break;
+      default:
+        b = st[--top];
+        a = st[--top];
+        st[top++] = op == OC_AND ? (a & b) : (op == OC_OR ? (a | b) : (a ^ b));
+    }
+  }
+  return st[0];
+}
+
 static const int orc_arity[9] = {1, 1, 2, 2, 2, 2, 2, 3, 3};
 
-int orc_op_arity(int op) { return (op >= 0 && op < 9) ? orc_arity[op] : -1; }
+int orc_op_arity(int op) {
+  if (op >= 0 && op < 9) return orc_arity[op];
+  if (op >= ORC_CELL_BASE && op - ORC_CELL_BASE < g_n_cells) return g_nin[op - ORC_CELL_BASE];
+  return -1;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Netlist check and topological order (Sec. III-A: the graph is levelized so
@@ -57,8 +292,8 @@ int orc_topo_order(int32_t n_pi, int32_t n_gates, const uint8_t *op,
   int64_t n_nets = (int64_t)n_pi + n_gates;
   if (n_pi < 0 || n_gates < 0 || fanin_ptr[0] != 0) return -1;
   for (int32_t g = 0; g < n_gates; ++g) {
-    if (op[g] > 8) return -1;
-    if (fanin_ptr[g + 1] - fanin_ptr[g] != orc_arity[op[g]]) return -1;
+    if (orc_op_arity(op[g]) < 0) return -1;
+    if (fanin_ptr[g + 1] - fanin_ptr[g] != orc_op_arity(op[g])) return -1;
     for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
       if (fanin[e] < 0 || fanin[e] >= n_nets) return -1;
   }
@@ -117,6 +352,7 @@ void orc_levels(int32_t n_pi, int32_t n_gates, const int32_t *fanin_ptr,
  * forms below (the paper gives AND = a0 a1 and NAND = 1 - a0 a1 as examples
  * in Alg. 2, and the OR/XOR/NOT forms in Sec. III-E). */
 static double sp_rule(int op, const double *x) {
+  if (op >= ORC_CELL_BASE) return cell_sp(op - ORC_CELL_BASE, x);
   switch (op) {
     case ORC_INV: return 1.0 - x[0];
     case ORC_BUF: return x[0];
@@ -135,6 +371,10 @@ static double sp_rule(int op, const double *x) {
  * d(ab)/da = b, d(OR)/da = 1-b, d(XOR)/da = 1-2b, d(NOT)/dx = -1; the
  * compound cells follow by the product rule). */
 static void sp_partials(int op, const double *x, double *d) {
+  if (op >= ORC_CELL_BASE) {
+    cell_partials(op - ORC_CELL_BASE, x, d);
+    return;
+  }
   switch (op) {
     case ORC_INV: d[0] = -1.0; break;
     case ORC_BUF: d[0] = 1.0; break;
@@ -154,6 +394,7 @@ static void sp_partials(int op, const double *x, double *d) {
 
 /* Boolean function of each cell on 64 parallel lanes (Sec. III-C). */
 static uint64_t bit_rule(int op, const uint64_t *w) {
+  if (op >= ORC_CELL_BASE) return cell_bits(op - ORC_CELL_BASE, w);
   switch (op) {
     case ORC_INV: return ~w[0];
     case ORC_BUF: return w[0];
@@ -170,7 +411,8 @@ static uint64_t bit_rule(int op, const uint64_t *w) {
 
 static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 
-/* Exported single-gate rules, for tests that enumerate truth tables. */
+/* Exported single-gate rules, for tests that enumerate truth tables (a
+ * library cell's opcode is ORC_CELL_BASE + its index). */
 double orc_gate_sp(int op, const double *x) { return sp_rule(op, x); }
 void orc_gate_partials(int op, const double *x, double *d) { sp_partials(op, x, d); }
 uint64_t orc_gate_bits(int op, const uint64_t *w) { return bit_rule(op, w); }
@@ -186,7 +428,7 @@ void orc_sp(int32_t n_pi, int32_t n_gates, const uint8_t *op,
   for (int32_t i = 0; i < n_pi; ++i) P[i] = p_pi[i];
   for (int32_t k = 0; k < n_gates; ++k) {
     int32_t g = order[k];
-    double x[3] = {0, 0, 0};
+    double x[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
     for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
       x[e - fanin_ptr[g]] = P[fanin[e]];
     P[n_pi + g] = clamp01(sp_rule(op[g], x));
@@ -198,6 +440,7 @@ void orc_sp(int32_t n_pi, int32_t n_gates, const uint8_t *op,
  * Im(F(p + i h e_k)) / h is the derivative of F with respect to p_k with no
  * subtractive cancellation.  Used only to check the adjoint. */
 static double complex sp_rule_c(int op, const double complex *x) {
+  if (op >= ORC_CELL_BASE) return cell_sp_c(op - ORC_CELL_BASE, x);
   switch (op) {
     case ORC_INV: return 1.0 - x[0];
     case ORC_BUF: return x[0];
@@ -224,7 +467,7 @@ double orc_power_complex_step(int32_t n_pi, int32_t n_gates, const uint8_t *op,
   for (int32_t i = 0; i < n_pi; ++i) P[i] = p_pi[i] + (i == pi ? I * h : 0.0);
   for (int32_t k = 0; k < n_gates; ++k) {
     int32_t g = order[k];
-    double complex x[3] = {0, 0, 0};
+    double complex x[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
     for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
       x[e - fanin_ptr[g]] = P[fanin[e]];
     P[n_pi + g] = sp_rule_c(op[g], x); /* values stay inside [0,1]: no clip */
@@ -343,7 +586,7 @@ void orc_sim(int32_t n_pi, int32_t n_gates, const uint8_t *op,
     for (int32_t i = 0; i < n_pi; ++i) cur[i] = pi_words[(int64_t)i * T + t];
     for (int32_t k = 0; k < n_gates; ++k) {
       int32_t g = order[k];
-      uint64_t w[3] = {0, 0, 0};
+      uint64_t w[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
       for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
         w[e - fanin_ptr[g]] = cur[fanin[e]];
       cur[n_pi + g] = bit_rule(op[g], w);
@@ -374,7 +617,7 @@ void orc_sim_range(int32_t n_pi, int32_t n_gates, const uint8_t *op,
     for (int32_t i = 0; i < n_pi; ++i) cur[i] = orc_stimulus_word(i, t, p_pi[i], seed);
     for (int32_t k = 0; k < n_gates; ++k) {
       int32_t g = order[k];
-      uint64_t w[3] = {0, 0, 0};
+      uint64_t w[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
       for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
         w[e - fanin_ptr[g]] = cur[fanin[e]];
       cur[n_pi + g] = bit_rule(op[g], w);
@@ -468,7 +711,7 @@ void orc_adjoint(int32_t n_pi, int32_t n_gates, const uint8_t *op,
     lambda[n] = lam;
     if (n >= n_pi) {
       int32_t g = (int32_t)(n - n_pi);
-      double x[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+      double x[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0}, d[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
       for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e)
         x[e - fanin_ptr[g]] = P[fanin[e]];
       sp_partials(op[g], x, d);
@@ -508,7 +751,7 @@ double orc_virus_power(int32_t n_pi, int32_t n_gates, const uint8_t *op,
   }
   for (int32_t k = 0; k < n_gates; ++k) {
     int32_t g = order[k];
-    uint64_t a0[3] = {0, 0, 0}, a1[3] = {0, 0, 0};
+    uint64_t a0[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0}, a1[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
     for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e) {
       a0[e - fanin_ptr[g]] = w0[fanin[e]];
       a1[e - fanin_ptr[g]] = w1[fanin[e]];
@@ -558,7 +801,7 @@ void orc_sp_override(int32_t n_pi, int32_t n_gates, const uint8_t *op,
   if (net >= 0 && net < n_pi) P[net] += delta;
   for (int32_t k = 0; k < n_gates; ++k) {
     int32_t g = order[k];
-    double x[3] = {0, 0, 0};
+    double x[ORC_MAX_IN] = {0, 0, 0, 0, 0, 0};
     for (int32_t e = fanin_ptr[g]; e < fanin_ptr[g + 1]; ++e) x[e - fanin_ptr[g]] = P[fanin[e]];
     P[n_pi + g] = clamp01(sp_rule(op[g], x));
     if ((int64_t)n_pi + g == net) P[net] += delta;

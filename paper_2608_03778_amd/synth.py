@@ -33,12 +33,14 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import re
 
 import numpy as np
 
 # Opcode numbering of the nine fixed cells.  The C-ABI header and the oracle
 # each declare the same numbering on their own; it is an interface, not code.
 INV, BUF, AND2, OR2, NAND2, NOR2, XOR2, AOI21, MUX2 = range(9)
+CELL_BASE = 16  # gate opcode of library cell c
 OP_NAMES = ("INV", "BUF", "AND2", "OR2", "NAND2", "NOR2", "XOR2", "AOI21", "MUX2")
 ARITY = np.array([1, 1, 2, 2, 2, 2, 2, 3, 3], dtype=np.int32)
 
@@ -57,6 +59,8 @@ class Netlist:
     fanin_ptr: np.ndarray  # int32 [G+1]
     fanin: np.ndarray      # int32 [sum of arities]
     stats: dict = dataclasses.field(default_factory=dict)
+    # library cells (Boolean expressions); gate opcode CELL_BASE + c is cell c
+    cells: tuple = ()
 
     @property
     def n_gates(self) -> int:
@@ -65,6 +69,36 @@ class Netlist:
     @property
     def n_nets(self) -> int:
         return self.n_pi + self.n_gates
+
+
+def cell_arity(expr: str) -> int:
+    """Inputs of a library cell: its distinct identifiers."""
+    return len(dict.fromkeys(re.findall(r"[A-Za-z_][A-Za-z0-9_]*", expr)))
+
+
+def arity_table(cells=()) -> np.ndarray:
+    """Arity of every opcode: the nine fixed cells, then the library."""
+    t = np.zeros(CELL_BASE + len(cells), dtype=np.int32)
+    t[:9] = ARITY
+    for c, e in enumerate(cells):
+        t[CELL_BASE + c] = cell_arity(e)
+    return t
+
+
+# A small cell library for the generic-cell workloads: read-once cells with
+# up to six inputs, a read-many majority, the multiplexer as an expression
+# and a constant.
+LIBRARY = (
+    "!((A1&A2)|(B1&B2))",    # AOI22
+    "!((A1|A2)&B)",          # OAI21
+    "A&B|A&C|B&C",           # MAJ3 (inputs read twice)
+    "!(A^B)",                # XNOR2
+    "(A&B)|(C&D)|(E&F)",     # AO222
+    "(I0&!S)|(I1&S)",        # MUX2 written out (S read twice)
+    "A&!B",                  # AND with an inverted input
+    "A|B|C|D",               # OR4
+    "1^A",                   # a constant operand
+)
 
 
 @dataclasses.dataclass
@@ -76,6 +110,7 @@ class DagSpec:
     fo_mean: float = 2.5
     fo_cap: int = 64
     ops: tuple = tuple(range(9))
+    cells: tuple = ()
 
 
 # The workloads measured by this project (sizes, PI counts, depths, fan-out).
@@ -118,6 +153,8 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
     if D < 1 or G < D:
         raise ValueError("need at least one gate per level")
     ops_choice = np.asarray(spec.ops, dtype=np.int32)
+    arity = arity_table(spec.cells)
+    kmax = max(3, int(arity[ops_choice].max()))
     widths = np.full(D, G // D, dtype=np.int64)
     widths[: G % D] += 1
     n_nets = n_pi + G
@@ -127,7 +164,7 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
     lvl_start[2:] = n_pi + np.cumsum(widths)
     budget = _budgets(rng, n_nets, spec.fo_mean, spec.fo_cap)
     op = np.empty(G, dtype=np.uint8)
-    pins = np.full((G, 3), -1, dtype=np.int64)
+    pins = np.full((G, kmax), -1, dtype=np.int64)
     n_reconv = 0
     n_other = 0
     for L in range(1, D + 1):
@@ -135,7 +172,7 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
         w = int(b - a)
         gop = ops_choice[rng.integers(0, ops_choice.shape[0], size=w)]
         op[a:b] = gop
-        k = ARITY[gop]
+        k = arity[gop]
         # weights: remaining budget, with a floor so exhausted nets stay reachable
         wts = np.maximum(budget[: lvl_start[L]], 0).astype(np.float64) + 1e-3
         prev_lo, prev_hi = lvl_start[L - 1], lvl_start[L]
@@ -143,7 +180,7 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
         cdf_all = np.cumsum(wts)
         p0 = prev_lo + _weighted_pick(rng, cdf_prev, w)
         pins[a:b, 0] = p0
-        for j in (1, 2):
+        for j in range(1, kmax):
             need = np.nonzero(k > j)[0]
             if need.size == 0:
                 continue
@@ -153,7 +190,7 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
             want = (rng.random(need.size) < spec.reconv) & (drv >= 0)
             if want.any():
                 dg = drv[want]
-                dk = ARITY[op[dg]]
+                dk = arity[op[dg]]
                 slot = (rng.random(dg.size) * dk).astype(np.int64)
                 choice[want] = pins[dg, slot]
                 n_reconv += int(want.sum())
@@ -161,11 +198,15 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
         # enforce distinct inputs within a gate by redrawing colliding pins
         for _ in range(100):
             blk = pins[a:b]
-            dup1 = (k > 1) & (blk[:, 1] == blk[:, 0])
-            dup2 = (k > 2) & ((blk[:, 2] == blk[:, 0]) | (blk[:, 2] == blk[:, 1]))
-            if not (dup1.any() or dup2.any()):
+            dups = []
+            for j in range(1, kmax):
+                dj = np.zeros(w, dtype=bool)
+                for i in range(j):
+                    dj |= blk[:, j] == blk[:, i]
+                dups.append((j, (k > j) & dj))
+            if not any(d.any() for _, d in dups):
                 break
-            for j, dup in ((1, dup1), (2, dup2)):
+            for j, dup in dups:
                 idx = np.nonzero(dup)[0]
                 if idx.size:
                     pins[a + idx, j] = _weighted_pick(rng, cdf_all, idx.size)
@@ -180,14 +221,14 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
     net_map[n_pi:] = n_pi + perm
     c_op = np.empty(G, dtype=np.uint8)
     c_op[perm] = op
-    c_pins = np.full((G, 3), -1, dtype=np.int64)
+    c_pins = np.full((G, kmax), -1, dtype=np.int64)
     m = pins >= 0
     mapped = np.where(m, net_map[np.where(m, pins, 0)], -1)
     c_pins[perm] = mapped
-    k = ARITY[c_op]
+    k = arity[c_op]
     fanin_ptr = np.zeros(G + 1, dtype=np.int32)
     fanin_ptr[1:] = np.cumsum(k)
-    mask = np.arange(3)[None, :] < k[:, None]
+    mask = np.arange(kmax)[None, :] < k[:, None]
     fanin = c_pins[mask].astype(np.int32)
     fo = np.bincount(pins[m].ravel(), minlength=n_nets)
     stats = dict(
@@ -200,24 +241,26 @@ def random_dag(spec: DagSpec, seed: int) -> Netlist:
         reconvergent_pin_fraction=(n_reconv / n_other) if n_other else 0.0,
         seed=seed,
     )
-    return Netlist(n_pi=n_pi, op=c_op, fanin_ptr=fanin_ptr, fanin=fanin, stats=stats)
+    return Netlist(n_pi=n_pi, op=c_op, fanin_ptr=fanin_ptr, fanin=fanin, stats=stats,
+                   cells=tuple(spec.cells))
 
 
-def from_gates(n_pi: int, gates) -> Netlist:
+def from_gates(n_pi: int, gates, cells=()) -> Netlist:
     """Build a netlist from a list of ``(op, [input nets])`` in caller order."""
     op = np.array([g[0] for g in gates], dtype=np.uint8)
     k = [len(g[1]) for g in gates]
     fanin_ptr = np.zeros(len(gates) + 1, dtype=np.int32)
     fanin_ptr[1:] = np.cumsum(k)
     fanin = np.array([n for g in gates for n in g[1]], dtype=np.int32)
-    return Netlist(n_pi=n_pi, op=op, fanin_ptr=fanin_ptr, fanin=fanin)
+    return Netlist(n_pi=n_pi, op=op, fanin_ptr=fanin_ptr, fanin=fanin, cells=tuple(cells))
 
 
-def random_tree(n_leaves: int, seed: int, ops=tuple(range(9))) -> Netlist:
+def random_tree(n_leaves: int, seed: int, ops=tuple(range(9)), cells=()) -> Netlist:
     """A random fan-out-free tree: every net (PI or gate output) feeds at most
     one gate pin, so the inputs of every gate are independent signals."""
     rng = np.random.default_rng(seed)
     ops = np.asarray(ops, dtype=np.int32)
+    ARITY = arity_table(cells)
     free = list(range(n_leaves))  # nets not yet consumed
     gates = []
     while len(free) > 1 or not gates:
@@ -230,7 +273,7 @@ def random_tree(n_leaves: int, seed: int, ops=tuple(range(9))) -> Netlist:
         free.append(n_leaves + len(gates) - 1)
         if len(gates) > 20 * n_leaves:
             break
-    return from_gates(n_leaves, gates)
+    return from_gates(n_leaves, gates, cells)
 
 
 def pi_probs(n_pi: int, seed: int, batch: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:

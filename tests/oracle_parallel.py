@@ -11,10 +11,10 @@ import numpy as np
 _NL = None
 
 
-def _init(n_pi, op, fanin_ptr, fanin):
+def _init(n_pi, op, fanin_ptr, fanin, cells):
     global _NL
     import oracle
-    _NL = oracle.Netlist(n_pi, op, fanin_ptr, fanin)
+    _NL = oracle.Netlist(n_pi, op, fanin_ptr, fanin, cells)
 
 
 def _run(args):
@@ -30,7 +30,8 @@ def sim_counts(nl, p, n_words, seed, workers=None):
             for i in range(workers) if bounds[i + 1] > bounds[i]]
     ctx = mp.get_context("spawn")
     with ctx.Pool(len(jobs), initializer=_init,
-                  initargs=(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin)) as pool:
+                  initargs=(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin,
+                            tuple(getattr(nl, "cells", ())))) as pool:
         parts = pool.map(_run, jobs)
     ones = sum(x[0] for x in parts)
     tog = sum(x[1] for x in parts)
