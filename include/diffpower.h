@@ -91,7 +91,10 @@ enum {
   DP_SCHED_PERSISTENT = 3 /* SP-only sweeps (modeled forward, reverse sweep) as
                              one cooperative launch with a grid barrier per
                              level; the simulation keeps one launch per level.
-                             Opt-in: the autotuner does not pick it */
+                             Opt-in: the autotuner does not pick it.  Fixed
+                             cells only: dp_eval_set_schedule returns
+                             DP_E_UNSUPPORTED for a design with library-cell
+                             gates */
 };
 
 typedef struct dp_ctx dp_ctx;
@@ -106,7 +109,7 @@ typedef struct dp_server dp_server;
 typedef struct {
   int32_t n_pi;
   int32_t n_gates;
-  const uint8_t *op;        /* [n_gates] DP_INV .. DP_MUX2 */
+  const uint8_t *op;        /* [n_gates] DP_INV .. DP_MUX2, or DP_CELL_BASE + c */
   const int32_t *fanin_ptr; /* [n_gates + 1], fanin_ptr[0] = 0 */
   const int32_t *fanin;     /* [fanin_ptr[n_gates]] net ids */
 } dp_netlist;
@@ -188,6 +191,26 @@ void dp_ctx_destroy(dp_ctx *ctx);
  * Host inputs only; they are copied.  Errors: DP_E_INVALID, DP_E_CYCLE,
  * DP_E_OOM, DP_E_HIP. */
 dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out);
+
+/* The same with a cell library (Sec. III-A, Alg. 1-3): cells[c] is the
+ * Boolean function of library cell c, and a gate whose opcode is
+ * DP_CELL_BASE + c is an instance of it.  Grammar: identifiers, 0, 1,
+ * parentheses, NOT '!' or '~' (binds tightest), then AND '&' or '*', XOR '^',
+ * OR '|' or '+', binary operators left associative.  A cell's inputs are its
+ * distinct identifiers in order of first appearance, and a gate's fan-in
+ * list follows that order; at most 6 inputs, 32 operations, 8 stack entries.
+ * Each expression is compiled to post-order stack code that the level
+ * kernels interpret operation by operation (the probability of an operation
+ * assumes independent operands, so an expression that reads an input twice,
+ * such as a multiplexer written out, gets the paper's op-by-op value), with
+ * reverse-mode partials over the same code; library-cell gates run in
+ * kernels of their own after a level's fixed cells.  An expression whose
+ * code is one of the fixed cells' (for example "A&B" or "!((A&B)|C)") runs
+ * as that cell.  n_cells <= 240; copies the expressions.  Errors as dp_compile,
+ * plus DP_E_INVALID for an expression that does not compile. */
+#define DP_CELL_BASE 16
+dp_status dp_compile_cells(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cells,
+                           const char *const *cells, dp_design **out);
 dp_status dp_design_info(const dp_design *design, dp_design_info_t *out);
 /* Level of every net in caller numbering ([n_nets], host). */
 dp_status dp_design_levels(const dp_design *design, int32_t *level);

@@ -20,6 +20,7 @@ _st = ctypes.c_int
 DP_OK, DP_E_INVALID, DP_E_CYCLE, DP_E_OOM, DP_E_HIP, DP_E_UNSUPPORTED, DP_E_STATE, DP_E_BUDGET, \
     DP_E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8
 DP_MODELED, DP_HYBRID, DP_FROZEN_BETA = 0, 1, 2
+DP_CELL_BASE = 16
 DP_BETA_LOCAL, DP_BETA_STE = 0, 1
 DP_SCHED_AUTO, DP_SCHED_LEVEL, DP_SCHED_GRAPH, DP_SCHED_PERSISTENT = 0, 1, 2, 3
 DP_Q_FWD, DP_Q_FWD_BWD = 0, 1
@@ -80,6 +81,7 @@ SIGNATURES = {
     "dp_ctx_synchronize": (_st, [_p]),
     "dp_ctx_destroy": (None, [_p]),
     "dp_compile": (_st, [_p, _p, _p]),
+    "dp_compile_cells": (_st, [_p, _p, _i32, _p, _p]),
     "dp_design_info": (_st, [_p, _p]),
     "dp_design_levels": (_st, [_p, _p]),
     "dp_design_destroy": (None, [_p]),

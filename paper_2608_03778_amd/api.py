@@ -87,7 +87,13 @@ class Design:
         nl = L.Netlist(int(netlist.n_pi), int(op.shape[0]), op.ctypes.data, ptr.ctypes.data,
                        fan.ctypes.data)
         h = ctypes.c_void_p()
-        check(self.lib.dp_compile(ctx.handle, ctypes.byref(nl), ctypes.byref(h)))
+        cells = [c.encode() for c in getattr(netlist, "cells", ()) or ()]
+        if cells:
+            arr = (ctypes.c_char_p * len(cells))(*cells)
+            check(self.lib.dp_compile_cells(ctx.handle, ctypes.byref(nl), len(cells),
+                                            ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(h)))
+        else:
+            check(self.lib.dp_compile(ctx.handle, ctypes.byref(nl), ctypes.byref(h)))
         self.handle = h
         info = L.DesignInfo()
         check(self.lib.dp_design_info(h, ctypes.byref(info)))

@@ -60,10 +60,23 @@ dp::GraphView view(const dp_design *d) {
   g.rev_ptr = d->rev_ptr.as<int32_t>();
   g.rev_edge = d->rev_edge.as<int32_t>();
   g.slot = d->slot.as<int32_t>();
+  g.code = d->code.as<uint16_t>();
+  g.cell = d->cell.as<int32_t>();
+  g.pins = d->pins;
   g.n_pi = d->n_pi;
   g.G = d->n_gates;
   g.n_nets = d->n_nets;
   return g;
+}
+
+// Level l as launch ranges: its fixed cells, then its library cells (ops
+// sort ascending inside a level), each range of one kind; f(g0, n, cells).
+template <class F>
+dp_status for_level_parts(const dp_design *d, int32_t l, F &&f) {
+  const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0, nf = d->lvl_fixed[l];
+  if (nf > 0) DP_TRY(f(g0, nf, false));
+  if (nf < n) DP_TRY(f(g0 + nf, n - nf, true));
+  return DP_OK;
 }
 
 int32_t s_prime(const dp_eval *ev) { return (ev->S > 0 && !ev->paired_sizes) ? ev->S : 1; }
@@ -263,7 +276,7 @@ float *beta_or_null(dp_eval *ev) {
 
 // Kernel launches of one forward sweep (what a captured graph would hold).
 int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
-  const int64_t depth = ev->d->depth;
+  const int64_t depth = ev->d->depth + ev->d->split_levels;
   if (!pl) return depth + 2;
   return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4;
 }
@@ -343,10 +356,11 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
                                         (int64_t)d->max_level_width * ev->B, cs);
       }));
     } else {
-      for (int32_t l = 1; l <= d->depth; ++l) {
-        dp::SpLevel lv{sp, ev->B, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l]};
-        DP_HIP_TRY(dp::launch_sp_level(g, lv, s));
-      }
+      for (int32_t l = 1; l <= d->depth; ++l)
+        DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
+          DP_HIP_TRY(dp::launch_sp_level(g, dp::SpLevel{sp, ev->B, g0, n}, cells, s));
+          return DP_OK;
+        }));
     }
   } else {
     const size_t nb = (size_t)d->n_nets * ev->B;
@@ -380,11 +394,12 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       for (int32_t l = 1; l <= d->depth; ++l) bytes += sim_level_bytes(d, l, nw, ev->B, fuse);
       // one span over the piece's level launches (their back-to-back time)
       SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth, ls);
-      for (int32_t l = 1; l <= d->depth; ++l) {
-        const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-        dp::SpLevel lv{sp, ev->B, g0, n};
-        DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, tune, ls));
-      }
+      for (int32_t l = 1; l <= d->depth; ++l)
+        DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
+          const dp::SpLevel lv{sp, ev->B, g0, n};
+          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, cells, tune, ls));
+          return DP_OK;
+        }));
     }
     if (L > 1)
       for (int32_t i = 1; i < L; ++i) {
@@ -604,10 +619,11 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
   }
   {
     SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
-    for (int32_t l = d->depth; l >= 1; --l) {
-      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-      DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, s));
-    }
+    for (int32_t l = d->depth; l >= 1; --l)
+      DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
+        DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, cells, s));
+        return DP_OK;
+      }));
   }
   DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
   return DP_OK;
@@ -705,7 +721,16 @@ dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(DP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
   }
-  return dp::compile_design(ctx, netlist, out);
+  return dp::compile_design(ctx, netlist, 0, nullptr, out);
+}
+
+dp_status dp_compile_cells(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cells,
+                           const char *const *cells, dp_design **out) {
+  if (ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(DP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  return dp::compile_design(ctx, netlist, n_cells, cells, out);
 }
 
 dp_status dp_design_info(const dp_design *d, dp_design_info_t *out) {
@@ -863,6 +888,9 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_
   if (!(sim_pairs_per_lane == 0 || sim_pairs_per_lane == 1 || sim_pairs_per_lane == 2 ||
         sim_pairs_per_lane == 4 || sim_pairs_per_lane == 8))
     return fail(DP_E_INVALID, "dp_eval_set_schedule: sim_pairs_per_lane must be 0, 1, 2, 4 or 8");
+  if (schedule == DP_SCHED_PERSISTENT && ev->d->has_cell_gates)
+    return fail(DP_E_UNSUPPORTED,
+                "dp_eval_set_schedule: the persistent schedule runs the fixed cells only");
   ev->schedule = schedule;
   ev->words_per_chunk = words_per_chunk;
   ev->sim_iters = sim_pairs_per_lane;
@@ -1165,10 +1193,11 @@ dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, fl
     const dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), B, b};
     DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, ev->sp.as<float>(),
                                    stim.as<uint64_t>() + (size_t)b * d->n_pi * 2, 2, 0, tune, s));
-    for (int32_t l = 1; l <= d->depth; ++l) {
-      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-      DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, nullptr, tune, s));
-    }
+    for (int32_t l = 1; l <= d->depth; ++l)
+      DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
+        DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, nullptr, cells, tune, s));
+        return DP_OK;
+      }));
   }
   DP_HIP_TRY(dp::launch_virus_power(ev->tog.as<uint32_t>(), ev->cap.as<float>(), d->n_nets, B,
                                     pv.as<double>(), s));
@@ -1196,6 +1225,104 @@ constexpr int32_t kGroupBranches = 4;  // streams beyond the hardware queues onl
 // Host threads that enqueue a group's branches side by side: a launch-bound
 // sweep is limited by how fast one thread submits kernels, so each branch
 // gets a thread of its own.  Workers live as long as the group.
+namespace dp {
+
+namespace {
+// Range of level l of one kind: fixed cells first, then library cells.
+void level_part(const dp_design *d, int32_t l, int k, int32_t *g0, int32_t *n) {
+  const int32_t a = d->level_ptr[l], nl = d->level_ptr[l + 1] - a, nf = d->lvl_fixed[l];
+  *g0 = k == 0 ? a : a + nf;
+  *n = k == 0 ? nf : nl - nf;
+}
+}  // namespace
+
+void MergedTables::build(const Lane *lanes, int32_t n) {
+  D = 0;
+  for (int32_t j = 0; j < n; ++j) D = std::max(D, lanes[j].ev->d->depth);
+  fs.clear();
+  bs.clear();
+  const size_t m = 2 * (size_t)(D + 1);
+  f_off.assign(m, 0);
+  f_cnt.assign(m, 0);
+  b_off.assign(m, 0);
+  b_cnt.assign(m, 0);
+  f_blk.assign(m, 0);
+  b_blk.assign(m, 0);
+  for (int32_t l = 1; l <= D; ++l)
+    for (int k = 0; k < 2; ++k) {
+      const size_t i = 2 * (size_t)l + k;
+      f_off[i] = (int32_t)fs.size();
+      b_off[i] = (int32_t)bs.size();
+      for (int32_t j = 0; j < n; ++j) {
+        dp_eval *ev = lanes[j].ev;
+        const dp_design *d = ev->d;
+        if (l > d->depth) continue;
+        int32_t g0, cnt;
+        level_part(d, l, k, &g0, &cnt);
+        if (cnt == 0) continue;
+        const uint32_t blocks = (uint32_t)(((int64_t)cnt * ev->B + 255) / 256);
+        fs.push_back({view(d), SpLevel{ev->sp.as<float>(), ev->B, g0, cnt}, f_blk[i]});
+        f_blk[i] += blocks;
+        if (lanes[j].backward) {
+          bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, cnt, b_blk[i]});
+          b_blk[i] += blocks;
+        }
+      }
+      f_cnt[i] = (int32_t)fs.size() - f_off[i];
+      b_cnt[i] = (int32_t)bs.size() - b_off[i];
+    }
+}
+
+int64_t MergedTables::level_launches(const Lane *lanes, int32_t n) {
+  int32_t depth = 0;
+  for (int32_t j = 0; j < n; ++j) depth = std::max(depth, lanes[j].ev->d->depth);
+  int64_t c = 0;
+  for (int32_t l = 1; l <= depth; ++l)
+    for (int k = 0; k < 2; ++k) {
+      bool any = false;
+      for (int32_t j = 0; j < n && !any; ++j) {
+        const dp_design *d = lanes[j].ev->d;
+        int32_t g0, cnt = 0;
+        if (l <= d->depth) level_part(d, l, k, &g0, &cnt);
+        any = cnt > 0;
+      }
+      c += any;
+    }
+  return c;
+}
+
+size_t MergedTables::bwd_offset() const { return (fs.size() * sizeof(SpSeg) + 255) & ~(size_t)255; }
+
+size_t MergedTables::bytes() const {
+  return std::max<size_t>(bwd_offset() + bs.size() * sizeof(BwdSeg), 256);
+}
+
+void MergedTables::pack(void *host) const {
+  if (!fs.empty()) std::memcpy(host, fs.data(), fs.size() * sizeof(SpSeg));
+  if (!bs.empty())
+    std::memcpy((char *)host + bwd_offset(), bs.data(), bs.size() * sizeof(BwdSeg));
+}
+
+dp_status MergedTables::launch_forward(const SpSeg *dev, hipStream_t s) const {
+  for (int32_t l = 1; l <= D; ++l)
+    for (int k = 0; k < 2; ++k) {
+      const size_t i = 2 * (size_t)l + k;
+      DP_HIP_TRY(launch_sp_multi(dev + f_off[i], f_cnt[i], f_blk[i], k == 1, s));
+    }
+  return DP_OK;
+}
+
+dp_status MergedTables::launch_reverse(const BwdSeg *dev, hipStream_t s) const {
+  for (int32_t l = D; l >= 1; --l)
+    for (int k = 0; k < 2; ++k) {
+      const size_t i = 2 * (size_t)l + k;
+      DP_HIP_TRY(launch_bwd_multi(dev + b_off[i], b_cnt[i], b_blk[i], k == 1, s));
+    }
+  return DP_OK;
+}
+
+}  // namespace dp
+
 struct GroupPool {
   std::vector<std::thread> workers;
   std::mutex mu;
@@ -1246,13 +1373,13 @@ struct GroupPool {
 struct dp_group {
   GroupPool pool;
   // Merged level launches of the group's modeled evals (one launch per level
-  // index covers that level of every such eval): device segment tables and,
-  // per level l, the offset of its first segment, the count and the blocks.
+  // index and kind covers that level of every such eval): host tables and
+  // their device copy (forward segments, then reverse at tab_dev_bwd).
   std::vector<int32_t> merged;      // eval indices
-  int32_t max_depth = 0;
-  dp::DevBuf fwd_segs, bwd_segs;
-  std::vector<int32_t> f_off, f_cnt, b_off, b_cnt;
-  std::vector<uint32_t> f_blocks, b_blocks;
+  dp::MergedTables tab;
+  dp::DevBuf tab_dev;
+  size_t tab_dev_bwd = 0;
+  bool have_tables = false;
   uint64_t tables_key = 0;
   dp_ctx *ctx = nullptr;
   std::vector<dp_eval *> evs;
@@ -1299,49 +1426,16 @@ void assign_branches(dp_group *g, const std::vector<int64_t> &cost) {
 // Fork from `origin` into the branches, enqueue each eval's forward (and
 // reverse) sweep on its branch with per-level launches, join back.
 // Segment tables of the merged level launches (host work, one upload).
-// Segments start on block boundaries, so a block (and its waves) belongs to
-// one design.
 dp_status build_merged_tables(dp_group *g) {
-  g->max_depth = 0;
-  for (int32_t i : g->merged) g->max_depth = std::max(g->max_depth, g->evs[i]->d->depth);
-  const int32_t D = g->max_depth;
-  std::vector<dp::SpSeg> fs;
-  std::vector<dp::BwdSeg> bs;
-  g->f_off.assign(D + 2, 0);
-  g->f_cnt.assign(D + 2, 0);
-  g->f_blocks.assign(D + 2, 0);
-  g->b_off = g->f_off;
-  g->b_cnt = g->f_cnt;
-  g->b_blocks = g->f_blocks;
-  for (int32_t l = 1; l <= D; ++l) {
-    g->f_off[l] = (int32_t)fs.size();
-    g->b_off[l] = (int32_t)bs.size();
-    uint32_t fb = 0, bb = 0;
-    for (int32_t i : g->merged) {
-      dp_eval *ev = g->evs[i];
-      const dp_design *d = ev->d;
-      if (l > d->depth) continue;
-      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-      if (n == 0) continue;
-      const uint32_t blocks = (uint32_t)(((int64_t)n * ev->B + 255) / 256);
-      fs.push_back({view(d), dp::SpLevel{ev->sp.as<float>(), ev->B, g0, n}, fb});
-      bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, n, bb});
-      fb += blocks;
-      bb += blocks;
-    }
-    g->f_cnt[l] = (int32_t)fs.size() - g->f_off[l];
-    g->b_cnt[l] = (int32_t)bs.size() - g->b_off[l];
-    g->f_blocks[l] = fb;
-    g->b_blocks[l] = bb;
-  }
-  DP_TRY(g->fwd_segs.alloc(std::max<size_t>(fs.size() * sizeof(dp::SpSeg), 16)));
-  DP_TRY(g->bwd_segs.alloc(std::max<size_t>(bs.size() * sizeof(dp::BwdSeg), 16)));
-  if (!fs.empty())
-    DP_HIP_TRY(hipMemcpy(g->fwd_segs.ptr, fs.data(), fs.size() * sizeof(dp::SpSeg),
-                         hipMemcpyHostToDevice));
-  if (!bs.empty())
-    DP_HIP_TRY(hipMemcpy(g->bwd_segs.ptr, bs.data(), bs.size() * sizeof(dp::BwdSeg),
-                         hipMemcpyHostToDevice));
+  std::vector<dp::MergedTables::Lane> lanes;
+  for (int32_t i : g->merged) lanes.push_back({g->evs[i], true});
+  g->tab.build(lanes.data(), (int32_t)lanes.size());
+  g->tab_dev_bwd = g->tab.bwd_offset();
+  DP_TRY(g->tab_dev.alloc(g->tab.bytes()));
+  std::vector<char> host(g->tab.bytes());
+  g->tab.pack(host.data());
+  DP_HIP_TRY(hipMemcpy(g->tab_dev.ptr, host.data(), host.size(), hipMemcpyHostToDevice));
+  g->have_tables = true;
   return DP_OK;
 }
 
@@ -1350,10 +1444,9 @@ dp_status build_merged_tables(dp_group *g) {
 // eval's PI adjoints.
 dp_status enqueue_merged(dp_group *g, hipStream_t origin, bool backward) {
   if (g->merged.empty()) return DP_OK;
-  const dp::SpSeg *fs = g->fwd_segs.as<dp::SpSeg>();
-  const dp::BwdSeg *bs = g->bwd_segs.as<dp::BwdSeg>();
-  for (int32_t l = 1; l <= g->max_depth; ++l)
-    DP_HIP_TRY(dp::launch_sp_multi(fs + g->f_off[l], g->f_cnt[l], g->f_blocks[l], origin));
+  const dp::SpSeg *fs = g->tab_dev.as<dp::SpSeg>();
+  const auto *bs = reinterpret_cast<const dp::BwdSeg *>((char *)g->tab_dev.ptr + g->tab_dev_bwd);
+  DP_TRY(g->tab.launch_forward(fs, origin));
   for (int32_t i : g->merged) {
     dp_eval *ev = g->evs[i];
     ev->branch = origin;
@@ -1362,8 +1455,7 @@ dp_status enqueue_merged(dp_group *g, hipStream_t origin, bool backward) {
     DP_TRY(st);
   }
   if (!backward) return DP_OK;
-  for (int32_t l = g->max_depth; l >= 1; --l)
-    DP_HIP_TRY(dp::launch_bwd_multi(bs + g->b_off[l], g->b_cnt[l], g->b_blocks[l], origin));
+  DP_TRY(g->tab.launch_reverse(bs, origin));
   for (int32_t i : g->merged) {
     dp_eval *ev = g->evs[i];
     DP_HIP_TRY(dp::launch_bwd_pi(view(ev->d), backward_args(ev, nullptr, 0, ev->B),
@@ -1508,7 +1600,7 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
     if (backward) {
       DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * ev->B * sizeof(float), 16)));
       DP_TRY(ev->pi_out.alloc(std::max<size_t>((size_t)ev->B * d->n_pi * sizeof(float), 16)));
-      cost[i] += d->depth + 1;
+      cost[i] += d->depth + d->split_levels + 1;
     }
     launches += cost[i];
     const int32_t sched = ev->schedule;
@@ -1533,9 +1625,10 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
       cost[i] = 0;
     }
   if (!g->merged.empty()) {
-    int32_t D = 0;
-    for (int32_t i : g->merged) D = std::max(D, g->evs[i]->d->depth);
-    launches += D * (backward ? 2 : 1) + (int64_t)g->merged.size() * (backward ? 4 : 3);
+    std::vector<dp::MergedTables::Lane> lanes;
+    for (int32_t i : g->merged) lanes.push_back({g->evs[i], true});
+    const int64_t per_sweep = dp::MergedTables::level_launches(lanes.data(), (int32_t)lanes.size());
+    launches += per_sweep * (backward ? 2 : 1) + (int64_t)g->merged.size() * (backward ? 4 : 3);
   }
   const int32_t want = g->max_branches > 0 ? g->max_branches : kGroupBranches;
   const int32_t nb = std::max<int32_t>(1, std::min<int32_t>({want, (int32_t)g->branch.size(), (int32_t)n}));
@@ -1549,7 +1642,7 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
     std::vector<hipStream_t> all;
     ~Restore() { g->branch = all; }
   } restore{g, all};
-  if (g->tables_key != key || g->f_off.empty()) {
+  if (g->tables_key != key || !g->have_tables) {
     DP_HIP_TRY(hipStreamSynchronize(s));  // no run reads the old tables
     DP_TRY(build_merged_tables(g));
     g->tables_key = key;
@@ -1716,7 +1809,10 @@ dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bo
     ba.ste = ev->prm.beta_grad == DP_BETA_STE;
     ba.paired = ev->paired_sizes;
     for (int32_t l = d->depth; l >= 1; --l)
-      DP_HIP_TRY(launch_bwd_level(g, ba, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l], s));
+      DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
+        DP_HIP_TRY(launch_bwd_level(g, ba, g0, n, cells, s));
+        return DP_OK;
+      }));
     DP_HIP_TRY(launch_bwd_pi(g, ba, ev->pi_out.as<float>(), s));
     if (dpi && d->n_pi > 0)
       DP_HIP_TRY(hipMemcpyAsync(dpi, ev->pi_out.ptr, (size_t)n * d->n_pi * 4,
@@ -1754,40 +1850,19 @@ dp_status lane_stage(dp_eval *ev, int32_t n, const float *p, const float *size, 
 
 dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t s,
                            StepScratch *sc) {
-  int32_t D = 0;
-  for (int32_t j = 0; j < n_jobs; ++j) {
+  for (int32_t j = 0; j < n_jobs; ++j)
     DP_TRY(lane_stage(jobs[j].ev, jobs[j].n, jobs[j].p, jobs[j].size, s));
-    D = std::max(D, jobs[j].ev->d->depth);
-  }
   // segment tables: forward over every lane, reverse over the lanes that
-  // want gradients; level l's segments are contiguous
-  std::vector<SpSeg> fs;
-  std::vector<BwdSeg> bs;
-  std::vector<int32_t> f_off(D + 2, 0), f_cnt(D + 2, 0), b_off(D + 2, 0), b_cnt(D + 2, 0);
-  std::vector<uint32_t> f_blk(D + 2, 0), b_blk(D + 2, 0);
-  for (int32_t l = 1; l <= D; ++l) {
-    f_off[l] = (int32_t)fs.size();
-    b_off[l] = (int32_t)bs.size();
-    for (int32_t j = 0; j < n_jobs; ++j) {
-      dp_eval *ev = jobs[j].ev;
-      const dp_design *d = ev->d;
-      if (l > d->depth) continue;
-      const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0;
-      if (n == 0) continue;
-      const uint32_t blocks = (uint32_t)(((int64_t)n * ev->B + 255) / 256);
-      fs.push_back({view(d), SpLevel{ev->sp.as<float>(), ev->B, g0, n}, f_blk[l]});
-      f_blk[l] += blocks;
-      if (jobs[j].backward) {
-        bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, n, b_blk[l]});
-        b_blk[l] += blocks;
-      }
-    }
-    f_cnt[l] = (int32_t)fs.size() - f_off[l];
-    b_cnt[l] = (int32_t)bs.size() - b_off[l];
+  // want gradients
+  std::vector<MergedTables::Lane> lanes(n_jobs);
+  bool any_backward = false;
+  for (int32_t j = 0; j < n_jobs; ++j) {
+    lanes[j] = {jobs[j].ev, jobs[j].backward};
+    any_backward = any_backward || jobs[j].backward;
   }
-  const size_t f_bytes = fs.size() * sizeof(SpSeg);
-  const size_t b_offset = (f_bytes + 255) & ~(size_t)255;
-  const size_t bytes = std::max<size_t>(b_offset + bs.size() * sizeof(BwdSeg), 256);
+  MergedTables tab;
+  tab.build(lanes.data(), n_jobs);
+  const size_t bytes = tab.bytes();
   if (bytes > sc->cap) {
     if (sc->host) (void)hipHostFree(sc->host);
     sc->host = nullptr;
@@ -1796,12 +1871,11 @@ dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t s,
     DP_TRY(sc->dev.alloc(bytes));
     sc->cap = bytes;
   }
-  if (!fs.empty()) std::memcpy(sc->host, fs.data(), f_bytes);
-  if (!bs.empty()) std::memcpy((char *)sc->host + b_offset, bs.data(), bs.size() * sizeof(BwdSeg));
+  tab.pack(sc->host);
   DP_HIP_TRY(hipMemcpyAsync(sc->dev.ptr, sc->host, bytes, hipMemcpyHostToDevice, s));
   const SpSeg *fd = sc->dev.as<SpSeg>();
-  const BwdSeg *bd = reinterpret_cast<const BwdSeg *>((char *)sc->dev.ptr + b_offset);
-  for (int32_t l = 1; l <= D; ++l) DP_HIP_TRY(launch_sp_multi(fd + f_off[l], f_cnt[l], f_blk[l], s));
+  const BwdSeg *bd = reinterpret_cast<const BwdSeg *>((char *)sc->dev.ptr + tab.bwd_offset());
+  DP_TRY(tab.launch_forward(fd, s));
   for (int32_t j = 0; j < n_jobs; ++j) {
     dp_eval *ev = jobs[j].ev;
     ev->branch = s;
@@ -1811,8 +1885,8 @@ dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t s,
     DP_HIP_TRY(hipMemcpyAsync(jobs[j].power, ev->power.ptr, (size_t)jobs[j].n * 4,
                               hipMemcpyDeviceToHost, s));
   }
-  if (bs.empty()) return DP_OK;
-  for (int32_t l = D; l >= 1; --l) DP_HIP_TRY(launch_bwd_multi(bd + b_off[l], b_cnt[l], b_blk[l], s));
+  if (!any_backward) return DP_OK;
+  DP_TRY(tab.launch_reverse(bd, s));
   for (int32_t j = 0; j < n_jobs; ++j) {
     if (!jobs[j].backward) continue;
     dp_eval *ev = jobs[j].ev;

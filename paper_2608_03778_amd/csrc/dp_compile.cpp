@@ -46,8 +46,29 @@ static dp_status upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
   return DP_OK;
 }
 
-dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
+dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
+                         const char *const *cells, dp_design **out) {
   if (!ctx || !nl || !out) return fail(DP_E_INVALID, "dp_compile: NULL argument");
+  if (n_cells < 0 || n_cells > 256 - kCellBase || (n_cells > 0 && !cells))
+    return fail(DP_E_INVALID, "dp_compile: need 0 <= n_cells <= 240 and a cell array");
+  // library cells: compile each expression; an expression that is one of
+  // the fixed cells runs as that cell
+  std::vector<CellCode> lib(n_cells);
+  std::vector<int> as_fixed(n_cells, -1);
+  for (int32_t c = 0; c < n_cells; ++c) {
+    const std::string err = compile_cell(cells[c], &lib[c]);
+    if (!err.empty())
+      return fail(DP_E_INVALID, "dp_compile: cell " + std::to_string(c) + ": " + err);
+    as_fixed[c] = fixed_op_of(lib[c]);
+  }
+  auto arity_of_op = [&](int op) -> int {
+    if (op < DP_N_OPS) return kArity[op];
+    if (op >= kCellBase && op - kCellBase < n_cells) return lib[op - kCellBase].n_in;
+    return -1;
+  };
+  auto internal_op = [&](int op) -> int {
+    return (op >= kCellBase && as_fixed[op - kCellBase] >= 0) ? as_fixed[op - kCellBase] : op;
+  };
   const int32_t n_pi = nl->n_pi, G = nl->n_gates;
   if (n_pi < 0 || G < 0) return fail(DP_E_INVALID, "dp_compile: negative size");
   if ((int64_t)n_pi + G > INT32_MAX / 2)
@@ -58,10 +79,10 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
   if (G > 0 && nl->fanin_ptr[0] != 0)
     return fail(DP_E_INVALID, "dp_compile: fanin_ptr[0] must be 0");
   for (int32_t g = 0; g < G; ++g) {
-    if (nl->op[g] >= DP_N_OPS)
+    if (arity_of_op(nl->op[g]) < 0)
       return fail(DP_E_INVALID, "dp_compile: gate " + std::to_string(g) + " has unknown cell " +
                                     std::to_string(nl->op[g]));
-    if (nl->fanin_ptr[g + 1] - nl->fanin_ptr[g] != kArity[nl->op[g]])
+    if (nl->fanin_ptr[g + 1] - nl->fanin_ptr[g] != arity_of_op(nl->op[g]))
       return fail(DP_E_INVALID, "dp_compile: gate " + std::to_string(g) +
                                     " has the wrong number of inputs");
     for (int32_t e = nl->fanin_ptr[g]; e < nl->fanin_ptr[g + 1]; ++e)
@@ -108,14 +129,16 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
   for (int32_t g = 0; g < G; ++g) depth = std::max(depth, level[n_pi + g]);
 
   // --- counting sort by (level, cell); stable, so caller id breaks ties
-  const int32_t n_keys = (depth + 1) * DP_N_OPS;
+  constexpr int32_t kOps = 256;
+  const int32_t n_keys = (depth + 1) * kOps;
   std::vector<int32_t> key_ptr(n_keys + 1, 0);
-  for (int32_t g = 0; g < G; ++g) ++key_ptr[level[n_pi + g] * DP_N_OPS + nl->op[g] + 1];
+  for (int32_t g = 0; g < G; ++g) ++key_ptr[level[n_pi + g] * kOps + internal_op(nl->op[g]) + 1];
   for (int32_t k = 0; k < n_keys; ++k) key_ptr[k + 1] += key_ptr[k];
   std::vector<int32_t> gate_of(G);  // internal -> caller gate
   {
     std::vector<int32_t> fill(key_ptr.begin(), key_ptr.end() - 1);
-    for (int32_t g = 0; g < G; ++g) gate_of[fill[level[n_pi + g] * DP_N_OPS + nl->op[g]]++] = g;
+    for (int32_t g = 0; g < G; ++g)
+      gate_of[fill[level[n_pi + g] * kOps + internal_op(nl->op[g])]++] = g;
   }
   auto *d = new dp_design();
   d->ctx = ctx;
@@ -126,7 +149,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
   d->n_edges = n_edges;
   d->level_ptr.assign(depth + 2, 0);
   for (int32_t l = 1; l <= depth + 1; ++l)
-    d->level_ptr[l] = (l <= depth) ? key_ptr[l * DP_N_OPS] : G;
+    d->level_ptr[l] = (l <= depth) ? key_ptr[l * kOps] : G;
   d->level_ptr[0] = 0;
   for (int32_t l = 1; l <= depth; ++l)
     d->max_level_width = std::max(d->max_level_width, d->level_ptr[l + 1] - d->level_ptr[l]);
@@ -138,16 +161,20 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
     d->h_int2ext[n_pi + gi] = n_pi + gate_of[gi];
     d->h_ext2int[n_pi + gate_of[gi]] = n_pi + gi;
   }
+  int32_t pins = 3;
+  for (int32_t g = 0; g < G; ++g) pins = std::max(pins, arity_of_op(nl->op[g]));
+  d->pins = pins;
+  d->n_cells = n_cells;
   d->h_op.resize(G);
   d->h_arity_prefix.assign(G + 1, 0);
-  std::vector<int32_t> in(3 * (size_t)G, 0);
+  std::vector<int32_t> in((size_t)pins * G, 0);
   std::vector<int32_t> rev_ptr(n_nets + 1, 0), rev_edge(n_edges);
   for (int32_t gi = 0; gi < G; ++gi) {
     int32_t g = gate_of[gi];
-    d->h_op[gi] = nl->op[g];
+    d->h_op[gi] = (uint8_t)internal_op(nl->op[g]);
     int32_t k = nl->fanin_ptr[g + 1] - nl->fanin_ptr[g];
     d->h_arity_prefix[gi + 1] = d->h_arity_prefix[gi] + k;
-    for (int32_t j = 0; j < 3; ++j) {
+    for (int32_t j = 0; j < pins; ++j) {
       // unused pins alias pin 0 so that no index is ever out of range
       int32_t e = nl->fanin_ptr[g] + (j < k ? j : 0);
       in[(size_t)j * G + gi] = d->h_ext2int[nl->fanin[e]];
@@ -169,7 +196,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
   // slot[j][g'] = where pin j of gate g' sits in its source net's fan-out
   // list: the reverse sweep writes a pin's contribution there, so a net sums
   // one contiguous range
-  std::vector<int32_t> slot(3 * (size_t)G, 0);
+  std::vector<int32_t> slot((size_t)pins * G, 0);
   for (int64_t e = 0; e < n_edges; ++e) slot[rev_edge[e]] = (int32_t)e;
   d->lvl_pins.assign(depth + 1, 0);
   d->lvl_fanout.assign(depth + 1, 0);
@@ -179,9 +206,28 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
       d->lvl_fanout[l] += rev_ptr[n_pi + gi + 1] - rev_ptr[n_pi + gi];
     }
   d->lvl_fanout[0] = rev_ptr[n_pi] - rev_ptr[0];
+  d->lvl_fixed.assign(depth + 1, 0);
+  for (int32_t l = 1; l <= depth; ++l) {
+    const int32_t g0 = d->level_ptr[l], g1 = d->level_ptr[l + 1];
+    int32_t f = g0;
+    while (f < g1 && d->h_op[f] < kCellBase) ++f;
+    d->lvl_fixed[l] = f - g0;
+    if (f < g1) d->has_cell_gates = true;
+    if (f > g0 && f < g1) ++d->split_levels;
+  }
+  // cell code and table
+  std::vector<uint16_t> code;
+  std::vector<int32_t> cell_tab(3 * (size_t)std::max(n_cells, 1), 0);
+  for (int32_t c = 0; c < n_cells; ++c) {
+    cell_tab[3 * c] = (int32_t)code.size();
+    cell_tab[3 * c + 1] = (int32_t)lib[c].code.size();
+    cell_tab[3 * c + 2] = lib[c].n_in;
+    code.insert(code.end(), lib[c].code.begin(), lib[c].code.end());
+  }
   hipStream_t s = ctx->stream;
   dp_status st = DP_OK;
-  if ((st = upload(d->op, d->h_op, s)) != DP_OK || (st = upload(d->in, in, s)) != DP_OK ||
+  if ((st = upload(d->code, code, s)) != DP_OK || (st = upload(d->cell, cell_tab, s)) != DP_OK ||
+      (st = upload(d->op, d->h_op, s)) != DP_OK || (st = upload(d->in, in, s)) != DP_OK ||
       (st = upload(d->rev_ptr, rev_ptr, s)) != DP_OK ||
       (st = upload(d->rev_edge, rev_edge, s)) != DP_OK ||
       (st = upload(d->slot, slot, s)) != DP_OK ||
@@ -197,7 +243,8 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out) {
     return fail(DP_E_HIP, std::string("dp_compile: upload failed: ") + hipGetErrorString(e));
   }
   d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
-                              d->slot.bytes + d->int2ext.bytes + d->ext2int.bytes);
+                              d->slot.bytes + d->int2ext.bytes + d->ext2int.bytes +
+                              d->code.bytes + d->cell.bytes);
   ctx_retain(ctx);
   *out = d;
   return DP_OK;

@@ -117,6 +117,33 @@ struct LaneJob {
 // gradients.  Each lane's results equal lane_run's bit for bit.
 dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t stream,
                            StepScratch *scratch);
+// Segment tables of merged level launches over several evals (design groups
+// and serving steps): for each level index l and kind k (0: fixed cells,
+// 1: library cells) the segments of every eval's level-l range of that kind,
+// one launch each.  Segments start on block boundaries, so a block belongs to
+// one eval.
+struct MergedTables {
+  struct Lane {
+    dp_eval *ev;
+    bool backward;  // reverse segments too
+  };
+  int32_t D = 0;
+  std::vector<SpSeg> fs;
+  std::vector<BwdSeg> bs;
+  // [2 (D + 1)], index 2 l + k: first segment, segment count, blocks
+  std::vector<int32_t> f_off, f_cnt, b_off, b_cnt;
+  std::vector<uint32_t> f_blk, b_blk;
+  void build(const Lane *lanes, int32_t n);
+  // Launches of one merged sweep (forward or reverse) over these lanes.
+  static int64_t level_launches(const Lane *lanes, int32_t n);
+  // Packed layout: forward segments, then the reverse ones at bwd_offset().
+  size_t bwd_offset() const;
+  size_t bytes() const;
+  void pack(void *host) const;
+  dp_status launch_forward(const SpSeg *dev, hipStream_t s) const;
+  dp_status launch_reverse(const BwdSeg *dev, hipStream_t s) const;
+};
+
 // Hybrid calibration at probability p_all for every PI: beta [n_nets] in
 // internal order into beta_int (device), on the context's stream.
 dp_status calibrate_beta(dp_design *d, const float *cap_ext, const dp_params *prm, float p_all,

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/diffpower.h"
+#include "dp_kernels.h"
 
 namespace dp {
 
@@ -47,6 +48,16 @@ struct DevBuf {
   template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// A library cell compiled to stack code (encoding in dp_kernels.h).
+struct CellCode {
+  std::vector<uint16_t> code;
+  int32_t n_in = 0;
+};
+// Compile one expression; returns an error message, or "" on success.
+std::string compile_cell(const char *text, CellCode *out);
+// The fixed cell (DP_INV ..) a compiled expression equals, or -1.
+int fixed_op_of(const CellCode &cc);
+
 }  // namespace dp
 
 // Contexts and designs are reference counted: a design holds its context,
@@ -77,12 +88,21 @@ struct dp_design {
   int32_t max_level_width = 0;
   std::vector<int64_t> lvl_pins;      // [depth + 1] fan-in pins of the level's gates
   std::vector<int64_t> lvl_fanout;    // [depth + 1] fan-out edges of the level's nets (0 = PIs)
+  // [depth + 1] fixed-cell gates of each level; its library-cell gates follow
+  // them and run in kernels of their own
+  std::vector<int32_t> lvl_fixed;
+  int32_t split_levels = 0;           // levels holding both kinds (one launch more each)
+  bool has_cell_gates = false;
   // device arrays
+  int32_t pins = 3;      // rows of `in` and `slot`: 3, or the widest library cell
+  int32_t n_cells = 0;   // library cells of the design
   dp::DevBuf op;        // uint8 [n_gates]
-  dp::DevBuf in;        // int32 [3][n_gates] input net of pin j (SoA)
+  dp::DevBuf in;        // int32 [pins][n_gates] input net of pin j (SoA)
   dp::DevBuf rev_ptr;   // int32 [n_nets + 1] fan-out list offsets
   dp::DevBuf rev_edge;  // int32 [n_edges] fan-out edges, id = j * n_gates + g'
-  dp::DevBuf slot;      // int32 [3][n_gates] position of pin (g', j) in its source's fan-out list
+  dp::DevBuf slot;      // int32 [pins][n_gates] position of pin (g', j) in its source's fan-out list
+  dp::DevBuf code;      // uint16: the library cells' stack code, concatenated
+  dp::DevBuf cell;      // int32 [n_cells][3]: code offset, length, inputs
   dp::DevBuf level_dev; // int32 [depth + 2] device copy of level_ptr
   dp::DevBuf int2ext;   // int32 [n_nets]
   dp::DevBuf ext2int;   // int32 [n_nets]
@@ -93,7 +113,8 @@ namespace dp {
 
 // Host-side compile: validation, levelization, sort, renumbering and the
 // device upload.  Implemented in dp_compile.cpp.
-dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, dp_design **out);
+dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
+                         const char *const *cells, dp_design **out);
 
 void ctx_retain(dp_ctx *c);
 void ctx_release(dp_ctx *c);

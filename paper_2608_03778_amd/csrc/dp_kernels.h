@@ -8,12 +8,25 @@
 namespace dp {
 
 // Net-level graph arrays in internal numbering (see dp_design).
+// Library cells: the host compiles each expression to post-order code for
+// a stack machine that the kernels interpret.  An instruction is
+// op | arg << 8; arg is the input index of kCellIn.
+constexpr int kCellBase = 16;  // gate opcode of library cell c is kCellBase + c
+constexpr int kCellMaxIn = 6;
+constexpr int kCellMaxCode = 32;
+constexpr int kCellMaxStack = 8;
+enum : int { kCellIn = 0, kCellNot = 1, kCellAnd = 2, kCellOr = 3, kCellXor = 4,
+             kCellZero = 5, kCellOne = 6 };
+
 struct GraphView {
   const uint8_t *op;        // [G]
-  const int32_t *in;        // [3][G]
+  const int32_t *in;        // [pins][G] (unused pins alias pin 0)
   const int32_t *rev_ptr;   // [n_nets + 1]
   const int32_t *rev_edge;  // [n_edges]
-  const int32_t *slot;      // [3][G] fan-out position of each pin
+  const int32_t *slot;      // [pins][G] fan-out position of each pin
+  const uint16_t *code;     // library cells' stack code (op | arg << 8)
+  const int32_t *cell;      // [n_cells][3]: code offset, length, inputs
+  int32_t pins;             // rows of in and slot (3, or the widest cell)
   int32_t n_pi, G, n_nets;
 };
 
@@ -70,7 +83,10 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
                                int32_t G, int32_t S, hipStream_t s);
 
 // One SP level (modeled sweep).
-hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s);
+// cells: the range holds library cells only (every launch below that takes
+// the flag runs a range of one kind; a level's library cells follow its
+// fixed cells).
+hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t s);
 
 // PI rows of one chunk: Philox stimulus (stim == nullptr) or explicit words
 // stim[i][T]; counts ones/toggles of the PI nets.
@@ -82,8 +98,8 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
 // One simulation level of one chunk, with the level's SP fused in when
 // sp != nullptr.
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
-                            int32_t g0, int32_t n, const SpLevel *sp, const SimTune &tune,
-                            hipStream_t s);
+                            int32_t g0, int32_t n, const SpLevel *sp, bool cells,
+                            const SimTune &tune, hipStream_t s);
 
 // Finalize per internal net and column: beta, X = kappa*beta*TR_model, the
 // local adjoint seed base, optional caller-numbered exports.
@@ -148,7 +164,7 @@ struct BwdArgs {
   int32_t n_pi, G, B, S, C, cdiv, ste, per_column, paired;
 };
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
-                            hipStream_t s);
+                            bool cells, hipStream_t s);
 // PI adjoints -> out[c][n_pi].
 hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s);
 
@@ -168,8 +184,10 @@ struct BwdSeg {
   uint32_t block0;
 };
 // segs: device array of n_segs; blocks: total blocks of the launch.
-hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
-hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s);
+hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
+                           hipStream_t s);
+hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
+                            hipStream_t s);
 
 // Every net's adjoint in caller numbering, lam_out [C][n_nets], and the
 // Eq. 8 score of every gate from its output net, score [C][G] caller gate
@@ -194,7 +212,7 @@ hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_n
                               double *out, hipStream_t s);
 
 // Persistent (cooperative) sweeps: all levels in one launch with a grid
-// barrier between levels.  level_ptr is the device copy of the design's
+// barrier between levels; fixed cells only.  level_ptr is the device copy of the design's
 // level table; max_items the largest level's item count.
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
                                 int32_t depth, int64_t max_items, hipStream_t s);

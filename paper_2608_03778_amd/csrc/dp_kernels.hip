@@ -91,6 +91,120 @@ __device__ __forceinline__ void sp_partials(int op, f2 a, f2 b, f2 c, float &d0,
   }
 }
 
+// ---------------------------------------------------------------- library cells
+// A library cell is post-order stack code (Alg. 1), interpreted operation by
+// operation: each binary operation applies its independent-input rule to its
+// two operands (Sec. III-E: AND ab, OR a + b - ab, XOR a + b - 2ab, NOT 1 - a),
+// in the same cancellation-free (p, q) form as the fixed cells.
+__device__ __forceinline__ void cell_info(const GraphView &g, int op, int &off, int &len,
+                                          int &nin) {
+  const int c = op - kCellBase;
+  off = g.cell[3 * c];
+  len = g.cell[3 * c + 1];
+  nin = g.cell[3 * c + 2];
+}
+
+__device__ __forceinline__ f2 pair_op(int op, f2 a, f2 b) {
+  if (op == kCellAnd) return f2{a.x * b.x, fmaf(a.x, b.y, a.y)};
+  if (op == kCellOr) return f2{fmaf(a.y, b.x, a.x), a.y * b.y};
+  return f2{fmaf(a.x, b.y, a.y * b.x), fmaf(a.x, b.x, a.y * b.y)};  // XOR
+}
+
+__device__ f2 cell_sp(const GraphView &g, int off, int len, const f2 *x) {
+  f2 st[kCellMaxStack];
+  int top = 0;
+  for (int i = 0; i < len; ++i) {
+    const int w = g.code[off + i], op = w & 0xff;
+    if (op == kCellIn) {
+      st[top++] = x[w >> 8];
+    } else if (op == kCellZero) {
+      st[top++] = f2{0.0f, 1.0f};
+    } else if (op == kCellOne) {
+      st[top++] = f2{1.0f, 0.0f};
+    } else if (op == kCellNot) {
+      st[top - 1] = f2{st[top - 1].y, st[top - 1].x};
+    } else {
+      const f2 b = st[--top];
+      const f2 a = st[--top];
+      st[top++] = pair_op(op, a, b);
+    }
+  }
+  return st[0];
+}
+
+__device__ uint64_t cell_word(const GraphView &g, int off, int len, const uint64_t *x) {
+  uint64_t st[kCellMaxStack];
+  int top = 0;
+  for (int i = 0; i < len; ++i) {
+    const int w = g.code[off + i], op = w & 0xff;
+    if (op == kCellIn) {
+      st[top++] = x[w >> 8];
+    } else if (op == kCellZero) {
+      st[top++] = 0ull;
+    } else if (op == kCellOne) {
+      st[top++] = ~0ull;
+    } else if (op == kCellNot) {
+      st[top - 1] = ~st[top - 1];
+    } else {
+      const uint64_t b = st[--top];
+      const uint64_t a = st[--top];
+      st[top++] = op == kCellAnd ? (a & b) : (op == kCellOr ? (a | b) : (a ^ b));
+    }
+  }
+  return st[0];
+}
+
+// Reverse mode over the code (Alg. 3): the forward pass keeps each binary
+// operation's operands, the backward pass walks the code in reverse with a
+// stack of output gradients (a binary operation replaces its gradient by its
+// operands', the right operand's on top; NOT negates; an input adds to its
+// partial; a constant drops its gradient).
+__device__ void cell_partials(const GraphView &g, int off, int len, int nin, const f2 *x,
+                              float *d) {
+  f2 st[kCellMaxStack], ta[kCellMaxCode], tb[kCellMaxCode];
+  float gs[kCellMaxStack + 1];
+  int top = 0;
+  for (int k = 0; k < nin; ++k) d[k] = 0.0f;
+  for (int i = 0; i < len; ++i) {
+    const int w = g.code[off + i], op = w & 0xff;
+    if (op == kCellIn) {
+      st[top++] = x[w >> 8];
+    } else if (op == kCellZero) {
+      st[top++] = f2{0.0f, 1.0f};
+    } else if (op == kCellOne) {
+      st[top++] = f2{1.0f, 0.0f};
+    } else if (op == kCellNot) {
+      st[top - 1] = f2{st[top - 1].y, st[top - 1].x};
+    } else {
+      const f2 b = st[--top];
+      const f2 a = st[--top];
+      ta[i] = a;
+      tb[i] = b;
+      st[top++] = pair_op(op, a, b);
+    }
+  }
+  int gt = 0;
+  gs[gt++] = 1.0f;
+  for (int i = len - 1; i >= 0; --i) {
+    const int w = g.code[off + i], op = w & 0xff;
+    const float gr = gs[--gt];
+    if (op == kCellIn) {
+      d[w >> 8] += gr;
+    } else if (op == kCellNot) {
+      gs[gt++] = -gr;
+    } else if (op == kCellAnd) {
+      gs[gt++] = gr * tb[i].x;  // d(ab)/da = b
+      gs[gt++] = gr * ta[i].x;
+    } else if (op == kCellOr) {
+      gs[gt++] = gr * tb[i].y;  // d(a + b - ab)/da = 1 - b
+      gs[gt++] = gr * ta[i].y;
+    } else if (op == kCellXor) {
+      gs[gt++] = gr * (tb[i].y - tb[i].x);  // 1 - 2b
+      gs[gt++] = gr * (ta[i].y - ta[i].x);
+    }
+  }
+}
+
 // Boolean function of a cell on 64 lanes (Sec. III-C).
 template <int OP>
 __device__ __forceinline__ uint64_t cell_bits(uint64_t a, uint64_t b, uint64_t c) {
@@ -181,6 +295,9 @@ __global__ __launch_bounds__(kBlock) void k_import_sizes(const float *__restrict
 // ---------------------------------------------------------------- SP level
 // One lane per (gate, column) of level [g0, g0 + n): gather the fan-in
 // probabilities, apply the cell rule, clip to [0, 1] (Alg. 2).
+// CELLS: the range holds library cells only (their own kernel instances, so
+// the fixed-cell kernels keep their register budget).
+template <bool CELLS>
 __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, uint32_t idx) {
   const int32_t B = lv.B;
   const uint32_t gl32 = idx / (uint32_t)B;
@@ -188,8 +305,16 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int32_t b = (int32_t)(idx - gl32 * (uint32_t)B);
   const int32_t gi = lv.g0 + gl;
   const int op = g.op[gi];
-  const int k = arity_of(op);
   f2 *sp = reinterpret_cast<f2 *>(lv.sp);
+  if constexpr (CELLS) {
+    int off, len, nin;
+    cell_info(g, op, off, len, nin);
+    f2 x[kCellMaxIn];
+    for (int k = 0; k < nin; ++k) x[k] = sp[(int64_t)g.in[k * g.G + gi] * B + b];
+    sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(g, off, len, x));
+    return;
+  }
+  const int k = arity_of(op);
   const f2 z = f2{0.0f, 1.0f};
   const f2 a = sp[(int64_t)g.in[gi] * B + b];
   const f2 bb = k > 1 ? sp[(int64_t)g.in[g.G + gi] * B + b] : z;
@@ -199,7 +324,12 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
 
 __global__ __launch_bounds__(kBlock) void k_sp_level(GraphView g, SpLevel lv) {
   const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item(g, lv, idx);
+  if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item<false>(g, lv, idx);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sp_cells(GraphView g, SpLevel lv) {
+  const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item<true>(g, lv, idx);
 }
 
 // The same for an even column count, two columns per lane: one 16-byte
@@ -280,13 +410,54 @@ __device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
   }
 }
 
+// A library cell's row: the code runs per word, one pair per lane per
+// iteration.
 template <int ITERS>
+__device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t gi,
+                                             const w2 *__restrict__ W, int64_t pp,
+                                             w2 *__restrict__ out, int32_t p_begin,
+                                             const ChunkView &c, int lane, uint32_t &ones,
+                                             uint32_t &togs) {
+  int off, len, nin;
+  cell_info(g, op, off, len, nin);
+  int64_t row[kCellMaxIn];
+  for (int k = 0; k < nin; ++k)
+    row[k] = (int64_t)__builtin_amdgcn_readfirstlane(g.in[k * g.G + gi]) * pp;
+  uint64_t carry = 0;
+  if (p_begin > 0) {
+    uint64_t x[kCellMaxIn];
+    for (int k = 0; k < nin; ++k) x[k] = W[row[k] + p_begin - 1].y;
+    carry = cell_word(g, off, len, x);
+  }
+  for (int it = 0; it < ITERS; ++it) {
+    const int32_t p = p_begin + it * 64 + lane;
+    const bool ok = p < c.pairs;
+    uint64_t xa[kCellMaxIn], xb[kCellMaxIn];
+    for (int k = 0; k < nin; ++k) {
+      const w2 v = ok ? W[row[k] + p] : w2{0, 0};
+      xa[k] = v.x;
+      xb[k] = v.y;
+    }
+    w2 y;
+    y.x = cell_word(g, off, len, xa);
+    y.y = cell_word(g, off, len, xb);
+    uint64_t prev = __shfl_up(y.y, 1u);
+    if (lane == 0) prev = carry;
+    carry = __shfl(y.y, 63);
+    if (ok) {
+      out[p] = y;
+      count_pair(c, p, y, prev, ones, togs);
+    }
+  }
+}
+
+template <int ITERS, bool CELLS>
 __global__ __launch_bounds__(kBlock) void k_sim_level(GraphView g, ChunkView c, CountView cnt,
                                                       int32_t g0, int32_t n, int32_t waves_per_row,
                                                       int32_t sim_blocks, SpLevel sp) {
   if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level
     const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kBlock + threadIdx.x;
-    if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item(g, sp, idx);
+    if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item<CELLS>(g, sp, idx);
     return;
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -305,6 +476,9 @@ __global__ __launch_bounds__(kBlock) void k_sim_level(GraphView g, ChunkView c, 
   w2 *out = reinterpret_cast<w2 *>(c.W) + (int64_t)(g.n_pi + gi) * pp;
   const int32_t p_begin = seg * 64 * ITERS;
   uint32_t ones = 0, togs = 0;
+  if constexpr (CELLS) {
+    sim_cell_row<ITERS>(g, op, gi, W, pp, out, p_begin, c, lane, ones, togs);
+  } else {
   switch (op) {
     case INV: sim_gate_row<INV, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
     case BUF: sim_gate_row<BUF, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
@@ -315,6 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_sim_level(GraphView g, ChunkView c, 
     case XOR2: sim_gate_row<XOR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
     case AOI21: sim_gate_row<AOI21, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
     default: sim_gate_row<MUX2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+  }
   }
   ones = wave_sum(ones);
   togs = wave_sum(togs);
@@ -720,6 +895,7 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
 // innermost; item counts stay below 2^31.
 // One (gate, column) item of a reverse level; every lane of the wave calls
 // it (pull_sum needs the whole wave), lanes past the end pass active = false.
+template <bool CELLS>
 __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, int32_t g0,
                                          int32_t n, uint32_t idx, int lane) {
   const bool active = idx < (uint32_t)n * (uint32_t)a.C;
@@ -736,12 +912,12 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   float seed = 0.0f, beta = 1.0f;
   const f2 z = f2{0.0f, 1.0f};
   f2 x0 = z, x1 = z, x2 = z;
+  const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
   if (active) {
     op = g.op[gi];
-    k = arity_of(op);
+    k = CELLS ? 0 : arity_of(op);
     const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
-    const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
-    x0 = sp[(int64_t)i0 * a.B + b];
+    if (k > 0) x0 = sp[(int64_t)i0 * a.B + b];
     if (k > 1) x1 = sp[(int64_t)i1 * a.B + b];
     if (k > 2) x2 = sp[(int64_t)i2 * a.B + b];
     if (a.beta) beta = a.beta[(int64_t)out * a.B + b];
@@ -752,6 +928,16 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   float lam = seed + pulled;
   if (a.ste) lam *= beta;
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
+  if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
+    int off, len, nin;
+    cell_info(g, op, off, len, nin);
+    f2 x[kCellMaxIn];
+    float d[kCellMaxIn];
+    for (int j = 0; j < nin; ++j) x[j] = sp[(int64_t)g.in[j * g.G + gi] * a.B + b];
+    cell_partials(g, off, len, nin, x, d);
+    for (int j = 0; j < nin; ++j) a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
+    return;
+  }
   float d0, d1, d2;
   sp_partials(op, x0, x1, x2, d0, d1, d2);
   a.contrib[(int64_t)g.slot[gi] * a.C + c] = lam * d0;
@@ -759,9 +945,10 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   if (k > 2) a.contrib[(int64_t)g.slot[2 * g.G + gi] * a.C + c] = lam * d2;
 }
 
+template <bool CELLS>
 __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
                                                       int32_t n) {
-  bwd_item(g, a, g0, n, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+  bwd_item<CELLS>(g, a, g0, n, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
 }
 
 __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a, float *out,
@@ -859,17 +1046,19 @@ __device__ __forceinline__ int32_t seg_of(const Seg *__restrict__ segs, int32_t 
   return k;
 }
 
+template <bool CELLS>
 __global__ __launch_bounds__(kBlock) void k_sp_multi(const SpSeg *__restrict__ segs,
                                                      int32_t n_segs) {
   const SpSeg sg = segs[seg_of(segs, n_segs)];
   const uint32_t idx = (blockIdx.x - sg.block0) * kBlock + threadIdx.x;
-  if (idx < (uint32_t)sg.lv.n * (uint32_t)sg.lv.B) sp_item(sg.g, sg.lv, idx);
+  if (idx < (uint32_t)sg.lv.n * (uint32_t)sg.lv.B) sp_item<CELLS>(sg.g, sg.lv, idx);
 }
 
+template <bool CELLS>
 __global__ __launch_bounds__(kBlock) void k_bwd_multi(const BwdSeg *__restrict__ segs,
                                                       int32_t n_segs) {
   const BwdSeg sg = segs[seg_of(segs, n_segs)];
-  bwd_item(sg.g, sg.a, sg.g0, sg.n, (blockIdx.x - sg.block0) * kBlock + threadIdx.x,
+  bwd_item<CELLS>(sg.g, sg.a, sg.g0, sg.n, (blockIdx.x - sg.block0) * kBlock + threadIdx.x,
            threadIdx.x & 63);
 }
 
@@ -889,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel l
     cur.n = level_ptr[l + 1] - cur.g0;
     const uint32_t items = (uint32_t)cur.n * (uint32_t)cur.B;
     for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < items; idx += stride)
-      sp_item(g, cur, idx);
+      sp_item<false>(g, cur, idx);
     grid.sync();
   }
 }
@@ -906,7 +1095,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs 
     const uint32_t items = (uint32_t)n * (uint32_t)a.C;
     // round the trip count up to whole waves
     for (uint32_t base = first - lane; base < items; base += stride)
-      bwd_item(g, a, g0, n, base + lane, lane);
+      bwd_item<false>(g, a, g0, n, base + lane, lane);
     grid.sync();
   }
   const uint32_t items = (uint32_t)g.n_pi * (uint32_t)a.C;
@@ -1057,23 +1246,33 @@ hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_n
   return hipGetLastError();
 }
 
-hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s) {
+hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
+                           hipStream_t s) {
   if (n_segs <= 0 || blocks == 0) return hipSuccess;
-  k_sp_multi<<<blocks, kBlock, 0, s>>>(segs, n_segs);
+  if (cells)
+    k_sp_multi<true><<<blocks, kBlock, 0, s>>>(segs, n_segs);
+  else
+    k_sp_multi<false><<<blocks, kBlock, 0, s>>>(segs, n_segs);
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, hipStream_t s) {
+hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
+                            hipStream_t s) {
   if (n_segs <= 0 || blocks == 0) return hipSuccess;
-  k_bwd_multi<<<blocks, kBlock, 0, s>>>(segs, n_segs);
+  if (cells)
+    k_bwd_multi<true><<<blocks, kBlock, 0, s>>>(segs, n_segs);
+  else
+    k_bwd_multi<false><<<blocks, kBlock, 0, s>>>(segs, n_segs);
   return hipGetLastError();
 }
 
-hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, hipStream_t s) {
+hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t s) {
   const int64_t n = (int64_t)lv.n * lv.B;
   if (n <= 0) return hipSuccess;
   if (n >= (1ll << 31)) return hipErrorInvalidValue;
-  if (lv.B % 2 == 0)
+  if (cells)
+    k_sp_cells<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
+  else if (lv.B % 2 == 0)
     k_sp_level_x2<<<blocks_for(n / 2), kBlock, 0, s>>>(g, lv);
   else
     k_sp_level<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
@@ -1104,10 +1303,10 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
 }
 
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
-                            int32_t g0, int32_t n, const SpLevel *sp, const SimTune &tune,
-                            hipStream_t s) {
+                            int32_t g0, int32_t n, const SpLevel *sp, bool cells,
+                            const SimTune &tune, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int iters = tune.iters;
+  const int iters = cells ? 1 : tune.iters;  // library cells: one pair per lane
   const int32_t wpr = waves_per_row(c, iters);
   const int64_t tasks = (int64_t)n * wpr;
   const int64_t sim_blocks64 = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1121,11 +1320,15 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   if (sim_blocks64 + sp_blocks > kMaxBlocks || sim_blocks64 > INT32_MAX) return hipErrorInvalidValue;
   const int32_t sim_blocks = (int32_t)sim_blocks64;
   const unsigned grid = (unsigned)(sim_blocks + sp_blocks);
+  if (cells) {
+    k_sim_level<1, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+    return hipGetLastError();
+  }
   switch (iters) {
-    case 1: k_sim_level<1><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    case 2: k_sim_level<2><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    case 4: k_sim_level<4><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    default: k_sim_level<8><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 1: k_sim_level<1, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 2: k_sim_level<2, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 4: k_sim_level<4, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    default: k_sim_level<8, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
   }
   return hipGetLastError();
 }
@@ -1187,11 +1390,14 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
 
 
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
-                            hipStream_t s) {
+                            bool cells, hipStream_t s) {
   const int64_t items = (int64_t)n * a.C;
   if (items <= 0) return hipSuccess;
   if (items >= (1ll << 31)) return hipErrorInvalidValue;
-  k_bwd_level<<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
+  if (cells)
+    k_bwd_level<true><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
+  else
+    k_bwd_level<false><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,198 @@
+"""Library cells given as Boolean expressions (Sec. III-A, Alg. 1-3) on the
+GPU, through the C ABI, against the FP64 oracle's interpreter of the same
+expressions: probabilities and partials operation by operation, bits by
+evaluating the code on packed words (counts bit-exact)."""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_03778_amd import _lib as L
+from paper_2608_03778_amd import api, synth
+from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, oracle_column, say)
+
+pytestmark = pytest.mark.gpu
+
+FWD_ALL = ("sp", "tr", "sp_acc", "tr_acc", "beta", "tr_hyb", "ones", "toggles", "power")
+# the fixed cells INV .. AOI21 written as expressions, in opcode order
+FIXED_AS_EXPR = ("!A", "A", "A&B", "A|B", "!(A&B)", "!(A|B)", "A^B", "!(A&B|C)")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return api.Context(0)
+
+
+def _mixed_spec(n_gates, n_pi, depth):
+    ops = tuple(range(9)) + tuple(synth.CELL_BASE + c for c in range(len(synth.LIBRARY)))
+    return synth.DagSpec(n_gates=n_gates, n_pi=n_pi, depth=depth, ops=ops, cells=synth.LIBRARY)
+
+
+def _check_forward(res, f, col, hybrid):
+    np.testing.assert_allclose(res["sp"][col], f["sp"], atol=SP_ABS, rtol=0)
+    np.testing.assert_allclose(res["tr"][col], f["tr_model"], atol=SP_ABS, rtol=0)
+    if hybrid:
+        np.testing.assert_array_equal(res["ones"][col].astype(np.uint64), f["ones"])
+        np.testing.assert_array_equal(res["toggles"][col].astype(np.uint64), f["toggles"])
+        np.testing.assert_allclose(res["sp_acc"][col], f["sp_acc"], atol=SP_ABS, rtol=0)
+        np.testing.assert_allclose(res["tr_acc"][col], f["tr_acc"], atol=SP_ABS, rtol=0)
+        np.testing.assert_allclose(res["tr_hyb"][col], f["tr_hyb"], atol=SP_ABS, rtol=0)
+        ok = f["tr_model"] > 1e-3
+        np.testing.assert_allclose(res["beta"][col][ok], f["beta"][ok], rtol=2e-4, atol=0)
+
+
+@pytest.mark.parametrize("c", range(len(synth.LIBRARY)))
+def test_each_library_cell_alone(ctx, c):
+    """One level of 600 instances of library cell c on random distinct PIs
+    (a ragged last wave), every forward output and both gradients."""
+    expr = synth.LIBRARY[c]
+    say(f"library cell {c}: {expr}")
+    rng = np.random.default_rng(100 + c)
+    n_pi, G = 40, 600
+    k = synth.cell_arity(expr)
+    gates = [(synth.CELL_BASE + c, list(rng.choice(n_pi, size=k, replace=False)))
+             for _ in range(G)]
+    nl = synth.from_gates(n_pi, gates, synth.LIBRARY)
+    p = synth.pi_probs(n_pi, 30 + c)
+    cap = synth.net_caps(nl.n_nets, 31 + c)
+    d = api.Design(ctx, nl)
+    assert d.depth == 1
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 9, seed=5)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(FWD_ALL)
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid", n_words=9, seed=5)
+    _check_forward(res, f, 0, True)
+    assert_power_close(res["power"], f["power"])
+    g = ev.backward(want=("dpi", "dcap"))
+    assert_grad_close(g["dpi"][0], adj["dpi"], "dP/dp")
+    assert_grad_close(g["dcap"], adj["dcap"], "dP/dC")
+
+
+@pytest.mark.parametrize("mode,sched,B", [("modeled", L.DP_SCHED_LEVEL, 3),
+                                          ("modeled", L.DP_SCHED_GRAPH, 2),
+                                          ("hybrid", L.DP_SCHED_LEVEL, 2),
+                                          ("hybrid", L.DP_SCHED_GRAPH, 1)])
+def test_mixed_dag_all_outputs(ctx, mode, sched, B):
+    """3,000 gates over the nine fixed cells and the library, depth 20: every
+    output per column, the PI and capacitance gradients, and every net's
+    adjoint (power gradients)."""
+    say(f"library dag {mode} sched={sched} B={B}")
+    nl = synth.random_dag(_mixed_spec(3000, 64, 20), 11)
+    assert (nl.op >= synth.CELL_BASE).any() and (nl.op < synth.CELL_BASE).any()
+    p = synth.pi_probs(nl.n_pi, 12, batch=B)
+    cap = synth.net_caps(nl.n_nets, 13)
+    d = api.Design(ctx, nl)
+    hyb = mode == "hybrid"
+    ev = api.Eval(d, B, mode=L.DP_HYBRID if hyb else L.DP_MODELED, n_sim=64 * 37, seed=9)
+    ev.set_schedule(sched)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(FWD_ALL if hyb else ("sp", "tr", "beta", "power"))
+    g = ev.backward(want=("dpi", "dcap"))
+    lam, _ = ev.power_gradients()
+    o = oracle.Netlist.of(nl)
+    np.testing.assert_array_equal(d.levels(), o.levels())
+    dcap = np.zeros(nl.n_nets)
+    for b in range(B):
+        f, adj = oracle_column(o, p[b], cap, mode=mode, n_words=37, seed=9)
+        _check_forward(res, f, b, hyb)
+        assert_power_close(res["power"][b], f["power"], f"power[{b}]")
+        assert_grad_close(g["dpi"][b], adj["dpi"], f"dP/dp[{b}]")
+        assert_grad_close(lam[b], adj["lam"], f"lambda[{b}]")
+        dcap += adj["dcap"]
+    assert_grad_close(g["dcap"], dcap, "dP/dC")
+
+
+def test_fixed_cells_written_as_expressions_run_as_fixed_cells(ctx):
+    """A netlist whose gates use library expressions equal to the fixed
+    cells gives bit-identical results to the fixed-cell netlist."""
+    say("fixed cells as expressions")
+    nl = synth.random_dag(synth.DagSpec(n_gates=2500, n_pi=64, depth=18, ops=tuple(range(8))), 17)
+    as_expr = dataclasses.replace(nl, op=(nl.op.astype(np.int32) + synth.CELL_BASE).astype(np.uint8),
+                                  cells=FIXED_AS_EXPR)
+    p = synth.pi_probs(nl.n_pi, 18, batch=2)
+    cap = synth.net_caps(nl.n_nets, 19)
+    out = []
+    for net in (nl, as_expr):
+        d = api.Design(ctx, net)
+        ev = api.Eval(d, 2, mode=L.DP_HYBRID, n_sim=64 * 20, seed=3)
+        ev.set_pi_prob(p)
+        ev.set_caps(cap)
+        ev.set_schedule(L.DP_SCHED_PERSISTENT if net is as_expr else L.DP_SCHED_LEVEL)
+        r = ev.forward(FWD_ALL)
+        r.update(ev.backward(want=("dpi", "dcap")))
+        out.append(r)
+    for k in FWD_ALL + ("dpi", "dcap"):
+        np.testing.assert_array_equal(out[0][k], out[1][k], err_msg=k)
+
+
+def test_library_design_in_group_and_serving(ctx):
+    """A library-cell design merged with a fixed-cell design (group launches
+    and serving steps) gives what it gives alone."""
+    say("library design: group and serving")
+    nls = [synth.random_dag(_mixed_spec(2000, 64, 16), 21), synth.random_dag(synth.SPECS["dag2k"], 22)]
+    caps = [synth.net_caps(nl.n_nets, 23 + i) for i, nl in enumerate(nls)]
+    designs = [api.Design(ctx, nl) for nl in nls]
+    alone, evs = [], []
+    for i, (nl, d) in enumerate(zip(nls, designs)):
+        ev = api.Eval(d, 2, mode=L.DP_MODELED, n_sim=128)
+        ev.set_pi_prob(synth.pi_probs(nl.n_pi, 24 + i, batch=2))
+        ev.set_caps(caps[i])
+        r = ev.forward(("sp", "power"))
+        r.update(ev.backward(want=("dpi",)))
+        alone.append(r)
+        evs.append(ev)
+    grp = api.Group(ctx, evs)
+    res = grp.run(("sp", "power"), backward=True)
+    for r, a in zip(res, alone):
+        for k in ("sp", "power", "dpi"):
+            np.testing.assert_array_equal(r[k], a[k], err_msg=k)
+    grp.close()
+    srv = api.Server(ctx, hbm_budget_bytes=128 << 20, max_batch=8, max_inflight=3)
+    ids = [srv.add_design(d, c, mode=L.DP_MODELED, n_sim=128, seed=5) for d, c in zip(designs, caps)]
+    rng = np.random.default_rng(25)
+    qs = [(k % 2, rng.uniform(0.1, 0.9, nls[k % 2].n_pi).astype(np.float32)) for k in range(16)]
+    one = [srv.wait(srv.submit(ids[i], p, None, True)) for i, p in qs[:4]]
+    mixed = [srv.wait(t) for t in [srv.submit(ids[i], p, None, True) for i, p in qs]]
+    for k in range(4):
+        assert one[k][0] == mixed[k][0]
+        np.testing.assert_array_equal(one[k][1], mixed[k][1])
+    o = oracle.Netlist.of(nls[0])
+    for k in (0, 2, 10):
+        f, adj = oracle_column(o, qs[k][1], caps[0])
+        assert_power_close(mixed[k][0], f["power"])
+        assert_grad_close(mixed[k][1], adj["dpi"], "served dP/dp")
+    srv.close()
+
+
+def test_library_errors(ctx):
+    say("library errors")
+    nl = synth.from_gates(3, [(synth.CELL_BASE, [0, 1])], ("A&B",))
+
+    def compile_with(cells, net=nl):
+        return api.Design(ctx, dataclasses.replace(net, cells=tuple(cells)))
+
+    for bad, what in (("A&", "operand"), ("(A|B", "')'"), ("A $ B", "character"),
+                      ("A B", "after"), ("a&b&c&d&e&f&g", "6 inputs"),
+                      ("&".join(["A"] * 20), "32 operations"),
+                      ("A|(B|(C|(D|(E|(F|(A|(B|C)))))))", "8 stack")):
+        with pytest.raises(L.DiffPowerError, match="INVALID") as ei:
+            compile_with([bad])
+        assert what in str(ei.value), (bad, str(ei.value))
+    with pytest.raises(L.DiffPowerError, match="INVALID"):  # arity: 3 inputs, 2 pins
+        compile_with(["A&B&C"])
+    with pytest.raises(L.DiffPowerError, match="INVALID"):  # opcode past the library
+        compile_with([])
+    d = compile_with(["A&!B"])  # not a fixed cell's code
+    ev = api.Eval(d, mode=L.DP_MODELED)
+    with pytest.raises(L.DiffPowerError, match="UNSUPPORTED"):
+        ev.set_schedule(L.DP_SCHED_PERSISTENT)
+    ev.set_pi_prob(np.array([[0.3, 0.6, 0.5]], np.float32))
+    ev.set_caps(np.ones(4, np.float32))
+    sp = ev.forward(("sp",))["sp"][0]
+    assert abs(sp[3] - 0.3 * 0.4) < 1e-6
