@@ -43,6 +43,12 @@ _int = ctypes.c_int
 
 
 def _declare(lib):
+    lib.orc_threshold_d.argtypes = [_d]
+    lib.orc_threshold_d.restype = _u64
+    lib.orc_markov_probs.argtypes = [ctypes.c_float, ctypes.c_float, _p, _p]
+    lib.orc_markov_probs.restype = None
+    lib.orc_stimulus_model.argtypes = [_i32, _p, _p, _p, _u64, _i64, _p]
+    lib.orc_stimulus_model.restype = None
     lib.orc_cell_compile.argtypes = [ctypes.c_char_p, _p, _p]
     lib.orc_cell_compile.restype = _int
     lib.orc_set_cells.argtypes = [_int, _p]
@@ -209,8 +215,11 @@ class Netlist:
             _ptr(out["beta"]), _ptr(out["tr_hyb"]), _ptr(out["ceff"]))
         return out
 
-    def adjoint(self, P, beta, cap, size=None, *, kappa=0.5, beta_ste=False):
-        """dict of lambda [n_nets], dpi [n_pi], dcap [n_nets], dsize [n_gates]."""
+    def adjoint(self, P, beta, cap, size=None, *, kappa=0.5, beta_ste=False, fixed=None):
+        """dict of lambda [n_nets], dpi [n_pi], dcap [n_nets], dsize [n_gates].
+        fixed [n_pi] (nonzero = a fixed infrastructure startpoint, such as a
+        clock or a reset): excluded from the gradients, its lambda and dpi
+        are 0 (startpoints feed nothing upstream, so nothing else changes)."""
         n = self.n_nets
         lam = np.zeros(n, dtype=np.float64)
         dcap = np.zeros(n, dtype=np.float64)
@@ -218,6 +227,8 @@ class Netlist:
         _load().orc_adjoint(*self._args(), _ptr(_c(P, np.float64)), _ptr(_c(beta, np.float64)),
                             _ptr(_c(cap, np.float32)), _ptr(_c(size, np.float32)), float(kappa),
                             int(bool(beta_ste)), _ptr(lam), _ptr(dcap), _ptr(dsize))
+        if fixed is not None:
+            lam[: self.n_pi][np.asarray(fixed) != 0] = 0.0
         return dict(lam=lam, dpi=lam[: self.n_pi].copy(), dcap=dcap, dsize=dsize[: self.n_gates])
 
     def power_complex_step(self, p_pi, beta, ceff, pi, *, kappa=0.5, h=1e-30):
@@ -307,6 +318,30 @@ def philox4x32_10(ctr, key):
 
 def threshold(p: float) -> int:
     return int(_load().orc_threshold(float(np.float32(p))))
+
+
+def markov_probs(p: float, tau: float):
+    """(rise, stay): the chain's P(0 -> 1) and P(1 -> 1) for stationary
+    probability p and transition rate tau (float32 inputs)."""
+    a, st = _d(), _d()
+    _load().orc_markov_probs(float(np.float32(p)), float(np.float32(tau)), ctypes.byref(a),
+                             ctypes.byref(st))
+    return a.value, st.value
+
+
+def threshold_d(x: float) -> int:
+    return int(_load().orc_threshold_d(float(x)))
+
+
+def stimulus_model(p_pi, seed: int, n_words: int, tau=None, stream=None) -> np.ndarray:
+    """uint64 [n_pi][n_words]: per-startpoint Markov chains with transition
+    rates tau (None: independent cycles) on shared streams (None: own)."""
+    p = _c(p_pi, np.float32)
+    n = p.shape[0]
+    w = np.zeros((n, n_words), dtype=np.uint64)
+    _load().orc_stimulus_model(int(n), _ptr(p), _ptr(_c(tau, np.float32)),
+                               _ptr(_c(stream, np.int32)), int(seed), int(n_words), _ptr(w))
+    return w
 
 
 def stimulus(p_pi, seed: int, t0: int, n_words: int) -> np.ndarray:

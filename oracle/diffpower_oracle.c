@@ -543,6 +543,88 @@ void orc_stimulus(int32_t n_pi, const float *p_pi, uint64_t seed, int64_t t0,
       words[(int64_t)i * n_words + t] = orc_stimulus_word(i, t0 + t, p_pi[i], seed);
 }
 
+/* Integer threshold of a double probability: floor(x 2^32), 0 below 0 and
+ * 2^32 from 1 up (x 2^32 is exact; floor then rounds down). */
+uint64_t orc_threshold_d(double x) {
+  double v = x * 4294967296.0;
+  if (!(v > 0.0)) return 0;
+  if (v >= 4294967296.0) return 4294967296ull;
+  return (uint64_t)floor(v);
+}
+
+/* The chain of a startpoint with stationary probability p and target
+ * transition rate tau (Sec. III-C): a two-state Markov chain whose
+ * stationary law is Bernoulli(p) and whose probability of a change per cycle
+ * is tau, so P(0 -> 1) = a = tau / (2 (1 - p)) and P(1 -> 0) = b =
+ * tau / (2 p).  Returned as the rise probability a and the stay-at-one
+ * probability 1 - b, clamped into [0, 1] (tau beyond 2 min(p, 1 - p) gives
+ * the fastest chain there is); p = 0 never leaves 0 and p = 1 never leaves 1.
+ * With tau = 2 p (1 - p) both equal p: every cycle is then an independent
+ * Bernoulli(p) draw, the temporal-independence model. */
+void orc_markov_probs(float p, float tau, double *rise, double *stay) {
+  double pd = (double)p, td = (double)tau, a, st;
+  if (pd <= 0.0) {
+    a = 0.0;
+    st = 0.0;
+  } else if (pd >= 1.0) {
+    a = 1.0;
+    st = 1.0;
+  } else {
+    a = td / (2.0 * (1.0 - pd));
+    st = 1.0 - td / (2.0 * pd);
+  }
+  if (a > 1.0) a = 1.0;
+  if (st < 0.0) st = 0.0;
+  *rise = a;
+  *stay = st;
+}
+
+/* Startpoint stimulus with a target transition rate and shared streams
+ * (Sec. III-C).  Startpoint i draws its uniforms from stream s_i = stream[i]
+ * (i when stream is NULL), so startpoints that share a stream and a
+ * (p, tau) get the same words: u(t, j) is lane (j mod 4) of
+ * Philox4x32-10(counter = (t, s_i, j div 4, 0), key = (seed lo, seed hi)).
+ * Lane j of startpoint i is its own chain: at cycle 0 it is 1 iff
+ * u(0, j) < floor(p_i 2^32) (the stationary law, the same bit as the
+ * independent stimulus); at cycle t >= 1 a lane at 1 stays at 1 iff
+ * u(t, j) < floor((1 - b) 2^32) and a lane at 0 rises iff
+ * u(t, j) < floor(a 2^32).  tau == NULL: every cycle draws like cycle 0
+ * (independent cycles).  Words [n_pi][T]. */
+void orc_stimulus_model(int32_t n_pi, const float *p_pi, const float *tau,
+                        const int32_t *stream, uint64_t seed, int64_t T,
+                        uint64_t *words) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int32_t i = 0; i < n_pi; ++i) {
+    uint32_t si = stream ? (uint32_t)stream[i] : (uint32_t)i;
+    uint64_t thr_p = orc_threshold(p_pi[i]);
+    uint64_t thr_rise = thr_p, thr_stay = thr_p;
+    if (tau) {
+      double a, st;
+      orc_markov_probs(p_pi[i], tau[i], &a, &st);
+      thr_rise = orc_threshold_d(a);
+      thr_stay = orc_threshold_d(st);
+    }
+    uint64_t prev = 0;
+    for (int64_t t = 0; t < T; ++t) {
+      uint64_t w = 0;
+      for (int q = 0; q < 16; ++q) {
+        uint32_t ctr[4] = {(uint32_t)t, si, (uint32_t)q, 0u};
+        uint32_t u[4];
+        orc_philox4x32_10(ctr, key, u);
+        for (int l = 0; l < 4; ++l) {
+          int j = 4 * q + l;
+          uint64_t thr;
+          if (t == 0) thr = thr_p;
+          else thr = ((prev >> j) & 1u) ? thr_stay : thr_rise;
+          if ((uint64_t)u[l] < thr) w |= (uint64_t)1 << j;
+        }
+      }
+      words[(int64_t)i * T + t] = w;
+      prev = w;
+    }
+  }
+}
+
 static int popcount64(uint64_t x) {
   int c = 0;
   while (x) {

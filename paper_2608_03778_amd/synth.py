@@ -276,6 +276,106 @@ def random_tree(n_leaves: int, seed: int, ops=tuple(range(9)), cells=()) -> Netl
     return from_gates(n_leaves, gates, cells)
 
 
+# -- sequential boundaries (Sec. III-A: timing startpoints are primary inputs
+#    and flip-flop outputs, endpoints are primary outputs and flip-flop inputs)
+
+DFF = 255  # opcode of a flip-flop in a sequential netlist; it never reaches the library
+
+
+@dataclasses.dataclass
+class SeqNetlist:
+    """A netlist with flip-flops: gate g with op DFF has one input, its D net,
+    and its output net n_pi + g is the flop's Q.  Combinational cycles are
+    allowed only through flops."""
+
+    n_pi: int
+    op: np.ndarray
+    fanin_ptr: np.ndarray
+    fanin: np.ndarray
+    cells: tuple = ()
+
+
+@dataclasses.dataclass
+class Cut:
+    """A sequential netlist cut at its flops into the combinational netlist
+    the library evaluates: startpoints are the PIs and then one pseudo-PI per
+    flop (flop order), gates keep their relative order."""
+
+    netlist: Netlist
+    ppi: np.ndarray      # int32 [n_ff] PI id of flop k's output in the cut netlist
+    ppo: np.ndarray      # int32 [n_ff] cut net id of flop k's D input (an endpoint)
+    stream: np.ndarray   # int32 [n_pi + n_ff] shared stream of every startpoint
+    net_map: np.ndarray  # int32 [n_nets of the sequential netlist] -> cut net id
+
+
+def cut_flops(seq: SeqNetlist) -> Cut:
+    """Cut at the flops.  Pseudo-PIs of flops whose D inputs are one net carry
+    one signal, so they share a stream (Sec. III-C): the stream of the first
+    such flop's pseudo-PI."""
+    op = np.asarray(seq.op)
+    G = op.shape[0]
+    is_ff = op == DFF
+    ff = np.nonzero(is_ff)[0]
+    comb = np.nonzero(~is_ff)[0]
+    n_ff = ff.shape[0]
+    n_start = seq.n_pi + n_ff
+    net_map = np.empty(seq.n_pi + G, dtype=np.int32)
+    net_map[: seq.n_pi] = np.arange(seq.n_pi)
+    net_map[seq.n_pi + ff] = seq.n_pi + np.arange(n_ff)
+    net_map[seq.n_pi + comb] = n_start + np.arange(comb.shape[0])
+    gates = []
+    for g in comb:
+        ins = seq.fanin[seq.fanin_ptr[g]:seq.fanin_ptr[g + 1]]
+        gates.append((int(op[g]), [int(net_map[n]) for n in ins]))
+    for g in ff:
+        if seq.fanin_ptr[g + 1] - seq.fanin_ptr[g] != 1:
+            raise ValueError(f"flop {g} needs exactly one input")
+    d_seq = np.array([seq.fanin[seq.fanin_ptr[g]] for g in ff], dtype=np.int64)
+    ppo = net_map[d_seq].astype(np.int32) if n_ff else np.zeros(0, np.int32)
+    stream = np.arange(n_start, dtype=np.int32)
+    first = {}
+    for k, dn in enumerate(d_seq.tolist()):
+        stream[seq.n_pi + k] = seq.n_pi + first.setdefault(dn, k)
+    nl = from_gates(n_start, gates, seq.cells)
+    return Cut(netlist=nl, ppi=(seq.n_pi + np.arange(n_ff)).astype(np.int32), ppo=ppo,
+               stream=stream, net_map=net_map)
+
+
+def random_seq_dag(spec: DagSpec, n_ff: int, seed: int, shared: float = 0.25) -> SeqNetlist:
+    """A sequential netlist: a random DAG over n_pi + n_ff startpoints whose
+    last n_ff startpoints are flop outputs, each flop's D a random net (a
+    fraction `shared` of the flops reuses another flop's D, so their outputs
+    share a driver), flops and gates interleaved in a random order."""
+    rng = np.random.default_rng(seed)
+    comb = random_dag(dataclasses.replace(spec, n_pi=spec.n_pi + n_ff), seed)
+    n_pi, G = spec.n_pi, comb.n_gates
+    n_nets = comb.n_nets
+    d = rng.integers(0, n_nets, n_ff)
+    for k in range(1, n_ff):
+        if rng.random() < shared:
+            d[k] = d[rng.integers(0, k)]
+    # sequential gate order: a random interleaving of the gates and the flops
+    order = rng.permutation(G + n_ff)  # position -> (gate g < G, or flop g - G)
+    pos = np.empty(G + n_ff, dtype=np.int64)
+    pos[order] = np.arange(G + n_ff)
+    seq_net = np.empty(n_nets, dtype=np.int64)  # combinational net -> sequential net
+    seq_net[:n_pi] = np.arange(n_pi)
+    seq_net[n_pi:n_pi + n_ff] = n_pi + pos[G + np.arange(n_ff)]
+    seq_net[n_pi + n_ff:] = n_pi + pos[np.arange(G)]
+    ops, fins = [], []
+    for x in order:
+        if x < G:
+            ops.append(int(comb.op[x]))
+            fins.append(seq_net[comb.fanin[comb.fanin_ptr[x]:comb.fanin_ptr[x + 1]]])
+        else:
+            ops.append(DFF)
+            fins.append(seq_net[[d[x - G]]])
+    fanin_ptr = np.zeros(G + n_ff + 1, dtype=np.int32)
+    fanin_ptr[1:] = np.cumsum([len(f) for f in fins])
+    return SeqNetlist(n_pi=n_pi, op=np.array(ops, dtype=np.uint8), fanin_ptr=fanin_ptr,
+                      fanin=np.concatenate(fins).astype(np.int32), cells=tuple(spec.cells))
+
+
 def pi_probs(n_pi: int, seed: int, batch: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
     """PI probabilities, float32 [batch][n_pi], U(lo, hi)."""
     rng = np.random.default_rng(seed)

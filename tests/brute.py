@@ -134,3 +134,46 @@ def philox4x32_10(ctr, key):
         c0, c1, c2, c3 = ((prod1 >> 32) ^ c1 ^ k0, prod1 & _MASK,
                           (prod0 >> 32) ^ c3 ^ k1, prod0 & _MASK)
     return [c0, c1, c2, c3]
+
+
+def markov_words(p, tau, stream, seed, n_words):
+    """Startpoint stimulus with transition rates and shared streams, written
+    from the definition independently of the oracle: lane j of startpoint i
+    starts from Bernoulli(p) and then keeps 1 with probability
+    1 - tau / (2p) and rises from 0 with probability tau / (2 (1 - p)),
+    each cycle's draw being lane j mod 4 of Philox(t, stream_i, j div 4)."""
+    import math
+
+    def thr(x):
+        v = x * 4294967296.0
+        return 0 if not v > 0 else (1 << 32 if v >= 4294967296.0 else math.floor(v))
+
+    key = (seed & _MASK, seed >> 32)
+    out = []
+    for i, pi in enumerate(p):
+        pf = float(np.float32(pi))
+        s = i if stream is None else int(stream[i])
+        t_p = thr(pf)
+        if tau is None:
+            t_rise = t_stay = t_p
+        else:
+            tf = float(np.float32(tau[i]))
+            if pf <= 0:
+                rise, stay = 0.0, 0.0
+            elif pf >= 1:
+                rise, stay = 1.0, 1.0
+            else:
+                rise, stay = min(tf / (2.0 * (1.0 - pf)), 1.0), max(1.0 - tf / (2.0 * pf), 0.0)
+            t_rise, t_stay = thr(rise), thr(stay)
+        state = [0] * 64
+        row = []
+        for t in range(n_words):
+            w = 0
+            for j in range(64):
+                u = philox4x32_10((t, s, j // 4, 0), key)[j % 4]
+                limit = t_p if t == 0 else (t_stay if state[j] else t_rise)
+                state[j] = 1 if u < limit else 0
+                w |= state[j] << j
+            row.append(w)
+        out.append(row)
+    return np.array(out, dtype=np.uint64)
