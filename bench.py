@@ -260,7 +260,7 @@ def scale_bench(ctx, reps=3):
 
 
 FORMS_DEFAULT = ("modeled_b1_level", "modeled_b1_graph", "modeled_b1_persistent", "modeled_b64",
-                 "design_group", "power_virus")
+                 "design_group", "power_virus", "library_cells")
 FORMS_EXTRA = ("sizing_sweep", "scale_2m")
 
 
@@ -419,6 +419,53 @@ def virus_form(args):
                 gain_over_random_max=float(pv[0] / pv_rand.max()))
 
 
+def library_form(args):
+    """The bench design's shape with half of its gates library cells (the
+    nine expressions of the synthetic library, up to six inputs): hybrid
+    forward and forward+backward at the headline's vector count, and the
+    modeled pair, each autotuned; % of HBM peak from the sweeps' algorithmic
+    bytes."""
+    import dataclasses
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    ops = tuple(range(9)) + tuple(synth.CELL_BASE + c for c in range(len(synth.LIBRARY)))
+    spec = dataclasses.replace(synth.SPECS[args.workload], ops=ops, cells=synth.LIBRARY)
+    nl = synth.random_dag(spec, seed=1)
+    lib_gates = int((nl.op >= synth.CELL_BASE).sum())
+    ctx = api.Context.for_torch(0)
+    d = api.Design(ctx, nl)
+    out = dict(design=args.workload, gates=nl.n_gates, library_gates=lib_gates,
+               pins=int(nl.fanin_ptr[-1]))
+    for mode, name in ((L.DP_HYBRID, "hybrid"), (L.DP_MODELED, "modeled")):
+        ev = api.Eval(d, 1, mode=mode, n_sim=args.n_sim, seed=1)
+        ev.set_pi_prob(synth.pi_probs(nl.n_pi, seed=2))
+        ev.set_caps(synth.net_caps(nl.n_nets, seed=3))
+        ev.autotune(3, with_backward=True)
+
+        def fwd():
+            ev.forward(("power",), device=True)
+
+        def fwdbwd():
+            ev.forward(("power",), device=True)
+            ev.backward(want=("dpi", "dcap"), device=True)
+        tf = time_steps(fwd, 10, 2)
+        tfb = time_steps(fwdbwd, 10, 2)
+        ev.profile(True)
+        fwdbwd()
+        pr = ev.get_profile()
+        ev.profile(False)
+        fb = pr["sim_bytes"] + pr["sp_bytes"]
+        log(f"[form] library cells {name}: forward {tf * 1e3:.3f} ms, "
+            f"forward+backward {tfb * 1e3:.3f} ms")
+        out[name] = dict(schedule=ev.get_schedule(), fwd_ms=tf * 1e3, fwdbwd_ms=tfb * 1e3,
+                         fwdbwd_gate_evals_s=nl.n_gates / tfb,
+                         fwd_hbm_frac=fb / tf / 1e9 / HBM_PEAK_GBS,
+                         fwdbwd_hbm_frac=(fb + pr["bwd_bytes"]) / tfb / 1e9 / HBM_PEAK_GBS)
+    return out
+
+
 def run_form(name, args):
     import torch
     torch.cuda.set_device(0)
@@ -430,6 +477,8 @@ def run_form(name, args):
         return group_form(args)
     if name == "power_virus":
         return virus_form(args)
+    if name == "library_cells":
+        return library_form(args)
     from paper_2608_03778_amd import api
     ctx = api.Context.for_torch(0)
     if name == "sizing_sweep":

@@ -240,6 +240,34 @@ dp_status dp_set_beta(dp_eval *ev, const float *beta, int32_t on_device);
  * [B][n_pi][n_sim/64] (bit j of word t = lane j at cycle t); NULL restores
  * the generator.  A test and replay hook. */
 dp_status dp_set_stimulus(dp_eval *ev, const uint64_t *words, int32_t on_device);
+/* Startpoint stimulus model of DP_HYBRID (Sec. III-C: 64-lane words from
+ * Markov chains calibrated to a target SP and TR).  tau[b][i], [B][n_pi],
+ * finite in [0, 1]: the target transition rate of PI i in column b.  Each
+ * lane of the PI is a two-state chain whose stationary law is its
+ * probability p (dp_set_pi_prob): cycle 0 is a Bernoulli(p) draw, then a
+ * lane at 1 stays with probability 1 - tau / (2p) and a lane at 0 rises with
+ * probability tau / (2 (1 - p)) (computed in double, clamped to [0, 1], so a
+ * tau beyond 2 min(p, 1 - p) gives the fastest chain there is).  Cycle t
+ * lane j compares lane j mod 4 of Philox4x32-10(counter (t, stream, j / 4,
+ * 0), key seed) with floor(probability * 2^32), as the independent
+ * stimulus does.  NULL restores independent cycles (tau = 2p(1-p)).  The
+ * modeled side is unchanged (Eq. 2); beta carries the difference.  An
+ * explicit stimulus (dp_set_stimulus) takes precedence.  Errors:
+ * DP_E_INVALID (a value out of range). */
+dp_status dp_set_pi_rates(dp_eval *ev, const float *tau, int32_t on_device);
+/* Shared streams (Sec. III-C: startpoints behind one sequential driver get
+ * one bitstream): stream[i], [n_pi] host memory, in [0, n_pi), is the
+ * Philox stream PI i draws from (its counter's second word); PIs with one
+ * stream and one (p, tau) get identical words.  NULL: every PI its own
+ * stream.  Applies to the generated stimulus, independent or Markov.
+ * Errors: DP_E_INVALID (a stream id out of range). */
+dp_status dp_set_pi_streams(dp_eval *ev, const int32_t *stream);
+/* Startpoints excluded from the gradients, such as fixed infrastructure nets
+ * (clocks, resets, scan enables) whose probabilities are not design
+ * variables: fixed[i] nonzero, [n_pi] host memory.  Their dP/dp (and their
+ * adjoint in dp_power_gradients) is 0, and dp_power_virus leaves their
+ * probabilities where they are; the forward is unchanged.  NULL: none. */
+dp_status dp_set_pi_fixed(dp_eval *ev, const uint8_t *fixed);
 
 /* Forward pass over all B columns (and S size vectors): SP sweep; in
  * DP_HYBRID also stimulus, bit-packed simulation and beta; finalize; power

@@ -93,6 +93,9 @@ SIGNATURES = {
     "dp_set_cell_sizes": (_st, [_p, _p, _i32]),
     "dp_set_beta": (_st, [_p, _p, _i32]),
     "dp_set_stimulus": (_st, [_p, _p, _i32]),
+    "dp_set_pi_rates": (_st, [_p, _p, _i32]),
+    "dp_set_pi_streams": (_st, [_p, _p]),
+    "dp_set_pi_fixed": (_st, [_p, _p]),
     "dp_forward": (_st, [_p, _p]),
     "dp_backward": (_st, [_p, _p, _p, _p, _p, _i32]),
     "dp_backward_columns": (_st, [_p, _p, _i32]),

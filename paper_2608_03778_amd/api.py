@@ -176,6 +176,30 @@ class Eval:
             return
         self._set(self.lib.dp_set_stimulus, words, np.uint64, "stim")
 
+    def set_pi_rates(self, tau):
+        """Target transition rate of every PI, [B][n_pi] (None: independent
+        cycles)."""
+        if tau is None:
+            check(self.lib.dp_set_pi_rates(self.handle, None, 0))
+            return
+        self._set(self.lib.dp_set_pi_rates, tau, np.float32, "tau")
+
+    def set_pi_streams(self, stream):
+        """Philox stream of every PI, [n_pi] (None: its own)."""
+        if stream is None:
+            check(self.lib.dp_set_pi_streams(self.handle, None))
+            return
+        a = np.ascontiguousarray(stream, dtype=np.int32)
+        check(self.lib.dp_set_pi_streams(self.handle, a.ctypes.data))
+
+    def set_pi_fixed(self, fixed):
+        """PIs excluded from the gradients, [n_pi] booleans (None: none)."""
+        if fixed is None:
+            check(self.lib.dp_set_pi_fixed(self.handle, None))
+            return
+        a = np.ascontiguousarray(fixed, dtype=np.uint8)
+        check(self.lib.dp_set_pi_fixed(self.handle, a.ctypes.data))
+
     def set_schedule(self, schedule=L.DP_SCHED_AUTO, words_per_chunk=0, pairs_per_lane=0):
         check(self.lib.dp_eval_set_schedule(self.handle, int(schedule), int(words_per_chunk),
                                             int(pairs_per_lane)))

@@ -274,11 +274,15 @@ float *beta_or_null(dp_eval *ev) {
   return ev->prm.mode == DP_MODELED ? nullptr : ev->beta.as<float>();
 }
 
+// Whether the forward draws Markov stimulus words (a target transition rate
+// per PI and no explicit stimulus).
+bool markov(const dp_eval *ev) { return ev->have_tau && !ev->have_stim; }
+
 // Kernel launches of one forward sweep (what a captured graph would hold).
 int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
   const int64_t depth = ev->d->depth + ev->d->split_levels;
   if (!pl) return depth + 2;
-  return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4;
+  return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4 + (markov(ev) ? 1 : 0);
 }
 
 // Allocate everything the forward sweep touches (before any capture).
@@ -297,6 +301,8 @@ dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
     DP_TRY(ev->tog.alloc(nb * sizeof(uint32_t)));
     const int32_t L = n_sim_streams(ev);
     DP_TRY(ev->words.alloc((size_t)L * d->n_nets * pl->pitch * sizeof(uint64_t)));
+    if (markov(ev))
+      DP_TRY(ev->mstim.alloc(std::max<size_t>((size_t)ev->B * d->n_pi * pl->T * sizeof(uint64_t), 16)));
     while ((int32_t)ev->lane_streams.size() < L - 1) {
       hipStream_t st = nullptr;
       DP_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -348,7 +354,7 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   if (!pl) {  // modeled (or frozen-beta) sweep: one span over all level launches
     double bytes = 0.0;
     for (int32_t l = 1; l <= d->depth; ++l) bytes += sp_level_bytes(d, l, ev->B);
-    SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth);
+    SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth + d->split_levels);
     if (ev->schedule == DP_SCHED_PERSISTENT) {
       dp::SpLevel lv{sp, ev->B, 0, 0};
       DP_TRY(on_coop_stream(ev, s, [&](hipStream_t cs) {
@@ -367,6 +373,16 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
     DP_HIP_TRY(dp::launch_fill_u32(ev->ones.as<uint32_t>(), (int64_t)nb, 0u, s));
     DP_HIP_TRY(dp::launch_fill_u32(ev->tog.as<uint32_t>(), (int64_t)nb, 0u, s));
     dp::SimTune tune{pick_iters(ev, *pl)};
+    const int32_t *streams = ev->have_streams ? ev->streams.as<int32_t>() : nullptr;
+    const uint64_t *stim_all = nullptr;  // [B][n_pi][T] words, or the generator
+    if (ev->have_stim) {
+      stim_all = ev->stim.as<uint64_t>();
+    } else if (markov(ev)) {
+      SpanGuard sg(ev, SPAN_STIM, 0.0, prof, 1);
+      DP_HIP_TRY(dp::launch_markov_words(sp, ev->tau.as<float>(), streams, d->n_pi, ev->B, pl->T,
+                                         ev->prm.seed, ev->mstim.as<uint64_t>(), s));
+      stim_all = ev->mstim.as<uint64_t>();
+    }
     // (column, chunk) pieces are independent: piece j runs on stream j % L
     // with its own word buffer; the SP of each level is fused into piece 0.
     const int32_t n_pieces = ev->B * pl->n_chunks;
@@ -381,19 +397,19 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       const int32_t b = j / pl->n_chunks, k = j % pl->n_chunks, lane = j % L;
       hipStream_t ls = lane == 0 ? s : ev->lane_streams[lane - 1];
       dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), ev->B, b};
-      const uint64_t *stim =
-          ev->have_stim ? ev->stim.as<uint64_t>() + (size_t)b * d->n_pi * pl->T : nullptr;
+      const uint64_t *stim = stim_all ? stim_all + (size_t)b * d->n_pi * pl->T : nullptr;
       const dp::ChunkView cv = chunk_view(ev, *pl, k, lane);
       {
         SpanGuard sg(ev, SPAN_STIM, 0.0, prof, 1, ls);
-        DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, ev->prm.seed, tune, ls));
+        DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, streams, ev->prm.seed, tune,
+                                       ls));
       }
       const bool fuse = (j == 0);
       const int64_t nw = cv.u_hi - cv.u_lo;
       double bytes = 0.0;
       for (int32_t l = 1; l <= d->depth; ++l) bytes += sim_level_bytes(d, l, nw, ev->B, fuse);
       // one span over the piece's level launches (their back-to-back time)
-      SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth, ls);
+      SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth + d->split_levels, ls);
       for (int32_t l = 1; l <= d->depth; ++l)
         DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
           const dp::SpLevel lv{sp, ev->B, g0, n};
@@ -529,6 +545,11 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
   std::memcpy(&bits, &ev->prm.beta_max, 8); mix(bits);
   mix((uint64_t)ev->have_stim);
   mix((uint64_t)(uintptr_t)ev->stim.ptr);
+  mix((uint64_t)markov(ev));
+  mix((uint64_t)(uintptr_t)ev->mstim.ptr);
+  mix((uint64_t)(uintptr_t)ev->tau.ptr);
+  mix((uint64_t)ev->have_streams);
+  mix((uint64_t)(uintptr_t)ev->streams.ptr);
   mix((uint64_t)(uintptr_t)ev->words.ptr);
   mix((uint64_t)(uintptr_t)ev->beta_frozen.ptr);
   mix((uint64_t)(uintptr_t)ev->size.ptr);
@@ -599,6 +620,7 @@ dp::BwdArgs backward_args(dp_eval *ev, const float *w, int per_column, int32_t C
   ba.ste = ev->prm.beta_grad == DP_BETA_STE;
   ba.per_column = per_column;
   ba.paired = ev->paired_sizes;
+  ba.fixed = ev->have_fixed ? ev->fixed.as<uint8_t>() : nullptr;
   return ba;
 }
 
@@ -618,7 +640,7 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
     });
   }
   {
-    SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
+    SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth + d->split_levels);
     for (int32_t l = d->depth; l >= 1; --l)
       DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
         DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, cells, s));
@@ -875,6 +897,57 @@ dp_status dp_set_stimulus(dp_eval *ev, const uint64_t *words, int32_t on_device)
   DP_TRY(stage_in(ev->stim, words, bytes, on_device, s));
   if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
   ev->have_stim = true;
+  return DP_OK;
+}
+
+dp_status dp_set_pi_rates(dp_eval *ev, const float *tau, int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_pi_rates: NULL eval");
+  ev->inputs_version++;
+  if (!tau) {
+    ev->have_tau = false;
+    return DP_OK;
+  }
+  const int64_t n = (int64_t)ev->B * ev->d->n_pi;
+  if (n > 0) {
+    DP_TRY(check_values(ev, tau, n, 0.0f, 1.0f, on_device, "dp_set_pi_rates"));
+    hipStream_t s = ev->stream();
+    DP_TRY(stage_in(ev->tau, tau, (size_t)n * sizeof(float), on_device, s));
+    if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
+  }
+  ev->have_tau = true;
+  return DP_OK;
+}
+
+dp_status dp_set_pi_streams(dp_eval *ev, const int32_t *stream) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_pi_streams: NULL eval");
+  ev->inputs_version++;
+  if (!stream) {
+    ev->have_streams = false;
+    return DP_OK;
+  }
+  const int32_t n_pi = ev->d->n_pi;
+  for (int32_t i = 0; i < n_pi; ++i)
+    if (stream[i] < 0 || stream[i] >= n_pi)
+      return fail(DP_E_INVALID, "dp_set_pi_streams: stream " + std::to_string(stream[i]) +
+                                    " of PI " + std::to_string(i) + " is not a PI");
+  if (n_pi > 0) {
+    hipStream_t s = ev->stream();
+    DP_TRY(stage_in(ev->streams, stream, (size_t)n_pi * sizeof(int32_t), 0, s));
+    DP_HIP_TRY(hipStreamSynchronize(s));
+  }
+  ev->have_streams = true;
+  return DP_OK;
+}
+
+dp_status dp_set_pi_fixed(dp_eval *ev, const uint8_t *fixed) {
+  if (!ev) return fail(DP_E_INVALID, "dp_set_pi_fixed: NULL eval");
+  ev->have_fixed = false;  // read by the reverse sweep only: the forward stays valid
+  const int32_t n_pi = ev->d->n_pi;
+  if (!fixed || n_pi == 0) return DP_OK;
+  hipStream_t s = ev->stream();
+  DP_TRY(stage_in(ev->fixed, fixed, (size_t)n_pi, 0, s));
+  DP_HIP_TRY(hipStreamSynchronize(s));
+  ev->have_fixed = true;
   return DP_OK;
 }
 
@@ -1192,7 +1265,8 @@ dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, fl
   for (int32_t b = 0; b < B; ++b) {
     const dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), B, b};
     DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, ev->sp.as<float>(),
-                                   stim.as<uint64_t>() + (size_t)b * d->n_pi * 2, 2, 0, tune, s));
+                                   stim.as<uint64_t>() + (size_t)b * d->n_pi * 2, 2, nullptr, 0,
+                                   tune, s));
     for (int32_t l = 1; l <= d->depth; ++l)
       DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
         DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, nullptr, cells, tune, s));
@@ -1609,6 +1683,7 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
     ev->schedule = sched;
     mix((uint64_t)(uintptr_t)ev->contrib.ptr);
     mix((uint64_t)(uintptr_t)ev->pi_out.ptr);
+    mix((uint64_t)(uintptr_t)(ev->have_fixed ? ev->fixed.ptr : nullptr));
     mix((uint64_t)ev->B);
     mix((uint64_t)(uintptr_t)ev->sp.ptr);
     mix((uint64_t)(uintptr_t)ev->beta.ptr);

@@ -27,8 +27,12 @@ struct dp_eval {
   dp::DevBuf beta_frozen;    // [n_nets][B]
   dp::DevBuf beta_stage;     // [B][n_nets]
   dp::DevBuf stim;           // [B][n_pi][T]
+  dp::DevBuf tau;            // [B][n_pi] target transition rates (caller layout)
+  dp::DevBuf streams;        // int32 [n_pi] Philox stream of each PI
+  dp::DevBuf fixed;          // uint8 [n_pi] PIs excluded from the gradients
+  dp::DevBuf mstim;          // [B][n_pi][T] Markov stimulus words of the forward
   bool have_pi = false, have_cap = false, have_size = false, have_beta = false,
-       have_stim = false;
+       have_stim = false, have_tau = false, have_streams = false, have_fixed = false;
   uint64_t inputs_version = 1, fwd_version = 0;
   // forward state
   dp::DevBuf words;          // simulation chunk [n_nets][pitch]

@@ -90,10 +90,17 @@ hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hi
 
 // PI rows of one chunk: Philox stimulus (stim == nullptr) or explicit words
 // stim[i][T]; counts ones/toggles of the PI nets.
+// stream [n_pi]: the Philox stream of each PI (null = its own index).
 hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
                            const float *p_col /* SP pairs [n_pi][B][2], column cnt.col */,
-                           const uint64_t *stim, int64_t T, uint64_t seed, const SimTune &tune,
-                           hipStream_t s);
+                           const uint64_t *stim, int64_t T, const int32_t *stream, uint64_t seed,
+                           const SimTune &tune, hipStream_t s);
+// Markov stimulus words out [B][n_pi][T] from the PI probabilities (SP pairs
+// [n_pi][B][2]), the target transition rates tau [B][n_pi] and the streams
+// (null = own).
+hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
+                               int32_t n_pi, int32_t B, int64_t T, uint64_t seed, uint64_t *out,
+                               hipStream_t s);
 
 // One simulation level of one chunk, with the level's SP fused in when
 // sp != nullptr.
@@ -160,6 +167,7 @@ struct BwdArgs {
   const float *size;          // [S][G] internal, or null (all 1)
   float *contrib;             // [n_edges][C], in fan-out (reader) order
   float *lam;                 // [C][n_nets] internal: every net's adjoint, or null
+  const uint8_t *fixed;       // [n_pi]: nonzero = excluded from the gradients (0), or null
   float kappa;
   int32_t n_pi, G, B, S, C, cdiv, ste, per_column, paired;
 };

@@ -542,10 +542,122 @@ __device__ __forceinline__ uint64_t stim_word(uint32_t pi, int64_t t, uint64_t t
   return w;
 }
 
+// ---------------------------------------------------------------- Markov stimulus
+// Startpoints with a target transition rate tau (Sec. III-C): each lane is a
+// two-state chain with stationary law Bernoulli(p); a lane at 1 stays with
+// probability 1 - tau / (2p), a lane at 0 rises with probability
+// tau / (2 (1 - p)), each cycle's draw being the same Philox uniform as the
+// independent stimulus (counter (t, stream, lane / 4)); cycle 0 is the
+// stationary draw.  Probabilities in double, clamped to [0, 1].
+__device__ __forceinline__ uint64_t threshold_d(double x) {
+  const double v = x * 4294967296.0;
+  if (!(v > 0.0)) return 0;
+  if (v >= 4294967296.0) return 1ull << 32;
+  return (uint64_t)v;
+}
+
+__device__ __forceinline__ void markov_probs(float p, float tau, double &rise, double &stay) {
+  const double pd = (double)p, td = (double)tau;
+  if (pd <= 0.0) {
+    rise = 0.0;
+    stay = 0.0;
+  } else if (pd >= 1.0) {
+    rise = 1.0;
+    stay = 1.0;
+  } else {
+    rise = td / (2.0 * (1.0 - pd));
+    stay = 1.0 - td / (2.0 * pd);
+  }
+  if (rise > 1.0) rise = 1.0;
+  if (stay < 0.0) stay = 0.0;
+}
+
+// A lane's next bit as a map of its previous bit: x -> (x & s) | (~x & u),
+// 64 lanes at once.  Maps compose associatively.
+struct BitMap {
+  uint64_t s, u;
+};
+__device__ __forceinline__ BitMap bitmap_then(BitMap first, BitMap then) {
+  return BitMap{(first.s & then.s) | (~first.s & then.u), (first.u & then.s) | (~first.u & then.u)};
+}
+__device__ __forceinline__ uint64_t bitmap_apply(BitMap m, uint64_t x) {
+  return (x & m.s) | (~x & m.u);
+}
+
+constexpr int kMarkovK = 4;  // consecutive words per lane and tile
+
+// Words [B][n_pi][T] of every (column, startpoint), one wave each.  A tile of
+// 64 K words: each lane draws the maps of its K words and composes them, an
+// inclusive scan over the lanes composes the prefixes, and each lane applies
+// its exclusive prefix to the word carried in from the previous tile, then
+// its own maps in order.
+__global__ __launch_bounds__(kBlock) void k_markov_words(const float *__restrict__ sp,
+                                                         const float *__restrict__ tau,
+                                                         const int32_t *__restrict__ stream,
+                                                         int32_t n_pi, int32_t B, int64_t T,
+                                                         uint32_t k0, uint32_t k1,
+                                                         uint64_t *__restrict__ out) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + wave;  // b * n_pi + i
+  if (row >= (int64_t)B * n_pi) return;
+  const int32_t b = (int32_t)(row / n_pi), i = (int32_t)(row - (int64_t)b * n_pi);
+  const float p = sp[((int64_t)i * B + b) * 2];
+  double rise, stay;
+  markov_probs(p, tau[(int64_t)b * n_pi + i], rise, stay);
+  const uint64_t thr_p = prob_threshold(p), thr_rise = threshold_d(rise),
+                 thr_stay = threshold_d(stay);
+  const uint32_t si = stream ? (uint32_t)stream[i] : (uint32_t)i;
+  uint64_t *orow = out + row * T;
+  const BitMap id = BitMap{~0ull, 0ull};
+  uint64_t carry = 0;  // cycle 0's map is constant, so the first carry is moot
+  for (int64_t t0 = 0; t0 < T; t0 += 64 * kMarkovK) {
+    BitMap m[kMarkovK];
+    BitMap f = id;
+#pragma unroll
+    for (int k = 0; k < kMarkovK; ++k) {
+      const int64_t t = t0 + (int64_t)lane * kMarkovK + k;
+      m[k] = id;
+      if (t < T) {
+        const uint64_t ts = t == 0 ? thr_p : thr_stay, tr = t == 0 ? thr_p : thr_rise;
+        uint64_t ms = 0, mu = 0;
+        for (uint32_t q = 0; q < 16; ++q) {
+          const uint4 u = philox4x32_10(make_uint4((uint32_t)t, si, q, 0u), k0, k1);
+          const uint64_t s4 = (uint64_t)((uint64_t)u.x < ts) | ((uint64_t)((uint64_t)u.y < ts) << 1) |
+                              ((uint64_t)((uint64_t)u.z < ts) << 2) |
+                              ((uint64_t)((uint64_t)u.w < ts) << 3);
+          const uint64_t u4 = (uint64_t)((uint64_t)u.x < tr) | ((uint64_t)((uint64_t)u.y < tr) << 1) |
+                              ((uint64_t)((uint64_t)u.z < tr) << 2) |
+                              ((uint64_t)((uint64_t)u.w < tr) << 3);
+          ms |= s4 << (4 * q);
+          mu |= u4 << (4 * q);
+        }
+        m[k] = BitMap{ms, mu};
+      }
+      f = bitmap_then(f, m[k]);
+    }
+    for (int d = 1; d < 64; d <<= 1) {  // inclusive scan: earlier lanes' maps first
+      const BitMap g = BitMap{__shfl_up(f.s, (unsigned)d), __shfl_up(f.u, (unsigned)d)};
+      if (lane >= d) f = bitmap_then(g, f);
+    }
+    BitMap e = BitMap{__shfl_up(f.s, 1u), __shfl_up(f.u, 1u)};
+    if (lane == 0) e = id;
+    uint64_t x = bitmap_apply(e, carry);
+#pragma unroll
+    for (int k = 0; k < kMarkovK; ++k) {
+      const int64_t t = t0 + (int64_t)lane * kMarkovK + k;
+      x = bitmap_apply(m[k], x);
+      if (t < T) orow[t] = x;
+    }
+    carry = __shfl(x, 63);
+  }
+}
+
 template <int ITERS>
 __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, CountView cnt,
                                                      const float *__restrict__ p_rows,
                                                      const uint64_t *__restrict__ stim, int64_t T,
+                                                     const int32_t *__restrict__ stream,
                                                      uint32_t k0, uint32_t k1,
                                                      int32_t waves_per_row) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -556,10 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
   const int32_t seg = (int32_t)(task - (int64_t)i * waves_per_row);
   const uint64_t thr = prob_threshold(p_rows[((int64_t)i * cnt.B + cnt.col) * 2]);
   const uint64_t *srow = stim ? stim + (int64_t)i * T : nullptr;
+  const uint32_t si = stream ? (uint32_t)stream[i] : (uint32_t)i;  // shared stream
   auto word = [&](int64_t u) -> uint64_t {
     const int64_t t = c.t_first + u;
     if (t < 0 || t >= T) return 0;
-    return srow ? srow[t] : stim_word((uint32_t)i, t, thr, k0, k1);
+    return srow ? srow[t] : stim_word(si, t, thr, k0, k1);
   };
   uint64_t *out = c.W + (int64_t)i * c.pitch;
   const int32_t p_begin = seg * 64 * ITERS;
@@ -969,6 +1082,7 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   if (!active) return;
   float lam = seed + pulled;
   if (a.ste) lam *= beta;
+  if (a.fixed && a.fixed[i]) lam = 0.0f;  // excluded from the gradients
   out[(int64_t)c * g.n_pi + i] = lam;
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + i] = lam;
 }
@@ -1284,8 +1398,9 @@ static int32_t waves_per_row(const ChunkView &c, int iters) {
 }
 
 hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
-                           const float *p_col, const uint64_t *stim, int64_t T, uint64_t seed,
-                           const SimTune &tune, hipStream_t s) {
+                           const float *p_col, const uint64_t *stim, int64_t T,
+                           const int32_t *stream, uint64_t seed, const SimTune &tune,
+                           hipStream_t s) {
   if (g.n_pi <= 0 || c.pairs <= 0) return hipSuccess;
   const int iters = tune.iters;
   const int32_t wpr = waves_per_row(c, iters);
@@ -1294,11 +1409,23 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
   const unsigned grid = (unsigned)((tasks + kWavesPerBlock - 1) / kWavesPerBlock);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   switch (iters) {
-    case 1: k_stimulus<1><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
-    case 2: k_stimulus<2><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
-    case 4: k_stimulus<4><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
-    default: k_stimulus<8><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, k0, k1, wpr); break;
+    case 1: k_stimulus<1><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, stream, k0, k1, wpr); break;
+    case 2: k_stimulus<2><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, stream, k0, k1, wpr); break;
+    case 4: k_stimulus<4><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, stream, k0, k1, wpr); break;
+    default: k_stimulus<8><<<grid, kBlock, 0, s>>>(g.n_pi, c, cnt, p_col, stim, T, stream, k0, k1, wpr); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
+                               int32_t n_pi, int32_t B, int64_t T, uint64_t seed, uint64_t *out,
+                               hipStream_t s) {
+  const int64_t rows = (int64_t)n_pi * B;
+  if (rows <= 0 || T <= 0) return hipSuccess;
+  const int64_t blocks = (rows + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+  k_markov_words<<<(unsigned)blocks, kBlock, 0, s>>>(sp, tau, stream, n_pi, B, T, (uint32_t)seed,
+                                                     (uint32_t)(seed >> 32), out);
   return hipGetLastError();
 }
 
