@@ -260,7 +260,7 @@ def scale_bench(ctx, reps=3):
 
 
 FORMS_DEFAULT = ("modeled_b1_level", "modeled_b1_graph", "modeled_b1_persistent", "modeled_b64",
-                 "design_group", "power_virus", "library_cells")
+                 "design_group", "power_virus", "library_cells", "markov_stimulus")
 FORMS_EXTRA = ("sizing_sweep", "scale_2m")
 
 
@@ -466,6 +466,51 @@ def library_form(args):
     return out
 
 
+def markov_form(args):
+    """The headline hybrid pass with Markov startpoints (a random rate in
+    [0, 2 min(p, 1 - p)] per PI, one stream per 4 PIs) against the
+    independent stimulus, and the word generator alone: words/s, and its
+    share of the pass."""
+    import torch
+
+    from paper_2608_03778_amd import _lib as L
+    from paper_2608_03778_amd import api, synth
+
+    nl = synth.random_dag(synth.SPECS[args.workload], seed=1)
+    ctx = api.Context.for_torch(0)
+    d = api.Design(ctx, nl)
+    p = synth.pi_probs(nl.n_pi, seed=2)
+    tau = (np.random.default_rng(5).uniform(0, 1, p.shape) * 2 * np.minimum(p, 1 - p)
+           ).astype(np.float32)
+    stream = (np.arange(nl.n_pi) // 4 * 4).astype(np.int32)
+    ev = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=args.n_sim, seed=1)
+    ev.set_pi_prob(p)
+    ev.set_caps(synth.net_caps(nl.n_nets, seed=3))
+    ev.set_schedule(L.DP_SCHED_LEVEL, 0, 4)
+
+    def fwdbwd():
+        ev.forward(("power",), device=True)
+        ev.backward(want=("dpi", "dcap"), device=True)
+    t_ind = time_steps(fwdbwd, 10, 2)
+    ev.set_pi_rates(tau)
+    ev.set_pi_streams(stream)
+    t_mk = time_steps(fwdbwd, 10, 2)
+    ev.profile(True)
+    ev.forward(("power",), device=True)
+    pr = ev.get_profile()
+    ev.profile(False)
+    torch.cuda.synchronize()
+    T = args.n_sim // 64
+    words = nl.n_pi * T
+    gen_ms = pr["stim_ms"]  # the generator and the PI-row loads of the pass
+    log(f"[form] markov: fwd+bwd {t_mk * 1e3:.3f} ms (independent {t_ind * 1e3:.3f} ms)")
+    return dict(design=args.workload, words=words, fwdbwd_ms=t_mk * 1e3,
+                independent_fwdbwd_ms=t_ind * 1e3, stimulus_ms=gen_ms,
+                stimulus_launches=pr["stim_launches"],
+                words_per_s=words / (gen_ms * 1e-3) if gen_ms > 0 else None,
+                philox_calls_per_s=16 * words / (gen_ms * 1e-3) if gen_ms > 0 else None)
+
+
 def run_form(name, args):
     import torch
     torch.cuda.set_device(0)
@@ -479,6 +524,8 @@ def run_form(name, args):
         return virus_form(args)
     if name == "library_cells":
         return library_form(args)
+    if name == "markov_stimulus":
+        return markov_form(args)
     from paper_2608_03778_amd import api
     ctx = api.Context.for_torch(0)
     if name == "sizing_sweep":
