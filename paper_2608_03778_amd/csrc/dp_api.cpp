@@ -282,7 +282,8 @@ bool markov(const dp_eval *ev) { return ev->have_tau && !ev->have_stim; }
 int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
   const int64_t depth = ev->d->depth + ev->d->split_levels;
   if (!pl) return depth + 2;
-  return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4 + (markov(ev) ? 1 : 0);
+  return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4 + (markov(ev) ? 1 : 0) +
+         ev->d->cell_levels;  // the library cells' SP launches
 }
 
 // Allocate everything the forward sweep touches (before any capture).
@@ -413,7 +414,9 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       for (int32_t l = 1; l <= d->depth; ++l)
         DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
           const dp::SpLevel lv{sp, ev->B, g0, n};
-          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, cells, tune, ls));
+          if (fuse && cells) DP_HIP_TRY(dp::launch_sp_level(g, lv, true, ls));
+          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse && !cells ? &lv : nullptr, cells,
+                                          tune, ls));
           return DP_OK;
         }));
     }
@@ -1835,6 +1838,9 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   hipError_t e = hipMemcpyAsync(ev->cap.ptr, cap_int, nn * 4, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && beta_int)
     e = hipMemcpyAsync(ev->beta_frozen.ptr, beta_int, nn * 4, hipMemcpyDeviceToDevice, stream);
+  // steps run on streams of their own: the lane's inputs must be in place
+  // before any of them reads the lane
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     delete ev;
     return fail(DP_E_HIP, std::string("lane_create: ") + hipGetErrorString(e));

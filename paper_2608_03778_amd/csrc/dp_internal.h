@@ -92,6 +92,7 @@ struct dp_design {
   // them and run in kernels of their own
   std::vector<int32_t> lvl_fixed;
   int32_t split_levels = 0;           // levels holding both kinds (one launch more each)
+  int32_t cell_levels = 0;            // levels holding library cells
   bool has_cell_gates = false;
   // device arrays
   int32_t pins = 3;      // rows of `in` and `slot`: 3, or the widest library cell

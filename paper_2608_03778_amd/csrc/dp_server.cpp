@@ -43,6 +43,7 @@ struct Request {
   Clock::time_point t_submit, t_done;
   bool done = false;
   dp_status status = DP_OK;
+  std::string error;  // why status is not DP_OK
 };
 
 struct DesignEntry {
@@ -210,8 +211,29 @@ void launch_step(dp_server *s, Step *st, const std::vector<Lane *> &ready) {
     l->busy = true;
   }
   dp_status rc = dp::lanes_run_merged(jobs.data(), (int32_t)jobs.size(), st->stream, &st->scratch);
-  if (rc == DP_OK && hipEventRecord(st->done, st->stream) != hipSuccess) rc = DP_E_HIP;
-  if (rc != DP_OK) s->thread_error = dp_last_error();
+  if (rc == DP_OK && hipEventRecord(st->done, st->stream) != hipSuccess)
+    rc = fail(DP_E_HIP, "hipEventRecord failed");
+  if (rc != DP_OK) {
+    // the step did not go out whole: its queries fail with the reason (their
+    // outputs are never read), after whatever was enqueued has drained
+    const std::string why = dp_last_error();
+    (void)hipStreamSynchronize(st->stream);
+    (void)hipGetLastError();
+    const auto now = Clock::now();
+    for (Lane *l : ready) {
+      for (Request *r : l->batch) {
+        r->status = rc;
+        r->error = "server step: " + why;
+        r->t_done = now;
+        r->done = true;
+        s->st.completed++;
+      }
+      l->batch.clear();
+      l->busy = false;
+    }
+    s->cv_done.notify_all();
+    return;
+  }
   st->lanes = ready;
   st->busy = true;
   if (s->inflight++ == 0) s->busy_since = Clock::now();
@@ -464,9 +486,11 @@ dp_status dp_wait(dp_server *s, uint64_t ticket, double *latency_s) {
   if (!r->done) return fail(DP_E_HIP, "server: " + s->thread_error);
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   const dp_status st = r->status;
+  const std::string why = r->error;
   s->reqs.erase(it);
   delete r;
-  if (st != DP_OK) return fail(st, "dp_wait: the query's cap_scale had a NaN or negative entry");
+  if (st != DP_OK)
+    return fail(st, why.empty() ? "dp_wait: the query's cap_scale had a NaN or negative entry" : why);
   return DP_OK;
 }
 
