@@ -219,15 +219,13 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
     if (f > g0 && f < g1) ++d->split_levels;
   }
   // cell code and table
-  // each cell's code padded to kCellMaxCode words (64 bytes), so a wave loads
-  // a whole program with four aligned 16-byte loads
-  std::vector<uint16_t> code((size_t)std::max(n_cells, 1) * kCellMaxCode, 0);
+  std::vector<uint16_t> code;
   std::vector<int32_t> cell_tab(3 * (size_t)std::max(n_cells, 1), 0);
   for (int32_t c = 0; c < n_cells; ++c) {
-    cell_tab[3 * c] = c * kCellMaxCode;
+    cell_tab[3 * c] = (int32_t)code.size();
     cell_tab[3 * c + 1] = (int32_t)lib[c].code.size();
     cell_tab[3 * c + 2] = lib[c].n_in;
-    std::copy(lib[c].code.begin(), lib[c].code.end(), code.begin() + (size_t)c * kCellMaxCode);
+    code.insert(code.end(), lib[c].code.begin(), lib[c].code.end());
   }
   hipStream_t s = ctx->stream;
   dp_status st = DP_OK;

@@ -95,47 +95,13 @@ __device__ __forceinline__ void sp_partials(int op, f2 a, f2 b, f2 c, float &d0,
 // A library cell is post-order stack code (Alg. 1), interpreted operation by
 // operation: each binary operation applies its independent-input rule to its
 // two operands (Sec. III-E: AND ab, OR a + b - ab, XOR a + b - 2ab, NOT 1 - a),
-// in the same cancellation-free (p, q) form as the fixed cells.  A wave runs
-// one cell's code at a time (the code is wave-uniform), held in registers:
-// each cell's code is padded to kCellMaxCode words, 64 bytes.
-struct CellProg {
-  uint32_t w[kCellMaxCode / 2];  // two instructions per dword
-  int len, nin;
-};
-
-// op must be wave-uniform: the program then lives in scalar registers.
-__device__ __forceinline__ CellProg cell_prog(const GraphView &g, int op) {
-  CellProg pr;
+// in the same cancellation-free (p, q) form as the fixed cells.
+__device__ __forceinline__ void cell_info(const GraphView &g, int op, int &off, int &len,
+                                          int &nin) {
   const int c = op - kCellBase;
-  pr.len = __builtin_amdgcn_readfirstlane(g.cell[3 * c + 1]);
-  pr.nin = __builtin_amdgcn_readfirstlane(g.cell[3 * c + 2]);
-  const uint4 *src = reinterpret_cast<const uint4 *>(g.code + (int64_t)c * kCellMaxCode);
-#pragma unroll
-  for (int k = 0; k < kCellMaxCode / 8; ++k) {
-    const uint4 v = src[k];
-    pr.w[4 * k] = __builtin_amdgcn_readfirstlane(v.x);
-    pr.w[4 * k + 1] = __builtin_amdgcn_readfirstlane(v.y);
-    pr.w[4 * k + 2] = __builtin_amdgcn_readfirstlane(v.z);
-    pr.w[4 * k + 3] = __builtin_amdgcn_readfirstlane(v.w);
-  }
-  return pr;
-}
-
-__device__ __forceinline__ int prog_at(const CellProg &pr, int i) {
-  return (int)((pr.w[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-}
-
-// Run f(op) with op wave-uniform: the lanes of each distinct op in the wave
-// take their turn (gates sort by op, so a wave usually holds one).
-template <class F>
-__device__ __forceinline__ void per_uniform_op(int op, F &&f) {
-  for (;;) {
-    const int u = __builtin_amdgcn_readfirstlane(op);
-    if (op == u) {
-      f(u);
-      break;
-    }
-  }
+  off = g.cell[3 * c];
+  len = g.cell[3 * c + 1];
+  nin = g.cell[3 * c + 2];
 }
 
 __device__ __forceinline__ f2 pair_op(int op, f2 a, f2 b) {
@@ -144,11 +110,11 @@ __device__ __forceinline__ f2 pair_op(int op, f2 a, f2 b) {
   return f2{fmaf(a.x, b.y, a.y * b.x), fmaf(a.x, b.x, a.y * b.y)};  // XOR
 }
 
-__device__ __forceinline__ f2 cell_sp(const CellProg &pr, const f2 *x) {
+__device__ f2 cell_sp(const GraphView &g, int off, int len, const f2 *x) {
   f2 st[kCellMaxStack];
   int top = 0;
-  for (int i = 0; i < pr.len; ++i) {
-    const int w = prog_at(pr, i), op = w & 0xff;
+  for (int i = 0; i < len; ++i) {
+    const int w = g.code[off + i], op = w & 0xff;
     if (op == kCellIn) {
       st[top++] = x[w >> 8];
     } else if (op == kCellZero) {
@@ -166,42 +132,41 @@ __device__ __forceinline__ f2 cell_sp(const CellProg &pr, const f2 *x) {
   return st[0];
 }
 
-// The code on N words at once (x [nin][N] -> y [N]), one stack each.
-template <int N>
-__device__ __forceinline__ void cell_words(const CellProg &pr, const uint64_t (*x)[N],
-                                           uint64_t *y) {
-  uint64_t st[kCellMaxStack][N];
+__device__ uint64_t cell_word(const GraphView &g, int off, int len, const uint64_t *x) {
+  uint64_t st[kCellMaxStack];
   int top = 0;
-  for (int i = 0; i < pr.len; ++i) {
-    const int w = prog_at(pr, i), op = w & 0xff;
-    if (op == kCellIn || op == kCellZero || op == kCellOne) {
-#pragma unroll
-      for (int n = 0; n < N; ++n)
-        st[top][n] = op == kCellIn ? x[w >> 8][n] : (op == kCellOne ? ~0ull : 0ull);
-      ++top;
+  for (int i = 0; i < len; ++i) {
+    const int w = g.code[off + i], op = w & 0xff;
+    if (op == kCellIn) {
+      st[top++] = x[w >> 8];
+    } else if (op == kCellZero) {
+      st[top++] = 0ull;
+    } else if (op == kCellOne) {
+      st[top++] = ~0ull;
     } else if (op == kCellNot) {
-#pragma unroll
-      for (int n = 0; n < N; ++n) st[top - 1][n] = ~st[top - 1][n];
+      st[top - 1] = ~st[top - 1];
     } else {
-      --top;
-#pragma unroll
-      for (int n = 0; n < N; ++n) {
-        const uint64_t a = st[top - 1][n], b = st[top][n];
-        st[top - 1][n] = op == kCellAnd ? (a & b) : (op == kCellOr ? (a | b) : (a ^ b));
-      }
+      const uint64_t b = st[--top];
+      const uint64_t a = st[--top];
+      st[top++] = op == kCellAnd ? (a & b) : (op == kCellOr ? (a | b) : (a ^ b));
     }
   }
-#pragma unroll
-  for (int n = 0; n < N; ++n) y[n] = st[0][n];
+  return st[0];
 }
 
-// The two operands of binary instruction i (the top of the stack before it).
-__device__ __forceinline__ void cell_operands(const CellProg &pr, const f2 *x, int i, f2 &a,
-                                              f2 &b) {
-  f2 st[kCellMaxStack];
+// Reverse mode over the code (Alg. 3): the forward pass keeps each binary
+// operation's operands, the backward pass walks the code in reverse with a
+// stack of output gradients (a binary operation replaces its gradient by its
+// operands', the right operand's on top; NOT negates; an input adds to its
+// partial; a constant drops its gradient).
+__device__ void cell_partials(const GraphView &g, int off, int len, int nin, const f2 *x,
+                              float *d) {
+  f2 st[kCellMaxStack], ta[kCellMaxCode], tb[kCellMaxCode];
+  float gs[kCellMaxStack + 1];
   int top = 0;
-  for (int j = 0; j < i; ++j) {
-    const int w = prog_at(pr, j), op = w & 0xff;
+  for (int k = 0; k < nin; ++k) d[k] = 0.0f;
+  for (int i = 0; i < len; ++i) {
+    const int w = g.code[off + i], op = w & 0xff;
     if (op == kCellIn) {
       st[top++] = x[w >> 8];
     } else if (op == kCellZero) {
@@ -211,46 +176,31 @@ __device__ __forceinline__ void cell_operands(const CellProg &pr, const f2 *x, i
     } else if (op == kCellNot) {
       st[top - 1] = f2{st[top - 1].y, st[top - 1].x};
     } else {
-      const f2 r = st[--top];
-      const f2 l = st[--top];
-      st[top++] = pair_op(op, l, r);
+      const f2 b = st[--top];
+      const f2 a = st[--top];
+      ta[i] = a;
+      tb[i] = b;
+      st[top++] = pair_op(op, a, b);
     }
   }
-  a = st[top - 2];
-  b = st[top - 1];
-}
-
-// Reverse mode over the code (Alg. 3), the tape recomputed rather than
-// stored: the code is walked from the end with a stack of output gradients
-// (a binary operation replaces its gradient by its operands', the right
-// operand's on top; NOT negates; an input adds to its partial; a constant
-// drops its gradient); a binary operation's operands come from re-running
-// the code up to it, which keeps the registers of a tape free.
-__device__ __forceinline__ void cell_partials(const CellProg &pr, const f2 *x, float *d) {
-  float gs[kCellMaxStack + 1];
-  for (int k = 0; k < kCellMaxIn; ++k) d[k] = 0.0f;
   int gt = 0;
   gs[gt++] = 1.0f;
-  for (int i = pr.len - 1; i >= 0; --i) {
-    const int w = prog_at(pr, i), op = w & 0xff;
+  for (int i = len - 1; i >= 0; --i) {
+    const int w = g.code[off + i], op = w & 0xff;
     const float gr = gs[--gt];
     if (op == kCellIn) {
       d[w >> 8] += gr;
     } else if (op == kCellNot) {
       gs[gt++] = -gr;
-    } else if (op == kCellAnd || op == kCellOr || op == kCellXor) {
-      f2 a, b;
-      cell_operands(pr, x, i, a, b);
-      if (op == kCellAnd) {
-        gs[gt++] = gr * b.x;  // d(ab)/da = b
-        gs[gt++] = gr * a.x;
-      } else if (op == kCellOr) {
-        gs[gt++] = gr * b.y;  // d(a + b - ab)/da = 1 - b
-        gs[gt++] = gr * a.y;
-      } else {
-        gs[gt++] = gr * (b.y - b.x);  // 1 - 2b
-        gs[gt++] = gr * (a.y - a.x);
-      }
+    } else if (op == kCellAnd) {
+      gs[gt++] = gr * tb[i].x;  // d(ab)/da = b
+      gs[gt++] = gr * ta[i].x;
+    } else if (op == kCellOr) {
+      gs[gt++] = gr * tb[i].y;  // d(a + b - ab)/da = 1 - b
+      gs[gt++] = gr * ta[i].y;
+    } else if (op == kCellXor) {
+      gs[gt++] = gr * (tb[i].y - tb[i].x);  // 1 - 2b
+      gs[gt++] = gr * (ta[i].y - ta[i].x);
     }
   }
 }
@@ -357,12 +307,11 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int op = g.op[gi];
   f2 *sp = reinterpret_cast<f2 *>(lv.sp);
   if constexpr (CELLS) {
-    per_uniform_op(op, [&](int u) {
-      const CellProg pr = cell_prog(g, u);
-      f2 x[kCellMaxIn];
-      for (int k = 0; k < pr.nin; ++k) x[k] = sp[(int64_t)g.in[k * g.G + gi] * B + b];
-      sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(pr, x));
-    });
+    int off, len, nin;
+    cell_info(g, op, off, len, nin);
+    f2 x[kCellMaxIn];
+    for (int k = 0; k < nin; ++k) x[k] = sp[(int64_t)g.in[k * g.G + gi] * B + b];
+    sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(g, off, len, x));
     return;
   }
   const int k = arity_of(op);
@@ -461,40 +410,37 @@ __device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
   }
 }
 
-// A library cell's row (op wave-uniform): the code in registers, run on both
-// words of a pair per lane and iteration (and once on the word before the
-// range, for the first toggle).
+// A library cell's row: the code runs per word, one pair per lane per
+// iteration.
 template <int ITERS>
 __device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t gi,
                                              const w2 *__restrict__ W, int64_t pp,
                                              w2 *__restrict__ out, int32_t p_begin,
                                              const ChunkView &c, int lane, uint32_t &ones,
                                              uint32_t &togs) {
-  const CellProg pr = cell_prog(g, op);
-  // row of input k (uniform; re-read from the scalar cache where used)
-  auto row = [&](int k) -> int64_t {
-    return (int64_t)__builtin_amdgcn_readfirstlane(g.in[k * g.G + gi]) * pp;
-  };
+  int off, len, nin;
+  cell_info(g, op, off, len, nin);
+  int64_t row[kCellMaxIn];
+  for (int k = 0; k < nin; ++k)
+    row[k] = (int64_t)__builtin_amdgcn_readfirstlane(g.in[k * g.G + gi]) * pp;
   uint64_t carry = 0;
   if (p_begin > 0) {
-    uint64_t x[kCellMaxIn][1];
-    for (int k = 0; k < pr.nin; ++k) x[k][0] = W[row(k) + p_begin - 1].y;
-    cell_words<1>(pr, x, &carry);
+    uint64_t x[kCellMaxIn];
+    for (int k = 0; k < nin; ++k) x[k] = W[row[k] + p_begin - 1].y;
+    carry = cell_word(g, off, len, x);
   }
-#pragma unroll 1
   for (int it = 0; it < ITERS; ++it) {
     const int32_t p = p_begin + it * 64 + lane;
     const bool ok = p < c.pairs;
-    uint64_t xa[kCellMaxIn][1], xb[kCellMaxIn][1];
-    for (int k = 0; k < pr.nin; ++k) {
-      const w2 v = ok ? W[row(k) + p] : w2{0, 0};
-      xa[k][0] = v.x;
-      xb[k][0] = v.y;
+    uint64_t xa[kCellMaxIn], xb[kCellMaxIn];
+    for (int k = 0; k < nin; ++k) {
+      const w2 v = ok ? W[row[k] + p] : w2{0, 0};
+      xa[k] = v.x;
+      xb[k] = v.y;
     }
-    uint64_t ya, yb;
-    cell_words<1>(pr, xa, &ya);
-    cell_words<1>(pr, xb, &yb);
-    const w2 y = w2{ya, yb};
+    w2 y;
+    y.x = cell_word(g, off, len, xa);
+    y.y = cell_word(g, off, len, xb);
     uint64_t prev = __shfl_up(y.y, 1u);
     if (lane == 0) prev = carry;
     carry = __shfl(y.y, 63);
@@ -1098,15 +1044,13 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   if (a.ste) lam *= beta;
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
-    per_uniform_op(op, [&](int u) {
-      const CellProg pr = cell_prog(g, u);
-      f2 x[kCellMaxIn];
-      float d[kCellMaxIn];
-      for (int j = 0; j < pr.nin; ++j) x[j] = sp[(int64_t)g.in[j * g.G + gi] * a.B + b];
-      cell_partials(pr, x, d);
-      for (int j = 0; j < pr.nin; ++j)
-        a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
-    });
+    int off, len, nin;
+    cell_info(g, op, off, len, nin);
+    f2 x[kCellMaxIn];
+    float d[kCellMaxIn];
+    for (int j = 0; j < nin; ++j) x[j] = sp[(int64_t)g.in[j * g.G + gi] * a.B + b];
+    cell_partials(g, off, len, nin, x, d);
+    for (int j = 0; j < nin; ++j) a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
     return;
   }
   float d0, d1, d2;
@@ -1492,7 +1436,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
                             const SimTune &tune, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (cells && sp) return hipErrorInvalidValue;  // no fused SP for library cells
-  const int iters = tune.iters;
+  const int iters = cells ? 1 : tune.iters;  // library cells: one pair per lane
   const int32_t wpr = waves_per_row(c, iters);
   const int64_t tasks = (int64_t)n * wpr;
   const int64_t sim_blocks64 = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1507,12 +1451,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   const int32_t sim_blocks = (int32_t)sim_blocks64;
   const unsigned grid = (unsigned)(sim_blocks + sp_blocks);
   if (cells) {
-    switch (iters) {
-      case 1: k_sim_level<1, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-      case 2: k_sim_level<2, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-      case 4: k_sim_level<4, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-      default: k_sim_level<8, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    }
+    k_sim_level<1, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
     return hipGetLastError();
   }
   switch (iters) {

@@ -73,6 +73,41 @@ def test_each_library_cell_alone(ctx, c):
     assert_grad_close(g["dcap"], adj["dcap"], "dP/dC")
 
 
+def test_waves_holding_several_library_cells(ctx):
+    """One level of the nine library cells and the fixed cells in random
+    order: after sorting, most waves hold several library cells, each taking
+    its turn with its own code (SP, bits, partials)."""
+    say("several library cells per wave")
+    ops = list(range(9)) + [synth.CELL_BASE + c for c in range(len(synth.LIBRARY))]
+    rng = np.random.default_rng(7)
+    n_pi, G = 40, 900
+    arity = synth.arity_table(synth.LIBRARY)
+    gates = []
+    for _ in range(G):
+        o = int(rng.choice(ops))
+        gates.append((o, list(rng.choice(n_pi, size=int(arity[o]), replace=False))))
+    nl = synth.from_gates(n_pi, gates, synth.LIBRARY)
+    p = synth.pi_probs(n_pi, 8, batch=2)
+    cap = synth.net_caps(nl.n_nets, 9)
+    d = api.Design(ctx, nl)
+    assert d.depth == 1
+    ev = api.Eval(d, 2, mode=L.DP_HYBRID, n_sim=64 * 11, seed=6)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(FWD_ALL)
+    g = ev.backward(want=("dpi", "dcap"))
+    lam, _ = ev.power_gradients()
+    o = oracle.Netlist.of(nl)
+    dcap = np.zeros(nl.n_nets)
+    for b in range(2):
+        f, adj = oracle_column(o, p[b], cap, mode="hybrid", n_words=11, seed=6)
+        _check_forward(res, f, b, True)
+        assert_grad_close(g["dpi"][b], adj["dpi"], f"dP/dp[{b}]")
+        assert_grad_close(lam[b], adj["lam"], f"lambda[{b}]")
+        dcap += adj["dcap"]
+    assert_grad_close(g["dcap"], dcap, "dP/dC")
+
+
 @pytest.mark.parametrize("mode,sched,B", [("modeled", L.DP_SCHED_LEVEL, 3),
                                           ("modeled", L.DP_SCHED_GRAPH, 2),
                                           ("hybrid", L.DP_SCHED_LEVEL, 2),
