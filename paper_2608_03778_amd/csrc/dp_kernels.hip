@@ -983,6 +983,44 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
   if (mine) acc = serial_pull(contrib, e0, e1, C, c);
   if (serial) return acc;
   uint64_t heavy = __ballot(active && !mine);
+  if (!heavy) return acc;
+  // the wave's heavy nets take consecutive strand positions (lane order);
+  // when they fit in 64, one round of loads covers them all
+  const int32_t cnt = ((heavy >> lane) & 1) ? (e1 - e0 + kStrand - 1) / kStrand : 0;
+  int32_t inc = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t t = __shfl_up(inc, (unsigned)d);
+    if (lane >= d) inc += t;
+  }
+  if (__builtin_amdgcn_readfirstlane(__shfl(inc, 63)) <= 64) {
+    const int32_t off = inc - cnt;
+    int32_t my_h = -1, my_j = 0;
+    for (uint64_t hh = heavy; hh; hh &= hh - 1) {
+      const int h = __builtin_ctzll(hh);
+      const int32_t ho = __builtin_amdgcn_readfirstlane(__shfl(off, h));
+      const int32_t hc = __builtin_amdgcn_readfirstlane(__shfl(cnt, h));
+      if (lane >= ho && lane < ho + hc) {
+        my_h = h;
+        my_j = lane - ho;
+      }
+    }
+    const int src = my_h < 0 ? lane : my_h;
+    const int32_t h0 = __shfl(e0, src), h1 = __shfl(e1, src), hcol = __shfl(c, src);
+    const float v = my_h >= 0 ? strand_sum(contrib, h0 + my_j * kStrand, h1, C, hcol) : 0.0f;
+    // each heavy net folds its strand sums in strand order
+    for (uint64_t hh = heavy; hh; hh &= hh - 1) {
+      const int h = __builtin_ctzll(hh);
+      const int32_t ho = __builtin_amdgcn_readfirstlane(__shfl(off, h));
+      const int32_t hc = __builtin_amdgcn_readfirstlane(__shfl(cnt, h));
+      float total = 0.0f;
+      for (int32_t t = 0; t < hc; ++t) {
+        const float u = __shfl(v, ho + t);
+        total = t == 0 ? u : total + u;
+      }
+      if (lane == h) acc = total;
+    }
+    return acc;
+  }
   while (heavy) {
     const int src = __builtin_ctzll(heavy);
     heavy &= heavy - 1;
