@@ -639,6 +639,12 @@ def main():
         ev.set_schedule(args.schedule, args.words_per_chunk, args.pairs_per_lane)
     else:
         tuned_ms = ev.autotune(3, with_backward=True)
+        sc = ev.get_schedule()
+        if sc["schedule"] == L.DP_SCHED_GRAPH:
+            # the timed region records HIP events around the level launches,
+            # which a captured graph cannot carry: time the same tiling per level
+            ev.set_schedule(L.DP_SCHED_LEVEL, sc["words_per_chunk"], sc["pairs_per_lane"])
+            ev.set_sim_streams(sc["sim_streams"])
     schedule = ev.get_schedule()
     log(f"[bench] schedule {schedule} (autotuned forward {tuned_ms} ms)")
 
@@ -697,6 +703,19 @@ def main():
                           f"({c['measured_s']:.1f} s measured)")}
         log(f"[bench] oracle {c['seconds_per_step']:.1f} s per step (extrapolated)")
 
+    # achievable HBM bandwidth for context: a 1 GiB device-to-device copy
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
     res = {
         "metric": METRIC,
         "value": value,
@@ -730,6 +749,7 @@ def main():
             "launches": prof["sim_launches"] // args.steps,
             "avg_launch_us": prof["sim_ms"] * 1e3 / max(prof["sim_launches"], 1),
             "algorithmic_bytes_per_launch": prof["sim_bytes"] / max(prof["sim_launches"], 1),
+            "copy_gbs": copy_gbs,  # a plain 1 GiB device copy on this GPU, for context
         },
         "cpu_baseline": cpu,
         "forms": forms,
