@@ -199,12 +199,14 @@ dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out);
  * OR '|' or '+', binary operators left associative.  A cell's inputs are its
  * distinct identifiers in order of first appearance, and a gate's fan-in
  * list follows that order; at most 6 inputs, 32 operations, 8 stack entries.
- * Each expression is compiled to post-order stack code that the level
- * kernels interpret operation by operation (the probability of an operation
- * assumes independent operands, so an expression that reads an input twice,
- * such as a multiplexer written out, gets the paper's op-by-op value), with
- * reverse-mode partials over the same code; library-cell gates run in
- * kernels of their own after a level's fixed cells.  An expression whose
+ * Each expression is compiled to post-order stack code that the SP and
+ * reverse kernels interpret operation by operation (the probability of an
+ * operation assumes independent operands, so an expression that reads an
+ * input twice, such as a multiplexer written out, gets the paper's op-by-op
+ * value), with reverse-mode partials over the same code; the simulation
+ * evaluates the expression's exact truth table.  Library-cell gates run in
+ * kernels of their own after a level's fixed cells.  A cell needs at least
+ * one input.  An expression whose
  * code is one of the fixed cells' (for example "A&B" or "!((A&B)|C)") runs
  * as that cell.  n_cells <= 240; copies the expressions.  Errors as dp_compile,
  * plus DP_E_INVALID for an expression that does not compile. */

@@ -62,6 +62,7 @@ dp::GraphView view(const dp_design *d) {
   g.slot = d->slot.as<int32_t>();
   g.code = d->code.as<uint16_t>();
   g.cell = d->cell.as<int32_t>();
+  g.tt = d->tt.as<uint64_t>();
   g.pins = d->pins;
   g.n_pi = d->n_pi;
   g.G = d->n_gates;

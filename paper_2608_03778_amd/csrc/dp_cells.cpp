@@ -126,6 +126,7 @@ std::string compile_cell(const char *text, CellCode *out) {
   if (c.err.empty() && c.tok == T_BAD) c.err = "unknown character";
   if (c.err.empty() && c.tok != T_END) c.err = "unexpected text after the expression";
   if (!c.err.empty()) return c.err;
+  if (c.inputs.empty()) return "no inputs (a cell reads at least one pin)";
   if (c.inputs.size() > (size_t)kCellMaxIn) return "more than 6 inputs";
   if (c.code.size() > (size_t)kCellMaxCode) return "more than 32 operations";
   if (c.max_depth > kCellMaxStack) return "deeper than 8 stack entries";
@@ -150,6 +151,36 @@ int fixed_op_of(const CellCode &cc) {
   if (is({I0, I1, kCellXor})) return DP_XOR2;
   if (is({I0, I1, kCellAnd, I2, kCellOr, kCellNot})) return DP_AOI21;
   return -1;
+}
+
+// The code run on 64 lanes at once, lane m carrying input pattern m.
+uint64_t truth_table(const CellCode &cc) {
+  uint64_t in[kCellMaxIn];
+  for (int k = 0; k < kCellMaxIn; ++k) {
+    uint64_t w = 0;
+    for (int m = 0; m < 64; ++m)
+      if ((m >> k) & 1) w |= 1ull << m;
+    in[k] = w;
+  }
+  uint64_t st[kCellMaxStack];
+  int top = 0;
+  for (uint16_t word : cc.code) {
+    const int op = word & 0xff, arg = word >> 8;
+    if (op == kCellIn) {
+      st[top++] = in[arg];
+    } else if (op == kCellZero) {
+      st[top++] = 0;
+    } else if (op == kCellOne) {
+      st[top++] = ~0ull;
+    } else if (op == kCellNot) {
+      st[top - 1] = ~st[top - 1];
+    } else {
+      const uint64_t b = st[--top];
+      const uint64_t a = st[--top];
+      st[top++] = op == kCellAnd ? (a & b) : (op == kCellOr ? (a | b) : (a ^ b));
+    }
+  }
+  return st[0];
 }
 
 }  // namespace dp

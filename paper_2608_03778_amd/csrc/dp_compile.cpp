@@ -227,9 +227,12 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
     cell_tab[3 * c + 2] = lib[c].n_in;
     code.insert(code.end(), lib[c].code.begin(), lib[c].code.end());
   }
+  std::vector<uint64_t> tt((size_t)std::max(n_cells, 1), 0);
+  for (int32_t c = 0; c < n_cells; ++c) tt[c] = truth_table(lib[c]);
   hipStream_t s = ctx->stream;
   dp_status st = DP_OK;
   if ((st = upload(d->code, code, s)) != DP_OK || (st = upload(d->cell, cell_tab, s)) != DP_OK ||
+      (st = upload(d->tt, tt, s)) != DP_OK ||
       (st = upload(d->op, d->h_op, s)) != DP_OK || (st = upload(d->in, in, s)) != DP_OK ||
       (st = upload(d->rev_ptr, rev_ptr, s)) != DP_OK ||
       (st = upload(d->rev_edge, rev_edge, s)) != DP_OK ||
@@ -247,7 +250,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   }
   d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
                               d->slot.bytes + d->int2ext.bytes + d->ext2int.bytes +
-                              d->code.bytes + d->cell.bytes);
+                              d->code.bytes + d->cell.bytes + d->tt.bytes);
   ctx_retain(ctx);
   *out = d;
   return DP_OK;

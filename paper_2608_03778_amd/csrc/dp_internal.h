@@ -57,6 +57,9 @@ struct CellCode {
 std::string compile_cell(const char *text, CellCode *out);
 // The fixed cell (DP_INV ..) a compiled expression equals, or -1.
 int fixed_op_of(const CellCode &cc);
+// Truth table of a compiled cell: bit m is the cell's output when input k
+// is bit k of m (m < 2^n_in; higher bits repeat the pattern).
+uint64_t truth_table(const CellCode &cc);
 
 }  // namespace dp
 
@@ -104,6 +107,7 @@ struct dp_design {
   dp::DevBuf slot;      // int32 [pins][n_gates] position of pin (g', j) in its source's fan-out list
   dp::DevBuf code;      // uint16: the library cells' stack code, concatenated
   dp::DevBuf cell;      // int32 [n_cells][3]: code offset, length, inputs
+  dp::DevBuf tt;        // uint64 [n_cells] truth tables (the simulation's cell function)
   dp::DevBuf level_dev; // int32 [depth + 2] device copy of level_ptr
   dp::DevBuf int2ext;   // int32 [n_nets]
   dp::DevBuf ext2int;   // int32 [n_nets]

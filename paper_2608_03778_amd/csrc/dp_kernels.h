@@ -26,6 +26,7 @@ struct GraphView {
   const int32_t *slot;      // [pins][G] fan-out position of each pin
   const uint16_t *code;     // library cells' stack code (op | arg << 8), concatenated
   const int32_t *cell;      // [n_cells][3]: code offset, length, inputs
+  const uint64_t *tt;       // [n_cells] truth tables: bit m = output for input pattern m
   int32_t pins;             // rows of in and slot (3, or the widest cell)
   int32_t n_pi, G, n_nets;
 };

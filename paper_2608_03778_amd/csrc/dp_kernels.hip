@@ -132,28 +132,6 @@ __device__ f2 cell_sp(const GraphView &g, int off, int len, const f2 *x) {
   return st[0];
 }
 
-__device__ uint64_t cell_word(const GraphView &g, int off, int len, const uint64_t *x) {
-  uint64_t st[kCellMaxStack];
-  int top = 0;
-  for (int i = 0; i < len; ++i) {
-    const int w = g.code[off + i], op = w & 0xff;
-    if (op == kCellIn) {
-      st[top++] = x[w >> 8];
-    } else if (op == kCellZero) {
-      st[top++] = 0ull;
-    } else if (op == kCellOne) {
-      st[top++] = ~0ull;
-    } else if (op == kCellNot) {
-      st[top - 1] = ~st[top - 1];
-    } else {
-      const uint64_t b = st[--top];
-      const uint64_t a = st[--top];
-      st[top++] = op == kCellAnd ? (a & b) : (op == kCellOr ? (a | b) : (a ^ b));
-    }
-  }
-  return st[0];
-}
-
 // Reverse mode over the code (Alg. 3): the forward pass keeps each binary
 // operation's operands, the backward pass walks the code in reverse with a
 // stack of output gradients (a binary operation replaces its gradient by its
@@ -410,44 +388,88 @@ __device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
   }
 }
 
-// A library cell's row: the code runs per word, one pair per lane per
-// iteration.
+// A library cell's Boolean function from its truth table (bit m = output for
+// the input pattern m, input k = bit k of m), by Shannon expansion depth
+// first: f = x_{N-1} ? f(x_{N-1} = 1) : f(x_{N-1} = 0), one bit select per
+// node, N + 1 words live.  The simulation needs exact bits only, which the
+// table gives; probabilities and partials follow the code (op by op).
+template <int N>
+__device__ __forceinline__ uint64_t tt_eval(const uint64_t *x, uint64_t tt, int base) {
+  if constexpr (N == 1) {
+    const uint64_t m0 = 0ull - ((tt >> base) & 1ull), m1 = 0ull - ((tt >> (base + 1)) & 1ull);
+    return (x[0] & m1) | (~x[0] & m0);
+  } else {
+    const uint64_t lo = tt_eval<N - 1>(x, tt, base);
+    const uint64_t hi = tt_eval<N - 1>(x, tt, base + (1 << (N - 1)));
+    return (x[N - 1] & hi) | (~x[N - 1] & lo);
+  }
+}
+
+// A library cell's row with N inputs: sim_gate_row with the table in place
+// of the fixed rule.
+template <int N, int ITERS>
+__device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint64_t tt,
+                                           const w2 *__restrict__ W, int64_t pp,
+                                           w2 *__restrict__ out, int32_t p_begin,
+                                           const ChunkView &c, int lane, uint32_t &ones,
+                                           uint32_t &togs) {
+  const w2 *r[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    r[k] = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[k * g.G + gi]) * pp;
+  uint64_t carry = 0;
+  if (p_begin > 0) {  // word just before this run, recomputed from its inputs
+    uint64_t x[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) x[k] = r[k][p_begin - 1].y;
+    carry = tt_eval<N>(x, tt, 0);
+  }
+  w2 v[N][ITERS];
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int32_t p = p_begin + it * 64 + lane;
+    const bool ok = p < c.pairs;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k][it] = ok ? r[k][p] : w2{0, 0};
+  }
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int32_t p = p_begin + it * 64 + lane;
+    uint64_t xa[N], xb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      xa[k] = v[k][it].x;
+      xb[k] = v[k][it].y;
+    }
+    const w2 y = w2{tt_eval<N>(xa, tt, 0), tt_eval<N>(xb, tt, 0)};
+    uint64_t prev = __shfl_up(y.y, 1u);
+    if (lane == 0) prev = carry;
+    carry = __shfl(y.y, 63);
+    if (p < c.pairs) {
+      out[p] = y;
+      count_pair(c, p, y, prev, ones, togs);
+    }
+  }
+}
+
 template <int ITERS>
 __device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t gi,
                                              const w2 *__restrict__ W, int64_t pp,
                                              w2 *__restrict__ out, int32_t p_begin,
                                              const ChunkView &c, int lane, uint32_t &ones,
                                              uint32_t &togs) {
-  int off, len, nin;
-  cell_info(g, op, off, len, nin);
-  int64_t row[kCellMaxIn];
-  for (int k = 0; k < nin; ++k)
-    row[k] = (int64_t)__builtin_amdgcn_readfirstlane(g.in[k * g.G + gi]) * pp;
-  uint64_t carry = 0;
-  if (p_begin > 0) {
-    uint64_t x[kCellMaxIn];
-    for (int k = 0; k < nin; ++k) x[k] = W[row[k] + p_begin - 1].y;
-    carry = cell_word(g, off, len, x);
-  }
-  for (int it = 0; it < ITERS; ++it) {
-    const int32_t p = p_begin + it * 64 + lane;
-    const bool ok = p < c.pairs;
-    uint64_t xa[kCellMaxIn], xb[kCellMaxIn];
-    for (int k = 0; k < nin; ++k) {
-      const w2 v = ok ? W[row[k] + p] : w2{0, 0};
-      xa[k] = v.x;
-      xb[k] = v.y;
-    }
-    w2 y;
-    y.x = cell_word(g, off, len, xa);
-    y.y = cell_word(g, off, len, xb);
-    uint64_t prev = __shfl_up(y.y, 1u);
-    if (lane == 0) prev = carry;
-    carry = __shfl(y.y, 63);
-    if (ok) {
-      out[p] = y;
-      count_pair(c, p, y, prev, ones, togs);
-    }
+  const int cl = op - kCellBase;
+  const int nin = __builtin_amdgcn_readfirstlane(g.cell[3 * cl + 2]);
+  const uint64_t t = g.tt[cl];
+  const uint64_t tt = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)t);
+  switch (nin) {
+    case 1: sim_tt_row<1, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
+    case 2: sim_tt_row<2, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
+    case 3: sim_tt_row<3, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
+    case 4: sim_tt_row<4, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
+    case 5: sim_tt_row<5, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
+    default: sim_tt_row<6, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
   }
 }
 
@@ -1474,7 +1496,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
                             const SimTune &tune, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (cells && sp) return hipErrorInvalidValue;  // no fused SP for library cells
-  const int iters = cells ? 1 : tune.iters;  // library cells: one pair per lane
+  const int iters = cells ? min(tune.iters, 2) : tune.iters;  // cells: up to 6 input rows
   const int32_t wpr = waves_per_row(c, iters);
   const int64_t tasks = (int64_t)n * wpr;
   const int64_t sim_blocks64 = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1489,7 +1511,10 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   const int32_t sim_blocks = (int32_t)sim_blocks64;
   const unsigned grid = (unsigned)(sim_blocks + sp_blocks);
   if (cells) {
-    k_sim_level<1, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+    if (iters == 1)
+      k_sim_level<1, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+    else
+      k_sim_level<2, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
     return hipGetLastError();
   }
   switch (iters) {

@@ -215,7 +215,7 @@ def test_library_errors(ctx):
     for bad, what in (("A&", "operand"), ("(A|B", "')'"), ("A $ B", "character"),
                       ("A B", "after"), ("a&b&c&d&e&f&g", "6 inputs"),
                       ("&".join(["A"] * 20), "32 operations"),
-                      ("A|(B|(C|(D|(E|(F|(A|(B|C)))))))", "8 stack")):
+                      ("A|(B|(C|(D|(E|(F|(A|(B|C)))))))", "8 stack"), ("1", "no inputs")):
         with pytest.raises(L.DiffPowerError, match="INVALID") as ei:
             compile_with([bad])
         assert what in str(ei.value), (bad, str(ei.value))
