@@ -1087,11 +1087,17 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   float seed = 0.0f, beta = 1.0f;
   const f2 z = f2{0.0f, 1.0f};
   f2 x0 = z, x1 = z, x2 = z;
+  int32_t s0 = 0, s1 = 0, s2 = 0;  // the fan-in slots the contributions go to
   const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
   if (active) {
     op = g.op[gi];
     k = CELLS ? 0 : arity_of(op);
     const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
+    if constexpr (!CELLS) {
+      s0 = g.slot[gi];
+      s1 = g.slot[g.G + gi];  // rows exist for every pin (unused pins hold 0)
+      s2 = g.slot[2 * g.G + gi];
+    }
     if (k > 0) x0 = sp[(int64_t)i0 * a.B + b];
     if (k > 1) x1 = sp[(int64_t)i1 * a.B + b];
     if (k > 2) x2 = sp[(int64_t)i2 * a.B + b];
@@ -1115,9 +1121,9 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   }
   float d0, d1, d2;
   sp_partials(op, x0, x1, x2, d0, d1, d2);
-  a.contrib[(int64_t)g.slot[gi] * a.C + c] = lam * d0;
-  if (k > 1) a.contrib[(int64_t)g.slot[g.G + gi] * a.C + c] = lam * d1;
-  if (k > 2) a.contrib[(int64_t)g.slot[2 * g.G + gi] * a.C + c] = lam * d2;
+  a.contrib[(int64_t)s0 * a.C + c] = lam * d0;
+  if (k > 1) a.contrib[(int64_t)s1 * a.C + c] = lam * d1;
+  if (k > 2) a.contrib[(int64_t)s2 * a.C + c] = lam * d2;
 }
 
 template <bool CELLS>
