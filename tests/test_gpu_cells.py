@@ -73,6 +73,49 @@ def test_each_library_cell_alone(ctx, c):
     assert_grad_close(g["dcap"], adj["dcap"], "dP/dC")
 
 
+# A cell at every limit at once: 6 inputs, 32 operations, 8 stack entries.
+LIMIT_CELL = "(A|(B|(C|(D|(E|(F|(A&B)))))))^(!C&!D)^(E|!F)^!(A^!B)"
+
+
+def test_cell_at_every_limit(ctx):
+    """Two levels of the limit cell (the second reading the first) next to
+    fixed cells: every output, counts bit-exact, gradients and adjoints."""
+    code, n_in = oracle.cell_code(LIMIT_CELL)
+    depth, top = 0, 0
+    for op, _ in code:
+        top += 1 if op in ("IN", "CONST0", "CONST1") else (0 if op == "NOT" else -1)
+        depth = max(depth, top)
+    assert (len(code), n_in, depth) == (32, 6, 8)
+    say("library cell at every limit")
+    rng = np.random.default_rng(11)
+    n_pi = 30
+    gates = [(synth.CELL_BASE, list(rng.choice(n_pi, size=6, replace=False))) for _ in range(300)]
+    lvl1 = n_pi + np.arange(300)
+    gates += [(synth.CELL_BASE, list(rng.choice(lvl1, size=6, replace=False))) for _ in range(200)]
+    gates += [(synth.AND2, list(rng.choice(lvl1, size=2, replace=False))) for _ in range(100)]
+    nl = synth.from_gates(n_pi, gates, (LIMIT_CELL,))
+    p = synth.pi_probs(n_pi, 12, batch=2)
+    cap = synth.net_caps(nl.n_nets, 13)
+    d = api.Design(ctx, nl)
+    assert d.depth == 2
+    ev = api.Eval(d, 2, mode=L.DP_HYBRID, n_sim=64 * 13, seed=4)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(FWD_ALL)
+    g = ev.backward(want=("dpi", "dcap"))
+    lam, _ = ev.power_gradients()
+    o = oracle.Netlist.of(nl)
+    dcap = np.zeros(nl.n_nets)
+    for b in range(2):
+        f, adj = oracle_column(o, p[b], cap, mode="hybrid", n_words=13, seed=4)
+        _check_forward(res, f, b, True)
+        assert_power_close(res["power"][b], f["power"], f"power[{b}]")
+        assert_grad_close(g["dpi"][b], adj["dpi"], f"dP/dp[{b}]")
+        assert_grad_close(lam[b], adj["lam"], f"lambda[{b}]")
+        dcap += adj["dcap"]
+    assert_grad_close(g["dcap"], dcap, "dP/dC")
+
+
 def test_waves_holding_several_library_cells(ctx):
     """One level of the nine library cells and the fixed cells in random
     order: after sorting, most waves hold several library cells, each taking
