@@ -218,14 +218,15 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
     }
     if (f > g0 && f < g1) ++d->split_levels;
   }
-  // cell code and table
-  std::vector<uint16_t> code;
+  // cell code, each cell's padded to kCellMaxCode words (64 bytes, so a lane
+  // loads it whole with four aligned 16-byte loads), and the cell table
+  std::vector<uint16_t> code((size_t)std::max(n_cells, 1) * kCellMaxCode, 0);
   std::vector<int32_t> cell_tab(3 * (size_t)std::max(n_cells, 1), 0);
   for (int32_t c = 0; c < n_cells; ++c) {
-    cell_tab[3 * c] = (int32_t)code.size();
+    cell_tab[3 * c] = c * kCellMaxCode;
     cell_tab[3 * c + 1] = (int32_t)lib[c].code.size();
     cell_tab[3 * c + 2] = lib[c].n_in;
-    code.insert(code.end(), lib[c].code.begin(), lib[c].code.end());
+    std::copy(lib[c].code.begin(), lib[c].code.end(), code.begin() + (size_t)c * kCellMaxCode);
   }
   std::vector<uint64_t> tt((size_t)std::max(n_cells, 1), 0);
   for (int32_t c = 0; c < n_cells; ++c) tt[c] = truth_table(lib[c]);

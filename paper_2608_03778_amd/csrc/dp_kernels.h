@@ -24,7 +24,7 @@ struct GraphView {
   const int32_t *rev_ptr;   // [n_nets + 1]
   const int32_t *rev_edge;  // [n_edges]
   const int32_t *slot;      // [pins][G] fan-out position of each pin
-  const uint16_t *code;     // library cells' stack code (op | arg << 8), concatenated
+  const uint16_t *code;     // [n_cells][kCellMaxCode] library cells' stack code (op | arg << 8), padded
   const int32_t *cell;      // [n_cells][3]: code offset, length, inputs
   const uint64_t *tt;       // [n_cells] truth tables: bit m = output for input pattern m
   int32_t pins;             // rows of in and slot (3, or the widest cell)

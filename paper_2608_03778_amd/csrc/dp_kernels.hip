@@ -96,12 +96,34 @@ __device__ __forceinline__ void sp_partials(int op, f2 a, f2 b, f2 c, float &d0,
 // operation: each binary operation applies its independent-input rule to its
 // two operands (Sec. III-E: AND ab, OR a + b - ab, XOR a + b - 2ab, NOT 1 - a),
 // in the same cancellation-free (p, q) form as the fixed cells.
-__device__ __forceinline__ void cell_info(const GraphView &g, int op, int &off, int &len,
-                                          int &nin) {
+// Each cell's code sits padded to kCellMaxCode words (64 bytes) at offset
+// c * kCellMaxCode, so a lane loads its whole program with four 16-byte
+// loads that depend only on the opcode, in flight with its input gathers,
+// and interprets it from registers.
+struct LaneCode {
+  uint32_t w[kCellMaxCode / 2];  // two instructions per dword
+  int len, nin;
+};
+
+__device__ __forceinline__ LaneCode lane_code(const GraphView &g, int op) {
+  LaneCode lc;
   const int c = op - kCellBase;
-  off = g.cell[3 * c];
-  len = g.cell[3 * c + 1];
-  nin = g.cell[3 * c + 2];
+  lc.len = g.cell[3 * c + 1];
+  lc.nin = g.cell[3 * c + 2];
+  const uint4 *src = reinterpret_cast<const uint4 *>(g.code + (int64_t)c * kCellMaxCode);
+#pragma unroll
+  for (int k = 0; k < kCellMaxCode / 8; ++k) {
+    const uint4 v = src[k];
+    lc.w[4 * k] = v.x;
+    lc.w[4 * k + 1] = v.y;
+    lc.w[4 * k + 2] = v.z;
+    lc.w[4 * k + 3] = v.w;
+  }
+  return lc;
+}
+
+__device__ __forceinline__ int code_at(const LaneCode &lc, int i) {
+  return (int)((lc.w[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
 }
 
 __device__ __forceinline__ f2 pair_op(int op, f2 a, f2 b) {
@@ -110,11 +132,11 @@ __device__ __forceinline__ f2 pair_op(int op, f2 a, f2 b) {
   return f2{fmaf(a.x, b.y, a.y * b.x), fmaf(a.x, b.x, a.y * b.y)};  // XOR
 }
 
-__device__ f2 cell_sp(const GraphView &g, int off, int len, const f2 *x) {
+__device__ f2 cell_sp(const LaneCode &lc, const f2 *x) {
   f2 st[kCellMaxStack];
   int top = 0;
-  for (int i = 0; i < len; ++i) {
-    const int w = g.code[off + i], op = w & 0xff;
+  for (int i = 0; i < lc.len; ++i) {
+    const int w = code_at(lc, i), op = w & 0xff;
     if (op == kCellIn) {
       st[top++] = x[w >> 8];
     } else if (op == kCellZero) {
@@ -137,14 +159,13 @@ __device__ f2 cell_sp(const GraphView &g, int off, int len, const f2 *x) {
 // stack of output gradients (a binary operation replaces its gradient by its
 // operands', the right operand's on top; NOT negates; an input adds to its
 // partial; a constant drops its gradient).
-__device__ void cell_partials(const GraphView &g, int off, int len, int nin, const f2 *x,
-                              float *d) {
+__device__ void cell_partials(const LaneCode &lc, const f2 *x, float *d) {
   f2 st[kCellMaxStack], ta[kCellMaxCode], tb[kCellMaxCode];
   float gs[kCellMaxStack + 1];
   int top = 0;
-  for (int k = 0; k < nin; ++k) d[k] = 0.0f;
-  for (int i = 0; i < len; ++i) {
-    const int w = g.code[off + i], op = w & 0xff;
+  for (int k = 0; k < lc.nin; ++k) d[k] = 0.0f;
+  for (int i = 0; i < lc.len; ++i) {
+    const int w = code_at(lc, i), op = w & 0xff;
     if (op == kCellIn) {
       st[top++] = x[w >> 8];
     } else if (op == kCellZero) {
@@ -163,8 +184,8 @@ __device__ void cell_partials(const GraphView &g, int off, int len, int nin, con
   }
   int gt = 0;
   gs[gt++] = 1.0f;
-  for (int i = len - 1; i >= 0; --i) {
-    const int w = g.code[off + i], op = w & 0xff;
+  for (int i = lc.len - 1; i >= 0; --i) {
+    const int w = code_at(lc, i), op = w & 0xff;
     const float gr = gs[--gt];
     if (op == kCellIn) {
       d[w >> 8] += gr;
@@ -285,11 +306,12 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int op = g.op[gi];
   f2 *sp = reinterpret_cast<f2 *>(lv.sp);
   if constexpr (CELLS) {
-    int off, len, nin;
-    cell_info(g, op, off, len, nin);
+    const LaneCode lc = lane_code(g, op);
+    // every pin row (unused pins alias pin 0), so the gathers need no count
     f2 x[kCellMaxIn];
-    for (int k = 0; k < nin; ++k) x[k] = sp[(int64_t)g.in[k * g.G + gi] * B + b];
-    sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(g, off, len, x));
+    for (int k = 0; k < kCellMaxIn; ++k)
+      x[k] = k < g.pins ? sp[(int64_t)g.in[k * g.G + gi] * B + b] : f2{0.0f, 1.0f};
+    sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(lc, x));
     return;
   }
   const int k = arity_of(op);
@@ -1110,13 +1132,14 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   if (a.ste) lam *= beta;
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
-    int off, len, nin;
-    cell_info(g, op, off, len, nin);
+    const LaneCode lc = lane_code(g, op);
     f2 x[kCellMaxIn];
     float d[kCellMaxIn];
-    for (int j = 0; j < nin; ++j) x[j] = sp[(int64_t)g.in[j * g.G + gi] * a.B + b];
-    cell_partials(g, off, len, nin, x, d);
-    for (int j = 0; j < nin; ++j) a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
+    for (int j = 0; j < kCellMaxIn; ++j)
+      x[j] = j < g.pins ? sp[(int64_t)g.in[j * g.G + gi] * a.B + b] : z;
+    cell_partials(lc, x, d);
+    for (int j = 0; j < lc.nin; ++j)
+      a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
     return;
   }
   float d0, d1, d2;
