@@ -1,0 +1,359 @@
+// CPU stand-in for the HIP runtime and the kernel launchers, for running the
+// library's host code (compile, validation, schedules, merged tables, the
+// serving scheduler) without a GPU.  "Device" memory is host malloc; each
+// launcher checks its launch against the design and touches the first and
+// last element of every extent the real kernel reads or writes, so a
+// host/kernel size disagreement faults here (or shows up under a sanitizer).
+// No kernel arithmetic runs: outputs are placeholders.  Test infrastructure.
+#include <hip/hip_runtime_api.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <algorithm>
+#include <mutex>
+#include <set>
+
+#include DP_KERNELS_H
+
+struct ihipStream_t { int capturing = 0; };
+struct ihipEvent_t { int x = 0; };
+struct ihipGraph { int x = 0; };
+struct hipGraphExec { int x = 0; };
+
+static std::mutex g_mu;
+static std::set<void *> g_live;
+
+static void note_alloc(void *p) { std::lock_guard<std::mutex> l(g_mu); g_live.insert(p); }
+static bool note_free(void *p) {
+  std::lock_guard<std::mutex> l(g_mu);
+  return g_live.erase(p) == 1;
+}
+
+extern "C" {
+hipError_t hipMalloc(void **ptr, size_t size) {
+  *ptr = std::malloc(size ? size : 1);
+  note_alloc(*ptr);
+  return hipSuccess;
+}
+hipError_t hipFree(void *ptr) {
+  if (!ptr) return hipSuccess;
+  if (!note_free(ptr)) { std::fprintf(stderr, "STUB: hipFree of unknown %p\n", ptr); std::abort(); }
+  std::free(ptr);
+  return hipSuccess;
+}
+hipError_t hipHostMalloc(void **ptr, size_t size, unsigned int) { return hipMalloc(ptr, size); }
+hipError_t hipHostFree(void *ptr) { return hipFree(ptr); }
+hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, hipStream_t) {
+  if (n) std::memmove(dst, src, n);
+  return hipSuccess;
+}
+hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind) {
+  if (n) std::memmove(dst, src, n);
+  return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+const char *hipGetErrorString(hipError_t) { return "stub error"; }
+hipError_t hipSetDevice(int d) { return d == 0 ? hipSuccess : hipErrorInvalidDevice; }
+hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
+hipError_t hipGetLastError(void) { return hipSuccess; }
+hipError_t hipEventCreate(hipEvent_t *e) { *e = new ihipEvent_t(); return hipSuccess; }
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { *e = new ihipEvent_t(); return hipSuccess; }
+hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->x++; return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t e) { (void)e->x; return hipSuccess; }
+hipError_t hipEventQuery(hipEvent_t e) { (void)e->x; return hipSuccess; }
+hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
+  (void)a->x; (void)b->x;
+  *ms = 0.001f;
+  return hipSuccess;
+}
+hipError_t hipStreamCreate(hipStream_t *s) { *s = new ihipStream_t(); return hipSuccess; }
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = new ihipStream_t(); return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) { delete s; return hipSuccess; }
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+  if (s) (void)s->capturing;
+  (void)e->x;
+  return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+  if (!s) return hipErrorInvalidValue;
+  s->capturing = 1;
+  return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g) {
+  s->capturing = 0;
+  *g = new ihipGraph();
+  return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, hipGraphNode_t *, char *, size_t) {
+  (void)g->x;
+  *x = new hipGraphExec();
+  return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t x) { delete x; return hipSuccess; }
+hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) { (void)x->x; return hipSuccess; }
+}
+
+// ---- launchers: touch the extents ------------------------------------------
+#define CONTRIB_ELEMS(g) n_edges_of(g)
+namespace {
+template <class T>
+void rd(const T *p, int64_t n) {
+  if (n <= 0) return;
+  if (!p) { std::fprintf(stderr, "STUB: null read of %lld\n", (long long)n); std::abort(); }
+  volatile T a = p[0]; volatile T b = p[n - 1]; (void)a; (void)b;
+}
+template <class T>
+void wr(T *p, int64_t n) {
+  if (n <= 0) return;
+  if (!p) { std::fprintf(stderr, "STUB: null write of %lld\n", (long long)n); std::abort(); }
+  std::memset((void *)&p[0], 0, sizeof(T));
+  std::memset((void *)&p[n - 1], 0, sizeof(T));
+}
+int64_t n_edges_of(const dp::GraphView &g) { return g.rev_ptr[g.n_nets]; }
+void rd_graph(const dp::GraphView &g, int32_t g0, int32_t n, bool cells) {
+  rd(g.op + g0, n);
+  for (int k = 0; k < g.pins; ++k) rd(g.in + (int64_t)k * g.G + g0, n);
+  for (int k = 0; k < g.pins; ++k) rd(g.slot + (int64_t)k * g.G + g0, n);
+  if (g0 < 0 || n < 0 || g0 + n > g.G) { std::fprintf(stderr, "STUB: range out of G\n"); std::abort(); }
+  for (int32_t i = g0; i < g0 + n; ++i) {
+    const bool is_cell = g.op[i] >= dp::kCellBase;
+    if (is_cell != cells) { std::fprintf(stderr, "STUB: gate %d kind mismatch\n", i); std::abort(); }
+    if (is_cell) {
+      const int c = g.op[i] - dp::kCellBase;
+      const int off = g.cell[3 * c], len = g.cell[3 * c + 1], nin = g.cell[3 * c + 2];
+      rd(g.code + off, len);
+      rd(g.tt + c, 1);
+      if (nin > g.pins || len > dp::kCellMaxCode) { std::fprintf(stderr, "STUB: cell\n"); std::abort(); }
+    }
+  }
+}
+}  // namespace
+
+namespace dp {
+constexpr int32_t kPowerChunk = 8192, kSlabNets = 2048;
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t) {
+  for (int64_t i = 0; i < n; ++i) p[i] = v;
+  return hipSuccess;
+}
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t) {
+  for (int64_t i = 0; i < n; ++i) p[i] = v;
+  return hipSuccess;
+}
+hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t) {
+  rd(p, (int64_t)n_pi * B);
+  wr(sp, (int64_t)n_pi * B * 2);
+  return hipSuccess;
+}
+hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
+                              hipStream_t) {
+  int32_t b = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(v[i] >= lo && v[i] <= hi)) b = 1;
+  *bad = b;
+  return hipSuccess;
+}
+hipError_t launch_gather_nets_f32(const float *src, const int32_t *int2ext, float *dst,
+                                  int32_t n_nets, hipStream_t) {
+  for (int32_t i = 0; i < n_nets; ++i) dst[i] = src[int2ext[i]];
+  return hipSuccess;
+}
+hipError_t launch_import_cols_f32(const float *src, const int32_t *int2ext, float *dst,
+                                  int32_t n_nets, int32_t B, hipStream_t) {
+  for (int32_t i = 0; i < n_nets; ++i)
+    for (int32_t b = 0; b < B; ++b) dst[(int64_t)i * B + b] = src[(int64_t)b * n_nets + int2ext[i]];
+  return hipSuccess;
+}
+hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *dst, int32_t n_pi,
+                               int32_t G, int32_t S, hipStream_t) {
+  rd(int2ext, n_pi + G);
+  rd(src, (int64_t)S * G);
+  wr(dst, (int64_t)S * G);
+  return hipSuccess;
+}
+hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t) {
+  rd_graph(g, lv.g0, lv.n, cells);
+  wr(lv.sp + (int64_t)(g.n_pi + lv.g0) * lv.B * 2, (int64_t)lv.n * lv.B * 2);
+  return hipSuccess;
+}
+hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
+                               int32_t n_pi, int32_t B, int64_t T, uint64_t, uint64_t *out,
+                               hipStream_t) {
+  rd(sp, (int64_t)n_pi * B * 2);
+  rd(tau, (int64_t)n_pi * B);
+  if (stream) {
+    rd(stream, n_pi);
+    for (int32_t i = 0; i < n_pi; ++i)
+      if (stream[i] < 0 || stream[i] >= n_pi) { std::fprintf(stderr, "STUB: stream\n"); std::abort(); }
+  }
+  wr(out, (int64_t)n_pi * B * T);
+  return hipSuccess;
+}
+hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
+                           const float *p_col, const uint64_t *stim, int64_t T,
+                           const int32_t *stream, uint64_t, const SimTune &, hipStream_t) {
+  if (stream) rd(stream, g.n_pi);
+  wr(c.W, (int64_t)g.n_pi * c.pitch);
+  rd(p_col, (int64_t)g.n_pi * cnt.B * 2);
+  if (stim) rd(stim, (int64_t)g.n_pi * T);
+  wr(cnt.ones, (int64_t)g.n_pi * cnt.B);
+  wr(cnt.tog, (int64_t)g.n_pi * cnt.B);
+  if (c.u_hi > c.pitch || c.u_lo < 0 || 2 * c.pairs > c.pitch) {
+    std::fprintf(stderr, "STUB: chunk view out of pitch\n");
+    std::abort();
+  }
+  return hipSuccess;
+}
+hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
+                            int32_t g0, int32_t n, const SpLevel *sp, bool cells,
+                            const SimTune &, hipStream_t) {
+  if (cells && sp) { std::fprintf(stderr, "STUB: fused SP on a library-cell range\n"); std::abort(); }
+  rd_graph(g, g0, n, cells);
+  wr(c.W + (int64_t)(g.n_pi + g0) * c.pitch, (int64_t)n * c.pitch);
+  wr(cnt.ones + (int64_t)(g.n_pi + g0) * cnt.B, (int64_t)n * cnt.B);
+  wr(cnt.tog + (int64_t)(g.n_pi + g0) * cnt.B, (int64_t)n * cnt.B);
+  if (sp) wr(sp->sp + (int64_t)(g.n_pi + g0) * sp->B * 2, (int64_t)n * sp->B * 2);
+  return hipSuccess;
+}
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t) {
+  const int64_t nb = (int64_t)a.n_nets * a.B;
+  rd(a.sp, nb * 2);
+  if (a.ones) rd(a.ones, nb);
+  if (a.tog) rd(a.tog, nb);
+  if (a.beta_frozen) rd(a.beta_frozen, a.beta_shared ? a.n_nets : nb);
+  rd(a.cap, a.n_nets);
+  if (a.beta) wr(a.beta, nb);
+  wr(a.xterm, nb);
+  return hipSuccess;
+}
+hipError_t launch_export(const ExportArgs &a, hipStream_t) {
+  const int64_t nb = (int64_t)a.n_nets * a.B;
+  rd(a.sp, nb * 2);
+  if (a.beta) rd(a.beta, nb);
+  rd(a.int2ext, a.n_nets);
+  if (a.o_sp) wr(a.o_sp, nb);
+  if (a.o_tr) wr(a.o_tr, nb);
+  if (a.o_sp_acc) { rd(a.ones, nb); wr(a.o_sp_acc, nb); }
+  if (a.o_tr_acc) { rd(a.tog, nb); wr(a.o_tr_acc, nb); }
+  if (a.o_beta) wr(a.o_beta, nb);
+  if (a.o_tr_hyb) wr(a.o_tr_hyb, nb);
+  if (a.o_ones) { rd(a.ones, nb); wr(a.o_ones, nb); }
+  if (a.o_tog) { rd(a.tog, nb); wr(a.o_tog, nb); }
+  return hipSuccess;
+}
+int32_t power_chunks(int32_t n_nets) {
+  return n_nets <= 0 ? 1 : (n_nets + kPowerChunk - 1) / kPowerChunk;
+}
+int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t paired) {
+  const int64_t cols = (int64_t)B * ((S > 0 && !paired) ? S : 1);
+  int64_t slabs = power_chunks(n_nets);
+  if (S > 0 && !paired) slabs = std::max<int64_t>(slabs, (n_nets + kSlabNets - 1) / kSlabNets);
+  return (int32_t)(slabs * cols);
+}
+hipError_t launch_power(const PowerArgs &a, hipStream_t) {
+  const int64_t nb = (int64_t)a.n_nets * a.B;
+  rd(a.xterm, nb);
+  rd(a.cap, a.n_nets);
+  if (a.S > 0 && a.size) rd(a.size, (int64_t)a.S * a.G);
+  wr(a.partial, power_partial_doubles(a.n_nets, a.B, a.S, a.paired));
+  const int64_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
+  wr(a.power, a.B * Sp);
+  return hipSuccess;
+}
+hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
+                            bool cells, hipStream_t) {
+  rd_graph(g, g0, n, cells);
+  rd(a.sp, (int64_t)g.n_nets * a.B * 2);
+  rd(a.cap, g.n_nets);
+  if (a.size) rd(a.size, (int64_t)(a.S > 0 ? a.S : a.B) * a.G);
+  if (a.w) rd(a.w, (int64_t)a.C);
+  wr(a.contrib, CONTRIB_ELEMS(g) * a.C);
+  if (a.lam) wr(a.lam, (int64_t)g.n_nets * a.C);
+  if (a.beta) rd(a.beta, (int64_t)g.n_nets * a.B);
+  if ((int64_t)a.C > (int64_t)a.B * a.cdiv) { std::fprintf(stderr, "STUB: C > B*cdiv\n"); std::abort(); }
+  return hipSuccess;
+}
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t) {
+  if (a.fixed) rd(a.fixed, g.n_pi);
+  rd(a.contrib, CONTRIB_ELEMS(g) * a.C);
+  wr(out, (int64_t)a.C * g.n_pi);
+  return hipSuccess;
+}
+hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
+                                int32_t depth, int64_t, hipStream_t) {
+  rd(level_ptr, depth + 2);
+  wr(lv.sp, (int64_t)g.n_nets * lv.B * 2);
+  return hipSuccess;
+}
+hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
+                                 int32_t depth, int64_t, float *pi_out, hipStream_t s) {
+  rd(level_ptr, depth + 2);
+  return launch_bwd_pi(g, a, pi_out, s);
+}
+hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
+                           hipStream_t st) {
+  for (int32_t k = 0; k < n_segs; ++k) {
+    const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
+    if (b1 < b0 || (int64_t)(b1 - b0) * 256 < (int64_t)segs[k].lv.n * segs[k].lv.B) {
+      std::fprintf(stderr, "STUB: sp segment %d too small\n", k);
+      std::abort();
+    }
+    launch_sp_level(segs[k].g, segs[k].lv, cells, st);
+  }
+  return hipSuccess;
+}
+hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
+                            hipStream_t st) {
+  for (int32_t k = 0; k < n_segs; ++k) {
+    const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
+    if (b1 < b0 || (int64_t)(b1 - b0) * 256 < (int64_t)segs[k].n * segs[k].a.C) {
+      std::fprintf(stderr, "STUB: bwd segment %d too small\n", k);
+      std::abort();
+    }
+    launch_bwd_level(segs[k].g, segs[k].a, segs[k].g0, segs[k].n, cells, st);
+  }
+  return hipSuccess;
+}
+hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const int32_t *int2ext,
+                                     int32_t n_pi, int32_t n_nets, int32_t B, int32_t C,
+                                     int32_t, float, float *lam_out, float *score, hipStream_t) {
+  rd(lam, (int64_t)n_nets * C);
+  rd(sp, (int64_t)n_nets * B * 2);
+  rd(int2ext, n_nets);
+  if (lam_out) wr(lam_out, (int64_t)n_nets * C);
+  if (score) wr(score, (int64_t)(n_nets - n_pi) * C);
+  return hipSuccess;
+}
+hipError_t launch_virus_step(float *sp, const float *grad, float, int32_t n_pi, int32_t B, hipStream_t) {
+  wr(sp, (int64_t)n_pi * B * 2);
+  rd(grad, (int64_t)n_pi * B);
+  return hipSuccess;
+}
+hipError_t launch_virus_vectors(const float *sp, uint64_t *stim, uint8_t *v0, float *p_out,
+                                int32_t n_pi, int32_t B, hipStream_t) {
+  rd(sp, (int64_t)n_pi * B * 2);
+  wr(stim, (int64_t)n_pi * B * 2);
+  wr(v0, (int64_t)n_pi * B);
+  if (p_out) wr(p_out, (int64_t)n_pi * B);
+  return hipSuccess;
+}
+hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_nets, int32_t B,
+                              double *out, hipStream_t) {
+  rd(tog, (int64_t)n_nets * B);
+  rd(cap, n_nets);
+  wr(out, B);
+  return hipSuccess;
+}
+hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t) {
+  const int64_t nb = (int64_t)a.n_nets * a.B;
+  rd(a.xterm, nb);
+  rd(a.cap, a.n_nets);
+  rd(a.int2ext, a.n_nets);
+  if (a.dcap) wr(a.dcap, a.n_nets);
+  if (a.dsize) wr(a.dsize, (int64_t)a.S * a.G);
+  return hipSuccess;
+}
+}  // namespace dp
