@@ -296,6 +296,25 @@ __global__ __launch_bounds__(kBlock) void k_import_sizes(const float *__restrict
 // probabilities, apply the cell rule, clip to [0, 1] (Alg. 2).
 // CELLS: the range holds library cells only (their own kernel instances, so
 // the fixed-cell kernels keep their register budget).
+// Row j of a per-pin table ([pins][G]), or row 0 where the design's widest
+// gate has fewer pins: a choice of address that is uniform across the
+// launch, so a gather through it waits on no other load.  (In the fan-in
+// table, pins a gate does not use alias its pin 0; callers ignore them.)
+__device__ __forceinline__ const int32_t *pin_row(const int32_t *tab, const GraphView &g, int j) {
+  return tab + (g.pins > j ? (int64_t)j * g.G : 0);
+}
+
+// Takes loaded values at this point: every load before it is then issued
+// ahead of the first wait, and none can be moved into the branch of the one
+// opcode that reads it or behind a use of another (each would add a
+// dependent round trip).
+template <typename T>
+__device__ __forceinline__ void value_taken(T v) { asm volatile("" ::"v"(v)); }
+template <typename... V>
+__device__ __forceinline__ void gathers_done(V... v) {
+  (value_taken(v), ...);
+}
+
 template <bool CELLS>
 __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, uint32_t idx) {
   const int32_t B = lv.B;
@@ -314,12 +333,19 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
     sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(lc, x));
     return;
   }
+  // every gather is issued before the opcode is known, so the level costs
+  // two dependent load rounds (indices, then probabilities)
+  const int32_t i0 = g.in[gi];
+  const int32_t i1 = pin_row(g.in, g, 1)[gi];
+  const int32_t i2 = pin_row(g.in, g, 2)[gi];
+  gathers_done(op, i0, i1, i2);
+  const f2 a = sp[(int64_t)i0 * B + b];
+  const f2 bv = sp[(int64_t)i1 * B + b];
+  const f2 cv = sp[(int64_t)i2 * B + b];
+  gathers_done(a.x, a.y, bv.x, bv.y, cv.x, cv.y);
   const int k = arity_of(op);
   const f2 z = f2{0.0f, 1.0f};
-  const f2 a = sp[(int64_t)g.in[gi] * B + b];
-  const f2 bb = k > 1 ? sp[(int64_t)g.in[g.G + gi] * B + b] : z;
-  const f2 cc = k > 2 ? sp[(int64_t)g.in[2 * g.G + gi] * B + b] : z;
-  sp[(int64_t)(g.n_pi + gi) * B + b] = settle(sp_rule(op, a, bb, cc));
+  sp[(int64_t)(g.n_pi + gi) * B + b] = settle(sp_rule(op, a, k > 1 ? bv : z, k > 2 ? cv : z));
 }
 
 __global__ __launch_bounds__(kBlock) void k_sp_level(GraphView g, SpLevel lv) {
@@ -348,9 +374,16 @@ __global__ __launch_bounds__(kBlock) void k_sp_level_x2(GraphView g, SpLevel lv)
   const f4 *sp4 = reinterpret_cast<const f4 *>(lv.sp);
   const int64_t B2 = lv.B / 2;
   const f4 z = f4{0.0f, 1.0f, 0.0f, 1.0f};
-  const f4 a = sp4[(int64_t)g.in[gi] * B2 + b / 2];
-  const f4 bb = k > 1 ? sp4[(int64_t)g.in[g.G + gi] * B2 + b / 2] : z;
-  const f4 cc = k > 2 ? sp4[(int64_t)g.in[2 * g.G + gi] * B2 + b / 2] : z;
+  const int32_t i0 = g.in[gi];
+  const int32_t i1 = pin_row(g.in, g, 1)[gi];
+  const int32_t i2 = pin_row(g.in, g, 2)[gi];
+  gathers_done(op, i0, i1, i2);
+  const f4 a = sp4[(int64_t)i0 * B2 + b / 2];
+  const f4 bl = sp4[(int64_t)i1 * B2 + b / 2];
+  const f4 cl = sp4[(int64_t)i2 * B2 + b / 2];
+  gathers_done(a.x, a.y, a.z, a.w, bl.x, bl.y, bl.z, bl.w, cl.x, cl.y, cl.z, cl.w);
+  const f4 bb = k > 1 ? bl : z;
+  const f4 cc = k > 2 ? cl : z;
   const f2 r0 = settle(sp_rule(op, f2{a.x, a.y}, f2{bb.x, bb.y}, f2{cc.x, cc.y}));
   const f2 r1 = settle(sp_rule(op, f2{a.z, a.w}, f2{bb.z, bb.w}, f2{cc.z, cc.w}));
   reinterpret_cast<f4 *>(lv.sp)[(int64_t)(g.n_pi + gi) * B2 + b / 2] = f4{r0.x, r0.y, r1.x, r1.y};
@@ -937,8 +970,8 @@ __global__ __launch_bounds__(kBlock) void k_power_final(PowerArgs a, int32_t n_c
 // Eq. 7), times beta (unless STE), the upstream weight and the driver's size
 // factor (per column, paired, or summed over the size vectors).
 __device__ __forceinline__ float seed_of(const BwdArgs &a, int32_t n, int32_t c, int32_t b,
-                                         f2 pq, float beta) {
-  const float local = a.kappa * a.cap[n] * 2.0f * (pq.y - pq.x);
+                                         f2 pq, float beta, float cap) {
+  const float local = a.kappa * cap * 2.0f * (pq.y - pq.x);
   const float base = a.ste ? local : beta * local;
   const bool gate = n >= a.n_pi && a.size;
   const int64_t g = (int64_t)(n - a.n_pi);
@@ -981,17 +1014,28 @@ __device__ __forceinline__ float seed_of(const BwdArgs &a, int32_t n, int32_t c,
 constexpr int32_t kStrand = 8;
 constexpr int32_t kSerialColumns = 32;  // C at which every pull is lane-serial
 
-__device__ __forceinline__ float strand_sum(const float *__restrict__ contrib, int32_t e,
-                                            int32_t e1, int32_t C, int32_t c) {
-  const int32_t m = min(kStrand, e1 - e);
-  float v[kStrand];
+// The entries [e, min(e + kStrand, e1)) of one strand into v (zeros past e1).
+__device__ __forceinline__ void strand_load(const float *__restrict__ contrib, int32_t e,
+                                            int32_t e1, int32_t C, int32_t c,
+                                            float (&v)[kStrand]) {
 #pragma unroll
-  for (int i = 0; i < kStrand; ++i) v[i] = i < m ? contrib[(int64_t)(e + i) * C + c] : 0.0f;
+  for (int i = 0; i < kStrand; ++i) v[i] = e + i < e1 ? contrib[(int64_t)(e + i) * C + c] : 0.0f;
+}
+
+// A strand's sum in entry order; m = entries left from the strand's start.
+__device__ __forceinline__ float strand_fold(const float (&v)[kStrand], int32_t m) {
   float acc = v[0];
 #pragma unroll
   for (int i = 1; i < kStrand; ++i)
     if (i < m) acc += v[i];
   return acc;
+}
+
+__device__ __forceinline__ float strand_sum(const float *__restrict__ contrib, int32_t e,
+                                            int32_t e1, int32_t C, int32_t c) {
+  float v[kStrand];
+  strand_load(contrib, e, e1, C, c, v);
+  return strand_fold(v, e1 - e);
 }
 
 // The canonical sum by one lane: a single strand directly; longer ranges four
@@ -1022,35 +1066,48 @@ __device__ __forceinline__ float serial_pull(const float *__restrict__ contrib, 
 __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int32_t e0,
                                           int32_t e1, int32_t C, int32_t c, bool active,
                                           int lane, bool serial) {
-  float acc = 0.0f;
-  const bool mine = active && (serial || e1 - e0 <= kStrand);
-  if (mine) acc = serial_pull(contrib, e0, e1, C, c);
-  if (serial) return acc;
-  uint64_t heavy = __ballot(active && !mine);
-  if (!heavy) return acc;
+  if (serial) return active ? serial_pull(contrib, e0, e1, C, c) : 0.0f;
+  const bool light = active && e1 - e0 <= kStrand;
+  uint64_t heavy = __ballot(active && !light);
   // the wave's heavy nets take consecutive strand positions (lane order);
-  // when they fit in 64, one round of loads covers them all
-  const int32_t cnt = ((heavy >> lane) & 1) ? (e1 - e0 + kStrand - 1) / kStrand : 0;
-  int32_t inc = cnt;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t t = __shfl_up(inc, (unsigned)d);
-    if (lane >= d) inc += t;
-  }
-  if (__builtin_amdgcn_readfirstlane(__shfl(inc, 63)) <= 64) {
-    const int32_t off = inc - cnt;
-    int32_t my_h = -1, my_j = 0;
-    for (uint64_t hh = heavy; hh; hh &= hh - 1) {
-      const int h = __builtin_ctzll(hh);
-      const int32_t ho = __builtin_amdgcn_readfirstlane(__shfl(off, h));
-      const int32_t hc = __builtin_amdgcn_readfirstlane(__shfl(cnt, h));
-      if (lane >= ho && lane < ho + hc) {
-        my_h = h;
-        my_j = lane - ho;
-      }
+  // when they fit in 64, their strands load in the same round as the light
+  // ranges
+  bool batched = false;
+  int32_t cnt = 0, off = 0, my_h = -1, my_j = 0;
+  if (heavy) {
+    cnt = ((heavy >> lane) & 1) ? (e1 - e0 + kStrand - 1) / kStrand : 0;
+    int32_t inc = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t t = __shfl_up(inc, (unsigned)d);
+      if (lane >= d) inc += t;
     }
+    off = inc - cnt;
+    batched = __builtin_amdgcn_readfirstlane(__shfl(inc, 63)) <= 64;
+    if (batched)
+      for (uint64_t hh = heavy; hh; hh &= hh - 1) {
+        const int h = __builtin_ctzll(hh);
+        const int32_t ho = __builtin_amdgcn_readfirstlane(__shfl(off, h));
+        const int32_t hc = __builtin_amdgcn_readfirstlane(__shfl(cnt, h));
+        if (lane >= ho && lane < ho + hc) {
+          my_h = h;
+          my_j = lane - ho;
+        }
+      }
+  }
+  int32_t hbeg = 0, hend = 0, hcol = 0;
+  if (batched) {
     const int src = my_h < 0 ? lane : my_h;
-    const int32_t h0 = __shfl(e0, src), h1 = __shfl(e1, src), hcol = __shfl(c, src);
-    const float v = my_h >= 0 ? strand_sum(contrib, h0 + my_j * kStrand, h1, C, hcol) : 0.0f;
+    hbeg = __shfl(e0, src) + my_j * kStrand;
+    hend = __shfl(e1, src);
+    hcol = __shfl(c, src);
+  }
+  float lv[kStrand], hv[kStrand];
+  if (light) strand_load(contrib, e0, e1, C, c, lv);
+  if (my_h >= 0) strand_load(contrib, hbeg, hend, C, hcol, hv);
+  float acc = light ? strand_fold(lv, e1 - e0) : 0.0f;
+  if (!heavy) return acc;
+  if (batched) {
+    const float v = my_h >= 0 ? strand_fold(hv, hend - hbeg) : 0.0f;
     // each heavy net folds its strand sums in strand order
     for (uint64_t hh = heavy; hh; hh &= hh - 1) {
       const int h = __builtin_ctzll(hh);
@@ -1092,46 +1149,36 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
 // innermost; item counts stay below 2^31.
 // One (gate, column) item of a reverse level; every lane of the wave calls
 // it (pull_sum needs the whole wave), lanes past the end pass active = false.
-template <bool CELLS>
+// WIDE: the launch's column count is at least kSerialColumns (pulls are
+// lane-serial); a choice per launch, so each form keeps its own registers.
+template <bool CELLS, bool WIDE>
 __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, int32_t g0,
                                          int32_t n, uint32_t idx, int lane) {
   const bool active = idx < (uint32_t)n * (uint32_t)a.C;
+  // lanes past the end read row g0 (a level has at least one gate) and
+  // store nothing, so every load below is unconditional
   const uint32_t gl = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - gl * (uint32_t)a.C) : 0;
   const int32_t gi = g0 + (int32_t)gl;
   const int32_t out = g.n_pi + gi;
-  const int32_t e0 = active ? g.rev_ptr[out] : 0;
-  const int32_t e1 = active ? g.rev_ptr[out + 1] : 0;
-  // loads that do not depend on the pull are issued first, so their latency
-  // overlaps the fan-out gather
   const int32_t b = c / a.cdiv;
-  int op = 0, k = 1;
-  float seed = 0.0f, beta = 1.0f;
-  const f2 z = f2{0.0f, 1.0f};
-  f2 x0 = z, x1 = z, x2 = z;
-  int32_t s0 = 0, s1 = 0, s2 = 0;  // the fan-in slots the contributions go to
   const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
-  if (active) {
-    op = g.op[gi];
-    k = CELLS ? 0 : arity_of(op);
-    const int32_t i0 = g.in[gi], i1 = g.in[g.G + gi], i2 = g.in[2 * g.G + gi];
-    if constexpr (!CELLS) {
-      s0 = g.slot[gi];
-      s1 = g.slot[g.G + gi];  // rows exist for every pin (unused pins hold 0)
-      s2 = g.slot[2 * g.G + gi];
-    }
-    if (k > 0) x0 = sp[(int64_t)i0 * a.B + b];
-    if (k > 1) x1 = sp[(int64_t)i1 * a.B + b];
-    if (k > 2) x2 = sp[(int64_t)i2 * a.B + b];
-    if (a.beta) beta = a.beta[(int64_t)out * a.B + b];
-    seed = seed_of(a, out, c, b, sp[(int64_t)out * a.B + b], beta);
-  }
-  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
-  if (!active) return;
-  float lam = seed + pulled;
-  if (a.ste) lam *= beta;
-  if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
+  const f2 z = f2{0.0f, 1.0f};
+  // first round: the item's structure and its own net's values; nothing here
+  // waits on another load
+  const int32_t e0 = g.rev_ptr[out];
+  const int32_t e1r = g.rev_ptr[out + 1];
+  const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
+  const int op = g.op[gi];
+  const f2 pq = sp[(int64_t)out * a.B + b];
+  const float beta = a.beta ? a.beta[(int64_t)out * a.B + b] : 1.0f;
+  const float cap = a.cap[out];
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
+    const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, WIDE);
+    if (!active) return;
+    float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
+    if (a.ste) lam *= beta;
+    if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
     const LaneCode lc = lane_code(g, op);
     f2 x[kCellMaxIn];
     float d[kCellMaxIn];
@@ -1142,17 +1189,57 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
       a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
     return;
   }
+  int32_t i0, i1, i2, s0, s1, s2;  // fan-in nets and the slots their contributions go to
+  f2 x0, x1, x2;
+  if constexpr (WIDE) {
+    // many columns: a wave's lanes share one or two gates, and the sweep is
+    // bound by the rows it moves, so only the pins a gate has are gathered
+    const int k = arity_of(op);
+    i0 = g.in[gi];
+    s0 = g.slot[gi];
+    x0 = sp[(int64_t)i0 * a.B + b];
+    x1 = x2 = z;
+    s1 = s2 = 0;
+    if (k > 1) {
+      i1 = g.in[g.G + gi];
+      s1 = g.slot[g.G + gi];
+      x1 = sp[(int64_t)i1 * a.B + b];
+    }
+    if (k > 2) {
+      i2 = g.in[2 * g.G + gi];
+      s2 = g.slot[2 * g.G + gi];
+      x2 = sp[(int64_t)i2 * a.B + b];
+    }
+  } else {
+    // few columns: the sweep is bound by round trips, so every gather goes
+    // out in the second round whatever the opcode
+    i0 = g.in[gi];
+    i1 = pin_row(g.in, g, 1)[gi];
+    i2 = pin_row(g.in, g, 2)[gi];
+    s0 = g.slot[gi];
+    s1 = pin_row(g.slot, g, 1)[gi];
+    s2 = pin_row(g.slot, g, 2)[gi];
+    x0 = sp[(int64_t)i0 * a.B + b];
+    x1 = sp[(int64_t)i1 * a.B + b];
+    x2 = sp[(int64_t)i2 * a.B + b];
+  }
+  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, WIDE);
+  if (!active) return;
+  float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
+  if (a.ste) lam *= beta;
+  if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
+  const int k = arity_of(op);
   float d0, d1, d2;
-  sp_partials(op, x0, x1, x2, d0, d1, d2);
+  sp_partials(op, x0, k > 1 ? x1 : z, k > 2 ? x2 : z, d0, d1, d2);
   a.contrib[(int64_t)s0 * a.C + c] = lam * d0;
   if (k > 1) a.contrib[(int64_t)s1 * a.C + c] = lam * d1;
   if (k > 2) a.contrib[(int64_t)s2 * a.C + c] = lam * d2;
 }
 
-template <bool CELLS>
+template <bool CELLS, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
                                                       int32_t n) {
-  bwd_item<CELLS>(g, a, g0, n, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+  bwd_item<CELLS, WIDE>(g, a, g0, n, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
 }
 
 __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a, float *out,
@@ -1160,18 +1247,16 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   const bool active = idx < (uint32_t)g.n_pi * (uint32_t)a.C;
   const uint32_t i = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - i * (uint32_t)a.C) : 0;
-  const int32_t e0 = active ? g.rev_ptr[i] : 0;
-  const int32_t e1 = active ? g.rev_ptr[i + 1] : 0;
+  const int32_t e0 = g.rev_ptr[i];  // lanes past the end read PI 0 and store nothing
+  const int32_t e1r = g.rev_ptr[i + 1];
+  const int32_t e1 = active ? e1r : e0;
   const int32_t b = c / a.cdiv;
-  float beta = 1.0f, seed = 0.0f;
-  if (active) {
-    if (a.beta) beta = a.beta[(int64_t)i * a.B + b];
-    seed = seed_of(a, (int32_t)i, c, b, reinterpret_cast<const f2 *>(a.sp)[(int64_t)i * a.B + b],
-                   beta);
-  }
+  const f2 pq = reinterpret_cast<const f2 *>(a.sp)[(int64_t)i * a.B + b];
+  const float beta = a.beta ? a.beta[(int64_t)i * a.B + b] : 1.0f;
+  const float cap = a.cap[i];
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
   if (!active) return;
-  float lam = seed + pulled;
+  float lam = seed_of(a, (int32_t)i, c, b, pq, beta, cap) + pulled;
   if (a.ste) lam *= beta;
   if (a.fixed && a.fixed[i]) lam = 0.0f;  // excluded from the gradients
   out[(int64_t)c * g.n_pi + i] = lam;
@@ -1263,8 +1348,11 @@ template <bool CELLS>
 __global__ __launch_bounds__(kBlock) void k_bwd_multi(const BwdSeg *__restrict__ segs,
                                                       int32_t n_segs) {
   const BwdSeg sg = segs[seg_of(segs, n_segs)];
-  bwd_item<CELLS>(sg.g, sg.a, sg.g0, sg.n, (blockIdx.x - sg.block0) * kBlock + threadIdx.x,
-           threadIdx.x & 63);
+  const uint32_t idx = (blockIdx.x - sg.block0) * kBlock + threadIdx.x;
+  if (!CELLS && sg.a.C >= kSerialColumns)  // segments differ in width: chosen per block
+    bwd_item<CELLS, true>(sg.g, sg.a, sg.g0, sg.n, idx, threadIdx.x & 63);
+  else
+    bwd_item<CELLS, false>(sg.g, sg.a, sg.g0, sg.n, idx, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------- persistent sweeps
@@ -1288,6 +1376,7 @@ __global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel l
   }
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs a,
                                                            const int32_t *__restrict__ level_ptr,
                                                            int32_t depth, float *pi_out) {
@@ -1300,7 +1389,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs 
     const uint32_t items = (uint32_t)n * (uint32_t)a.C;
     // round the trip count up to whole waves
     for (uint32_t base = first - lane; base < items; base += stride)
-      bwd_item<false>(g, a, g0, n, base + lane, lane);
+      bwd_item<false, WIDE>(g, a, g0, n, base + lane, lane);
     grid.sync();
   }
   const uint32_t items = (uint32_t)g.n_pi * (uint32_t)a.C;
@@ -1617,9 +1706,11 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
   if (items <= 0) return hipSuccess;
   if (items >= (1ll << 31)) return hipErrorInvalidValue;
   if (cells)
-    k_bwd_level<true><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
+    k_bwd_level<true, false><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
+  else if (a.C >= kSerialColumns)
+    k_bwd_level<false, true><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
   else
-    k_bwd_level<false><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
+    k_bwd_level<false, false><<<blocks_for(items), kBlock, 0, s>>>(g, a, g0, n);
   return hipGetLastError();
 }
 
@@ -1666,8 +1757,11 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
                                  int32_t depth, int64_t max_items, float *pi_out, hipStream_t s) {
   max_items = std::max<int64_t>(max_items, (int64_t)g.n_pi * a.C);
   if (max_items >= (1ll << 31)) return hipErrorInvalidValue;
+  const void *kernel = a.C >= kSerialColumns
+                           ? reinterpret_cast<const void *>(&k_bwd_persistent<true>)
+                           : reinterpret_cast<const void *>(&k_bwd_persistent<false>);
   unsigned grid = 0;
-  hipError_t e = persistent_grid(reinterpret_cast<const void *>(&k_bwd_persistent), max_items, &grid);
+  hipError_t e = persistent_grid(kernel, max_items, &grid);
   if (e != hipSuccess) return e;
   GraphView gv = g;
   BwdArgs ba = a;
@@ -1675,8 +1769,7 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
   int32_t d = depth;
   float *po = pi_out;
   void *args[] = {&gv, &ba, &lp, &d, &po};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_bwd_persistent), dim3(grid),
-                                    dim3(kBlock), args, 0, s);
+  return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t s) {
