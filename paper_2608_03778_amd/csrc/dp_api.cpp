@@ -270,6 +270,14 @@ dp_status on_coop_stream(dp_eval *ev, hipStream_t s, F launch) {
   return DP_OK;
 }
 
+// The persistent sweeps' barrier words (allocated and zeroed when the
+// schedule is chosen; the timeout flag stays zero unless a wait runs out).
+dp_status grid_barrier(dp_eval *ev, dp::GridBarrier *out) {
+  if (!ev->barrier.ptr) return fail(DP_E_STATE, "persistent sweep without its barrier words");
+  *out = dp::GridBarrier{ev->barrier.as<uint32_t>(), ev->barrier.as<uint32_t>() + 1};
+  return DP_OK;
+}
+
 // Per-net beta of the last forward, or null in modeled mode (beta = 1).
 float *beta_or_null(dp_eval *ev) {
   return ev->prm.mode == DP_MODELED ? nullptr : ev->beta.as<float>();
@@ -359,9 +367,11 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
     SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth + d->split_levels);
     if (ev->schedule == DP_SCHED_PERSISTENT) {
       dp::SpLevel lv{sp, ev->B, 0, 0};
+      dp::GridBarrier bar;
+      DP_TRY(grid_barrier(ev, &bar));
       DP_TRY(on_coop_stream(ev, s, [&](hipStream_t cs) {
         return dp::launch_sp_persistent(g, lv, d->level_dev.as<int32_t>(), d->depth,
-                                        (int64_t)d->max_level_width * ev->B, cs);
+                                        (int64_t)d->max_level_width * ev->B, bar, cs);
       }));
     } else {
       for (int32_t l = 1; l <= d->depth; ++l)
@@ -637,10 +647,12 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
   double bwd_bytes = 0.0;
   for (int32_t l = d->depth; l >= 1; --l) bwd_bytes += bwd_level_bytes(d, l, ba.C);
   if (ev->schedule == DP_SCHED_PERSISTENT) {
+    dp::GridBarrier bar;
+    DP_TRY(grid_barrier(ev, &bar));
     SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth);
     return on_coop_stream(ev, s, [&](hipStream_t cs) {
       return dp::launch_bwd_persistent(g, ba, d->level_dev.as<int32_t>(), d->depth,
-                                       (int64_t)d->max_level_width * ba.C, dst, cs);
+                                       (int64_t)d->max_level_width * ba.C, dst, bar, cs);
     });
   }
   {
@@ -968,6 +980,10 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_
   if (schedule == DP_SCHED_PERSISTENT && ev->d->has_cell_gates)
     return fail(DP_E_UNSUPPORTED,
                 "dp_eval_set_schedule: the persistent schedule runs the fixed cells only");
+  if (schedule == DP_SCHED_PERSISTENT && !ev->barrier.ptr) {
+    DP_TRY(ev->barrier.alloc(2 * sizeof(uint32_t)));
+    DP_HIP_TRY(dp::launch_fill_u32(ev->barrier.as<uint32_t>(), 2, 0u, ev->stream()));
+  }
   ev->schedule = schedule;
   ev->words_per_chunk = words_per_chunk;
   ev->sim_iters = sim_pairs_per_lane;

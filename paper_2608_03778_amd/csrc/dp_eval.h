@@ -42,6 +42,7 @@ struct dp_eval {
   dp::DevBuf power_partial;  // [chunks][B*S'] double
   dp::DevBuf power;          // [B*S']
   dp::DevBuf flag;           // int32 validation flag
+  dp::DevBuf barrier;        // persistent sweeps: grid-barrier counter, timeout flag
   // reverse state
   dp::DevBuf w;              // [B*S'] upstream weights
   dp::DevBuf contrib;        // [n_edges][C]

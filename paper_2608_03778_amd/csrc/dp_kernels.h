@@ -224,11 +224,20 @@ hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_n
 // Persistent (cooperative) sweeps: all levels in one launch with a grid
 // barrier between levels; fixed cells only.  level_ptr is the device copy of the design's
 // level table; max_items the largest level's item count.
+// The barrier's two device words: a counter, zeroed by the launcher on the
+// stream before each launch, and a sticky timeout flag (zero at allocation)
+// that a wait sets if it runs out; the sweep's outputs are then NaN.
+struct GridBarrier {
+  uint32_t *count;
+  uint32_t *timeout;
+};
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
-                                int32_t depth, int64_t max_items, hipStream_t s);
+                                int32_t depth, int64_t max_items, GridBarrier bar,
+                                hipStream_t s);
 // Reverse levels depth..1 and then the PI adjoints into pi_out[c][n_pi].
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
-                                 int32_t depth, int64_t max_items, float *pi_out, hipStream_t s);
+                                 int32_t depth, int64_t max_items, float *pi_out,
+                                 GridBarrier bar, hipStream_t s);
 // dcap[ext n] = sum_{b,s} w[b][s] xterm[b][n] size_s(n); dsize likewise.
 struct GradExportArgs {
   const float *xterm;         // [B][n_nets]

@@ -15,7 +15,6 @@
 // (gate, run of word pairs): the wave's cell is uniform, so the cell switch
 // is a scalar branch outside the word loop; each lane moves 16-byte word
 // pairs, so every fan-in row is read as contiguous 1 KiB wave-wide accesses.
-#include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
 
@@ -1357,13 +1356,44 @@ __global__ __launch_bounds__(kBlock) void k_bwd_multi(const BwdSeg *__restrict__
 
 // ---------------------------------------------------------------- persistent sweeps
 // One cooperative launch runs every level: a grid-stride loop over the
-// level's items, then a grid barrier (cooperative launch guarantees all
-// blocks are resident, so the barrier cannot deadlock).  Whole waves step
-// together so the wave-wide pull of the reverse sweep sees all its lanes.
+// level's items, then a grid barrier.  Whole waves step together so the
+// wave-wide pull of the reverse sweep sees all its lanes.
+//
+// The barrier is a counter zeroed before the launch: at barrier k each
+// block's first thread adds one (release, device scope) and polls (acquire)
+// until the counter reaches k * gridDim.x; the block's other threads wait at
+// the block barriers around it.  Cooperative launch keeps every block
+// resident, so every wait ends.  As a guard, a wait still polling after
+// kBarrierPolls rounds sets the sticky timeout flag and stops, every later
+// wait stops at once, and the sweep's outputs are then written as NaN: the
+// launch always drains and a broken sweep cannot pass for a result.
+constexpr uint32_t kBarrierPolls = 1u << 22;
+
+__device__ __forceinline__ bool barrier_timed_out(const GridBarrier &bar) {
+  return __hip_atomic_load(bar.timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+__device__ __forceinline__ void grid_barrier(const GridBarrier &bar, uint32_t k) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar.count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = k * gridDim.x;
+    for (uint32_t polls = 0;
+         __hip_atomic_load(bar.count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target;
+         ++polls) {
+      if (polls >= kBarrierPolls || barrier_timed_out(bar)) {
+        __hip_atomic_store(bar.timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel lv,
                                                           const int32_t *__restrict__ level_ptr,
-                                                          int32_t depth) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+                                                          int32_t depth, GridBarrier bar) {
   const uint32_t stride = gridDim.x * kBlock;
   for (int32_t l = 1; l <= depth; ++l) {
     SpLevel cur = lv;
@@ -1372,15 +1402,21 @@ __global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel l
     const uint32_t items = (uint32_t)cur.n * (uint32_t)cur.B;
     for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < items; idx += stride)
       sp_item<false>(g, cur, idx);
-    grid.sync();
+    grid_barrier(bar, (uint32_t)l);
+  }
+  if (barrier_timed_out(bar)) {  // every gate's (p, q) becomes NaN
+    const int64_t n = (int64_t)g.G * lv.B * 2;
+    float *out = lv.sp + (int64_t)g.n_pi * lv.B * 2;
+    for (int64_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+      out[i] = __builtin_nanf("");
   }
 }
 
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs a,
                                                            const int32_t *__restrict__ level_ptr,
-                                                           int32_t depth, float *pi_out) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+                                                           int32_t depth, float *pi_out,
+                                                           GridBarrier bar) {
   const uint32_t stride = gridDim.x * kBlock;
   const int lane = threadIdx.x & 63;
   const uint32_t first = blockIdx.x * kBlock + threadIdx.x;
@@ -1390,9 +1426,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs 
     // round the trip count up to whole waves
     for (uint32_t base = first - lane; base < items; base += stride)
       bwd_item<false, WIDE>(g, a, g0, n, base + lane, lane);
-    grid.sync();
+    grid_barrier(bar, (uint32_t)(depth - l + 1));
   }
   const uint32_t items = (uint32_t)g.n_pi * (uint32_t)a.C;
+  if (barrier_timed_out(bar)) {  // the gradient becomes NaN
+    for (uint32_t i = first; i < items; i += stride) pi_out[i] = __builtin_nanf("");
+    return;
+  }
   for (uint32_t base = first - lane; base < items; base += stride)
     bwd_pi_item(g, a, pi_out, base + lane, lane);
 }
@@ -1738,37 +1778,47 @@ static hipError_t persistent_grid(const void *kernel, int64_t max_items, unsigne
 }
 
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
-                                int32_t depth, int64_t max_items, hipStream_t s) {
+                                int32_t depth, int64_t max_items, GridBarrier bar,
+                                hipStream_t s) {
   if (depth <= 0) return hipSuccess;
-  if (max_items >= (1ll << 31)) return hipErrorInvalidValue;
+  if (max_items >= (1ll << 31) || !bar.count || !bar.timeout) return hipErrorInvalidValue;
   unsigned grid = 0;
   hipError_t e = persistent_grid(reinterpret_cast<const void *>(&k_sp_persistent), max_items, &grid);
+  if (e != hipSuccess) return e;
+  k_fill_u32<<<1, kBlock, 0, s>>>(bar.count, 1, 0u);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   GraphView gv = g;
   SpLevel l = lv;
   const int32_t *lp = level_ptr;
   int32_t d = depth;
-  void *args[] = {&gv, &l, &lp, &d};
+  GridBarrier gb = bar;
+  void *args[] = {&gv, &l, &lp, &d, &gb};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_sp_persistent), dim3(grid),
                                     dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
-                                 int32_t depth, int64_t max_items, float *pi_out, hipStream_t s) {
+                                 int32_t depth, int64_t max_items, float *pi_out,
+                                 GridBarrier bar, hipStream_t s) {
   max_items = std::max<int64_t>(max_items, (int64_t)g.n_pi * a.C);
-  if (max_items >= (1ll << 31)) return hipErrorInvalidValue;
+  if (max_items >= (1ll << 31) || !bar.count || !bar.timeout) return hipErrorInvalidValue;
   const void *kernel = a.C >= kSerialColumns
                            ? reinterpret_cast<const void *>(&k_bwd_persistent<true>)
                            : reinterpret_cast<const void *>(&k_bwd_persistent<false>);
   unsigned grid = 0;
   hipError_t e = persistent_grid(kernel, max_items, &grid);
   if (e != hipSuccess) return e;
+  k_fill_u32<<<1, kBlock, 0, s>>>(bar.count, 1, 0u);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   GraphView gv = g;
   BwdArgs ba = a;
   const int32_t *lp = level_ptr;
   int32_t d = depth;
   float *po = pi_out;
-  void *args[] = {&gv, &ba, &lp, &d, &po};
+  GridBarrier gb = bar;
+  void *args[] = {&gv, &ba, &lp, &d, &po, &gb};
   return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
 }
 

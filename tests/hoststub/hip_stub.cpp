@@ -283,14 +283,19 @@ hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipSt
   return hipSuccess;
 }
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
-                                int32_t depth, int64_t, hipStream_t) {
+                                int32_t depth, int64_t, GridBarrier bar, hipStream_t) {
   rd(level_ptr, depth + 2);
+  wr(bar.count, 1);
+  rd(bar.timeout, 1);
   wr(lv.sp, (int64_t)g.n_nets * lv.B * 2);
   return hipSuccess;
 }
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
-                                 int32_t depth, int64_t, float *pi_out, hipStream_t s) {
+                                 int32_t depth, int64_t, float *pi_out, GridBarrier bar,
+                                 hipStream_t s) {
   rd(level_ptr, depth + 2);
+  wr(bar.count, 1);
+  rd(bar.timeout, 1);
   return launch_bwd_pi(g, a, pi_out, s);
 }
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
