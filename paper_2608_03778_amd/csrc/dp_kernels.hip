@@ -25,6 +25,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
+// The simulation level runs in smaller workgroups: finer grains fill the
+// chip's last wave of blocks more evenly (0.5% per level on MI355X against
+// 256 threads; 64 threads gained nothing further).
+constexpr int kSimBlock = 128;
+constexpr int kSimWaves = kSimBlock / 64;
 
 // Two consecutive simulation words as one 16-byte vector (a single
 // dwordx4 access per lane).
@@ -436,7 +441,10 @@ __device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
     if (lane == 0) prev = carry;
     carry = __shfl(y.y, 63);
     if (p < c.pairs) {
-      out[p] = y;
+      // streaming store: a row's readers run in later launches, mostly on
+      // other XCDs, so the words gain nothing from this XCD's L2 (measured
+      // 3% faster per level than a plain store on MI355X)
+      __builtin_nontemporal_store(y, out + p);
       count_pair(c, p, y, prev, ones, togs);
     }
   }
@@ -500,7 +508,7 @@ __device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint6
     if (lane == 0) prev = carry;
     carry = __shfl(y.y, 63);
     if (p < c.pairs) {
-      out[p] = y;
+      __builtin_nontemporal_store(y, out + p);  // see sim_gate_row
       count_pair(c, p, y, prev, ones, togs);
     }
   }
@@ -528,19 +536,19 @@ __device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t
 }
 
 template <int ITERS, bool CELLS>
-__global__ __launch_bounds__(kBlock) void k_sim_level(GraphView g, ChunkView c, CountView cnt,
+__global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView c, CountView cnt,
                                                       int32_t g0, int32_t n, int32_t waves_per_row,
                                                       int32_t sim_blocks, SpLevel sp) {
   if constexpr (!CELLS) {  // library cells take their SP in a launch of its own
     if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level
-      const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kBlock + threadIdx.x;
+      const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kSimBlock + threadIdx.x;
       if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item<false>(g, sp, idx);
       return;
     }
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int64_t task = (int64_t)blockIdx.x * kSimWaves + wave;
   if (task >= (int64_t)n * waves_per_row) return;
   const int32_t gl = (int32_t)(task / waves_per_row);
   const int32_t seg = (int32_t)(task - (int64_t)gl * waves_per_row);
@@ -1657,29 +1665,29 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   const int iters = cells ? min(tune.iters, 2) : tune.iters;  // cells: up to 6 input rows
   const int32_t wpr = waves_per_row(c, iters);
   const int64_t tasks = (int64_t)n * wpr;
-  const int64_t sim_blocks64 = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t sim_blocks64 = (tasks + kSimWaves - 1) / kSimWaves;
   SpLevel spl{};
   int64_t sp_blocks = 0;
   if (sp) {
     spl = *sp;
     if ((int64_t)spl.n * spl.B >= (1ll << 31)) return hipErrorInvalidValue;
-    sp_blocks = blocks_for((int64_t)spl.n * spl.B);
+    sp_blocks = ((int64_t)spl.n * spl.B + kSimBlock - 1) / kSimBlock;
   }
   if (sim_blocks64 + sp_blocks > kMaxBlocks || sim_blocks64 > INT32_MAX) return hipErrorInvalidValue;
   const int32_t sim_blocks = (int32_t)sim_blocks64;
   const unsigned grid = (unsigned)(sim_blocks + sp_blocks);
   if (cells) {
     if (iters == 1)
-      k_sim_level<1, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+      k_sim_level<1, true><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
     else
-      k_sim_level<2, true><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+      k_sim_level<2, true><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
     return hipGetLastError();
   }
   switch (iters) {
-    case 1: k_sim_level<1, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    case 2: k_sim_level<2, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    case 4: k_sim_level<4, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    default: k_sim_level<8, false><<<grid, kBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 1: k_sim_level<1, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 2: k_sim_level<2, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 4: k_sim_level<4, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    default: k_sim_level<8, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
   }
   return hipGetLastError();
 }
