@@ -1156,14 +1156,15 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
 // innermost; item counts stay below 2^31.
 // One (gate, column) item of a reverse level; every lane of the wave calls
 // it (pull_sum needs the whole wave), lanes past the end pass active = false.
-// WIDE: the launch's column count is at least kSerialColumns (pulls are
-// lane-serial); a choice per launch, so each form keeps its own registers.
+// WIDE (fixed cells): the launch's column count is at least kSerialColumns
+// (pulls are lane-serial); a choice per launch, so each form keeps its own
+// registers.  Library cells decide the pull per launch at run time.
 template <bool CELLS, bool WIDE>
 __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, int32_t g0,
                                          int32_t n, uint32_t idx, int lane) {
   const bool active = idx < (uint32_t)n * (uint32_t)a.C;
   // lanes past the end read row g0 (a level has at least one gate) and
-  // store nothing, so every load below is unconditional
+  // store nothing, so no load needs a guard for them
   const uint32_t gl = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - gl * (uint32_t)a.C) : 0;
   const int32_t gi = g0 + (int32_t)gl;
@@ -1181,7 +1182,8 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const float beta = a.beta ? a.beta[(int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
-    const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, WIDE);
+    const float pulled =
+        pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
     if (!active) return;
     float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
     if (a.ste) lam *= beta;
