@@ -94,7 +94,11 @@ enum {
                              Opt-in: the autotuner does not pick it.  Fixed
                              cells only: dp_eval_set_schedule returns
                              DP_E_UNSUPPORTED for a design with library-cell
-                             gates */
+                             gates.  The barrier's wait is bounded: should it
+                             ever run out (it cannot while the launch's blocks
+                             stay resident), that sweep's outputs are NaN, and
+                             so are those of every later persistent sweep of
+                             the eval */
 };
 
 typedef struct dp_ctx dp_ctx;
