@@ -20,7 +20,7 @@ def ctx():
     return api.Context(0)
 
 
-def _full_check(ctx, name, n_sim, seed, fd_samples=0):
+def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=()):
     spec = synth.SPECS[name]
     nl = synth.random_dag(spec, seed=1)
     p = synth.pi_probs(nl.n_pi, seed=2)
@@ -48,6 +48,15 @@ def _full_check(ctx, name, n_sim, seed, fd_samples=0):
     assert_power_close(res["power"], f["power"], f"{name} power")
     assert_grad_close(g["dpi"][0], adj["dpi"], f"{name} dP/dp")
     assert_grad_close(g["dcap"], adj["dcap"], f"{name} dP/dC")
+    for ppl in tilings:  # other launch tilings: the same results bit for bit
+        say(f"{name}: per-level launches, {ppl} word pairs per lane")
+        ev.set_schedule(L.DP_SCHED_LEVEL, 0, ppl)
+        r2 = ev.forward(("ones", "toggles", "sp", "power"))
+        g2 = ev.backward(want=("dpi", "dcap"))
+        for k in r2:
+            np.testing.assert_array_equal(r2[k], res[k], err_msg=f"{k} at {ppl} pairs per lane")
+        for k in g2:
+            np.testing.assert_array_equal(g2[k], g[k], err_msg=f"{k} at {ppl} pairs per lane")
     if fd_samples:
         # FP64 central differences of the oracle's frozen-beta power, h = 1e-6
         rng = np.random.default_rng(7)
@@ -77,8 +86,10 @@ def test_dag117k_hybrid_fwd_bwd_with_fd():
 
 def test_dag1m_bench_configuration():
     """The bench workload: 1M gates, 8,192 PIs, depth 100, 65,536 vectors,
-    default schedule; every net's counts bit-exact."""
-    _full_check(api.Context(0), "dag1m", 65536, seed=1)
+    default schedule; every net's counts bit-exact; then the tilings the
+    benchmark chooses among (per-level launches of whole rows on one
+    stream, 2, 4 or 8 word pairs per lane) give the same results."""
+    _full_check(api.Context(0), "dag1m", 65536, seed=1, tilings=(2, 4, 8))
 
 
 def test_dag117k_sizing_sweep_spot_parity():
