@@ -395,3 +395,30 @@ def test_persistent_schedule_is_bitwise_equal(ctx, mode, B, ste):
     f, adj = oracle_column(o, p[0], cap, mode="hybrid" if mode == L.DP_HYBRID else "modeled",
                            n_words=40, seed=6, ste=ste)
     assert_grad_close(res[L.DP_SCHED_PERSISTENT]["dpi"][0], adj["dpi"], "persistent dP/dp")
+
+
+def test_persistent_schedule_with_a_large_grid(ctx):
+    """The grid barrier with hundreds of blocks (10,000 gates, 512 columns:
+    about 170,000 items per level, one block per 256 of them up to what
+    stays resident): modeled SP and gradients equal the per-level launches'
+    bit for bit, and a second persistent run repeats them."""
+    say("persistent schedule, large grid")
+    nl = synth.random_dag(synth.SPECS["dag10k"], 15)
+    B = 512
+    p, cap, _ = _inputs(nl, 15, B=B)
+    d = api.Design(ctx, nl)
+    res = {}
+    for sched in (L.DP_SCHED_LEVEL, L.DP_SCHED_PERSISTENT, L.DP_SCHED_PERSISTENT):
+        ev = api.Eval(d, B, mode=L.DP_MODELED)
+        ev.set_pi_prob(p)
+        ev.set_caps(cap)
+        ev.set_schedule(sched)
+        out = ev.forward(("sp", "power"))
+        out.update(ev.backward(want=("dpi", "dcap")))
+        assert np.isfinite(out["power"]).all() and np.isfinite(out["dpi"]).all()
+        if res:
+            for k in res:
+                np.testing.assert_array_equal(out[k], res[k], err_msg=f"{k} schedule {sched}")
+        else:
+            res = out
+        ev.close()
