@@ -329,9 +329,11 @@ dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
 
 double sim_level_bytes(const dp_design *d, int32_t l, int64_t words, int32_t B, bool fused) {
   const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
-  const int64_t pins = d->lvl_pins[l];
-  double b = (double)(8 * pins + 8 * n) * (double)words  // fan-in words + output word
-             + (double)(4 * pins + n) + 8.0 * n;         // indices, cell, counters
+  const int64_t pins = d->lvl_pins[l], read = d->lvl_read[l];
+  // fan-in words, and output words of the nets that have readers (a net
+  // without readers needs only its counts, so its words are not stored)
+  double b = (double)(8 * pins + 8 * read) * (double)words
+             + (double)(4 * pins + n) + 8.0 * n + 8.0 * n;  // indices, cell, fan-out range, counters
   if (fused) b += (double)B * (8 * pins + 8 * n);         // SP pair gathers and writes
   return b;
 }

@@ -200,10 +200,12 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   for (int64_t e = 0; e < n_edges; ++e) slot[rev_edge[e]] = (int32_t)e;
   d->lvl_pins.assign(depth + 1, 0);
   d->lvl_fanout.assign(depth + 1, 0);
+  d->lvl_read.assign(depth + 1, 0);
   for (int32_t l = 1; l <= depth; ++l)
     for (int32_t gi = d->level_ptr[l]; gi < d->level_ptr[l + 1]; ++gi) {
       d->lvl_pins[l] += d->h_arity_prefix[gi + 1] - d->h_arity_prefix[gi];
       d->lvl_fanout[l] += rev_ptr[n_pi + gi + 1] - rev_ptr[n_pi + gi];
+      d->lvl_read[l] += rev_ptr[n_pi + gi + 1] > rev_ptr[n_pi + gi];
     }
   d->lvl_fanout[0] = rev_ptr[n_pi] - rev_ptr[0];
   d->lvl_fixed.assign(depth + 1, 0);

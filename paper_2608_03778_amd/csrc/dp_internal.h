@@ -91,6 +91,7 @@ struct dp_design {
   int32_t max_level_width = 0;
   std::vector<int64_t> lvl_pins;      // [depth + 1] fan-in pins of the level's gates
   std::vector<int64_t> lvl_fanout;    // [depth + 1] fan-out edges of the level's nets (0 = PIs)
+  std::vector<int64_t> lvl_read;      // [depth + 1] the level's gates whose output has readers
   // [depth + 1] fixed-cell gates of each level; its library-cell gates follow
   // them and run in kernels of their own
   std::vector<int32_t> lvl_fixed;

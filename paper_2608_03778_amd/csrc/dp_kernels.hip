@@ -412,7 +412,7 @@ template <int OP, int ITERS>
 __device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
                                              const w2 *__restrict__ r1,
                                              const w2 *__restrict__ r2,
-                                             w2 *__restrict__ out, int32_t p_begin,
+                                             w2 *__restrict__ out, bool keep, int32_t p_begin,
                                              const ChunkView &c, int lane, uint32_t &ones,
                                              uint32_t &togs) {
   constexpr int K = kArity<OP>;
@@ -443,8 +443,9 @@ __device__ __forceinline__ void sim_gate_row(const w2 *__restrict__ r0,
     if (p < c.pairs) {
       // streaming store: a row's readers run in later launches, mostly on
       // other XCDs, so the words gain nothing from this XCD's L2 (measured
-      // 3% faster per level than a plain store on MI355X)
-      __builtin_nontemporal_store(y, out + p);
+      // 3% faster per level than a plain store on MI355X); a row nobody
+      // reads is not stored at all
+      if (keep) __builtin_nontemporal_store(y, out + p);
       count_pair(c, p, y, prev, ones, togs);
     }
   }
@@ -472,7 +473,7 @@ __device__ __forceinline__ uint64_t tt_eval(const uint64_t *x, uint64_t tt, int 
 template <int N, int ITERS>
 __device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint64_t tt,
                                            const w2 *__restrict__ W, int64_t pp,
-                                           w2 *__restrict__ out, int32_t p_begin,
+                                           w2 *__restrict__ out, bool keep, int32_t p_begin,
                                            const ChunkView &c, int lane, uint32_t &ones,
                                            uint32_t &togs) {
   const w2 *r[N];
@@ -508,7 +509,7 @@ __device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint6
     if (lane == 0) prev = carry;
     carry = __shfl(y.y, 63);
     if (p < c.pairs) {
-      __builtin_nontemporal_store(y, out + p);  // see sim_gate_row
+      if (keep) __builtin_nontemporal_store(y, out + p);  // see sim_gate_row
       count_pair(c, p, y, prev, ones, togs);
     }
   }
@@ -517,7 +518,7 @@ __device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint6
 template <int ITERS>
 __device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t gi,
                                              const w2 *__restrict__ W, int64_t pp,
-                                             w2 *__restrict__ out, int32_t p_begin,
+                                             w2 *__restrict__ out, bool keep, int32_t p_begin,
                                              const ChunkView &c, int lane, uint32_t &ones,
                                              uint32_t &togs) {
   const int cl = op - kCellBase;
@@ -526,12 +527,12 @@ __device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t
   const uint64_t tt = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32) |
                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)t);
   switch (nin) {
-    case 1: sim_tt_row<1, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
-    case 2: sim_tt_row<2, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
-    case 3: sim_tt_row<3, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
-    case 4: sim_tt_row<4, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
-    case 5: sim_tt_row<5, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
-    default: sim_tt_row<6, ITERS>(g, gi, tt, W, pp, out, p_begin, c, lane, ones, togs); break;
+    case 1: sim_tt_row<1, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 2: sim_tt_row<2, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 3: sim_tt_row<3, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 4: sim_tt_row<4, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 5: sim_tt_row<5, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    default: sim_tt_row<6, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
   }
 }
 
@@ -560,21 +561,25 @@ __global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView 
   const w2 *r1 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[g.G + gi]) * pp;
   const w2 *r2 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[2 * g.G + gi]) * pp;
   w2 *out = reinterpret_cast<w2 *>(c.W) + (int64_t)(g.n_pi + gi) * pp;
+  // a net with no readers needs its counts only: its words are not stored
+  const int32_t on = g.n_pi + gi;
+  const bool keep = __builtin_amdgcn_readfirstlane(g.rev_ptr[on + 1]) >
+                    __builtin_amdgcn_readfirstlane(g.rev_ptr[on]);
   const int32_t p_begin = seg * 64 * ITERS;
   uint32_t ones = 0, togs = 0;
   if constexpr (CELLS) {
-    sim_cell_row<ITERS>(g, op, gi, W, pp, out, p_begin, c, lane, ones, togs);
+    sim_cell_row<ITERS>(g, op, gi, W, pp, out, keep, p_begin, c, lane, ones, togs);
   } else {
   switch (op) {
-    case INV: sim_gate_row<INV, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case BUF: sim_gate_row<BUF, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case AND2: sim_gate_row<AND2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case OR2: sim_gate_row<OR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case NAND2: sim_gate_row<NAND2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case NOR2: sim_gate_row<NOR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case XOR2: sim_gate_row<XOR2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    case AOI21: sim_gate_row<AOI21, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
-    default: sim_gate_row<MUX2, ITERS>(r0, r1, r2, out, p_begin, c, lane, ones, togs); break;
+    case INV: sim_gate_row<INV, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case BUF: sim_gate_row<BUF, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case AND2: sim_gate_row<AND2, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case OR2: sim_gate_row<OR2, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case NAND2: sim_gate_row<NAND2, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case NOR2: sim_gate_row<NOR2, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case XOR2: sim_gate_row<XOR2, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    case AOI21: sim_gate_row<AOI21, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
+    default: sim_gate_row<MUX2, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
   }
   }
   ones = wave_sum(ones);
