@@ -7,7 +7,8 @@
 // which sums over nets (Eq. 1), is unchanged.
 //
 // Steps: validate -> ASAP levels with Kahn's algorithm (cycle detection) ->
-// counting sort of gates by (level, cell, caller id) -> renumber nets so
+// counting sort of gates by (level, kind, heavy fan-out first, cell, caller
+// id) -> renumber nets so
 // level l's outputs are one contiguous range and a gate's output id is
 // implicit -> per-pin fan-in arrays (structure of arrays) -> fan-out lists
 // (reverse CSR, edges in ascending order, which fixes the summation order
@@ -128,17 +129,46 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   int32_t depth = 0;
   for (int32_t g = 0; g < G; ++g) depth = std::max(depth, level[n_pi + g]);
 
-  // --- counting sort by (level, cell); stable, so caller id breaks ties
-  constexpr int32_t kOps = 256;
-  const int32_t n_keys = (depth + 1) * kOps;
+  // --- counting sort by (level, kind, heavy first, cell); stable, so caller
+  // id breaks ties.  Within a level the fixed cells precede the library
+  // cells (each kind runs in kernels of its own).  Within each kind the
+  // gates whose output has more than kHeavyFanout readers are then spread
+  // one per 64 positions from the start of the range: with many columns the
+  // reverse sweep sums their long fan-out ranges in several dependent load
+  // rounds, which then overlap the rest of the level instead of trailing
+  // it, and with few columns no wave holds more than one of them, so each
+  // wave's long ranges still go out in one round.
+  constexpr int32_t kHeavyFanout = 32;
+  constexpr int32_t kSlots = 1024;  // per level: [kind 512][heavy 256][cell < 256]
+  auto key_of = [&](int32_t g) {
+    const int32_t op = internal_op(nl->op[g]);
+    const bool cell = op >= dp::kCellBase;
+    const bool heavy = cons_ptr[g + 1] - cons_ptr[g] > kHeavyFanout;
+    return level[n_pi + g] * kSlots + (cell ? 512 : 0) + (heavy ? 0 : 256) +
+           (cell ? op - dp::kCellBase : op);
+  };
+  const int32_t n_keys = (depth + 1) * kSlots;
   std::vector<int32_t> key_ptr(n_keys + 1, 0);
-  for (int32_t g = 0; g < G; ++g) ++key_ptr[level[n_pi + g] * kOps + internal_op(nl->op[g]) + 1];
+  for (int32_t g = 0; g < G; ++g) ++key_ptr[key_of(g) + 1];
   for (int32_t k = 0; k < n_keys; ++k) key_ptr[k + 1] += key_ptr[k];
   std::vector<int32_t> gate_of(G);  // internal -> caller gate
   {
     std::vector<int32_t> fill(key_ptr.begin(), key_ptr.end() - 1);
-    for (int32_t g = 0; g < G; ++g)
-      gate_of[fill[level[n_pi + g] * kOps + internal_op(nl->op[g])]++] = g;
+    for (int32_t g = 0; g < G; ++g) gate_of[fill[key_of(g)]++] = g;
+    // spread each (level, kind)'s heavy gates (sorted first) one per 64
+    std::vector<int32_t> part;
+    for (int32_t l = 1; l <= depth; ++l)
+      for (int32_t kind = 0; kind < 2; ++kind) {
+        const int32_t k0 = l * kSlots + kind * 512;
+        const int32_t a = key_ptr[k0], h = key_ptr[k0 + 256] - a, b = key_ptr[k0 + 512];
+        if (h == 0 || h == b - a) continue;
+        part.assign(gate_of.begin() + a, gate_of.begin() + b);
+        int32_t hi = 0, ni = h;  // next heavy, next other
+        for (int32_t i = 0; i < b - a; ++i) {
+          const bool take_heavy = hi < h && (i % 64 == 0 || ni == b - a);
+          gate_of[a + i] = take_heavy ? part[hi++] : part[ni++];
+        }
+      }
   }
   auto *d = new dp_design();
   d->ctx = ctx;
@@ -149,7 +179,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   d->n_edges = n_edges;
   d->level_ptr.assign(depth + 2, 0);
   for (int32_t l = 1; l <= depth + 1; ++l)
-    d->level_ptr[l] = (l <= depth) ? key_ptr[l * kOps] : G;
+    d->level_ptr[l] = (l <= depth) ? key_ptr[l * kSlots] : G;
   d->level_ptr[0] = 0;
   for (int32_t l = 1; l <= depth; ++l)
     d->max_level_width = std::max(d->max_level_width, d->level_ptr[l + 1] - d->level_ptr[l]);
