@@ -1084,27 +1084,25 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
   // the wave's heavy nets take consecutive strand positions (lane order);
   // when they fit in 64, their strands load in the same round as the light
   // ranges
+  // (A wave holds few heavy nets, so their offsets are a short uniform loop
+  // over the heavy lanes; lane values are read with readlane, a register
+  // read, rather than cross-lane shuffles through LDS.)
   bool batched = false;
-  int32_t cnt = 0, off = 0, my_h = -1, my_j = 0;
+  int32_t cnt = 0, my_h = -1, my_j = 0;
   if (heavy) {
     cnt = ((heavy >> lane) & 1) ? (e1 - e0 + kStrand - 1) / kStrand : 0;
-    int32_t inc = cnt;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int32_t t = __shfl_up(inc, (unsigned)d);
-      if (lane >= d) inc += t;
-    }
-    off = inc - cnt;
-    batched = __builtin_amdgcn_readfirstlane(__shfl(inc, 63)) <= 64;
-    if (batched)
-      for (uint64_t hh = heavy; hh; hh &= hh - 1) {
-        const int h = __builtin_ctzll(hh);
-        const int32_t ho = __builtin_amdgcn_readfirstlane(__shfl(off, h));
-        const int32_t hc = __builtin_amdgcn_readfirstlane(__shfl(cnt, h));
-        if (lane >= ho && lane < ho + hc) {
-          my_h = h;
-          my_j = lane - ho;
-        }
+    int32_t run = 0;
+    for (uint64_t hh = heavy; hh; hh &= hh - 1) {
+      const int h = __builtin_ctzll(hh);
+      const int32_t hc = __builtin_amdgcn_readlane(cnt, h);
+      if (lane >= run && lane < run + hc) {
+        my_h = h;
+        my_j = lane - run;
       }
+      run += hc;
+    }
+    batched = run <= 64;
+    if (!batched) my_h = -1;
   }
   int32_t hbeg = 0, hend = 0, hcol = 0;
   if (batched) {
@@ -1120,17 +1118,17 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
   if (!heavy) return acc;
   if (batched) {
     const float v = my_h >= 0 ? strand_fold(hv, hend - hbeg) : 0.0f;
+    const int32_t vbits = __float_as_int(v);
     // each heavy net folds its strand sums in strand order
+    int32_t run = 0;
     for (uint64_t hh = heavy; hh; hh &= hh - 1) {
       const int h = __builtin_ctzll(hh);
-      const int32_t ho = __builtin_amdgcn_readfirstlane(__shfl(off, h));
-      const int32_t hc = __builtin_amdgcn_readfirstlane(__shfl(cnt, h));
-      float total = 0.0f;
-      for (int32_t t = 0; t < hc; ++t) {
-        const float u = __shfl(v, ho + t);
-        total = t == 0 ? u : total + u;
-      }
+      const int32_t hc = __builtin_amdgcn_readlane(cnt, h);
+      float total = __int_as_float(__builtin_amdgcn_readlane(vbits, run));
+      for (int32_t t = 1; t < hc; ++t)
+        total = total + __int_as_float(__builtin_amdgcn_readlane(vbits, run + t));
       if (lane == h) acc = total;
+      run += hc;
     }
     return acc;
   }
