@@ -274,3 +274,33 @@ def test_library_errors(ctx):
     ev.set_caps(np.ones(4, np.float32))
     sp = ev.forward(("sp",))["sp"][0]
     assert abs(sp[3] - 0.3 * 0.4) < 1e-6
+
+
+def test_mixed_dag_many_columns_equal_single_columns(ctx):
+    """40 columns (lane-serial reverse pulls for both cell kinds): each
+    column's SP, power and gradients equal a one-column eval's bit for bit,
+    and column 0 matches the oracle."""
+    say("library dag, 40 columns")
+    nl = synth.random_dag(_mixed_spec(3000, 64, 20), 21)
+    B = 40
+    p = synth.pi_probs(nl.n_pi, 22, batch=B)
+    cap = synth.net_caps(nl.n_nets, 23)
+    d = api.Design(ctx, nl)
+    ev = api.Eval(d, B, mode=L.DP_MODELED)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(("sp", "power"))
+    g = ev.backward(want=("dpi",))
+    one = api.Eval(d, 1, mode=L.DP_MODELED)
+    one.set_caps(cap)
+    for b in (0, 17, B - 1):
+        one.set_pi_prob(p[b:b + 1])
+        r1 = one.forward(("sp", "power"))
+        g1 = one.backward(want=("dpi",))
+        np.testing.assert_array_equal(r1["sp"][0], res["sp"][b], err_msg=f"sp[{b}]")
+        np.testing.assert_array_equal(r1["power"][0], res["power"][b], err_msg=f"power[{b}]")
+        np.testing.assert_array_equal(g1["dpi"][0], g["dpi"][b], err_msg=f"dP/dp[{b}]")
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode="modeled")
+    assert_power_close(res["power"][0], f["power"], "power[0]")
+    assert_grad_close(g["dpi"][0], adj["dpi"], "dP/dp[0]")
