@@ -1356,7 +1356,8 @@ void MergedTables::build(const Lane *lanes, int32_t n) {
         int32_t g0, cnt;
         level_part(d, l, k, &g0, &cnt);
         if (cnt == 0) continue;
-        const uint32_t blocks = (uint32_t)(((int64_t)cnt * ev->B + 255) / 256);
+        const uint32_t blocks =
+            (uint32_t)(((int64_t)cnt * ev->B + kMergedBlock - 1) / kMergedBlock);
         fs.push_back({view(d), SpLevel{ev->sp.as<float>(), ev->B, g0, cnt}, f_blk[i]});
         f_blk[i] += blocks;
         if (lanes[j].backward) {

@@ -193,6 +193,10 @@ struct BwdSeg {
   int32_t g0, n;
   uint32_t block0;
 };
+// Threads per workgroup of the merged launches; a segment's block0 and the
+// launch's block count are in these units.  One wave: the launches are
+// latency-bound gathers, and one-wave groups spread them over more CUs.
+constexpr int kMergedBlock = 64;
 // segs: device array of n_segs; blocks: total blocks of the launch.
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
                            hipStream_t s);

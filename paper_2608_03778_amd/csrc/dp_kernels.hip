@@ -1355,18 +1355,18 @@ __device__ __forceinline__ int32_t seg_of(const Seg *__restrict__ segs, int32_t 
 }
 
 template <bool CELLS>
-__global__ __launch_bounds__(kBlock) void k_sp_multi(const SpSeg *__restrict__ segs,
-                                                     int32_t n_segs) {
+__global__ __launch_bounds__(kMergedBlock) void k_sp_multi(const SpSeg *__restrict__ segs,
+                                                           int32_t n_segs) {
   const SpSeg sg = segs[seg_of(segs, n_segs)];
-  const uint32_t idx = (blockIdx.x - sg.block0) * kBlock + threadIdx.x;
+  const uint32_t idx = (blockIdx.x - sg.block0) * kMergedBlock + threadIdx.x;
   if (idx < (uint32_t)sg.lv.n * (uint32_t)sg.lv.B) sp_item<CELLS>(sg.g, sg.lv, idx);
 }
 
 template <bool CELLS>
-__global__ __launch_bounds__(kBlock) void k_bwd_multi(const BwdSeg *__restrict__ segs,
-                                                      int32_t n_segs) {
+__global__ __launch_bounds__(kMergedBlock) void k_bwd_multi(const BwdSeg *__restrict__ segs,
+                                                            int32_t n_segs) {
   const BwdSeg sg = segs[seg_of(segs, n_segs)];
-  const uint32_t idx = (blockIdx.x - sg.block0) * kBlock + threadIdx.x;
+  const uint32_t idx = (blockIdx.x - sg.block0) * kMergedBlock + threadIdx.x;
   if (!CELLS && sg.a.C >= kSerialColumns)  // segments differ in width: chosen per block
     bwd_item<CELLS, true>(sg.g, sg.a, sg.g0, sg.n, idx, threadIdx.x & 63);
   else
@@ -1603,9 +1603,9 @@ hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, b
                            hipStream_t s) {
   if (n_segs <= 0 || blocks == 0) return hipSuccess;
   if (cells)
-    k_sp_multi<true><<<blocks, kBlock, 0, s>>>(segs, n_segs);
+    k_sp_multi<true><<<blocks, kMergedBlock, 0, s>>>(segs, n_segs);
   else
-    k_sp_multi<false><<<blocks, kBlock, 0, s>>>(segs, n_segs);
+    k_sp_multi<false><<<blocks, kMergedBlock, 0, s>>>(segs, n_segs);
   return hipGetLastError();
 }
 
@@ -1613,9 +1613,9 @@ hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks,
                             hipStream_t s) {
   if (n_segs <= 0 || blocks == 0) return hipSuccess;
   if (cells)
-    k_bwd_multi<true><<<blocks, kBlock, 0, s>>>(segs, n_segs);
+    k_bwd_multi<true><<<blocks, kMergedBlock, 0, s>>>(segs, n_segs);
   else
-    k_bwd_multi<false><<<blocks, kBlock, 0, s>>>(segs, n_segs);
+    k_bwd_multi<false><<<blocks, kMergedBlock, 0, s>>>(segs, n_segs);
   return hipGetLastError();
 }
 

@@ -302,7 +302,7 @@ hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, b
                            hipStream_t st) {
   for (int32_t k = 0; k < n_segs; ++k) {
     const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
-    if (b1 < b0 || (int64_t)(b1 - b0) * 256 < (int64_t)segs[k].lv.n * segs[k].lv.B) {
+    if (b1 < b0 || (int64_t)(b1 - b0) * kMergedBlock < (int64_t)segs[k].lv.n * segs[k].lv.B) {
       std::fprintf(stderr, "STUB: sp segment %d too small\n", k);
       std::abort();
     }
@@ -314,7 +314,7 @@ hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks,
                             hipStream_t st) {
   for (int32_t k = 0; k < n_segs; ++k) {
     const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
-    if (b1 < b0 || (int64_t)(b1 - b0) * 256 < (int64_t)segs[k].n * segs[k].a.C) {
+    if (b1 < b0 || (int64_t)(b1 - b0) * kMergedBlock < (int64_t)segs[k].n * segs[k].a.C) {
       std::fprintf(stderr, "STUB: bwd segment %d too small\n", k);
       std::abort();
     }
