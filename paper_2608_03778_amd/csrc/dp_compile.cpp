@@ -7,8 +7,8 @@
 // which sums over nets (Eq. 1), is unchanged.
 //
 // Steps: validate -> ASAP levels with Kahn's algorithm (cycle detection) ->
-// counting sort of gates by (level, kind, heavy fan-out first, cell, caller
-// id) -> renumber nets so
+// counting sort of gates by (level, kind, heavy fan-out first, cell), then
+// by first fan-in net -> renumber nets so
 // level l's outputs are one contiguous range and a gate's output id is
 // implicit -> per-pin fan-in arrays (structure of arrays) -> fan-out lists
 // (reverse CSR, edges in ascending order, which fixes the summation order
@@ -155,9 +155,22 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   {
     std::vector<int32_t> fill(key_ptr.begin(), key_ptr.end() - 1);
     for (int32_t g = 0; g < G; ++g) gate_of[fill[key_of(g)]++] = g;
-    // spread each (level, kind)'s heavy gates (sorted first) one per 64
-    std::vector<int32_t> part;
-    for (int32_t l = 1; l <= depth; ++l)
+    // Level by level: within each (kind, heavy, cell) bucket, order gates by
+    // the internal id of their first fan-in net (stable), so consecutive
+    // waves of the simulation read that pin's rows in address order; then
+    // spread each (level, kind)'s heavy gates (sorted first) one per 64.
+    std::vector<int32_t> pos(G, 0), part;
+    auto src_of = [&](int32_t g) {
+      const int32_t n = nl->fanin[nl->fanin_ptr[g]];
+      return n < n_pi ? n : n_pi + pos[n - n_pi];
+    };
+    for (int32_t l = 1; l <= depth; ++l) {
+      for (int32_t k = l * kSlots; k < (l + 1) * kSlots; ++k) {
+        const int32_t a = key_ptr[k], b = key_ptr[k + 1];
+        if (b - a > 1)
+          std::stable_sort(gate_of.begin() + a, gate_of.begin() + b,
+                           [&](int32_t x, int32_t y) { return src_of(x) < src_of(y); });
+      }
       for (int32_t kind = 0; kind < 2; ++kind) {
         const int32_t k0 = l * kSlots + kind * 512;
         const int32_t a = key_ptr[k0], h = key_ptr[k0 + 256] - a, b = key_ptr[k0 + 512];
@@ -169,6 +182,8 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
           gate_of[a + i] = take_heavy ? part[hi++] : part[ni++];
         }
       }
+      for (int32_t i = key_ptr[l * kSlots]; i < key_ptr[(l + 1) * kSlots]; ++i) pos[gate_of[i]] = i;
+    }
   }
   auto *d = new dp_design();
   d->ctx = ctx;
