@@ -333,7 +333,11 @@ dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0,
  * held on the device at once (0 = automatic; otherwise a multiple of 2 that
  * splits the n_sim/64 words into chunks carrying a two-word halo), and the
  * word pairs each simulation lane handles per wave (1, 2, 4 or 8; 0 =
- * automatic).  Results are bitwise independent of all three. */
+ * automatic).  Results are bitwise independent of all three.  Choosing
+ * DP_SCHED_PERSISTENT the first time allocates the eval's two barrier words
+ * (8 bytes of device memory, zeroed on the eval's stream).
+ * Errors: DP_E_INVALID (unknown schedule or tiling), DP_E_UNSUPPORTED
+ * (persistent with library cells), DP_E_OOM, DP_E_HIP. */
 dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule,
                                int64_t words_per_chunk,
                                int32_t sim_pairs_per_lane);
