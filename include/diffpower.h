@@ -382,6 +382,33 @@ typedef struct {
 dp_status dp_eval_profile(dp_eval *ev, int32_t enable);
 dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
 
+/* --- forward without allocation ----------------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * forward as dp_forward on a one-column eval in DP_MODELED or DP_FROZEN_BETA
+ * (per-level launches; bit for bit the same results), without an eval: the
+ * SP pairs, the internal capacitances and beta, the per-net power terms and
+ * the power partial sums live in a static device array of the library
+ * (about 40 MiB on each GPU it runs on, held until the process ends; its
+ * device address is resolved once per GPU by dp_ctx_create).  The call
+ * allocates nothing, enqueues on the design's context stream and does not
+ * synchronize; the caller still provides every input and output.
+ *  pi_prob [n_pi], cap [n_nets] (caller numbering), beta [n_nets] (caller
+ *  numbering; DP_FROZEN_BETA only, else NULL), power [1], sp and tr
+ *  [n_nets] (caller numbering, each may be NULL): all device memory on the
+ *  context's GPU.  Input values are not checked (a NaN or an out-of-range
+ *  probability gives NaN or unclipped results).
+ * Limit: at most 2^21 nets (2,097,152).  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents: calls that overlap on
+ * one GPU (two streams, or two host threads) race and must be serialized
+ * by the caller.  Errors: DP_E_INVALID (NULL argument, bad params, beta
+ * given in the wrong mode, more nets than the limit), DP_E_UNSUPPORTED
+ * (DP_HYBRID), DP_E_STATE (no context was created on the design's GPU),
+ * DP_E_HIP. */
+dp_status dp_forward_static(const dp_design *design, const dp_params *params,
+                            const float *pi_prob, const float *cap, const float *beta,
+                            float *power, float *sp, float *tr);
+
 /* --- design groups: several designs in one launch ----------------------- */
 /* A group runs several evals -- of any designs of one context, of uneven
  * sizes -- as one unit (the batched form over designs): their forward sweeps,

@@ -101,6 +101,7 @@ SIGNATURES = {
     "dp_backward_columns": (_st, [_p, _p, _i32]),
     "dp_power_virus": (_st, [_p, _i32, ctypes.c_double, _p, _p, _p, _i32]),
     "dp_power_gradients": (_st, [_p, _p, _p, _i32]),
+    "dp_forward_static": (_st, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "dp_group_create": (_st, [_p, _p, _i32, _p]),
     "dp_group_run": (_st, [_p, _i32, _p, _p, _i32]),
     "dp_group_configure": (_st, [_p, _i32, _i32]),

@@ -101,6 +101,23 @@ class Design:
         self.n_pi, self.n_gates, self.n_nets = info.n_pi, info.n_gates, info.n_nets
         self.depth = info.depth
 
+    def forward_static(self, p, cap, *, out_power, mode=L.DP_MODELED, beta=None, out_sp=None,
+                       out_tr=None, **kw):
+        """One modeled (or frozen-beta) forward through dp_forward_static,
+        which allocates nothing: every argument is a torch CUDA tensor the
+        caller owns (p [n_pi], cap and beta [n_nets], out_power [1], out_sp
+        and out_tr [n_nets] or None).  Enqueued on the context's stream."""
+        prm = params(mode, **kw)
+
+        def dev(x):
+            if x is None:
+                return None
+            if not (_is_torch(x) and x.is_cuda and x.is_contiguous()):
+                raise ValueError("forward_static takes contiguous torch CUDA tensors")
+            return ctypes.c_void_p(x.data_ptr())
+        check(self.lib.dp_forward_static(self.handle, ctypes.byref(prm), dev(p), dev(cap),
+                                         dev(beta), dev(out_power), dev(out_sp), dev(out_tr)))
+
     def levels(self) -> np.ndarray:
         lv = np.zeros(self.n_nets, dtype=np.int32)
         check(self.lib.dp_design_levels(self.handle, lv.ctypes.data_as(ctypes.c_void_p)))

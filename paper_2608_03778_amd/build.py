@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdiffpower.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["dp_kernels.hip", "dp_api.cpp", "dp_compile.cpp", "dp_cells.cpp", "dp_server.cpp"]
+SOURCES = ["dp_kernels.hip", "dp_api.cpp", "dp_compile.cpp", "dp_cells.cpp", "dp_server.cpp",
+           "dp_static.hip"]
 ARCH = os.environ.get("DP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -53,32 +53,8 @@ constexpr int64_t kMaxGraphLaunches = 1024;
 const char *kVersion = "diffpower-mi355x 0.1 (gfx950)";
 enum { SPAN_SIM = 0, SPAN_SP = 1, SPAN_BWD = 2, SPAN_STIM = 3 };
 
-dp::GraphView view(const dp_design *d) {
-  dp::GraphView g;
-  g.op = d->op.as<uint8_t>();
-  g.in = d->in.as<int32_t>();
-  g.rev_ptr = d->rev_ptr.as<int32_t>();
-  g.rev_edge = d->rev_edge.as<int32_t>();
-  g.slot = d->slot.as<int32_t>();
-  g.code = d->code.as<uint16_t>();
-  g.cell = d->cell.as<int32_t>();
-  g.tt = d->tt.as<uint64_t>();
-  g.pins = d->pins;
-  g.n_pi = d->n_pi;
-  g.G = d->n_gates;
-  g.n_nets = d->n_nets;
-  return g;
-}
-
-// Level l as launch ranges: its fixed cells, then its library cells (ops
-// sort ascending inside a level), each range of one kind; f(g0, n, cells).
-template <class F>
-dp_status for_level_parts(const dp_design *d, int32_t l, F &&f) {
-  const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0, nf = d->lvl_fixed[l];
-  if (nf > 0) DP_TRY(f(g0, nf, false));
-  if (nf < n) DP_TRY(f(g0 + nf, n - nf, true));
-  return DP_OK;
-}
+dp::GraphView view(const dp_design *d) { return dp::design_view(d); }
+using dp::for_level_parts;
 
 int32_t s_prime(const dp_eval *ev) { return (ev->S > 0 && !ev->paired_sizes) ? ev->S : 1; }
 double kappa_of(const dp_params &p) { return p.energy_factor * p.vdd * p.vdd * p.fclk; }
@@ -671,6 +647,11 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
 
 }  // namespace
 
+namespace dp {
+dp_status params_ok(const dp_params *p) { return check_params(p); }
+double kappa(const dp_params &p) { return kappa_of(p); }
+}  // namespace dp
+
 dp_eval::~dp_eval() {
   if (graph_fwd) (void)hipGraphExecDestroy(graph_fwd);
   if (capture_stream_owned) (void)hipStreamDestroy(capture_stream_owned);
@@ -714,6 +695,7 @@ dp_status dp_ctx_create(int32_t device, void *hip_stream, dp_ctx **out) {
   if (device < 0 || device >= n)
     return fail(DP_E_INVALID, "dp_ctx_create: no device " + std::to_string(device));
   DP_HIP_TRY(hipSetDevice(device));
+  DP_TRY(dp::static_scratch_init(device));  // once per device: dp_forward_static's scratch
   auto *c = new dp_ctx();
   c->device = device;
   if (hip_stream == (void *)hipStreamLegacy) {

@@ -117,6 +117,43 @@ struct dp_design {
 
 namespace dp {
 
+// Device arrays of a design as the kernels see them.
+inline GraphView design_view(const dp_design *d) {
+  GraphView g;
+  g.op = d->op.as<uint8_t>();
+  g.in = d->in.as<int32_t>();
+  g.rev_ptr = d->rev_ptr.as<int32_t>();
+  g.rev_edge = d->rev_edge.as<int32_t>();
+  g.slot = d->slot.as<int32_t>();
+  g.code = d->code.as<uint16_t>();
+  g.cell = d->cell.as<int32_t>();
+  g.tt = d->tt.as<uint64_t>();
+  g.pins = d->pins;
+  g.n_pi = d->n_pi;
+  g.G = d->n_gates;
+  g.n_nets = d->n_nets;
+  return g;
+}
+
+// Level l as launch ranges: its fixed cells, then its library cells (ops
+// sort ascending inside a level), each range of one kind; f(g0, n, cells).
+template <class F>
+dp_status for_level_parts(const dp_design *d, int32_t l, F &&f) {
+  const int32_t g0 = d->level_ptr[l], n = d->level_ptr[l + 1] - g0, nf = d->lvl_fixed[l];
+  if (nf > 0) DP_TRY(f(g0, nf, false));
+  if (nf < n) DP_TRY(f(g0 + nf, n - nf, true));
+  return DP_OK;
+}
+
+// Parameter validation and kappa = energy_factor Vdd^2 f (Eq. 1), shared by
+// every entry point that takes a dp_params.
+dp_status params_ok(const dp_params *p);
+double kappa(const dp_params &p);
+
+// The static scratch of dp_forward_static: resolve its device address on
+// `device` (the device must be current; once per device).
+dp_status static_scratch_init(int device);
+
 // Host-side compile: validation, levelization, sort, renumbering and the
 // device upload.  Implemented in dp_compile.cpp.
 dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,

@@ -19,8 +19,10 @@ def available() -> bool:
 def build(out_dir: str) -> str:
     out = os.path.join(out_dir, "libdp_stub.so")
     kernels_h = os.path.join(CSRC, "dp_kernels.h")
+    abi_h = os.path.join(ROOT, "include", "diffpower.h")
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
-           "-I/opt/rocm/include", f'-DDP_KERNELS_H="{kernels_h}"', "-o", out,
+           "-I/opt/rocm/include", f'-DDP_KERNELS_H="{kernels_h}"', f'-DDP_ABI_H="{abi_h}"',
+           "-o", out,
            os.path.join(HERE, "hip_stub.cpp")] + [os.path.join(CSRC, s) for s in HOST_SOURCES]
     cmd += ["-lpthread"]
     subprocess.run(cmd, check=True, capture_output=True, text=True)

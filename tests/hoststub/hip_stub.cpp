@@ -15,6 +15,17 @@
 #include <set>
 
 #include DP_KERNELS_H
+#include DP_ABI_H
+
+// dp_forward_static's device scratch lives in a HIP source the stand-in
+// does not build; contexts only resolve its address.
+namespace dp {
+dp_status static_scratch_init(int) { return DP_OK; }
+}  // namespace dp
+extern "C" dp_status dp_forward_static(const dp_design *, const dp_params *, const float *,
+                                       const float *, const float *, float *, float *, float *) {
+  return DP_E_UNSUPPORTED;
+}
 
 struct ihipStream_t { int capturing = 0; };
 struct ihipEvent_t { int x = 0; };
