@@ -89,16 +89,23 @@ enum {
                              (forward sweeps of at most 1024 launches; a
                              larger one returns DP_E_UNSUPPORTED) */
   DP_SCHED_PERSISTENT = 3 /* SP-only sweeps (modeled forward, reverse sweep) as
-                             one cooperative launch with a grid barrier per
-                             level; the simulation keeps one launch per level.
-                             Opt-in: the autotuner does not pick it.  Fixed
-                             cells only: dp_eval_set_schedule returns
+                             one cooperative launch (at most one workgroup per
+                             compute unit) with a grid barrier per level; the
+                             simulation keeps one launch per level.  Opt-in:
+                             the autotuner does not pick it.  Fixed cells
+                             only: dp_eval_set_schedule returns
                              DP_E_UNSUPPORTED for a design with library-cell
-                             gates.  The barrier's wait is bounded: should it
-                             ever run out (it cannot while the launch's blocks
-                             stay resident), that sweep's outputs are NaN, and
-                             so are those of every later persistent sweep of
-                             the eval */
+                             gates.  A barrier wait that sees no progress for
+                             dp_eval_set_barrier_timeout's limit (1 ms by
+                             default; it cannot run out while the launch's
+                             blocks stay resident) gives up, every later wait
+                             of that launch stops at once and its outputs are
+                             NaN; the eval's next host synchronization (a
+                             call with host outputs, dp_power_gradients,
+                             dp_power_virus or dp_eval_synchronize) then
+                             returns DP_E_HIP saying so.  Each launch starts
+                             with its barrier reset, so later sweeps are not
+                             affected */
 };
 
 typedef struct dp_ctx dp_ctx;
@@ -363,6 +370,17 @@ dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule,
                                int64_t *words_per_chunk,
                                int32_t *sim_pairs_per_lane,
                                int32_t *sim_streams);
+
+/* Block until the eval's stream is idle.  Returns DP_E_HIP if a persistent
+ * sweep since the eval's last host synchronization had a grid-barrier wait
+ * give up (its outputs are NaN). */
+dp_status dp_eval_synchronize(dp_eval *ev);
+/* Time a grid-barrier wait of the persistent schedule may see no progress
+ * before it gives up (microseconds, finite, >= 0; default 1000).  A guard
+ * against a sweep whose blocks are not all resident, and a way for tests
+ * to make the give-up path run: at 0 every wait that has to wait at all
+ * gives up.  Errors: DP_E_INVALID. */
+dp_status dp_eval_set_barrier_timeout(dp_eval *ev, double microseconds);
 
 /* Kernel timing of the last forward/backward, accumulated with HIP events
  * on the context's stream while profiling is enabled. */

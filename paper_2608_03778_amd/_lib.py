@@ -110,6 +110,8 @@ SIGNATURES = {
     "dp_eval_autotune": (_st, [_p, _i32, _i32, _p]),
     "dp_eval_set_sim_streams": (_st, [_p, _i32]),
     "dp_eval_get_schedule": (_st, [_p, _p, _p, _p, _p]),
+    "dp_eval_synchronize": (_st, [_p]),
+    "dp_eval_set_barrier_timeout": (_st, [_p, ctypes.c_double]),
     "dp_eval_profile": (_st, [_p, _i32]),
     "dp_eval_get_profile": (_st, [_p, _p]),
     "dp_server_create": (_st, [_p, ctypes.c_size_t, _p]),

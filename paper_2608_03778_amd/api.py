@@ -321,6 +321,14 @@ class Eval:
         return dict(schedule=sc.value, words_per_chunk=ch.value, pairs_per_lane=pp.value,
                     sim_streams=ns.value)
 
+    def synchronize(self):
+        """Wait for the eval's stream; raises if a persistent sweep's grid
+        barrier gave up since the last host synchronization."""
+        check(self.lib.dp_eval_synchronize(self.handle))
+
+    def set_barrier_timeout(self, microseconds: float):
+        check(self.lib.dp_eval_set_barrier_timeout(self.handle, float(microseconds)))
+
     def profile(self, enable: bool = True):
         check(self.lib.dp_eval_profile(self.handle, int(bool(enable))))
 

@@ -247,11 +247,39 @@ dp_status on_coop_stream(dp_eval *ev, hipStream_t s, F launch) {
 }
 
 // The persistent sweeps' barrier words (allocated and zeroed when the
-// schedule is chosen; the timeout flag stays zero unless a wait runs out).
+// schedule is chosen; the launcher zeroes all but the report word before
+// each launch).
 dp_status grid_barrier(dp_eval *ev, dp::GridBarrier *out) {
   if (!ev->barrier.ptr) return fail(DP_E_STATE, "persistent sweep without its barrier words");
-  *out = dp::GridBarrier{ev->barrier.as<uint32_t>(), ev->barrier.as<uint32_t>() + 1};
+  const double ticks = ev->barrier_limit_us * 100.0;  // the real-time counter runs at 100 MHz
+  *out = dp::GridBarrier{ev->barrier.as<uint32_t>(), (uint64_t)std::max(ticks, 0.0)};
+  ev->barrier_pending = true;
   return DP_OK;
+}
+
+// At a host synchronization of the eval (its stream idle): whether a
+// persistent sweep since the last check had a barrier wait give up.  Reads
+// and clears the report word.
+dp_status barrier_status(dp_eval *ev) {
+  if (!ev->barrier_pending) return DP_OK;
+  uint32_t rep = 0;
+  uint32_t *w = ev->barrier.as<uint32_t>() + dp::kBarrierReport;
+  DP_HIP_TRY(hipMemcpy(&rep, w, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  ev->barrier_pending = false;
+  if (rep == 0u) return DP_OK;
+  DP_HIP_TRY(dp::launch_fill_u32(w, 1, 0u, ev->stream()));
+  DP_HIP_TRY(hipStreamSynchronize(ev->stream()));
+  return fail(DP_E_HIP, "a persistent sweep's grid barrier gave up waiting (no progress for " +
+                            std::to_string(ev->barrier_limit_us) +
+                            " us); that sweep's outputs are NaN and not a result");
+}
+
+// Synchronize the eval's stream when a persistent sweep is unchecked, then
+// report it (host-output calls end here).
+dp_status sync_and_check(dp_eval *ev) {
+  if (!ev->barrier_pending) return DP_OK;
+  DP_HIP_TRY(hipStreamSynchronize(ev->stream()));
+  return barrier_status(ev);
 }
 
 // Per-net beta of the last forward, or null in modeled mode (beta = 1).
@@ -965,8 +993,8 @@ dp_status dp_eval_set_schedule(dp_eval *ev, int32_t schedule, int64_t words_per_
     return fail(DP_E_UNSUPPORTED,
                 "dp_eval_set_schedule: the persistent schedule runs the fixed cells only");
   if (schedule == DP_SCHED_PERSISTENT && !ev->barrier.ptr) {
-    DP_TRY(ev->barrier.alloc(2 * sizeof(uint32_t)));
-    DP_HIP_TRY(dp::launch_fill_u32(ev->barrier.as<uint32_t>(), 2, 0u, ev->stream()));
+    DP_TRY(ev->barrier.alloc(dp::kBarrierAlloc * sizeof(uint32_t)));
+    DP_HIP_TRY(dp::launch_fill_u32(ev->barrier.as<uint32_t>(), dp::kBarrierAlloc, 0u, ev->stream()));
   }
   ev->schedule = schedule;
   ev->words_per_chunk = words_per_chunk;
@@ -1074,6 +1102,21 @@ dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule, int64_t *wo
   return DP_OK;
 }
 
+dp_status dp_eval_synchronize(dp_eval *ev) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_synchronize: NULL eval");
+  DP_HIP_TRY(hipSetDevice(ev->d->ctx->device));
+  DP_HIP_TRY(hipStreamSynchronize(ev->stream()));
+  return barrier_status(ev);
+}
+
+dp_status dp_eval_set_barrier_timeout(dp_eval *ev, double microseconds) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_set_barrier_timeout: NULL eval");
+  if (!(microseconds >= 0.0) || !std::isfinite(microseconds))
+    return fail(DP_E_INVALID, "dp_eval_set_barrier_timeout: need a finite time >= 0");
+  ev->barrier_limit_us = microseconds;
+  return DP_OK;
+}
+
 dp_status dp_eval_profile(dp_eval *ev, int32_t enable) {
   if (!ev) return fail(DP_E_INVALID, "dp_eval_profile: NULL eval");
   ev->profiling = enable != 0;
@@ -1122,6 +1165,7 @@ dp_status dp_forward(dp_eval *ev, const dp_fwd_out *out) {
   }
   ev->fwd_version = ev->inputs_version;
   if (out) DP_TRY(export_forward(ev, out, pl));
+  if (out && !out->on_device) DP_TRY(sync_and_check(ev));
   return DP_OK;
 }
 
@@ -1173,6 +1217,7 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
     DP_HIP_TRY(dp::launch_grad_export(ga, s));
     DP_TRY(om.flush(s));
   }
+  if (!on_device) DP_TRY(sync_and_check(ev));
   if (!on_device) DP_HIP_TRY(hipStreamSynchronize(s));
   return DP_OK;
 }
@@ -1210,7 +1255,7 @@ dp_status dp_power_gradients(dp_eval *ev, float *dpower_dsp, float *score, int32
                                            0x1p-20f, o_lam, o_score, s));
   DP_TRY(om.flush(s));
   DP_HIP_TRY(hipStreamSynchronize(s));  // the adjoint buffer is freed on return
-  return DP_OK;
+  return barrier_status(ev);
 }
 
 dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, float *p_final,
@@ -1285,7 +1330,7 @@ dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, fl
   if (p_virus) DP_HIP_TRY(hipMemcpyAsync(p_virus, pv.ptr, (size_t)B * sizeof(double), k, s));
   DP_HIP_TRY(hipStreamSynchronize(s));  // the scratch buffers are freed on return
   ev->inputs_version++;  // the PI probabilities are now the ascended ones
-  return DP_OK;
+  return barrier_status(ev);
 }
 
 dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device) {

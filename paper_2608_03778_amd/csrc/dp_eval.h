@@ -42,7 +42,9 @@ struct dp_eval {
   dp::DevBuf power_partial;  // [chunks][B*S'] double
   dp::DevBuf power;          // [B*S']
   dp::DevBuf flag;           // int32 validation flag
-  dp::DevBuf barrier;        // persistent sweeps: grid-barrier counter, timeout flag
+  dp::DevBuf barrier;        // persistent sweeps: grid-barrier words (dp::kBarrierAlloc)
+  bool barrier_pending = false;      // a persistent sweep ran since the report word was read
+  double barrier_limit_us = 1000.0;  // a barrier wait gives up after this long without progress
   // reverse state
   dp::DevBuf w;              // [B*S'] upstream weights
   dp::DevBuf contrib;        // [n_edges][C]

@@ -226,14 +226,30 @@ hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_n
                               double *out, hipStream_t s);
 
 // Persistent (cooperative) sweeps: all levels in one launch with a grid
-// barrier between levels; fixed cells only.  level_ptr is the device copy of the design's
-// level table; max_items the largest level's item count.
-// The barrier's two device words: a counter, zeroed by the launcher on the
-// stream before each launch, and a sticky timeout flag (zero at allocation)
-// that a wait sets if it runs out; the sweep's outputs are then NaN.
+// barrier between levels; fixed cells only.  level_ptr is the device copy of
+// the design's level table; max_items the largest level's item count.
+//
+// The barrier's device words (kBarrierWords uint32, each counter on a line
+// of its own, zeroed by the launcher on the stream before each launch):
+// kBarrierGroups arrival counters (block b arrives at counter b mod
+// kBarrierGroups), the global counter the last arrival of each group bumps,
+// and the timeout flag.  A wait that sees no progress for limit_ticks ticks
+// of the 100 MHz real-time counter sets the flag and stops, and every later
+// wait of the launch stops at once; the sweep's outputs are then NaN and the
+// report word (kBarrierReport) is set for the host to read.
+constexpr int kBarrierGroups = 8;
+constexpr int kBarrierStride = 32;  // 128 bytes between counters
+constexpr int kBarrierGlobal = kBarrierGroups * kBarrierStride;
+constexpr int kBarrierTimeout = kBarrierGlobal + kBarrierStride;
+constexpr int kBarrierWords = kBarrierTimeout + kBarrierStride;
+// One more word after them, not zeroed per launch: a wait that gives up also
+// sets it, so it records that some sweep since the host last cleared it
+// failed.
+constexpr int kBarrierReport = kBarrierWords;
+constexpr int kBarrierAlloc = kBarrierWords + kBarrierStride;
 struct GridBarrier {
-  uint32_t *count;
-  uint32_t *timeout;
+  uint32_t *words;       // [kBarrierAlloc]
+  uint64_t limit_ticks;  // 100 MHz ticks without progress before a wait gives up
 };
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
                                 int32_t depth, int64_t max_items, GridBarrier bar,

@@ -1378,34 +1378,61 @@ __global__ __launch_bounds__(kMergedBlock) void k_bwd_multi(const BwdSeg *__rest
 // level's items, then a grid barrier.  Whole waves step together so the
 // wave-wide pull of the reverse sweep sees all its lanes.
 //
-// The barrier is a counter zeroed before the launch: at barrier k each
-// block's first thread adds one (release, device scope) and polls (acquire)
-// until the counter reaches k * gridDim.x; the block's other threads wait at
-// the block barriers around it.  Cooperative launch keeps every block
-// resident, so every wait ends.  As a guard, a wait still polling after
-// kBarrierPolls rounds sets the sticky timeout flag and stops, every later
-// wait stops at once, and the sweep's outputs are then written as NaN: the
-// launch always drains and a broken sweep cannot pass for a result.
-constexpr uint32_t kBarrierPolls = 1u << 22;
-
+// The barrier: at barrier k each block's first thread adds one to its
+// group's counter (block b is in group b mod kBarrierGroups; acquire-release
+// at device scope, so the group's last arrival carries every earlier
+// arrival's writes); the group's last arrival (the one that brings the
+// counter to k times the group's size) adds one to the global counter
+// (release); every block then polls the global counter with plain
+// device-scope loads until it reaches k times the number of groups, and
+// takes one acquire fence.  Spreading the arrivals over eight counters keeps
+// any one of them from serialising all blocks' atomics.  Cooperative launch
+// keeps every block resident, so every wait ends; as a guard, a wait that
+// sees the global counter stand still for limit_ticks ticks of the 100 MHz
+// real-time counter sets the timeout flag and stops, a wait that finds the
+// flag set stops at once, and the sweep's outputs are then written as NaN.
+// The wait that gives up also sets the report word, which the host reads at
+// its next synchronization, so a broken sweep is reported and cannot pass
+// for a result.
 __device__ __forceinline__ bool barrier_timed_out(const GridBarrier &bar) {
-  return __hip_atomic_load(bar.timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+  return __hip_atomic_load(bar.words + kBarrierTimeout, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT) != 0u;
 }
 
 __device__ __forceinline__ void grid_barrier(const GridBarrier &bar, uint32_t k) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar.count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t target = k * gridDim.x;
-    for (uint32_t polls = 0;
-         __hip_atomic_load(bar.count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target;
-         ++polls) {
-      if (polls >= kBarrierPolls || barrier_timed_out(bar)) {
-        __hip_atomic_store(bar.timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t blocks = gridDim.x;
+    const uint32_t grp = blockIdx.x % kBarrierGroups;
+    const uint32_t grp_size = blocks / kBarrierGroups + (grp < blocks % kBarrierGroups ? 1u : 0u);
+    const uint32_t groups = blocks < (uint32_t)kBarrierGroups ? blocks : (uint32_t)kBarrierGroups;
+    uint32_t *cnt = bar.words + grp * kBarrierStride;
+    uint32_t *glob = bar.words + kBarrierGlobal;
+    const uint32_t before =
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (before + 1u == k * grp_size)
+      __hip_atomic_fetch_add(glob, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = k * groups;
+    uint32_t seen = 0xffffffffu;
+    uint64_t since = __builtin_amdgcn_s_memrealtime();
+    for (uint32_t it = 0;; ++it) {
+      const uint32_t c = __hip_atomic_load(glob, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c >= target) break;
+      if ((it & 15u) == 0u && barrier_timed_out(bar)) break;
+      const uint64_t now = __builtin_amdgcn_s_memrealtime();
+      if (c != seen) {
+        seen = c;
+        since = now;
+      } else if (now - since >= bar.limit_ticks) {
+        __hip_atomic_store(bar.words + kBarrierTimeout, 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(bar.words + kBarrierReport, 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -1783,13 +1810,16 @@ hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipSt
 
 // Blocks of a cooperative launch: enough for the widest level, at most what
 // stays resident on the device.
+// One block per compute unit at most (and never more than stays resident):
+// the barrier's cost grows with its block count, and a wider level is
+// covered by the grid-stride loop.
 static hipError_t persistent_grid(const void *kernel, int64_t max_items, unsigned *grid) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
   if (e != hipSuccess) return e;
-  const int64_t resident = (int64_t)per_cu * ncu;
+  const int64_t resident = std::min<int64_t>((int64_t)per_cu * ncu, ncu);
   if (resident < 1) return hipErrorInvalidValue;
   const int64_t want = std::max<int64_t>(1, (max_items + kBlock - 1) / kBlock);
   *grid = (unsigned)std::min(resident, want);
@@ -1800,11 +1830,11 @@ hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int
                                 int32_t depth, int64_t max_items, GridBarrier bar,
                                 hipStream_t s) {
   if (depth <= 0) return hipSuccess;
-  if (max_items >= (1ll << 31) || !bar.count || !bar.timeout) return hipErrorInvalidValue;
+  if (max_items >= (1ll << 31) || !bar.words) return hipErrorInvalidValue;
   unsigned grid = 0;
   hipError_t e = persistent_grid(reinterpret_cast<const void *>(&k_sp_persistent), max_items, &grid);
   if (e != hipSuccess) return e;
-  k_fill_u32<<<1, kBlock, 0, s>>>(bar.count, 1, 0u);
+  k_fill_u32<<<blocks_for(kBarrierWords), kBlock, 0, s>>>(bar.words, kBarrierWords, 0u);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   GraphView gv = g;
@@ -1821,14 +1851,14 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
                                  int32_t depth, int64_t max_items, float *pi_out,
                                  GridBarrier bar, hipStream_t s) {
   max_items = std::max<int64_t>(max_items, (int64_t)g.n_pi * a.C);
-  if (max_items >= (1ll << 31) || !bar.count || !bar.timeout) return hipErrorInvalidValue;
+  if (max_items >= (1ll << 31) || !bar.words) return hipErrorInvalidValue;
   const void *kernel = a.C >= kSerialColumns
                            ? reinterpret_cast<const void *>(&k_bwd_persistent<true>)
                            : reinterpret_cast<const void *>(&k_bwd_persistent<false>);
   unsigned grid = 0;
   hipError_t e = persistent_grid(kernel, max_items, &grid);
   if (e != hipSuccess) return e;
-  k_fill_u32<<<1, kBlock, 0, s>>>(bar.count, 1, 0u);
+  k_fill_u32<<<blocks_for(kBarrierWords), kBlock, 0, s>>>(bar.words, kBarrierWords, 0u);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   GraphView gv = g;

@@ -296,8 +296,8 @@ hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipSt
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
                                 int32_t depth, int64_t, GridBarrier bar, hipStream_t) {
   rd(level_ptr, depth + 2);
-  wr(bar.count, 1);
-  rd(bar.timeout, 1);
+  wr(bar.words, kBarrierWords);
+  rd(bar.words + kBarrierReport, 1);
   wr(lv.sp, (int64_t)g.n_nets * lv.B * 2);
   return hipSuccess;
 }
@@ -305,8 +305,8 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
                                  int32_t depth, int64_t, float *pi_out, GridBarrier bar,
                                  hipStream_t s) {
   rd(level_ptr, depth + 2);
-  wr(bar.count, 1);
-  rd(bar.timeout, 1);
+  wr(bar.words, kBarrierWords);
+  rd(bar.words + kBarrierReport, 1);
   return launch_bwd_pi(g, a, pi_out, s);
 }
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,

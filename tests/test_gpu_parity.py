@@ -397,6 +397,46 @@ def test_persistent_schedule_is_bitwise_equal(ctx, mode, B, ste):
     assert_grad_close(res[L.DP_SCHED_PERSISTENT]["dpi"][0], adj["dpi"], "persistent dP/dp")
 
 
+def test_persistent_barrier_gives_up_and_reports(ctx):
+    """The grid barrier's bounded wait, forced from the host: at a limit of
+    0 us every wait that has to wait gives up, every later wait of the
+    launch stops at once (so every kernel exits normally), and the host
+    reports DP_E_HIP at the eval's next synchronization instead of passing
+    the NaN outputs off as a result.  With the default limit restored the
+    next sweeps are whole again: bit for bit the per-level launches'."""
+    say("persistent barrier give-up (forced from the host)")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 17)
+    B = 40  # about 4,000 items per level: several workgroups wait at each barrier
+    p, cap, _ = _inputs(nl, 17, B=B)
+    d = api.Design(ctx, nl)
+    ref = api.Eval(d, B)
+    ref.set_pi_prob(p)
+    ref.set_caps(cap)
+    ref.set_schedule(L.DP_SCHED_LEVEL)
+    want = ref.forward(("sp", "power"))
+    want.update(ref.backward(want=("dpi",)))
+    ev = api.Eval(d, B)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    ev.set_schedule(L.DP_SCHED_PERSISTENT)
+    ev.set_barrier_timeout(0.0)
+    with pytest.raises(L.DiffPowerError, match="gave up"):
+        ev.forward(("sp", "power"))
+    # device outputs: reported at the next synchronization of the eval
+    ev.forward(("power",), device=True)
+    with pytest.raises(L.DiffPowerError, match="gave up"):
+        ev.synchronize()
+    with pytest.raises(L.DiffPowerError, match="gave up"):
+        ev.backward(want=("dpi",))
+    ev.synchronize()  # reported once: nothing left to report
+    ev.set_barrier_timeout(1000.0)
+    got = ev.forward(("sp", "power"))
+    got.update(ev.backward(want=("dpi",)))
+    ev.synchronize()
+    for k in want:
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+
+
 def test_persistent_schedule_with_a_large_grid(ctx):
     """The grid barrier with hundreds of blocks (10,000 gates, 512 columns:
     about 170,000 items per level, one block per 256 of them up to what
