@@ -128,12 +128,45 @@ def set_cells(exprs) -> None:
         raise ValueError(f"cell {-rc - 1} does not compile")
 
 
+def expression_inputs(expr: str):
+    """A cell expression's identifiers in order of first appearance: the
+    inputs the oracle's compiler numbers 0, 1, ... as it reads left to
+    right."""
+    import re
+    seen = []
+    for m in re.finditer(r"[A-Za-z_][A-Za-z0-9_]*", expr):
+        if m.group(0) not in seen:
+            seen.append(m.group(0))
+    return seen
+
+
+def _inputs_in_expression_order(op, fanin_ptr, fanin, cells, pins):
+    """Reorder each library-cell gate's fan-in from its pin list's order
+    (pins[c], names separated by commas or blanks) into the order of its
+    expression's inputs (Alg. 1's perm), so the rest of the oracle reads
+    input k at position k."""
+    import re
+    out = fanin.copy()
+    for c, pl in enumerate(pins):
+        if not pl:
+            continue
+        names = [x for x in re.split(r"[,\s]+", pl) if x]
+        ids = expression_inputs(cells[c])
+        if sorted(names) != sorted(ids) or len(set(names)) != len(names):
+            raise ValueError(f"pin list {pl!r} does not match the inputs {ids} of cell {c}")
+        src = [names.index(ident) for ident in ids]  # fan-in position of input k
+        for g in np.nonzero(op == CELL_BASE + c)[0]:
+            a = int(fanin_ptr[g])
+            out[a:a + len(ids)] = fanin[[a + j for j in src]]
+    return out
+
+
 class Netlist:
     """The oracle's own copy of a netlist (caller numbering) plus its
     topological order.  Gates with opcode CELL_BASE + c are instances of
     cells[c], a Boolean expression."""
 
-    def __init__(self, n_pi, op, fanin_ptr, fanin, cells=None):
+    def __init__(self, n_pi, op, fanin_ptr, fanin, cells=None, pins=None):
         lib = _load()
         self.cells = list(cells or [])
         set_cells(self.cells)
@@ -141,6 +174,9 @@ class Netlist:
         self.op = _c(op, np.uint8)
         self.fanin_ptr = _c(fanin_ptr, np.int32)
         self.fanin = _c(fanin, np.int32)
+        if pins and any(pins):
+            self.fanin = _inputs_in_expression_order(self.op, self.fanin_ptr, self.fanin,
+                                                     self.cells, list(pins))
         self.n_gates = int(self.op.shape[0])
         self.n_nets = self.n_pi + self.n_gates
         self.order = np.zeros(max(self.n_gates, 1), dtype=np.int32)
@@ -153,7 +189,8 @@ class Netlist:
 
     @classmethod
     def of(cls, nl):
-        return cls(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin, getattr(nl, "cells", None))
+        return cls(nl.n_pi, nl.op, nl.fanin_ptr, nl.fanin, getattr(nl, "cells", None),
+                   getattr(nl, "pins", None))
 
     def _args(self):
         set_cells(self.cells)  # the library is process state: bind ours first

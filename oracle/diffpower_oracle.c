@@ -211,45 +211,48 @@ static double complex cell_sp_c(int c, const double complex *x) {
   return st[0];
 }
 
-/* Reverse-mode derivative of cell_sp (Sec. III-E, Alg. 3): a forward pass
- * keeps each binary operation's operands; a backward pass over the code in
- * reverse keeps a stack of output gradients: an input adds its gradient to
- * its slot, NOT negates, a binary operation replaces the gradient of its
- * result by those of its two operands (the right operand's on top, as it
- * was computed last), a constant drops it. */
+/* Partial derivatives of cell_sp with respect to each input (Sec. III-E),
+ * by forward-mode differentiation: for input k the code is evaluated on
+ * (value, derivative with respect to x_k) pairs, each operation applying
+ * the chain rule to its independent-operand rule:
+ *   NOT  1 - a        ->  -a'
+ *   AND  a b          ->  a' b + a b'
+ *   OR   a + b - a b  ->  a' + b' - (a' b + a b')
+ *   XOR  a + b - 2ab  ->  a' + b' - 2 (a' b + a b')
+ * an input contributes 1 for x_k and 0 otherwise, a constant 0. */
 static void cell_partials(int c, const double *x, double *d) {
-  double st[ORC_MAX_CODE], ta[ORC_MAX_CODE], tb[ORC_MAX_CODE], gs[ORC_MAX_CODE];
-  int top = 0;
-  for (int k = 0; k < g_nin[c]; ++k) d[k] = 0.0;
-  for (int i = 0; i < g_len[c]; ++i) {
-    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
-    switch (op) {
-      case OC_IN: st[top++] = x[arg]; break;
-      case OC_ZERO: st[top++] = 0.0; break;
-      case OC_ONE: st[top++] = 1.0; break;
-      case OC_NOT: st[top - 1] = 1.0 - st[top - 1]; break;
-      default: {
-        double b = st[--top], a = st[--top];
-        ta[i] = a;
-        tb[i] = b;
-        st[top++] = op == OC_AND ? a * b : (op == OC_OR ? a + b - a * b : a + b - 2.0 * a * b);
+  for (int k = 0; k < g_nin[c]; ++k) {
+    double v[ORC_MAX_CODE], dv[ORC_MAX_CODE];
+    int top = 0;
+    for (int i = 0; i < g_len[c]; ++i) {
+      int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
+      if (op == OC_IN || op == OC_ZERO || op == OC_ONE) {
+        v[top] = op == OC_IN ? x[arg] : (op == OC_ONE ? 1.0 : 0.0);
+        dv[top] = (op == OC_IN && arg == k) ? 1.0 : 0.0;
+        ++top;
+      } else if (op == OC_NOT) {
+        v[top - 1] = 1.0 - v[top - 1];
+        dv[top - 1] = -dv[top - 1];
+      } else {
+        --top;
+        double b = v[top], db = dv[top];
+        --top;
+        double a = v[top], da = dv[top];
+        double prod = da * b + a * db;
+        if (op == OC_AND) {
+          v[top] = a * b;
+          dv[top] = prod;
+        } else if (op == OC_OR) {
+          v[top] = a + b - a * b;
+          dv[top] = da + db - prod;
+        } else {
+          v[top] = a + b - 2.0 * a * b;
+          dv[top] = da + db - 2.0 * prod;
+        }
+        ++top;
       }
     }
-  }
-  int gt = 0;
-  gs[gt++] = 1.0;
-  for (int i = g_len[c] - 1; i >= 0; --i) {
-    int op = g_code[c][i] & 0xff, arg = g_code[c][i] >> 8;
-    double g = gs[--gt];
-    switch (op) {
-      case OC_IN: d[arg] += g; break;
-      case OC_ZERO:
-      case OC_ONE: break;
-      case OC_NOT: gs[gt++] = -g; break;
-      case OC_AND: gs[gt++] = g * tb[i]; gs[gt++] = g * ta[i]; break;
-      case OC_OR: gs[gt++] = g * (1.0 - tb[i]); gs[gt++] = g * (1.0 - ta[i]); break;
-      default: gs[gt++] = g * (1.0 - 2.0 * tb[i]); gs[gt++] = g * (1.0 - 2.0 * ta[i]); break;
-    }
+    d[k] = dv[0];
   }
 }
 

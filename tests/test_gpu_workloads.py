@@ -10,7 +10,7 @@ import oracle
 from paper_2608_03778_amd import _lib as L
 from paper_2608_03778_amd import api, rank, synth
 from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, say)
-from tests.oracle_parallel import sim_counts
+from oracle.parallel import sim_counts
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 

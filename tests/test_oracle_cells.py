@@ -210,3 +210,26 @@ def test_sim_with_cells_counts_exhaustive_stimulus():
     ones, _ = o.sim(2, pi_words=words)
     exact = brute_exact(nl, np.full(nl.n_pi, 0.5)) * 64
     np.testing.assert_array_equal(ones, (2 * exact).round().astype(np.uint64))
+
+
+def test_pin_lists_reorder_fanin_into_expression_order():
+    """The oracle's own Alg. 1 perm: a gate wired by pin list equals the
+    same gate with its fan-in written in the expression's order of first
+    appearance; identifiers are numbered as the parser first meets them."""
+    assert oracle.expression_inputs("(I0&!S)|(I1&S)") == ["I0", "S", "I1"]
+    assert oracle.expression_inputs("!(b1 ^ a_2) | 1 & b1") == ["b1", "a_2"]
+    expr = "(I0&!S)|(I1&S)"
+    rng = np.random.default_rng(5)
+    n_pi = 9
+    wires = [list(rng.choice(n_pi, 3, replace=False)) for _ in range(20)]
+    op = np.full(20, oracle.CELL_BASE, np.uint8)
+    ptr = np.arange(21, dtype=np.int32) * 3
+    by_pins = oracle.Netlist(n_pi, op, ptr, np.array(sum(wires, []), np.int32), [expr],
+                             ["I0, I1, S"])
+    by_hand = oracle.Netlist(n_pi, op, ptr,
+                             np.array(sum([[w[0], w[2], w[1]] for w in wires], []), np.int32),
+                             [expr])
+    p = rng.uniform(0.1, 0.9, n_pi)
+    np.testing.assert_array_equal(by_pins.sp(p), by_hand.sp(p))
+    with pytest.raises(ValueError):
+        oracle.Netlist(n_pi, op, ptr, np.array(sum(wires, []), np.int32), [expr], ["I0,I1"])
