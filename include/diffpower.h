@@ -85,9 +85,12 @@ enum {
 enum {
   DP_SCHED_AUTO = 0,      /* the autotuned choice (default) */
   DP_SCHED_LEVEL = 1,     /* one launch per level */
-  DP_SCHED_GRAPH = 2,     /* the same launches captured once into a HIP graph
-                             (forward sweeps of at most 1024 launches; a
-                             larger one returns DP_E_UNSUPPORTED) */
+  DP_SCHED_GRAPH = 2,     /* the same launches captured once into HIP graphs,
+                             one per forward sweep and one per reverse sweep
+                             of dp_backward / dp_backward_columns (forward
+                             sweeps of at most 1024 launches; a larger one
+                             returns DP_E_UNSUPPORTED; a larger reverse sweep
+                             runs launch by launch) */
   DP_SCHED_PERSISTENT = 3 /* SP-only sweeps (modeled forward, reverse sweep) as
                              one cooperative launch (at most one workgroup per
                              compute unit) with a grid barrier per level; the
@@ -224,6 +227,25 @@ dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out);
 #define DP_CELL_BASE 16
 dp_status dp_compile_cells(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cells,
                            const char *const *cells, dp_design **out);
+/* The same with pin lists (Alg. 1's perm): pins[c] names the pins of
+ * library cell c in the order a gate of that cell lists its fan-in, names
+ * separated by commas or blanks, for example "I0,I1,S" for the multiplexer
+ * "(I0&!S)|(I1&S)", whose inputs in order of first appearance are
+ * [I0, S, I1].  Each list names every identifier of the expression once
+ * and nothing else; pins NULL or pins[c] NULL keeps the order of first
+ * appearance.  Cells whose compiled code is the same share one logic id
+ * (Alg. 1's dedup: one code-table entry, and their gates sort together
+ * within a level).  Errors as dp_compile_cells, plus DP_E_INVALID for a pin
+ * list that does not match its expression. */
+dp_status dp_compile_library(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cells,
+                             const char *const *cells, const char *const *pins,
+                             dp_design **out);
+/* Logic ids of a design's library cells: logic[c] ([n_cells] of the
+ * compile call, host; may be NULL) is the id of cell c's compiled code
+ * (cells with the same code share it), or -1 - op for a cell that runs as
+ * fixed cell op; *n_logic (may be NULL) receives the number of distinct
+ * ids.  Errors: DP_E_INVALID. */
+dp_status dp_design_cell_logic(const dp_design *design, int32_t *logic, int32_t *n_logic);
 dp_status dp_design_info(const dp_design *design, dp_design_info_t *out);
 /* Level of every net in caller numbering ([n_nets], host). */
 dp_status dp_design_levels(const dp_design *design, int32_t *level);
@@ -365,6 +387,12 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward,
  * Counts are integer sums, so results do not depend on it.  A captured
  * graph (DP_SCHED_GRAPH) records its pieces on one stream. */
 dp_status dp_eval_set_sim_streams(dp_eval *ev, int32_t sim_streams);
+/* Query columns one simulation launch covers (each column with a word
+ * buffer of its own; 0 = automatic: as many as the word budget of 32 GiB
+ * per simulation stream holds, at least one).  Fewer columns per launch
+ * mean more launches per level; counts do not depend on it.
+ * Errors: DP_E_INVALID (columns < 0). */
+dp_status dp_eval_set_sim_columns(dp_eval *ev, int32_t columns);
 /* The schedule in force (as set or as chosen by the autotuner). */
 dp_status dp_eval_get_schedule(const dp_eval *ev, int32_t *schedule,
                                int64_t *words_per_chunk,
@@ -405,9 +433,9 @@ dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * forward as dp_forward on a one-column eval in DP_MODELED or DP_FROZEN_BETA
  * (per-level launches; bit for bit the same results), without an eval: the
- * SP pairs, the internal capacitances and beta, the per-net power terms and
+ * SP, the internal capacitances and beta, the per-net power terms and
  * the power partial sums live in a static device array of the library
- * (about 40 MiB on each GPU it runs on, held until the process ends; its
+ * (32 MiB on each GPU it runs on, held until the process ends; its
  * device address is resolved once per GPU by dp_ctx_create).  The call
  * allocates nothing, enqueues on the design's context stream and does not
  * synchronize; the caller still provides every input and output.
@@ -510,6 +538,9 @@ typedef struct {
   int64_t peak_slot_bytes;  /* slot memory high-water mark */
   int32_t max_inflight;     /* most queries on the device at once */
   int32_t reserved;
+  int64_t lanes_created;    /* slot groups allocated */
+  int64_t lanes_freed;      /* idle slot groups freed to make room under the budget */
+  int64_t memory_waits;     /* times a waiting query found no memory for a slot */
 } dp_server_stats;
 dp_status dp_server_get_stats(dp_server *srv, dp_server_stats *out);
 void dp_server_destroy(dp_server *srv);

@@ -68,7 +68,8 @@ class Query(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("device_steps", _i64),
                 ("busy_s", ctypes.c_double), ("peak_slot_bytes", _i64), ("max_inflight", _i32),
-                ("reserved", _i32)]
+                ("reserved", _i32), ("lanes_created", _i64), ("lanes_freed", _i64),
+                ("memory_waits", _i64)]
 
 
 # name -> (restype, argtypes); every symbol the header declares
@@ -82,6 +83,8 @@ SIGNATURES = {
     "dp_ctx_destroy": (None, [_p]),
     "dp_compile": (_st, [_p, _p, _p]),
     "dp_compile_cells": (_st, [_p, _p, _i32, _p, _p]),
+    "dp_compile_library": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "dp_design_cell_logic": (_st, [_p, _p, _p]),
     "dp_design_info": (_st, [_p, _p]),
     "dp_design_levels": (_st, [_p, _p]),
     "dp_design_destroy": (None, [_p]),
@@ -109,6 +112,7 @@ SIGNATURES = {
     "dp_eval_set_schedule": (_st, [_p, _i32, _i64, _i32]),
     "dp_eval_autotune": (_st, [_p, _i32, _i32, _p]),
     "dp_eval_set_sim_streams": (_st, [_p, _i32]),
+    "dp_eval_set_sim_columns": (_st, [_p, _i32]),
     "dp_eval_get_schedule": (_st, [_p, _p, _p, _p, _p]),
     "dp_eval_synchronize": (_st, [_p]),
     "dp_eval_set_barrier_timeout": (_st, [_p, ctypes.c_double]),

@@ -88,7 +88,16 @@ class Design:
                        fan.ctypes.data)
         h = ctypes.c_void_p()
         cells = [c.encode() for c in getattr(netlist, "cells", ()) or ()]
-        if cells:
+        pins = list(getattr(netlist, "pins", ()) or ())
+        self.n_cells = len(cells)
+        if cells and pins:
+            arr = (ctypes.c_char_p * len(cells))(*cells)
+            parr = (ctypes.c_char_p * len(cells))(*[(x.encode() if x else None) for x in pins])
+            check(self.lib.dp_compile_library(ctx.handle, ctypes.byref(nl), len(cells),
+                                              ctypes.cast(arr, ctypes.c_void_p),
+                                              ctypes.cast(parr, ctypes.c_void_p),
+                                              ctypes.byref(h)))
+        elif cells:
             arr = (ctypes.c_char_p * len(cells))(*cells)
             check(self.lib.dp_compile_cells(ctx.handle, ctypes.byref(nl), len(cells),
                                             ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(h)))
@@ -117,6 +126,15 @@ class Design:
             return ctypes.c_void_p(x.data_ptr())
         check(self.lib.dp_forward_static(self.handle, ctypes.byref(prm), dev(p), dev(cap),
                                          dev(beta), dev(out_power), dev(out_sp), dev(out_tr)))
+
+    def cell_logic(self):
+        """(logic id of every library cell, or -1 - op for one that runs as a
+        fixed cell; number of distinct ids)."""
+        logic = np.zeros(max(self.n_cells, 1), dtype=np.int32)
+        n = ctypes.c_int32()
+        check(self.lib.dp_design_cell_logic(self.handle, logic.ctypes.data_as(ctypes.c_void_p),
+                                            ctypes.byref(n)))
+        return logic[: self.n_cells], n.value
 
     def levels(self) -> np.ndarray:
         lv = np.zeros(self.n_nets, dtype=np.int32)
@@ -313,6 +331,10 @@ class Eval:
 
     def set_sim_streams(self, n: int):
         check(self.lib.dp_eval_set_sim_streams(self.handle, int(n)))
+
+    def set_sim_columns(self, n: int):
+        """Query columns per simulation launch (0 = as many as fit)."""
+        check(self.lib.dp_eval_set_sim_columns(self.handle, int(n)))
 
     def get_schedule(self) -> dict:
         sc, ch, pp, ns = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()

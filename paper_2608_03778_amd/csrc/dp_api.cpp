@@ -171,9 +171,14 @@ dp_status resolve_profile(dp_eval *ev) {
 }
 
 // --- chunking of the simulated words
+// The simulation holds `cols` query columns' word buffers per stream (a
+// column group, simulated by the same launches), each Tc words (plus a
+// two-word halo when the run is cut into chunks) per net.
 struct ChunkPlan {
   int64_t T = 0, Tc = 0, pitch = 0;
   int32_t halo = 0, n_chunks = 0;
+  int32_t cols = 1;      // query columns per launch
+  int32_t n_groups = 1;  // column groups, ceil(B / cols)
 };
 
 int32_t n_sim_streams(const dp_eval *ev) { return ev->sim_streams > 0 ? ev->sim_streams : 1; }
@@ -181,10 +186,12 @@ int32_t n_sim_streams(const dp_eval *ev) { return ev->sim_streams > 0 ? ev->sim_
 ChunkPlan plan_chunks(const dp_eval *ev) {
   ChunkPlan c;
   c.T = n_words(ev->prm);
-  int64_t want = ev->words_per_chunk;
+  // words per net that fit one stream's share of the budget, over all the
+  // columns of its buffer
   const int64_t row_budget = std::max<int64_t>(
       kAutoWordBudget / (8 * (int64_t)ev->d->n_nets * n_sim_streams(ev)), 4);
-  if (want <= 0) want = c.T <= row_budget ? c.T : row_budget - 2;
+  int64_t want = ev->words_per_chunk;
+  if (want <= 0) want = c.T + (c.T & 1) <= row_budget ? c.T : row_budget - 2;
   want = std::max<int64_t>(2, want + (want & 1));
   if (want >= c.T) {
     c.Tc = c.T + (c.T & 1);
@@ -196,13 +203,21 @@ ChunkPlan plan_chunks(const dp_eval *ev) {
     c.n_chunks = (int32_t)((c.T + c.Tc - 1) / c.Tc);
   }
   c.pitch = c.halo + c.Tc;
+  // as many columns per launch as the budget holds at this pitch
+  c.cols = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ev->B, row_budget / c.pitch));
+  if (ev->sim_cols > 0) c.cols = std::min(c.cols, ev->sim_cols);
+  c.n_groups = (ev->B + c.cols - 1) / c.cols;
   return c;
 }
 
-dp::ChunkView chunk_view(const dp_eval *ev, const ChunkPlan &pl, int32_t k, int32_t lane) {
+// Chunk k of column group `grp` on simulation stream `lane`.
+dp::ChunkView chunk_view(const dp_eval *ev, const ChunkPlan &pl, int32_t k, int32_t lane,
+                         int32_t grp) {
   dp::ChunkView v;
-  v.W = ev->words.as<uint64_t>() + (size_t)lane * ev->d->n_nets * pl.pitch;
+  const int64_t col_stride = (int64_t)ev->d->n_nets * pl.pitch;
+  v.W = ev->words.as<uint64_t>() + (size_t)lane * pl.cols * col_stride;
   v.pitch = pl.pitch;
+  v.col_stride = col_stride;
   const int64_t t0 = (int64_t)k * pl.Tc;
   const int64_t nw = std::min<int64_t>(pl.Tc, pl.T - t0);
   v.t_first = t0 - pl.halo;
@@ -210,6 +225,7 @@ dp::ChunkView chunk_view(const dp_eval *ev, const ChunkPlan &pl, int32_t k, int3
   v.u_hi = (int32_t)(pl.halo + nw);
   v.u_tog_lo = t0 == 0 ? pl.halo + 1 : pl.halo;
   v.pairs = (v.u_hi + 1) / 2;
+  v.n_cols = std::min(pl.cols, ev->B - grp * pl.cols);
   return v;
 }
 
@@ -295,7 +311,7 @@ bool markov(const dp_eval *ev) { return ev->have_tau && !ev->have_stim; }
 int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
   const int64_t depth = ev->d->depth + ev->d->split_levels;
   if (!pl) return depth + 2;
-  return (int64_t)ev->B * pl->n_chunks * (depth + 1) + 4 + (markov(ev) ? 1 : 0) +
+  return (int64_t)pl->n_groups * pl->n_chunks * (depth + 1) + 4 + (markov(ev) ? 1 : 0) +
          ev->d->cell_levels;  // the library cells' SP launches
 }
 
@@ -314,7 +330,7 @@ dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
     DP_TRY(ev->ones.alloc(nb * sizeof(uint32_t)));
     DP_TRY(ev->tog.alloc(nb * sizeof(uint32_t)));
     const int32_t L = n_sim_streams(ev);
-    DP_TRY(ev->words.alloc((size_t)L * d->n_nets * pl->pitch * sizeof(uint64_t)));
+    DP_TRY(ev->words.alloc((size_t)L * pl->cols * d->n_nets * pl->pitch * sizeof(uint64_t)));
     if (markov(ev))
       DP_TRY(ev->mstim.alloc(std::max<size_t>((size_t)ev->B * d->n_pi * pl->T * sizeof(uint64_t), 16)));
     while ((int32_t)ev->lane_streams.size() < L - 1) {
@@ -331,28 +347,34 @@ dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
   return DP_OK;
 }
 
-double sim_level_bytes(const dp_design *d, int32_t l, int64_t words, int32_t B, bool fused) {
+// Algorithmic bytes of one simulation launch of level l over `cols`
+// columns of `words` words each (and the level's SP over B columns when
+// fused).
+double sim_level_bytes(const dp_design *d, int32_t l, int64_t words, int32_t cols, int32_t B,
+                       bool fused) {
   const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
   const int64_t pins = d->lvl_pins[l], read = d->lvl_read[l];
-  // fan-in words, and output words of the nets that have readers (a net
-  // without readers needs only its counts, so its words are not stored)
-  double b = (double)(8 * pins + 8 * read) * (double)words
-             + (double)(4 * pins + n) + 8.0 * n + 8.0 * n;  // indices, cell, fan-out range, counters
-  if (fused) b += (double)B * (8 * pins + 8 * n);         // SP pair gathers and writes
+  // per column: fan-in words, output words of the nets that have readers (a
+  // net without readers needs only its counts, so its words are not
+  // stored), counters; per launch: indices, cell, fan-out range
+  double b = (double)cols * ((double)(8 * pins + 8 * read) * (double)words + 8.0 * n)
+             + (double)(4 * pins + n) + 8.0 * n;
+  if (fused) b += (double)B * (4 * pins + 4 * n);  // SP gathers and writes
   return b;
 }
 
 double sp_level_bytes(const dp_design *d, int32_t l, int32_t B) {
   const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
   const int64_t pins = d->lvl_pins[l];
-  return (double)B * (8 * pins + 8 * n) + (double)(4 * pins + n);  // (p, q) pairs
+  return (double)B * (4 * pins + 4 * n) + (double)(4 * pins + n);  // stored SP gathers, writes
 }
 
 double bwd_level_bytes(const dp_design *d, int32_t l, int32_t C) {
   const int64_t n = d->level_ptr[l + 1] - d->level_ptr[l];
   const int64_t pins = d->lvl_pins[l], fo = d->lvl_fanout[l];
-  // per column: seed, pulled contributions, fan-in SP pair gathers, contribution writes
-  const double per_col = 4.0 * n + 4.0 * fo + 8.0 * pins + 4.0 * pins;
+  // per column: own SP (the seed), pulled contributions, fan-in SP gathers,
+  // contribution writes
+  const double per_col = 4.0 * n + 4.0 * fo + 4.0 * pins + 4.0 * pins;
   // structure: fan-out offsets and edge ids, fan-in indices, cell
   const double structure = 8.0 * n + 4.0 * fo + 4.0 * pins + n;
   return (double)C * per_col + structure;
@@ -401,9 +423,10 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
                                          ev->prm.seed, ev->mstim.as<uint64_t>(), s));
       stim_all = ev->mstim.as<uint64_t>();
     }
-    // (column, chunk) pieces are independent: piece j runs on stream j % L
-    // with its own word buffer; the SP of each level is fused into piece 0.
-    const int32_t n_pieces = ev->B * pl->n_chunks;
+    // (column group, chunk) pieces are independent: piece j runs on stream
+    // j % L with its own word buffers; the SP of each level is fused into
+    // piece 0.
+    const int32_t n_pieces = pl->n_groups * pl->n_chunks;
     // a capture records one stream only (multi-stream captures are off)
     const int32_t L = ev->capturing ? 1 : std::min<int32_t>(n_sim_streams(ev), n_pieces);
     if (L > 1) {
@@ -412,11 +435,12 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
         DP_HIP_TRY(hipStreamWaitEvent(ev->lane_streams[i - 1], ev->lane_events[0], 0));
     }
     for (int32_t j = 0; j < n_pieces; ++j) {
-      const int32_t b = j / pl->n_chunks, k = j % pl->n_chunks, lane = j % L;
+      const int32_t grp = j / pl->n_chunks, k = j % pl->n_chunks, lane = j % L;
+      const int32_t b = grp * pl->cols;  // first column of the group
       hipStream_t ls = lane == 0 ? s : ev->lane_streams[lane - 1];
       dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), ev->B, b};
       const uint64_t *stim = stim_all ? stim_all + (size_t)b * d->n_pi * pl->T : nullptr;
-      const dp::ChunkView cv = chunk_view(ev, *pl, k, lane);
+      const dp::ChunkView cv = chunk_view(ev, *pl, k, lane, grp);
       {
         SpanGuard sg(ev, SPAN_STIM, 0.0, prof, 1, ls);
         DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, sp, stim, pl->T, streams, ev->prm.seed, tune,
@@ -425,7 +449,8 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       const bool fuse = (j == 0);
       const int64_t nw = cv.u_hi - cv.u_lo;
       double bytes = 0.0;
-      for (int32_t l = 1; l <= d->depth; ++l) bytes += sim_level_bytes(d, l, nw, ev->B, fuse);
+      for (int32_t l = 1; l <= d->depth; ++l)
+        bytes += sim_level_bytes(d, l, nw, cv.n_cols, ev->B, fuse);
       // one span over the piece's level launches (their back-to-back time)
       SpanGuard sg(ev, SPAN_SIM, bytes, prof && d->depth > 0, d->depth + d->split_levels, ls);
       for (int32_t l = 1; l <= d->depth; ++l)
@@ -515,23 +540,25 @@ struct OutMap {
   }
 };
 
-// Capture the forward sweep into ev->graph_fwd.  The capture runs on a
-// private stream (the caller's stream may be the null stream, which cannot be
-// captured); the graph is then launched on the caller's stream.
-dp_status capture_forward(dp_eval *ev, const ChunkPlan *pl, uint64_t key) {
+// Capture what `enqueue` puts on the eval's stream into *exec.  The capture
+// runs on a private stream (the caller's stream may be the null stream,
+// which cannot be captured); the graph is then launched on the caller's
+// stream.  An older graph in *exec is destroyed once the stream drains.
+template <class F>
+dp_status capture_into(dp_eval *ev, hipGraphExec_t *exec, F &&enqueue) {
   if (!ev->capture_stream_owned)
     DP_HIP_TRY(hipStreamCreateWithFlags(&ev->capture_stream_owned, hipStreamNonBlocking));
-  if (ev->graph_fwd) {
+  if (*exec) {
     DP_HIP_TRY(hipStreamSynchronize(ev->stream()));  // no launch of the old graph in flight
-    (void)hipGraphExecDestroy(ev->graph_fwd);
-    ev->graph_fwd = nullptr;
+    (void)hipGraphExecDestroy(*exec);
+    *exec = nullptr;
   }
   hipStream_t s = ev->capture_stream_owned;
   DP_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   const bool prof = ev->profiling;
   ev->profiling = false;
   ev->capturing = true;  // stream() is the capture stream meanwhile
-  dp_status st = enqueue_forward(ev, pl);
+  dp_status st = enqueue();
   ev->capturing = false;
   ev->profiling = prof;
   hipGraph_t graph = nullptr;
@@ -541,12 +568,18 @@ dp_status capture_forward(dp_eval *ev, const ChunkPlan *pl, uint64_t key) {
     return st;
   }
   if (e != hipSuccess) return fail(DP_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&ev->graph_fwd, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    ev->graph_fwd = nullptr;
+    *exec = nullptr;
     return fail(DP_E_HIP, std::string("graph instantiate failed: ") + hipGetErrorString(e));
   }
+  return DP_OK;
+}
+
+// Capture the forward sweep into ev->graph_fwd.
+dp_status capture_forward(dp_eval *ev, const ChunkPlan *pl, uint64_t key) {
+  DP_TRY(capture_into(ev, &ev->graph_fwd, [&]() { return enqueue_forward(ev, pl); }));
   ev->graph_key = key;
   return DP_OK;
 }
@@ -576,6 +609,7 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
   mix((uint64_t)(uintptr_t)ev->stream());
   if (pl) {
     mix((uint64_t)pl->Tc);
+    mix((uint64_t)pl->cols);
     mix((uint64_t)pick_iters(ev, *pl));
     mix((uint64_t)n_sim_streams(ev));
   }
@@ -673,6 +707,34 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
   return DP_OK;
 }
 
+// The reverse sweep of run_backward: under DP_SCHED_GRAPH captured once
+// into ev->graph_bwd (re-captured when any launch argument changes) and
+// replayed, otherwise enqueued launch by launch.
+dp_status reverse_sweep(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
+  const dp_design *d = ev->d;
+  const int64_t launches = (int64_t)d->depth + d->split_levels + 1;
+  if (ev->schedule != DP_SCHED_GRAPH || ev->profiling || launches > kMaxGraphLaunches)
+    return enqueue_backward(ev, ba, dst);
+  uint64_t k = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
+  for (const void *ptr : {(const void *)ba.sp, (const void *)ba.beta, (const void *)ba.cap,
+                          (const void *)ba.w, (const void *)ba.size, (const void *)ba.contrib,
+                          (const void *)ba.lam, (const void *)ba.fixed, (const void *)dst,
+                          (const void *)ev->stream()})
+    mix((uint64_t)(uintptr_t)ptr);
+  uint32_t kb;
+  std::memcpy(&kb, &ba.kappa, 4);
+  mix(kb);
+  for (int32_t v : {ba.n_pi, ba.G, ba.B, ba.S, ba.C, ba.cdiv, ba.ste, ba.per_column, ba.paired})
+    mix((uint64_t)(uint32_t)v);
+  if (!ev->graph_bwd || ev->graph_bwd_key != k) {
+    DP_TRY(capture_into(ev, &ev->graph_bwd, [&]() { return enqueue_backward(ev, ba, dst); }));
+    ev->graph_bwd_key = k;
+  }
+  DP_HIP_TRY(hipGraphLaunch(ev->graph_bwd, ev->stream()));
+  return DP_OK;
+}
+
 }  // namespace
 
 namespace dp {
@@ -682,6 +744,7 @@ double kappa(const dp_params &p) { return kappa_of(p); }
 
 dp_eval::~dp_eval() {
   if (graph_fwd) (void)hipGraphExecDestroy(graph_fwd);
+  if (graph_bwd) (void)hipGraphExecDestroy(graph_bwd);
   if (capture_stream_owned) (void)hipStreamDestroy(capture_stream_owned);
   if (coop_stream) {
     (void)hipStreamSynchronize(coop_stream);
@@ -771,7 +834,7 @@ dp_status dp_compile(dp_ctx *ctx, const dp_netlist *netlist, dp_design **out) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(DP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
   }
-  return dp::compile_design(ctx, netlist, 0, nullptr, out);
+  return dp::compile_design(ctx, netlist, 0, nullptr, nullptr, out);
 }
 
 dp_status dp_compile_cells(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cells,
@@ -780,7 +843,25 @@ dp_status dp_compile_cells(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cel
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(DP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
   }
-  return dp::compile_design(ctx, netlist, n_cells, cells, out);
+  return dp::compile_design(ctx, netlist, n_cells, cells, nullptr, out);
+}
+
+dp_status dp_compile_library(dp_ctx *ctx, const dp_netlist *netlist, int32_t n_cells,
+                             const char *const *cells, const char *const *pins,
+                             dp_design **out) {
+  if (ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(DP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  return dp::compile_design(ctx, netlist, n_cells, cells, pins, out);
+}
+
+dp_status dp_design_cell_logic(const dp_design *d, int32_t *logic, int32_t *n_logic) {
+  if (!d) return fail(DP_E_INVALID, "dp_design_cell_logic: NULL design");
+  if (logic && !d->h_cell_logic.empty())
+    std::memcpy(logic, d->h_cell_logic.data(), sizeof(int32_t) * d->h_cell_logic.size());
+  if (n_logic) *n_logic = d->n_cells;
+  return DP_OK;
 }
 
 dp_status dp_design_info(const dp_design *d, dp_design_info_t *out) {
@@ -817,7 +898,7 @@ dp_status dp_eval_create(dp_design *d, int32_t n_cols, int32_t n_size, const dp_
   ev->B = n_cols;
   ev->S = n_size;
   ev->prm = *params;
-  dp_status st = ev->sp.alloc((size_t)d->n_nets * n_cols * 2 * sizeof(float));  // (p, 1-p)
+  dp_status st = ev->sp.alloc((size_t)d->n_nets * n_cols * sizeof(float));
   if (st == DP_OK) st = ev->cap.alloc((size_t)d->n_nets * sizeof(float));
   if (st == DP_OK && n_size > 0) st = ev->size.alloc((size_t)n_size * d->n_gates * sizeof(float));
   if (st != DP_OK) {
@@ -1019,8 +1100,15 @@ dp_status dp_eval_autotune(dp_eval *ev, int32_t reps, int32_t with_backward, dou
     const int64_t chunks[3] = {0, (T / 2 + 1) & ~1ll, (T / 4 + 1) & ~1ll};
     for (int k = 0; k < 3; ++k) {
       if (k > 0 && chunks[k] < 128) continue;
-      const int64_t pieces = (int64_t)ev->B * (k == 0 ? 1 : (T + chunks[k] - 1) / chunks[k]);
       for (int32_t lanes : {1, 2, 4}) {
+        const int64_t keep_chunk = ev->words_per_chunk;
+        const int32_t keep_lanes = ev->sim_streams;
+        ev->words_per_chunk = chunks[k];
+        ev->sim_streams = lanes;
+        const ChunkPlan cp = plan_chunks(ev);
+        ev->words_per_chunk = keep_chunk;
+        ev->sim_streams = keep_lanes;
+        const int64_t pieces = (int64_t)cp.n_groups * cp.n_chunks;  // independent pieces
         if (lanes > 1 && lanes > pieces) continue;
         if ((int64_t)lanes * ev->d->n_nets * 8 * (k == 0 ? T : chunks[k] + 2) > kAutoWordBudget)
           continue;
@@ -1089,6 +1177,13 @@ dp_status dp_eval_set_sim_streams(dp_eval *ev, int32_t sim_streams) {
   if (sim_streams < 0 || sim_streams > 16)
     return fail(DP_E_INVALID, "dp_eval_set_sim_streams: need 0 <= sim_streams <= 16");
   ev->sim_streams = sim_streams;
+  return DP_OK;
+}
+
+dp_status dp_eval_set_sim_columns(dp_eval *ev, int32_t columns) {
+  if (!ev) return fail(DP_E_INVALID, "dp_eval_set_sim_columns: NULL eval");
+  if (columns < 0) return fail(DP_E_INVALID, "dp_eval_set_sim_columns: need columns >= 0");
+  ev->sim_cols = columns;
   return DP_OK;
 }
 
@@ -1194,7 +1289,7 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
       DP_TRY(ev->pi_out.alloc(std::max<size_t>(bytes, 16)));
       dst = ev->pi_out.as<float>();
     }
-    DP_TRY(enqueue_backward(ev, ba, dst));
+    DP_TRY(reverse_sweep(ev, ba, dst));
     if (!on_device && bytes)
       DP_HIP_TRY(hipMemcpyAsync(dpi, dst, bytes, hipMemcpyDeviceToHost, s));
   }
@@ -1291,7 +1386,7 @@ dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, fl
   // v0, v1 = 1 - v0 and a two-cycle bit-parallel simulation of the pair
   DevBuf stim, words, v0_dev, p_dev, pv;
   DP_TRY(stim.alloc(std::max<size_t>(pb * 2 * sizeof(uint64_t), 16)));
-  DP_TRY(words.alloc((size_t)d->n_nets * 2 * sizeof(uint64_t)));
+  DP_TRY(words.alloc((size_t)B * d->n_nets * 2 * sizeof(uint64_t)));
   DP_TRY(v0_dev.alloc(std::max<size_t>(pb, 16)));
   DP_TRY(p_dev.alloc(std::max<size_t>(pb * sizeof(float), 16)));
   DP_TRY(pv.alloc(std::max<size_t>((size_t)B * sizeof(double), 16)));
@@ -1303,25 +1398,24 @@ dp_status dp_power_virus(dp_eval *ev, int32_t steps, double eta, uint8_t *v0, fl
   DP_HIP_TRY(dp::launch_fill_u32(ev->tog.as<uint32_t>(), (int64_t)nb, 0u, s));
   const dp::GraphView g = view(d);
   const dp::SimTune tune{1};
-  dp::ChunkView cv{};
+  dp::ChunkView cv{};  // every column's pair in one launch per level
   cv.W = words.as<uint64_t>();
   cv.pitch = 2;
+  cv.col_stride = (int64_t)d->n_nets * 2;
   cv.t_first = 0;
   cv.pairs = 1;
   cv.u_lo = 0;
   cv.u_hi = 2;
   cv.u_tog_lo = 1;
-  for (int32_t b = 0; b < B; ++b) {
-    const dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), B, b};
-    DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, ev->sp.as<float>(),
-                                   stim.as<uint64_t>() + (size_t)b * d->n_pi * 2, 2, nullptr, 0,
-                                   tune, s));
-    for (int32_t l = 1; l <= d->depth; ++l)
-      DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
-        DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, nullptr, cells, tune, s));
-        return DP_OK;
-      }));
-  }
+  cv.n_cols = B;
+  const dp::CountView cnt{ev->ones.as<uint32_t>(), ev->tog.as<uint32_t>(), B, 0};
+  DP_HIP_TRY(dp::launch_stimulus(g, cv, cnt, ev->sp.as<float>(), stim.as<uint64_t>(), 2, nullptr,
+                                 0, tune, s));
+  for (int32_t l = 1; l <= d->depth; ++l)
+    DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
+      DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, nullptr, cells, tune, s));
+      return DP_OK;
+    }));
   DP_HIP_TRY(dp::launch_virus_power(ev->tog.as<uint32_t>(), ev->cap.as<float>(), d->n_nets, B,
                                     pv.as<double>(), s));
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1844,7 +1938,9 @@ namespace dp {
 
 size_t lane_bytes(const dp_design *d, int32_t capacity) {
   const size_t nn = d->n_nets, G = d->n_gates, np = d->n_pi;
-  const size_t per_col = 4 * (4 * nn + (size_t)d->n_edges + 2 * G + 2 * np) +
+  // SP, beta and the per-net power term per net; contributions per edge;
+  // sizes (and their staging) per gate; probabilities (and staging, dP/dp)
+  const size_t per_col = 4 * (3 * nn + (size_t)d->n_edges + 2 * G + 2 * np) +
                          8 * (size_t)power_chunks(d->n_nets) + 16;
   return (size_t)capacity * per_col + 8 * nn;
 }
@@ -1866,7 +1962,7 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   auto A = [&](DevBuf &b, size_t bytes) {
     if (st == DP_OK) st = b.alloc(std::max<size_t>(bytes, 16));
   };
-  A(ev->sp, nn * capacity * 8);  // (p, 1-p) pairs
+  A(ev->sp, nn * capacity * 4);
   A(ev->cap, nn * 4);
   A(ev->size, (size_t)capacity * d->n_gates * 4);
   A(ev->size_stage, (size_t)capacity * d->n_gates * 4);

@@ -132,6 +132,40 @@ std::string compile_cell(const char *text, CellCode *out) {
   if (c.max_depth > kCellMaxStack) return "deeper than 8 stack entries";
   out->code = c.code;
   out->n_in = (int32_t)c.inputs.size();
+  out->inputs = c.inputs;
+  return "";
+}
+
+// Alg. 1's perm: the fan-in position of each input of a compiled cell given
+// its pin list (names separated by commas or blanks, in the order a gate
+// lists its fan-in).  perm[k] = pin position of input k (identifier k in
+// order of first appearance).  Returns an error message, or "".
+std::string pin_permutation(const CellCode &cc, const char *pins, std::vector<int32_t> *perm) {
+  std::vector<std::string> names;
+  std::string cur;
+  for (const char *q = pins;; ++q) {
+    const char ch = *q;
+    if (ch == ',' || ch == ' ' || ch == '\t' || ch == 0) {
+      if (!cur.empty()) names.push_back(cur);
+      cur.clear();
+      if (!ch) break;
+    } else if (std::isalnum((unsigned char)ch) || ch == '_') {
+      cur += ch;
+    } else {
+      return std::string("bad character '") + ch + "' in the pin list";
+    }
+  }
+  if ((int32_t)names.size() != cc.n_in)
+    return "the pin list names " + std::to_string(names.size()) + " pins; the function reads " +
+           std::to_string(cc.n_in);
+  perm->assign(cc.n_in, -1);
+  for (int32_t j = 0; j < (int32_t)names.size(); ++j) {
+    const auto it = std::find(cc.inputs.begin(), cc.inputs.end(), names[j]);
+    if (it == cc.inputs.end()) return "pin " + names[j] + " is not read by the function";
+    int32_t &slot = (*perm)[it - cc.inputs.begin()];
+    if (slot >= 0) return "pin " + names[j] + " is listed twice";
+    slot = j;
+  }
   return "";
 }
 

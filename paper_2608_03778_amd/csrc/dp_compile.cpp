@@ -48,27 +48,45 @@ static dp_status upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
 }
 
 dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
-                         const char *const *cells, dp_design **out) {
+                         const char *const *cells, const char *const *pins, dp_design **out) {
   if (!ctx || !nl || !out) return fail(DP_E_INVALID, "dp_compile: NULL argument");
   if (n_cells < 0 || n_cells > 256 - kCellBase || (n_cells > 0 && !cells))
     return fail(DP_E_INVALID, "dp_compile: need 0 <= n_cells <= 240 and a cell array");
-  // library cells: compile each expression; an expression that is one of
-  // the fixed cells runs as that cell
+  // library cells (Alg. 1): compile each expression; map each pin list onto
+  // the expression's inputs (perm: the fan-in position of input k); an
+  // expression that is one of the fixed cells runs as that cell; the others
+  // share one logic id per distinct code (dedup), and the kernels see logic
+  // ids only
   std::vector<CellCode> lib(n_cells);
-  std::vector<int> as_fixed(n_cells, -1);
+  std::vector<std::vector<int32_t>> perm(n_cells);
+  std::vector<int> as_fixed(n_cells, -1), logic(n_cells, -1);
+  std::vector<int32_t> logic_cell;  // a cell of each logic id
   for (int32_t c = 0; c < n_cells; ++c) {
-    const std::string err = compile_cell(cells[c], &lib[c]);
+    std::string err = compile_cell(cells[c], &lib[c]);
+    if (err.empty() && pins && pins[c]) err = pin_permutation(lib[c], pins[c], &perm[c]);
     if (!err.empty())
       return fail(DP_E_INVALID, "dp_compile: cell " + std::to_string(c) + ": " + err);
+    if (perm[c].empty()) {
+      perm[c].resize(lib[c].n_in);
+      std::iota(perm[c].begin(), perm[c].end(), 0);
+    }
     as_fixed[c] = fixed_op_of(lib[c]);
+    if (as_fixed[c] >= 0) continue;
+    int32_t id = 0;
+    while (id < (int32_t)logic_cell.size() && lib[logic_cell[id]].code != lib[c].code) ++id;
+    if (id == (int32_t)logic_cell.size()) logic_cell.push_back(c);
+    logic[c] = id;
   }
+  const int32_t n_logic = (int32_t)logic_cell.size();
   auto arity_of_op = [&](int op) -> int {
     if (op < DP_N_OPS) return kArity[op];
     if (op >= kCellBase && op - kCellBase < n_cells) return lib[op - kCellBase].n_in;
     return -1;
   };
   auto internal_op = [&](int op) -> int {
-    return (op >= kCellBase && as_fixed[op - kCellBase] >= 0) ? as_fixed[op - kCellBase] : op;
+    if (op < kCellBase) return op;
+    const int c = op - kCellBase;
+    return as_fixed[c] >= 0 ? as_fixed[c] : kCellBase + logic[c];
   };
   const int32_t n_pi = nl->n_pi, G = nl->n_gates;
   if (n_pi < 0 || G < 0) return fail(DP_E_INVALID, "dp_compile: negative size");
@@ -206,23 +224,30 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
     d->h_int2ext[n_pi + gi] = n_pi + gate_of[gi];
     d->h_ext2int[n_pi + gate_of[gi]] = n_pi + gi;
   }
-  int32_t pins = 3;
-  for (int32_t g = 0; g < G; ++g) pins = std::max(pins, arity_of_op(nl->op[g]));
-  d->pins = pins;
-  d->n_cells = n_cells;
+  int32_t pins_max = 3;
+  for (int32_t g = 0; g < G; ++g) pins_max = std::max(pins_max, arity_of_op(nl->op[g]));
+  const int32_t pins_rows = pins_max;
+  d->pins = pins_max;
+  d->n_cells = n_logic;
+  d->h_cell_logic.resize(n_cells);
+  for (int32_t c = 0; c < n_cells; ++c)
+    d->h_cell_logic[c] = as_fixed[c] >= 0 ? -1 - as_fixed[c] : logic[c];
   d->h_op.resize(G);
   d->h_arity_prefix.assign(G + 1, 0);
-  std::vector<int32_t> in((size_t)pins * G, 0);
+  std::vector<int32_t> in((size_t)pins_rows * G, 0);
   std::vector<int32_t> rev_ptr(n_nets + 1, 0), rev_edge(n_edges);
   for (int32_t gi = 0; gi < G; ++gi) {
     int32_t g = gate_of[gi];
     d->h_op[gi] = (uint8_t)internal_op(nl->op[g]);
     int32_t k = nl->fanin_ptr[g + 1] - nl->fanin_ptr[g];
     d->h_arity_prefix[gi + 1] = d->h_arity_prefix[gi] + k;
-    for (int32_t j = 0; j < pins; ++j) {
+    // a library cell's input j comes from fan-in position perm[j] (its pin
+    // list); fixed cells read their pins in order
+    const int32_t *pm = nl->op[g] >= kCellBase ? perm[nl->op[g] - kCellBase].data() : nullptr;
+    for (int32_t j = 0; j < pins_rows; ++j) {
       // unused pins alias pin 0 so that no index is ever out of range
-      int32_t e = nl->fanin_ptr[g] + (j < k ? j : 0);
-      in[(size_t)j * G + gi] = d->h_ext2int[nl->fanin[e]];
+      const int32_t pos = j < k ? (pm ? pm[j] : j) : (pm ? pm[0] : 0);
+      in[(size_t)j * G + gi] = d->h_ext2int[nl->fanin[nl->fanin_ptr[g] + pos]];
     }
     for (int32_t j = 0; j < k; ++j) ++rev_ptr[in[(size_t)j * G + gi] + 1];
   }
@@ -241,7 +266,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   // slot[j][g'] = where pin j of gate g' sits in its source net's fan-out
   // list: the reverse sweep writes a pin's contribution there, so a net sums
   // one contiguous range
-  std::vector<int32_t> slot((size_t)pins * G, 0);
+  std::vector<int32_t> slot((size_t)pins_rows * G, 0);
   for (int64_t e = 0; e < n_edges; ++e) slot[rev_edge[e]] = (int32_t)e;
   d->lvl_pins.assign(depth + 1, 0);
   d->lvl_fanout.assign(depth + 1, 0);
@@ -265,18 +290,19 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
     }
     if (f > g0 && f < g1) ++d->split_levels;
   }
-  // cell code, each cell's padded to kCellMaxCode words (64 bytes, so a lane
-  // loads it whole with four aligned 16-byte loads), and the cell table
-  std::vector<uint16_t> code((size_t)std::max(n_cells, 1) * kCellMaxCode, 0);
-  std::vector<int32_t> cell_tab(3 * (size_t)std::max(n_cells, 1), 0);
-  for (int32_t c = 0; c < n_cells; ++c) {
-    cell_tab[3 * c] = c * kCellMaxCode;
-    cell_tab[3 * c + 1] = (int32_t)lib[c].code.size();
-    cell_tab[3 * c + 2] = lib[c].n_in;
-    std::copy(lib[c].code.begin(), lib[c].code.end(), code.begin() + (size_t)c * kCellMaxCode);
+  // code of each logic id, padded to kCellMaxCode words (64 bytes, so a lane
+  // loads it whole with four aligned 16-byte loads), and the logic table
+  std::vector<uint16_t> code((size_t)std::max(n_logic, 1) * kCellMaxCode, 0);
+  std::vector<int32_t> cell_tab(3 * (size_t)std::max(n_logic, 1), 0);
+  std::vector<uint64_t> tt((size_t)std::max(n_logic, 1), 0);
+  for (int32_t id = 0; id < n_logic; ++id) {
+    const CellCode &cc = lib[logic_cell[id]];
+    cell_tab[3 * id] = id * kCellMaxCode;
+    cell_tab[3 * id + 1] = (int32_t)cc.code.size();
+    cell_tab[3 * id + 2] = cc.n_in;
+    std::copy(cc.code.begin(), cc.code.end(), code.begin() + (size_t)id * kCellMaxCode);
+    tt[id] = truth_table(cc);
   }
-  std::vector<uint64_t> tt((size_t)std::max(n_cells, 1), 0);
-  for (int32_t c = 0; c < n_cells; ++c) tt[c] = truth_table(lib[c]);
   hipStream_t s = ctx->stream;
   dp_status st = DP_OK;
   if ((st = upload(d->code, code, s)) != DP_OK || (st = upload(d->cell, cell_tab, s)) != DP_OK ||

@@ -15,6 +15,7 @@ struct dp_eval {
   int64_t words_per_chunk = 0;
   int32_t sim_iters = 0;
   int32_t sim_streams = 0;                 // 0 = automatic (1)
+  int32_t sim_cols = 0;                    // columns per simulation launch, 0 = what the budget holds
   std::vector<hipStream_t> lane_streams;   // extra simulation streams (owned)
   std::vector<hipEvent_t> lane_events;     // fork + one join per extra stream
   // inputs
@@ -80,6 +81,8 @@ struct dp_eval {
   // captured sweeps
   hipGraphExec_t graph_fwd = nullptr;
   uint64_t graph_key = 0;
+  hipGraphExec_t graph_bwd = nullptr;  // the reverse sweep of dp_backward
+  uint64_t graph_bwd_key = 0;
   ~dp_eval();
 };
 

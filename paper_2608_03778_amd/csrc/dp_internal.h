@@ -52,9 +52,13 @@ struct DevBuf {
 struct CellCode {
   std::vector<uint16_t> code;
   int32_t n_in = 0;
+  std::vector<std::string> inputs;  // identifiers in order of first appearance (IN index)
 };
 // Compile one expression; returns an error message, or "" on success.
 std::string compile_cell(const char *text, CellCode *out);
+// Fan-in position of each input of a compiled cell from its pin list
+// (Alg. 1's perm); returns an error message, or "".
+std::string pin_permutation(const CellCode &cc, const char *pins, std::vector<int32_t> *perm);
 // The fixed cell (DP_INV ..) a compiled expression equals, or -1.
 int fixed_op_of(const CellCode &cc);
 // Truth table of a compiled cell: bit m is the cell's output when input k
@@ -100,7 +104,10 @@ struct dp_design {
   bool has_cell_gates = false;
   // device arrays
   int32_t pins = 3;      // rows of `in` and `slot`: 3, or the widest library cell
-  int32_t n_cells = 0;   // library cells of the design
+  int32_t n_cells = 0;   // distinct library-cell logics of the design (after dedup)
+  // per library cell of the caller: its logic id (>= 0), or -1 - op for a
+  // cell that runs as fixed cell op
+  std::vector<int32_t> h_cell_logic;
   dp::DevBuf op;        // uint8 [n_gates]
   dp::DevBuf in;        // int32 [pins][n_gates] input net of pin j (SoA)
   dp::DevBuf rev_ptr;   // int32 [n_nets + 1] fan-out list offsets
@@ -156,8 +163,10 @@ dp_status static_scratch_init(int device);
 
 // Host-side compile: validation, levelization, sort, renumbering and the
 // device upload.  Implemented in dp_compile.cpp.
+// pins: per cell, the pin names in a gate's fan-in order (null = the
+// expression's inputs in order of first appearance).
 dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
-                         const char *const *cells, dp_design **out);
+                         const char *const *cells, const char *const *pins, dp_design **out);
 
 void ctx_retain(dp_ctx *c);
 void ctx_release(dp_ctx *c);

@@ -31,31 +31,37 @@ struct GraphView {
   int32_t n_pi, G, n_nets;
 };
 
-// Simulation word buffer: row r (an internal net) holds words
-// [t0 - halo, t0 - halo + pitch) of the current chunk at W + r * pitch.
-// Local word u counts ones when u in [u_lo, u_hi) and toggles (against
-// word u - 1) when u in [u_tog_lo, u_hi).
+// Simulation word buffers of the query columns a launch covers: column
+// cnt.col + c has its own buffer at W + c * col_stride, whose row r (an
+// internal net) holds words [t0 - halo, t0 - halo + pitch) of the current
+// chunk at r * pitch.  Local word u counts ones when u in [u_lo, u_hi) and
+// toggles (against word u - 1) when u in [u_tog_lo, u_hi).
 struct ChunkView {
   uint64_t *W;
   int64_t pitch;       // words per row (even)
+  int64_t col_stride;  // words between the buffers of consecutive columns
   int64_t t_first;     // global cycle of local word 0 (t0 - halo)
   int32_t pairs;       // word pairs per row to compute, ceil(u_hi / 2)
   int32_t u_lo, u_hi, u_tog_lo;
+  int32_t n_cols;      // columns of the launch, cnt.col .. cnt.col + n_cols - 1
 };
 
-// Counter arrays [n_nets][B]; this launch adds into column `col`.
+// Counter arrays [n_nets][B]; a launch adds into columns cnt.col onwards.
 struct CountView {
   uint32_t *ones, *tog;
   int32_t B, col;
 };
 
-// Signal probabilities are stored as pairs (p, q = 1 - p) per net and
-// column, [n_nets][B][2]: every cell rule has a form without cancellation
-// for both, so TR = 2 p q keeps its relative accuracy when p is near 0 or 1.
+// Signal probabilities are stored as one float per net and column,
+// [n_nets][B]: the smaller of p and q = 1 - p, negated when it is q.  The
+// kernels work on the pair (p, q): every cell rule has a form without
+// cancellation for both, so TR = 2 p q keeps its relative accuracy when p is
+// near 0 or 1, and the larger of the two is always 1 minus the smaller, so
+// the one float holds the pair exactly.
 
 // SP of one level of B columns, optionally fused into a simulation launch.
 struct SpLevel {
-  float *sp;          // [n_nets][B][2]
+  float *sp;          // [n_nets][B]
   int32_t B;
   int32_t g0, n;      // level gate range (internal ids)
 };
@@ -68,7 +74,7 @@ struct SimTune {
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 
-// PI probabilities [B][n_pi] (caller layout) -> SP pairs [n_pi][B][2].
+// PI probabilities [B][n_pi] (caller layout) -> stored SP [n_pi][B].
 hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t s);
 // Check values are finite and inside [lo, hi]; sets *bad = 1 otherwise.
 hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
@@ -89,21 +95,23 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
 // fixed cells).
 hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t s);
 
-// PI rows of one chunk: Philox stimulus (stim == nullptr) or explicit words
-// stim[i][T]; counts ones/toggles of the PI nets.
+// PI rows of one chunk for the launch's columns: Philox stimulus (stim ==
+// nullptr) or explicit words stim[c][i][T] (c counted from column cnt.col);
+// counts ones/toggles of the PI nets.
 // stream [n_pi]: the Philox stream of each PI (null = its own index).
 hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
-                           const float *p_col /* SP pairs [n_pi][B][2], column cnt.col */,
+                           const float *p_col /* stored SP [n_pi][B] */,
                            const uint64_t *stim, int64_t T, const int32_t *stream, uint64_t seed,
                            const SimTune &tune, hipStream_t s);
-// Markov stimulus words out [B][n_pi][T] from the PI probabilities (SP pairs
-// [n_pi][B][2]), the target transition rates tau [B][n_pi] and the streams
+// Markov stimulus words out [B][n_pi][T] from the PI probabilities (stored
+// SP [n_pi][B]), the target transition rates tau [B][n_pi] and the streams
 // (null = own).
 hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
                                int32_t n_pi, int32_t B, int64_t T, uint64_t seed, uint64_t *out,
                                hipStream_t s);
 
-// One simulation level of one chunk, with the level's SP fused in when
+// One simulation level of one chunk for the launch's columns, with the
+// level's SP (every column of the SpLevel) fused in when
 // sp != nullptr (fixed cells only: a library-cell range takes its SP from
 // launch_sp_level).
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
@@ -113,7 +121,7 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
 // Finalize per internal net and column: beta, X = kappa*beta*TR_model, the
 // local adjoint seed base, optional caller-numbered exports.
 struct FinalizeArgs {
-  const float *sp;          // [n_nets][B][2]
+  const float *sp;          // [n_nets][B]
   const uint32_t *ones, *tog;  // [n_nets][B] or null (modeled)
   const float *beta_frozen; // [n_nets][B], or [n_nets] when beta_shared, or null
   int32_t beta_shared;      // one frozen beta for every column
@@ -129,7 +137,7 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
 // Caller-numbered exports of forward quantities, [B][n_nets].
 struct ExportArgs {
-  const float *sp;            // [n_nets][B][2]
+  const float *sp;            // [n_nets][B]
   const float *beta;
   const uint32_t *ones, *tog;
   const int32_t *int2ext;
@@ -162,7 +170,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s);
 //   per_column: w[c] s_{c mod S'}(n);  paired: w[b] s_b(n);
 //   otherwise (contracted): sum_s w[b][s] s_s(n).
 struct BwdArgs {
-  const float *sp;            // [n_nets][B][2]
+  const float *sp;            // [n_nets][B]
   const float *beta;          // [n_nets][B], or null (beta = 1)
   const float *cap;           // [n_nets] internal
   const float *w;             // [B][S'] (null = 1)
@@ -212,7 +220,7 @@ hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const in
                                      hipStream_t s);
 
 // Power-virus ascent (Alg. 4): P <- clip(P + eta * grad) on the PI rows of
-// the SP pairs [n_pi][B]; grad is [B][n_pi].
+// the stored SP [n_pi][B]; grad is [B][n_pi].
 hipError_t launch_virus_step(float *sp, const float *grad, float eta, int32_t n_pi, int32_t B,
                              hipStream_t s);
 // v0 = [P >= 1/2] ([B][n_pi] bytes), P ([B][n_pi] floats, or null) and the

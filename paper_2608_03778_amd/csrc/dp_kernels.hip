@@ -1,7 +1,7 @@
 // gfx950 kernels of the DiffPower hot path.
 //
 // Layouts (internal net numbering, see dp_design):
-//   SP (p, 1 - p pairs)            float2 [n_nets][B]      (query column innermost)
+//   SP (packed, see sp_load)       float  [n_nets][B]      (query column innermost)
 //   beta                           float  [n_nets][B]      (absent when modeled)
 //   xterm                          float  [B][n_nets]      (net innermost: the power
 //                                                          and gradient reductions
@@ -48,13 +48,26 @@ __device__ __forceinline__ int arity_of(int op) { return op < AND2 ? 1 : (op < A
 
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
 
+// A net's probability is stored as one float: the smaller of p and q =
+// 1 - p, negated when it is q (sign bit set: p is the larger, so p = 1 is
+// -0.0).  The larger is always 1 minus the smaller (settle() makes it so for
+// gate outputs, and for a startpoint p >= 1/2 the difference 1 - p is exact),
+// so the (p, q) pair the rules work on comes back bit for bit from 4 bytes.
+__device__ __forceinline__ f2 sp_load(float s) {
+  const float m = fabsf(s);
+  return (__float_as_uint(s) >> 31) ? f2{1.0f - m, m} : f2{m, 1.0f - m};
+}
+
+// A startpoint probability in the stored form.
+__device__ __forceinline__ float sp_pack(float p) { return p <= 0.5f ? p : -(1.0f - p); }
+
 // Clip to [0, 1] (Alg. 2) and re-tie the pair: the smaller of p and q comes
 // from its own formula (full relative accuracy), the larger is 1 minus it.
 // Without this, rounding drift of p + q - 1 adds up along reconvergent
-// paths and grows with the number of paths.
-__device__ __forceinline__ f2 settle(f2 v) {
+// paths and grows with the number of paths.  Returns the stored form.
+__device__ __forceinline__ float settle(f2 v) {
   const float p = clamp01(v.x), q = clamp01(v.y);
-  return p <= q ? f2{p, 1.0f - p} : f2{1.0f - q, q};
+  return p <= q ? p : -q;
 }
 
 // Probability that the cell output is 1, and its complement, for
@@ -163,52 +176,57 @@ __device__ f2 cell_sp(const LaneCode &lc, const f2 *x) {
   return st[0];
 }
 
-// Reverse mode over the code (Alg. 3): the forward pass keeps each binary
-// operation's operands, the backward pass walks the code in reverse with a
-// stack of output gradients (a binary operation replaces its gradient by its
-// operands', the right operand's on top; NOT negates; an input adds to its
-// partial; a constant drops its gradient).
+// Partial derivatives of a cell's probability with respect to its inputs
+// (Sec. III-E, Alg. 3), by reverse mode over the code read as a tape.  The
+// forward pass gives every instruction its value and records, for each
+// operation, which instructions produced its operands (the stack holds
+// instruction indices).  Every value feeds exactly one later instruction
+// (the code is a tree), so the backward pass visits the instructions from
+// the last to the first with each adjoint complete when reached: an
+// operation hands its adjoint to its operands' instructions times the local
+// derivative (AND: the other operand; OR: its complement; XOR: q - p of the
+// other operand; NOT: -1), and an input instruction adds its adjoint to the
+// input's partial.
 __device__ void cell_partials(const LaneCode &lc, const f2 *x, float *d) {
-  f2 st[kCellMaxStack], ta[kCellMaxCode], tb[kCellMaxCode];
-  float gs[kCellMaxStack + 1];
+  f2 val[kCellMaxCode];
+  float adj[kCellMaxCode];
+  uint8_t lhs[kCellMaxCode], rhs[kCellMaxCode];
+  uint8_t st[kCellMaxStack];
   int top = 0;
-  for (int k = 0; k < lc.nin; ++k) d[k] = 0.0f;
   for (int i = 0; i < lc.len; ++i) {
     const int w = code_at(lc, i), op = w & 0xff;
+    adj[i] = 0.0f;
     if (op == kCellIn) {
-      st[top++] = x[w >> 8];
+      val[i] = x[w >> 8];
     } else if (op == kCellZero) {
-      st[top++] = f2{0.0f, 1.0f};
+      val[i] = f2{0.0f, 1.0f};
     } else if (op == kCellOne) {
-      st[top++] = f2{1.0f, 0.0f};
+      val[i] = f2{1.0f, 0.0f};
     } else if (op == kCellNot) {
-      st[top - 1] = f2{st[top - 1].y, st[top - 1].x};
+      lhs[i] = st[--top];
+      val[i] = f2{val[lhs[i]].y, val[lhs[i]].x};
     } else {
-      const f2 b = st[--top];
-      const f2 a = st[--top];
-      ta[i] = a;
-      tb[i] = b;
-      st[top++] = pair_op(op, a, b);
+      rhs[i] = st[--top];
+      lhs[i] = st[--top];
+      val[i] = pair_op(op, val[lhs[i]], val[rhs[i]]);
     }
+    st[top++] = (uint8_t)i;
   }
-  int gt = 0;
-  gs[gt++] = 1.0f;
+  for (int k = 0; k < lc.nin; ++k) d[k] = 0.0f;
+  adj[lc.len - 1] = 1.0f;
   for (int i = lc.len - 1; i >= 0; --i) {
     const int w = code_at(lc, i), op = w & 0xff;
-    const float gr = gs[--gt];
+    const float a = adj[i];
     if (op == kCellIn) {
-      d[w >> 8] += gr;
+      d[w >> 8] += a;
     } else if (op == kCellNot) {
-      gs[gt++] = -gr;
-    } else if (op == kCellAnd) {
-      gs[gt++] = gr * tb[i].x;  // d(ab)/da = b
-      gs[gt++] = gr * ta[i].x;
-    } else if (op == kCellOr) {
-      gs[gt++] = gr * tb[i].y;  // d(a + b - ab)/da = 1 - b
-      gs[gt++] = gr * ta[i].y;
-    } else if (op == kCellXor) {
-      gs[gt++] = gr * (tb[i].y - tb[i].x);  // 1 - 2b
-      gs[gt++] = gr * (ta[i].y - ta[i].x);
+      adj[lhs[i]] -= a;
+    } else if (op == kCellAnd || op == kCellOr || op == kCellXor) {
+      const f2 u = val[lhs[i]], v = val[rhs[i]];
+      const float du = op == kCellAnd ? v.x : (op == kCellOr ? v.y : v.y - v.x);
+      const float dv = op == kCellAnd ? u.x : (op == kCellOr ? u.y : u.y - u.x);
+      adj[lhs[i]] += a * du;
+      adj[rhs[i]] += a * dv;
     }
   }
 }
@@ -262,8 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_load_pi(const float *__restrict__ p,
   int64_t idx = gidx();
   if (idx >= (int64_t)n_pi * B) return;
   int32_t i = (int32_t)(idx / B), b = (int32_t)(idx - (int64_t)i * B);
-  const float v = p[(int64_t)b * n_pi + i];
-  reinterpret_cast<f2 *>(sp)[idx] = f2{v, 1.0f - v};  // exact for v >= 1/2
+  sp[idx] = sp_pack(p[(int64_t)b * n_pi + i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_range(const float *__restrict__ v, int64_t n,
@@ -333,13 +350,13 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int32_t b = (int32_t)(idx - gl32 * (uint32_t)B);
   const int32_t gi = lv.g0 + gl;
   const int op = g.op[gi];
-  f2 *sp = reinterpret_cast<f2 *>(lv.sp);
+  float *sp = lv.sp;
   if constexpr (CELLS) {
     const LaneCode lc = lane_code(g, op);
     // every pin row (unused pins alias pin 0), so the gathers need no count
     f2 x[kCellMaxIn];
     for (int k = 0; k < kCellMaxIn; ++k)
-      x[k] = k < g.pins ? sp[(int64_t)g.in[k * g.G + gi] * B + b] : f2{0.0f, 1.0f};
+      x[k] = k < g.pins ? sp_load(sp[(int64_t)g.in[k * g.G + gi] * B + b]) : f2{0.0f, 1.0f};
     sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(lc, x));
     return;
   }
@@ -349,13 +366,14 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int32_t i1 = pin_row(g.in, g, 1)[gi];
   const int32_t i2 = pin_row(g.in, g, 2)[gi];
   gathers_done(op, i0, i1, i2);
-  const f2 a = sp[(int64_t)i0 * B + b];
-  const f2 bv = sp[(int64_t)i1 * B + b];
-  const f2 cv = sp[(int64_t)i2 * B + b];
-  gathers_done(a.x, a.y, bv.x, bv.y, cv.x, cv.y);
+  const float sa = sp[(int64_t)i0 * B + b];
+  const float sb = sp[(int64_t)i1 * B + b];
+  const float sc = sp[(int64_t)i2 * B + b];
+  gathers_done(sa, sb, sc);
   const int k = arity_of(op);
   const f2 z = f2{0.0f, 1.0f};
-  sp[(int64_t)(g.n_pi + gi) * B + b] = settle(sp_rule(op, a, k > 1 ? bv : z, k > 2 ? cv : z));
+  sp[(int64_t)(g.n_pi + gi) * B + b] =
+      settle(sp_rule(op, sp_load(sa), k > 1 ? sp_load(sb) : z, k > 2 ? sp_load(sc) : z));
 }
 
 __global__ __launch_bounds__(kLevelBlock) void k_sp_level(GraphView g, SpLevel lv) {
@@ -368,9 +386,9 @@ __global__ __launch_bounds__(kBlock) void k_sp_cells(GraphView g, SpLevel lv) {
   if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item<true>(g, lv, idx);
 }
 
-// The same for an even column count, two columns per lane: one 16-byte
-// access moves two (p, q) pairs, and half as many waves cover the level.
-typedef float f4 __attribute__((ext_vector_type(4)));
+// The same for an even column count, two columns per lane: one 8-byte
+// access moves two stored probabilities, and half as many waves cover the
+// level.
 
 __global__ __launch_bounds__(kLevelBlock) void k_sp_level_x2(GraphView g, SpLevel lv) {
   const uint32_t idx = blockIdx.x * kLevelBlock + threadIdx.x;
@@ -381,22 +399,22 @@ __global__ __launch_bounds__(kLevelBlock) void k_sp_level_x2(GraphView g, SpLeve
   const int32_t gi = lv.g0 + (int32_t)gl;
   const int op = g.op[gi];
   const int k = arity_of(op);
-  const f4 *sp4 = reinterpret_cast<const f4 *>(lv.sp);
+  const f2 *sp2 = reinterpret_cast<const f2 *>(lv.sp);
   const int64_t B2 = lv.B / 2;
-  const f4 z = f4{0.0f, 1.0f, 0.0f, 1.0f};
+  const f2 z = f2{0.0f, 1.0f};
   const int32_t i0 = g.in[gi];
   const int32_t i1 = pin_row(g.in, g, 1)[gi];
   const int32_t i2 = pin_row(g.in, g, 2)[gi];
   gathers_done(op, i0, i1, i2);
-  const f4 a = sp4[(int64_t)i0 * B2 + b / 2];
-  const f4 bl = sp4[(int64_t)i1 * B2 + b / 2];
-  const f4 cl = sp4[(int64_t)i2 * B2 + b / 2];
-  gathers_done(a.x, a.y, a.z, a.w, bl.x, bl.y, bl.z, bl.w, cl.x, cl.y, cl.z, cl.w);
-  const f4 bb = k > 1 ? bl : z;
-  const f4 cc = k > 2 ? cl : z;
-  const f2 r0 = settle(sp_rule(op, f2{a.x, a.y}, f2{bb.x, bb.y}, f2{cc.x, cc.y}));
-  const f2 r1 = settle(sp_rule(op, f2{a.z, a.w}, f2{bb.z, bb.w}, f2{cc.z, cc.w}));
-  reinterpret_cast<f4 *>(lv.sp)[(int64_t)(g.n_pi + gi) * B2 + b / 2] = f4{r0.x, r0.y, r1.x, r1.y};
+  const f2 a = sp2[(int64_t)i0 * B2 + b / 2];
+  const f2 bl = sp2[(int64_t)i1 * B2 + b / 2];
+  const f2 cl = sp2[(int64_t)i2 * B2 + b / 2];
+  gathers_done(a.x, a.y, bl.x, bl.y, cl.x, cl.y);
+  const float r0 = settle(sp_rule(op, sp_load(a.x), k > 1 ? sp_load(bl.x) : z,
+                                  k > 2 ? sp_load(cl.x) : z));
+  const float r1 = settle(sp_rule(op, sp_load(a.y), k > 1 ? sp_load(bl.y) : z,
+                                  k > 2 ? sp_load(cl.y) : z));
+  reinterpret_cast<f2 *>(lv.sp)[(int64_t)(g.n_pi + gi) * B2 + b / 2] = f2{r0, r1};
 }
 
 // ---------------------------------------------------------------- simulation
@@ -556,17 +574,22 @@ __global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t task = (int64_t)blockIdx.x * kSimWaves + wave;
-  if (task >= (int64_t)n * waves_per_row) return;
-  const int32_t gl = (int32_t)(task / waves_per_row);
-  const int32_t seg = (int32_t)(task - (int64_t)gl * waves_per_row);
+  // tasks: (column, gate, run of word pairs), column outermost
+  const int64_t per_col = (int64_t)n * waves_per_row;
+  if (task >= per_col * c.n_cols) return;
+  const int32_t lc = (int32_t)(task / per_col);
+  const int64_t rest = task - (int64_t)lc * per_col;
+  const int32_t gl = (int32_t)(rest / waves_per_row);
+  const int32_t seg = (int32_t)(rest - (int64_t)gl * waves_per_row);
   const int32_t gi = g0 + gl;
   const int op = __builtin_amdgcn_readfirstlane((int)g.op[gi]);
   const int64_t pp = c.pitch / 2;  // pairs per row
-  const w2 *W = reinterpret_cast<const w2 *>(c.W);
+  uint64_t *Wc = c.W + (int64_t)lc * c.col_stride;
+  const w2 *W = reinterpret_cast<const w2 *>(Wc);
   const w2 *r0 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[gi]) * pp;
   const w2 *r1 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[g.G + gi]) * pp;
   const w2 *r2 = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[2 * g.G + gi]) * pp;
-  w2 *out = reinterpret_cast<w2 *>(c.W) + (int64_t)(g.n_pi + gi) * pp;
+  w2 *out = reinterpret_cast<w2 *>(Wc) + (int64_t)(g.n_pi + gi) * pp;
   // a net with no readers needs its counts only: its words are not stored
   const int32_t on = g.n_pi + gi;
   const bool keep = __builtin_amdgcn_readfirstlane(g.rev_ptr[on + 1]) >
@@ -591,7 +614,7 @@ __global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView 
   ones = wave_sum(ones);
   togs = wave_sum(togs);
   if (lane == 0) {
-    const int64_t o = (int64_t)(g.n_pi + gi) * cnt.B + cnt.col;
+    const int64_t o = (int64_t)(g.n_pi + gi) * cnt.B + cnt.col + lc;
     if (ones) atomicAdd(cnt.ones + o, ones);
     if (togs) atomicAdd(cnt.tog + o, togs);
   }
@@ -699,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_markov_words(const float *__restrict
   const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + wave;  // b * n_pi + i
   if (row >= (int64_t)B * n_pi) return;
   const int32_t b = (int32_t)(row / n_pi), i = (int32_t)(row - (int64_t)b * n_pi);
-  const float p = sp[((int64_t)i * B + b) * 2];
+  const float p = sp_load(sp[(int64_t)i * B + b]).x;
   double rise, stay;
   markov_probs(p, tau[(int64_t)b * n_pi + i], rise, stay);
   const uint64_t thr_p = prob_threshold(p), thr_rise = threshold_d(rise),
@@ -760,18 +783,23 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  if (task >= (int64_t)n_pi * waves_per_row) return;
-  const int32_t i = (int32_t)(task / waves_per_row);
-  const int32_t seg = (int32_t)(task - (int64_t)i * waves_per_row);
-  const uint64_t thr = prob_threshold(p_rows[((int64_t)i * cnt.B + cnt.col) * 2]);
-  const uint64_t *srow = stim ? stim + (int64_t)i * T : nullptr;
+  // tasks: (column, PI, run of word pairs), column outermost
+  const int64_t per_col = (int64_t)n_pi * waves_per_row;
+  if (task >= per_col * c.n_cols) return;
+  const int32_t lc = (int32_t)(task / per_col);
+  const int64_t rest = task - (int64_t)lc * per_col;
+  const int32_t i = (int32_t)(rest / waves_per_row);
+  const int32_t seg = (int32_t)(rest - (int64_t)i * waves_per_row);
+  const int32_t col = cnt.col + lc;
+  const uint64_t thr = prob_threshold(sp_load(p_rows[(int64_t)i * cnt.B + col]).x);
+  const uint64_t *srow = stim ? stim + ((int64_t)lc * n_pi + i) * T : nullptr;
   const uint32_t si = stream ? (uint32_t)stream[i] : (uint32_t)i;  // shared stream
   auto word = [&](int64_t u) -> uint64_t {
     const int64_t t = c.t_first + u;
     if (t < 0 || t >= T) return 0;
     return srow ? srow[t] : stim_word(si, t, thr, k0, k1);
   };
-  uint64_t *out = c.W + (int64_t)i * c.pitch;
+  uint64_t *out = c.W + (int64_t)lc * c.col_stride + (int64_t)i * c.pitch;
   const int32_t p_begin = seg * 64 * ITERS;
   uint64_t carry = p_begin > 0 ? word(2 * (int64_t)p_begin - 1) : 0;
   uint32_t ones = 0, togs = 0;
@@ -793,7 +821,7 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
   ones = wave_sum(ones);
   togs = wave_sum(togs);
   if (lane == 0) {
-    const int64_t o = (int64_t)i * cnt.B + cnt.col;
+    const int64_t o = (int64_t)i * cnt.B + col;
     if (ones) atomicAdd(cnt.ones + o, ones);
     if (togs) atomicAdd(cnt.tog + o, togs);
   }
@@ -820,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a, int32_t tb,
     const int32_t n = n0 + r, b = b0 + c;
     if (n >= a.n_nets || b >= a.B) continue;
     const int64_t idx = (int64_t)n * a.B + b;
-    const f2 pq = reinterpret_cast<const f2 *>(a.sp)[idx];
+    const f2 pq = sp_load(a.sp[idx]);
     const float tm = 2.0f * pq.x * pq.y;
     float beta = 1.0f;
     if (a.mode == 1) {
@@ -849,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
   if (idx >= (int64_t)a.n_nets * a.B) return;
   const int32_t n = (int32_t)(idx / a.B), b = (int32_t)(idx - (int64_t)n * a.B);
   const int64_t o = (int64_t)b * a.n_nets + a.int2ext[n];
-  const f2 pq = reinterpret_cast<const f2 *>(a.sp)[idx];
+  const f2 pq = sp_load(a.sp[idx]);
   const float tm = 2.0f * pq.x * pq.y;
   if (a.o_sp) a.o_sp[o] = pq.x;
   if (a.o_tr) a.o_tr[o] = tm;
@@ -1179,7 +1207,7 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const int32_t gi = g0 + (int32_t)gl;
   const int32_t out = g.n_pi + gi;
   const int32_t b = c / a.cdiv;
-  const f2 *sp = reinterpret_cast<const f2 *>(a.sp);
+  const float *sp = a.sp;
   const f2 z = f2{0.0f, 1.0f};
   // first round: the item's structure and its own net's values; nothing here
   // waits on another load
@@ -1187,7 +1215,7 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const int32_t e1r = g.rev_ptr[out + 1];
   const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
   const int op = g.op[gi];
-  const f2 pq = sp[(int64_t)out * a.B + b];
+  const f2 pq = sp_load(sp[(int64_t)out * a.B + b]);
   const float beta = a.beta ? a.beta[(int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
@@ -1201,7 +1229,7 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
     f2 x[kCellMaxIn];
     float d[kCellMaxIn];
     for (int j = 0; j < kCellMaxIn; ++j)
-      x[j] = j < g.pins ? sp[(int64_t)g.in[j * g.G + gi] * a.B + b] : z;
+      x[j] = j < g.pins ? sp_load(sp[(int64_t)g.in[j * g.G + gi] * a.B + b]) : z;
     cell_partials(lc, x, d);
     for (int j = 0; j < lc.nin; ++j)
       a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
@@ -1215,18 +1243,18 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
     const int k = arity_of(op);
     i0 = g.in[gi];
     s0 = g.slot[gi];
-    x0 = sp[(int64_t)i0 * a.B + b];
+    x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
     x1 = x2 = z;
     s1 = s2 = 0;
     if (k > 1) {
       i1 = g.in[g.G + gi];
       s1 = g.slot[g.G + gi];
-      x1 = sp[(int64_t)i1 * a.B + b];
+      x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
     }
     if (k > 2) {
       i2 = g.in[2 * g.G + gi];
       s2 = g.slot[2 * g.G + gi];
-      x2 = sp[(int64_t)i2 * a.B + b];
+      x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
     }
   } else {
     // few columns: the sweep is bound by round trips, so every gather goes
@@ -1237,9 +1265,9 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
     s0 = g.slot[gi];
     s1 = pin_row(g.slot, g, 1)[gi];
     s2 = pin_row(g.slot, g, 2)[gi];
-    x0 = sp[(int64_t)i0 * a.B + b];
-    x1 = sp[(int64_t)i1 * a.B + b];
-    x2 = sp[(int64_t)i2 * a.B + b];
+    x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
+    x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
+    x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
   }
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, WIDE);
   if (!active) return;
@@ -1269,7 +1297,7 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   const int32_t e1r = g.rev_ptr[i + 1];
   const int32_t e1 = active ? e1r : e0;
   const int32_t b = c / a.cdiv;
-  const f2 pq = reinterpret_cast<const f2 *>(a.sp)[(int64_t)i * a.B + b];
+  const f2 pq = sp_load(a.sp[(int64_t)i * a.B + b]);
   const float beta = a.beta ? a.beta[(int64_t)i * a.B + b] : 1.0f;
   const float cap = a.cap[i];
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
@@ -1297,7 +1325,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_lambda_export(
   const int32_t e = int2ext[n];
   if (lam_out) lam_out[(int64_t)c * n_nets + e] = l;
   if (score && n >= n_pi) {
-    const f2 pq = reinterpret_cast<const f2 *>(sp)[(int64_t)n * B + c / cdiv];
+    const f2 pq = sp_load(sp[(int64_t)n * B + c / cdiv]);
     const float slope = fmaxf(fabsf(pq.y - pq.x), eps);  // |1 - 2P| from the pair
     score[(int64_t)c * (n_nets - n_pi) + (e - n_pi)] = fabsf(l) * (pq.x * pq.y) / slope;
   }
@@ -1310,9 +1338,8 @@ __global__ __launch_bounds__(kBlock) void k_virus_step(float *sp, const float *_
   const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
   if (idx >= (uint32_t)n_pi * (uint32_t)B) return;
   const int32_t i = (int32_t)(idx / (uint32_t)B), b = (int32_t)(idx - (uint32_t)i * B);
-  f2 *pq = reinterpret_cast<f2 *>(sp);
-  const float p = clamp01(fmaf(eta, grad[(int64_t)b * n_pi + i], pq[idx].x));
-  pq[idx] = f2{p, 1.0f - p};
+  const float p = clamp01(fmaf(eta, grad[(int64_t)b * n_pi + i], sp_load(sp[idx]).x));
+  sp[idx] = sp_pack(p);
 }
 
 // Threshold at 1/2 and spell out the two-cycle stimulus (v0, 1 - v0).
@@ -1322,7 +1349,7 @@ __global__ __launch_bounds__(kBlock) void k_virus_vectors(const float *__restric
   const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
   if (idx >= (uint32_t)n_pi * (uint32_t)B) return;
   const int32_t b = (int32_t)(idx / (uint32_t)n_pi), i = (int32_t)(idx - (uint32_t)b * n_pi);
-  const float p = reinterpret_cast<const f2 *>(sp)[(int64_t)i * B + b].x;
+  const float p = sp_load(sp[(int64_t)i * B + b]).x;
   const bool one = p >= 0.5f;
   v0[idx] = one ? 1 : 0;
   if (p_out) p_out[idx] = p;
@@ -1450,9 +1477,9 @@ __global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel l
       sp_item<false>(g, cur, idx);
     grid_barrier(bar, (uint32_t)l);
   }
-  if (barrier_timed_out(bar)) {  // every gate's (p, q) becomes NaN
-    const int64_t n = (int64_t)g.G * lv.B * 2;
-    float *out = lv.sp + (int64_t)g.n_pi * lv.B * 2;
+  if (barrier_timed_out(bar)) {  // every gate's probability becomes NaN
+    const int64_t n = (int64_t)g.G * lv.B;
+    float *out = lv.sp + (int64_t)g.n_pi * lv.B;
     for (int64_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
       out[i] = __builtin_nanf("");
   }
@@ -1668,9 +1695,10 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
                            const int32_t *stream, uint64_t seed, const SimTune &tune,
                            hipStream_t s) {
   if (g.n_pi <= 0 || c.pairs <= 0) return hipSuccess;
+  if (c.n_cols <= 0) return hipSuccess;
   const int iters = tune.iters;
   const int32_t wpr = waves_per_row(c, iters);
-  const int64_t tasks = (int64_t)g.n_pi * wpr;
+  const int64_t tasks = (int64_t)g.n_pi * wpr * c.n_cols;
   if ((tasks + kWavesPerBlock - 1) / kWavesPerBlock > kMaxBlocks) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((tasks + kWavesPerBlock - 1) / kWavesPerBlock);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -1698,11 +1726,11 @@ hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t 
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
                             const SimTune &tune, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+  if (n <= 0 || c.n_cols <= 0) return hipSuccess;
   if (cells && sp) return hipErrorInvalidValue;  // no fused SP for library cells
   const int iters = cells ? min(tune.iters, 2) : tune.iters;  // cells: up to 6 input rows
   const int32_t wpr = waves_per_row(c, iters);
-  const int64_t tasks = (int64_t)n * wpr;
+  const int64_t tasks = (int64_t)n * wpr * c.n_cols;
   const int64_t sim_blocks64 = (tasks + kSimWaves - 1) / kSimWaves;
   SpLevel spl{};
   int64_t sp_blocks = 0;

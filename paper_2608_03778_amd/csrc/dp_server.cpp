@@ -132,6 +132,7 @@ Lane *make_lane(dp_server *s, int32_t design, int32_t cap) {
   l->bytes = dp::lane_bytes(d, cap);
   s->lanes.push_back(l);
   s->used += l->bytes;
+  s->st.lanes_created++;
   s->st.peak_slot_bytes = std::max<int64_t>(s->st.peak_slot_bytes, (int64_t)s->used);
   return l;
 }
@@ -142,6 +143,7 @@ bool make_room(dp_server *s, size_t need, int32_t keep_design) {
     Lane *l = s->lanes[i];
     if (!l->busy && l->design != keep_design) {
       s->used -= l->bytes;
+      s->st.lanes_freed++;
       destroy_lane(l);
       s->lanes.erase(s->lanes.begin() + i);
     } else {
@@ -293,6 +295,7 @@ void admit(dp_server *s) {
       while (cap > 1 && dp::lane_bytes(d, cap) > s->budget) cap >>= 1;
       const size_t need = dp::lane_bytes(d, cap);
       if (s->used + need > s->budget && !make_room(s, need, r->design)) {
+        s->st.memory_waits++;
         ++i;  // no memory now; a running lane will free some
         continue;
       }

@@ -13,14 +13,14 @@ namespace {
 
 // Scratch layout for a design of n nets (one query column), every part
 // 256-byte aligned:
-//   SP pairs (p, 1 - p)   float2 [n]      8 n bytes
+//   SP (stored form)      float  [n]      4 n bytes
 //   capacitance           float  [n]      4 n bytes (internal numbering)
 //   frozen beta           float  [n]      4 n bytes (internal numbering)
 //   per-net power term    float  [n]      4 n bytes (kappa beta TR_model)
 //   power partial sums    double [chunks]
 constexpr int64_t kMaxNets = int64_t(1) << 21;
 constexpr int64_t kPartBytes = 64 << 10;  // >= 8 * power_partial_doubles(kMaxNets, 1, 0, 0)
-constexpr int64_t kScratchBytes = 20 * kMaxNets + kPartBytes + 4 * 256;
+constexpr int64_t kScratchBytes = 16 * kMaxNets + kPartBytes + 4 * 256;
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -77,7 +77,7 @@ extern "C" dp_status dp_forward_static(const dp_design *d, const dp_params *prm,
   const int32_t nn = d->n_nets;
   char *s0 = static_cast<char *>(base);
   float *spp = reinterpret_cast<float *>(s0);
-  float *capi = reinterpret_cast<float *>(s0 + up256(8 * (int64_t)nn));
+  float *capi = reinterpret_cast<float *>(s0 + up256(4 * (int64_t)nn));
   float *betai = reinterpret_cast<float *>(reinterpret_cast<char *>(capi) + up256(4 * (int64_t)nn));
   float *xterm = reinterpret_cast<float *>(reinterpret_cast<char *>(betai) + up256(4 * (int64_t)nn));
   double *part = reinterpret_cast<double *>(reinterpret_cast<char *>(xterm) + up256(4 * (int64_t)nn));

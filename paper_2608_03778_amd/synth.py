@@ -61,6 +61,9 @@ class Netlist:
     stats: dict = dataclasses.field(default_factory=dict)
     # library cells (Boolean expressions); gate opcode CELL_BASE + c is cell c
     cells: tuple = ()
+    # per cell, its pin names in fan-in order ("I0,I1,S"), or None for the
+    # expression's identifiers in order of first appearance; () = all None
+    pins: tuple = ()
 
     @property
     def n_gates(self) -> int:

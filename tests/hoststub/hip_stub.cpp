@@ -156,7 +156,7 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t) {
 }
 hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t) {
   rd(p, (int64_t)n_pi * B);
-  wr(sp, (int64_t)n_pi * B * 2);
+  wr(sp, (int64_t)n_pi * B);
   return hipSuccess;
 }
 hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
@@ -187,13 +187,13 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
 }
 hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t) {
   rd_graph(g, lv.g0, lv.n, cells);
-  wr(lv.sp + (int64_t)(g.n_pi + lv.g0) * lv.B * 2, (int64_t)lv.n * lv.B * 2);
+  wr(lv.sp + (int64_t)(g.n_pi + lv.g0) * lv.B, (int64_t)lv.n * lv.B);
   return hipSuccess;
 }
 hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
                                int32_t n_pi, int32_t B, int64_t T, uint64_t, uint64_t *out,
                                hipStream_t) {
-  rd(sp, (int64_t)n_pi * B * 2);
+  rd(sp, (int64_t)n_pi * B);
   rd(tau, (int64_t)n_pi * B);
   if (stream) {
     rd(stream, n_pi);
@@ -207,9 +207,13 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
                            const float *p_col, const uint64_t *stim, int64_t T,
                            const int32_t *stream, uint64_t, const SimTune &, hipStream_t) {
   if (stream) rd(stream, g.n_pi);
-  wr(c.W, (int64_t)g.n_pi * c.pitch);
-  rd(p_col, (int64_t)g.n_pi * cnt.B * 2);
-  if (stim) rd(stim, (int64_t)g.n_pi * T);
+  if (c.n_cols < 1 || cnt.col < 0 || cnt.col + c.n_cols > cnt.B) {
+    std::fprintf(stderr, "STUB: stimulus columns out of range\n");
+    std::abort();
+  }
+  for (int32_t k = 0; k < c.n_cols; ++k) wr(c.W + k * c.col_stride, (int64_t)g.n_pi * c.pitch);
+  rd(p_col, (int64_t)g.n_pi * cnt.B);
+  if (stim) rd(stim, (int64_t)c.n_cols * g.n_pi * T);
   wr(cnt.ones, (int64_t)g.n_pi * cnt.B);
   wr(cnt.tog, (int64_t)g.n_pi * cnt.B);
   if (c.u_hi > c.pitch || c.u_lo < 0 || 2 * c.pairs > c.pitch) {
@@ -223,15 +227,22 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
                             const SimTune &, hipStream_t) {
   if (cells && sp) { std::fprintf(stderr, "STUB: fused SP on a library-cell range\n"); std::abort(); }
   rd_graph(g, g0, n, cells);
-  wr(c.W + (int64_t)(g.n_pi + g0) * c.pitch, (int64_t)n * c.pitch);
+  if (c.n_cols < 1 || cnt.col < 0 || cnt.col + c.n_cols > cnt.B) {
+    std::fprintf(stderr, "STUB: simulation columns out of range\n");
+    std::abort();
+  }
+  for (int32_t k = 0; k < c.n_cols; ++k) {
+    rd(c.W + k * c.col_stride, (int64_t)g.n_nets * c.pitch);  // fan-in rows anywhere below
+    wr(c.W + k * c.col_stride + (int64_t)(g.n_pi + g0) * c.pitch, (int64_t)n * c.pitch);
+  }
   wr(cnt.ones + (int64_t)(g.n_pi + g0) * cnt.B, (int64_t)n * cnt.B);
   wr(cnt.tog + (int64_t)(g.n_pi + g0) * cnt.B, (int64_t)n * cnt.B);
-  if (sp) wr(sp->sp + (int64_t)(g.n_pi + g0) * sp->B * 2, (int64_t)n * sp->B * 2);
+  if (sp) wr(sp->sp + (int64_t)(g.n_pi + g0) * sp->B, (int64_t)n * sp->B);
   return hipSuccess;
 }
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t) {
   const int64_t nb = (int64_t)a.n_nets * a.B;
-  rd(a.sp, nb * 2);
+  rd(a.sp, nb);
   if (a.ones) rd(a.ones, nb);
   if (a.tog) rd(a.tog, nb);
   if (a.beta_frozen) rd(a.beta_frozen, a.beta_shared ? a.n_nets : nb);
@@ -242,7 +253,7 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t) {
 }
 hipError_t launch_export(const ExportArgs &a, hipStream_t) {
   const int64_t nb = (int64_t)a.n_nets * a.B;
-  rd(a.sp, nb * 2);
+  rd(a.sp, nb);
   if (a.beta) rd(a.beta, nb);
   rd(a.int2ext, a.n_nets);
   if (a.o_sp) wr(a.o_sp, nb);
@@ -277,7 +288,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t) {
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
                             bool cells, hipStream_t) {
   rd_graph(g, g0, n, cells);
-  rd(a.sp, (int64_t)g.n_nets * a.B * 2);
+  rd(a.sp, (int64_t)g.n_nets * a.B);
   rd(a.cap, g.n_nets);
   if (a.size) rd(a.size, (int64_t)(a.S > 0 ? a.S : a.B) * a.G);
   if (a.w) rd(a.w, (int64_t)a.C);
@@ -298,7 +309,7 @@ hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int
   rd(level_ptr, depth + 2);
   wr(bar.words, kBarrierWords);
   rd(bar.words + kBarrierReport, 1);
-  wr(lv.sp, (int64_t)g.n_nets * lv.B * 2);
+  wr(lv.sp, (int64_t)g.n_nets * lv.B);
   return hipSuccess;
 }
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
@@ -337,20 +348,20 @@ hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const in
                                      int32_t n_pi, int32_t n_nets, int32_t B, int32_t C,
                                      int32_t, float, float *lam_out, float *score, hipStream_t) {
   rd(lam, (int64_t)n_nets * C);
-  rd(sp, (int64_t)n_nets * B * 2);
+  rd(sp, (int64_t)n_nets * B);
   rd(int2ext, n_nets);
   if (lam_out) wr(lam_out, (int64_t)n_nets * C);
   if (score) wr(score, (int64_t)(n_nets - n_pi) * C);
   return hipSuccess;
 }
 hipError_t launch_virus_step(float *sp, const float *grad, float, int32_t n_pi, int32_t B, hipStream_t) {
-  wr(sp, (int64_t)n_pi * B * 2);
+  wr(sp, (int64_t)n_pi * B);
   rd(grad, (int64_t)n_pi * B);
   return hipSuccess;
 }
 hipError_t launch_virus_vectors(const float *sp, uint64_t *stim, uint8_t *v0, float *p_out,
                                 int32_t n_pi, int32_t B, hipStream_t) {
-  rd(sp, (int64_t)n_pi * B * 2);
+  rd(sp, (int64_t)n_pi * B);
   wr(stim, (int64_t)n_pi * B * 2);
   wr(v0, (int64_t)n_pi * B);
   if (p_out) wr(p_out, (int64_t)n_pi * B);

@@ -103,6 +103,14 @@ def scenario_flows(ctx):
                 scheds = [(L.DP_SCHED_LEVEL, 0, 0, 1), (L.DP_SCHED_GRAPH, 0, 0, 1)]
                 if mode == L.DP_HYBRID:
                     scheds += [(L.DP_SCHED_LEVEL, 8, 2, 2), (L.DP_SCHED_LEVEL, 6, 1, 3)]
+                    if B > 1:  # ragged column groups, alone and with chunks on streams
+                        ev.set_sim_columns(2)
+                        for chunk, lanes in ((0, 1), (8, 2)):
+                            ev.set_schedule(L.DP_SCHED_LEVEL, chunk, 0)
+                            ev.set_sim_streams(lanes)
+                            ev.forward(("sp", "tr", "power"))
+                            runs += 1
+                        ev.set_sim_columns(0)
                 if name == "fixed":
                     scheds += [(L.DP_SCHED_PERSISTENT, 0, 0, 1)]
                 for sched, chunk, ppl, lanes in scheds:

@@ -52,6 +52,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(L.Netlist) == 8 + 3 * 8
     assert ctypes.sizeof(L.FwdOut) == 9 * 8 + 8
     assert ctypes.sizeof(L.DesignInfo) == 4 * 4 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(L.ServerStats) == 3 * 8 + 8 + 8 + 4 + 4 + 3 * 8
 
 
 def test_defaults_and_version(lib):

@@ -304,3 +304,89 @@ def test_mixed_dag_many_columns_equal_single_columns(ctx):
     f, adj = oracle_column(o, p[0], cap, mode="modeled")
     assert_power_close(res["power"][0], f["power"], "power[0]")
     assert_grad_close(g["dpi"][0], adj["dpi"], "dP/dp[0]")
+
+
+MUX_OUT = "(I0&!S)|(I1&S)"  # a multiplexer written out: inputs [I0, S, I1] by first appearance
+
+
+def test_pin_list_wires_the_written_out_multiplexer(ctx):
+    """Alg. 1's perm: the written-out multiplexer with pin list "I0,I1,S"
+    and its gates' fan-in given in that pin order.  Every output equals the
+    oracle's (given the same pin list), the output SP equals the op-by-op
+    value (1 - s) i0 + s i1 - i0 i1 s (1 - s) of the expression read once
+    per operation, and the design is bit for bit the one compiled without a
+    pin list from the fan-in put into first-appearance order by hand."""
+    say("pin list: written-out multiplexer")
+    rng = np.random.default_rng(77)
+    n_pi, G = 24, 300
+    gates = [(synth.CELL_BASE, list(rng.choice(n_pi, size=3, replace=False))) for _ in range(G)]
+    by_pins = dataclasses.replace(synth.from_gates(n_pi, gates, (MUX_OUT,)), pins=("I0,I1,S",))
+    # the same gates with each fan-in reordered [I0, I1, S] -> [I0, S, I1]
+    by_hand = synth.from_gates(n_pi, [(op, [f[0], f[2], f[1]]) for op, f in gates], (MUX_OUT,))
+    p = synth.pi_probs(n_pi, 78)
+    cap = synth.net_caps(n_pi + G, 79)
+    res = {}
+    for name, nl in (("pins", by_pins), ("hand", by_hand)):
+        d = api.Design(ctx, nl)
+        ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 7, seed=3)
+        ev.set_pi_prob(p)
+        ev.set_caps(cap)
+        res[name] = ev.forward(FWD_ALL)
+        res[name].update(ev.backward(want=("dpi", "dcap")))
+    for k in res["pins"]:
+        np.testing.assert_array_equal(res["pins"][k], res["hand"][k], err_msg=k)
+    o = oracle.Netlist.of(by_pins)
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid", n_words=7, seed=3)
+    _check_forward(res["pins"], f, 0, True)
+    assert_power_close(res["pins"]["power"], f["power"])
+    assert_grad_close(res["pins"]["dpi"][0], adj["dpi"], "dP/dp")
+    pp = p[0].astype(np.float64)
+    for g, (_, (i0, i1, s)) in enumerate(gates):
+        a, b, c = pp[i0], pp[i1], pp[s]
+        want = (1 - c) * a + c * b - a * b * c * (1 - c)
+        assert abs(res["pins"]["sp"][0][n_pi + g] - want) <= SP_ABS
+
+
+def test_identical_codes_share_one_logic_id(ctx):
+    """Alg. 1's dedup: expressions that compile to the same code (up to the
+    names of their identifiers, with pin lists mapping each onto its gates'
+    fan-in) share one logic id; one that is a fixed cell runs as it.  The
+    deduplicated design matches the oracle."""
+    say("dedup of library cells")
+    cells = ("A&!B", "X&!Y", MUX_OUT, "(a&!c)|(b&c)", "B&A", "Q&!P")
+    pins = (None, None, "I0,I1,S", "a b c", "A,B", "P,Q")
+    rng = np.random.default_rng(80)
+    n_pi = 30
+    gates = []
+    for _ in range(900):
+        c = int(rng.integers(0, len(cells)))
+        gates.append((synth.CELL_BASE + c, list(rng.choice(n_pi, size=2 if c in (0, 1, 4, 5) else 3,
+                                                           replace=False))))
+    nl = dataclasses.replace(synth.from_gates(n_pi, gates, cells), pins=pins)
+    d = api.Design(ctx, nl)
+    logic, n_logic = d.cell_logic()
+    # A&!B, X&!Y and Q&!P (pins P,Q: input Q is pin 1) share one code; the two
+    # multiplexers another; B&A is the fixed AND2
+    assert n_logic == 2
+    assert logic[0] == logic[1] == logic[5] and logic[2] == logic[3] and logic[0] != logic[2]
+    assert logic[4] == -1 - 2
+    p = synth.pi_probs(n_pi, 81)
+    cap = synth.net_caps(nl.n_nets, 82)
+    ev = api.Eval(d, mode=L.DP_HYBRID, n_sim=64 * 5, seed=4)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    res = ev.forward(FWD_ALL)
+    g = ev.backward(want=("dpi",))
+    o = oracle.Netlist.of(nl)
+    f, adj = oracle_column(o, p[0], cap, mode="hybrid", n_words=5, seed=4)
+    _check_forward(res, f, 0, True)
+    assert_power_close(res["power"], f["power"])
+    assert_grad_close(g["dpi"][0], adj["dpi"], "dP/dp")
+
+
+def test_pin_list_errors(ctx):
+    say("pin list errors")
+    nl = synth.from_gates(4, [(synth.CELL_BASE, [0, 1, 2])], (MUX_OUT,))
+    for bad in ("I0,I1", "I0,I1,S,T", "I0,I0,S", "I0,I1,X", "I0;I1;S"):
+        with pytest.raises(L.DiffPowerError, match="INVALID"):
+            api.Design(ctx, dataclasses.replace(nl, pins=(bad,)))

@@ -115,6 +115,39 @@ def test_chunking_and_lane_tiling_are_bit_exact(ctx, chunk, ppl, streams):
     np.testing.assert_array_equal(res["toggles"][0].astype(np.uint64), tog)
 
 
+@pytest.mark.parametrize("cols,chunk,streams", [(0, 0, 1), (2, 0, 1), (1, 0, 1), (0, 30, 1),
+                                                (2, 30, 2), (3, 0, 2), (0, 30, 3)])
+def test_column_groups_are_bit_exact(ctx, cols, chunk, streams):
+    """Five hybrid query columns simulated together, in ragged column
+    groups, word chunks and concurrent streams: every column's counts, SP,
+    beta and power equal that column computed alone, bit for bit, and its
+    counts equal the oracle's."""
+    say(f"column groups cols={cols} chunk={chunk} streams={streams}")
+    nl = synth.random_dag(synth.SPECS["dag2k"], 12)
+    B, T = 5, 67
+    p, cap, _ = _inputs(nl, 12, B=B)
+    d = api.Design(ctx, nl)
+    outs = ("sp", "beta", "ones", "toggles", "power")
+    ev = api.Eval(d, B, mode=L.DP_HYBRID, n_sim=64 * T, seed=9)
+    ev.set_pi_prob(p)
+    ev.set_caps(cap)
+    ev.set_schedule(L.DP_SCHED_LEVEL, chunk, 0)
+    ev.set_sim_columns(cols)
+    ev.set_sim_streams(streams)
+    res = ev.forward(outs)
+    one = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=64 * T, seed=9)
+    one.set_caps(cap)
+    o = oracle.Netlist.of(nl)
+    for b in range(B):
+        one.set_pi_prob(p[b:b + 1])
+        alone = one.forward(outs)
+        for k in outs:
+            np.testing.assert_array_equal(res[k][b], alone[k][0], err_msg=f"{k} column {b}")
+        ones, tog = o.sim(T, p_pi=p[b], seed=9)
+        np.testing.assert_array_equal(res["ones"][b].astype(np.uint64), ones)
+        np.testing.assert_array_equal(res["toggles"][b].astype(np.uint64), tog)
+
+
 def test_explicit_stimulus_matches_generator(ctx):
     """dp_set_stimulus with the oracle's Philox words gives the generator's
     counts; exhaustive words give the exact minterm counts."""
@@ -298,16 +331,15 @@ def test_errors_and_state(ctx):
         ev.backward()
     with pytest.raises(L.DiffPowerError, match="INVALID"):
         api.Eval(d, mode=L.DP_HYBRID, n_sim=100)
-    # a hybrid sweep of 64 columns x 21 launches is more than a graph holds:
-    # refused before any capture, and the autotuner does not offer it
-    big = api.Eval(d, 64, mode=L.DP_HYBRID, n_sim=128)
-    big.set_pi_prob(synth.pi_probs(nl.n_pi, 1, batch=64))
+    # a hybrid sweep of 64 word chunks x 21 launches is more than a graph
+    # holds: refused before any capture; per-level launches run it
+    big = api.Eval(d, 2, mode=L.DP_HYBRID, n_sim=64 * 256)
+    big.set_pi_prob(synth.pi_probs(nl.n_pi, 1, batch=2))
     big.set_caps(synth.net_caps(nl.n_nets, 1))
-    big.set_schedule(L.DP_SCHED_GRAPH)
+    big.set_schedule(L.DP_SCHED_GRAPH, 4)
     with pytest.raises(L.DiffPowerError, match="UNSUPPORTED"):
         big.forward()
-    big.autotune(1)
-    assert big.get_schedule()["schedule"] != L.DP_SCHED_GRAPH
+    big.set_schedule(L.DP_SCHED_LEVEL, 4)
     big.forward()
 
 
