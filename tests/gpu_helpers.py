@@ -31,6 +31,32 @@ def assert_grad_close(g, ref, what=""):
                            f"{ref[bad[np.argmax(err[bad])]]:.6g})")
 
 
+# A net's TR_model relative to the oracle's: every cell rule is a sum of
+# products of p's and q's (no cancellation), so FP32 keeps relative accuracy
+# even where TR_model is tiny; the bar is loose next to the rounding the
+# test designs show (about 1e-6).
+TR_REL = 1e-4
+
+
+def assert_beta_close(beta, tr, f, what=""):
+    """beta = clip(TR_acc / TR_model) on every net: TR_acc comes from exact
+    counts (one float rounding), the quotient adds one more, and the clip
+    cannot widen a difference, so |beta - beta_ref| <= beta_ref (r / (1 - r)
+    + 2^-21) with r the net's relative TR_model error, itself within TR_REL.
+    Where TR_model is 0 in the oracle (P is 0 or 1), beta follows the
+    zero-denominator rule exactly."""
+    beta = np.asarray(beta, np.float64)
+    tr = np.asarray(tr, np.float64)
+    ref_tr, ref_beta = f["tr_model"], f["beta"]
+    zero = ref_tr == 0
+    np.testing.assert_array_equal(beta[zero], ref_beta[zero], err_msg=what)
+    r = np.abs(tr[~zero] - ref_tr[~zero]) / ref_tr[~zero]
+    assert r.size == 0 or r.max() <= TR_REL, f"{what}: TR_model relative error {r.max():.3g}"
+    bound = ref_beta[~zero] * (r / (1 - r) + 2.0 ** -21)
+    err = np.abs(beta[~zero] - ref_beta[~zero])
+    assert (err <= bound).all(), (f"{what}: beta off by {(err / bound).max():.3g} x its bound")
+
+
 def assert_power_close(p, ref, what=""):
     p = np.asarray(p, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()

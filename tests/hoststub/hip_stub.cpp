@@ -12,7 +12,10 @@
 #include <cstring>
 #include <algorithm>
 #include <mutex>
+#include <map>
 #include <set>
+#include <thread>
+#include <vector>
 
 #include DP_KERNELS_H
 #include DP_ABI_H
@@ -27,84 +30,262 @@ extern "C" dp_status dp_forward_static(const dp_design *, const dp_params *, con
   return DP_E_UNSUPPORTED;
 }
 
-struct ihipStream_t { int capturing = 0; };
-struct ihipEvent_t { int x = 0; };
-struct ihipGraph { int x = 0; };
-struct hipGraphExec { int x = 0; };
+// ---- stream capture model -------------------------------------------------
+// A capture begins on one stream; another stream joins it by waiting on an
+// event recorded in it (a fork) and must be waited on again, through an
+// event recorded on it, before the capture ends (a join), or the end fails
+// as unjoined.  Work enqueued on a capturing stream is recorded, not run:
+// each launch's extents (every range the real kernel would touch) go into
+// the graph, and every launch of the instantiated graph checks that each
+// extent still lies inside a live allocation.  Calls the thread-local
+// capture mode forbids while the calling thread captures (allocation, free,
+// synchronization) abort, and so does waiting on an event whose last record
+// belongs to an ended capture.
+struct Extent {
+  const void *p;
+  size_t bytes;
+  const char *what;
+};
+struct Capture {
+  hipStream_t origin;
+  std::thread::id thread;
+  std::vector<Extent> extents;
+  std::set<hipStream_t> members;  // origin and joined streams
+  std::set<hipStream_t> forked;   // joined streams not yet joined back
+  bool broken = false;
+};
+struct ihipStream_t { Capture *cap = nullptr; };
+struct ihipEvent_t {
+  Capture *cap = nullptr;   // the capture it was last recorded in (null: recorded outside)
+  hipStream_t from = nullptr;
+  bool stale = false;       // last recorded in a capture that has ended
+};
+struct ihipGraph { std::vector<Extent> extents; };
+struct hipGraphExec { std::vector<Extent> extents; };
 
 static std::mutex g_mu;
-static std::set<void *> g_live;
+static std::map<const char *, size_t> g_live;  // allocation base -> bytes
+static std::set<Capture *> g_caps;             // captures in progress
+static std::set<hipEvent_t> g_events;
+static long g_forks = 0, g_captures = 0, g_graph_launches = 0;
 
-static void note_alloc(void *p) { std::lock_guard<std::mutex> l(g_mu); g_live.insert(p); }
+static void fatal(const char *msg) {
+  std::fprintf(stderr, "STUB: %s\n", msg);
+  std::abort();
+}
+static void note_alloc(void *p, size_t n) {
+  std::lock_guard<std::mutex> l(g_mu);
+  g_live[static_cast<const char *>(p)] = n;
+}
 static bool note_free(void *p) {
   std::lock_guard<std::mutex> l(g_mu);
-  return g_live.erase(p) == 1;
+  return g_live.erase(static_cast<const char *>(p)) == 1;
+}
+static bool is_live(const void *p, size_t bytes) {
+  std::lock_guard<std::mutex> l(g_mu);
+  const char *c = static_cast<const char *>(p);
+  auto it = g_live.upper_bound(c);
+  if (it == g_live.begin()) return false;
+  --it;
+  return c >= it->first && c + bytes <= it->first + it->second;
+}
+// Whether the calling thread is capturing (thread-local capture mode).
+static bool thread_captures() {
+  std::lock_guard<std::mutex> l(g_mu);
+  for (Capture *c : g_caps)
+    if (c->thread == std::this_thread::get_id()) return true;
+  return false;
+}
+static void end_capture(Capture *c) {
+  {
+    std::lock_guard<std::mutex> l(g_mu);
+    g_caps.erase(c);
+    for (hipEvent_t e : g_events)
+      if (e->cap == c) {
+        e->cap = nullptr;
+        e->stale = true;
+      }
+  }
+  for (hipStream_t m : c->members) m->cap = nullptr;
+  delete c;
 }
 
+// Recording target of the launch being made (null: run, i.e. touch memory).
+static thread_local Capture *g_rec = nullptr;
+struct Scope {
+  Capture *prev;
+  explicit Scope(hipStream_t s) : prev(g_rec) { g_rec = s ? s->cap : nullptr; }
+  ~Scope() { g_rec = prev; }
+};
+
 extern "C" {
+// Counts of what the capture model saw: captures, forks into them, graph
+// launches (read by the host-logic scenarios).
+void stub_capture_counts(long *out) {
+  out[0] = g_captures;
+  out[1] = g_forks;
+  out[2] = g_graph_launches;
+}
 hipError_t hipMalloc(void **ptr, size_t size) {
+  if (thread_captures()) fatal("hipMalloc while this thread captures a stream");
   *ptr = std::malloc(size ? size : 1);
-  note_alloc(*ptr);
+  note_alloc(*ptr, size ? size : 1);
   return hipSuccess;
 }
 hipError_t hipFree(void *ptr) {
   if (!ptr) return hipSuccess;
+  if (thread_captures()) fatal("hipFree while this thread captures a stream");
   if (!note_free(ptr)) { std::fprintf(stderr, "STUB: hipFree of unknown %p\n", ptr); std::abort(); }
   std::free(ptr);
   return hipSuccess;
 }
 hipError_t hipHostMalloc(void **ptr, size_t size, unsigned int) { return hipMalloc(ptr, size); }
 hipError_t hipHostFree(void *ptr) { return hipFree(ptr); }
-hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, hipStream_t) {
+hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, hipStream_t s) {
+  if (s && s->cap) {
+    s->cap->extents.push_back({dst, n, "copy destination"});
+    s->cap->extents.push_back({src, n, "copy source"});
+    return hipSuccess;
+  }
   if (n) std::memmove(dst, src, n);
   return hipSuccess;
 }
 hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind) {
+  if (thread_captures()) fatal("hipMemcpy while this thread captures a stream");
   if (n) std::memmove(dst, src, n);
   return hipSuccess;
 }
-hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t s) {
+  if (s && s->cap) fatal("hipStreamSynchronize of a capturing stream");
+  if (thread_captures()) fatal("hipStreamSynchronize while this thread captures a stream");
+  return hipSuccess;
+}
 const char *hipGetErrorString(hipError_t) { return "stub error"; }
 hipError_t hipSetDevice(int d) { return d == 0 ? hipSuccess : hipErrorInvalidDevice; }
 hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
 hipError_t hipGetLastError(void) { return hipSuccess; }
-hipError_t hipEventCreate(hipEvent_t *e) { *e = new ihipEvent_t(); return hipSuccess; }
-hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { *e = new ihipEvent_t(); return hipSuccess; }
-hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
-hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->x++; return hipSuccess; }
-hipError_t hipEventSynchronize(hipEvent_t e) { (void)e->x; return hipSuccess; }
-hipError_t hipEventQuery(hipEvent_t e) { (void)e->x; return hipSuccess; }
+hipError_t hipEventCreate(hipEvent_t *e) {
+  *e = new ihipEvent_t();
+  std::lock_guard<std::mutex> l(g_mu);
+  g_events.insert(*e);
+  return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
+hipError_t hipEventDestroy(hipEvent_t e) {
+  {
+    std::lock_guard<std::mutex> l(g_mu);
+    g_events.erase(e);
+  }
+  delete e;
+  return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
+  e->cap = s ? s->cap : nullptr;
+  e->from = s;
+  e->stale = false;
+  return hipSuccess;
+}
+static void check_usable(hipEvent_t e, const char *what) {
+  if (e->cap) {
+    std::fprintf(stderr, "STUB: %s of an event recorded in a capture in progress\n", what);
+    std::abort();
+  }
+  if (e->stale) {
+    std::fprintf(stderr, "STUB: %s of an event last recorded in an ended capture\n", what);
+    std::abort();
+  }
+}
+hipError_t hipEventSynchronize(hipEvent_t e) {
+  check_usable(e, "hipEventSynchronize");
+  return hipSuccess;
+}
+hipError_t hipEventQuery(hipEvent_t e) {
+  check_usable(e, "hipEventQuery");
+  return hipSuccess;
+}
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
-  (void)a->x; (void)b->x;
+  check_usable(a, "hipEventElapsedTime");
+  check_usable(b, "hipEventElapsedTime");
   *ms = 0.001f;
   return hipSuccess;
 }
 hipError_t hipStreamCreate(hipStream_t *s) { *s = new ihipStream_t(); return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = new ihipStream_t(); return hipSuccess; }
-hipError_t hipStreamDestroy(hipStream_t s) { delete s; return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) {
+  if (s && s->cap) fatal("hipStreamDestroy of a capturing stream");
+  delete s;
+  return hipSuccess;
+}
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
-  if (s) (void)s->capturing;
-  (void)e->x;
+  Capture *c = e->cap;
+  Capture *sc = s ? s->cap : nullptr;
+  if (c) {
+    if (!s) fatal("the null stream waits on an event of a capture");
+    if (sc && sc != c) fatal("a stream of one capture waits on an event of another");
+    if (!sc) {  // a fork: s joins the capture
+      ++g_forks;
+      s->cap = c;
+      c->members.insert(s);
+      c->forked.insert(s);
+    } else if (e->from != s) {
+      c->forked.erase(e->from);  // a join of the branch the event was recorded on
+    }
+    return hipSuccess;
+  }
+  if (sc) fatal("a capturing stream waits on an event recorded outside the capture");
+  if (e->stale) fatal("a stream waits on an event last recorded in an ended capture");
   return hipSuccess;
 }
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
   if (!s) return hipErrorInvalidValue;
-  s->capturing = 1;
+  if (s->cap) fatal("hipStreamBeginCapture on a stream that already captures");
+  ++g_captures;
+  auto *c = new Capture();
+  c->origin = s;
+  c->thread = std::this_thread::get_id();
+  c->members.insert(s);
+  s->cap = c;
+  std::lock_guard<std::mutex> l(g_mu);
+  g_caps.insert(c);
   return hipSuccess;
 }
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g) {
-  s->capturing = 0;
-  *g = new ihipGraph();
+  Capture *c = s ? s->cap : nullptr;
+  if (!c || c->origin != s) fatal("hipStreamEndCapture on a stream that did not begin a capture");
+  const bool unjoined = !c->forked.empty();
+  auto *graph = new ihipGraph();
+  graph->extents = c->extents;
+  end_capture(c);
+  if (unjoined) {
+    delete graph;
+    *g = nullptr;
+    std::fprintf(stderr, "STUB: capture ended with a forked stream not joined back\n");
+    return hipErrorStreamCaptureUnjoined;
+  }
+  *g = graph;
   return hipSuccess;
 }
 hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, hipGraphNode_t *, char *, size_t) {
-  (void)g->x;
   *x = new hipGraphExec();
+  (*x)->extents = g->extents;
   return hipSuccess;
 }
 hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t x) { delete x; return hipSuccess; }
-hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) { (void)x->x; return hipSuccess; }
+hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s) {
+  if (s && s->cap) {
+    s->cap->extents.insert(s->cap->extents.end(), x->extents.begin(), x->extents.end());
+    return hipSuccess;
+  }
+  ++g_graph_launches;
+  for (const Extent &e : x->extents)
+    if (e.bytes && !is_live(e.p, e.bytes)) {
+      std::fprintf(stderr, "STUB: graph launch touches %zu bytes at %p (%s) outside any live "
+                           "allocation\n", e.bytes, e.p, e.what);
+      std::abort();
+    }
+  return hipSuccess;
+}
 }
 
 // ---- launchers: touch the extents ------------------------------------------
@@ -114,12 +295,20 @@ template <class T>
 void rd(const T *p, int64_t n) {
   if (n <= 0) return;
   if (!p) { std::fprintf(stderr, "STUB: null read of %lld\n", (long long)n); std::abort(); }
+  if (g_rec) {  // captured: checked when the graph is launched
+    g_rec->extents.push_back({p, (size_t)n * sizeof(T), "kernel read"});
+    return;
+  }
   volatile T a = p[0]; volatile T b = p[n - 1]; (void)a; (void)b;
 }
 template <class T>
 void wr(T *p, int64_t n) {
   if (n <= 0) return;
   if (!p) { std::fprintf(stderr, "STUB: null write of %lld\n", (long long)n); std::abort(); }
+  if (g_rec) {
+    g_rec->extents.push_back({p, (size_t)n * sizeof(T), "kernel write"});
+    return;
+  }
   std::memset((void *)&p[0], 0, sizeof(T));
   std::memset((void *)&p[n - 1], 0, sizeof(T));
 }
@@ -146,21 +335,25 @@ void rd_graph(const dp::GraphView &g, int32_t g0, int32_t n, bool cells) {
 namespace dp {
 constexpr int32_t kPowerChunk = 8192, kSlabNets = 2048;
 
-hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t) {
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream_) {
+  Scope sc_(stream_);
   for (int64_t i = 0; i < n; ++i) p[i] = v;
   return hipSuccess;
 }
-hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t) {
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t stream_) {
+  Scope sc_(stream_);
   for (int64_t i = 0; i < n; ++i) p[i] = v;
   return hipSuccess;
 }
-hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t) {
+hipError_t launch_load_pi(const float *p, float *sp, int32_t n_pi, int32_t B, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(p, (int64_t)n_pi * B);
   wr(sp, (int64_t)n_pi * B);
   return hipSuccess;
 }
 hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int32_t *bad,
-                              hipStream_t) {
+                              hipStream_t stream_) {
+  Scope sc_(stream_);
   int32_t b = 0;
   for (int64_t i = 0; i < n; ++i)
     if (!(v[i] >= lo && v[i] <= hi)) b = 1;
@@ -168,31 +361,36 @@ hipError_t launch_check_range(const float *v, int64_t n, float lo, float hi, int
   return hipSuccess;
 }
 hipError_t launch_gather_nets_f32(const float *src, const int32_t *int2ext, float *dst,
-                                  int32_t n_nets, hipStream_t) {
+                                  int32_t n_nets, hipStream_t stream_) {
+  Scope sc_(stream_);
   for (int32_t i = 0; i < n_nets; ++i) dst[i] = src[int2ext[i]];
   return hipSuccess;
 }
 hipError_t launch_import_cols_f32(const float *src, const int32_t *int2ext, float *dst,
-                                  int32_t n_nets, int32_t B, hipStream_t) {
+                                  int32_t n_nets, int32_t B, hipStream_t stream_) {
+  Scope sc_(stream_);
   for (int32_t i = 0; i < n_nets; ++i)
     for (int32_t b = 0; b < B; ++b) dst[(int64_t)i * B + b] = src[(int64_t)b * n_nets + int2ext[i]];
   return hipSuccess;
 }
 hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *dst, int32_t n_pi,
-                               int32_t G, int32_t S, hipStream_t) {
+                               int32_t G, int32_t S, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(int2ext, n_pi + G);
   rd(src, (int64_t)S * G);
   wr(dst, (int64_t)S * G);
   return hipSuccess;
 }
-hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t) {
+hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd_graph(g, lv.g0, lv.n, cells);
   wr(lv.sp + (int64_t)(g.n_pi + lv.g0) * lv.B, (int64_t)lv.n * lv.B);
   return hipSuccess;
 }
 hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
                                int32_t n_pi, int32_t B, int64_t T, uint64_t, uint64_t *out,
-                               hipStream_t) {
+                               hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(sp, (int64_t)n_pi * B);
   rd(tau, (int64_t)n_pi * B);
   if (stream) {
@@ -205,7 +403,8 @@ hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t 
 }
 hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountView &cnt,
                            const float *p_col, const uint64_t *stim, int64_t T,
-                           const int32_t *stream, uint64_t, const SimTune &, hipStream_t) {
+                           const int32_t *stream, uint64_t, const SimTune &, hipStream_t stream_) {
+  Scope sc_(stream_);
   if (stream) rd(stream, g.n_pi);
   if (c.n_cols < 1 || cnt.col < 0 || cnt.col + c.n_cols > cnt.B) {
     std::fprintf(stderr, "STUB: stimulus columns out of range\n");
@@ -224,7 +423,8 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
 }
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
-                            const SimTune &, hipStream_t) {
+                            const SimTune &, hipStream_t stream_) {
+  Scope sc_(stream_);
   if (cells && sp) { std::fprintf(stderr, "STUB: fused SP on a library-cell range\n"); std::abort(); }
   rd_graph(g, g0, n, cells);
   if (c.n_cols < 1 || cnt.col < 0 || cnt.col + c.n_cols > cnt.B) {
@@ -240,7 +440,8 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   if (sp) wr(sp->sp + (int64_t)(g.n_pi + g0) * sp->B, (int64_t)n * sp->B);
   return hipSuccess;
 }
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t) {
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t stream_) {
+  Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
   rd(a.sp, nb);
   if (a.ones) rd(a.ones, nb);
@@ -251,7 +452,8 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t) {
   wr(a.xterm, nb);
   return hipSuccess;
 }
-hipError_t launch_export(const ExportArgs &a, hipStream_t) {
+hipError_t launch_export(const ExportArgs &a, hipStream_t stream_) {
+  Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
   rd(a.sp, nb);
   if (a.beta) rd(a.beta, nb);
@@ -275,7 +477,8 @@ int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t pair
   if (S > 0 && !paired) slabs = std::max<int64_t>(slabs, (n_nets + kSlabNets - 1) / kSlabNets);
   return (int32_t)(slabs * cols);
 }
-hipError_t launch_power(const PowerArgs &a, hipStream_t) {
+hipError_t launch_power(const PowerArgs &a, hipStream_t stream_) {
+  Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
   rd(a.xterm, nb);
   rd(a.cap, a.n_nets);
@@ -286,7 +489,8 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t) {
   return hipSuccess;
 }
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
-                            bool cells, hipStream_t) {
+                            bool cells, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd_graph(g, g0, n, cells);
   rd(a.sp, (int64_t)g.n_nets * a.B);
   rd(a.cap, g.n_nets);
@@ -298,14 +502,16 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
   if ((int64_t)a.C > (int64_t)a.B * a.cdiv) { std::fprintf(stderr, "STUB: C > B*cdiv\n"); std::abort(); }
   return hipSuccess;
 }
-hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t) {
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t stream_) {
+  Scope sc_(stream_);
   if (a.fixed) rd(a.fixed, g.n_pi);
   rd(a.contrib, CONTRIB_ELEMS(g) * a.C);
   wr(out, (int64_t)a.C * g.n_pi);
   return hipSuccess;
 }
 hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int32_t *level_ptr,
-                                int32_t depth, int64_t, GridBarrier bar, hipStream_t) {
+                                int32_t depth, int64_t, GridBarrier bar, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(level_ptr, depth + 2);
   wr(bar.words, kBarrierWords);
   rd(bar.words + kBarrierReport, 1);
@@ -315,6 +521,7 @@ hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
                                  int32_t depth, int64_t, float *pi_out, GridBarrier bar,
                                  hipStream_t s) {
+  Scope sc_(s);
   rd(level_ptr, depth + 2);
   wr(bar.words, kBarrierWords);
   rd(bar.words + kBarrierReport, 1);
@@ -322,6 +529,7 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
 }
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
                            hipStream_t st) {
+  Scope sc_(st);
   for (int32_t k = 0; k < n_segs; ++k) {
     const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
     if (b1 < b0 || (int64_t)(b1 - b0) * kMergedBlock < (int64_t)segs[k].lv.n * segs[k].lv.B) {
@@ -334,6 +542,7 @@ hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, b
 }
 hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
                             hipStream_t st) {
+  Scope sc_(st);
   for (int32_t k = 0; k < n_segs; ++k) {
     const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
     if (b1 < b0 || (int64_t)(b1 - b0) * kMergedBlock < (int64_t)segs[k].n * segs[k].a.C) {
@@ -346,7 +555,8 @@ hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks,
 }
 hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const int32_t *int2ext,
                                      int32_t n_pi, int32_t n_nets, int32_t B, int32_t C,
-                                     int32_t, float, float *lam_out, float *score, hipStream_t) {
+                                     int32_t, float, float *lam_out, float *score, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(lam, (int64_t)n_nets * C);
   rd(sp, (int64_t)n_nets * B);
   rd(int2ext, n_nets);
@@ -354,13 +564,15 @@ hipError_t launch_grad_lambda_export(const float *lam, const float *sp, const in
   if (score) wr(score, (int64_t)(n_nets - n_pi) * C);
   return hipSuccess;
 }
-hipError_t launch_virus_step(float *sp, const float *grad, float, int32_t n_pi, int32_t B, hipStream_t) {
+hipError_t launch_virus_step(float *sp, const float *grad, float, int32_t n_pi, int32_t B, hipStream_t stream_) {
+  Scope sc_(stream_);
   wr(sp, (int64_t)n_pi * B);
   rd(grad, (int64_t)n_pi * B);
   return hipSuccess;
 }
 hipError_t launch_virus_vectors(const float *sp, uint64_t *stim, uint8_t *v0, float *p_out,
-                                int32_t n_pi, int32_t B, hipStream_t) {
+                                int32_t n_pi, int32_t B, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(sp, (int64_t)n_pi * B);
   wr(stim, (int64_t)n_pi * B * 2);
   wr(v0, (int64_t)n_pi * B);
@@ -368,13 +580,15 @@ hipError_t launch_virus_vectors(const float *sp, uint64_t *stim, uint8_t *v0, fl
   return hipSuccess;
 }
 hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_nets, int32_t B,
-                              double *out, hipStream_t) {
+                              double *out, hipStream_t stream_) {
+  Scope sc_(stream_);
   rd(tog, (int64_t)n_nets * B);
   rd(cap, n_nets);
   wr(out, B);
   return hipSuccess;
 }
-hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t) {
+hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t stream_) {
+  Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
   rd(a.xterm, nb);
   rd(a.cap, a.n_nets);

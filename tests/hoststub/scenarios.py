@@ -215,8 +215,54 @@ def scenario_group_serving(ctx):
     return out
 
 
+def scenario_capture_order(ctx):
+    """The order in which a host crash was once seen on the GPU: design
+    groups and serving, then the autotuner (graph candidates, several
+    simulation streams) on a hybrid eval, in one process; then graph
+    captures of multi-column hybrid sweeps and of a hybrid design group.
+    The stand-in runtime checks every capture's forks and joins, the calls
+    a capturing thread may not make, event reuse across captures, and that
+    each graph launch touches only live allocations."""
+    out = scenario_group_serving(ctx)
+    nl = synth.random_dag(synth.SPECS["dag2k"], 13)
+    d = api.Design(ctx, nl)
+    cap = synth.net_caps(nl.n_nets, 14)
+    for B in (1, 2, 3):
+        ev = api.Eval(d, B, mode=L.DP_HYBRID, n_sim=64 * 512, seed=8)
+        ev.set_pi_prob(synth.pi_probs(nl.n_pi, 13, batch=B))
+        ev.set_caps(cap)
+        ev.forward(("sp", "ones", "toggles", "power"))
+        ev.autotune(2, with_backward=True)
+        ev.forward(("sp", "ones", "toggles", "power"))
+        ev.backward(want=("dpi",))
+        for chunk, lanes in ((128, 2), (0, 1), (128, 3)):
+            ev.set_schedule(L.DP_SCHED_GRAPH, chunk, 0)
+            ev.set_sim_streams(lanes)
+            ev.forward(("power",))
+            ev.backward(want=("dpi",))
+        ev.close()
+    evs = []
+    for i in range(3):
+        e = api.Eval(d, 2, mode=L.DP_HYBRID if i else L.DP_MODELED, n_sim=64 * 16, seed=i)
+        e.set_pi_prob(synth.pi_probs(nl.n_pi, 40 + i, batch=2))
+        e.set_caps(cap)
+        evs.append(e)
+    grp = api.Group(ctx, evs)
+    for use_graph in (True, False, True):
+        grp.configure(use_graph=use_graph)
+        grp.run(("power",), backward=True)
+    grp.close()
+    out["capture_order_done"] = True
+    import ctypes
+    counts = (ctypes.c_long * 3)()
+    ctypes.CDLL(sys.argv[1]).stub_capture_counts(counts)
+    out["captures"], out["forks"], out["graph_launches"] = counts[0], counts[1], counts[2]
+    return out
+
+
 if __name__ == "__main__":
     context = api.Context(0)
     result = {"compile": scenario_compile, "flows": scenario_flows,
-              "group_serving": scenario_group_serving}[sys.argv[2]](context)
+              "group_serving": scenario_group_serving,
+              "capture_order": scenario_capture_order}[sys.argv[2]](context)
     print(json.dumps(result), flush=True)

@@ -12,7 +12,8 @@ import pytest
 import oracle
 from paper_2608_03778_amd import _lib as L
 from paper_2608_03778_amd import api, synth
-from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, oracle_column, say)
+from tests.gpu_helpers import (SP_ABS, assert_beta_close, assert_grad_close, assert_power_close,
+                               oracle_column, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,8 +41,7 @@ def _check_forward(res, f, col, hybrid):
         np.testing.assert_allclose(res["sp_acc"][col], f["sp_acc"], atol=SP_ABS, rtol=0)
         np.testing.assert_allclose(res["tr_acc"][col], f["tr_acc"], atol=SP_ABS, rtol=0)
         np.testing.assert_allclose(res["tr_hyb"][col], f["tr_hyb"], atol=SP_ABS, rtol=0)
-        ok = f["tr_model"] > 1e-3
-        np.testing.assert_allclose(res["beta"][col][ok], f["beta"][ok], rtol=2e-4, atol=0)
+        assert_beta_close(res["beta"][col], res["tr"][col], f, "beta")
 
 
 @pytest.mark.parametrize("c", range(len(synth.LIBRARY)))

@@ -11,7 +11,8 @@ import pytest
 import oracle
 from paper_2608_03778_amd import _lib as L
 from paper_2608_03778_amd import api, synth
-from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, oracle_column, say)
+from tests.gpu_helpers import (SP_ABS, assert_beta_close, assert_grad_close, assert_power_close,
+                               oracle_column, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +66,7 @@ def test_markov_counts_match_oracle(ctx, sched, chunk, lanes, T):
         np.testing.assert_allclose(res["sp"][b], f["sp"], atol=SP_ABS, rtol=0)
         np.testing.assert_allclose(res["tr_acc"][b], f["tr_acc"], atol=SP_ABS, rtol=0)
         np.testing.assert_allclose(res["tr_hyb"][b], f["tr_hyb"], atol=SP_ABS, rtol=0)
+        assert_beta_close(res["beta"][b], res["tr"][b], f, f"beta[{b}]")
         assert_power_close(res["power"][b], f["power"], f"power[{b}]")
         assert_grad_close(g["dpi"][b], adj["dpi"], f"dP/dp[{b}]")
     # the shared stream with one (p, tau): identical PI words, so equal counts

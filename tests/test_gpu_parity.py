@@ -11,7 +11,8 @@ import oracle
 from paper_2608_03778_amd import _lib as L
 from paper_2608_03778_amd import api, synth
 from tests import brute
-from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, oracle_column, say)
+from tests.gpu_helpers import (SP_ABS, assert_beta_close, assert_grad_close, assert_power_close,
+                               oracle_column, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +40,7 @@ def _check_forward(res, f, col, hybrid):
         np.testing.assert_allclose(res["sp_acc"][col], f["sp_acc"], atol=SP_ABS, rtol=0)
         np.testing.assert_allclose(res["tr_acc"][col], f["tr_acc"], atol=SP_ABS, rtol=0)
         np.testing.assert_allclose(res["tr_hyb"][col], f["tr_hyb"], atol=SP_ABS, rtol=0)
-        # beta = TR_acc / TR_model: its float32 error is relative to TR_model's
-        ok = f["tr_model"] > 1e-3
-        np.testing.assert_allclose(res["beta"][col][ok], f["beta"][ok], rtol=2e-4, atol=0)
+        assert_beta_close(res["beta"][col], res["tr"][col], f, "beta")
 
 
 @pytest.mark.parametrize("op", range(9))

@@ -9,7 +9,8 @@ import pytest
 import oracle
 from paper_2608_03778_amd import _lib as L
 from paper_2608_03778_amd import api, rank, synth
-from tests.gpu_helpers import (SP_ABS, assert_grad_close, assert_power_close, say)
+from tests.gpu_helpers import (SP_ABS, assert_beta_close, assert_grad_close, assert_power_close,
+                               say)
 from oracle.parallel import sim_counts
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -31,7 +32,7 @@ def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=()):
     ev = api.Eval(d, 1, mode=L.DP_HYBRID, n_sim=n_sim, seed=seed)
     ev.set_pi_prob(p)
     ev.set_caps(cap)
-    res = ev.forward(("sp", "tr", "tr_acc", "tr_hyb", "ones", "toggles", "power"))
+    res = ev.forward(("sp", "tr", "tr_acc", "tr_hyb", "beta", "ones", "toggles", "power"))
     g = ev.backward(want=("dpi", "dcap"))
     say(f"{name}: oracle")
     o = oracle.Netlist.of(nl)
@@ -45,6 +46,7 @@ def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=()):
     np.testing.assert_allclose(res["tr"][0], f["tr_model"], atol=SP_ABS, rtol=0)
     np.testing.assert_allclose(res["tr_acc"][0], f["tr_acc"], atol=SP_ABS, rtol=0)
     np.testing.assert_allclose(res["tr_hyb"][0], f["tr_hyb"], atol=SP_ABS, rtol=0)
+    assert_beta_close(res["beta"][0], res["tr"][0], f, f"{name} beta")
     assert_power_close(res["power"], f["power"], f"{name} power")
     assert_grad_close(g["dpi"][0], adj["dpi"], f"{name} dP/dp")
     assert_grad_close(g["dcap"], adj["dcap"], f"{name} dP/dC")

@@ -72,3 +72,15 @@ def test_groups_and_serving(stub_lib):
     assert r["served"] == 60 and r["completed"] >= 60 and r["batched"]
     assert r["nan_size"] == "DP_E_INVALID" and r["bad_p"] == "DP_E_INVALID"
     assert r["unknown_ticket"] == "DP_E_NOTFOUND" and r["budget"] == "DP_E_BUDGET"
+
+
+def test_capture_order_under_the_capture_model(stub_lib):
+    """Groups and serving, then the autotuner and graph-captured multi-column
+    hybrid sweeps and a captured hybrid design group, in one process, under
+    the stand-in's capture model (forks and joins, calls a capturing thread
+    may not make, event reuse across captures, graph launches touching only
+    live allocations).  Captures record one stream, so nothing forks."""
+    r = _run(stub_lib, "capture_order")
+    assert r["capture_order_done"] and r["served"] == 60
+    assert r["captures"] > 20 and r["graph_launches"] > 100
+    assert r["forks"] == 0
