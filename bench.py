@@ -277,6 +277,13 @@ def sizing_bench(ctx, reps=3):
         ev.backward_columns(device=True)
     t_b = time_steps(batched, reps, 1)
     t_f = time_steps(lambda: ev.forward(("power",), device=True), reps, 1)
+    tuned = ev.get_schedule()
+    # the same sweeps captured: one graph launch for the forward (one
+    # stimulus and one launch per level for all 32 columns, finalize,
+    # power) and one for the reverse sweep
+    ev.set_schedule(L.DP_SCHED_GRAPH)
+    t_gb = time_steps(batched, reps, 1)
+    t_gf = time_steps(lambda: ev.forward(("power",), device=True), reps, 1)
     one = api.Eval(d, 1, 1, mode=L.DP_HYBRID, n_sim=65536, seed=1)
     one.set_pi_prob(p[:1])
     one.set_caps(cap)
@@ -289,10 +296,12 @@ def sizing_bench(ctx, reps=3):
     t_1 = time_steps(single, reps, 1)
     return dict(design="dag117k", columns=B, size_vectors=S, results=B * S, n_sim=65536,
                 batched_fwd_ms=t_f * 1e3, batched_fwdbwd_ms=t_b * 1e3,
+                graph_fwd_ms=t_gf * 1e3, graph_fwdbwd_ms=t_gb * 1e3,
+                graph_launches_per_query=2,
                 single_query_fwdbwd_ms=t_1 * 1e3,
                 one_at_a_time_fwdbwd_ms=t_1 * 1e3 * B * S,
-                speedup_vs_one_at_a_time=t_1 * B * S / t_b,
-                schedule=ev.get_schedule())
+                speedup_vs_one_at_a_time=t_1 * B * S / min(t_b, t_gb),
+                schedule=tuned)
 
 
 def scale_bench(ctx, reps=3):
@@ -410,11 +419,19 @@ def modeled_form(args, schedule_name, B):
     pr = ev.get_profile()
     ev.profile(False)
     fwd_bytes, bwd_bytes = pr["sp_bytes"], pr["bwd_bytes"]
+    # nominal per-gate bytes (every operand at natural width, once per use,
+    # whatever this path fuses away): 8 of structure, 20 per gate-column
+    # forward (fan-in SP 8, SP write 4, capacitance 4, TR 4) and 40 reverse
+    # (upstream adjoint 4, fan-in SP 8, edge write 8 and pull 8, seed 12)
+    nom_fwd, nom_fwdbwd = G * (8 + 20 * B), G * (8 + 60 * B)
     return dict(columns=B, schedule=ev.get_schedule(), fwd_us=tf * 1e6, fwdbwd_us=tfb * 1e6,
                 fwd_gate_evals_s=G * B / tf, fwdbwd_gate_evals_s=G * B / tfb,
                 fwd_bytes=fwd_bytes, bwd_bytes=bwd_bytes,
                 fwd_hbm_frac=fwd_bytes / tf / 1e9 / HBM_PEAK_GBS,
-                fwdbwd_hbm_frac=(fwd_bytes + bwd_bytes) / tfb / 1e9 / HBM_PEAK_GBS)
+                fwdbwd_hbm_frac=(fwd_bytes + bwd_bytes) / tfb / 1e9 / HBM_PEAK_GBS,
+                nominal_fwd_bytes=nom_fwd, nominal_fwdbwd_bytes=nom_fwdbwd,
+                nominal_fwd_hbm_frac=nom_fwd / tf / 1e9 / HBM_PEAK_GBS,
+                nominal_fwdbwd_hbm_frac=nom_fwdbwd / tfb / 1e9 / HBM_PEAK_GBS)
 
 
 def group_form(args):
@@ -508,6 +525,13 @@ def virus_form(args):
     v0, pf, pv = ev.power_virus(steps, eta)
     dt = time.perf_counter() - t0
     log(f"[form] power virus: {steps} steps in {dt * 1e3:.1f} ms, P_virus {pv[0]:.1f}")
+    # step-size sensitivity: the same ascent at other step sizes
+    sens = {}
+    for f in (0.25, 4.0, 16.0):
+        ev.set_pi_prob(np.full(nl.n_pi, 0.5, np.float32))
+        _, _, pvf = ev.power_virus(steps, eta * f)
+        sens[f"eta_x{f:g}"] = float(pvf[0])
+    log(f"[form] power virus step sizes: {sens}")
     rnd = api.Eval(d, 64, mode=L.DP_MODELED)
     rnd.set_caps(cap)
     rnd.set_pi_prob(np.random.default_rng(11).uniform(0, 1, (64, nl.n_pi)).astype(np.float32))
@@ -515,6 +539,7 @@ def virus_form(args):
     return dict(design=args.workload, gates=nl.n_gates, steps=steps, eta=eta,
                 ascent_ms=dt * 1e3, ms_per_step=dt * 1e3 / steps,
                 p_virus=float(pv[0]), total_cap=float(cap.astype(np.float64).sum()),
+                p_virus_other_step_sizes=sens,
                 random_pairs_mean=float(pv_rand.mean()), random_pairs_max=float(pv_rand.max()),
                 gain_over_random_mean=float(pv[0] / pv_rand.mean()),
                 gain_over_random_max=float(pv[0] / pv_rand.max()))

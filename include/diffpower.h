@@ -433,9 +433,9 @@ dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * forward as dp_forward on a one-column eval in DP_MODELED or DP_FROZEN_BETA
  * (per-level launches; bit for bit the same results), without an eval: the
- * SP, the internal capacitances and beta, the per-net power terms and
- * the power partial sums live in a static device array of the library
- * (32 MiB on each GPU it runs on, held until the process ends; its
+ * SP, the internal capacitances and beta and the power partial sums
+ * live in a static device array of the library
+ * (24 MiB on each GPU it runs on, held until the process ends; its
  * device address is resolved once per GPU by dp_ctx_create).  The call
  * allocates nothing, enqueues on the design's context stream and does not
  * synchronize; the caller still provides every input and output.

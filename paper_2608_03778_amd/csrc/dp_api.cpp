@@ -298,9 +298,12 @@ dp_status sync_and_check(dp_eval *ev) {
   return barrier_status(ev);
 }
 
-// Per-net beta of the last forward, or null in modeled mode (beta = 1).
+// Per-net beta [n_nets][B] of the last forward: the computed one (hybrid),
+// the frozen one as given, or null in modeled mode (beta = 1).  (A frozen
+// beta shared by every column is [n_nets]: see backward_args.)
 float *beta_or_null(dp_eval *ev) {
-  return ev->prm.mode == DP_MODELED ? nullptr : ev->beta.as<float>();
+  if (ev->prm.mode == DP_MODELED) return nullptr;
+  return ev->prm.mode == DP_HYBRID ? ev->beta.as<float>() : ev->beta_frozen.as<float>();
 }
 
 // Whether the forward draws Markov stimulus words (a target transition rate
@@ -319,8 +322,7 @@ int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
 dp_status ensure_forward_buffers(dp_eval *ev, const ChunkPlan *pl) {
   const dp_design *d = ev->d;
   const size_t nb = (size_t)d->n_nets * ev->B;
-  if (ev->prm.mode != DP_MODELED) DP_TRY(ev->beta.alloc(nb * sizeof(float)));
-  DP_TRY(ev->xterm.alloc(nb * sizeof(float)));
+  if (ev->prm.mode == DP_HYBRID) DP_TRY(ev->beta.alloc(nb * sizeof(float)));
   const int32_t cols = ev->B * s_prime(ev);
   DP_TRY(ev->power_partial.alloc(
       (size_t)dp::power_partial_doubles(d->n_nets, ev->B, ev->S, ev->paired_sizes) *
@@ -471,33 +473,24 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   return enqueue_forward_tail(ev, pl);
 }
 
-// Finalize (TR, beta, xterm) and the power reduction of a swept forward.
+// The power terms (TR, beta) and their sum over nets, after a forward sweep.
 dp_status enqueue_forward_tail(dp_eval *ev, const ChunkPlan *pl) {
   const dp_design *d = ev->d;
   hipStream_t s = ev->stream();
   float *sp = ev->sp.as<float>();
-  dp::FinalizeArgs fa{};
-  fa.sp = sp;
-  fa.ones = pl ? ev->ones.as<uint32_t>() : nullptr;
-  fa.tog = pl ? ev->tog.as<uint32_t>() : nullptr;
-  fa.beta_frozen = ev->prm.mode == DP_FROZEN_BETA ? ev->beta_frozen.as<float>() : nullptr;
-  fa.beta_shared = ev->beta_shared;
-  fa.cap = ev->cap.as<float>();
-  fa.T = pl ? pl->T : 0;
-  fa.kappa = (float)kappa_of(ev->prm);
-  fa.beta_min = (float)ev->prm.beta_min;
-  fa.beta_max = (float)ev->prm.beta_max;
-  fa.mode = ev->prm.mode;
-  fa.ste = ev->prm.beta_grad == DP_BETA_STE;
-  fa.beta = beta_or_null(ev);
-  fa.xterm = ev->xterm.as<float>();
-  fa.n_nets = d->n_nets;
-  fa.B = ev->B;
-  DP_HIP_TRY(dp::launch_finalize(fa, s));
   dp::PowerArgs pa{};
-  pa.xterm = ev->xterm.as<float>();
+  pa.sp = sp;
+  pa.tog = pl ? ev->tog.as<uint32_t>() : nullptr;
+  pa.beta_frozen = ev->prm.mode == DP_FROZEN_BETA ? ev->beta_frozen.as<float>() : nullptr;
+  pa.beta_shared = ev->beta_shared;
   pa.cap = ev->cap.as<float>();
   pa.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
+  pa.T = pl ? pl->T : 0;
+  pa.kappa = (float)kappa_of(ev->prm);
+  pa.beta_min = (float)ev->prm.beta_min;
+  pa.beta_max = (float)ev->prm.beta_max;
+  pa.mode = ev->prm.mode;
+  pa.beta = hybrid(ev) ? ev->beta.as<float>() : nullptr;  // hybrid: stored on the way
   pa.n_pi = d->n_pi;
   pa.n_nets = d->n_nets;
   pa.G = d->n_gates;
@@ -659,7 +652,12 @@ dp::BwdArgs backward_args(dp_eval *ev, const float *w, int per_column, int32_t C
   const dp_design *d = ev->d;
   dp::BwdArgs ba{};
   ba.sp = ev->sp.as<float>();
-  ba.beta = beta_or_null(ev);
+  if (ev->beta_shared && ev->prm.mode == DP_FROZEN_BETA) {  // one beta per net (serving)
+    ba.beta = ev->beta_frozen.as<float>();
+    ba.beta_shared = 1;
+  } else {
+    ba.beta = beta_or_null(ev);
+  }
   ba.cap = ev->cap.as<float>();
   ba.w = w;
   ba.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
@@ -1296,7 +1294,11 @@ static dp_status run_backward(dp_eval *ev, const float *grad_power, int per_colu
   if (dcap || (dsize && ev->S > 0)) {
     OutMap om{ev, on_device};
     dp::GradExportArgs ga{};
-    ga.xterm = ev->xterm.as<float>();
+    ga.sp = ev->sp.as<float>();
+    ga.beta = beta_or_null(ev);
+    ga.beta_shared = ev->beta_shared && ev->prm.mode == DP_FROZEN_BETA;
+    if (ga.beta_shared) ga.beta = ev->beta_frozen.as<float>();
+    ga.kappa = (float)kappa_of(ev->prm);
     ga.cap = ev->cap.as<float>();
     ga.w = w;
     ga.size = ev->S > 0 ? ev->size.as<float>() : nullptr;
@@ -1832,7 +1834,6 @@ dp_status dp_group_run(dp_group *g, int32_t backward, const dp_fwd_out *outs,
     mix((uint64_t)(uintptr_t)ev->sp.ptr);
     mix((uint64_t)(uintptr_t)ev->beta.ptr);
     mix((uint64_t)(uintptr_t)ev->cap.ptr);
-    mix((uint64_t)(uintptr_t)ev->xterm.ptr);
   }
   // modeled evals go into the merged level launches; the others (hybrid)
   // run on the branches
@@ -1938,9 +1939,10 @@ namespace dp {
 
 size_t lane_bytes(const dp_design *d, int32_t capacity) {
   const size_t nn = d->n_nets, G = d->n_gates, np = d->n_pi;
-  // SP, beta and the per-net power term per net; contributions per edge;
-  // sizes (and their staging) per gate; probabilities (and staging, dP/dp)
-  const size_t per_col = 4 * (3 * nn + (size_t)d->n_edges + 2 * G + 2 * np) +
+  // SP per net (the frozen beta is one per net, shared by the columns);
+  // contributions per edge; sizes (and their staging) per gate;
+  // probabilities (and staging, dP/dp)
+  const size_t per_col = 4 * (nn + (size_t)d->n_edges + 2 * G + 2 * np) +
                          8 * (size_t)power_chunks(d->n_nets) + 16;
   return (size_t)capacity * per_col + 8 * nn;
 }
@@ -1967,8 +1969,7 @@ dp_status lane_create(dp_design *d, int32_t capacity, const dp_params *prm, hipS
   A(ev->size, (size_t)capacity * d->n_gates * 4);
   A(ev->size_stage, (size_t)capacity * d->n_gates * 4);
   A(ev->p_stage, (size_t)capacity * d->n_pi * 4);
-  if (prm->mode != DP_MODELED) A(ev->beta, nn * capacity * 4);
-  A(ev->xterm, nn * capacity * 4);
+  if (prm->mode == DP_HYBRID) A(ev->beta, nn * capacity * 4);
   A(ev->power_partial, (size_t)power_chunks(d->n_nets) * capacity * 8);
   A(ev->power, (size_t)capacity * 4);
   A(ev->contrib, (size_t)d->n_edges * capacity * 4);
@@ -2017,21 +2018,7 @@ dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bo
   DP_HIP_TRY(hipMemcpyAsync(power, ev->power.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, s));
   if (backward) {
     const GraphView g = view(d);
-    BwdArgs ba{};
-    ba.sp = ev->sp.as<float>();
-    ba.beta = beta_or_null(ev);
-    ba.cap = ev->cap.as<float>();
-    ba.size = size ? ev->size.as<float>() : nullptr;
-    ba.contrib = ev->contrib.as<float>();
-    ba.kappa = (float)kappa_of(ev->prm);
-    ba.n_pi = d->n_pi;
-    ba.G = d->n_gates;
-    ba.B = n;
-    ba.S = ev->S;
-    ba.C = n;
-    ba.cdiv = 1;
-    ba.ste = ev->prm.beta_grad == DP_BETA_STE;
-    ba.paired = ev->paired_sizes;
+    const BwdArgs ba = backward_args(ev, nullptr, 0, n);
     for (int32_t l = d->depth; l >= 1; --l)
       DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
         DP_HIP_TRY(launch_bwd_level(g, ba, g0, n, cells, s));

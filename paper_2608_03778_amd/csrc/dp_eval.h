@@ -38,8 +38,7 @@ struct dp_eval {
   // forward state
   dp::DevBuf words;          // simulation chunk [n_nets][pitch]
   dp::DevBuf ones, tog;      // [n_nets][B]
-  dp::DevBuf beta;           // [n_nets][B] (not in modeled mode)
-  dp::DevBuf xterm;          // [B][n_nets]
+  dp::DevBuf beta;           // [n_nets][B] computed beta (hybrid mode only)
   dp::DevBuf power_partial;  // [chunks][B*S'] double
   dp::DevBuf power;          // [B*S']
   dp::DevBuf flag;           // int32 validation flag

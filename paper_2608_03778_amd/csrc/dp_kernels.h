@@ -118,23 +118,6 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
                             const SimTune &tune, hipStream_t s);
 
-// Finalize per internal net and column: beta, X = kappa*beta*TR_model, the
-// local adjoint seed base, optional caller-numbered exports.
-struct FinalizeArgs {
-  const float *sp;          // [n_nets][B]
-  const uint32_t *ones, *tog;  // [n_nets][B] or null (modeled)
-  const float *beta_frozen; // [n_nets][B], or [n_nets] when beta_shared, or null
-  int32_t beta_shared;      // one frozen beta for every column
-  const float *cap;         // [n_nets] internal
-  int64_t T;                // simulated words
-  float kappa, beta_min, beta_max;
-  int32_t mode, ste;
-  float *beta;              // out [n_nets][B], or null (modeled: beta = 1)
-  float *xterm;             // out [B][n_nets] kappa * beta * TR_model
-  int32_t n_nets, B;
-};
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
-
 // Caller-numbered exports of forward quantities, [B][n_nets].
 struct ExportArgs {
   const float *sp;            // [n_nets][B]
@@ -148,10 +131,24 @@ struct ExportArgs {
 };
 hipError_t launch_export(const ExportArgs &a, hipStream_t s);
 
-// Power P[b][s] = sum_n xterm[b][n] * cap[n] * size_s(n), double accumulation
-// in a fixed order.  partial: [n_chunks][B*S'] doubles.
+// The per-net power terms and their sum (Eq. 1, 2, 5).  For net n and
+// column b: TR_model = 2 P (1 - P); beta = 1 (modeled), the frozen beta,
+// or in hybrid mode clip(TR_acc / TR_model) with TR_acc = toggles /
+// (64 (T - 1)) (0/0 -> 1, x/0 -> beta_max), stored in `beta`; the term
+// x = kappa beta TR_model, and P[b][s] = sum_n x[n][b] C_n s_s(drv n),
+// accumulated in double in an order fixed by the net index alone.  No
+// per-net term array is stored: whatever needs x again (the gradient with
+// respect to C and s) recomputes it from SP and beta.
 struct PowerArgs {
-  const float *xterm, *cap, *size;  // size: [S][G] internal or null
+  const float *sp;                  // [n_nets][B]
+  const uint32_t *tog;              // [n_nets][B] toggle counts (hybrid), or null
+  const float *beta_frozen;         // [n_nets][B], [n_nets] when beta_shared, or null
+  int32_t beta_shared;              // one frozen beta for every column
+  const float *cap, *size;          // cap [n_nets] internal; size [S][G] internal or null
+  int64_t T;                        // simulated words (hybrid)
+  float kappa, beta_min, beta_max;
+  int32_t mode;                     // DP_MODELED, DP_HYBRID, DP_FROZEN_BETA
+  float *beta;                      // out [n_nets][B] (hybrid), or null
   int32_t n_pi, n_nets, G, B, S;    // S = 0: no sizes
   int32_t paired;                   // column b uses size row b; power is [B]
   double *partial;                  // scratch
@@ -171,7 +168,7 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s);
 //   otherwise (contracted): sum_s w[b][s] s_s(n).
 struct BwdArgs {
   const float *sp;            // [n_nets][B]
-  const float *beta;          // [n_nets][B], or null (beta = 1)
+  const float *beta;          // [n_nets][B], [n_nets] when beta_shared, or null (beta = 1)
   const float *cap;           // [n_nets] internal
   const float *w;             // [B][S'] (null = 1)
   const float *size;          // [S][G] internal, or null (all 1)
@@ -180,6 +177,7 @@ struct BwdArgs {
   const uint8_t *fixed;       // [n_pi]: nonzero = excluded from the gradients (0), or null
   float kappa;
   int32_t n_pi, G, B, S, C, cdiv, ste, per_column, paired;
+  int32_t beta_shared;        // one beta per net for every column
 };
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
                             bool cells, hipStream_t s);
@@ -266,9 +264,14 @@ hipError_t launch_sp_persistent(const GraphView &g, const SpLevel &lv, const int
 hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int32_t *level_ptr,
                                  int32_t depth, int64_t max_items, float *pi_out,
                                  GridBarrier bar, hipStream_t s);
-// dcap[ext n] = sum_{b,s} w[b][s] xterm[b][n] size_s(n); dsize likewise.
+// dcap[ext n] = sum_{b,s} w[b][s] x[n][b] size_s(n) and dsize[s][ext g] =
+// sum_b w[b][s] x[out g][b] C_out g, with x = kappa beta TR_model
+// recomputed from SP and beta.
 struct GradExportArgs {
-  const float *xterm;         // [B][n_nets]
+  const float *sp;            // [n_nets][B]
+  const float *beta;          // [n_nets][B], [n_nets] when beta_shared, or null (beta = 1)
+  int32_t beta_shared;
+  float kappa;
   const float *cap;           // [n_nets]
   const float *w;             // [B][S'] or null
   const float *size;          // [S][G] internal or null

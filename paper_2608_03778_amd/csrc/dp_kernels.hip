@@ -2,15 +2,12 @@
 //
 // Layouts (internal net numbering, see dp_design):
 //   SP (packed, see sp_load)       float  [n_nets][B]      (query column innermost)
-//   beta                           float  [n_nets][B]      (absent when modeled)
-//   xterm                          float  [B][n_nets]      (net innermost: the power
-//                                                          and gradient reductions
-//                                                          run along nets)
+//   beta                           float  [n_nets][B]      (hybrid; a frozen beta is read as given)
 //   contrib                        float  [n_edges][C]     (fan-out order of the reader)
 //   simulation words W             uint64 [n_nets][pitch]  (one chunk of cycles)
 //   ones, toggles                  uint32 [n_nets][B]
 //
-// Work mapping: the SP, finalize and reverse kernels give one lane to each
+// Work mapping: the SP and reverse kernels give one lane to each
 // (gate or net, column).  The simulation kernel gives one 64-lane wave to a
 // (gate, run of word pairs): the wave's cell is uniform, so the cell switch
 // is a scalar branch outside the word loop; each lane moves 16-byte word
@@ -182,8 +179,8 @@ __device__ f2 cell_sp(const LaneCode &lc, const f2 *x) {
 // operation, which instructions produced its operands (the stack holds
 // instruction indices).  Every value feeds exactly one later instruction
 // (the code is a tree), so the backward pass visits the instructions from
-// the last to the first with each adjoint complete when reached: an
-// operation hands its adjoint to its operands' instructions times the local
+// the last to the first and finds each adjoint set, once, by its consumer:
+// an operation sets its operands' adjoints to its own times the local
 // derivative (AND: the other operand; OR: its complement; XOR: q - p of the
 // other operand; NOT: -1), and an input instruction adds its adjoint to the
 // input's partial.
@@ -195,7 +192,6 @@ __device__ void cell_partials(const LaneCode &lc, const f2 *x, float *d) {
   int top = 0;
   for (int i = 0; i < lc.len; ++i) {
     const int w = code_at(lc, i), op = w & 0xff;
-    adj[i] = 0.0f;
     if (op == kCellIn) {
       val[i] = x[w >> 8];
     } else if (op == kCellZero) {
@@ -220,13 +216,13 @@ __device__ void cell_partials(const LaneCode &lc, const f2 *x, float *d) {
     if (op == kCellIn) {
       d[w >> 8] += a;
     } else if (op == kCellNot) {
-      adj[lhs[i]] -= a;
+      adj[lhs[i]] = -a;
     } else if (op == kCellAnd || op == kCellOr || op == kCellXor) {
       const f2 u = val[lhs[i]], v = val[rhs[i]];
       const float du = op == kCellAnd ? v.x : (op == kCellOr ? v.y : v.y - v.x);
       const float dv = op == kCellAnd ? u.x : (op == kCellOr ? u.y : u.y - u.x);
-      adj[lhs[i]] += a * du;
-      adj[rhs[i]] += a * dv;
+      adj[lhs[i]] = a * du;
+      adj[rhs[i]] = a * dv;
     }
   }
 }
@@ -262,6 +258,17 @@ __device__ __forceinline__ int64_t gidx() {
 constexpr int64_t kMaxBlocks = (1ll << 32) / kBlock - 1;
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned level_blocks(int64_t n) { return (unsigned)((n + kLevelBlock - 1) / kLevelBlock); }
+// SP level launches of many lanes take 256-thread workgroups: a dependent
+// launch of 5,000 one-wave workgroups costs about 0.3 us more than one of
+// 1,250 four-wave workgroups, while a few waves still spread over as many
+// CUs as one-wave workgroups give them.
+constexpr int kWideBlock = 256;
+constexpr int64_t kWideLanes = 65536;
+inline unsigned level_block(int64_t lanes) { return lanes >= kWideLanes ? kWideBlock : kLevelBlock; }
+inline unsigned level_grid(int64_t lanes) {
+  const int64_t bs = level_block(lanes);
+  return (unsigned)((lanes + bs - 1) / bs);
+}
 inline bool too_big(int64_t items) { return (items + kBlock - 1) / kBlock > kMaxBlocks; }
 
 // ---------------------------------------------------------------- plumbing
@@ -360,24 +367,25 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
     sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(lc, x));
     return;
   }
-  // every gather is issued before the opcode is known, so the level costs
-  // two dependent load rounds (indices, then probabilities)
+  // the opcode and every pin's index arrive in one load round; the second
+  // round gathers the probabilities of the pins the gate has
   const int32_t i0 = g.in[gi];
   const int32_t i1 = pin_row(g.in, g, 1)[gi];
   const int32_t i2 = pin_row(g.in, g, 2)[gi];
   gathers_done(op, i0, i1, i2);
-  const float sa = sp[(int64_t)i0 * B + b];
-  const float sb = sp[(int64_t)i1 * B + b];
-  const float sc = sp[(int64_t)i2 * B + b];
-  gathers_done(sa, sb, sc);
   const int k = arity_of(op);
+  const float sa = sp[(int64_t)i0 * B + b];
+  float sb = 0.0f, sc = 0.0f;
+  if (k > 1) sb = sp[(int64_t)i1 * B + b];
+  if (k > 2) sc = sp[(int64_t)i2 * B + b];
+  gathers_done(sa, sb, sc);
   const f2 z = f2{0.0f, 1.0f};
   sp[(int64_t)(g.n_pi + gi) * B + b] =
       settle(sp_rule(op, sp_load(sa), k > 1 ? sp_load(sb) : z, k > 2 ? sp_load(sc) : z));
 }
 
-__global__ __launch_bounds__(kLevelBlock) void k_sp_level(GraphView g, SpLevel lv) {
-  const uint32_t idx = blockIdx.x * kLevelBlock + threadIdx.x;
+__global__ __launch_bounds__(kWideBlock) void k_sp_level(GraphView g, SpLevel lv) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item<false>(g, lv, idx);
 }
 
@@ -390,8 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_sp_cells(GraphView g, SpLevel lv) {
 // access moves two stored probabilities, and half as many waves cover the
 // level.
 
-__global__ __launch_bounds__(kLevelBlock) void k_sp_level_x2(GraphView g, SpLevel lv) {
-  const uint32_t idx = blockIdx.x * kLevelBlock + threadIdx.x;
+__global__ __launch_bounds__(kWideBlock) void k_sp_level_x2(GraphView g, SpLevel lv) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t half = (uint32_t)lv.B / 2;
   if (idx >= (uint32_t)lv.n * half) return;
   const uint32_t gl = idx / half;
@@ -407,8 +415,9 @@ __global__ __launch_bounds__(kLevelBlock) void k_sp_level_x2(GraphView g, SpLeve
   const int32_t i2 = pin_row(g.in, g, 2)[gi];
   gathers_done(op, i0, i1, i2);
   const f2 a = sp2[(int64_t)i0 * B2 + b / 2];
-  const f2 bl = sp2[(int64_t)i1 * B2 + b / 2];
-  const f2 cl = sp2[(int64_t)i2 * B2 + b / 2];
+  f2 bl = f2{0.0f, 0.0f}, cl = f2{0.0f, 0.0f};
+  if (k > 1) bl = sp2[(int64_t)i1 * B2 + b / 2];
+  if (k > 2) cl = sp2[(int64_t)i2 * B2 + b / 2];
   gathers_done(a.x, a.y, bl.x, bl.y, cl.x, cl.y);
   const float r0 = settle(sp_rule(op, sp_load(a.x), k > 1 ? sp_load(bl.x) : z,
                                   k > 2 ? sp_load(cl.x) : z));
@@ -827,49 +836,33 @@ __global__ __launch_bounds__(kBlock) void k_stimulus(int32_t n_pi, ChunkView c, 
   }
 }
 
-// ---------------------------------------------------------------- finalize
-// Per (net, column): TR_model = 2P(1-P) (Eq. 2); in hybrid mode
-// TR_acc = toggles / (64 (T-1)) (Eq. 4) and beta = clip(TR_acc / TR_model)
-// (Eq. 5, 0/0 -> 1, x/0 -> beta_max); xterm = kappa beta TR_model is the
-// per-unit-capacitance power of the net (Eq. 1).
-// A block owns a tile of tn nets x tb columns (tb = min(B, 64), tn * tb <=
-// kFinTile): beta is written in [n][b] order, xterm is staged
-// in LDS and written transposed, [b][n], so both sides stay coalesced.
-constexpr int32_t kFinTile = 2048;
+// ---------------------------------------------------------------- beta and terms
+// The hybrid beta of a net whose TR_model is tm and whose simulation counted
+// tog toggles: clip(TR_acc / TR_model) with TR_acc = toggles / (64 (T - 1))
+// (Eq. 4-5; 0/0 -> 1, x/0 -> beta_max).
+__device__ __forceinline__ float hybrid_beta(const PowerArgs &a, uint32_t tog, float tm) {
+  const float ta = (float)((double)tog / (64.0 * (double)(a.T - 1)));
+  const float beta = tm == 0.0f ? (ta == 0.0f ? 1.0f : a.beta_max) : ta / tm;
+  return fminf(fmaxf(beta, a.beta_min), a.beta_max);
+}
 
-__global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a, int32_t tb, int32_t tn) {
-  __shared__ float xt[kFinTile + 64];
-  const int32_t tiles_b = (a.B + tb - 1) / tb;
-  const int32_t n0 = (int32_t)(blockIdx.x / tiles_b) * tn;
-  const int32_t b0 = (int32_t)(blockIdx.x % tiles_b) * tb;
-  const int32_t items = tn * tb;
-  for (int32_t e = threadIdx.x; e < items; e += kBlock) {
-    const int32_t r = e / tb, c = e - r * tb;
-    const int32_t n = n0 + r, b = b0 + c;
-    if (n >= a.n_nets || b >= a.B) continue;
-    const int64_t idx = (int64_t)n * a.B + b;
-    const f2 pq = sp_load(a.sp[idx]);
-    const float tm = 2.0f * pq.x * pq.y;
-    float beta = 1.0f;
-    if (a.mode == 1) {
-      const float ta = (float)((double)a.tog[idx] / (64.0 * (double)(a.T - 1)));
-      if (tm == 0.0f)
-        beta = (ta == 0.0f) ? 1.0f : a.beta_max;
-      else
-        beta = ta / tm;
-      beta = fminf(fmaxf(beta, a.beta_min), a.beta_max);
-    } else if (a.mode == 2) {
-      beta = a.beta_shared ? a.beta_frozen[n] : a.beta_frozen[idx];
-    }
-    if (a.beta) a.beta[idx] = beta;
-    xt[c * (tn + 1) + r] = a.kappa * beta * tm;
-  }
-  __syncthreads();
-  for (int32_t e = threadIdx.x; e < items; e += kBlock) {
-    const int32_t c = e / tn, r = e - c * tn;
-    const int32_t n = n0 + r, b = b0 + c;
-    if (n < a.n_nets && b < a.B) a.xterm[(int64_t)b * a.n_nets + n] = xt[c * (tn + 1) + r];
-  }
+// beta of net n in column b (idx = n B + b) with TR_model = tm: 1 in modeled
+// mode, the frozen value, or the hybrid value.
+__device__ __forceinline__ float beta_of(const PowerArgs &a, int64_t idx, int32_t n, float tm) {
+  if (a.mode == 1) return hybrid_beta(a, a.tog[idx], tm);
+  if (a.mode == 2) return a.beta_shared ? a.beta_frozen[n] : a.beta_frozen[idx];
+  return 1.0f;
+}
+
+// The hybrid beta of every (net, column), for the contraction with many
+// size vectors (the sum over nets with one or paired sizes takes it in the
+// same pass, k_power_sp).
+__global__ __launch_bounds__(kBlock) void k_beta(PowerArgs a) {
+  const int64_t idx = gidx();
+  if (idx >= (int64_t)a.n_nets * a.B) return;
+  const int32_t n = (int32_t)(idx / a.B);
+  const f2 pq = sp_load(a.sp[idx]);
+  a.beta[idx] = beta_of(a, idx, n, 2.0f * pq.x * pq.y);
 }
 
 __global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
@@ -891,10 +884,90 @@ __global__ __launch_bounds__(kBlock) void k_export(ExportArgs a) {
 }
 
 // ---------------------------------------------------------------- power
-// P[b][s] = sum_n xterm[n][b] C_n s_s(drv n), accumulated in double: one
-// block per (chunk of nets, column), fixed thread -> net map, LDS tree, then
-// a fixed-order sum over chunks.  The result is independent of the launch.
-constexpr int32_t kPowerChunk = 8192;
+// P[b] = sum_n x[n][b] C_n s_b(drv n) with x = kappa beta TR_model, one or
+// paired sizes, accumulated in double in an order fixed by the net index
+// alone, so a column's power does not depend on the launch it rides in:
+// nets in chunks of kPowerChunk; lane j of kPowerLanes sums the chunk's
+// nets j, j + kPowerLanes, ... in increasing order; the lane sums are added
+// by a fixed pairwise tree (stride 32, 16, ..., 1); the chunks by
+// k_power_final.  A block takes one chunk for a tile of tb columns (tb a
+// power of two up to 64), the column innermost, so a wave's SP loads are
+// whole row segments of tb columns; with tb = 64 a thread keeps the sums
+// of several lanes.  Each term is computed where it is summed, and in
+// hybrid mode beta is stored on the way.  The column tiles of one chunk go
+// to blocks of one XCD (blocks are dealt to the XCDs in turn), which then
+// share the chunk's capacitance and size lines in their L2.
+constexpr int32_t kPowerChunk = 2048;
+constexpr int32_t kPowerLanes = 64;
+constexpr int32_t kPowerCols = 64;       // columns per block at most
+constexpr int32_t kPowerThreads = 1024;  // threads per block at most
+constexpr int32_t kPowerBatch = 8;       // terms per thread whose loads go out together
+constexpr int32_t kXcds = 8;
+
+// NQ lanes per thread (1 for tb <= 16 columns, 2 for 32, 4 for 64); MODE
+// is the beta mode (0 modeled, 1 hybrid, 2 frozen).  Every operand of a
+// round's eight terms is loaded (at a clamped, valid address) before the
+// first term is formed; a term past the chunk's end is dropped.
+template <int NQ, int MODE>
+__global__ __launch_bounds__(kPowerThreads) void k_power_sp(PowerArgs a, int32_t tb,
+                                                           int32_t col_tiles) {
+  constexpr int U = kPowerBatch / NQ;  // nets of each lane per round
+  constexpr int32_t jper = kPowerLanes / NQ;
+  __shared__ double lds[kPowerLanes * kPowerCols];
+  const int32_t xcd = (int32_t)(blockIdx.x % kXcds), slot = (int32_t)(blockIdx.x / kXcds);
+  const int32_t chunk = (slot / col_tiles) * kXcds + xcd;
+  const int32_t tile = slot - (slot / col_tiles) * col_tiles;
+  if (chunk >= a.n_chunks) return;  // the grid's round-up to whole XCD rounds
+  const int32_t c = (int32_t)threadIdx.x % tb, j0 = (int32_t)threadIdx.x / tb;
+  const int32_t b = tile * tb + c;
+  const int32_t n_lo = chunk * kPowerChunk, n_hi = min(n_lo + kPowerChunk, a.n_nets);
+  const bool sized = a.size && a.paired;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (b < a.B) {
+    for (int32_t i0 = 0; n_lo + i0 * kPowerLanes < n_hi; i0 += U) {
+      // aux: the toggle count (hybrid) or the frozen beta's bits
+      float v[kPowerBatch], cv[kPowerBatch], sv[kPowerBatch];
+      uint32_t aux[kPowerBatch];
+#pragma unroll
+      for (int k = 0; k < kPowerBatch; ++k) {
+        const int32_t n = min(n_lo + j0 + (k / U) * jper + (i0 + k % U) * kPowerLanes, n_hi - 1);
+        const int64_t idx = (int64_t)n * a.B + b;
+        v[k] = a.sp[idx];
+        cv[k] = a.cap[n];
+        if constexpr (MODE == 1) aux[k] = a.tog[idx];
+        if constexpr (MODE == 2)
+          aux[k] = __float_as_uint(a.beta_frozen[a.beta_shared ? (int64_t)n : idx]);
+        sv[k] = (sized && n >= a.n_pi) ? a.size[(int64_t)b * a.G + max(n - a.n_pi, 0)] : 1.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < kPowerBatch; ++k) {
+        const int32_t n = n_lo + j0 + (k / U) * jper + (i0 + k % U) * kPowerLanes;
+        if (n < n_hi) {
+          const f2 pq = sp_load(v[k]);
+          const float tm = 2.0f * pq.x * pq.y;
+          float beta = 1.0f;
+          if constexpr (MODE == 2) beta = __uint_as_float(aux[k]);
+          if constexpr (MODE == 1) {
+            beta = hybrid_beta(a, aux[k], tm);
+            a.beta[(int64_t)n * a.B + b] = beta;
+          }
+          acc[k / U] += (double)(a.kappa * beta * tm) * (double)(cv[k] * sv[k]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) lds[(j0 + q * jper) * tb + c] = acc[q];
+  __syncthreads();
+  for (int32_t stride = kPowerLanes / 2; stride > 0; stride >>= 1) {
+    for (int32_t e = threadIdx.x; e < stride * tb; e += blockDim.x)
+      lds[e] += lds[e + stride * tb];
+    __syncthreads();
+  }
+  if (threadIdx.x < tb && b < a.B) a.partial[(int64_t)chunk * a.B + b] = lds[c];
+}
 
 __device__ __forceinline__ double block_sum_d(double v, double *lds) {
 #pragma unroll
@@ -908,39 +981,8 @@ __device__ __forceinline__ double block_sum_d(double v, double *lds) {
   return r;
 }
 
-__global__ __launch_bounds__(kBlock) void k_power_partial(PowerArgs a) {
-  __shared__ double lds[kWavesPerBlock];
-  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
-  const int32_t n_cols = a.B * Sp;
-  const int32_t col = (int32_t)(blockIdx.x / a.n_chunks);  // b * S' + s
-  const int32_t chunk = (int32_t)(blockIdx.x - (uint32_t)col * a.n_chunks);
-  const int32_t b = col / Sp;
-  const int32_t s = a.paired ? b : col - b * Sp;
-  const int32_t n_lo = chunk * kPowerChunk;
-  const int32_t n_hi = min(n_lo + kPowerChunk, a.n_nets);
-  const float *__restrict__ x = a.xterm + (int64_t)b * a.n_nets;
-  auto term = [&](int32_t n, float xv) {
-    const float sz = (a.size && n >= a.n_pi) ? a.size[(int64_t)s * a.G + (n - a.n_pi)] : 1.0f;
-    return (double)xv * (double)(a.cap[n] * sz);
-  };
-  // each thread adds its nets n_lo + t, n_lo + t + 256, ... in that order;
-  // eight loads are issued before their eight adds
-  double acc = 0.0;
-  int32_t n = n_lo + threadIdx.x;
-  for (; n + 7 * kBlock < n_hi; n += 8 * kBlock) {
-    float xv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = x[n + u * kBlock];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc += term(n + u * kBlock, xv[u]);
-  }
-  for (; n < n_hi; n += kBlock) acc += term(n, x[n]);
-  const double r = block_sum_d(acc, lds);
-  if (threadIdx.x == 0) a.partial[(int64_t)chunk * n_cols + col] = r;
-}
-
 // Many size vectors (S > 0, not paired): P[b][s] = sum_n X[n][b] Y[n][s]
-// with X = xterm and Y[n][s] = C_n s_s(drv n) is a small dense product
+// with X[n][b] = kappa beta TR_model and Y[n][s] = C_n s_s(drv n) is a small dense product
 // (B x N) (N x S).  A block owns a 32 x 64 (b, s) tile and one slab of nets;
 // X and Y slabs are staged through LDS and each thread accumulates 8 outputs
 // in double.  Partials [slab][b][s] are summed over slabs in a fixed order.
@@ -964,11 +1006,20 @@ __global__ __launch_bounds__(kBlock) void k_power_tiled(PowerArgs a, int32_t n_s
 #pragma unroll
   for (int j = 0; j < 8; ++j) acc[j] = 0.0;
   for (int32_t base = n_lo; base < n_hi; base += kStage) {
-    // stage X[n][b0..b0+31] and Y[n][s0..s0+63] for kStage nets
+    // stage X[n][b0..b0+31] (x = kappa beta TR_model from SP and beta) and
+    // Y[n][s0..s0+63] for kStage nets
     for (int e = tid; e < kStage * kTileB; e += kBlock) {
-      const int cb = e / kStage, r = e % kStage;  // consecutive lanes walk nets
+      const int cb = e % kTileB, r = e / kTileB;  // consecutive lanes walk columns
       const int32_t n = base + r, b = b0 + cb;
-      xs[r][cb] = (n < n_hi && b < a.B) ? a.xterm[(int64_t)b * a.n_nets + n] : 0.0f;
+      float x = 0.0f;
+      if (n < n_hi && b < a.B) {
+        const int64_t idx = (int64_t)n * a.B + b;
+        const f2 pq = sp_load(a.sp[idx]);
+        const float tm = 2.0f * pq.x * pq.y;
+        const float beta = a.mode == 1 ? a.beta[idx] : beta_of(a, idx, n, tm);
+        x = a.kappa * beta * tm;
+      }
+      xs[r][cb] = x;
     }
     for (int e = tid; e < kStage * kTileS; e += kBlock) {
       const int cs = e / kStage, r = e % kStage;  // consecutive lanes walk nets
@@ -1216,7 +1267,7 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
   const int op = g.op[gi];
   const f2 pq = sp_load(sp[(int64_t)out * a.B + b]);
-  const float beta = a.beta ? a.beta[(int64_t)out * a.B + b] : 1.0f;
+  const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)out : (int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
     const float pulled =
@@ -1283,9 +1334,9 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
 }
 
 template <bool CELLS, bool WIDE>
-__global__ __launch_bounds__(kLevelBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
+__global__ __launch_bounds__(kWideBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
                                                            int32_t n) {
-  bwd_item<CELLS, WIDE>(g, a, g0, n, blockIdx.x * kLevelBlock + threadIdx.x, threadIdx.x & 63);
+  bwd_item<CELLS, WIDE>(g, a, g0, n, blockIdx.x * blockDim.x + threadIdx.x, threadIdx.x & 63);
 }
 
 __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a, float *out,
@@ -1298,7 +1349,7 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   const int32_t e1 = active ? e1r : e0;
   const int32_t b = c / a.cdiv;
   const f2 pq = sp_load(a.sp[(int64_t)i * a.B + b]);
-  const float beta = a.beta ? a.beta[(int64_t)i * a.B + b] : 1.0f;
+  const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)i : (int64_t)i * a.B + b] : 1.0f;
   const float cap = a.cap[i];
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
   if (!active) return;
@@ -1512,9 +1563,30 @@ __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs 
 
 // dP/dC_n = sum_{b,s} w[b][s] kappa beta TR_model s_s(drv n);
 // dP/ds[s][g] = sum_b w[b][s] kappa beta TR_model C of g's output net.
-__global__ __launch_bounds__(kBlock) void k_grad_cap(GradExportArgs a) {
-  const int64_t n = gidx();
-  if (n >= a.n_nets) return;
+// x = kappa beta TR_model of net n in column b, recomputed as the forward's
+// power sum computed it.
+__device__ __forceinline__ float x_of(const GradExportArgs &a, int64_t n, int32_t b) {
+  const int64_t idx = n * a.B + b;
+  const f2 pq = sp_load(a.sp[idx]);
+  const float tm = 2.0f * pq.x * pq.y;
+  const float beta = a.beta ? a.beta[a.beta_shared ? n : idx] : 1.0f;
+  return a.kappa * beta * tm;
+}
+
+// One wave per 64 nets.  The x values of the nets' rows are staged through
+// LDS a tile of up to 32 columns at a time (consecutive lanes read
+// consecutive (net, column) entries, so the loads are whole row segments;
+// sixteen go out before the first store), then lane r sums its net's
+// columns in order.
+constexpr int32_t kCapRows = 64, kCapCols = 32, kCapBatch = 16;
+
+template <bool BETA>  // BETA: a beta array is present
+__global__ __launch_bounds__(kCapRows) void k_grad_cap(GradExportArgs a) {
+  __shared__ float xs[kCapRows][kCapCols + 1];
+  const int32_t r = (int32_t)threadIdx.x;
+  const int64_t n0 = (int64_t)blockIdx.x * kCapRows;
+  const int64_t n = n0 + r;
+  const int32_t rows = (int32_t)min<int64_t>(kCapRows, a.n_nets - n0);
   const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const bool gate = n >= a.n_pi && a.size;
   auto weight = [&](int32_t b) {
@@ -1527,18 +1599,39 @@ __global__ __launch_bounds__(kBlock) void k_grad_cap(GradExportArgs a) {
     }
     return ws;
   };
-  // columns in order; eight xterm loads are issued before their adds
   double acc = 0.0;
-  int32_t b = 0;
-  for (; b + 8 <= a.B; b += 8) {
-    float xv[8];
+  for (int32_t b0 = 0; b0 < a.B; b0 += kCapCols) {
+    const int32_t tw = min(kCapCols, a.B - b0), total = rows * tw;
+    for (int32_t e0 = r; e0 < total; e0 += kCapBatch * kCapRows) {
+      float v[kCapBatch];
+      float bt[kCapBatch];
+      // (row, column) of entry e: shifts for a whole tile, else a division
+      const bool full = tw == kCapCols;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = a.xterm[(int64_t)(b + u) * a.n_nets + n];
+      for (int u = 0; u < kCapBatch; ++u) {  // clamped: every load is valid
+        const int32_t e = min(e0 + u * kCapRows, total - 1);
+        const int32_t rr = full ? e / kCapCols : e / tw;
+        const int64_t nn = n0 + rr, idx = nn * a.B + b0 + (e - rr * tw);
+        v[u] = a.sp[idx];
+        bt[u] = BETA ? a.beta[a.beta_shared ? nn : idx] : 1.0f;
+      }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += (double)xv[u] * (double)weight(b + u);
+      for (int u = 0; u < kCapBatch; ++u) {  // x as x_of forms it
+        const f2 pq = sp_load(v[u]);
+        v[u] = a.kappa * bt[u] * (2.0f * pq.x * pq.y);
+      }
+#pragma unroll
+      for (int u = 0; u < kCapBatch; ++u) {
+        const int32_t e = e0 + u * kCapRows, rr = full ? e / kCapCols : e / tw;
+        if (e < total) xs[rr][e - rr * tw] = v[u];
+      }
+    }
+    __syncthreads();
+    if (r < rows)
+      for (int32_t cc = 0; cc < tw; ++cc) acc += (double)xs[r][cc] * (double)weight(b0 + cc);
+    __syncthreads();
   }
-  for (; b < a.B; ++b) acc += (double)a.xterm[(int64_t)b * a.n_nets + n] * (double)weight(b);
-  a.dcap[a.int2ext[n]] = (float)acc;
+  if (r < rows) a.dcap[a.int2ext[n]] = (float)acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_grad_size(GradExportArgs a) {
@@ -1548,11 +1641,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_size(GradExportArgs a) {
   const int32_t n = a.n_pi + g;
   double acc = 0.0;
   if (a.paired) {  // size row s belongs to column s only
-    acc = (double)a.xterm[(int64_t)s * a.n_nets + n] * (double)(a.w ? a.w[s] : 1.0f);
+    acc = (double)x_of(a, n, s) * (double)(a.w ? a.w[s] : 1.0f);
   } else {
     for (int32_t b = 0; b < a.B; ++b) {
       const float w = a.w ? a.w[(int64_t)b * a.S + s] : 1.0f;
-      acc += (double)a.xterm[(int64_t)b * a.n_nets + n] * (double)w;
+      acc += (double)x_of(a, n, b) * (double)w;
     }
   }
   a.dsize[(int64_t)s * a.G + (a.int2ext[n] - a.n_pi)] = (float)(acc * (double)a.cap[n]);
@@ -1680,9 +1773,9 @@ hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hi
   if (cells)
     k_sp_cells<<<blocks_for(n), kBlock, 0, s>>>(g, lv);
   else if (lv.B % 2 == 0)
-    k_sp_level_x2<<<level_blocks(n / 2), kLevelBlock, 0, s>>>(g, lv);
+    k_sp_level_x2<<<level_grid(n / 2), level_block(n / 2), 0, s>>>(g, lv);
   else
-    k_sp_level<<<level_blocks(n), kLevelBlock, 0, s>>>(g, lv);
+    k_sp_level<<<level_grid(n), level_block(n), 0, s>>>(g, lv);
   return hipGetLastError();
 }
 
@@ -1758,17 +1851,6 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
-  const int64_t n = (int64_t)a.n_nets * a.B;
-  if (n <= 0) return hipSuccess;
-  const int32_t tb = std::min<int32_t>(a.B, 64);
-  const int32_t tn = kFinTile / tb;
-  const int64_t blocks = ((int64_t)a.n_nets + tn - 1) / tn * ((a.B + tb - 1) / tb);
-  if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-  k_finalize<<<(unsigned)blocks, kBlock, 0, s>>>(a, tb, tn);
-  return hipGetLastError();
-}
-
 hipError_t launch_export(const ExportArgs &a, hipStream_t s) {
   const int64_t n = (int64_t)a.n_nets * a.B;
   if (n <= 0) return hipSuccess;
@@ -1791,7 +1873,14 @@ int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t pair
 hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
   const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   const int32_t n_cols = a.B * Sp;
+  if ((int64_t)a.n_nets * a.B <= 0) return hipSuccess;
   if (a.S > 0 && !a.paired && a.size) {
+    if (a.mode == 1) {  // the hybrid beta first: the contraction reads it
+      if (!a.beta || too_big((int64_t)a.n_nets * a.B)) return hipErrorInvalidValue;
+      k_beta<<<blocks_for((int64_t)a.n_nets * a.B), kBlock, 0, s>>>(a);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     const int32_t n_slabs = (a.n_nets + kSlabNets - 1) / kSlabNets;
     const int64_t blocks = (int64_t)n_slabs * ((a.B + kTileB - 1) / kTileB) *
                            ((a.S + kTileS - 1) / kTileS);
@@ -1804,9 +1893,21 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
     k_power_final<<<(unsigned)n_cols, kBlock, 0, s>>>(f, n_cols);
     return hipGetLastError();
   }
-  const int64_t blocks = (int64_t)a.n_chunks * n_cols;
+  if (a.mode == 1 && !a.beta) return hipErrorInvalidValue;
+  if (a.n_chunks != power_chunks(a.n_nets)) return hipErrorInvalidValue;
+  int32_t tb = 1;
+  while (tb < a.B && tb < kPowerCols) tb *= 2;
+  const int32_t col_tiles = (a.B + tb - 1) / tb;
+  const int64_t blocks = (int64_t)kXcds * col_tiles * ((a.n_chunks + kXcds - 1) / kXcds);
   if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-  k_power_partial<<<(unsigned)blocks, kBlock, 0, s>>>(a);
+  if (a.mode < 0 || a.mode > 2) return hipErrorInvalidValue;
+  const unsigned threads = (unsigned)std::min(kPowerLanes * tb, kPowerThreads);
+  using K = void (*)(PowerArgs, int32_t, int32_t);
+  static const K table[3][3] = {{k_power_sp<1, 0>, k_power_sp<1, 1>, k_power_sp<1, 2>},
+                                {k_power_sp<2, 0>, k_power_sp<2, 1>, k_power_sp<2, 2>},
+                                {k_power_sp<4, 0>, k_power_sp<4, 1>, k_power_sp<4, 2>}};
+  const K kern = table[tb == 64 ? 2 : tb == 32 ? 1 : 0][a.mode];
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, s, a, tb, col_tiles);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_power_final<<<(unsigned)n_cols, kBlock, 0, s>>>(a, n_cols);
@@ -1822,9 +1923,9 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
   if (cells)
     k_bwd_level<true, false><<<level_blocks(items), kLevelBlock, 0, s>>>(g, a, g0, n);
   else if (a.C >= kSerialColumns)
-    k_bwd_level<false, true><<<level_blocks(items), kLevelBlock, 0, s>>>(g, a, g0, n);
+    k_bwd_level<false, true><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n);
   else
-    k_bwd_level<false, false><<<level_blocks(items), kLevelBlock, 0, s>>>(g, a, g0, n);
+    k_bwd_level<false, false><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n);
   return hipGetLastError();
 }
 
@@ -1901,7 +2002,11 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
 
 hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t s) {
   if (a.dcap && a.n_nets > 0) {
-    k_grad_cap<<<blocks_for(a.n_nets), kBlock, 0, s>>>(a);
+    const unsigned blocks = (unsigned)((a.n_nets + kCapRows - 1) / kCapRows);
+    if (a.beta)
+      k_grad_cap<true><<<blocks, kCapRows, 0, s>>>(a);
+    else
+      k_grad_cap<false><<<blocks, kCapRows, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -293,6 +293,13 @@ void admit(dp_server *s) {
       while (c2 < cap) c2 <<= 1;
       cap = std::min(c2, s->max_batch);
       while (cap > 1 && dp::lane_bytes(d, cap) > s->budget) cap >>= 1;
+      // under memory pressure a smaller lane that fits what is free now is
+      // preferred to freeing other designs' idle lanes: a lane costs
+      // allocations to create, which freeing throws away
+      const size_t free_now = s->used < s->budget ? s->budget - s->used : 0;
+      int32_t fit = cap;
+      while (fit > 1 && dp::lane_bytes(d, fit) > free_now) fit >>= 1;
+      if (dp::lane_bytes(d, fit) <= free_now) cap = fit;
       const size_t need = dp::lane_bytes(d, cap);
       if (s->used + need > s->budget && !make_room(s, need, r->design)) {
         s->st.memory_waits++;

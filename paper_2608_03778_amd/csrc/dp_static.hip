@@ -16,11 +16,10 @@ namespace {
 //   SP (stored form)      float  [n]      4 n bytes
 //   capacitance           float  [n]      4 n bytes (internal numbering)
 //   frozen beta           float  [n]      4 n bytes (internal numbering)
-//   per-net power term    float  [n]      4 n bytes (kappa beta TR_model)
 //   power partial sums    double [chunks]
 constexpr int64_t kMaxNets = int64_t(1) << 21;
 constexpr int64_t kPartBytes = 64 << 10;  // >= 8 * power_partial_doubles(kMaxNets, 1, 0, 0)
-constexpr int64_t kScratchBytes = 16 * kMaxNets + kPartBytes + 4 * 256;
+constexpr int64_t kScratchBytes = 12 * kMaxNets + kPartBytes + 3 * 256;
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -79,8 +78,7 @@ extern "C" dp_status dp_forward_static(const dp_design *d, const dp_params *prm,
   float *spp = reinterpret_cast<float *>(s0);
   float *capi = reinterpret_cast<float *>(s0 + up256(4 * (int64_t)nn));
   float *betai = reinterpret_cast<float *>(reinterpret_cast<char *>(capi) + up256(4 * (int64_t)nn));
-  float *xterm = reinterpret_cast<float *>(reinterpret_cast<char *>(betai) + up256(4 * (int64_t)nn));
-  double *part = reinterpret_cast<double *>(reinterpret_cast<char *>(xterm) + up256(4 * (int64_t)nn));
+  double *part = reinterpret_cast<double *>(reinterpret_cast<char *>(betai) + up256(4 * (int64_t)nn));
   if ((int64_t)dp::power_partial_doubles(nn, 1, 0, 0) * 8 > kPartBytes)
     return fail(DP_E_INVALID, "dp_forward_static: power partials exceed the static scratch");
 
@@ -95,23 +93,15 @@ extern "C" dp_status dp_forward_static(const dp_design *d, const dp_params *prm,
       DP_HIP_TRY(dp::launch_sp_level(g, dp::SpLevel{spp, 1, g0, n}, cells, s));
       return DP_OK;
     }));
-  dp::FinalizeArgs fa{};
-  fa.sp = spp;
-  fa.beta_frozen = beta ? betai : nullptr;
-  fa.beta_shared = 1;
-  fa.cap = capi;
-  fa.kappa = (float)dp::kappa(*prm);
-  fa.beta_min = (float)prm->beta_min;
-  fa.beta_max = (float)prm->beta_max;
-  fa.mode = prm->mode;
-  fa.ste = prm->beta_grad == DP_BETA_STE;
-  fa.xterm = xterm;
-  fa.n_nets = nn;
-  fa.B = 1;
-  DP_HIP_TRY(dp::launch_finalize(fa, s));
   dp::PowerArgs pa{};
-  pa.xterm = xterm;
+  pa.sp = spp;
+  pa.beta_frozen = beta ? betai : nullptr;
+  pa.beta_shared = 1;
   pa.cap = capi;
+  pa.kappa = (float)dp::kappa(*prm);
+  pa.beta_min = (float)prm->beta_min;
+  pa.beta_max = (float)prm->beta_max;
+  pa.mode = prm->mode;
   pa.n_pi = d->n_pi;
   pa.n_nets = nn;
   pa.G = d->n_gates;

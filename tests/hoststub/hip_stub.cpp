@@ -333,7 +333,7 @@ void rd_graph(const dp::GraphView &g, int32_t g0, int32_t n, bool cells) {
 }  // namespace
 
 namespace dp {
-constexpr int32_t kPowerChunk = 8192, kSlabNets = 2048;
+constexpr int32_t kPowerChunk = 2048, kSlabNets = 2048;
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream_) {
   Scope sc_(stream_);
@@ -440,18 +440,6 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   if (sp) wr(sp->sp + (int64_t)(g.n_pi + g0) * sp->B, (int64_t)n * sp->B);
   return hipSuccess;
 }
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t stream_) {
-  Scope sc_(stream_);
-  const int64_t nb = (int64_t)a.n_nets * a.B;
-  rd(a.sp, nb);
-  if (a.ones) rd(a.ones, nb);
-  if (a.tog) rd(a.tog, nb);
-  if (a.beta_frozen) rd(a.beta_frozen, a.beta_shared ? a.n_nets : nb);
-  rd(a.cap, a.n_nets);
-  if (a.beta) wr(a.beta, nb);
-  wr(a.xterm, nb);
-  return hipSuccess;
-}
 hipError_t launch_export(const ExportArgs &a, hipStream_t stream_) {
   Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
@@ -480,9 +468,16 @@ int32_t power_partial_doubles(int32_t n_nets, int32_t B, int32_t S, int32_t pair
 hipError_t launch_power(const PowerArgs &a, hipStream_t stream_) {
   Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
-  rd(a.xterm, nb);
+  rd(a.sp, nb);
+  if (a.mode == 1) {  // hybrid: toggle counts in, beta out
+    rd(a.tog, nb);
+    if (!a.beta) fatal("hybrid power without its beta output");
+    wr(a.beta, nb);
+  }
+  if (a.beta_frozen) rd(a.beta_frozen, a.beta_shared ? a.n_nets : nb);
   rd(a.cap, a.n_nets);
   if (a.S > 0 && a.size) rd(a.size, (int64_t)a.S * a.G);
+  if (a.n_chunks != power_chunks(a.n_nets)) fatal("power chunk count");
   wr(a.partial, power_partial_doubles(a.n_nets, a.B, a.S, a.paired));
   const int64_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
   wr(a.power, a.B * Sp);
@@ -498,7 +493,7 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
   if (a.w) rd(a.w, (int64_t)a.C);
   wr(a.contrib, CONTRIB_ELEMS(g) * a.C);
   if (a.lam) wr(a.lam, (int64_t)g.n_nets * a.C);
-  if (a.beta) rd(a.beta, (int64_t)g.n_nets * a.B);
+  if (a.beta) rd(a.beta, a.beta_shared ? (int64_t)g.n_nets : (int64_t)g.n_nets * a.B);
   if ((int64_t)a.C > (int64_t)a.B * a.cdiv) { std::fprintf(stderr, "STUB: C > B*cdiv\n"); std::abort(); }
   return hipSuccess;
 }
@@ -590,7 +585,8 @@ hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_n
 hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t stream_) {
   Scope sc_(stream_);
   const int64_t nb = (int64_t)a.n_nets * a.B;
-  rd(a.xterm, nb);
+  rd(a.sp, nb);
+  if (a.beta) rd(a.beta, a.beta_shared ? a.n_nets : nb);
   rd(a.cap, a.n_nets);
   rd(a.int2ext, a.n_nets);
   if (a.dcap) wr(a.dcap, a.n_nets);

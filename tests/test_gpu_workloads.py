@@ -38,7 +38,7 @@ def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=()):
     o = oracle.Netlist.of(nl)
     ones, tog = sim_counts(nl, p[0], T, seed)
     P = o.sp(p[0].astype(np.float64))
-    f = o.power(P, cap, hybrid=True, ones=ones, toggles=tog, n_words=T)
+    f = {**o.power(P, cap, hybrid=True, ones=ones, toggles=tog, n_words=T), "sp": P}
     adj = o.adjoint(P, f["beta"], cap)
     np.testing.assert_array_equal(res["ones"][0].astype(np.uint64), ones)
     np.testing.assert_array_equal(res["toggles"][0].astype(np.uint64), tog)
