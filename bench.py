@@ -48,12 +48,24 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+SIM_SOURCE_END = b"// ---------------------------------------------------------------- stimulus"
+
+
+def sim_source_sha(src):
+    """Hash of the kernel source the simulation launch compiles from: the
+    kernel file up to its stimulus section (cell functions, plumbing, the SP
+    rules fused into the launch, the simulation itself)."""
+    import hashlib
+    text = open(src, "rb").read()
+    end = text.find(SIM_SOURCE_END)
+    return hashlib.sha256(text[:end] if end > 0 else text).hexdigest()[:16]
+
+
 def measured_traffic(workload, n_sim, schedule):
     """HBM bytes per simulation launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
     the kernel source changed since the counters were taken or the launch
     configuration differs."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "sim_level_dag1m_traffic.txt")
     src = os.path.join(ROOT, "paper_2608_03778_amd", "csrc", "dp_kernels.hip")
     if workload != "dag1m" or n_sim != 65536 or schedule.get("pairs_per_lane") != 4 \
@@ -62,7 +74,7 @@ def measured_traffic(workload, n_sim, schedule):
     try:
         kv = dict(ln.strip().split("=", 1) for ln in open(path)
                   if "=" in ln and not ln.startswith("#"))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = sim_source_sha(src)
     except OSError:
         return None
     if kv.get("kernel_source_sha256_16") != sha:

@@ -697,11 +697,13 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
     SpanGuard sg(ev, SPAN_BWD, bwd_bytes, ev->profiling && d->depth > 0, d->depth + d->split_levels);
     for (int32_t l = d->depth; l >= 1; --l)
       DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
-        DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, cells, s));
+        const dp::HeavySpan hs = dp::heavy_span(d, g0, n);
+        DP_HIP_TRY(dp::launch_bwd_level(g, ba, g0, n, cells, s, hs.gates, hs.n));
         return DP_OK;
       }));
   }
-  DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s));
+  const dp::HeavySpan hp = dp::heavy_pis(d);
+  DP_HIP_TRY(dp::launch_bwd_pi(g, ba, dst, s, hp.gates, hp.n));
   return DP_OK;
 }
 
@@ -1678,8 +1680,9 @@ dp_status enqueue_merged(dp_group *g, hipStream_t origin, bool backward) {
   DP_TRY(g->tab.launch_reverse(bs, origin));
   for (int32_t i : g->merged) {
     dp_eval *ev = g->evs[i];
+    const dp::HeavySpan hp = dp::heavy_pis(ev->d);
     DP_HIP_TRY(dp::launch_bwd_pi(view(ev->d), backward_args(ev, nullptr, 0, ev->B),
-                                 ev->pi_out.as<float>(), origin));
+                                 ev->pi_out.as<float>(), origin, hp.gates, hp.n));
   }
   return DP_OK;
 }
@@ -2021,10 +2024,12 @@ dp_status lane_run(dp_eval *ev, int32_t n, const float *p, const float *size, bo
     const BwdArgs ba = backward_args(ev, nullptr, 0, n);
     for (int32_t l = d->depth; l >= 1; --l)
       DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
-        DP_HIP_TRY(launch_bwd_level(g, ba, g0, n, cells, s));
+        const HeavySpan hs = heavy_span(d, g0, n);
+        DP_HIP_TRY(launch_bwd_level(g, ba, g0, n, cells, s, hs.gates, hs.n));
         return DP_OK;
       }));
-    DP_HIP_TRY(launch_bwd_pi(g, ba, ev->pi_out.as<float>(), s));
+    const HeavySpan hp = heavy_pis(d);
+    DP_HIP_TRY(launch_bwd_pi(g, ba, ev->pi_out.as<float>(), s, hp.gates, hp.n));
     if (dpi && d->n_pi > 0)
       DP_HIP_TRY(hipMemcpyAsync(dpi, ev->pi_out.ptr, (size_t)n * d->n_pi * 4,
                                 hipMemcpyDeviceToHost, s));
@@ -2102,7 +2107,9 @@ dp_status lanes_run_merged(const LaneJob *jobs, int32_t n_jobs, hipStream_t s,
     if (!jobs[j].backward) continue;
     dp_eval *ev = jobs[j].ev;
     const dp_design *d = ev->d;
-    DP_HIP_TRY(launch_bwd_pi(view(d), backward_args(ev, nullptr, 0, ev->B), ev->pi_out.as<float>(), s));
+    const HeavySpan hp = heavy_pis(d);
+    DP_HIP_TRY(launch_bwd_pi(view(d), backward_args(ev, nullptr, 0, ev->B),
+                             ev->pi_out.as<float>(), s, hp.gates, hp.n));
     if (jobs[j].dpi && d->n_pi > 0)
       DP_HIP_TRY(hipMemcpyAsync(jobs[j].dpi, ev->pi_out.ptr, (size_t)jobs[j].n * d->n_pi * 4,
                                 hipMemcpyDeviceToHost, s));

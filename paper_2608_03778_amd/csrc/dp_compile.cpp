@@ -156,7 +156,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   // rounds, which then overlap the rest of the level instead of trailing
   // it, and with few columns no wave holds more than one of them, so each
   // wave's long ranges still go out in one round.
-  constexpr int32_t kHeavyFanout = 32;
+  constexpr int32_t kHeavyFanout = kHeavyPull;
   constexpr int32_t kSlots = 1024;  // per level: [kind 512][heavy 256][cell < 256]
   auto key_of = [&](int32_t g) {
     const int32_t op = internal_op(nl->op[g]);
@@ -278,6 +278,12 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
       d->lvl_read[l] += rev_ptr[n_pi + gi + 1] > rev_ptr[n_pi + gi];
     }
   d->lvl_fanout[0] = rev_ptr[n_pi] - rev_ptr[0];
+  // gates whose fan-out range the many-column reverse levels pull with
+  // whole workgroups (ascending internal id)
+  for (int32_t gi = 0; gi < G; ++gi)
+    if (rev_ptr[n_pi + gi + 1] - rev_ptr[n_pi + gi] > kHeavyPull) d->h_heavy.push_back(gi);
+  for (int32_t i = 0; i < n_pi; ++i)
+    if (rev_ptr[i + 1] - rev_ptr[i] > kHeavyPull) d->h_heavy_pi.push_back(i);
   d->lvl_fixed.assign(depth + 1, 0);
   for (int32_t l = 1; l <= depth; ++l) {
     const int32_t g0 = d->level_ptr[l], g1 = d->level_ptr[l + 1];
@@ -313,7 +319,9 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
       (st = upload(d->slot, slot, s)) != DP_OK ||
       (st = upload(d->level_dev, d->level_ptr, s)) != DP_OK ||
       (st = upload(d->int2ext, d->h_int2ext, s)) != DP_OK ||
-      (st = upload(d->ext2int, d->h_ext2int, s)) != DP_OK) {
+      (st = upload(d->ext2int, d->h_ext2int, s)) != DP_OK ||
+      (st = upload(d->heavy, d->h_heavy, s)) != DP_OK ||
+      (st = upload(d->heavy_pi, d->h_heavy_pi, s)) != DP_OK) {
     delete d;
     return st;
   }
@@ -324,7 +332,8 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   }
   d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
                               d->slot.bytes + d->int2ext.bytes + d->ext2int.bytes +
-                              d->code.bytes + d->cell.bytes + d->tt.bytes);
+                              d->code.bytes + d->cell.bytes + d->tt.bytes + d->heavy.bytes +
+                              d->heavy_pi.bytes);
   ctx_retain(ctx);
   *out = d;
   return DP_OK;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <string>
@@ -119,6 +120,10 @@ struct dp_design {
   dp::DevBuf level_dev; // int32 [depth + 2] device copy of level_ptr
   dp::DevBuf int2ext;   // int32 [n_nets]
   dp::DevBuf ext2int;   // int32 [n_nets]
+  // gates (internal ids, ascending) and PIs with more than kHeavyPull
+  // fan-out entries, and their device copies
+  std::vector<int32_t> h_heavy, h_heavy_pi;
+  dp::DevBuf heavy, heavy_pi;
   int64_t device_bytes = 0;
 };
 
@@ -150,6 +155,24 @@ dp_status for_level_parts(const dp_design *d, int32_t l, F &&f) {
   if (nf > 0) DP_TRY(f(g0, nf, false));
   if (nf < n) DP_TRY(f(g0 + nf, n - nf, true));
   return DP_OK;
+}
+
+// The heavy gates of the launch range [g0, g0 + n): a slice of the design's
+// ascending list.
+struct HeavySpan {
+  const int32_t *gates;
+  int32_t n;
+};
+inline HeavySpan heavy_span(const dp_design *d, int32_t g0, int32_t n) {
+  const auto lo = std::lower_bound(d->h_heavy.begin(), d->h_heavy.end(), g0);
+  const auto hi = std::lower_bound(lo, d->h_heavy.end(), g0 + n);
+  const int32_t k = (int32_t)(hi - lo);
+  return HeavySpan{k ? d->heavy.as<int32_t>() + (lo - d->h_heavy.begin()) : nullptr, k};
+}
+
+inline HeavySpan heavy_pis(const dp_design *d) {
+  const int32_t k = (int32_t)d->h_heavy_pi.size();
+  return HeavySpan{k ? d->heavy_pi.as<int32_t>() : nullptr, k};
 }
 
 // Parameter validation and kappa = energy_factor Vdd^2 f (Eq. 1), shared by

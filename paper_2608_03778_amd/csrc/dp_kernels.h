@@ -179,10 +179,20 @@ struct BwdArgs {
   int32_t n_pi, G, B, S, C, cdiv, ste, per_column, paired;
   int32_t beta_shared;        // one beta per net for every column
 };
+// Gates whose fan-out range has more than kHeavyPull entries are "heavy":
+// with kSerialColumns columns or more, heavy[0, n_heavy) lists the launch
+// range's heavy gates (internal ids, ascending; all of them, no others),
+// which cooperative workgroups pull; fewer columns ignore the list.
+constexpr int32_t kHeavyPull = 32;
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
-                            bool cells, hipStream_t s);
+                            bool cells, hipStream_t s, const int32_t *heavy = nullptr,
+                            int32_t n_heavy = 0);
 // PI adjoints -> out[c][n_pi].
-hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s);
+// heavy[0, n_heavy): every PI with more than kHeavyPull fan-out entries
+// (ascending), pulled by cooperative workgroups at kSerialColumns columns or
+// more; fewer columns ignore the list.
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s,
+                         const int32_t *heavy = nullptr, int32_t n_heavy = 0);
 
 // Several designs in one launch: one level index of every design of a group.
 // Segment k owns the blocks [block0_k, block0_{k+1}) (block0 ascending, the

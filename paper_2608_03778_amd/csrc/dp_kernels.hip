@@ -1247,9 +1247,12 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
 // WIDE (fixed cells): the launch's column count is at least kSerialColumns
 // (pulls are lane-serial); a choice per launch, so each form keeps its own
 // registers.  Library cells decide the pull per launch at run time.
+// skip_heavy (WIDE only): items of gates with more than kHeavyPull fan-out
+// entries are left to the launch's cooperative blocks (bwd_heavy).
 template <bool CELLS, bool WIDE>
 __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, int32_t g0,
-                                         int32_t n, uint32_t idx, int lane) {
+                                         int32_t n, uint32_t idx, int lane,
+                                         bool skip_heavy = false) {
   const bool active = idx < (uint32_t)n * (uint32_t)a.C;
   // lanes past the end read row g0 (a level has at least one gate) and
   // store nothing, so no load needs a guard for them
@@ -1320,6 +1323,8 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
     x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
     x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
   }
+  // (after every first- and second-round load has gone out)
+  if (WIDE && skip_heavy && e1r - e0 > kHeavyPull) return;
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, WIDE);
   if (!active) return;
   float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
@@ -1333,14 +1338,116 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   if (k > 2) a.contrib[(int64_t)s2 * a.C + c] = lam * d2;
 }
 
-template <bool CELLS, bool WIDE>
-__global__ __launch_bounds__(kWideBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
-                                                           int32_t n) {
-  bwd_item<CELLS, WIDE>(g, a, g0, n, blockIdx.x * blockDim.x + threadIdx.x, threadIdx.x & 63);
+// One gate with a long fan-out range, for 64 columns of a many-column
+// reverse level, by a whole workgroup.  Lane-serially, one lane would pull a
+// net's entries 32 at a time, one dependent round each (a 200-reader net:
+// seven rounds, the level's critical path).  Here the waves share the
+// strands: wave w sums strand groups w, w + waves, ... (four strands, 32
+// loads, per group) into LDS, and wave 0 folds the strand sums in strand
+// order: the canonical sum, bit for bit.  Wave 0 then finishes the item as
+// bwd_item does; its own values and fan-in gathers go out before the pull.
+constexpr int32_t kHeavyPass = 64;  // strand sums held in LDS at a time
+
+// The canonical sum of [e0, e1) for column c by the whole workgroup; the
+// result is meaningful in wave 0 (every thread must call it).
+__device__ __forceinline__ float heavy_pull(const float *__restrict__ contrib, int32_t e0,
+                                            int32_t e1, int32_t C, int32_t c) {
+  __shared__ float ss[kHeavyPass][64];
+  const int w = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6), lane = threadIdx.x & 63;
+  const int32_t strands = (e1 - e0 + kStrand - 1) / kStrand;
+  float pulled = 0.0f;
+  for (int32_t p0 = 0; p0 < strands; p0 += kHeavyPass) {
+    const int32_t np = min(kHeavyPass, strands - p0);
+    for (int32_t q = 4 * w; q < np; q += 4 * nw) {
+      const int32_t es = e0 + (p0 + q) * kStrand;
+      float v[4 * kStrand];
+#pragma unroll
+      for (int i = 0; i < 4 * kStrand; ++i)
+        v[i] = es + i < e1 ? contrib[(int64_t)(es + i) * C + c] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int32_t st = es + t * kStrand;
+        if (q + t < np) {
+          float sum = v[t * kStrand];
+#pragma unroll
+          for (int i = 1; i < kStrand; ++i)
+            if (st + i < e1) sum += v[t * kStrand + i];
+          ss[q + t][lane] = sum;
+        }
+      }
+    }
+    __syncthreads();
+    if (w == 0)
+      for (int32_t t = 0; t < np; ++t) pulled = (p0 == 0 && t == 0) ? ss[0][lane] : pulled + ss[t][lane];
+    __syncthreads();
+  }
+  return pulled;
 }
 
+__device__ __forceinline__ void bwd_heavy(const GraphView &g, const BwdArgs &a,
+                                          const int32_t *__restrict__ heavy, uint32_t hb) {
+  const int32_t cgroups = (a.C + 63) / 64;
+  const int32_t gi = heavy[hb / (uint32_t)cgroups];
+  const int32_t cg = (int32_t)(hb % (uint32_t)cgroups);
+  const int w = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const bool active = cg * 64 + lane < a.C;
+  const int32_t c = active ? cg * 64 + lane : cg * 64;  // idle lanes load in-row
+  const int32_t out = g.n_pi + gi;
+  const int32_t b = c / a.cdiv;
+  const float *sp = a.sp;
+  const f2 z = f2{0.0f, 1.0f};
+  const int32_t e0 = g.rev_ptr[out], e1 = g.rev_ptr[out + 1];
+  const int op = g.op[gi];
+  const int k = arity_of(op);
+  const f2 pq = sp_load(sp[(int64_t)out * a.B + b]);
+  const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)out : (int64_t)out * a.B + b] : 1.0f;
+  const float cap = a.cap[out];
+  const int32_t i0 = g.in[gi], s0 = g.slot[gi];
+  int32_t s1 = 0, s2 = 0;
+  f2 x1 = z, x2 = z;
+  const f2 x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
+  if (k > 1) {
+    s1 = g.slot[g.G + gi];
+    x1 = sp_load(sp[(int64_t)g.in[g.G + gi] * a.B + b]);
+  }
+  if (k > 2) {
+    s2 = g.slot[2 * g.G + gi];
+    x2 = sp_load(sp[(int64_t)g.in[2 * g.G + gi] * a.B + b]);
+  }
+  const float pulled = heavy_pull(a.contrib, e0, e1, a.C, c);
+  if (w != 0 || !active) return;
+  float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
+  if (a.ste) lam *= beta;
+  if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
+  float d0, d1, d2;
+  sp_partials(op, x0, k > 1 ? x1 : z, k > 2 ? x2 : z, d0, d1, d2);
+  a.contrib[(int64_t)s0 * a.C + c] = lam * d0;
+  if (k > 1) a.contrib[(int64_t)s1 * a.C + c] = lam * d1;
+  if (k > 2) a.contrib[(int64_t)s2 * a.C + c] = lam * d2;
+}
+
+// With many columns the first heavy_blocks blocks take the level's heavy
+// gates (heavy[0, n_heavy), in groups of 64 columns; first, so their longer
+// pulls start first), and the blocks after them the (gate, column) items,
+// skipping the heavy gates.
+template <bool CELLS, bool WIDE>
+__global__ __launch_bounds__(kWideBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
+                                                           int32_t n, const int32_t *heavy,
+                                                           int32_t n_heavy, uint32_t heavy_blocks) {
+  if constexpr (WIDE && !CELLS) {
+    if (blockIdx.x < heavy_blocks) {
+      bwd_heavy(g, a, heavy, blockIdx.x);
+      return;
+    }
+  }
+  bwd_item<CELLS, WIDE>(g, a, g0, n, (blockIdx.x - heavy_blocks) * blockDim.x + threadIdx.x,
+                        threadIdx.x & 63, n_heavy > 0);
+}
+
+// skip_heavy: PIs with more than kHeavyPull fan-out entries are left to the
+// launch's cooperative blocks (bwd_pi_heavy).
 __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a, float *out,
-                                            uint32_t idx, int lane) {
+                                            uint32_t idx, int lane, bool skip_heavy = false) {
   const bool active = idx < (uint32_t)g.n_pi * (uint32_t)a.C;
   const uint32_t i = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - i * (uint32_t)a.C) : 0;
@@ -1351,7 +1458,9 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   const f2 pq = sp_load(a.sp[(int64_t)i * a.B + b]);
   const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)i : (int64_t)i * a.B + b] : 1.0f;
   const float cap = a.cap[i];
-  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
+  const bool serial = a.C >= kSerialColumns;
+  if (serial && skip_heavy && e1r - e0 > kHeavyPull) return;  // (lane-serial pulls only)
+  const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, serial);
   if (!active) return;
   float lam = seed_of(a, (int32_t)i, c, b, pq, beta, cap) + pulled;
   if (a.ste) lam *= beta;
@@ -1360,8 +1469,40 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + i] = lam;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out) {
-  bwd_pi_item(g, a, out, blockIdx.x * kBlock + threadIdx.x, threadIdx.x & 63);
+// A PI with a long fan-out range, for 64 columns, by a whole workgroup (as
+// bwd_heavy for gates).
+__device__ __forceinline__ void bwd_pi_heavy(const GraphView &g, const BwdArgs &a, float *out,
+                                             const int32_t *__restrict__ heavy, uint32_t hb) {
+  const int32_t cgroups = (a.C + 63) / 64;
+  const int32_t i = heavy[hb / (uint32_t)cgroups];
+  const int32_t cg = (int32_t)(hb % (uint32_t)cgroups);
+  const int w = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const bool active = cg * 64 + lane < a.C;
+  const int32_t c = active ? cg * 64 + lane : cg * 64;
+  const int32_t b = c / a.cdiv;
+  const int32_t e0 = g.rev_ptr[i], e1 = g.rev_ptr[i + 1];
+  const f2 pq = sp_load(a.sp[(int64_t)i * a.B + b]);
+  const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)i : (int64_t)i * a.B + b] : 1.0f;
+  const float cap = a.cap[i];
+  const float pulled = heavy_pull(a.contrib, e0, e1, a.C, c);
+  if (w != 0 || !active) return;
+  float lam = seed_of(a, i, c, b, pq, beta, cap) + pulled;
+  if (a.ste) lam *= beta;
+  if (a.fixed && a.fixed[i]) lam = 0.0f;
+  out[(int64_t)c * g.n_pi + i] = lam;
+  if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + i] = lam;
+}
+
+// The first heavy_blocks blocks take the heavy PIs (many columns only).
+__global__ __launch_bounds__(kBlock) void k_bwd_pi(GraphView g, BwdArgs a, float *out,
+                                                   const int32_t *heavy, int32_t n_heavy,
+                                                   uint32_t heavy_blocks) {
+  if (blockIdx.x < heavy_blocks) {
+    bwd_pi_heavy(g, a, out, heavy, blockIdx.x);
+    return;
+  }
+  bwd_pi_item(g, a, out, (blockIdx.x - heavy_blocks) * kBlock + threadIdx.x, threadIdx.x & 63,
+              n_heavy > 0);
 }
 
 // ---------------------------------------------------------------- adjoints and scores
@@ -1916,24 +2057,38 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t s) {
 
 
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
-                            bool cells, hipStream_t s) {
+                            bool cells, hipStream_t s, const int32_t *heavy, int32_t n_heavy) {
   const int64_t items = (int64_t)n * a.C;
   if (items <= 0) return hipSuccess;
   if (items >= (1ll << 31)) return hipErrorInvalidValue;
-  if (cells)
-    k_bwd_level<true, false><<<level_blocks(items), kLevelBlock, 0, s>>>(g, a, g0, n);
-  else if (a.C >= kSerialColumns)
-    k_bwd_level<false, true><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n);
-  else
-    k_bwd_level<false, false><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n);
+  if (cells) {
+    k_bwd_level<true, false><<<level_blocks(items), kLevelBlock, 0, s>>>(g, a, g0, n, nullptr,
+                                                                          0, 0);
+  } else if (a.C >= kSerialColumns) {
+    if (n_heavy < 0 || (n_heavy > 0 && !heavy)) return hipErrorInvalidValue;
+    const int64_t hb = (int64_t)n_heavy * ((a.C + 63) / 64);
+    const int64_t blocks = hb + level_grid(items);
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    k_bwd_level<false, true><<<(unsigned)blocks, level_block(items), 0, s>>>(g, a, g0, n, heavy,
+                                                                            n_heavy, (uint32_t)hb);
+  } else {
+    k_bwd_level<false, false><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n,
+                                                                              nullptr, 0, 0);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s) {
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t s,
+                         const int32_t *heavy, int32_t n_heavy) {
   const int64_t items = (int64_t)g.n_pi * a.C;
   if (items <= 0) return hipSuccess;
   if (items >= (1ll << 31)) return hipErrorInvalidValue;
-  k_bwd_pi<<<blocks_for(items), kBlock, 0, s>>>(g, a, out);
+  if (n_heavy < 0 || (n_heavy > 0 && !heavy)) return hipErrorInvalidValue;
+  if (a.C < kSerialColumns) n_heavy = 0;
+  const int64_t hb = (int64_t)n_heavy * ((a.C + 63) / 64);
+  const int64_t blocks = hb + blocks_for(items);
+  if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+  k_bwd_pi<<<(unsigned)blocks, kBlock, 0, s>>>(g, a, out, heavy, n_heavy, (uint32_t)hb);
   return hipGetLastError();
 }
 

@@ -483,10 +483,26 @@ hipError_t launch_power(const PowerArgs &a, hipStream_t stream_) {
   wr(a.power, a.B * Sp);
   return hipSuccess;
 }
+constexpr int32_t kNoHeavyCheck = -1;  // a caller of the stand-in that passes no list
 hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, int32_t n,
-                            bool cells, hipStream_t stream_) {
+                            bool cells, hipStream_t stream_, const int32_t *heavy,
+                            int32_t n_heavy) {
   Scope sc_(stream_);
   rd_graph(g, g0, n, cells);
+  // the heavy list: every gate of the range whose fan-out range is longer
+  // than kHeavyPull, ascending, and nothing else
+  if ((n_heavy < 0 && n_heavy != kNoHeavyCheck) || (n_heavy > 0 && !heavy)) fatal("heavy list");
+  rd(heavy, n_heavy);
+  if (!cells && n_heavy != kNoHeavyCheck) {
+    int32_t k = 0;
+    for (int32_t gi = g0; gi < g0 + n; ++gi) {
+      const int32_t out = g.n_pi + gi;
+      if (g.rev_ptr[out + 1] - g.rev_ptr[out] <= dp::kHeavyPull) continue;
+      if (k >= n_heavy || heavy[k] != gi) fatal("heavy list misses a gate");
+      ++k;
+    }
+    if (k != n_heavy) fatal("heavy list holds a gate it should not");
+  }
   rd(a.sp, (int64_t)g.n_nets * a.B);
   rd(a.cap, g.n_nets);
   if (a.size) rd(a.size, (int64_t)(a.S > 0 ? a.S : a.B) * a.G);
@@ -497,8 +513,20 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
   if ((int64_t)a.C > (int64_t)a.B * a.cdiv) { std::fprintf(stderr, "STUB: C > B*cdiv\n"); std::abort(); }
   return hipSuccess;
 }
-hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t stream_) {
+hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipStream_t stream_,
+                         const int32_t *heavy, int32_t n_heavy) {
   Scope sc_(stream_);
+  if ((n_heavy < 0 && n_heavy != kNoHeavyCheck) || (n_heavy > 0 && !heavy)) fatal("heavy PI list");
+  rd(heavy, n_heavy);
+  if (n_heavy != kNoHeavyCheck) {  // every PI with a long fan-out range, ascending, no other
+    int32_t k = 0;
+    for (int32_t i = 0; i < g.n_pi; ++i) {
+      if (g.rev_ptr[i + 1] - g.rev_ptr[i] <= dp::kHeavyPull) continue;
+      if (k >= n_heavy || heavy[k] != i) fatal("heavy PI list misses a PI");
+      ++k;
+    }
+    if (k != n_heavy) fatal("heavy PI list holds a PI it should not");
+  }
   if (a.fixed) rd(a.fixed, g.n_pi);
   rd(a.contrib, CONTRIB_ELEMS(g) * a.C);
   wr(out, (int64_t)a.C * g.n_pi);
@@ -520,7 +548,7 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
   rd(level_ptr, depth + 2);
   wr(bar.words, kBarrierWords);
   rd(bar.words + kBarrierReport, 1);
-  return launch_bwd_pi(g, a, pi_out, s);
+  return launch_bwd_pi(g, a, pi_out, s, nullptr, kNoHeavyCheck);  // its own PI pass
 }
 hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, bool cells,
                            hipStream_t st) {
@@ -544,7 +572,9 @@ hipError_t launch_bwd_multi(const BwdSeg *segs, int32_t n_segs, uint32_t blocks,
       std::fprintf(stderr, "STUB: bwd segment %d too small\n", k);
       std::abort();
     }
-    launch_bwd_level(segs[k].g, segs[k].a, segs[k].g0, segs[k].n, cells, st);
+    // merged launches pull every gate in its own item (no heavy list)
+    launch_bwd_level(segs[k].g, segs[k].a, segs[k].g0, segs[k].n, cells, st, nullptr,
+                     kNoHeavyCheck);
   }
   return hipSuccess;
 }

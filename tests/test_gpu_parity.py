@@ -344,14 +344,16 @@ def test_errors_and_state(ctx):
 
 @pytest.mark.parametrize("B", [1, 3, 70])
 def test_heavy_fanout_reverse_sweep(ctx, B):
-    """Nets read by 3, 9, 70 and 200 gates (light and wave-cooperative pulls
-    of the reverse sweep) at B columns; every column's gradient equals the
-    oracle and is bitwise the same as the column computed alone."""
+    """Nets read by 3, 9, 70, 200 and 600 gates (light, wave-cooperative and,
+    from 32 columns, workgroup pulls of the reverse sweep; 600 readers take
+    two passes of the workgroup's strand sums) at B columns; every column's
+    gradient equals the oracle and is bitwise the same as the column
+    computed alone."""
     say(f"heavy fan-out B={B}")
     rng = np.random.default_rng(B)
     n_pi = 16
-    gates = [(synth.AND2, [0, 1]), (synth.XOR2, [2, 3])]  # nets 16, 17
-    for fo, src in ((200, 4), (70, 16), (9, 17), (3, 5)):
+    gates = [(synth.AND2, [0, 1]), (synth.XOR2, [2, 3]), (synth.OR2, [6, 7])]  # nets 16-18
+    for fo, src in ((200, 4), (70, 16), (600, 18), (9, 17), (3, 5)):
         for _ in range(fo):
             op = int(rng.integers(0, 9))
             k = int(synth.ARITY[op])
