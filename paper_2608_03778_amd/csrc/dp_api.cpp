@@ -458,9 +458,8 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       for (int32_t l = 1; l <= d->depth; ++l)
         DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
           const dp::SpLevel lv{sp, ev->B, g0, n};
-          if (fuse && cells) DP_HIP_TRY(dp::launch_sp_level(g, lv, true, ls));
-          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse && !cells ? &lv : nullptr, cells,
-                                          tune, ls));
+          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, cells, tune,
+                                          ls));
           return DP_OK;
         }));
     }

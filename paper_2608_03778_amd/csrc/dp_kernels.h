@@ -111,9 +111,8 @@ hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t 
                                hipStream_t s);
 
 // One simulation level of one chunk for the launch's columns, with the
-// level's SP (every column of the SpLevel) fused in when
-// sp != nullptr (fixed cells only: a library-cell range takes its SP from
-// launch_sp_level).
+// range's SP (every column of the SpLevel, the same gate range and kind)
+// fused in when sp != nullptr.
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
                             const SimTune &tune, hipStream_t s);

@@ -573,12 +573,10 @@ template <int ITERS, bool CELLS>
 __global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView c, CountView cnt,
                                                       int32_t g0, int32_t n, int32_t waves_per_row,
                                                       int32_t sim_blocks, SpLevel sp) {
-  if constexpr (!CELLS) {  // library cells take their SP in a launch of its own
-    if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level
-      const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kSimBlock + threadIdx.x;
-      if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item<false>(g, sp, idx);
-      return;
-    }
+  if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level (and kind)
+    const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kSimBlock + threadIdx.x;
+    if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item<CELLS>(g, sp, idx);
+    return;
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1961,7 +1959,6 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
                             const SimTune &tune, hipStream_t s) {
   if (n <= 0 || c.n_cols <= 0) return hipSuccess;
-  if (cells && sp) return hipErrorInvalidValue;  // no fused SP for library cells
   const int iters = cells ? min(tune.iters, 2) : tune.iters;  // cells: up to 6 input rows
   const int32_t wpr = waves_per_row(c, iters);
   const int64_t tasks = (int64_t)n * wpr * c.n_cols;

@@ -425,8 +425,8 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
                             const SimTune &, hipStream_t stream_) {
   Scope sc_(stream_);
-  if (cells && sp) { std::fprintf(stderr, "STUB: fused SP on a library-cell range\n"); std::abort(); }
   rd_graph(g, g0, n, cells);
+  if (sp && (sp->g0 != g0 || sp->n != n)) fatal("fused SP range differs from the simulation's");
   if (c.n_cols < 1 || cnt.col < 0 || cnt.col + c.n_cols > cnt.B) {
     std::fprintf(stderr, "STUB: simulation columns out of range\n");
     std::abort();
