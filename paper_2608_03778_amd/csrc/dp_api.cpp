@@ -458,8 +458,20 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
       for (int32_t l = 1; l <= d->depth; ++l)
         DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
           const dp::SpLevel lv{sp, ev->B, g0, n};
-          DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, cells, tune,
-                                          ls));
+          if (!cells) {
+            DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, n, fuse ? &lv : nullptr, false, tune,
+                                            ls));
+            return DP_OK;
+          }
+          // library cells: the narrow ones (sorted first) and the wider ones in
+          // launches of their own; the range's SP rides with the first
+          const int32_t ns = d->lvl_small_cells[l];
+          if (ns > 0)
+            DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0, ns, fuse ? &lv : nullptr, true, tune,
+                                            ls, dp::kSmallCellInputs));
+          if (ns < n)
+            DP_HIP_TRY(dp::launch_sim_level(g, cv, cnt, g0 + ns, n - ns,
+                                            fuse && ns == 0 ? &lv : nullptr, true, tune, ls));
           return DP_OK;
         }));
     }

@@ -157,13 +157,19 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   // it, and with few columns no wave holds more than one of them, so each
   // wave's long ranges still go out in one round.
   constexpr int32_t kHeavyFanout = kHeavyPull;
-  constexpr int32_t kSlots = 1024;  // per level: [kind 512][heavy 256][cell < 256]
+  // per level: [kind 1024][class 512][heavy 256][cell < 256]; the class of a
+  // library cell is its input count above kSmallCellInputs (the simulation
+  // runs the two classes in launches of their own), always 0 for fixed cells
+  constexpr int32_t kSlots = 2048;
+  auto big_cell = [&](int32_t op) {
+    return op >= dp::kCellBase && lib[logic_cell[op - dp::kCellBase]].n_in > kSmallCellInputs;
+  };
   auto key_of = [&](int32_t g) {
     const int32_t op = internal_op(nl->op[g]);
     const bool cell = op >= dp::kCellBase;
     const bool heavy = cons_ptr[g + 1] - cons_ptr[g] > kHeavyFanout;
-    return level[n_pi + g] * kSlots + (cell ? 512 : 0) + (heavy ? 0 : 256) +
-           (cell ? op - dp::kCellBase : op);
+    return level[n_pi + g] * kSlots + (cell ? 1024 : 0) + (big_cell(op) ? 512 : 0) +
+           (heavy ? 0 : 256) + (cell ? op - dp::kCellBase : op);
   };
   const int32_t n_keys = (depth + 1) * kSlots;
   std::vector<int32_t> key_ptr(n_keys + 1, 0);
@@ -173,10 +179,11 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   {
     std::vector<int32_t> fill(key_ptr.begin(), key_ptr.end() - 1);
     for (int32_t g = 0; g < G; ++g) gate_of[fill[key_of(g)]++] = g;
-    // Level by level: within each (kind, heavy, cell) bucket, order gates by
-    // the internal id of their first fan-in net (stable), so consecutive
-    // waves of the simulation read that pin's rows in address order; then
-    // spread each (level, kind)'s heavy gates (sorted first) one per 64.
+    // Level by level: within each (kind, class, heavy, cell) bucket, order
+    // gates by the internal id of their first fan-in net (stable), so
+    // consecutive waves of the simulation read that pin's rows in address
+    // order; then spread each (level, kind, class)'s heavy gates (sorted
+    // first) one per 64.
     std::vector<int32_t> pos(G, 0), part;
     auto src_of = [&](int32_t g) {
       const int32_t n = nl->fanin[nl->fanin_ptr[g]];
@@ -189,8 +196,8 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
           std::stable_sort(gate_of.begin() + a, gate_of.begin() + b,
                            [&](int32_t x, int32_t y) { return src_of(x) < src_of(y); });
       }
-      for (int32_t kind = 0; kind < 2; ++kind) {
-        const int32_t k0 = l * kSlots + kind * 512;
+      for (int32_t kc = 0; kc < 4; ++kc) {  // (kind, class)
+        const int32_t k0 = l * kSlots + kc * 512;
         const int32_t a = key_ptr[k0], h = key_ptr[k0 + 256] - a, b = key_ptr[k0 + 512];
         if (h == 0 || h == b - a) continue;
         part.assign(gate_of.begin() + a, gate_of.begin() + b);
@@ -285,11 +292,15 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   for (int32_t i = 0; i < n_pi; ++i)
     if (rev_ptr[i + 1] - rev_ptr[i] > kHeavyPull) d->h_heavy_pi.push_back(i);
   d->lvl_fixed.assign(depth + 1, 0);
+  d->lvl_small_cells.assign(depth + 1, 0);
   for (int32_t l = 1; l <= depth; ++l) {
     const int32_t g0 = d->level_ptr[l], g1 = d->level_ptr[l + 1];
     int32_t f = g0;
     while (f < g1 && d->h_op[f] < kCellBase) ++f;
     d->lvl_fixed[l] = f - g0;
+    int32_t sc = f;
+    while (sc < g1 && !big_cell(d->h_op[sc])) ++sc;
+    d->lvl_small_cells[l] = sc - f;
     if (f < g1) {
       d->has_cell_gates = true;
       ++d->cell_levels;
@@ -309,10 +320,13 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
     std::copy(cc.code.begin(), cc.code.end(), code.begin() + (size_t)id * kCellMaxCode);
     tt[id] = truth_table(cc);
   }
+  std::vector<uint8_t> arity(std::max(G, 1), 0);
+  for (int32_t gi = 0; gi < G; ++gi)
+    arity[gi] = (uint8_t)(d->h_arity_prefix[gi + 1] - d->h_arity_prefix[gi]);
   hipStream_t s = ctx->stream;
   dp_status st = DP_OK;
   if ((st = upload(d->code, code, s)) != DP_OK || (st = upload(d->cell, cell_tab, s)) != DP_OK ||
-      (st = upload(d->tt, tt, s)) != DP_OK ||
+      (st = upload(d->tt, tt, s)) != DP_OK || (st = upload(d->arity, arity, s)) != DP_OK ||
       (st = upload(d->op, d->h_op, s)) != DP_OK || (st = upload(d->in, in, s)) != DP_OK ||
       (st = upload(d->rev_ptr, rev_ptr, s)) != DP_OK ||
       (st = upload(d->rev_edge, rev_edge, s)) != DP_OK ||
@@ -332,7 +346,7 @@ dp_status compile_design(dp_ctx *ctx, const dp_netlist *nl, int32_t n_cells,
   }
   d->device_bytes = (int64_t)(d->op.bytes + d->in.bytes + d->rev_ptr.bytes + d->rev_edge.bytes +
                               d->slot.bytes + d->int2ext.bytes + d->ext2int.bytes +
-                              d->code.bytes + d->cell.bytes + d->tt.bytes + d->heavy.bytes +
+                              d->code.bytes + d->cell.bytes + d->tt.bytes + d->arity.bytes + d->heavy.bytes +
                               d->heavy_pi.bytes);
   ctx_retain(ctx);
   *out = d;

@@ -100,6 +100,9 @@ struct dp_design {
   // [depth + 1] fixed-cell gates of each level; its library-cell gates follow
   // them and run in kernels of their own
   std::vector<int32_t> lvl_fixed;
+  // [depth + 1] library cells of each level with at most kSmallCellInputs
+  // inputs; they precede the level's wider cells
+  std::vector<int32_t> lvl_small_cells;
   int32_t split_levels = 0;           // levels holding both kinds (one launch more each)
   int32_t cell_levels = 0;            // levels holding library cells
   bool has_cell_gates = false;
@@ -117,6 +120,7 @@ struct dp_design {
   dp::DevBuf code;      // uint16: the library cells' stack code, concatenated
   dp::DevBuf cell;      // int32 [n_cells][3]: code offset, length, inputs
   dp::DevBuf tt;        // uint64 [n_cells] truth tables (the simulation's cell function)
+  dp::DevBuf arity;     // uint8 [n_gates] input count of each gate
   dp::DevBuf level_dev; // int32 [depth + 2] device copy of level_ptr
   dp::DevBuf int2ext;   // int32 [n_nets]
   dp::DevBuf ext2int;   // int32 [n_nets]
@@ -140,6 +144,7 @@ inline GraphView design_view(const dp_design *d) {
   g.code = d->code.as<uint16_t>();
   g.cell = d->cell.as<int32_t>();
   g.tt = d->tt.as<uint64_t>();
+  g.arity = d->arity.as<uint8_t>();
   g.pins = d->pins;
   g.n_pi = d->n_pi;
   g.G = d->n_gates;

@@ -27,6 +27,7 @@ struct GraphView {
   const uint16_t *code;     // [n_cells][kCellMaxCode] library cells' stack code (op | arg << 8), padded
   const int32_t *cell;      // [n_cells][3]: code offset, length, inputs
   const uint64_t *tt;       // [n_cells] truth tables: bit m = output for input pattern m
+  const uint8_t *arity;     // [G] input count of each gate
   int32_t pins;             // rows of in and slot (3, or the widest cell)
   int32_t n_pi, G, n_nets;
 };
@@ -110,12 +111,17 @@ hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t 
                                int32_t n_pi, int32_t B, int64_t T, uint64_t seed, uint64_t *out,
                                hipStream_t s);
 
-// One simulation level of one chunk for the launch's columns, with the
-// range's SP (every column of the SpLevel, the same gate range and kind)
-// fused in when sp != nullptr.
+// Library cells with at most this many inputs run in simulation launches
+// of their own, with more word pairs per lane than the wider cells.
+constexpr int kSmallCellInputs = 3;
+
+// One simulation level of one chunk for the launch's columns, with SP of
+// the gates of sp (every column; gates of the launch's kind) fused in when
+// sp != nullptr.  cell_inputs: the most inputs a library cell of the range
+// has (kSmallCellInputs or fewer selects the narrow instance).
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
-                            const SimTune &tune, hipStream_t s);
+                            const SimTune &tune, hipStream_t s, int cell_inputs = 6);
 
 // Caller-numbered exports of forward quantities, [B][n_nets].
 struct ExportArgs {

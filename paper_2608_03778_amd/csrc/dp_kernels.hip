@@ -503,16 +503,15 @@ __device__ __forceinline__ uint64_t tt_eval(const uint64_t *x, uint64_t tt, int 
 
 // A library cell's row with N inputs: sim_gate_row with the table in place
 // of the fixed rule.
-template <int N, int ITERS>
-__device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint64_t tt,
+template <int N, int ITERS, int NMAX>
+__device__ __forceinline__ void sim_tt_row(const int32_t (&ix)[NMAX], uint64_t tt,
                                            const w2 *__restrict__ W, int64_t pp,
                                            w2 *__restrict__ out, bool keep, int32_t p_begin,
                                            const ChunkView &c, int lane, uint32_t &ones,
                                            uint32_t &togs) {
   const w2 *r[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k)
-    r[k] = W + (int64_t)__builtin_amdgcn_readfirstlane(g.in[k * g.G + gi]) * pp;
+  for (int k = 0; k < N; ++k) r[k] = W + (int64_t)ix[k] * pp;
   uint64_t carry = 0;
   if (p_begin > 0) {  // word just before this run, recomputed from its inputs
     uint64_t x[N];
@@ -548,34 +547,50 @@ __device__ __forceinline__ void sim_tt_row(const GraphView &g, int32_t gi, uint6
   }
 }
 
-template <int ITERS>
+template <int ITERS, int NMAX>
 __device__ __forceinline__ void sim_cell_row(const GraphView &g, int op, int32_t gi,
                                              const w2 *__restrict__ W, int64_t pp,
                                              w2 *__restrict__ out, bool keep, int32_t p_begin,
                                              const ChunkView &c, int lane, uint32_t &ones,
                                              uint32_t &togs) {
+  // the gate's input count and every pin's input net go out with the
+  // opcode (pin rows past the design's widest cell alias pin 0), so the
+  // input rows load in the next round; the table rides along with them
+  const int nin = __builtin_amdgcn_readfirstlane((int)g.arity[gi]);
+  int32_t ix[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) ix[k] = __builtin_amdgcn_readfirstlane(pin_row(g.in, g, k)[gi]);
   const int cl = op - kCellBase;
-  const int nin = __builtin_amdgcn_readfirstlane(g.cell[3 * cl + 2]);
   const uint64_t t = g.tt[cl];
   const uint64_t tt = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32) |
                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)t);
+  // NMAX: the most inputs a cell of the launch has (the instance for narrow
+  // cells keeps fewer registers, so more of its waves are resident)
   switch (nin) {
-    case 1: sim_tt_row<1, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
-    case 2: sim_tt_row<2, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
-    case 3: sim_tt_row<3, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
-    case 4: sim_tt_row<4, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
-    case 5: sim_tt_row<5, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
-    default: sim_tt_row<6, ITERS>(g, gi, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 1: sim_tt_row<1, ITERS>(ix, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 2: sim_tt_row<2, ITERS>(ix, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    case 3: sim_tt_row<3, ITERS>(ix, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+    default:
+      if constexpr (NMAX > 3) {
+        switch (nin) {
+          case 4: sim_tt_row<4, ITERS>(ix, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+          case 5: sim_tt_row<5, ITERS>(ix, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+          default: sim_tt_row<6, ITERS>(ix, tt, W, pp, out, keep, p_begin, c, lane, ones, togs); break;
+        }
+      }
+      break;
   }
 }
 
-template <int ITERS, bool CELLS>
+// CELLS: 0 for fixed cells, else the most inputs a library cell of the
+// launch has.
+template <int ITERS, int CELLS>
 __global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView c, CountView cnt,
                                                       int32_t g0, int32_t n, int32_t waves_per_row,
                                                       int32_t sim_blocks, SpLevel sp) {
   if ((int32_t)blockIdx.x >= sim_blocks) {  // fused SP of the same level (and kind)
     const uint32_t idx = (blockIdx.x - (uint32_t)sim_blocks) * kSimBlock + threadIdx.x;
-    if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item<CELLS>(g, sp, idx);
+    if (idx < (uint32_t)sp.n * (uint32_t)sp.B) sp_item<(CELLS > 0)>(g, sp, idx);
     return;
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -603,8 +618,8 @@ __global__ __launch_bounds__(kSimBlock) void k_sim_level(GraphView g, ChunkView 
                     __builtin_amdgcn_readfirstlane(g.rev_ptr[on]);
   const int32_t p_begin = seg * 64 * ITERS;
   uint32_t ones = 0, togs = 0;
-  if constexpr (CELLS) {
-    sim_cell_row<ITERS>(g, op, gi, W, pp, out, keep, p_begin, c, lane, ones, togs);
+  if constexpr (CELLS > 0) {
+    sim_cell_row<ITERS, CELLS>(g, op, gi, W, pp, out, keep, p_begin, c, lane, ones, togs);
   } else {
   switch (op) {
     case INV: sim_gate_row<INV, ITERS>(r0, r1, r2, out, keep, p_begin, c, lane, ones, togs); break;
@@ -1957,9 +1972,11 @@ hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t 
 
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
-                            const SimTune &tune, hipStream_t s) {
+                            const SimTune &tune, hipStream_t s, int cell_inputs) {
   if (n <= 0 || c.n_cols <= 0) return hipSuccess;
-  const int iters = cells ? min(tune.iters, 2) : tune.iters;  // cells: up to 6 input rows
+  const bool narrow = cells && cell_inputs <= kSmallCellInputs;
+  // cells: up to 2 pairs per lane (up to 6 input rows each), narrow cells up to 4
+  const int iters = cells ? min(tune.iters, narrow ? 4 : 2) : tune.iters;
   const int32_t wpr = waves_per_row(c, iters);
   const int64_t tasks = (int64_t)n * wpr * c.n_cols;
   const int64_t sim_blocks64 = (tasks + kSimWaves - 1) / kSimWaves;
@@ -1973,18 +1990,26 @@ hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountV
   if (sim_blocks64 + sp_blocks > kMaxBlocks || sim_blocks64 > INT32_MAX) return hipErrorInvalidValue;
   const int32_t sim_blocks = (int32_t)sim_blocks64;
   const unsigned grid = (unsigned)(sim_blocks + sp_blocks);
+  if (narrow) {
+    switch (iters) {
+      case 1: k_sim_level<1, 3><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+      case 2: k_sim_level<2, 3><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+      default: k_sim_level<4, 3><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    }
+    return hipGetLastError();
+  }
   if (cells) {
     if (iters == 1)
-      k_sim_level<1, true><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+      k_sim_level<1, 6><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
     else
-      k_sim_level<2, true><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
+      k_sim_level<2, 6><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl);
     return hipGetLastError();
   }
   switch (iters) {
-    case 1: k_sim_level<1, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    case 2: k_sim_level<2, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    case 4: k_sim_level<4, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
-    default: k_sim_level<8, false><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 1: k_sim_level<1, 0><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 2: k_sim_level<2, 0><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    case 4: k_sim_level<4, 0><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
+    default: k_sim_level<8, 0><<<grid, kSimBlock, 0, s>>>(g, c, cnt, g0, n, wpr, sim_blocks, spl); break;
   }
   return hipGetLastError();
 }

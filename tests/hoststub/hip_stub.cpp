@@ -423,10 +423,14 @@ hipError_t launch_stimulus(const GraphView &g, const ChunkView &c, const CountVi
 }
 hipError_t launch_sim_level(const GraphView &g, const ChunkView &c, const CountView &cnt,
                             int32_t g0, int32_t n, const SpLevel *sp, bool cells,
-                            const SimTune &, hipStream_t stream_) {
+                            const SimTune &, hipStream_t stream_, int cell_inputs) {
   Scope sc_(stream_);
   rd_graph(g, g0, n, cells);
-  if (sp && (sp->g0 != g0 || sp->n != n)) fatal("fused SP range differs from the simulation's");
+  if (sp) rd_graph(g, sp->g0, sp->n, cells);  // the fused SP: gates of the same kind
+  if (cells)  // every cell of the range within the instance's input count
+    for (int32_t i = g0; i < g0 + n; ++i)
+      if (g.cell[3 * (g.op[i] - dp::kCellBase) + 2] > cell_inputs)
+        fatal("library cell wider than its simulation launch");
   if (c.n_cols < 1 || cnt.col < 0 || cnt.col + c.n_cols > cnt.B) {
     std::fprintf(stderr, "STUB: simulation columns out of range\n");
     std::abort();
