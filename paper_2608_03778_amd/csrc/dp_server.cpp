@@ -301,7 +301,13 @@ void admit(dp_server *s) {
       while (fit > 1 && dp::lane_bytes(d, fit) > free_now) fit >>= 1;
       if (dp::lane_bytes(d, fit) <= free_now) cap = fit;
       const size_t need = dp::lane_bytes(d, cap);
-      if (s->used + need > s->budget && !make_room(s, need, r->design)) {
+      // other designs' idle lanes are freed only for a design that has no
+      // lane at all; one that has (busy) lanes waits for them instead, so
+      // designs do not free and recreate each other's lanes under load (a
+      // lane's pinned staging alone takes a large design hundreds of ms)
+      bool has_lane = false;
+      for (Lane *l : s->lanes) has_lane |= l->design == r->design;
+      if (s->used + need > s->budget && (has_lane || !make_room(s, need, r->design))) {
         s->st.memory_waits++;
         ++i;  // no memory now; a running lane will free some
         continue;
