@@ -726,8 +726,9 @@ def main():
                     help="rate of the like-for-like comparison with one query at a time")
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-budget-gb", type=float, default=1.0,
-                    help="HBM budget of the query slots (small enough that admission binds)")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.75,
+                    help="HBM budget of the query lanes (small enough that admission binds: "
+                         "queries wait for memory at 2,000 q/s)")
     ap.add_argument("--serve-inflight", type=int, default=3,
                     help="device steps in flight at once (continuous batching)")
     ap.add_argument("--pmc-pass", action="store_true",

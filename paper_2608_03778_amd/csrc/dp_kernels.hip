@@ -1262,7 +1262,10 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
 // registers.  Library cells decide the pull per launch at run time.
 // skip_heavy (WIDE only): items of gates with more than kHeavyPull fan-out
 // entries are left to the launch's cooperative blocks (bwd_heavy).
-template <bool CELLS, bool WIDE>
+// UNI (WIDE, a multiple of 64 columns): every wave holds one gate, so the
+// gate's values are made wave-uniform once loaded (scalar branches, scalar
+// row addresses, loops with scalar bounds).
+template <bool CELLS, bool WIDE, bool UNI = false>
 __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, int32_t g0,
                                          int32_t n, uint32_t idx, int lane,
                                          bool skip_heavy = false) {
@@ -1278,10 +1281,15 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const f2 z = f2{0.0f, 1.0f};
   // first round: the item's structure and its own net's values; nothing here
   // waits on another load
-  const int32_t e0 = g.rev_ptr[out];
-  const int32_t e1r = g.rev_ptr[out + 1];
+  int32_t e0 = g.rev_ptr[out];
+  int32_t e1r = g.rev_ptr[out + 1];
+  int op = g.op[gi];
+  if constexpr (UNI) {
+    e0 = __builtin_amdgcn_readfirstlane(e0);
+    e1r = __builtin_amdgcn_readfirstlane(e1r);
+    op = __builtin_amdgcn_readfirstlane(op);
+  }
   const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
-  const int op = g.op[gi];
   const f2 pq = sp_load(sp[(int64_t)out * a.B + b]);
   const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)out : (int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
@@ -1306,23 +1314,28 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   f2 x0, x1, x2;
   if constexpr (WIDE) {
     // many columns: a wave's lanes share one or two gates, and the sweep is
-    // bound by the rows it moves, so only the pins a gate has are gathered
-    const int k = arity_of(op);
+    // bound by the rows it moves, so only the pins a gate has are gathered;
+    // every pin's index and slot go out with the opcode (unused pin rows
+    // alias pin 0), so the gathers wait on one round only
     i0 = g.in[gi];
+    i1 = pin_row(g.in, g, 1)[gi];
+    i2 = pin_row(g.in, g, 2)[gi];
     s0 = g.slot[gi];
+    s1 = pin_row(g.slot, g, 1)[gi];
+    s2 = pin_row(g.slot, g, 2)[gi];
+    if constexpr (UNI) {
+      i0 = __builtin_amdgcn_readfirstlane(i0);
+      i1 = __builtin_amdgcn_readfirstlane(i1);
+      i2 = __builtin_amdgcn_readfirstlane(i2);
+      s0 = __builtin_amdgcn_readfirstlane(s0);
+      s1 = __builtin_amdgcn_readfirstlane(s1);
+      s2 = __builtin_amdgcn_readfirstlane(s2);
+    }
+    const int k = arity_of(op);
     x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
     x1 = x2 = z;
-    s1 = s2 = 0;
-    if (k > 1) {
-      i1 = g.in[g.G + gi];
-      s1 = g.slot[g.G + gi];
-      x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
-    }
-    if (k > 2) {
-      i2 = g.in[2 * g.G + gi];
-      s2 = g.slot[2 * g.G + gi];
-      x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
-    }
+    if (k > 1) x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
+    if (k > 2) x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
   } else {
     // few columns: the sweep is bound by round trips, so every gather goes
     // out in the second round whatever the opcode
@@ -1443,7 +1456,7 @@ __device__ __forceinline__ void bwd_heavy(const GraphView &g, const BwdArgs &a,
 // gates (heavy[0, n_heavy), in groups of 64 columns; first, so their longer
 // pulls start first), and the blocks after them the (gate, column) items,
 // skipping the heavy gates.
-template <bool CELLS, bool WIDE>
+template <bool CELLS, bool WIDE, bool UNI = false>
 __global__ __launch_bounds__(kWideBlock) void k_bwd_level(GraphView g, BwdArgs a, int32_t g0,
                                                            int32_t n, const int32_t *heavy,
                                                            int32_t n_heavy, uint32_t heavy_blocks) {
@@ -1453,8 +1466,8 @@ __global__ __launch_bounds__(kWideBlock) void k_bwd_level(GraphView g, BwdArgs a
       return;
     }
   }
-  bwd_item<CELLS, WIDE>(g, a, g0, n, (blockIdx.x - heavy_blocks) * blockDim.x + threadIdx.x,
-                        threadIdx.x & 63, n_heavy > 0);
+  bwd_item<CELLS, WIDE, UNI>(g, a, g0, n, (blockIdx.x - heavy_blocks) * blockDim.x + threadIdx.x,
+                             threadIdx.x & 63, n_heavy > 0);
 }
 
 // skip_heavy: PIs with more than kHeavyPull fan-out entries are left to the
@@ -1737,6 +1750,7 @@ constexpr int32_t kCapRows = 64, kCapCols = 32, kCapBatch = 16;
 template <bool BETA>  // BETA: a beta array is present
 __global__ __launch_bounds__(kCapRows) void k_grad_cap(GradExportArgs a) {
   __shared__ float xs[kCapRows][kCapCols + 1];
+  __shared__ float wcol[kCapCols];  // without sizes a column's weight is the net's
   const int32_t r = (int32_t)threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.x * kCapRows;
   const int64_t n = n0 + r;
@@ -1780,12 +1794,43 @@ __global__ __launch_bounds__(kCapRows) void k_grad_cap(GradExportArgs a) {
         if (e < total) xs[rr][e - rr * tw] = v[u];
       }
     }
+    // without sizes the weight of column b is the same for every net: one
+    // lane per column forms it (as weight() would), the row loop reads it
+    if (!a.size && r < tw) wcol[r] = weight(b0 + r);
     __syncthreads();
-    if (r < rows)
-      for (int32_t cc = 0; cc < tw; ++cc) acc += (double)xs[r][cc] * (double)weight(b0 + cc);
+    if (r < rows) {
+      if (!a.size)
+        for (int32_t cc = 0; cc < tw; ++cc) acc += (double)xs[r][cc] * (double)wcol[cc];
+      else
+        for (int32_t cc = 0; cc < tw; ++cc) acc += (double)xs[r][cc] * (double)weight(b0 + cc);
+    }
     __syncthreads();
   }
   if (r < rows) a.dcap[a.int2ext[n]] = (float)acc;
+}
+
+// Few columns: one thread per net, its columns in order (the same sum as
+// k_grad_cap); consecutive threads read consecutive rows, which at few
+// columns are already whole lines, and no LDS pass is needed.
+constexpr int32_t kCapRowsMinCols = 16;  // from this many columns k_grad_cap stages rows
+
+__global__ __launch_bounds__(kBlock) void k_grad_cap_narrow(GradExportArgs a) {
+  const int64_t n = gidx();
+  if (n >= a.n_nets) return;
+  const int32_t Sp = (a.S > 0 && !a.paired) ? a.S : 1;
+  const bool gate = n >= a.n_pi && a.size;
+  double acc = 0.0;
+  for (int32_t b = 0; b < a.B; ++b) {
+    float ws = 0.0f;
+    for (int32_t s = 0; s < Sp; ++s) {
+      const int32_t row = a.paired ? b : s;
+      const float w = a.w ? a.w[(int64_t)b * Sp + s] : 1.0f;
+      const float sz = gate ? a.size[(int64_t)row * a.G + (n - a.n_pi)] : 1.0f;
+      ws = fmaf(w, sz, ws);
+    }
+    acc += (double)x_of(a, n, b) * (double)ws;
+  }
+  a.dcap[a.int2ext[n]] = (float)acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_grad_size(GradExportArgs a) {
@@ -2091,8 +2136,12 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
     const int64_t hb = (int64_t)n_heavy * ((a.C + 63) / 64);
     const int64_t blocks = hb + level_grid(items);
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-    k_bwd_level<false, true><<<(unsigned)blocks, level_block(items), 0, s>>>(g, a, g0, n, heavy,
-                                                                            n_heavy, (uint32_t)hb);
+    if (a.C % 64 == 0)  // one gate per wave
+      k_bwd_level<false, true, true><<<(unsigned)blocks, level_block(items), 0, s>>>(
+          g, a, g0, n, heavy, n_heavy, (uint32_t)hb);
+    else
+      k_bwd_level<false, true><<<(unsigned)blocks, level_block(items), 0, s>>>(
+          g, a, g0, n, heavy, n_heavy, (uint32_t)hb);
   } else {
     k_bwd_level<false, false><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n,
                                                                               nullptr, 0, 0);
@@ -2180,7 +2229,9 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
 hipError_t launch_grad_export(const GradExportArgs &a, hipStream_t s) {
   if (a.dcap && a.n_nets > 0) {
     const unsigned blocks = (unsigned)((a.n_nets + kCapRows - 1) / kCapRows);
-    if (a.beta)
+    if (a.B < kCapRowsMinCols)
+      k_grad_cap_narrow<<<blocks_for(a.n_nets), kBlock, 0, s>>>(a);
+    else if (a.beta)
       k_grad_cap<true><<<blocks, kCapRows, 0, s>>>(a);
     else
       k_grad_cap<false><<<blocks, kCapRows, 0, s>>>(a);
