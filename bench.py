@@ -656,6 +656,8 @@ def run_form(name, args):
         return modeled_form(args, name[len("modeled_b1_"):], 1)
     if name == "modeled_b64":
         return modeled_form(args, "auto", args.batch)
+    if name.startswith("modeled_b64_"):
+        return modeled_form(args, name[len("modeled_b64_"):], args.batch)
     if name == "design_group":
         return group_form(args)
     if name == "power_virus":

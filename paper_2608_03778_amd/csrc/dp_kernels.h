@@ -250,18 +250,17 @@ hipError_t launch_virus_power(const uint32_t *tog, const float *cap, int32_t n_n
 // barrier between levels; fixed cells only.  level_ptr is the device copy of
 // the design's level table; max_items the largest level's item count.
 //
-// The barrier's device words (kBarrierWords uint32, each counter on a line
-// of its own, zeroed by the launcher on the stream before each launch):
-// kBarrierGroups arrival counters (block b arrives at counter b mod
-// kBarrierGroups), the global counter the last arrival of each group bumps,
-// and the timeout flag.  A wait that sees no progress for limit_ticks ticks
-// of the 100 MHz real-time counter sets the flag and stops, and every later
-// wait of the launch stops at once; the sweep's outputs are then NaN and the
-// report word (kBarrierReport) is set for the host to read.
-constexpr int kBarrierGroups = 8;
-constexpr int kBarrierStride = 32;  // 128 bytes between counters
-constexpr int kBarrierGlobal = kBarrierGroups * kBarrierStride;
-constexpr int kBarrierTimeout = kBarrierGlobal + kBarrierStride;
+// The barrier's device words (kBarrierWords uint32, zeroed by the launcher
+// on the stream before each launch): one arrival flag per block (block b
+// stores the number of the barrier it reached to word b; a launch has at
+// most kBarrierFlags blocks) and the timeout flag.  A wait that sees no new
+// arrival for limit_ticks ticks of the 100 MHz real-time counter sets the
+// timeout flag and stops, and every later wait of the launch stops at once;
+// the sweep's outputs are then NaN and the report word (kBarrierReport) is
+// set for the host to read.
+constexpr int kBarrierFlags = 1024;
+constexpr int kBarrierStride = 32;  // 128 bytes
+constexpr int kBarrierTimeout = kBarrierFlags;
 constexpr int kBarrierWords = kBarrierTimeout + kBarrierStride;
 // One more word after them, not zeroed per launch: a wait that gives up also
 // sets it, so it records that some sweep since the host last cleared it

@@ -1623,22 +1623,20 @@ __global__ __launch_bounds__(kMergedBlock) void k_bwd_multi(const BwdSeg *__rest
 // level's items, then a grid barrier.  Whole waves step together so the
 // wave-wide pull of the reverse sweep sees all its lanes.
 //
-// The barrier: at barrier k each block's first thread adds one to its
-// group's counter (block b is in group b mod kBarrierGroups; acquire-release
-// at device scope, so the group's last arrival carries every earlier
-// arrival's writes); the group's last arrival (the one that brings the
-// counter to k times the group's size) adds one to the global counter
-// (release); every block then polls the global counter with plain
-// device-scope loads until it reaches k times the number of groups, and
-// takes one acquire fence.  Spreading the arrivals over eight counters keeps
-// any one of them from serialising all blocks' atomics.  Cooperative launch
-// keeps every block resident, so every wait ends; as a guard, a wait that
-// sees the global counter stand still for limit_ticks ticks of the 100 MHz
-// real-time counter sets the timeout flag and stops, a wait that finds the
-// flag set stops at once, and the sweep's outputs are then written as NaN.
-// The wait that gives up also sets the report word, which the host reads at
-// its next synchronization, so a broken sweep is reported and cannot pass
-// for a result.
+// The barrier: at barrier k every block, once all its threads have stored
+// their results, publishes k in its own arrival flag (a release store at
+// device scope, which makes the block's stores visible beyond its XCD's L2);
+// then the block's first wave reads all the flags, 64 at a time (lane i
+// reads flags i, i + 64, ...), until every flag reads k or more, and takes
+// one acquire fence.  No block waits on another's atomic: a barrier costs
+// one release, the store's trip and the reads that see the last one.
+// Cooperative launch keeps every block resident, so every wait ends; as a
+// guard, a wait that sees no new arrival for limit_ticks ticks of the
+// 100 MHz real-time counter sets the timeout flag and stops, a wait that
+// finds the flag set stops at once, and the sweep's outputs are then written
+// as NaN.  The wait that gives up also sets the report word, which the host
+// reads at its next synchronization, so a broken sweep is reported and
+// cannot pass for a result.
 __device__ __forceinline__ bool barrier_timed_out(const GridBarrier &bar) {
   return __hip_atomic_load(bar.words + kBarrierTimeout, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT) != 0u;
@@ -1646,60 +1644,103 @@ __device__ __forceinline__ bool barrier_timed_out(const GridBarrier &bar) {
 
 __device__ __forceinline__ void grid_barrier(const GridBarrier &bar, uint32_t k) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t blocks = gridDim.x;
-    const uint32_t grp = blockIdx.x % kBarrierGroups;
-    const uint32_t grp_size = blocks / kBarrierGroups + (grp < blocks % kBarrierGroups ? 1u : 0u);
-    const uint32_t groups = blocks < (uint32_t)kBarrierGroups ? blocks : (uint32_t)kBarrierGroups;
-    uint32_t *cnt = bar.words + grp * kBarrierStride;
-    uint32_t *glob = bar.words + kBarrierGlobal;
-    const uint32_t before =
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (before + 1u == k * grp_size)
-      __hip_atomic_fetch_add(glob, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t target = k * groups;
-    uint32_t seen = 0xffffffffu;
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x, blocks = gridDim.x;
+    if (lane == 0)
+      __hip_atomic_store(bar.words + blockIdx.x, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t seen = 0;
     uint64_t since = __builtin_amdgcn_s_memrealtime();
     for (uint32_t it = 0;; ++it) {
-      const uint32_t c = __hip_atomic_load(glob, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (c >= target) break;
+      uint32_t arrived = 0;
+      for (uint32_t b = lane; b < blocks; b += 64)
+        arrived += __hip_atomic_load(bar.words + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= k;
+      arrived = wave_sum(arrived);
+      if (arrived == blocks) break;
       if ((it & 15u) == 0u && barrier_timed_out(bar)) break;
       const uint64_t now = __builtin_amdgcn_s_memrealtime();
-      if (c != seen) {
-        seen = c;
+      if (arrived != seen) {  // a new arrival restarts the clock
+        seen = arrived;
         since = now;
-      } else if (now - since >= bar.limit_ticks) {
-        __hip_atomic_store(bar.words + kBarrierTimeout, 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(bar.words + kBarrierReport, 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (now - since >= bar.limit_ticks) {  // at a limit of 0: the first poll that waits
+        if (lane == 0) {
+          __hip_atomic_store(bar.words + kBarrierTimeout, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(bar.words + kBarrierReport, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
         break;
       }
-      __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
 
+// A level item's structure (opcode and pin indices), loaded apart from its
+// gathers so the persistent sweep can fetch the next level's before it
+// waits at the barrier: the indices do not depend on any level's results.
+struct SpFetch {
+  int32_t op, i0, i1, i2;
+};
+
+__device__ __forceinline__ SpFetch sp_fetch(const GraphView &g, int32_t gi) {
+  SpFetch f;
+  f.op = g.op[gi];
+  f.i0 = g.in[gi];
+  f.i1 = pin_row(g.in, g, 1)[gi];
+  f.i2 = pin_row(g.in, g, 2)[gi];
+  return f;
+}
+
+__device__ __forceinline__ void sp_finish(const GraphView &g, const SpLevel &lv, int32_t gi,
+                                          int32_t b, const SpFetch &f) {
+  const int32_t B = lv.B;
+  float *sp = lv.sp;
+  const int k = arity_of(f.op);
+  const float sa = sp[(int64_t)f.i0 * B + b];
+  float sb = 0.0f, sc = 0.0f;
+  if (k > 1) sb = sp[(int64_t)f.i1 * B + b];
+  if (k > 2) sc = sp[(int64_t)f.i2 * B + b];
+  gathers_done(sa, sb, sc);
+  const f2 z = f2{0.0f, 1.0f};
+  sp[(int64_t)(g.n_pi + gi) * B + b] =
+      settle(sp_rule(f.op, sp_load(sa), k > 1 ? sp_load(sb) : z, k > 2 ? sp_load(sc) : z));
+}
+
 __global__ __launch_bounds__(kBlock) void k_sp_persistent(GraphView g, SpLevel lv,
                                                           const int32_t *__restrict__ level_ptr,
                                                           int32_t depth, GridBarrier bar) {
   const uint32_t stride = gridDim.x * kBlock;
+  const uint32_t first = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t B = (uint32_t)lv.B;
+  // this thread's first item of the coming level, fetched ahead
+  int32_t g0 = level_ptr[1], n = level_ptr[2] - g0;
+  SpFetch ahead{};
+  if (first < (uint32_t)n * B) ahead = sp_fetch(g, g0 + (int32_t)(first / B));
   for (int32_t l = 1; l <= depth; ++l) {
     SpLevel cur = lv;
-    cur.g0 = level_ptr[l];
-    cur.n = level_ptr[l + 1] - cur.g0;
-    const uint32_t items = (uint32_t)cur.n * (uint32_t)cur.B;
-    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < items; idx += stride)
-      sp_item<false>(g, cur, idx);
+    cur.g0 = g0;
+    cur.n = n;
+    const uint32_t items = (uint32_t)n * B;
+    for (uint32_t idx = first; idx < items; idx += stride) {
+      const uint32_t gl = idx / B;
+      const int32_t gi = g0 + (int32_t)gl;
+      const SpFetch f = idx == first ? ahead : sp_fetch(g, gi);
+      if (idx != first) gathers_done(f.op, f.i0, f.i1, f.i2);
+      sp_finish(g, cur, gi, (int32_t)(idx - gl * B), f);
+    }
+    if (l < depth) {  // the next level's structure loads go out before the wait
+      g0 = level_ptr[l + 1];
+      n = level_ptr[l + 2] - g0;
+      if (first < (uint32_t)n * B) ahead = sp_fetch(g, g0 + (int32_t)(first / B));
+    }
     grid_barrier(bar, (uint32_t)l);
   }
   if (barrier_timed_out(bar)) {  // every gate's probability becomes NaN
-    const int64_t n = (int64_t)g.G * lv.B;
+    const int64_t nn = (int64_t)g.G * lv.B;
     float *out = lv.sp + (int64_t)g.n_pi * lv.B;
-    for (int64_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-      out[i] = __builtin_nanf("");
+    for (int64_t i = first; i < nn; i += stride) out[i] = __builtin_nanf("");
   }
 }
 
@@ -2174,7 +2215,8 @@ static hipError_t persistent_grid(const void *kernel, int64_t max_items, unsigne
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
   if (e != hipSuccess) return e;
-  const int64_t resident = std::min<int64_t>((int64_t)per_cu * ncu, ncu);
+  // one block per CU at most, and no more blocks than the barrier has flags
+  const int64_t resident = std::min<int64_t>({(int64_t)per_cu * ncu, ncu, kBarrierFlags});
   if (resident < 1) return hipErrorInvalidValue;
   const int64_t want = std::max<int64_t>(1, (max_items + kBlock - 1) / kBlock);
   *grid = (unsigned)std::min(resident, want);
