@@ -21,7 +21,7 @@ def ctx():
     return api.Context(0)
 
 
-def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=()):
+def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=(), schedules=()):
     spec = synth.SPECS[name]
     nl = synth.random_dag(spec, seed=1)
     p = synth.pi_probs(nl.n_pi, seed=2)
@@ -59,6 +59,16 @@ def _full_check(ctx, name, n_sim, seed, fd_samples=0, tilings=()):
             np.testing.assert_array_equal(r2[k], res[k], err_msg=f"{k} at {ppl} pairs per lane")
         for k in g2:
             np.testing.assert_array_equal(g2[k], g[k], err_msg=f"{k} at {ppl} pairs per lane")
+    for sched in schedules:  # the other schedules the benchmark times: bit for bit
+        say(f"{name}: schedule {sched}")
+        ev.set_schedule(sched)
+        for rep in range(2):  # a captured graph replays: check more than one launch
+            r2 = ev.forward(("ones", "toggles", "sp", "power"))
+            g2 = ev.backward(want=("dpi", "dcap"))
+            for k in r2:
+                np.testing.assert_array_equal(r2[k], res[k], err_msg=f"{k}, schedule {sched}")
+            for k in g2:
+                np.testing.assert_array_equal(g2[k], g[k], err_msg=f"{k}, schedule {sched}")
     if fd_samples:
         # FP64 central differences of the oracle's frozen-beta power, h = 1e-6
         rng = np.random.default_rng(7)
@@ -112,6 +122,14 @@ def test_dag117k_sizing_sweep_spot_parity():
     ev.set_cell_sizes(size)
     power = ev.forward(("power",))["power"]
     cols = ev.backward_columns()
+    # the whole sweep captured as two graph launches, as the benchmark also
+    # times it, gives the same results bit for bit (the autotuner's own pick
+    # is checked in a process of its own: test_gpu_autotune.py)
+    say("sizing sweep: graph schedule")
+    ev.set_schedule(L.DP_SCHED_GRAPH)
+    for _ in range(2):
+        np.testing.assert_array_equal(ev.forward(("power",))["power"], power)
+        np.testing.assert_array_equal(ev.backward_columns(), cols)
     o = oracle.Netlist.of(nl)
     rng = np.random.default_rng(3)
     for b in rng.choice(B, 4, replace=False):
@@ -127,5 +145,7 @@ def test_dag117k_sizing_sweep_spot_parity():
 
 def test_dag2m_scale_chunked():
     """2M gates, 16,384 PIs, depth 120, 262,144 vectors in word chunks: every
-    net's counts bit-exact, SP/TR, power and gradients."""
-    _full_check(api.Context(0), "dag2m", 262144, seed=1)
+    net's counts bit-exact, SP/TR, power and gradients; the captured graph
+    and the persistent reverse sweep give the same results bit for bit."""
+    _full_check(api.Context(0), "dag2m", 262144, seed=1,
+                schedules=(L.DP_SCHED_GRAPH, L.DP_SCHED_PERSISTENT))
