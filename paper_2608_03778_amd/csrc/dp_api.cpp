@@ -310,10 +310,38 @@ float *beta_or_null(dp_eval *ev) {
 // per PI and no explicit stimulus).
 bool markov(const dp_eval *ev) { return ev->have_tau && !ev->have_stim; }
 
+// Whether the modeled sweep runs levels l and l + 1 in one launch
+// (launch_sp_pair): both levels hold fixed cells only, and the pair's lanes
+// are few enough that a level launch is bound by its latency rather than its
+// bytes (the pair recomputes up to three gates per lane of its second level).
+constexpr int64_t kPairMaxLanes = 3 << 18;
+bool pairs_levels(const dp_design *d, int32_t l, int32_t B) {
+  if (l + 1 > d->depth) return false;
+  const int32_t a = d->level_ptr[l], m = d->level_ptr[l + 1], e = d->level_ptr[l + 2];
+  return d->lvl_fixed[l] == m - a && d->lvl_fixed[l + 1] == e - m &&
+         (int64_t)(e - a) * B <= kPairMaxLanes;
+}
+
+// Launches of the modeled sweep's SP levels.
+int64_t sp_sweep_launches(const dp_design *d, int32_t B) {
+  int64_t n = 0;
+  for (int32_t l = 1; l <= d->depth;) {
+    if (pairs_levels(d, l, B)) {
+      ++n;
+      l += 2;
+    } else {
+      n += d->lvl_fixed[l] > 0 ? 1 : 0;
+      n += d->lvl_fixed[l] < d->level_ptr[l + 1] - d->level_ptr[l] ? 1 : 0;
+      ++l;
+    }
+  }
+  return n;
+}
+
 // Kernel launches of one forward sweep (what a captured graph would hold).
 int64_t forward_launches(const dp_eval *ev, const ChunkPlan *pl) {
   const int64_t depth = ev->d->depth + ev->d->split_levels;
-  if (!pl) return depth + 2;
+  if (!pl) return sp_sweep_launches(ev->d, ev->B) + 2;
   return (int64_t)pl->n_groups * pl->n_chunks * (depth + 1) + 4 + (markov(ev) ? 1 : 0) +
          ev->d->cell_levels;  // the library cells' SP launches
 }
@@ -385,6 +413,7 @@ double bwd_level_bytes(const dp_design *d, int32_t l, int32_t C) {
 // Enqueue the whole forward sweep (no host sync, no allocation).
 dp_status enqueue_forward_tail(dp_eval *ev, const ChunkPlan *pl);
 
+
 dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   const dp_design *d = ev->d;
   hipStream_t s = ev->stream();
@@ -394,7 +423,8 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
   if (!pl) {  // modeled (or frozen-beta) sweep: one span over all level launches
     double bytes = 0.0;
     for (int32_t l = 1; l <= d->depth; ++l) bytes += sp_level_bytes(d, l, ev->B);
-    SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0, d->depth + d->split_levels);
+    SpanGuard sg(ev, SPAN_SP, bytes, prof && d->depth > 0,
+                 ev->schedule == DP_SCHED_PERSISTENT ? 1 : sp_sweep_launches(d, ev->B));
     if (ev->schedule == DP_SCHED_PERSISTENT) {
       dp::SpLevel lv{sp, ev->B, 0, 0};
       dp::GridBarrier bar;
@@ -404,11 +434,20 @@ dp_status enqueue_forward(dp_eval *ev, const ChunkPlan *pl) {
                                         (int64_t)d->max_level_width * ev->B, bar, cs);
       }));
     } else {
-      for (int32_t l = 1; l <= d->depth; ++l)
+      for (int32_t l = 1; l <= d->depth;) {
+        if (pairs_levels(d, l, ev->B)) {  // levels l and l + 1 in one launch
+          const int32_t a0 = d->level_ptr[l], a1 = d->level_ptr[l + 1], b1 = d->level_ptr[l + 2];
+          DP_HIP_TRY(dp::launch_sp_pair(g, dp::SpLevel{sp, ev->B, a0, a1 - a0},
+                                        dp::SpLevel{sp, ev->B, a1, b1 - a1}, s));
+          l += 2;
+          continue;
+        }
         DP_TRY(for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
           DP_HIP_TRY(dp::launch_sp_level(g, dp::SpLevel{sp, ev->B, g0, n}, cells, s));
           return DP_OK;
         }));
+        ++l;
+      }
     }
   } else {
     const size_t nb = (size_t)d->n_nets * ev->B;
@@ -1473,18 +1512,25 @@ void MergedTables::build(const Lane *lanes, int32_t n) {
   for (int32_t j = 0; j < n; ++j) D = std::max(D, lanes[j].ev->d->depth);
   fs.clear();
   bs.clear();
+  f_launch.clear();
   const size_t m = 2 * (size_t)(D + 1);
-  f_off.assign(m, 0);
-  f_cnt.assign(m, 0);
   b_off.assign(m, 0);
   b_cnt.assign(m, 0);
-  f_blk.assign(m, 0);
   b_blk.assign(m, 0);
-  for (int32_t l = 1; l <= D; ++l)
-    for (int k = 0; k < 2; ++k) {
-      const size_t i = 2 * (size_t)l + k;
-      f_off[i] = (int32_t)fs.size();
-      b_off[i] = (int32_t)bs.size();
+  // forward: level indices l and l + 1 share a launch when every design that
+  // has level l holds fixed cells only there and pairs it with l + 1 (or
+  // ends at l)
+  for (int32_t l = 1; l <= D;) {
+    bool pair = l + 1 <= D;
+    for (int32_t j = 0; j < n && pair; ++j) {
+      const dp_eval *ev = lanes[j].ev;
+      const dp_design *d = ev->d;
+      if (l > d->depth) continue;
+      if (d->lvl_fixed[l] != d->level_ptr[l + 1] - d->level_ptr[l]) pair = false;
+      else if (l + 1 <= d->depth && !pairs_levels(d, l, ev->B)) pair = false;
+    }
+    for (int k = 0; k < (pair ? 1 : 2); ++k) {
+      FwdLaunch fl{(int32_t)fs.size(), 0, 0, k == 1};
       for (int32_t j = 0; j < n; ++j) {
         dp_eval *ev = lanes[j].ev;
         const dp_design *d = ev->d;
@@ -1492,16 +1538,37 @@ void MergedTables::build(const Lane *lanes, int32_t n) {
         int32_t g0, cnt;
         level_part(d, l, k, &g0, &cnt);
         if (cnt == 0) continue;
+        SpLevel second{ev->sp.as<float>(), ev->B, 0, 0};
+        if (pair && l + 1 <= d->depth) {
+          second.g0 = d->level_ptr[l + 1];
+          second.n = d->level_ptr[l + 2] - second.g0;
+        }
+        const uint32_t blocks =
+            (uint32_t)(((int64_t)(cnt + second.n) * ev->B + kMergedBlock - 1) / kMergedBlock);
+        fs.push_back({view(d), SpLevel{ev->sp.as<float>(), ev->B, g0, cnt}, second, fl.blocks});
+        fl.blocks += blocks;
+      }
+      fl.cnt = (int32_t)fs.size() - fl.off;
+      if (fl.cnt > 0) f_launch.push_back(fl);
+    }
+    l += pair ? 2 : 1;
+  }
+  for (int32_t l = 1; l <= D; ++l)
+    for (int k = 0; k < 2; ++k) {
+      const size_t i = 2 * (size_t)l + k;
+      b_off[i] = (int32_t)bs.size();
+      for (int32_t j = 0; j < n; ++j) {
+        dp_eval *ev = lanes[j].ev;
+        const dp_design *d = ev->d;
+        if (l > d->depth || !lanes[j].backward) continue;
+        int32_t g0, cnt;
+        level_part(d, l, k, &g0, &cnt);
+        if (cnt == 0) continue;
         const uint32_t blocks =
             (uint32_t)(((int64_t)cnt * ev->B + kMergedBlock - 1) / kMergedBlock);
-        fs.push_back({view(d), SpLevel{ev->sp.as<float>(), ev->B, g0, cnt}, f_blk[i]});
-        f_blk[i] += blocks;
-        if (lanes[j].backward) {
-          bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, cnt, b_blk[i]});
-          b_blk[i] += blocks;
-        }
+        bs.push_back({view(d), backward_args(ev, nullptr, 0, ev->B), g0, cnt, b_blk[i]});
+        b_blk[i] += blocks;
       }
-      f_cnt[i] = (int32_t)fs.size() - f_off[i];
       b_cnt[i] = (int32_t)bs.size() - b_off[i];
     }
 }
@@ -1537,11 +1604,8 @@ void MergedTables::pack(void *host) const {
 }
 
 dp_status MergedTables::launch_forward(const SpSeg *dev, hipStream_t s) const {
-  for (int32_t l = 1; l <= D; ++l)
-    for (int k = 0; k < 2; ++k) {
-      const size_t i = 2 * (size_t)l + k;
-      DP_HIP_TRY(launch_sp_multi(dev + f_off[i], f_cnt[i], f_blk[i], k == 1, s));
-    }
+  for (const FwdLaunch &fl : f_launch)
+    DP_HIP_TRY(launch_sp_multi(dev + fl.off, fl.cnt, fl.blocks, fl.cells, s));
   return DP_OK;
 }
 

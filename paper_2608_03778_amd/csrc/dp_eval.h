@@ -139,11 +139,21 @@ struct MergedTables {
   int32_t D = 0;
   std::vector<SpSeg> fs;
   std::vector<BwdSeg> bs;
-  // [2 (D + 1)], index 2 l + k: first segment, segment count, blocks
-  std::vector<int32_t> f_off, f_cnt, b_off, b_cnt;
-  std::vector<uint32_t> f_blk, b_blk;
+  // the forward's launches in order: first segment, segment count, blocks,
+  // kind (a launch covers one level index, or two when every design in it
+  // pairs them)
+  struct FwdLaunch {
+    int32_t off, cnt;
+    uint32_t blocks;
+    bool cells;
+  };
+  std::vector<FwdLaunch> f_launch;
+  // reverse, [2 (D + 1)], index 2 l + k: first segment, segment count, blocks
+  std::vector<int32_t> b_off, b_cnt;
+  std::vector<uint32_t> b_blk;
   void build(const Lane *lanes, int32_t n);
-  // Launches of one merged sweep (forward or reverse) over these lanes.
+  // Launches of one merged sweep over these lanes (the reverse; the
+  // forward's are at most as many).
   static int64_t level_launches(const Lane *lanes, int32_t n);
   // Packed layout: forward segments, then the reverse ones at bwd_offset().
   size_t bwd_offset() const;

@@ -95,6 +95,11 @@ hipError_t launch_import_sizes(const float *src, const int32_t *int2ext, float *
 // the flag runs a range of one kind; a level's library cells follow its
 // fixed cells).
 hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hipStream_t s);
+// Two consecutive levels of fixed cells in one launch (b starts where a
+// ends; the same columns and SP array): level b's lanes recompute the pins
+// level a drives instead of waiting for them, bit for bit as level a's
+// lanes compute them.
+hipError_t launch_sp_pair(const GraphView &g, const SpLevel &a, const SpLevel &b, hipStream_t s);
 
 // PI rows of one chunk for the launch's columns: Philox stimulus (stim ==
 // nullptr) or explicit words stim[c][i][T] (c counted from column cnt.col);
@@ -206,6 +211,9 @@ hipError_t launch_bwd_pi(const GraphView &g, const BwdArgs &a, float *out, hipSt
 struct SpSeg {
   GraphView g;
   SpLevel lv;
+  // the design's next level in the same launch (fixed cells, launch_sp_pair's
+  // recomputation), or n = 0; the segment's items are then (lv.n + lv2.n) B
+  SpLevel lv2;
   uint32_t block0;
 };
 struct BwdSeg {

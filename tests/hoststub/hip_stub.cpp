@@ -387,6 +387,24 @@ hipError_t launch_sp_level(const GraphView &g, const SpLevel &lv, bool cells, hi
   wr(lv.sp + (int64_t)(g.n_pi + lv.g0) * lv.B, (int64_t)lv.n * lv.B);
   return hipSuccess;
 }
+hipError_t launch_sp_pair(const GraphView &g, const SpLevel &a, const SpLevel &b, hipStream_t stream_) {
+  Scope sc_(stream_);
+  if (a.B != b.B || a.sp != b.sp || b.g0 != a.g0 + a.n) fatal("level pair not adjacent");
+  rd_graph(g, a.g0, a.n, false);
+  rd_graph(g, b.g0, b.n, false);
+  // every pin of the second level is stored before the launch or driven by
+  // the first level, whose gates read only nets stored before the launch
+  static const int kAr[9] = {1, 1, 2, 2, 2, 2, 2, 3, 3};
+  const int32_t lo = g.n_pi + a.g0, hi = lo + a.n;
+  for (int32_t i = a.g0; i < a.g0 + a.n; ++i)
+    for (int k = 0; k < kAr[g.op[i]]; ++k)
+      if (g.in[(int64_t)k * g.G + i] >= lo) fatal("first level of a pair reads its own level");
+  for (int32_t i = b.g0; i < b.g0 + b.n; ++i)
+    for (int k = 0; k < kAr[g.op[i]]; ++k)
+      if (g.in[(int64_t)k * g.G + i] >= hi) fatal("second level of a pair reads its own level");
+  wr(a.sp + (int64_t)(g.n_pi + a.g0) * a.B, ((int64_t)a.n + b.n) * a.B);
+  return hipSuccess;
+}
 hipError_t launch_markov_words(const float *sp, const float *tau, const int32_t *stream,
                                int32_t n_pi, int32_t B, int64_t T, uint64_t, uint64_t *out,
                                hipStream_t stream_) {
@@ -559,11 +577,17 @@ hipError_t launch_sp_multi(const SpSeg *segs, int32_t n_segs, uint32_t blocks, b
   Scope sc_(st);
   for (int32_t k = 0; k < n_segs; ++k) {
     const uint32_t b0 = segs[k].block0, b1 = k + 1 < n_segs ? segs[k + 1].block0 : blocks;
-    if (b1 < b0 || (int64_t)(b1 - b0) * kMergedBlock < (int64_t)segs[k].lv.n * segs[k].lv.B) {
+    const int64_t items = ((int64_t)segs[k].lv.n + segs[k].lv2.n) * segs[k].lv.B;
+    if (b1 < b0 || (int64_t)(b1 - b0) * kMergedBlock < items) {
       std::fprintf(stderr, "STUB: sp segment %d too small\n", k);
       std::abort();
     }
-    launch_sp_level(segs[k].g, segs[k].lv, cells, st);
+    if (segs[k].lv2.n > 0) {  // a pair: the single-design pair launch's checks
+      if (cells) fatal("a paired segment in a library-cell launch");
+      launch_sp_pair(segs[k].g, segs[k].lv, segs[k].lv2, st);
+    } else {
+      launch_sp_level(segs[k].g, segs[k].lv, cells, st);
+    }
   }
   return hipSuccess;
 }
