@@ -84,7 +84,10 @@ enum {
 /* Sweep schedules (see dp_eval_set_schedule). */
 enum {
   DP_SCHED_AUTO = 0,      /* the autotuned choice (default) */
-  DP_SCHED_LEVEL = 1,     /* one launch per level */
+  DP_SCHED_LEVEL = 1,     /* one launch per level (an SP-only forward with
+                             few columns: one per two levels of fixed cells,
+                             the second level recomputing the pins the first
+                             drives; bit for bit the same results) */
   DP_SCHED_GRAPH = 2,     /* the same launches captured once into HIP graphs,
                              one per forward sweep and one per reverse sweep
                              of dp_backward / dp_backward_columns (forward
@@ -432,7 +435,8 @@ dp_status dp_eval_get_profile(dp_eval *ev, dp_profile *out);
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * forward as dp_forward on a one-column eval in DP_MODELED or DP_FROZEN_BETA
- * (per-level launches; bit for bit the same results), without an eval: the
+ * (the same launches: one per level, or one per two levels of fixed cells;
+ * bit for bit the same results), without an eval: the
  * SP, the internal capacitances and beta and the power partial sums
  * live in a static device array of the library
  * (24 MiB on each GPU it runs on, held until the process ends; its

@@ -55,6 +55,7 @@ enum { SPAN_SIM = 0, SPAN_SP = 1, SPAN_BWD = 2, SPAN_STIM = 3 };
 
 dp::GraphView view(const dp_design *d) { return dp::design_view(d); }
 using dp::for_level_parts;
+using dp::pairs_levels;
 
 int32_t s_prime(const dp_eval *ev) { return (ev->S > 0 && !ev->paired_sizes) ? ev->S : 1; }
 double kappa_of(const dp_params &p) { return p.energy_factor * p.vdd * p.vdd * p.fclk; }
@@ -309,18 +310,6 @@ float *beta_or_null(dp_eval *ev) {
 // Whether the forward draws Markov stimulus words (a target transition rate
 // per PI and no explicit stimulus).
 bool markov(const dp_eval *ev) { return ev->have_tau && !ev->have_stim; }
-
-// Whether the modeled sweep runs levels l and l + 1 in one launch
-// (launch_sp_pair): both levels hold fixed cells only, and the pair's lanes
-// are few enough that a level launch is bound by its latency rather than its
-// bytes (the pair recomputes up to three gates per lane of its second level).
-constexpr int64_t kPairMaxLanes = 3 << 18;
-bool pairs_levels(const dp_design *d, int32_t l, int32_t B) {
-  if (l + 1 > d->depth) return false;
-  const int32_t a = d->level_ptr[l], m = d->level_ptr[l + 1], e = d->level_ptr[l + 2];
-  return d->lvl_fixed[l] == m - a && d->lvl_fixed[l + 1] == e - m &&
-         (int64_t)(e - a) * B <= kPairMaxLanes;
-}
 
 // Launches of the modeled sweep's SP levels.
 int64_t sp_sweep_launches(const dp_design *d, int32_t B) {

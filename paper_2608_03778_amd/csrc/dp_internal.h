@@ -162,6 +162,18 @@ dp_status for_level_parts(const dp_design *d, int32_t l, F &&f) {
   return DP_OK;
 }
 
+// Whether a probability-only sweep runs levels l and l + 1 in one launch
+// (launch_sp_pair): both levels hold fixed cells only, and the pair's lanes
+// are few enough that a level launch is bound by its latency rather than its
+// bytes (the pair recomputes up to three gates per lane of its second level).
+constexpr int64_t kPairMaxLanes = 3 << 18;
+inline bool pairs_levels(const dp_design *d, int32_t l, int32_t B) {
+  if (l + 1 > d->depth) return false;
+  const int32_t a = d->level_ptr[l], m = d->level_ptr[l + 1], e = d->level_ptr[l + 2];
+  return d->lvl_fixed[l] == m - a && d->lvl_fixed[l + 1] == e - m &&
+         (int64_t)(e - a) * B <= kPairMaxLanes;
+}
+
 // The heavy gates of the launch range [g0, g0 + n): a slice of the design's
 // ascending list.
 struct HeavySpan {

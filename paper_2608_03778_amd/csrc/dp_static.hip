@@ -88,11 +88,20 @@ extern "C" dp_status dp_forward_static(const dp_design *d, const dp_params *prm,
   DP_HIP_TRY(dp::launch_load_pi(pi_prob, spp, d->n_pi, 1, s));
   DP_HIP_TRY(dp::launch_gather_nets_f32(cap, i2e, capi, nn, s));
   if (beta) DP_HIP_TRY(dp::launch_gather_nets_f32(beta, i2e, betai, nn, s));
-  for (int32_t l = 1; l <= d->depth; ++l)
+  for (int32_t l = 1; l <= d->depth;) {
+    if (dp::pairs_levels(d, l, 1)) {  // levels l and l + 1 in one launch
+      const int32_t a0 = d->level_ptr[l], a1 = d->level_ptr[l + 1], b1 = d->level_ptr[l + 2];
+      DP_HIP_TRY(dp::launch_sp_pair(g, dp::SpLevel{spp, 1, a0, a1 - a0},
+                                    dp::SpLevel{spp, 1, a1, b1 - a1}, s));
+      l += 2;
+      continue;
+    }
     DP_TRY(dp::for_level_parts(d, l, [&](int32_t g0, int32_t n, bool cells) -> dp_status {
       DP_HIP_TRY(dp::launch_sp_level(g, dp::SpLevel{spp, 1, g0, n}, cells, s));
       return DP_OK;
     }));
+    ++l;
+  }
   dp::PowerArgs pa{};
   pa.sp = spp;
   pa.beta_frozen = beta ? betai : nullptr;
