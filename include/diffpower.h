@@ -44,7 +44,7 @@ typedef enum {
   DP_E_CYCLE = -2,       /* the netlist has a combinational cycle */
   DP_E_OOM = -3,         /* device or host allocation failed */
   DP_E_HIP = -4,         /* a HIP runtime call failed */
-  DP_E_UNSUPPORTED = -5, /* valid request this build does not implement */
+  DP_E_UNSUPPORTED = -5, /* a valid request the library does not implement */
   DP_E_STATE = -6,       /* call out of order (e.g. backward before forward) */
   DP_E_BUDGET = -7,      /* request can never fit the server's memory budget */
   DP_E_NOTFOUND = -8     /* unknown ticket or design id */

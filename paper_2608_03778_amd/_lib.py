@@ -158,8 +158,8 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"{path} is not built; run `python -c 'import __graft_entry__ as g; "
-                          "g.build()'` (hipcc, gfx950) first")
+        raise ImportError(f"{path} is not built; run `python -m paper_2608_03778_amd.build` "
+                          "(hipcc, gfx950) first")
     _settle_hip_runtime()
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():

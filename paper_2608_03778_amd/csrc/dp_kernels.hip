@@ -422,7 +422,7 @@ __device__ __forceinline__ void sp_pair_item(const GraphView &g, const SpLevel &
   const int32_t col = (int32_t)(t - gl * (uint32_t)B);
   const int32_t gi = b.g0 + (int32_t)gl;
   float *sp = b.sp;
-  // round 1: the gate's opcode and pins
+  // first load round: the gate's opcode and pins
   const int op = g.op[gi];
   const int32_t i0 = g.in[gi];
   const int32_t i1 = pin_row(g.in, g, 1)[gi];
@@ -432,7 +432,7 @@ __device__ __forceinline__ void sp_pair_item(const GraphView &g, const SpLevel &
   const int32_t lo = g.n_pi + a.g0, hi = lo + a.n;  // the nets level a drives
   const bool r0 = i0 >= lo && i0 < hi, r1 = k > 1 && i1 >= lo && i1 < hi,
              r2 = k > 2 && i2 >= lo && i2 < hi;
-  // round 2: a pin level a drives gives that gate's structure, any other
+  // second load round: a pin level a drives gives that gate's structure, any other
   // pin its stored probability
   int32_t po[3] = {0, 0, 0}, pj[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   float v[3] = {0.0f, 0.0f, 0.0f};
@@ -453,7 +453,7 @@ __device__ __forceinline__ void sp_pair_item(const GraphView &g, const SpLevel &
   }
   gathers_done(po[0], po[1], po[2], pj[0][0], pj[0][1], pj[0][2], pj[1][0], pj[1][1], pj[1][2],
                pj[2][0], pj[2][1], pj[2][2], v[0], v[1], v[2]);
-  // round 3: the recomputed gates' inputs (levels below a: already stored)
+  // third load round: the recomputed gates' inputs (levels below a: stored)
   float u[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
 #pragma unroll
   for (int j = 0; j < 3; ++j) {

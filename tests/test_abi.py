@@ -30,7 +30,7 @@ def _exported():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(L.LIB_PATH):
-        pytest.fail("libdiffpower.so is not built (run __graft_entry__.build())")
+        pytest.fail("libdiffpower.so is not built (run python -m paper_2608_03778_amd.build)")
     return L.load()
 
 
