@@ -394,87 +394,6 @@ __global__ __launch_bounds__(kBlock) void k_sp_cells(GraphView g, SpLevel lv) {
   if (idx < (uint32_t)lv.n * (uint32_t)lv.B) sp_item<true>(g, lv, idx);
 }
 
-// Two consecutive fixed-cell levels in one launch: lanes [0, a.n B) run
-// level a as k_sp_level does; lanes [a.n B, (a.n + b.n) B) run level b, and
-// a pin that level a drives is recomputed from that gate's own inputs (its
-// structure in the second load round, its inputs in the third) with the
-// arithmetic level a's lane performs, so the value is bit for bit the one
-// that lane stores.  One dependent round more than a level launch, one
-// launch boundary less: for a few columns, where a level's launch is
-// latency-bound, two levels cost about what one did.
-__device__ __forceinline__ f2 sp_recomputed(int op, float u0, float u1, float u2) {
-  const int k = arity_of(op);
-  const f2 z = f2{0.0f, 1.0f};
-  return sp_load(settle(sp_rule(op, sp_load(u0), k > 1 ? sp_load(u1) : z, k > 2 ? sp_load(u2) : z)));
-}
-
-__device__ __forceinline__ void sp_pair_item(const GraphView &g, const SpLevel &a,
-                                             const SpLevel &b, uint32_t idx) {
-  const uint32_t na = (uint32_t)a.n * (uint32_t)a.B;
-  if (idx < na) {
-    sp_item<false>(g, a, idx);
-    return;
-  }
-  const uint32_t t = idx - na;
-  const int32_t B = b.B;
-  if (t >= (uint32_t)b.n * (uint32_t)B) return;
-  const uint32_t gl = t / (uint32_t)B;
-  const int32_t col = (int32_t)(t - gl * (uint32_t)B);
-  const int32_t gi = b.g0 + (int32_t)gl;
-  float *sp = b.sp;
-  // first load round: the gate's opcode and pins
-  const int op = g.op[gi];
-  const int32_t i0 = g.in[gi];
-  const int32_t i1 = pin_row(g.in, g, 1)[gi];
-  const int32_t i2 = pin_row(g.in, g, 2)[gi];
-  gathers_done(op, i0, i1, i2);
-  const int k = arity_of(op);
-  const int32_t lo = g.n_pi + a.g0, hi = lo + a.n;  // the nets level a drives
-  const bool r0 = i0 >= lo && i0 < hi, r1 = k > 1 && i1 >= lo && i1 < hi,
-             r2 = k > 2 && i2 >= lo && i2 < hi;
-  // second load round: a pin level a drives gives that gate's structure, any other
-  // pin its stored probability
-  int32_t po[3] = {0, 0, 0}, pj[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  float v[3] = {0.0f, 0.0f, 0.0f};
-  const int32_t pin[3] = {i0, i1, i2};
-  const bool rec[3] = {r0, r1, r2};
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    if (j >= k) continue;
-    if (rec[j]) {
-      const int32_t pg = pin[j] - g.n_pi;
-      po[j] = g.op[pg];
-      pj[j][0] = g.in[pg];
-      pj[j][1] = pin_row(g.in, g, 1)[pg];
-      pj[j][2] = pin_row(g.in, g, 2)[pg];
-    } else {
-      v[j] = sp[(int64_t)pin[j] * B + col];
-    }
-  }
-  gathers_done(po[0], po[1], po[2], pj[0][0], pj[0][1], pj[0][2], pj[1][0], pj[1][1], pj[1][2],
-               pj[2][0], pj[2][1], pj[2][2], v[0], v[1], v[2]);
-  // third load round: the recomputed gates' inputs (levels below a: stored)
-  float u[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    if (j >= k || !rec[j]) continue;
-    const int kp = arity_of(po[j]);
-    u[j][0] = sp[(int64_t)pj[j][0] * B + col];
-    if (kp > 1) u[j][1] = sp[(int64_t)pj[j][1] * B + col];
-    if (kp > 2) u[j][2] = sp[(int64_t)pj[j][2] * B + col];
-  }
-  f2 x[3];
-  const f2 z = f2{0.0f, 1.0f};
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-    x[j] = j >= k ? z : (rec[j] ? sp_recomputed(po[j], u[j][0], u[j][1], u[j][2]) : sp_load(v[j]));
-  sp[(int64_t)(g.n_pi + gi) * B + col] = settle(sp_rule(op, x[0], x[1], x[2]));
-}
-
-__global__ __launch_bounds__(kWideBlock) void k_sp_pair(GraphView g, SpLevel a, SpLevel b) {
-  sp_pair_item(g, a, b, blockIdx.x * blockDim.x + threadIdx.x);
-}
-
 // The same for an even column count, two columns per lane: one 8-byte
 // access moves two stored probabilities, and half as many waves cover the
 // level.
@@ -763,6 +682,88 @@ __device__ __forceinline__ uint64_t stim_word(uint32_t pi, int64_t t, uint64_t t
     w |= bits << (4 * q);
   }
   return w;
+}
+
+// ---------------------------------------------------------------- paired SP levels
+// Two consecutive fixed-cell levels in one launch: lanes [0, a.n B) run
+// level a as k_sp_level does; lanes [a.n B, (a.n + b.n) B) run level b, and
+// a pin that level a drives is recomputed from that gate's own inputs (its
+// structure in the second load round, its inputs in the third) with the
+// arithmetic level a's lane performs, so the value is bit for bit the one
+// that lane stores.  One dependent round more than a level launch, one
+// launch boundary less: for a few columns, where a level's launch is
+// latency-bound, two levels cost about what one did.
+__device__ __forceinline__ f2 sp_recomputed(int op, float u0, float u1, float u2) {
+  const int k = arity_of(op);
+  const f2 z = f2{0.0f, 1.0f};
+  return sp_load(settle(sp_rule(op, sp_load(u0), k > 1 ? sp_load(u1) : z, k > 2 ? sp_load(u2) : z)));
+}
+
+__device__ __forceinline__ void sp_pair_item(const GraphView &g, const SpLevel &a,
+                                             const SpLevel &b, uint32_t idx) {
+  const uint32_t na = (uint32_t)a.n * (uint32_t)a.B;
+  if (idx < na) {
+    sp_item<false>(g, a, idx);
+    return;
+  }
+  const uint32_t t = idx - na;
+  const int32_t B = b.B;
+  if (t >= (uint32_t)b.n * (uint32_t)B) return;
+  const uint32_t gl = t / (uint32_t)B;
+  const int32_t col = (int32_t)(t - gl * (uint32_t)B);
+  const int32_t gi = b.g0 + (int32_t)gl;
+  float *sp = b.sp;
+  // first load round: the gate's opcode and pins
+  const int op = g.op[gi];
+  const int32_t i0 = g.in[gi];
+  const int32_t i1 = pin_row(g.in, g, 1)[gi];
+  const int32_t i2 = pin_row(g.in, g, 2)[gi];
+  gathers_done(op, i0, i1, i2);
+  const int k = arity_of(op);
+  const int32_t lo = g.n_pi + a.g0, hi = lo + a.n;  // the nets level a drives
+  const bool r0 = i0 >= lo && i0 < hi, r1 = k > 1 && i1 >= lo && i1 < hi,
+             r2 = k > 2 && i2 >= lo && i2 < hi;
+  // second load round: a pin level a drives gives that gate's structure, any other
+  // pin its stored probability
+  int32_t po[3] = {0, 0, 0}, pj[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  float v[3] = {0.0f, 0.0f, 0.0f};
+  const int32_t pin[3] = {i0, i1, i2};
+  const bool rec[3] = {r0, r1, r2};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (j >= k) continue;
+    if (rec[j]) {
+      const int32_t pg = pin[j] - g.n_pi;
+      po[j] = g.op[pg];
+      pj[j][0] = g.in[pg];
+      pj[j][1] = pin_row(g.in, g, 1)[pg];
+      pj[j][2] = pin_row(g.in, g, 2)[pg];
+    } else {
+      v[j] = sp[(int64_t)pin[j] * B + col];
+    }
+  }
+  gathers_done(po[0], po[1], po[2], pj[0][0], pj[0][1], pj[0][2], pj[1][0], pj[1][1], pj[1][2],
+               pj[2][0], pj[2][1], pj[2][2], v[0], v[1], v[2]);
+  // third load round: the recomputed gates' inputs (levels below a: stored)
+  float u[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (j >= k || !rec[j]) continue;
+    const int kp = arity_of(po[j]);
+    u[j][0] = sp[(int64_t)pj[j][0] * B + col];
+    if (kp > 1) u[j][1] = sp[(int64_t)pj[j][1] * B + col];
+    if (kp > 2) u[j][2] = sp[(int64_t)pj[j][2] * B + col];
+  }
+  f2 x[3];
+  const f2 z = f2{0.0f, 1.0f};
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    x[j] = j >= k ? z : (rec[j] ? sp_recomputed(po[j], u[j][0], u[j][1], u[j][2]) : sp_load(v[j]));
+  sp[(int64_t)(g.n_pi + gi) * B + col] = settle(sp_rule(op, x[0], x[1], x[2]));
+}
+
+__global__ __launch_bounds__(kWideBlock) void k_sp_pair(GraphView g, SpLevel a, SpLevel b) {
+  sp_pair_item(g, a, b, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- Markov stimulus
