@@ -1204,7 +1204,12 @@ __device__ __forceinline__ float seed_of(const BwdArgs &a, int32_t n, int32_t c,
 // Every lane of the wave must call this (inactive lanes pass e0 == e1 and
 // active == false); `serial` must be uniform across the wave.
 constexpr int32_t kStrand = 8;
-constexpr int32_t kSerialColumns = 32;  // C at which every pull is lane-serial
+// C at which every pull is lane-serial (nets with more than kHeavyPull entries
+// pulled by whole workgroups); below it a wave's lanes share its nets' long
+// ranges.  Measured on the 1M-gate design (modeled fwd+bwd): the shared pull
+// wins at 1 and 4 columns (0.65 against 1.11 ms, 1.05 against 1.16 ms), the
+// lane-serial one from 5 (1.18 against 1.30 ms) and by 3.2x at 16.
+constexpr int32_t kSerialColumns = 5;
 
 // The entries [e, min(e + kStrand, e1)) of one strand into v (zeros past e1).
 __device__ __forceinline__ void strand_load(const float *__restrict__ contrib, int32_t e,
@@ -2269,14 +2274,18 @@ hipError_t launch_bwd_level(const GraphView &g, const BwdArgs &a, int32_t g0, in
                                                                           0, 0);
   } else if (a.C >= kSerialColumns) {
     if (n_heavy < 0 || (n_heavy > 0 && !heavy)) return hipErrorInvalidValue;
+    // 256-thread workgroups at every size: the instance holds 16 KiB of LDS
+    // for its heavy-net blocks, so one-wave workgroups would leave a CU ten
+    // waves (8 columns: 0.87 ms fwd+bwd against 1.18 ms at 6 with one-wave
+    // groups on the 1M-gate design)
     const int64_t hb = (int64_t)n_heavy * ((a.C + 63) / 64);
-    const int64_t blocks = hb + level_grid(items);
+    const int64_t blocks = hb + blocks_for(items);
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     if (a.C % 64 == 0)  // one gate per wave
-      k_bwd_level<false, true, true><<<(unsigned)blocks, level_block(items), 0, s>>>(
+      k_bwd_level<false, true, true><<<(unsigned)blocks, kWideBlock, 0, s>>>(
           g, a, g0, n, heavy, n_heavy, (uint32_t)hb);
     else
-      k_bwd_level<false, true><<<(unsigned)blocks, level_block(items), 0, s>>>(
+      k_bwd_level<false, true><<<(unsigned)blocks, kWideBlock, 0, s>>>(
           g, a, g0, n, heavy, n_heavy, (uint32_t)hb);
   } else {
     k_bwd_level<false, false><<<level_grid(items), level_block(items), 0, s>>>(g, a, g0, n,
