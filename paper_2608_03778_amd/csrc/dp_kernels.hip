@@ -1207,9 +1207,14 @@ constexpr int32_t kStrand = 8;
 // C at which every pull is lane-serial (nets with more than kHeavyPull entries
 // pulled by whole workgroups); below it a wave's lanes share its nets' long
 // ranges.  Measured on the 1M-gate design (modeled fwd+bwd): the shared pull
-// wins at 1 and 4 columns (0.65 against 1.11 ms, 1.05 against 1.16 ms), the
-// lane-serial one from 5 (1.18 against 1.30 ms) and by 3.2x at 16.
-constexpr int32_t kSerialColumns = 5;
+// wins at 1 and 2 columns (0.65 against 0.81 ms, 0.71 against 0.82 ms), the
+// lane-serial one from 3 (0.83 against 0.88 ms; 0.83 against 1.06 ms at 4, and
+// 3.2x at 16).
+constexpr int32_t kSerialColumns = 3;
+// The same switch for launches without heavy-net workgroups (library cells,
+// merged launches of several designs, the persistent kernel), where a
+// lane-serial pull of a long range costs one lane several dependent rounds.
+constexpr int32_t kSerialColumnsNoHeavy = 32;
 
 // The entries [e, min(e + kStrand, e1)) of one strand into v (zeros past e1).
 __device__ __forceinline__ void strand_load(const float *__restrict__ contrib, int32_t e,
@@ -1382,7 +1387,7 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const float cap = a.cap[out];
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
     const float pulled =
-        pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumns);
+        pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumnsNoHeavy);
     if (!active) return;
     float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
     if (a.ste) lam *= beta;
@@ -1559,8 +1564,11 @@ __global__ __launch_bounds__(kWideBlock) void k_bwd_level(GraphView g, BwdArgs a
 
 // skip_heavy: PIs with more than kHeavyPull fan-out entries are left to the
 // launch's cooperative blocks (bwd_pi_heavy).
+// serial_cols: the column count from which pulls are lane-serial (the
+// launch's choice: with or without heavy-PI workgroups).
 __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a, float *out,
-                                            uint32_t idx, int lane, bool skip_heavy = false) {
+                                            uint32_t idx, int lane, bool skip_heavy = false,
+                                            int32_t serial_cols = kSerialColumns) {
   const bool active = idx < (uint32_t)g.n_pi * (uint32_t)a.C;
   const uint32_t i = active ? idx / (uint32_t)a.C : 0;
   const int32_t c = active ? (int32_t)(idx - i * (uint32_t)a.C) : 0;
@@ -1571,7 +1579,7 @@ __device__ __forceinline__ void bwd_pi_item(const GraphView &g, const BwdArgs &a
   const f2 pq = sp_load(a.sp[(int64_t)i * a.B + b]);
   const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)i : (int64_t)i * a.B + b] : 1.0f;
   const float cap = a.cap[i];
-  const bool serial = a.C >= kSerialColumns;
+  const bool serial = a.C >= serial_cols;
   if (serial && skip_heavy && e1r - e0 > kHeavyPull) return;  // (lane-serial pulls only)
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, serial);
   if (!active) return;
@@ -1703,7 +1711,7 @@ __global__ __launch_bounds__(kMergedBlock) void k_bwd_multi(const BwdSeg *__rest
                                                             int32_t n_segs) {
   const BwdSeg sg = segs[seg_of(segs, n_segs)];
   const uint32_t idx = (blockIdx.x - sg.block0) * kMergedBlock + threadIdx.x;
-  if (!CELLS && sg.a.C >= kSerialColumns)  // segments differ in width: chosen per block
+  if (!CELLS && sg.a.C >= kSerialColumnsNoHeavy)  // segments differ in width: chosen per block
     bwd_item<CELLS, true>(sg.g, sg.a, sg.g0, sg.n, idx, threadIdx.x & 63);
   else
     bwd_item<CELLS, false>(sg.g, sg.a, sg.g0, sg.n, idx, threadIdx.x & 63);
@@ -1857,7 +1865,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_persistent(GraphView g, BwdArgs 
     return;
   }
   for (uint32_t base = first - lane; base < items; base += stride)
-    bwd_pi_item(g, a, pi_out, base + lane, lane);
+    bwd_pi_item(g, a, pi_out, base + lane, lane, false, kSerialColumnsNoHeavy);
 }
 
 // dP/dC_n = sum_{b,s} w[b][s] kappa beta TR_model s_s(drv n);
@@ -2353,7 +2361,7 @@ hipError_t launch_bwd_persistent(const GraphView &g, const BwdArgs &a, const int
                                  GridBarrier bar, hipStream_t s) {
   max_items = std::max<int64_t>(max_items, (int64_t)g.n_pi * a.C);
   if (max_items >= (1ll << 31) || !bar.words) return hipErrorInvalidValue;
-  const void *kernel = a.C >= kSerialColumns
+  const void *kernel = a.C >= kSerialColumnsNoHeavy
                            ? reinterpret_cast<const void *>(&k_bwd_persistent<true>)
                            : reinterpret_cast<const void *>(&k_bwd_persistent<false>);
   unsigned grid = 0;
