@@ -291,11 +291,14 @@ def sizing_bench(ctx, reps=3):
     t_f = time_steps(lambda: ev.forward(("power",), device=True), reps, 1)
     tuned = ev.get_schedule()
     # the same sweeps captured: one graph launch for the forward (one
-    # stimulus and one launch per level for all 32 columns, finalize,
-    # power) and one for the reverse sweep
+    # stimulus and one launch per level for all 32 columns, power) and one
+    # for the reverse sweep
     ev.set_schedule(L.DP_SCHED_GRAPH)
     t_gb = time_steps(batched, reps, 1)
     t_gf = time_steps(lambda: ev.forward(("power",), device=True), reps, 1)
+    # forward and reverse sweep captured together: the whole sweep (8,192
+    # results) is one graph launch
+    t_1g = time_steps(lambda: ev.forward_backward_columns(device=True), reps, 1)
     one = api.Eval(d, 1, 1, mode=L.DP_HYBRID, n_sim=65536, seed=1)
     one.set_pi_prob(p[:1])
     one.set_caps(cap)
@@ -310,9 +313,10 @@ def sizing_bench(ctx, reps=3):
                 batched_fwd_ms=t_f * 1e3, batched_fwdbwd_ms=t_b * 1e3,
                 graph_fwd_ms=t_gf * 1e3, graph_fwdbwd_ms=t_gb * 1e3,
                 graph_launches_per_query=2,
+                one_graph_fwdbwd_ms=t_1g * 1e3, one_graph_launches=1,
                 single_query_fwdbwd_ms=t_1 * 1e3,
                 one_at_a_time_fwdbwd_ms=t_1 * 1e3 * B * S,
-                speedup_vs_one_at_a_time=t_1 * B * S / min(t_b, t_gb),
+                speedup_vs_one_at_a_time=t_1 * B * S / min(t_b, t_gb, t_1g),
                 schedule=tuned)
 
 

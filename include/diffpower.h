@@ -329,6 +329,19 @@ dp_status dp_backward(dp_eval *ev, const float *grad_power, float *dpower_dpi,
  * partial derivatives to its S' seeds.  Errors as dp_backward. */
 dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device);
 
+/* The forward pass and the per-(b, s) reverse sweep of dp_backward_columns
+ * in one call (a sizing sweep over B PI vectors and S size vectors, Sec.
+ * III-E applied to every column): power [B][S'] and dpower_dpi
+ * [B][S'][n_pi], both on the device (on_device = 1) or host.  Under
+ * DP_SCHED_GRAPH both sweeps are captured into one graph, so the whole
+ * sweep is one graph launch (re-captured when any launch argument
+ * changes; a sweep of more than 1024 launches runs launch by launch).
+ * Results are bit for bit those of dp_forward followed by
+ * dp_backward_columns.  Either output may be NULL.  Errors as dp_forward
+ * and dp_backward. */
+dp_status dp_forward_backward_columns(dp_eval *ev, float *power, float *dpower_dpi,
+                                      int32_t on_device);
+
 /* Power gradients of every net (Sec. IV): one reverse sweep after a
  * completed forward (grad_power = 1, per query column) that keeps every
  * net's adjoint.  dpower_dsp [B][n_nets] (caller numbering) receives

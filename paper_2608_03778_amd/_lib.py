@@ -102,6 +102,7 @@ SIGNATURES = {
     "dp_forward": (_st, [_p, _p]),
     "dp_backward": (_st, [_p, _p, _p, _p, _p, _i32]),
     "dp_backward_columns": (_st, [_p, _p, _i32]),
+    "dp_forward_backward_columns": (_st, [_p, _p, _p, _i32]),
     "dp_power_virus": (_st, [_p, _i32, ctypes.c_double, _p, _p, _p, _i32]),
     "dp_power_gradients": (_st, [_p, _p, _p, _i32]),
     "dp_forward_static": (_st, [_p, _p, _p, _p, _p, _p, _p, _p]),

@@ -301,6 +301,24 @@ class Eval:
         check(self.lib.dp_backward_columns(self.handle, ptr, int(bool(device))))
         return arr
 
+    def forward_backward_columns(self, device: bool = False):
+        """The forward pass and backward_columns in one call (one graph
+        launch under DP_SCHED_GRAPH): power [B][S'] and dP/dp [B][S'][n_pi]."""
+        d = self.design
+        Sp = max(self.S, 1)
+        if device:
+            import torch
+            dev = f"cuda:{d.ctx.device}"
+            power = torch.empty((self.B, Sp), dtype=torch.float32, device=dev)
+            dpi = torch.empty((self.B, Sp, d.n_pi), dtype=torch.float32, device=dev)
+            pp, pd = ctypes.c_void_p(power.data_ptr()), ctypes.c_void_p(dpi.data_ptr())
+        else:
+            power = np.empty((self.B, Sp), dtype=np.float32)
+            dpi = np.empty((self.B, Sp, d.n_pi), dtype=np.float32)
+            pp, pd = power.ctypes.data_as(ctypes.c_void_p), dpi.ctypes.data_as(ctypes.c_void_p)
+        check(self.lib.dp_forward_backward_columns(self.handle, pp, pd, int(bool(device))))
+        return power, dpi
+
     def power_gradients(self):
         """Every net's dPower/dP [B][n_nets] and the Eq. 8 sizing score of
         every gate [B][n_gates] (caller numbering), after a forward."""

@@ -784,6 +784,7 @@ double kappa(const dp_params &p) { return kappa_of(p); }
 dp_eval::~dp_eval() {
   if (graph_fwd) (void)hipGraphExecDestroy(graph_fwd);
   if (graph_bwd) (void)hipGraphExecDestroy(graph_bwd);
+  if (graph_fb) (void)hipGraphExecDestroy(graph_fb);
   if (capture_stream_owned) (void)hipStreamDestroy(capture_stream_owned);
   if (coop_stream) {
     (void)hipStreamSynchronize(coop_stream);
@@ -1474,6 +1475,82 @@ dp_status dp_backward_columns(dp_eval *ev, float *dpower_dpi, int32_t on_device)
   if (!ev) return fail(DP_E_INVALID, "dp_backward_columns: NULL eval");
   if (!dpower_dpi) return fail(DP_E_INVALID, "dp_backward_columns: NULL output");
   return run_backward(ev, nullptr, 1, dpower_dpi, nullptr, nullptr, on_device);
+}
+
+dp_status dp_forward_backward_columns(dp_eval *ev, float *power, float *dpower_dpi,
+                                      int32_t on_device) {
+  if (!ev) return fail(DP_E_INVALID, "dp_forward_backward_columns: NULL eval");
+  const dp_design *d = ev->d;
+  // the schedules that capture: the whole pair of sweeps as one graph;
+  // otherwise the two calls as they are
+  const bool hyb = hybrid(ev);
+  ChunkPlan plan;
+  if (hyb) plan = plan_chunks(ev);
+  const ChunkPlan *pl = hyb ? &plan : nullptr;
+  const int64_t launches = forward_launches(ev, pl) + d->depth + d->split_levels + 1;
+  if (ev->schedule != DP_SCHED_GRAPH || ev->profiling || launches > kMaxGraphLaunches) {
+    DP_TRY(dp_forward(ev, nullptr));
+    if (power) {
+      const size_t bytes = (size_t)ev->B * s_prime(ev) * sizeof(float);
+      DP_HIP_TRY(hipMemcpyAsync(power, ev->power.ptr, bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                ev->stream()));
+    }
+    if (dpower_dpi) return run_backward(ev, nullptr, 1, dpower_dpi, nullptr, nullptr, on_device);
+    if (!on_device) {
+      DP_TRY(sync_and_check(ev));
+      DP_HIP_TRY(hipStreamSynchronize(ev->stream()));
+    }
+    return DP_OK;
+  }
+  // the checks of dp_forward and dp_backward, then every buffer before the
+  // capture
+  if (!ev->have_pi) return fail(DP_E_STATE, "dp_forward_backward_columns: PI probabilities not set");
+  if (!ev->have_cap) return fail(DP_E_STATE, "dp_forward_backward_columns: capacitances not set");
+  if (ev->S > 0 && !ev->have_size)
+    return fail(DP_E_STATE, "dp_forward_backward_columns: cell sizes not set");
+  if (ev->prm.mode == DP_FROZEN_BETA && !ev->have_beta)
+    return fail(DP_E_STATE, "dp_forward_backward_columns: DP_FROZEN_BETA needs dp_set_beta");
+  if (hyb && ev->have_stim &&
+      ev->stim.bytes < (size_t)ev->B * d->n_pi * n_words(ev->prm) * sizeof(uint64_t))
+    return fail(DP_E_STATE, "dp_forward_backward_columns: the explicit stimulus is shorter than "
+                            "n_sim/64 words");
+  DP_HIP_TRY(hipSetDevice(d->ctx->device));
+  hipStream_t s = ev->stream();
+  DP_TRY(ensure_forward_buffers(ev, pl));
+  const int32_t C = ev->B * s_prime(ev);
+  DP_TRY(ev->contrib.alloc(std::max<size_t>((size_t)d->n_edges * C * sizeof(float), 16)));
+  const size_t dpi_bytes = (size_t)C * d->n_pi * sizeof(float);
+  float *dst = on_device ? dpower_dpi : nullptr;
+  if (!dst) {  // host output, or none: the sweep writes the staging buffer
+    DP_TRY(ev->pi_out.alloc(std::max<size_t>(dpi_bytes, 16)));
+    dst = ev->pi_out.as<float>();
+  }
+  const dp::BwdArgs ba = backward_args(ev, nullptr, 1, C);
+  uint64_t key = graph_key(ev, pl);
+  auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+  mix((uint64_t)(uintptr_t)dst);
+  mix((uint64_t)(uintptr_t)ev->contrib.ptr);
+  mix((uint64_t)C);
+  if (!ev->graph_fb || ev->graph_fb_key != key) {
+    DP_TRY(capture_into(ev, &ev->graph_fb, [&]() -> dp_status {
+      DP_TRY(enqueue_forward(ev, pl));
+      return enqueue_backward(ev, ba, dst);
+    }));
+    ev->graph_fb_key = key;
+  }
+  DP_HIP_TRY(hipGraphLaunch(ev->graph_fb, s));
+  ev->fwd_version = ev->inputs_version;
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (power)
+    DP_HIP_TRY(hipMemcpyAsync(power, ev->power.ptr, (size_t)C * sizeof(float), k, s));
+  if (dpower_dpi && !on_device && dpi_bytes)
+    DP_HIP_TRY(hipMemcpyAsync(dpower_dpi, dst, dpi_bytes, hipMemcpyDeviceToHost, s));
+  if (!on_device) {
+    DP_TRY(sync_and_check(ev));
+    DP_HIP_TRY(hipStreamSynchronize(s));
+  }
+  return DP_OK;
 }
 
 }  // extern "C"

@@ -82,6 +82,8 @@ struct dp_eval {
   uint64_t graph_key = 0;
   hipGraphExec_t graph_bwd = nullptr;  // the reverse sweep of dp_backward
   uint64_t graph_bwd_key = 0;
+  hipGraphExec_t graph_fb = nullptr;   // both sweeps of dp_forward_backward_columns
+  uint64_t graph_fb_key = 0;
   ~dp_eval();
 };
 
