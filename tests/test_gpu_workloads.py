@@ -122,14 +122,19 @@ def test_dag117k_sizing_sweep_spot_parity():
     ev.set_cell_sizes(size)
     power = ev.forward(("power",))["power"]
     cols = ev.backward_columns()
-    # the whole sweep captured as two graph launches, as the benchmark also
-    # times it, gives the same results bit for bit (the autotuner's own pick
+    # the whole sweep captured as two graph launches, and as one, as the
+    # benchmark also times it, gives the same results bit for bit (the autotuner's own pick
     # is checked in a process of its own: test_gpu_autotune.py)
     say("sizing sweep: graph schedule")
     ev.set_schedule(L.DP_SCHED_GRAPH)
     for _ in range(2):
         np.testing.assert_array_equal(ev.forward(("power",))["power"], power)
         np.testing.assert_array_equal(ev.backward_columns(), cols)
+    say("sizing sweep: forward and reverse as one graph launch")
+    for _ in range(2):
+        pw, g = ev.forward_backward_columns()
+        np.testing.assert_array_equal(pw, power)
+        np.testing.assert_array_equal(g, cols)
     o = oracle.Netlist.of(nl)
     rng = np.random.default_rng(3)
     for b in rng.choice(B, 4, replace=False):
