@@ -119,6 +119,13 @@ def scenario_flows(ctx):
                     ev.forward(("sp", "tr", "power"))
                     ev.backward(want=("dpi", "dcap") + (("dsize",) if S else ()))
                     runs += 1
+                # a sizing sweep's two sweeps in one call: one captured graph
+                # (twice: the second replays it), then the plain calls
+                for sched in (L.DP_SCHED_GRAPH, L.DP_SCHED_GRAPH, L.DP_SCHED_LEVEL):
+                    ev.set_schedule(sched)
+                    ev.set_sim_streams(1)
+                    ev.forward_backward_columns()
+                    runs += 1
                 ev.set_schedule(L.DP_SCHED_LEVEL)
                 ev.set_sim_streams(1)
                 ev.power_gradients()

@@ -55,7 +55,7 @@ def test_compile_and_levelization(stub_lib):
 
 def test_eval_flows_and_validation(stub_lib):
     r = _run(stub_lib, "flows")
-    assert r["fixed_runs"] == 28 and r["library_runs"] == 22
+    assert r["fixed_runs"] == 46 and r["library_runs"] == 40
     for name in ("fixed", "library"):
         assert r[f"{name}_backward_first"] == "DP_E_STATE"
         assert r[f"{name}_forward_no_inputs"] == "DP_E_STATE"
