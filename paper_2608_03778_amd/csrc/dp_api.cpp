@@ -746,14 +746,9 @@ dp_status enqueue_backward(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
   return DP_OK;
 }
 
-// The reverse sweep of run_backward: under DP_SCHED_GRAPH captured once
-// into ev->graph_bwd (re-captured when any launch argument changes) and
-// replayed, otherwise enqueued launch by launch.
-dp_status reverse_sweep(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
-  const dp_design *d = ev->d;
-  const int64_t launches = (int64_t)d->depth + d->split_levels + 1;
-  if (ev->schedule != DP_SCHED_GRAPH || ev->profiling || launches > kMaxGraphLaunches)
-    return enqueue_backward(ev, ba, dst);
+// Every argument the reverse sweep's launches take (a captured sweep is
+// replayed only while all of them are unchanged).
+uint64_t reverse_key(const dp_eval *ev, const dp::BwdArgs &ba, const float *dst) {
   uint64_t k = 1469598103934665603ull;
   auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
   for (const void *ptr : {(const void *)ba.sp, (const void *)ba.beta, (const void *)ba.cap,
@@ -764,8 +759,21 @@ dp_status reverse_sweep(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
   uint32_t kb;
   std::memcpy(&kb, &ba.kappa, 4);
   mix(kb);
-  for (int32_t v : {ba.n_pi, ba.G, ba.B, ba.S, ba.C, ba.cdiv, ba.ste, ba.per_column, ba.paired})
+  for (int32_t v : {ba.n_pi, ba.G, ba.B, ba.S, ba.C, ba.cdiv, ba.ste, ba.per_column, ba.paired,
+                    ba.beta_shared})
     mix((uint64_t)(uint32_t)v);
+  return k;
+}
+
+// The reverse sweep of run_backward: under DP_SCHED_GRAPH captured once
+// into ev->graph_bwd (re-captured when any launch argument changes) and
+// replayed, otherwise enqueued launch by launch.
+dp_status reverse_sweep(dp_eval *ev, const dp::BwdArgs &ba, float *dst) {
+  const dp_design *d = ev->d;
+  const int64_t launches = (int64_t)d->depth + d->split_levels + 1;
+  if (ev->schedule != DP_SCHED_GRAPH || ev->profiling || launches > kMaxGraphLaunches)
+    return enqueue_backward(ev, ba, dst);
+  const uint64_t k = reverse_key(ev, ba, dst);
   if (!ev->graph_bwd || ev->graph_bwd_key != k) {
     DP_TRY(capture_into(ev, &ev->graph_bwd, [&]() { return enqueue_backward(ev, ba, dst); }));
     ev->graph_bwd_key = k;
@@ -1527,11 +1535,8 @@ dp_status dp_forward_backward_columns(dp_eval *ev, float *power, float *dpower_d
     dst = ev->pi_out.as<float>();
   }
   const dp::BwdArgs ba = backward_args(ev, nullptr, 1, C);
-  uint64_t key = graph_key(ev, pl);
-  auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
-  mix((uint64_t)(uintptr_t)dst);
-  mix((uint64_t)(uintptr_t)ev->contrib.ptr);
-  mix((uint64_t)C);
+  // the forward's key and the reverse sweep's, combined
+  const uint64_t key = graph_key(ev, pl) * 1099511628211ull ^ reverse_key(ev, ba, dst);
   if (!ev->graph_fb || ev->graph_fb_key != key) {
     DP_TRY(capture_into(ev, &ev->graph_fb, [&]() -> dp_status {
       DP_TRY(enqueue_forward(ev, pl));

@@ -420,6 +420,19 @@ def test_forward_backward_columns_in_one_graph(ctx, mode):
         np.testing.assert_array_equal(pw.cpu().numpy(), want[1][0])
         np.testing.assert_array_equal(g.cpu().numpy(), want[1][1])
         np.testing.assert_array_equal(ev.backward_columns(), want[1][1])
+    # an argument only the reverse sweep takes changes after a capture (PIs
+    # marked fixed): the graph is captured again, not replayed stale
+    ev = make(L.DP_SCHED_GRAPH)
+    ev.forward_backward_columns()
+    fixed = np.arange(nl.n_pi) % 3 == 0
+    for e in (ev, ref):
+        e.set_pi_prob(p)
+        e.set_pi_fixed(fixed)
+    want_f = (ref.forward(("power",))["power"], ref.backward_columns())
+    assert (want_f[1][:, :, fixed] == 0).all() and (want_f[1][:, :, ~fixed] != 0).any()
+    pw, g = ev.forward_backward_columns()
+    np.testing.assert_array_equal(pw, want_f[0])
+    np.testing.assert_array_equal(g, want_f[1])
 
 
 @pytest.mark.skip(reason="a host crash inside dp_eval_autotune when this test ran after the "
