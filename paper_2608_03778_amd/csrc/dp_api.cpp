@@ -639,6 +639,10 @@ uint64_t graph_key(const dp_eval *ev, const ChunkPlan *pl) {
   mix((uint64_t)(uintptr_t)ev->beta_frozen.ptr);
   mix((uint64_t)(uintptr_t)ev->size.ptr);
   mix((uint64_t)(uintptr_t)ev->stream());
+  mix((uint64_t)ev->B);
+  mix((uint64_t)ev->S);
+  mix((uint64_t)ev->paired_sizes);
+  mix((uint64_t)ev->beta_shared);
   if (pl) {
     mix((uint64_t)pl->Tc);
     mix((uint64_t)pl->cols);
