@@ -398,6 +398,48 @@ def test_adjoint_beta_modes():
     assert lam_l[0] == pytest.approx(0.5 * local)
 
 
+def test_adjoint_ste_is_the_derivative_of_its_surrogate():
+    """Eq. 6 read literally (beta_ste) is reverse mode through a surrogate
+    forward in which every net passes on y_n = beta_n x_n + (1 - beta_n) x*_n
+    (x*_n its value at the base point: the same value, slope beta_n) and the
+    power is sum_n kappa C_n 2 y_n (1 - y_n).  The surrogate's complex-step
+    derivative, from a minterm-sum forward written here, equals the STE
+    adjoint at every PI of a random DAG whose betas are far from 1."""
+    nl = synth.random_dag(synth.DagSpec(n_gates=300, n_pi=12, depth=10), 7)
+    o = oracle.Netlist.of(nl)
+    rng = np.random.default_rng(7)
+    p = rng.uniform(0.1, 0.9, nl.n_pi)
+    cap = synth.net_caps(nl.n_nets, 7)
+    beta = rng.uniform(0.3, 2.5, nl.n_nets)
+    kappa = 0.5
+    gate_order = np.argsort(o.levels()[nl.n_pi:], kind="stable")
+
+    def surrogate(dp, slope, base):
+        y = np.zeros(nl.n_nets, dtype=complex)
+        y[: nl.n_pi] = p + slope[: nl.n_pi] * dp  # x* = p at a PI
+        for g in gate_order:
+            fan = nl.fanin[nl.fanin_ptr[g]:nl.fanin_ptr[g + 1]]
+            x = brute.gate_probability(int(nl.op[g]), [y[i] for i in fan])
+            n = nl.n_pi + g
+            y[n] = slope[n] * x + (1 - slope[n]) * base[n]
+        return y, sum(kappa * float(cap[n]) * 2 * y[n] * (1 - y[n]) for n in range(nl.n_nets))
+
+    ones = np.ones(nl.n_nets)
+    base = surrogate(np.zeros(nl.n_pi), ones, np.zeros(nl.n_nets))[0].real  # plain forward
+    y0 = surrogate(np.zeros(nl.n_pi), beta, base)[0]
+    np.testing.assert_allclose(y0.real, base, rtol=0, atol=1e-14)  # the same values, any beta
+    P = o.sp(p)
+    np.testing.assert_allclose(base, P, rtol=0, atol=1e-14)
+    lam = o.adjoint(P, beta, cap, kappa=kappa, beta_ste=True)["lam"]
+    h = 1e-30
+    cs = np.array([surrogate(np.eye(nl.n_pi)[i] * 1j * h, beta, base)[1].imag / h
+                   for i in range(nl.n_pi)])
+    np.testing.assert_allclose(lam[: nl.n_pi], cs, rtol=1e-12, atol=1e-14 * np.abs(cs).max())
+    # and it is not the local-beta gradient, which the surrogate does not give
+    lam_local = o.adjoint(P, beta, cap, kappa=kappa)["lam"]
+    assert np.abs(lam_local[: nl.n_pi] - cs).max() > 1e-3 * np.abs(cs).max()
+
+
 def test_stimulus_threshold_boundary():
     """A lane whose uniform equals the threshold exactly is 0 (strict u < thr):
     find a Philox output with 8 trailing zero bits, so u / 2^32 is a float32,
