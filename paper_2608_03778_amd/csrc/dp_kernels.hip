@@ -1376,16 +1376,12 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   int32_t e0 = g.rev_ptr[out];
   int32_t e1r = g.rev_ptr[out + 1];
   int op = g.op[gi];
-  if constexpr (UNI) {
-    e0 = __builtin_amdgcn_readfirstlane(e0);
-    e1r = __builtin_amdgcn_readfirstlane(e1r);
-    op = __builtin_amdgcn_readfirstlane(op);
-  }
-  const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
-  const f2 pq = sp_load(sp[(int64_t)out * a.B + b]);
+  const float sp_out = sp[(int64_t)out * a.B + b];
   const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)out : (int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
   if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
+    const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
+    const f2 pq = sp_load(sp_out);
     const float pulled =
         pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumnsNoHeavy);
     if (!active) return;
@@ -1402,55 +1398,45 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
       a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
     return;
   }
-  int32_t i0, i1, i2, s0, s1, s2;  // fan-in nets and the slots their contributions go to
-  f2 x0, x1, x2;
-  if constexpr (WIDE) {
-    // many columns: a wave's lanes share one or two gates, and the sweep is
-    // bound by the rows it moves, so only the pins a gate has are gathered;
-    // every pin's index and slot go out with the opcode (unused pin rows
-    // alias pin 0), so the gathers wait on one round only
-    i0 = g.in[gi];
-    i1 = pin_row(g.in, g, 1)[gi];
-    i2 = pin_row(g.in, g, 2)[gi];
-    s0 = g.slot[gi];
-    s1 = pin_row(g.slot, g, 1)[gi];
-    s2 = pin_row(g.slot, g, 2)[gi];
-    if constexpr (UNI) {
-      i0 = __builtin_amdgcn_readfirstlane(i0);
-      i1 = __builtin_amdgcn_readfirstlane(i1);
-      i2 = __builtin_amdgcn_readfirstlane(i2);
-      s0 = __builtin_amdgcn_readfirstlane(s0);
-      s1 = __builtin_amdgcn_readfirstlane(s1);
-      s2 = __builtin_amdgcn_readfirstlane(s2);
-    }
-    const int k = arity_of(op);
-    x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
-    x1 = x2 = z;
-    if (k > 1) x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
-    if (k > 2) x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
-  } else {
-    // few columns: the sweep is bound by round trips, so every gather goes
-    // out in the second round whatever the opcode
-    i0 = g.in[gi];
-    i1 = pin_row(g.in, g, 1)[gi];
-    i2 = pin_row(g.in, g, 2)[gi];
-    s0 = g.slot[gi];
-    s1 = pin_row(g.slot, g, 1)[gi];
-    s2 = pin_row(g.slot, g, 2)[gi];
-    x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
-    x1 = sp_load(sp[(int64_t)i1 * a.B + b]);
-    x2 = sp_load(sp[(int64_t)i2 * a.B + b]);
+  // every pin's index and slot go out with the opcode and the fan-out range
+  // (unused pin rows alias pin 0); taken here, so none of them is moved
+  // into the branch of the arity that reads it (each would add a dependent
+  // round trip)
+  int32_t i0 = g.in[gi];
+  int32_t i1 = pin_row(g.in, g, 1)[gi];
+  int32_t i2 = pin_row(g.in, g, 2)[gi];
+  int32_t s0 = g.slot[gi];
+  int32_t s1 = pin_row(g.slot, g, 1)[gi];
+  int32_t s2 = pin_row(g.slot, g, 2)[gi];
+  gathers_done(op, e0, e1r, i0, i1, i2, s0, s1, s2);
+  if constexpr (UNI) {
+    e0 = __builtin_amdgcn_readfirstlane(e0);
+    e1r = __builtin_amdgcn_readfirstlane(e1r);
+    op = __builtin_amdgcn_readfirstlane(op);
+    i0 = __builtin_amdgcn_readfirstlane(i0);
+    i1 = __builtin_amdgcn_readfirstlane(i1);
+    i2 = __builtin_amdgcn_readfirstlane(i2);
+    s0 = __builtin_amdgcn_readfirstlane(s0);
+    s1 = __builtin_amdgcn_readfirstlane(s1);
+    s2 = __builtin_amdgcn_readfirstlane(s2);
   }
-  // (after every first- and second-round load has gone out)
+  // second round: every pin's probability, whatever the opcode (a pin the
+  // gate lacks reads pin 0's row again, a cache hit), beside the pull's
+  // loads; the values are unpacked only after the pull, so no load waits
+  // on another
+  const float r0 = sp[(int64_t)i0 * a.B + b];
+  const float r1 = sp[(int64_t)i1 * a.B + b];
+  const float r2 = sp[(int64_t)i2 * a.B + b];
   if (WIDE && skip_heavy && e1r - e0 > kHeavyPull) return;
+  const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
   const float pulled = pull_sum(a.contrib, e0, e1, a.C, c, active, lane, WIDE);
   if (!active) return;
-  float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
+  float lam = seed_of(a, out, c, b, sp_load(sp_out), beta, cap) + pulled;
   if (a.ste) lam *= beta;
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
   const int k = arity_of(op);
   float d0, d1, d2;
-  sp_partials(op, x0, k > 1 ? x1 : z, k > 2 ? x2 : z, d0, d1, d2);
+  sp_partials(op, sp_load(r0), k > 1 ? sp_load(r1) : z, k > 2 ? sp_load(r2) : z, d0, d1, d2);
   a.contrib[(int64_t)s0 * a.C + c] = lam * d0;
   if (k > 1) a.contrib[(int64_t)s1 * a.C + c] = lam * d1;
   if (k > 2) a.contrib[(int64_t)s2 * a.C + c] = lam * d2;
