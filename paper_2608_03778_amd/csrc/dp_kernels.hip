@@ -1379,23 +1379,37 @@ __device__ __forceinline__ void bwd_item(const GraphView &g, const BwdArgs &a, i
   const float sp_out = sp[(int64_t)out * a.B + b];
   const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)out : (int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
-  if constexpr (CELLS) {  // library cell: partials by reverse mode over its code
+  if constexpr (CELLS) {  // library cell: partials over its code
+    // the first round also takes every pin's index and slot; the second
+    // every pin's probability, the cell's code and the pull, none of them
+    // waiting on another
+    int32_t pin[kCellMaxIn], sl[kCellMaxIn];
+#pragma unroll
+    for (int j = 0; j < kCellMaxIn; ++j) {
+      pin[j] = j < g.pins ? g.in[j * g.G + gi] : 0;
+      sl[j] = j < g.pins ? g.slot[j * g.G + gi] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kCellMaxIn; ++j) value_taken(pin[j]);
+    float r[kCellMaxIn];
+#pragma unroll
+    for (int j = 0; j < kCellMaxIn; ++j) r[j] = j < g.pins ? sp[(int64_t)pin[j] * a.B + b] : 0.0f;
+    const LaneCode lc = lane_code(g, op);
     const int32_t e1 = active ? e1r : e0;  // lanes past the end pull nothing
-    const f2 pq = sp_load(sp_out);
     const float pulled =
         pull_sum(a.contrib, e0, e1, a.C, c, active, lane, a.C >= kSerialColumnsNoHeavy);
     if (!active) return;
-    float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
+    float lam = seed_of(a, out, c, b, sp_load(sp_out), beta, cap) + pulled;
     if (a.ste) lam *= beta;
     if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
-    const LaneCode lc = lane_code(g, op);
     f2 x[kCellMaxIn];
     float d[kCellMaxIn];
-    for (int j = 0; j < kCellMaxIn; ++j)
-      x[j] = j < g.pins ? sp_load(sp[(int64_t)g.in[j * g.G + gi] * a.B + b]) : z;
+#pragma unroll
+    for (int j = 0; j < kCellMaxIn; ++j) x[j] = j < g.pins ? sp_load(r[j]) : z;
     cell_partials(lc, x, d);
-    for (int j = 0; j < lc.nin; ++j)
-      a.contrib[(int64_t)g.slot[j * g.G + gi] * a.C + c] = lam * d[j];
+#pragma unroll
+    for (int j = 0; j < kCellMaxIn; ++j)
+      if (j < lc.nin) a.contrib[(int64_t)sl[j] * a.C + c] = lam * d[j];
     return;
   }
   // every pin's index and slot go out with the opcode and the fan-out range
