@@ -359,11 +359,22 @@ __device__ __forceinline__ void sp_item(const GraphView &g, const SpLevel &lv, u
   const int op = g.op[gi];
   float *sp = lv.sp;
   if constexpr (CELLS) {
+    // every pin row (unused pins alias pin 0), so the gathers need no count;
+    // the indices arrive with the opcode, the probabilities with the cell's
+    // code, and no gather waits on another
+    int32_t pin[kCellMaxIn];
+#pragma unroll
+    for (int k = 0; k < kCellMaxIn; ++k) pin[k] = k < g.pins ? g.in[k * g.G + gi] : 0;
+    value_taken(op);
+#pragma unroll
+    for (int k = 0; k < kCellMaxIn; ++k) value_taken(pin[k]);
+    float r[kCellMaxIn];
+#pragma unroll
+    for (int k = 0; k < kCellMaxIn; ++k) r[k] = k < g.pins ? sp[(int64_t)pin[k] * B + b] : 0.0f;
     const LaneCode lc = lane_code(g, op);
-    // every pin row (unused pins alias pin 0), so the gathers need no count
     f2 x[kCellMaxIn];
-    for (int k = 0; k < kCellMaxIn; ++k)
-      x[k] = k < g.pins ? sp_load(sp[(int64_t)g.in[k * g.G + gi] * B + b]) : f2{0.0f, 1.0f};
+#pragma unroll
+    for (int k = 0; k < kCellMaxIn; ++k) x[k] = k < g.pins ? sp_load(r[k]) : f2{0.0f, 1.0f};
     sp[(int64_t)(g.n_pi + gi) * B + b] = settle(cell_sp(lc, x));
     return;
   }
