@@ -1531,25 +1531,22 @@ __device__ __forceinline__ void bwd_heavy(const GraphView &g, const BwdArgs &a,
   const f2 pq = sp_load(sp[(int64_t)out * a.B + b]);
   const float beta = a.beta ? a.beta[a.beta_shared ? (int64_t)out : (int64_t)out * a.B + b] : 1.0f;
   const float cap = a.cap[out];
+  // every pin's index and slot in the first round (unused pin rows alias
+  // pin 0), every pin's probability beside the pull's first loads
   const int32_t i0 = g.in[gi], s0 = g.slot[gi];
-  int32_t s1 = 0, s2 = 0;
-  f2 x1 = z, x2 = z;
-  const f2 x0 = sp_load(sp[(int64_t)i0 * a.B + b]);
-  if (k > 1) {
-    s1 = g.slot[g.G + gi];
-    x1 = sp_load(sp[(int64_t)g.in[g.G + gi] * a.B + b]);
-  }
-  if (k > 2) {
-    s2 = g.slot[2 * g.G + gi];
-    x2 = sp_load(sp[(int64_t)g.in[2 * g.G + gi] * a.B + b]);
-  }
+  const int32_t i1 = pin_row(g.in, g, 1)[gi], s1 = pin_row(g.slot, g, 1)[gi];
+  const int32_t i2 = pin_row(g.in, g, 2)[gi], s2 = pin_row(g.slot, g, 2)[gi];
+  gathers_done(i0, i1, i2);
+  const float r0 = sp[(int64_t)i0 * a.B + b];
+  const float r1 = sp[(int64_t)i1 * a.B + b];
+  const float r2 = sp[(int64_t)i2 * a.B + b];
   const float pulled = heavy_pull(a.contrib, e0, e1, a.C, c);
   if (w != 0 || !active) return;
   float lam = seed_of(a, out, c, b, pq, beta, cap) + pulled;
   if (a.ste) lam *= beta;
   if (a.lam) a.lam[(int64_t)c * (a.n_pi + a.G) + out] = lam;
   float d0, d1, d2;
-  sp_partials(op, x0, k > 1 ? x1 : z, k > 2 ? x2 : z, d0, d1, d2);
+  sp_partials(op, sp_load(r0), k > 1 ? sp_load(r1) : z, k > 2 ? sp_load(r2) : z, d0, d1, d2);
   a.contrib[(int64_t)s0 * a.C + c] = lam * d0;
   if (k > 1) a.contrib[(int64_t)s1 * a.C + c] = lam * d1;
   if (k > 2) a.contrib[(int64_t)s2 * a.C + c] = lam * d2;
