@@ -1281,6 +1281,9 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
                                           int lane, bool serial) {
   if (serial) return active ? serial_pull(contrib, e0, e1, C, c) : 0.0f;
   const bool light = active && e1 - e0 <= kStrand;
+  // the light ranges' loads go out before the heavy batching's shuffles
+  float lv[kStrand];
+  if (light) strand_load(contrib, e0, e1, C, c, lv);
   uint64_t heavy = __ballot(active && !light);
   // the wave's heavy nets take consecutive strand positions (lane order);
   // when they fit in 64, their strands load in the same round as the light
@@ -1312,8 +1315,7 @@ __device__ __forceinline__ float pull_sum(const float *__restrict__ contrib, int
     hend = __shfl(e1, src);
     hcol = __shfl(c, src);
   }
-  float lv[kStrand], hv[kStrand];
-  if (light) strand_load(contrib, e0, e1, C, c, lv);
+  float hv[kStrand];
   if (my_h >= 0) strand_load(contrib, hbeg, hend, C, hcol, hv);
   float acc = light ? strand_fold(lv, e1 - e0) : 0.0f;
   if (!heavy) return acc;
